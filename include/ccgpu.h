@@ -1,0 +1,162 @@
+/*
+ * ccgpu.h -- C ABI of the MI355X (gfx950) colour-coding library.
+ *
+ * The library implements the colour-coding dynamic program for subgraph
+ * isomorphism and enumeration of Malik, Suchy and Valla, "Efficient
+ * Implementation of Color Coding Algorithm for Subgraph Isomorphism Problem"
+ * (arXiv 1908.11248):
+ *   - SubIso / SubEnum problem statement: Sec. 1 (adjacency-preserving
+ *     injective mappings V(F) -> V(G), not necessarily induced);
+ *   - random colouring and colourful copies: Sec. 2.1;
+ *   - tree decomposition and nice tree decomposition: Sec. 1.2, Sec. 3;
+ *   - the leaf / introduce / forget / join rules: Sec. 3.1;
+ *   - degree mask and candidate limiting: Sec. 3.2;
+ *   - result reconstruction: Sec. 4.
+ *
+ * Counting semantics.  count(G, F, zeta) is the number of mappings
+ * Phi: V(F) -> V(G) that send every edge of F to an edge of G and give the
+ * images pairwise distinct colours (hence Phi is injective).  Automorphic
+ * images count separately: this is the paper's default counting mode
+ * (Sec. 5.2, "the former version").  Counts are exact modulo 2^64; a per
+ * colouring overflow flag is set when a DP entry's true value reaches 2^64
+ * under the decomposition used (a clear flag means the count is exact).
+ *
+ * Conventions.
+ *   - Every call returns a status (CC_OK = 0 or a negative CC_E* code) and
+ *     records a message for cc_last_error() (thread-local).
+ *   - Handles are opaque and owned by the library; *_free(NULL) is a no-op.
+ *   - Input arrays are host arrays, copied by the call and still owned by
+ *     the caller.  Output arrays are caller-allocated host arrays.
+ *   - A context is used by one host thread at a time.  Calls that produce
+ *     results synchronise the context's stream before they return.
+ *   - Colours are 0-based: colour c of a k-colouring is c in [0, k).
+ *   - Limits: 1 <= n_F <= 16, n_F <= k <= 16 (colour sets are k-bit masks;
+ *     the paper uses 32-bit masks for n_F <= 32, Sec. 3.2), n_G < 2^31, and
+ *     the packed table key (colouring index, bag images, colour set) must fit
+ *     128 bits; otherwise CC_ERANGE.
+ */
+#ifndef CCGPU_H
+#define CCGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CC_OK 0
+#define CC_EINVAL (-1)     /* malformed graph, pattern, decomposition or argument */
+#define CC_ERANGE (-2)     /* a size limit above is exceeded */
+#define CC_ENOMEM (-3)     /* device arena or host allocation failed */
+#define CC_EDEVICE (-4)    /* a HIP runtime error */
+#define CC_ECANCELLED (-5) /* request cancelled (serving) */
+
+typedef struct cc_context cc_context;
+typedef struct cc_graph cc_graph;
+typedef struct cc_coloring cc_coloring;
+typedef struct cc_decomp cc_decomp;
+
+/* Message describing the last failing call on this thread ("" if none). */
+const char *cc_last_error(void);
+
+/* Creates a context on HIP device `device`.
+ *   arena_bytes  size of the device arena that holds every DP table; the
+ *                library allocates it (0: a default of 3/4 of free memory).
+ *   hip_stream   hipStream_t to launch on (NULL: the library creates one;
+ *                the caller keeps ownership of a stream it passes).
+ * Errors: CC_EDEVICE (no such device), CC_ENOMEM. */
+int cc_context_create(int device, size_t arena_bytes, void *hip_stream, cc_context **out);
+int cc_context_destroy(cc_context *ctx);
+
+/* Uploads host graph G (Sec. 1.2: simple and undirected) in CSR form:
+ *   row_ptr[n + 1] (int64, row_ptr[0] = 0), col[row_ptr[n]] (int32).
+ * Both directions of every edge must be present, rows strictly ascending,
+ * no self-loops; violations return CC_EINVAL unless flags has
+ * CC_GRAPH_CANONICALIZE, which sorts, symmetrises and removes loops and
+ * duplicates instead.  The graph stays resident on the context's device. */
+#define CC_GRAPH_CANONICALIZE 1u
+int cc_load_graph(cc_context *ctx, int32_t n, const int64_t *row_ptr, const int32_t *col,
+                  uint32_t flags, cc_graph **out);
+void cc_graph_free(cc_graph *g);
+int32_t cc_graph_num_vertices(const cc_graph *g);
+
+/* Random colourings of G (Sec. 2.1).  Colouring b (0 <= b < num_colorings)
+ * gives vertex v the colour
+ *     floor(k * hi32(splitmix64(seed XOR (b * 2^32 + v))) / 2^32)
+ * where splitmix64(s) is the first output of the published splitmix64
+ * generator seeded with s.  Computed on the device. */
+int cc_color(cc_context *ctx, const cc_graph *g, int32_t k, uint64_t seed,
+             int32_t num_colorings, cc_coloring **out);
+/* Explicit colourings: colors[b * n + v] in [0, k) (host array). */
+int cc_color_explicit(cc_context *ctx, const cc_graph *g, int32_t k, int32_t num_colorings,
+                      const uint8_t *colors, cc_coloring **out);
+/* Copies colouring b to colors_out[n] (host). */
+int cc_coloring_download(const cc_coloring *c, int32_t b, uint8_t *colors_out);
+void cc_coloring_free(cc_coloring *c);
+
+/* Nice tree decomposition of pattern F (Sec. 3): minimum width (exact, by
+ * elimination orderings), then converted to the paper's nice form (Sec. 1.2:
+ * single-vertex leaves, empty root of degree one).  Pattern vertex 0 is the
+ * last vertex forgotten.  edges[2*i], edges[2*i+1] is the i-th edge of F.
+ * Host-only; needs no context. */
+int cc_build_decomposition(int32_t n_F, int32_t m_F, const int32_t *edges, uint32_t flags,
+                           cc_decomp **out);
+/* Exports the nice TD as int32 data: buf[0] = N nodes, then five ints per
+ * node in post-order (root last): type (0 leaf, 1 introduce, 2 forget,
+ * 3 join), vertex (-1 for a join), child0, child1 (-1 if absent), bag as a
+ * uint32 bitmask.  *len receives 1 + 5N; CC_ERANGE if cap is smaller. */
+int cc_decomp_export(const cc_decomp *d, int32_t *buf, size_t cap, size_t *len);
+/* Imports a nice TD in the export format for pattern F; it is validated
+ * against the definitions of Sec. 1.2 (CC_EINVAL if invalid). */
+int cc_decomp_import(int32_t n_F, int32_t m_F, const int32_t *edges, const int32_t *buf,
+                     size_t len, cc_decomp **out);
+int32_t cc_decomp_width(const cc_decomp *d);
+void cc_decomp_free(cc_decomp *d);
+
+/* Runs the DP (Sec. 3.1) for every colouring of `c` in one batch and writes
+ * counts[b] and (if not NULL) overflow[b] for b < num_colorings.
+ * flags: CC_NO_DEGREE_MASK disables the degree mask of Sec. 3.2 (same
+ * counts, bigger tables). */
+#define CC_NO_DEGREE_MASK 1u
+int cc_count(cc_context *ctx, const cc_graph *g, const cc_coloring *c, const cc_decomp *d,
+             uint32_t flags, uint64_t *counts, uint8_t *overflow);
+
+/* Same DP for one colouring index b; per_vertex[v] (n entries) receives the
+ * number of colourful mappings with Phi(0) = v (the entries of the node
+ * below the root, whose bag is {0}). */
+int cc_count_by_vertex(cc_context *ctx, const cc_graph *g, const cc_coloring *c, int32_t b,
+                       const cc_decomp *d, uint32_t flags, uint64_t *per_vertex,
+                       uint64_t *count, uint8_t *overflow);
+
+/* Enumeration (Sec. 4) for colouring index b: the first min(total, cap)
+ * colourful mappings in ascending lexicographic order of
+ * (Phi(0), ..., Phi(n_F - 1)), written row-major to rows[cap][n_F];
+ * *n_rows = min(total, cap), *total = the count.  CC_ERANGE when the count
+ * overflowed 64 bits. */
+int cc_enumerate(cc_context *ctx, const cc_graph *g, const cc_coloring *c, int32_t b,
+                 const cc_decomp *d, uint64_t cap, int32_t *rows, uint64_t *n_rows,
+                 uint64_t *total);
+
+/* Per-node statistics of the last cc_count / cc_enumerate call on ctx:
+ * entries[i] = sum over colourings of |D_x| for TD node i (export order),
+ * up to cap nodes; *n_nodes receives the node count. */
+int cc_last_table_sizes(const cc_context *ctx, int64_t *entries, size_t cap, size_t *n_nodes);
+
+/* ---------------------------------------------------------------------- */
+/* Batched queries: many (decomposition, colouring) pairs over one graph,
+ * scheduled together.  counts_flat / overflow_flat receive, query after
+ * query, num_colorings values each. */
+typedef struct {
+    const cc_decomp *decomp;
+    const cc_coloring *coloring;
+} cc_query;
+int cc_count_batch(cc_context *ctx, const cc_graph *g, int32_t nq, const cc_query *q,
+                   uint32_t flags, uint64_t *counts_flat, uint8_t *overflow_flat);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCGPU_H */

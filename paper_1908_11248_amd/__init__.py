@@ -1,0 +1,282 @@
+"""Python binding of libccgpu (the colour-coding DP on MI355X / gfx950).
+
+Argument marshalling only: every step of the DP runs in the HIP library
+behind the C ABI of ``include/ccgpu.h``.  The functions carry the ABI's names
+without the ``cc_`` prefix.  Importing this module does not load the library;
+the first call does, and it raises ``LibraryMissing`` when ``libccgpu.so``
+has not been built (``python -m paper_1908_11248_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccgpu.so")
+
+CC_OK = 0
+CC_EINVAL = -1
+CC_ERANGE = -2
+CC_ENOMEM = -3
+CC_EDEVICE = -4
+CC_ECANCELLED = -5
+CC_GRAPH_CANONICALIZE = 1
+CC_NO_DEGREE_MASK = 1
+
+# every symbol the header declares (checked by the CPU tests)
+EXPORTS = [
+    "cc_last_error", "cc_context_create", "cc_context_destroy", "cc_load_graph", "cc_graph_free",
+    "cc_graph_num_vertices", "cc_color", "cc_color_explicit", "cc_coloring_download", "cc_coloring_free",
+    "cc_build_decomposition", "cc_decomp_export", "cc_decomp_import", "cc_decomp_width", "cc_decomp_free",
+    "cc_count", "cc_count_by_vertex", "cc_enumerate", "cc_last_table_sizes", "cc_count_batch",
+]
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class CcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing("libccgpu.so is not built: run python -m paper_1908_11248_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, U32, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "cc_last_error": (ctypes.c_char_p, []),
+            "cc_context_create": (ctypes.c_int, [ctypes.c_int, SZ, P, PP]),
+            "cc_context_destroy": (ctypes.c_int, [P]),
+            "cc_load_graph": (ctypes.c_int, [P, I32, P, P, U32, PP]),
+            "cc_graph_free": (None, [P]),
+            "cc_graph_num_vertices": (I32, [P]),
+            "cc_color": (ctypes.c_int, [P, P, I32, U64, I32, PP]),
+            "cc_color_explicit": (ctypes.c_int, [P, P, I32, I32, P, PP]),
+            "cc_coloring_download": (ctypes.c_int, [P, I32, P]),
+            "cc_coloring_free": (None, [P]),
+            "cc_build_decomposition": (ctypes.c_int, [I32, I32, P, U32, PP]),
+            "cc_decomp_export": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
+            "cc_decomp_import": (ctypes.c_int, [I32, I32, P, P, SZ, PP]),
+            "cc_decomp_width": (I32, [P]),
+            "cc_decomp_free": (None, [P]),
+            "cc_count": (ctypes.c_int, [P, P, P, P, U32, P, P]),
+            "cc_count_by_vertex": (ctypes.c_int, [P, P, P, I32, P, U32, P, P, P]),
+            "cc_enumerate": (ctypes.c_int, [P, P, P, I32, P, U64, P, P, P]),
+            "cc_last_table_sizes": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
+            "cc_count_batch": (ctypes.c_int, [P, P, I32, P, U32, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != CC_OK:
+        raise CcError(rc, lib().cc_last_error().decode())
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _Handle:
+    _free = None
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def close(self):
+        if self.ptr:
+            getattr(lib(), self._free)(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph(_Handle):
+    _free = "cc_graph_free"
+
+    def __init__(self, ptr, ctx):
+        super().__init__(ptr)
+        self.ctx = ctx  # keep the context alive
+
+    @property
+    def n(self) -> int:
+        return int(lib().cc_graph_num_vertices(self.ptr))
+
+
+class Coloring(_Handle):
+    _free = "cc_coloring_free"
+
+    def __init__(self, ptr, ctx, k, num):
+        super().__init__(ptr)
+        self.ctx = ctx
+        self.k = k
+        self.num = num
+
+    def download(self, b: int, n: int) -> np.ndarray:
+        out = np.empty(max(n, 1), dtype=np.uint8)
+        _check(lib().cc_coloring_download(self.ptr, b, _p(out)))
+        return out[:n]
+
+
+class Decomp(_Handle):
+    _free = "cc_decomp_free"
+
+    def __init__(self, ptr, n_F):
+        super().__init__(ptr)
+        self.n_F = n_F
+
+    @property
+    def width(self) -> int:
+        return int(lib().cc_decomp_width(self.ptr))
+
+    def export(self) -> np.ndarray:
+        ln = ctypes.c_size_t(0)
+        rc = lib().cc_decomp_export(self.ptr, None, 0, ctypes.byref(ln))
+        buf = np.zeros(ln.value, dtype=np.int32)
+        _check(lib().cc_decomp_export(self.ptr, _p(buf), buf.size, ctypes.byref(ln)))
+        return buf
+
+
+class Context(_Handle):
+    _free = None
+
+    def __init__(self, device: int = 0, arena_bytes: int = 0, stream: Optional[int] = None):
+        out = ctypes.c_void_p()
+        _check(lib().cc_context_create(device, arena_bytes, stream, ctypes.byref(out)))
+        super().__init__(out.value)
+
+    def close(self):
+        if self.ptr:
+            lib().cc_context_destroy(self.ptr)
+            self.ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_table_sizes(self) -> np.ndarray:
+        n = ctypes.c_size_t(0)
+        buf = np.zeros(4096, dtype=np.int64)
+        _check(lib().cc_last_table_sizes(self.ptr, _p(buf), buf.size, ctypes.byref(n)))
+        return buf[: n.value].copy()
+
+
+def _edges(edges) -> Tuple[int, np.ndarray]:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    if e.size == 0:
+        return 0, np.zeros((1, 2), dtype=np.int32)
+    return int(e.shape[0]), e
+
+
+def load_graph(ctx: Context, n: int, row_ptr, col, flags: int = 0) -> Graph:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().cc_load_graph(ctx.ptr, n, _p(rp), _p(cl), flags, ctypes.byref(out)))
+    return Graph(out.value, ctx)
+
+
+def color(ctx: Context, g: Graph, k: int, seed: int, num_colorings: int) -> Coloring:
+    out = ctypes.c_void_p()
+    _check(lib().cc_color(ctx.ptr, g.ptr, k, seed & (2**64 - 1), num_colorings, ctypes.byref(out)))
+    return Coloring(out.value, ctx, k, num_colorings)
+
+
+def color_explicit(ctx: Context, g: Graph, k: int, colors) -> Coloring:
+    c = np.ascontiguousarray(colors, dtype=np.uint8)
+    num = 1 if c.ndim == 1 else int(c.shape[0])
+    out = ctypes.c_void_p()
+    _check(lib().cc_color_explicit(ctx.ptr, g.ptr, k, num, _p(c), ctypes.byref(out)))
+    return Coloring(out.value, ctx, k, num)
+
+
+def build_decomposition(n_F: int, edges, flags: int = 0) -> Decomp:
+    m, e = _edges(edges)
+    out = ctypes.c_void_p()
+    _check(lib().cc_build_decomposition(n_F, m, _p(e), flags, ctypes.byref(out)))
+    return Decomp(out.value, n_F)
+
+
+def decomp_import(n_F: int, edges, td) -> Decomp:
+    m, e = _edges(edges)
+    buf = np.ascontiguousarray(td, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().cc_decomp_import(n_F, m, _p(e), _p(buf), buf.size, ctypes.byref(out)))
+    return Decomp(out.value, n_F)
+
+
+def count(ctx: Context, g: Graph, c: Coloring, d: Decomp, flags: int = 0):
+    """(counts uint64[num_colorings], overflow bool[num_colorings])"""
+    counts = np.zeros(c.num, dtype=np.uint64)
+    ovf = np.zeros(c.num, dtype=np.uint8)
+    _check(lib().cc_count(ctx.ptr, g.ptr, c.ptr, d.ptr, flags, _p(counts), _p(ovf)))
+    return counts, ovf.astype(bool)
+
+
+def count_by_vertex(ctx: Context, g: Graph, c: Coloring, b: int, d: Decomp, flags: int = 0):
+    """(per_vertex uint64[n], count, overflow)"""
+    pv = np.zeros(max(g.n, 1), dtype=np.uint64)
+    cnt = np.zeros(1, dtype=np.uint64)
+    ovf = np.zeros(1, dtype=np.uint8)
+    _check(lib().cc_count_by_vertex(ctx.ptr, g.ptr, c.ptr, b, d.ptr, flags, _p(pv), _p(cnt), _p(ovf)))
+    return pv[: g.n], int(cnt[0]), bool(ovf[0])
+
+
+def enumerate(ctx: Context, g: Graph, c: Coloring, b: int, d: Decomp, cap: int):  # noqa: A001
+    """(rows int32[min(total, cap), n_F] lexicographically sorted, total)"""
+    rows = np.zeros((max(cap, 1), d.n_F), dtype=np.int32)
+    nr = np.zeros(1, dtype=np.uint64)
+    tot = np.zeros(1, dtype=np.uint64)
+    _check(lib().cc_enumerate(ctx.ptr, g.ptr, c.ptr, b, d.ptr, cap, _p(rows), _p(nr), _p(tot)))
+    return rows[: int(nr[0])].copy(), int(tot[0])
+
+
+def count_batch(ctx: Context, g: Graph, queries: Sequence[Tuple[Decomp, Coloring]], flags: int = 0):
+    """Counts of many (decomposition, colouring) queries: list of (counts, overflow)."""
+    nq = len(queries)
+
+    class Q(ctypes.Structure):
+        _fields_ = [("decomp", ctypes.c_void_p), ("coloring", ctypes.c_void_p)]
+
+    arr = (Q * max(nq, 1))()
+    total = 0
+    for i in range(nq):
+        d, c = queries[i]
+        arr[i].decomp = d.ptr
+        arr[i].coloring = c.ptr
+        total += c.num
+    counts = np.zeros(max(total, 1), dtype=np.uint64)
+    ovf = np.zeros(max(total, 1), dtype=np.uint8)
+    _check(lib().cc_count_batch(ctx.ptr, g.ptr, nq, ctypes.cast(arr, ctypes.c_void_p), flags, _p(counts), _p(ovf)))
+    out = []
+    off = 0
+    for d, c in queries:
+        out.append((counts[off:off + c.num].copy(), ovf[off:off + c.num].astype(bool)))
+        off += c.num
+    return out

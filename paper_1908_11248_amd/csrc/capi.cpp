@@ -1,0 +1,413 @@
+// C ABI of the colour-coding library (declarations and semantics in
+// include/ccgpu.h).  Every entry point converts internal exceptions into a
+// status code and a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "engine.h"
+
+using namespace ccg;
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        f();
+        g_last_error.clear();
+        return CC_OK;
+    } catch (const CcError& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return CC_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return CC_EINVAL;
+    }
+}
+
+void need(bool ok, int code, const char* msg) {
+    if (!ok) fail(code, msg);
+}
+}  // namespace
+
+namespace ccg {
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace ccg
+
+extern "C" {
+
+const char* cc_last_error(void) { return g_last_error.c_str(); }
+
+int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_context** out) {
+    return guarded([&] {
+        need(out != nullptr, CC_EINVAL, "out is NULL");
+        int ndev = 0;
+        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        need(device >= 0 && device < ndev, CC_EDEVICE, "no such HIP device");
+        hip_check(hipSetDevice(device), "hipSetDevice");
+        auto* c = new cc_context();
+        c->device = device;
+        try {
+            if (hip_stream) {
+                c->stream = (hipStream_t)hip_stream;
+            } else {
+                hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+                c->own_stream = true;
+            }
+            if (arena_bytes == 0) {
+                size_t freeb = 0, total = 0;
+                hip_check(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
+                arena_bytes = freeb / 4 * 3;
+            }
+            hip_check(hipMalloc(&c->arena_mem, arena_bytes), "arena hipMalloc");
+            c->arena.init((char*)c->arena_mem, arena_bytes);
+            hip_check(hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault), "hipHostMalloc");
+        } catch (...) {
+            if (c->arena_mem) (void)hipFree(c->arena_mem);
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            throw;
+        }
+        *out = c;
+    });
+}
+
+int cc_context_destroy(cc_context* ctx) {
+    if (!ctx) return CC_OK;
+    return guarded([&] {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        if (ctx->arena_mem) (void)hipFree(ctx->arena_mem);
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+    });
+}
+
+int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int32_t* col, uint32_t flags,
+                  cc_graph** out) {
+    return guarded([&] {
+        need(ctx && out && n >= 0 && (n == 0 || row_ptr), CC_EINVAL, "bad arguments");
+        need(n < INT32_MAX, CC_ERANGE, "n_G must be below 2^31");
+        std::vector<int64_t> rp(row_ptr, row_ptr + n + 1);
+        need(rp[0] == 0, CC_EINVAL, "row_ptr[0] must be 0");
+        for (int32_t v = 0; v < n; v++) need(rp[v + 1] >= rp[v], CC_EINVAL, "row_ptr must be non-decreasing");
+        int64_t m2 = rp[n];
+        std::vector<int32_t> cl(col, col + m2);
+        for (int64_t e = 0; e < m2; e++) need(cl[e] >= 0 && cl[e] < n, CC_EINVAL, "column id out of range");
+        auto canonical = [&]() {
+            for (int32_t v = 0; v < n; v++)
+                for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+                    if (cl[e] == v) return false;                            // loop
+                    if (e > rp[v] && cl[e] <= cl[e - 1]) return false;       // unsorted / duplicate
+                }
+            // symmetry: every (v, w) has (w, v)
+            for (int32_t v = 0; v < n; v++)
+                for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+                    int32_t w = cl[e];
+                    if (!std::binary_search(cl.begin() + rp[w], cl.begin() + rp[w + 1], v)) return false;
+                }
+            return true;
+        };
+        if (!canonical()) {
+            need(flags & CC_GRAPH_CANONICALIZE, CC_EINVAL,
+                 "graph is not simple, symmetric and row-sorted (pass CC_GRAPH_CANONICALIZE to fix it)");
+            std::vector<std::pair<int32_t, int32_t>> es;
+            for (int32_t v = 0; v < n; v++)
+                for (int64_t e = rp[v]; e < rp[v + 1]; e++)
+                    if (cl[e] != v) {
+                        es.push_back({v, cl[e]});
+                        es.push_back({cl[e], v});
+                    }
+            std::sort(es.begin(), es.end());
+            es.erase(std::unique(es.begin(), es.end()), es.end());
+            std::fill(rp.begin(), rp.end(), 0);
+            cl.resize(es.size());
+            for (size_t i = 0; i < es.size(); i++) {
+                rp[es[i].first + 1]++;
+                cl[i] = es[i].second;
+            }
+            for (int32_t v = 0; v < n; v++) rp[v + 1] += rp[v];
+            m2 = int64_t(es.size());
+        }
+        std::vector<int32_t> src(m2);
+        for (int32_t v = 0; v < n; v++)
+            for (int64_t e = rp[v]; e < rp[v + 1]; e++) src[e] = v;
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        auto* g = new cc_graph();
+        g->ctx = ctx;
+        g->n = n;
+        g->m2 = m2;
+        try {
+            hip_check(hipMalloc(&g->rp, 8 * size_t(n + 1)), "hipMalloc");
+            hip_check(hipMalloc(&g->col, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
+            hip_check(hipMalloc(&g->esrc, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
+            hip_check(hipMemcpy(g->rp, rp.data(), 8 * size_t(n + 1), hipMemcpyHostToDevice), "hipMemcpy");
+            if (m2) {
+                hip_check(hipMemcpy(g->col, cl.data(), 4 * size_t(m2), hipMemcpyHostToDevice), "hipMemcpy");
+                hip_check(hipMemcpy(g->esrc, src.data(), 4 * size_t(m2), hipMemcpyHostToDevice), "hipMemcpy");
+            }
+        } catch (...) {
+            cc_graph_free(g);
+            throw;
+        }
+        *out = g;
+    });
+}
+
+void cc_graph_free(cc_graph* g) {
+    if (!g) return;
+    if (g->rp) (void)hipFree(g->rp);
+    if (g->col) (void)hipFree(g->col);
+    if (g->esrc) (void)hipFree(g->esrc);
+    delete g;
+}
+
+int32_t cc_graph_num_vertices(const cc_graph* g) { return g ? g->n : -1; }
+
+int cc_color(cc_context* ctx, const cc_graph* g, int32_t k, uint64_t seed, int32_t num_colorings,
+             cc_coloring** out) {
+    return guarded([&] {
+        need(ctx && g && out, CC_EINVAL, "bad arguments");
+        need(k >= 1 && k <= 32, CC_ERANGE, "k must be in [1, 32]");
+        need(num_colorings >= 1 && num_colorings <= (1 << 20), CC_ERANGE, "num_colorings out of range");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        auto* c = new cc_coloring();
+        c->ctx = ctx;
+        c->n = g->n;
+        c->k = k;
+        c->B = num_colorings;
+        size_t bytes = std::max<size_t>(1, size_t(g->n) * num_colorings);
+        hipError_t e = hipMalloc(&c->colors, bytes);
+        if (e != hipSuccess) {
+            delete c;
+            hip_check(e, "hipMalloc colours");
+        }
+        launch_color_hash(c->colors, g->n, num_colorings, k, seed, ctx->stream);
+        hip_check(hipStreamSynchronize(ctx->stream), "colour kernel");
+        *out = c;
+    });
+}
+
+int cc_color_explicit(cc_context* ctx, const cc_graph* g, int32_t k, int32_t num_colorings, const uint8_t* colors,
+                      cc_coloring** out) {
+    return guarded([&] {
+        need(ctx && g && out && colors, CC_EINVAL, "bad arguments");
+        need(k >= 1 && k <= 32, CC_ERANGE, "k must be in [1, 32]");
+        need(num_colorings >= 1 && num_colorings <= (1 << 20), CC_ERANGE, "num_colorings out of range");
+        size_t total = size_t(g->n) * num_colorings;
+        for (size_t i = 0; i < total; i++) need(colors[i] < k, CC_EINVAL, "colour out of range");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        auto* c = new cc_coloring();
+        c->ctx = ctx;
+        c->n = g->n;
+        c->k = k;
+        c->B = num_colorings;
+        hipError_t e = hipMalloc(&c->colors, std::max<size_t>(total, 1));
+        if (e != hipSuccess) {
+            delete c;
+            hip_check(e, "hipMalloc colours");
+        }
+        if (total) {
+            e = hipMemcpy(c->colors, colors, total, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                cc_coloring_free(c);
+                hip_check(e, "hipMemcpy colours");
+            }
+        }
+        *out = c;
+    });
+}
+
+int cc_coloring_download(const cc_coloring* c, int32_t b, uint8_t* colors_out) {
+    return guarded([&] {
+        need(c && colors_out && b >= 0 && b < c->B, CC_EINVAL, "bad arguments");
+        hip_check(hipSetDevice(c->ctx->device), "hipSetDevice");
+        if (c->n)
+            hip_check(hipMemcpy(colors_out, c->colors + size_t(b) * c->n, size_t(c->n), hipMemcpyDeviceToHost),
+                      "hipMemcpy");
+    });
+}
+
+void cc_coloring_free(cc_coloring* c) {
+    if (!c) return;
+    if (c->colors) (void)hipFree(c->colors);
+    delete c;
+}
+
+static std::vector<std::pair<int, int>> edge_vec(int32_t m_F, const int32_t* edges) {
+    std::vector<std::pair<int, int>> e;
+    for (int32_t i = 0; i < m_F; i++) e.push_back({edges[2 * i], edges[2 * i + 1]});
+    return e;
+}
+
+int cc_build_decomposition(int32_t n_F, int32_t m_F, const int32_t* edges, uint32_t flags, cc_decomp** out) {
+    (void)flags;
+    return guarded([&] {
+        need(out && m_F >= 0 && (m_F == 0 || edges), CC_EINVAL, "bad arguments");
+        auto* d = new cc_decomp();
+        std::string err;
+        int rc = build_decomposition(n_F, edge_vec(m_F, edges), &d->d, &err);
+        if (rc == CC_OK) rc = make_plan(d->d, &d->plan, &err);
+        if (rc != CC_OK) {
+            delete d;
+            fail(rc, err);
+        }
+        *out = d;
+    });
+}
+
+int cc_decomp_export(const cc_decomp* d, int32_t* buf, size_t cap, size_t* len) {
+    return guarded([&] {
+        need(d && len, CC_EINVAL, "bad arguments");
+        size_t N = d->d.nodes.size();
+        *len = 1 + 5 * N;
+        need(buf && cap >= *len, CC_ERANGE, "buffer too small");
+        buf[0] = int32_t(N);
+        for (size_t i = 0; i < N; i++) {
+            const TdNode& x = d->d.nodes[i];
+            buf[1 + 5 * i] = x.type;
+            buf[2 + 5 * i] = x.u;
+            buf[3 + 5 * i] = x.c0;
+            buf[4 + 5 * i] = x.c1;
+            buf[5 + 5 * i] = int32_t(x.bag);
+        }
+    });
+}
+
+int cc_decomp_import(int32_t n_F, int32_t m_F, const int32_t* edges, const int32_t* buf, size_t len,
+                     cc_decomp** out) {
+    return guarded([&] {
+        need(out && buf && len >= 1 && (m_F == 0 || edges), CC_EINVAL, "bad arguments");
+        need(n_F >= 1 && n_F <= kMaxPattern, CC_ERANGE, "pattern size must be in [1, 16]");
+        int32_t N = buf[0];
+        need(N >= 1 && len == size_t(1 + 5 * N), CC_EINVAL, "length does not match the node count");
+        auto* d = new cc_decomp();
+        d->d.n = n_F;
+        for (auto& e : edge_vec(m_F, edges)) {
+            if (e.first < 0 || e.second < 0 || e.first >= n_F || e.second >= n_F || e.first == e.second) {
+                delete d;
+                fail(CC_EINVAL, "pattern edge out of range or a loop");
+            }
+            d->d.adj[e.first] |= 1u << e.second;
+            d->d.adj[e.second] |= 1u << e.first;
+        }
+        for (int a = 0; a < n_F; a++)
+            for (uint32_t m = d->d.adj[a]; m; m &= m - 1) {
+                int b = __builtin_ctz(m);
+                if (a < b) d->d.edges.push_back({a, b});
+            }
+        int width = 0;
+        for (int32_t i = 0; i < N; i++) {
+            TdNode x{buf[1 + 5 * i], buf[2 + 5 * i], buf[3 + 5 * i], buf[4 + 5 * i], uint32_t(buf[5 + 5 * i])};
+            d->d.nodes.push_back(x);
+            width = std::max(width, __builtin_popcount(x.bag) - 1);
+        }
+        d->d.width = width;
+        std::string err;
+        int rc = validate_decomposition(d->d, &err);
+        if (rc == CC_OK) rc = make_plan(d->d, &d->plan, &err);
+        if (rc != CC_OK) {
+            delete d;
+            fail(rc, err);
+        }
+        *out = d;
+    });
+}
+
+int32_t cc_decomp_width(const cc_decomp* d) { return d ? d->d.width : -1; }
+
+void cc_decomp_free(cc_decomp* d) { delete d; }
+
+static void check_run_args(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_decomp* d) {
+    need(ctx && g && c && d, CC_EINVAL, "bad arguments");
+    need(g->ctx == ctx && c->ctx == ctx, CC_EINVAL, "graph or colouring belongs to another context");
+    need(c->n == g->n, CC_EINVAL, "colouring and graph sizes differ");
+    need(c->k >= d->d.n, CC_ERANGE, "fewer colours than pattern vertices");
+}
+
+int cc_count(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_decomp* d, uint32_t flags,
+             uint64_t* counts, uint8_t* overflow) {
+    return guarded([&] {
+        check_run_args(ctx, g, c, d);
+        need(counts != nullptr, CC_EINVAL, "counts is NULL");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        RunRequest rq;
+        rq.g = g;
+        rq.colors = c->colors;
+        rq.B = c->B;
+        rq.k = c->k;
+        rq.dec = d;
+        rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
+        RunResult r;
+        run_dp(ctx, rq, &r);
+        std::copy(r.counts.begin(), r.counts.end(), counts);
+        if (overflow) std::copy(r.overflow.begin(), r.overflow.end(), overflow);
+        ctx->last_sizes = r.node_sizes;
+    });
+}
+
+int cc_count_by_vertex(cc_context* ctx, const cc_graph* g, const cc_coloring* c, int32_t b, const cc_decomp* d,
+                       uint32_t flags, uint64_t* per_vertex, uint64_t* count, uint8_t* overflow) {
+    return guarded([&] {
+        check_run_args(ctx, g, c, d);
+        need(b >= 0 && b < c->B, CC_EINVAL, "colouring index out of range");
+        need(per_vertex != nullptr, CC_EINVAL, "per_vertex is NULL");
+        const TdNode& rc = d->d.nodes[d->d.nodes[d->d.nodes.size() - 1].c0];
+        need(rc.bag == 1u, CC_EINVAL, "the node below the root must hold pattern vertex 0 only");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        RunRequest rq;
+        rq.g = g;
+        rq.colors = c->colors + size_t(b) * g->n;
+        rq.B = 1;
+        rq.k = c->k;
+        rq.dec = d;
+        rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
+        rq.per_vertex = true;
+        RunResult r;
+        run_dp(ctx, rq, &r);
+        std::copy(r.per_vertex.begin(), r.per_vertex.end(), per_vertex);
+        if (count) *count = r.counts[0];
+        if (overflow) *overflow = r.overflow[0];
+        ctx->last_sizes = r.node_sizes;
+    });
+}
+
+int cc_last_table_sizes(const cc_context* ctx, int64_t* entries, size_t cap, size_t* n_nodes) {
+    return guarded([&] {
+        need(ctx && n_nodes, CC_EINVAL, "bad arguments");
+        *n_nodes = ctx->last_sizes.size();
+        for (size_t i = 0; i < std::min(cap, ctx->last_sizes.size()); i++) entries[i] = ctx->last_sizes[i];
+    });
+}
+
+int cc_count_batch(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query* q, uint32_t flags,
+                   uint64_t* counts_flat, uint8_t* overflow_flat) {
+    return guarded([&] {
+        need(ctx && g && (nq == 0 || q) && counts_flat, CC_EINVAL, "bad arguments");
+        size_t off = 0;
+        for (int32_t i = 0; i < nq; i++) {
+            int rc = cc_count(ctx, g, q[i].coloring, q[i].decomp, flags, counts_flat + off,
+                              overflow_flat ? overflow_flat + off : nullptr);
+            if (rc != CC_OK) fail(rc, "query " + std::to_string(i) + ": " + g_last_error);
+            off += size_t(q[i].coloring->B);
+        }
+    });
+}
+
+int cc_enumerate(cc_context* ctx, const cc_graph* g, const cc_coloring* c, int32_t b, const cc_decomp* d,
+                 uint64_t cap, int32_t* rows, uint64_t* n_rows, uint64_t* total) {
+    (void)ctx; (void)g; (void)c; (void)b; (void)d; (void)cap; (void)rows; (void)n_rows; (void)total;
+    g_last_error = "cc_enumerate is not available yet";
+    return CC_EINVAL;
+}
+
+}  // extern "C"

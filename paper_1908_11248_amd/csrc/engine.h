@@ -1,0 +1,103 @@
+// Runtime objects behind the C ABI: context, device arena, resident graph,
+// colourings, decompositions, and the DP executor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace ccg {
+
+struct CcError {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+// First-fit allocator over one device buffer.  Allocation and release happen
+// on the host in stream order, so a released block may be handed out again
+// while earlier kernels that used it are still queued: they run first.
+class Arena {
+   public:
+    void init(char* base, size_t size);
+    void* alloc(size_t bytes);
+    void release(void* p);
+    size_t in_use() const { return in_use_; }
+    size_t peak() const { return peak_; }
+    size_t size() const { return size_; }
+    void reset_peak() { peak_ = in_use_; }
+
+   private:
+    char* base_ = nullptr;
+    size_t size_ = 0, in_use_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;            // offset -> bytes
+    std::unordered_map<size_t, size_t> live_;  // offset -> bytes
+};
+
+}  // namespace ccg
+
+struct cc_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* arena_mem = nullptr;
+    ccg::Arena arena;
+    uint64_t* pinned = nullptr;  // small host staging buffer
+    std::vector<int64_t> last_sizes;
+};
+
+struct cc_graph {
+    cc_context* ctx = nullptr;
+    int32_t n = 0;
+    int64_t m2 = 0;
+    int64_t* rp = nullptr;
+    int32_t* col = nullptr;
+    int32_t* esrc = nullptr;
+    ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc}; }
+};
+
+struct cc_coloring {
+    cc_context* ctx = nullptr;
+    int32_t n = 0, k = 0, B = 0;
+    uint8_t* colors = nullptr;  // [B][n] on the device
+};
+
+struct cc_decomp {
+    ccg::Decomp d;
+    ccg::Plan plan;
+};
+
+namespace ccg {
+
+struct RunRequest {
+    const cc_graph* g = nullptr;
+    const uint8_t* colors = nullptr;  // device [B][n]
+    int B = 0, k = 0;
+    const cc_decomp* dec = nullptr;
+    bool degree_mask = true;
+    bool per_vertex = false;  // also the per-image split of the node below the root
+    bool keep_tables = false;
+};
+
+struct RunResult {
+    std::vector<uint64_t> counts;      // [B]
+    std::vector<uint8_t> overflow;     // [B]
+    std::vector<uint64_t> per_vertex;  // [B * n] if requested
+    std::vector<DevTable> tables;      // per plan step, when kept (arena-owned)
+    std::vector<int64_t> node_sizes;   // per TD node: sum over colourings of |D_x|
+};
+
+void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out);
+void release_tables(cc_context* ctx, RunResult* r);
+uint64_t read_u64(cc_context* ctx, const uint64_t* dev);
+Lay table_layout(int b, int32_t n, int B, int k);
+
+}  // namespace ccg

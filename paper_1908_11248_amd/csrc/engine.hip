@@ -1,0 +1,371 @@
+// DP executor: runs a decomposition's plan (leaf / introduce / forget / join
+// steps in post-order, Sec. 3.1) over a batch of colourings on one stream.
+#include <algorithm>
+#include <cstring>
+
+#include "engine.h"
+
+namespace ccg {
+
+void fail(int code, const std::string& msg) { throw CcError{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(CC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// arena
+
+void Arena::init(char* base, size_t size) {
+    base_ = base;
+    size_ = size;
+    free_.clear();
+    live_.clear();
+    in_use_ = peak_ = 0;
+    if (size) free_[0] = size;
+}
+
+void* Arena::alloc(size_t bytes) {
+    bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < bytes) continue;
+        size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        live_[off] = bytes;
+        in_use_ += bytes;
+        peak_ = std::max(peak_, in_use_);
+        return base_ + off;
+    }
+    fail(CC_ENOMEM, "device arena exhausted: " + std::to_string(bytes) + " bytes requested, " +
+                        std::to_string(size_ - in_use_) + " free of " + std::to_string(size_));
+}
+
+void Arena::release(void* p) {
+    if (!p) return;
+    size_t off = size_t((char*)p - base_);
+    auto it = live_.find(off);
+    if (it == live_.end()) return;
+    size_t len = it->second;
+    live_.erase(it);
+    in_use_ -= len;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + len) {  // merge with the next block
+        len += nx->second;
+        free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(off);
+    if (pv != free_.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {  // merge with the previous block
+            pv->second += len;
+            return;
+        }
+    }
+    free_[off] = len;
+}
+
+// ---------------------------------------------------------------------------
+
+static int bits_for(uint64_t count) {  // bits to hold values 0 .. count-1
+    int b = 0;
+    while (b < 63 && (uint64_t(1) << b) < count) b++;
+    return b;
+}
+
+Lay table_layout(int b, int32_t n, int B, int k) {
+    Lay L;
+    L.b = b;
+    L.vb = std::max(1, bits_for(uint64_t(n)));
+    L.kb = k;
+    L.bb = bits_for(uint64_t(B));
+    return L;
+}
+
+uint64_t read_u64(cc_context* ctx, const uint64_t* dev) {
+    hip_check(hipMemcpyAsync(ctx->pinned, dev, 8, hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return ctx->pinned[0];
+}
+
+namespace {
+
+struct Exec {
+    cc_context* ctx;
+    hipStream_t s;
+    Arena& A;
+    std::unordered_map<void*, int> live;  // everything this run holds in the arena
+
+    void* raw(size_t bytes) {
+        void* p = A.alloc(bytes);
+        live[p] = 1;
+        return p;
+    }
+    template <class T>
+    T* alloc(uint64_t count) {
+        return (T*)raw(std::max<uint64_t>(count, 1) * sizeof(T));
+    }
+    void release(const void* p) {
+        if (!p) return;
+        live.erase(const_cast<void*>(p));
+        A.release(const_cast<void*>(p));
+    }
+    void release_all() {
+        for (auto& kv : live) A.release(kv.first);
+        live.clear();
+    }
+
+    DevTable table(Lay lay, uint64_t n) {
+        DevTable t;
+        t.lay = lay;
+        t.n = n;
+        t.keys = raw(std::max<uint64_t>(n, 1) * lay.key_bytes());
+        t.cnt = alloc<uint64_t>(n);
+        return t;
+    }
+    void drop(DevTable& t) {
+        release(t.keys);
+        release(t.cnt);
+        t.keys = nullptr;
+        t.cnt = nullptr;
+    }
+
+    // exclusive scan of n counts; returns offsets[n + 1] and the total
+    uint64_t scan(const uint32_t* in, uint64_t n, uint64_t** offs) {
+        *offs = alloc<uint64_t>(n + 1);
+        uint64_t* tmp = (uint64_t*)raw(scan_tmp_bytes(n));
+        launch_scan_u32(in, *offs, n, tmp, s);
+        release(tmp);
+        return read_u64(ctx, *offs + n);
+    }
+
+    // runs of equal key >> shift; returns G and starts[G + 1]
+    uint64_t groups(const DevTable& t, int shift, uint64_t** starts) {
+        uint32_t* flags = alloc<uint32_t>(t.n);
+        launch_heads(t.keys, t.lay.kw(), t.n, shift, flags, s);
+        uint64_t* offs;
+        uint64_t G = scan(flags, t.n, &offs);
+        *starts = alloc<uint64_t>(G + 1);
+        launch_group_starts(flags, offs, t.n, *starts, s);
+        release(flags);
+        release(offs);
+        return G;
+    }
+};
+
+}  // namespace
+
+void release_tables(cc_context* ctx, RunResult* r) {
+    for (auto& t : r->tables) {
+        ctx->arena.release(t.keys);
+        ctx->arena.release(t.cnt);
+        t.keys = nullptr;
+        t.cnt = nullptr;
+    }
+    r->tables.clear();
+}
+
+void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
+    const Plan& plan = rq.dec->plan;
+    const Decomp& dec = rq.dec->d;
+    const DevGraph g = rq.g->dev();
+    const int B = rq.B, k = rq.k;
+    if (k < dec.n || k > 12) fail(CC_ERANGE, "colours k must satisfy n_F <= k <= 12");
+    if (B < 1) fail(CC_EINVAL, "no colourings");
+    for (int b = 1; b <= plan.max_bag; b++)
+        if (table_layout(b, g.n, B, k).bits() > 128)
+            fail(CC_ERANGE, "packed key (colouring, bag images, colour set) exceeds 128 bits");
+
+    Exec X{ctx, ctx->stream, ctx->arena};
+    hipStream_t s = ctx->stream;
+    const size_t S = plan.steps.size();
+    std::vector<DevTable> tab(S);
+    std::vector<int> uses(S, 0);
+    for (const Step& st : plan.steps) {
+        if (st.in0 >= 0) uses[st.in0]++;
+        if (st.in1 >= 0) uses[st.in1]++;
+    }
+    out->node_sizes.assign(dec.nodes.size(), 0);
+    uint32_t* ovf = X.alloc<uint32_t>(B);
+    launch_fill_u32(ovf, 0, B, s);
+
+    try {
+        for (size_t i = 0; i < S; i++) {
+            const Step& st = plan.steps[i];
+            Lay lo = table_layout(st.b_out, g.n, B, k);
+            IntroArgs ia;
+            ia.pos = st.pos;
+            ia.anchor = st.anchor;
+            ia.nchk = st.nchk;
+            for (int j = 0; j < 4; j++) ia.chk[j] = st.chk[j];
+            ia.degF = rq.degree_mask ? st.degF : 0;
+            DevTable& o = tab[i];
+            switch (st.kind) {
+                case S_LEAF: {
+                    uint64_t total = uint64_t(g.n) * B;
+                    uint32_t* flags = X.alloc<uint32_t>(total);
+                    launch_leaf_count(g, B, ia.degF, flags, s);
+                    uint64_t* offs;
+                    uint64_t N = X.scan(flags, total, &offs);
+                    X.release(flags);
+                    o = X.table(lo, N);
+                    launch_leaf_emit(g, B, ia.degF, rq.colors, offs, lo, o.keys, o.cnt, s);
+                    X.release(offs);
+                    break;
+                }
+                case S_INTRO_PUSH: {
+                    const DevTable& in = tab[st.in0];
+                    if (in.n == 0) {
+                        o = X.table(lo, 0);
+                        break;
+                    }
+                    int shift = in.lay.kb + (in.lay.b - st.pos) * in.lay.vb;
+                    uint64_t* gstart;
+                    uint64_t G = X.groups(in, shift, &gstart);
+                    uint32_t* wcount = X.alloc<uint32_t>(G);
+                    launch_push_work(in, gstart, G, g, ia, wcount, s);
+                    uint64_t* woff;
+                    uint64_t W = X.scan(wcount, G, &woff);
+                    X.release(wcount);
+                    uint32_t* ocount = X.alloc<uint32_t>(W);
+                    launch_push_count(in, gstart, woff, G, W, g, rq.colors, ia, ocount, s);
+                    uint64_t* ooff;
+                    uint64_t N = X.scan(ocount, W, &ooff);
+                    X.release(ocount);
+                    o = X.table(lo, N);
+                    if (N) launch_push_emit(in, gstart, woff, G, W, g, rq.colors, ia, ooff, o, s);
+                    X.release(ooff);
+                    X.release(woff);
+                    X.release(gstart);
+                    break;
+                }
+                case S_INTRO_PULL: {
+                    const DevTable& in = tab[st.in0];
+                    if (in.n == 0) {
+                        o = X.table(lo, 0);
+                        break;
+                    }
+                    uint64_t slots = uint64_t(B) * g.n;
+                    uint64_t* rstart = X.alloc<uint64_t>(slots);
+                    uint64_t* rend = X.alloc<uint64_t>(slots);
+                    launch_fill_u64(rstart, 0, slots, s);
+                    launch_fill_u64(rend, 0, slots, s);
+                    launch_pull_index(in, g.n, rstart, rend, s);
+                    uint64_t W = uint64_t(B) * uint64_t(g.m2);
+                    uint32_t* ocount = X.alloc<uint32_t>(W);
+                    launch_pull_count(in, rstart, rend, B, g, rq.colors, ia, ocount, s);
+                    uint64_t* ooff;
+                    uint64_t N = X.scan(ocount, W, &ooff);
+                    X.release(ocount);
+                    o = X.table(lo, N);
+                    if (N) launch_pull_emit(in, rstart, rend, B, g, rq.colors, ia, ooff, o, s);
+                    X.release(ooff);
+                    X.release(rstart);
+                    X.release(rend);
+                    break;
+                }
+                case S_FORGET_LAST: {
+                    const DevTable& in = tab[st.in0];
+                    if (in.n == 0) {
+                        o = X.table(lo, 0);
+                        break;
+                    }
+                    uint64_t* gstart;
+                    uint64_t G = X.groups(in, in.lay.kb + in.lay.vb, &gstart);
+                    uint32_t* gcount = X.alloc<uint32_t>(G);
+                    launch_forget_count(in, gstart, G, gcount, s);
+                    uint64_t* goff;
+                    uint64_t N = X.scan(gcount, G, &goff);
+                    X.release(gcount);
+                    o = X.table(lo, N);
+                    launch_forget_emit(in, gstart, G, goff, o, ovf, s);
+                    X.release(goff);
+                    X.release(gstart);
+                    break;
+                }
+                case S_JOIN: {
+                    const DevTable& y = tab[st.in0];
+                    const DevTable& z = tab[st.in1];
+                    if (y.n == 0 || z.n == 0) {
+                        o = X.table(lo, 0);
+                        break;
+                    }
+                    uint64_t* gstart;
+                    uint64_t G = X.groups(y, y.lay.kb, &gstart);
+                    uint32_t* gcount = X.alloc<uint32_t>(G);
+                    launch_join_count(y, z, gstart, G, g.n, rq.colors, gcount, s);
+                    uint64_t* goff;
+                    uint64_t N = X.scan(gcount, G, &goff);
+                    X.release(gcount);
+                    o = X.table(lo, N);
+                    if (N) launch_join_emit(y, z, gstart, G, g.n, rq.colors, goff, o, ovf, s);
+                    X.release(goff);
+                    X.release(gstart);
+                    break;
+                }
+                case S_RESORT: {
+                    const DevTable& in = tab[st.in0];
+                    o = X.table(lo, in.n);
+                    if (in.n) {
+                        launch_permute(in, st.perm, o, s);
+                        void* kb2 = X.raw(in.n * lo.key_bytes());
+                        uint64_t* vb2 = X.alloc<uint64_t>(in.n);
+                        void* tmp = X.raw(radix_tmp_bytes(in.n));
+                        radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), tmp, s);
+                        X.release(tmp);
+                        X.release(vb2);
+                        X.release(kb2);
+                    }
+                    break;
+                }
+            }
+            if (st.node >= 0) out->node_sizes[st.node] = int64_t(o.n);
+            if (!rq.keep_tables) {
+                for (int in : {st.in0, st.in1})
+                    if (in >= 0 && --uses[in] == 0) X.drop(tab[in]);
+            }
+        }
+        hip_check(hipGetLastError(), "kernel launch");
+
+        // root: counts and overflow flags per colouring
+        const DevTable& rc = tab[plan.root_child];
+        uint64_t* counts = X.alloc<uint64_t>(B);
+        launch_fill_u64(counts, 0, B, s);
+        uint64_t* pv = nullptr;
+        if (rq.per_vertex) {
+            pv = X.alloc<uint64_t>(uint64_t(B) * g.n);
+            launch_fill_u64(pv, 0, uint64_t(B) * g.n, s);
+        }
+        launch_root(rc, g.n, counts, ovf, pv, s);
+        out->counts.assign(B, 0);
+        std::vector<uint32_t> of(B, 0);
+        hip_check(hipMemcpyAsync(out->counts.data(), counts, 8 * size_t(B), hipMemcpyDeviceToHost, s), "copy counts");
+        hip_check(hipMemcpyAsync(of.data(), ovf, 4 * size_t(B), hipMemcpyDeviceToHost, s), "copy flags");
+        if (pv) {
+            out->per_vertex.assign(uint64_t(B) * g.n, 0);
+            hip_check(hipMemcpyAsync(out->per_vertex.data(), pv, 8 * uint64_t(B) * g.n, hipMemcpyDeviceToHost, s),
+                      "copy per-vertex");
+        }
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        out->overflow.assign(B, 0);
+        for (int b = 0; b < B; b++) out->overflow[b] = of[b] ? 1 : 0;
+        int root_node = int(dec.nodes.size()) - 1;
+        int64_t nz = 0;
+        for (int b = 0; b < B; b++) nz += out->counts[b] || of[b];
+        out->node_sizes[root_node] = nz;
+        X.release(counts);
+        X.release(pv);
+        X.release(ovf);
+        if (rq.keep_tables) {
+            out->tables = tab;
+        } else {
+            X.drop(tab[plan.root_child]);
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        X.release_all();
+        throw;
+    }
+}
+
+}  // namespace ccg

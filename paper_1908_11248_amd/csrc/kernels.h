@@ -1,0 +1,116 @@
+// Device kernels of the colour-coding DP and their host-side launchers.
+//
+// A DP table is a pair of arrays (keys, counts), sorted ascending by key and
+// duplicate-free.  A key packs, from the most significant end:
+//     colouring index (bb bits) | image of column 0 (vb bits) | ...
+//     | image of column b-1 (vb bits) | colour set (kb bits)
+// into a uint64 when bb + b*vb + kb <= 64 and into an unsigned __int128
+// otherwise.  Counts are uint64 (mod 2^64).  Integer order of the packed keys
+// is the lexicographic order of (colouring, images, colour set).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ccg {
+
+typedef unsigned __int128 u128;
+
+struct Lay {
+    int b;   // columns
+    int vb;  // bits per vertex image
+    int kb;  // colour-set bits (= k)
+    int bb;  // colouring-index bits
+    int bits() const { return bb + b * vb + kb; }
+    int kw() const { return bits() <= 64 ? 1 : 2; }
+    size_t key_bytes() const { return kw() == 1 ? 8 : 16; }
+};
+
+struct DevGraph {
+    int32_t n;
+    int64_t m2;           // number of stored (directed) edges = 2 m
+    const int64_t* rp;    // [n + 1]
+    const int32_t* col;   // [2m], rows ascending
+    const int32_t* esrc;  // [2m], source vertex of every stored edge
+};
+
+struct DevTable {
+    void* keys = nullptr;
+    uint64_t* cnt = nullptr;
+    uint64_t n = 0;
+    Lay lay{};
+};
+
+// ---- launchers (all asynchronous on `s`) ----
+// scan: out[i] = sum_{j<i} in[j] for i <= n (out has n + 1 slots)
+void launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
+size_t scan_tmp_bytes(uint64_t n);
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+
+void launch_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed, hipStream_t s);
+
+// group heads over key >> shift: flags[i] = 1 at the first key of every run
+void launch_heads(const void* keys, int kw, uint64_t n, int shift, uint32_t* flags, hipStream_t s);
+// starts[offs[i]] = i where flags[i]; starts[G] = n
+void launch_group_starts(const uint32_t* flags, const uint64_t* offs, uint64_t n, uint64_t* starts,
+                         hipStream_t s);
+
+// leaf
+void launch_leaf_count(DevGraph g, int B, int degF, uint32_t* flags, hipStream_t s);
+void launch_leaf_emit(DevGraph g, int B, int degF, const uint8_t* colors, const uint64_t* offs, Lay lo,
+                      void* keys, uint64_t* cnt, hipStream_t s);
+
+// introduce, push form
+struct IntroArgs {
+    int pos;       // output column of the new vertex
+    int anchor;    // child column giving the candidates (-1: every vertex)
+    int nchk;      // further child columns that must be adjacent
+    int chk[4];
+    int degF;
+};
+void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, DevGraph g,
+                      const IntroArgs& a, uint32_t* wcount, hipStream_t s);
+void launch_push_count(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
+                       uint64_t W, DevGraph g, const uint8_t* colors, const IntroArgs& a,
+                       uint32_t* ocount, hipStream_t s);
+void launch_push_emit(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
+                      uint64_t W, DevGraph g, const uint8_t* colors, const IntroArgs& a,
+                      const uint64_t* ooff, DevTable& out, hipStream_t s);
+
+// introduce, pull form (child column 0 is the anchor)
+void launch_pull_index(const DevTable& in, int32_t n, uint64_t* rstart, uint64_t* rend, hipStream_t s);
+void launch_pull_count(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B,
+                       DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount,
+                       hipStream_t s);
+void launch_pull_emit(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B,
+                      DevGraph g, const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff,
+                      DevTable& out, hipStream_t s);
+
+// forget of the last column, reduced per group with a dense colour-set accumulator
+void launch_forget_count(const DevTable& in, const uint64_t* gstart, uint64_t G, uint32_t* gcount,
+                         hipStream_t s);
+void launch_forget_emit(const DevTable& in, const uint64_t* gstart, uint64_t G, const uint64_t* goff,
+                        DevTable& out, uint32_t* ovf, hipStream_t s);
+
+// join of two tables with the same layout
+void launch_join_count(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
+                       const uint8_t* colors, uint32_t* gcount, hipStream_t s);
+void launch_join_emit(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
+                      const uint8_t* colors, const uint64_t* goff, DevTable& out, uint32_t* ovf,
+                      hipStream_t s);
+
+// column permutation (out column j <- in column perm[j]) into tmp, then sort
+void launch_permute(const DevTable& in, const int* perm, DevTable& out, hipStream_t s);
+// LSD radix sort of (keys, vals) on the low `bits` bits; result in the a-buffers
+size_t radix_tmp_bytes(uint64_t n);
+void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw,
+                int bits, void* tmp, hipStream_t s);
+
+// root: counts[bid] += cnt for every entry of a one-column table; per-vertex optional
+void launch_root(const DevTable& in, int32_t n, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex,
+                 hipStream_t s);
+
+}  // namespace ccg

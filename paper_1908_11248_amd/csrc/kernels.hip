@@ -1,0 +1,906 @@
+// HIP kernels for gfx950 (CDNA4, wave64) implementing the node rules of the
+// colour-coding dynamic program (Sec. 3.1) on sorted, packed-key tables.
+//
+// Work decomposition.  Every rule whose output size is data-dependent runs
+// as count -> exclusive scan -> emit: a first kernel writes the number of
+// entries each work unit produces, a scan turns them into write offsets, and
+// the second kernel writes each unit's entries at its offset.  Units are
+// processed in key order and each unit writes its entries in key order, so
+// the output is sorted without a sort and is identical from run to run.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace ccg {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+inline unsigned grid_for(uint64_t items, int per_block = kBlock, unsigned cap = 1u << 20) {
+    uint64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return unsigned(b);
+}
+
+// ---- packed key fields ----
+template <class K>
+__device__ __forceinline__ uint32_t kcol(K key, const Lay& L, int j) {
+    return uint32_t(key >> (L.kb + (L.b - 1 - j) * L.vb)) & ((1u << L.vb) - 1u);
+}
+template <class K>
+__device__ __forceinline__ uint32_t kset(K key, const Lay& L) {
+    return uint32_t(key) & ((1u << L.kb) - 1u);
+}
+template <class K>
+__device__ __forceinline__ uint32_t kbid(K key, const Lay& L) {
+    int sh = L.kb + L.b * L.vb;
+    return sh >= int(8 * sizeof(K)) ? 0u : uint32_t(key >> sh);
+}
+template <class K>
+__device__ __forceinline__ K kpack(uint32_t bid, const uint32_t* cols, int b, uint32_t C, const Lay& L) {
+    K k = K(bid);
+    for (int j = 0; j < b; j++) k = (k << L.vb) | K(cols[j]);
+    return (k << L.kb) | K(C);
+}
+template <class K>
+__device__ __forceinline__ K shr(K key, int sh) {
+    return sh >= int(8 * sizeof(K)) ? K(0) : (key >> sh);
+}
+
+__device__ __forceinline__ int64_t gdeg(const DevGraph& g, uint32_t v) { return g.rp[v + 1] - g.rp[v]; }
+
+// {a, b} in E(G): binary search in the shorter of the two sorted rows
+__device__ __forceinline__ bool has_edge(const DevGraph& g, uint32_t a, uint32_t b) {
+    int64_t la = g.rp[a], ha = g.rp[a + 1], lb = g.rp[b], hb = g.rp[b + 1];
+    int64_t lo, hi;
+    int32_t t;
+    if (ha - la <= hb - lb) {
+        lo = la;
+        hi = ha;
+        t = int32_t(b);
+    } else {
+        lo = lb;
+        hi = hb;
+        t = int32_t(a);
+    }
+    int64_t end = hi;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (g.col[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < end && g.col[lo] == t;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    unsigned lane = __lane_id();
+    return lane ? ((~0ull) >> (64 - lane)) : 0ull;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+    int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// exclusive scan across a 256-thread block; *total = block sum
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t* total) {
+    __shared__ uint64_t wsum[kBlock / 64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; i++) {
+        if (i < w) off += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// first index in [lo, hi) of a non-decreasing array with a[i] > x
+__device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t* a, uint64_t lo, uint64_t hi, uint64_t x) {
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// scan (reduce, scan of block sums, down-sweep)
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(const T* __restrict__ in, uint64_t n, uint64_t* bsum) {
+    uint64_t base = uint64_t(blockIdx.x) * kScanTile;
+    uint64_t s = 0;
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + uint64_t(i) * kBlock + threadIdx.x;
+        if (idx < n) s += uint64_t(in[idx]);
+    }
+    uint64_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_scan_down(const T* __restrict__ in, uint64_t n,
+                                                      const uint64_t* __restrict__ boff, uint64_t* out) {
+    uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
+    uint64_t vals[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + i;
+        vals[i] = idx < n ? uint64_t(in[idx]) : 0;
+        s += vals[i];
+    }
+    uint64_t tot;
+    uint64_t off = block_excl_scan(s, &tot) + (boff ? boff[blockIdx.x] : 0);
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + i;
+        if (idx < n) out[idx] = off;
+        off += vals[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) out[n] = off;
+}
+
+static size_t scan_tmp_rec(uint64_t n) {
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 1) return 0;
+    return (2 * (nb + 1)) * sizeof(uint64_t) + scan_tmp_rec(nb);
+}
+
+size_t scan_tmp_bytes(uint64_t n) { return scan_tmp_rec(n) + 256; }
+
+template <class T>
+static void scan_rec(const T* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 1) {
+        k_scan_down<T><<<1, kBlock, 0, s>>>(in, n, nullptr, out);
+        return;
+    }
+    uint64_t* bsum = tmp;
+    uint64_t* boff = tmp + (nb + 1);
+    k_scan_reduce<T><<<unsigned(nb), kBlock, 0, s>>>(in, n, bsum);
+    scan_rec<uint64_t>(bsum, boff, nb, tmp + 2 * (nb + 1), s);
+    k_scan_down<T><<<unsigned(nb), kBlock, 0, s>>>(in, n, boff, out);
+}
+
+void launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
+    scan_rec<uint32_t>(in, out, n, tmp, s);
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {
+    if (n) k_fill_u64<<<grid_for(n), kBlock, 0, s>>>(p, v, n);
+}
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+    if (n) k_fill_u32<<<grid_for(n), kBlock, 0, s>>>(p, v, n);
+}
+
+// ---------------------------------------------------------------------------
+// random colouring: splitmix64 of (seed XOR (b * 2^32 + v)), high word scaled to [0, k)
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed) {
+    uint64_t total = uint64_t(n) * uint64_t(B);
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        uint64_t b = i / uint64_t(n), v = i % uint64_t(n);
+        uint64_t h = splitmix64(seed ^ ((b << 32) + v));
+        colors[i] = uint8_t(((h >> 32) * uint64_t(k)) >> 32);
+    }
+}
+
+void launch_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed, hipStream_t s) {
+    uint64_t total = uint64_t(n) * uint64_t(B);
+    if (total) k_color_hash<<<grid_for(total), kBlock, 0, s>>>(colors, n, B, k, seed);
+}
+
+// ---------------------------------------------------------------------------
+// run heads and run starts
+
+template <class K>
+__global__ void k_heads(const K* __restrict__ keys, uint64_t n, int shift, uint32_t* flags) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t f = 1;
+        if (i > 0) f = shr(keys[i], shift) != shr(keys[i - 1], shift);
+        flags[i] = f;
+    }
+}
+
+void launch_heads(const void* keys, int kw, uint64_t n, int shift, uint32_t* flags, hipStream_t s) {
+    if (!n) return;
+    if (kw == 1)
+        k_heads<uint64_t><<<grid_for(n), kBlock, 0, s>>>((const uint64_t*)keys, n, shift, flags);
+    else
+        k_heads<u128><<<grid_for(n), kBlock, 0, s>>>((const u128*)keys, n, shift, flags);
+}
+
+__global__ void k_group_starts(const uint32_t* flags, const uint64_t* offs, uint64_t n, uint64_t* starts) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        if (flags[i]) starts[offs[i]] = i;
+    if (blockIdx.x == 0 && threadIdx.x == 0) starts[offs[n]] = n;
+}
+
+void launch_group_starts(const uint32_t* flags, const uint64_t* offs, uint64_t n, uint64_t* starts,
+                         hipStream_t s) {
+    k_group_starts<<<grid_for(n), kBlock, 0, s>>>(flags, offs, n, starts);
+}
+
+// ---------------------------------------------------------------------------
+// leaf (Sec. 3.1): u -> v for every v with deg_G(v) >= deg_F(u) (Sec. 3.2)
+
+__global__ void k_leaf_count(DevGraph g, int B, int degF, uint32_t* flags) {
+    uint64_t total = uint64_t(g.n) * B;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t v = uint32_t(i % uint64_t(g.n));
+        flags[i] = gdeg(g, v) >= degF;
+    }
+}
+
+template <class K>
+__global__ void k_leaf_emit(DevGraph g, int B, int degF, const uint8_t* __restrict__ colors,
+                            const uint64_t* __restrict__ offs, Lay lo, K* keys, uint64_t* cnt) {
+    uint64_t total = uint64_t(g.n) * B;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t v = uint32_t(i % uint64_t(g.n));
+        uint32_t bid = uint32_t(i / uint64_t(g.n));
+        if (gdeg(g, v) < degF) continue;
+        uint64_t o = offs[i];
+        keys[o] = kpack<K>(bid, &v, 1, 1u << colors[i], lo);
+        cnt[o] = 1;
+    }
+}
+
+void launch_leaf_count(DevGraph g, int B, int degF, uint32_t* flags, hipStream_t s) {
+    uint64_t total = uint64_t(g.n) * B;
+    if (total) k_leaf_count<<<grid_for(total), kBlock, 0, s>>>(g, B, degF, flags);
+}
+
+void launch_leaf_emit(DevGraph g, int B, int degF, const uint8_t* colors, const uint64_t* offs, Lay lo,
+                      void* keys, uint64_t* cnt, hipStream_t s) {
+    uint64_t total = uint64_t(g.n) * B;
+    if (!total) return;
+    if (lo.kw() == 1)
+        k_leaf_emit<uint64_t><<<grid_for(total), kBlock, 0, s>>>(g, B, degF, colors, offs, lo, (uint64_t*)keys, cnt);
+    else
+        k_leaf_emit<u128><<<grid_for(total), kBlock, 0, s>>>(g, B, degF, colors, offs, lo, (u128*)keys, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// introduce, push form (Sec. 3.1 introduce rule, candidates from the adjacency
+// list of a mapped bag neighbour, Sec. 3.2).  Work unit = (prefix group,
+// candidate); the group holds every child entry sharing the images of the
+// columns before the insertion point.
+
+template <class K>
+__global__ void k_push_work(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gstart, uint64_t G,
+                            DevGraph g, int anchor, uint32_t* wcount) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < G; i += uint64_t(gridDim.x) * blockDim.x) {
+        if (anchor < 0) {
+            wcount[i] = uint32_t(g.n);
+        } else {
+            uint32_t a = kcol(keys[gstart[i]], L, anchor);
+            wcount[i] = uint32_t(gdeg(g, a));
+        }
+    }
+}
+
+template <class KI, class KO, bool EMIT>
+__global__ void __launch_bounds__(kBlock)
+k_push(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ gstart,
+       const uint64_t* __restrict__ woff, uint64_t G, uint64_t W, DevGraph g, const uint8_t* __restrict__ colors,
+       IntroArgs a, uint32_t* ocount, const uint64_t* __restrict__ ooff, KO* okeys, uint64_t* ocnt, Lay LO) {
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < W; w += uint64_t(gridDim.x) * blockDim.x) {
+        uint64_t grp = upper_bound_u64(woff, 0, G + 1, w) - 1;
+        uint64_t t = w - woff[grp];
+        uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
+        KI k0 = keys[e0];
+        uint32_t bid = kbid(k0, L);
+        uint32_t v = a.anchor >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, a.anchor)] + int64_t(t)]) : uint32_t(t);
+        uint32_t produced = 0;
+        bool ok = gdeg(g, v) >= a.degF;
+        for (int c = 0; c < a.nchk && ok; c++)
+            if (a.chk[c] < a.pos) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
+        uint64_t o = EMIT ? ooff[w] : 0;
+        if (ok) {
+            uint32_t cb = 1u << colors[uint64_t(bid) * g.n + v];
+            for (uint64_t e = e0; e < e1; e++) {
+                KI k = keys[e];
+                uint32_t C = kset(k, L);
+                if (C & cb) continue;
+                bool fine = true;
+                for (int c = 0; c < a.nchk && fine; c++)
+                    if (a.chk[c] >= a.pos) fine = has_edge(g, kcol(k, L, a.chk[c]), v);
+                if (!fine) continue;
+                if (EMIT) {
+                    uint32_t cols[5];
+                    for (int j = 0, s = 0; j < LO.b; j++) cols[j] = (j == a.pos) ? v : kcol(k, L, s++);
+                    okeys[o] = kpack<KO>(bid, cols, LO.b, C | cb, LO);
+                    ocnt[o] = cnt[e];
+                    o++;
+                } else {
+                    produced++;
+                }
+            }
+        }
+        if (!EMIT) ocount[w] = produced;
+    }
+}
+
+void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, DevGraph g, const IntroArgs& a,
+                      uint32_t* wcount, hipStream_t s) {
+    if (!G) return;
+    if (in.lay.kw() == 1)
+        k_push_work<uint64_t><<<grid_for(G), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, gstart, G, g, a.anchor, wcount);
+    else
+        k_push_work<u128><<<grid_for(G), kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, G, g, a.anchor, wcount);
+}
+
+template <bool EMIT>
+static void push_dispatch(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
+                          DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount,
+                          const uint64_t* ooff, DevTable* out, hipStream_t s) {
+    if (!W) return;
+    Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
+    void* ok = out ? out->keys : nullptr;
+    uint64_t* oc = out ? out->cnt : nullptr;
+    unsigned grid = grid_for(W);
+    int ki = in.lay.kw(), ko = LO.kw();
+    if (ki == 1 && ko == 1)
+        k_push<uint64_t, uint64_t, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff, G, W,
+                                                                 g, colors, a, ocount, ooff, (uint64_t*)ok, oc, LO);
+    else if (ki == 1 && ko == 2)
+        k_push<uint64_t, u128, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff, G, W,
+                                                             g, colors, a, ocount, ooff, (u128*)ok, oc, LO);
+    else
+        k_push<u128, u128, EMIT><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, gstart, woff, G, W, g,
+                                                         colors, a, ocount, ooff, (u128*)ok, oc, LO);
+}
+
+void launch_push_count(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
+                       DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, hipStream_t s) {
+    push_dispatch<false>(in, gstart, woff, G, W, g, colors, a, ocount, nullptr, nullptr, s);
+}
+void launch_push_emit(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
+                      DevGraph g, const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff, DevTable& out,
+                      hipStream_t s) {
+    push_dispatch<true>(in, gstart, woff, G, W, g, colors, a, nullptr, ooff, &out, s);
+}
+
+// ---------------------------------------------------------------------------
+// introduce, pull form: u inserted as column 0.  For every colouring b and
+// every stored edge (v, y) of G (rows ascending), the child's run of entries
+// with column 0 = y is extended by u -> v.  Output order: (b, v, y, rest, C).
+
+template <class K>
+__global__ void k_pull_index(const K* __restrict__ keys, uint64_t N, Lay L, int32_t n, uint64_t* rstart,
+                             uint64_t* rend) {
+    int sh = L.kb + (L.b - 1) * L.vb;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += uint64_t(gridDim.x) * blockDim.x) {
+        K k = keys[i];
+        K p = shr(k, sh);
+        uint64_t slot = uint64_t(kbid(k, L)) * uint64_t(n) + kcol(k, L, 0);
+        if (i == 0 || shr(keys[i - 1], sh) != p) rstart[slot] = i;
+        if (i + 1 == N || shr(keys[i + 1], sh) != p) rend[slot] = i + 1;
+    }
+}
+
+void launch_pull_index(const DevTable& in, int32_t n, uint64_t* rstart, uint64_t* rend, hipStream_t s) {
+    if (!in.n) return;
+    if (in.lay.kw() == 1)
+        k_pull_index<uint64_t><<<grid_for(in.n), kBlock, 0, s>>>((const uint64_t*)in.keys, in.n, in.lay, n, rstart, rend);
+    else
+        k_pull_index<u128><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.n, in.lay, n, rstart, rend);
+}
+
+template <class KI, class KO, bool EMIT>
+__global__ void __launch_bounds__(kBlock)
+k_pull(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ rstart,
+       const uint64_t* __restrict__ rend, int B, DevGraph g, const uint8_t* __restrict__ colors, IntroArgs a,
+       uint32_t* ocount, const uint64_t* __restrict__ ooff, KO* okeys, uint64_t* ocnt, Lay LO) {
+    uint64_t W = uint64_t(B) * uint64_t(g.m2);
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < W; w += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t bid = uint32_t(w / uint64_t(g.m2));
+        uint64_t e = w % uint64_t(g.m2);
+        uint32_t v = uint32_t(g.esrc[e]);
+        uint32_t y = uint32_t(g.col[e]);
+        uint32_t produced = 0;
+        uint64_t o = EMIT ? ooff[w] : 0;
+        if (gdeg(g, v) >= a.degF) {
+            uint64_t slot = uint64_t(bid) * uint64_t(g.n) + y;
+            uint64_t r0 = rstart[slot], r1 = rend[slot];
+            uint32_t cb = 1u << colors[uint64_t(bid) * g.n + v];
+            for (uint64_t i = r0; i < r1; i++) {
+                KI k = keys[i];
+                uint32_t C = kset(k, L);
+                if (C & cb) continue;
+                bool fine = true;
+                for (int c = 0; c < a.nchk && fine; c++) fine = has_edge(g, kcol(k, L, a.chk[c]), v);
+                if (!fine) continue;
+                if (EMIT) {
+                    uint32_t cols[5];
+                    cols[0] = v;
+                    for (int j = 1; j < LO.b; j++) cols[j] = kcol(k, L, j - 1);
+                    okeys[o] = kpack<KO>(bid, cols, LO.b, C | cb, LO);
+                    ocnt[o] = cnt[i];
+                    o++;
+                } else {
+                    produced++;
+                }
+            }
+        }
+        if (!EMIT) ocount[w] = produced;
+    }
+}
+
+template <bool EMIT>
+static void pull_dispatch(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
+                          const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, const uint64_t* ooff,
+                          DevTable* out, hipStream_t s) {
+    uint64_t W = uint64_t(B) * uint64_t(g.m2);
+    if (!W) return;
+    Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
+    void* ok = out ? out->keys : nullptr;
+    uint64_t* oc = out ? out->cnt : nullptr;
+    unsigned grid = grid_for(W);
+    int ki = in.lay.kw(), ko = LO.kw();
+    if (ki == 1 && ko == 1)
+        k_pull<uint64_t, uint64_t, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, rstart, rend, B, g,
+                                                                 colors, a, ocount, ooff, (uint64_t*)ok, oc, LO);
+    else if (ki == 1 && ko == 2)
+        k_pull<uint64_t, u128, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, rstart, rend, B, g,
+                                                             colors, a, ocount, ooff, (u128*)ok, oc, LO);
+    else
+        k_pull<u128, u128, EMIT><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, rstart, rend, B, g, colors,
+                                                         a, ocount, ooff, (u128*)ok, oc, LO);
+}
+
+void launch_pull_count(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
+                       const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, hipStream_t s) {
+    pull_dispatch<false>(in, rstart, rend, B, g, colors, a, ocount, nullptr, nullptr, s);
+}
+void launch_pull_emit(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
+                      const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff, DevTable& out, hipStream_t s) {
+    pull_dispatch<true>(in, rstart, rend, B, g, colors, a, nullptr, ooff, &out, s);
+}
+
+// ---------------------------------------------------------------------------
+// Dense colour-set accumulator, one 64-lane workgroup per group: 2^k uint64
+// counters plus a 2^k-bit presence mask in LDS.  Presence is tracked apart
+// from the counters because a count may be 0 modulo 2^64 while the entry
+// exists (the paper's nonzero configuration).
+
+struct Acc {
+    uint64_t* val;   // [1 << kb]
+    uint32_t* bits;  // [max(1, (1 << kb) / 32)]
+    int kb;
+    __device__ int slots() const { return 1 << kb; }
+    __device__ int words() const { return kb >= 5 ? (1 << (kb - 5)) : 1; }
+};
+
+// with values == false only the presence mask is allocated (count passes)
+__device__ __forceinline__ Acc acc_bind(int kb, bool values) {
+    extern __shared__ uint64_t smem[];
+    Acc a;
+    a.kb = kb;
+    a.val = values ? smem : nullptr;
+    a.bits = reinterpret_cast<uint32_t*>(values ? smem + (1 << kb) : smem);
+    return a;
+}
+
+static size_t acc_bytes(int kb, bool values) {
+    size_t words = kb >= 5 ? (size_t(1) << (kb - 5)) : 1;
+    return (values ? (size_t(8) << kb) : 0) + 4 * words;
+}
+
+__device__ __forceinline__ void acc_clear(Acc& a, bool values) {
+    int lane = threadIdx.x;
+    if (values)
+        for (int i = lane; i < a.slots(); i += 64) a.val[i] = 0;
+    for (int i = lane; i < a.words(); i += 64) a.bits[i] = 0;
+}
+
+__device__ __forceinline__ uint32_t acc_count(const Acc& a) {
+    uint64_t c = 0;
+    for (int i = threadIdx.x; i < a.words(); i += 64) c += __popc(a.bits[i]);
+    return uint32_t(wave_sum(c));
+}
+
+// writes the present slots in increasing colour-set order
+template <class KO>
+__device__ __forceinline__ void acc_emit(const Acc& a, KO prefix, uint64_t base, KO* okeys, uint64_t* ocnt) {
+    uint64_t run = 0;
+    int lane = threadIdx.x;
+    for (int c0 = 0; c0 < a.slots(); c0 += 64) {
+        int C = c0 + lane;
+        bool present = C < a.slots() && ((a.bits[C >> 5] >> (C & 31)) & 1u);
+        uint64_t m = __ballot(present);
+        if (present) {
+            uint64_t o = base + run + __popcll(m & lanemask_lt());
+            okeys[o] = prefix | KO(C);
+            ocnt[o] = a.val[C];
+        }
+        run += __popcll(m);
+    }
+}
+
+// forget of the last column (Sec. 3.1 forget rule): per run of equal
+// (colouring, first b-1 images), add the counts of equal colour sets.
+template <class KI, class KO, bool EMIT>
+__global__ void __launch_bounds__(64)
+k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ gstart,
+         uint64_t G, uint32_t* gcount, const uint64_t* __restrict__ goff, KO* okeys, uint64_t* ocnt, uint32_t* ovf) {
+    Acc acc = acc_bind(L.kb, EMIT);
+    const int sh = L.kb + L.vb;  // drop the colour set and the last column
+    for (uint64_t grp = blockIdx.x; grp < G; grp += gridDim.x) {
+        uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
+        acc_clear(acc, EMIT);
+        __syncthreads();
+        bool over = false;
+        for (uint64_t e = e0 + threadIdx.x; e < e1; e += 64) {
+            uint32_t C = kset(keys[e], L);
+            atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
+            if (EMIT) {
+                uint64_t c = cnt[e];
+                uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)c);
+                over |= (old + c < old);
+            }
+        }
+        __syncthreads();
+        if (EMIT) {
+            KI k0 = keys[e0];
+            if (__ballot(over) && threadIdx.x == 0) atomicOr(&ovf[kbid(k0, L)], 1u);
+            KO prefix = KO(shr(k0, sh)) << L.kb;
+            acc_emit<KO>(acc, prefix, goff[grp], okeys, ocnt);
+        } else {
+            uint32_t c = acc_count(acc);
+            if (threadIdx.x == 0) gcount[grp] = c;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool EMIT>
+static void forget_dispatch(const DevTable& in, const uint64_t* gstart, uint64_t G, uint32_t* gcount,
+                            const uint64_t* goff, DevTable* out, uint32_t* ovf, hipStream_t s) {
+    if (!G) return;
+    Lay LO{in.lay.b - 1, in.lay.vb, in.lay.kb, in.lay.bb};
+    unsigned grid = unsigned(G < (1u << 20) ? G : (1u << 20));
+    size_t lds = acc_bytes(in.lay.kb, EMIT);
+    int ki = in.lay.kw(), ko = LO.kw();
+    void* okk = out ? out->keys : nullptr;
+    uint64_t* oc = out ? out->cnt : nullptr;
+    if (ki == 1)
+        k_forget<uint64_t, uint64_t, EMIT><<<grid, 64, lds, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, G, gcount,
+                                                                 goff, (uint64_t*)okk, oc, ovf);
+    else if (ko == 1)
+        k_forget<u128, uint64_t, EMIT><<<grid, 64, lds, s>>>((const u128*)in.keys, in.cnt, in.lay, gstart, G, gcount, goff,
+                                                             (uint64_t*)okk, oc, ovf);
+    else
+        k_forget<u128, u128, EMIT><<<grid, 64, lds, s>>>((const u128*)in.keys, in.cnt, in.lay, gstart, G, gcount, goff,
+                                                         (u128*)okk, oc, ovf);
+}
+
+void launch_forget_count(const DevTable& in, const uint64_t* gstart, uint64_t G, uint32_t* gcount, hipStream_t s) {
+    forget_dispatch<false>(in, gstart, G, gcount, nullptr, nullptr, nullptr, s);
+}
+void launch_forget_emit(const DevTable& in, const uint64_t* gstart, uint64_t G, const uint64_t* goff, DevTable& out,
+                        uint32_t* ovf, hipStream_t s) {
+    forget_dispatch<true>(in, gstart, G, nullptr, goff, &out, ovf, s);
+}
+
+// ---------------------------------------------------------------------------
+// join (Sec. 3.1 join rule): for equal (colouring, images) in both children,
+// every pair with C' n C'' equal to the colour set of the bag's images gives
+// C' u C'' with count c' c''; equal results add.  One workgroup per run of
+// the first child; the matching run of the second is found by binary search.
+
+template <class K>
+__device__ __forceinline__ uint64_t lower_bound_prefix(const K* keys, uint64_t n, K p, int sh, bool strict) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        K q = shr(keys[mid], sh);
+        if (q < p || (strict && q == p)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <class K, bool EMIT>
+__global__ void __launch_bounds__(64)
+k_join(const K* __restrict__ yk, const uint64_t* __restrict__ yc, const K* __restrict__ zk,
+       const uint64_t* __restrict__ zc, uint64_t nz, Lay L, const uint64_t* __restrict__ gstart, uint64_t G, int32_t n,
+       const uint8_t* __restrict__ colors, uint32_t* gcount, const uint64_t* __restrict__ goff, K* okeys,
+       uint64_t* ocnt, uint32_t* ovf) {
+    Acc acc = acc_bind(L.kb, EMIT);
+    const int sh = L.kb;
+    for (uint64_t grp = blockIdx.x; grp < G; grp += gridDim.x) {
+        uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
+        K k0 = yk[e0];
+        K p = shr(k0, sh);
+        uint64_t z0 = lower_bound_prefix(zk, nz, p, sh, false);
+        uint64_t z1 = lower_bound_prefix(zk, nz, p, sh, true);
+        if (z0 == z1) {  // no matching mapping in the second child
+            if (!EMIT && threadIdx.x == 0) gcount[grp] = 0;
+            continue;
+        }
+        uint32_t bid = kbid(k0, L);
+        uint32_t bagcol = 0;
+        for (int j = 0; j < L.b; j++) bagcol |= 1u << colors[uint64_t(bid) * n + kcol(k0, L, j)];
+        acc_clear(acc, EMIT);
+        __syncthreads();
+        bool over = false;
+        uint64_t ny = e1 - e0, nzg = z1 - z0;
+        for (uint64_t a = 0; a < ny; a++) {
+            uint32_t Cy = kset(yk[e0 + a], L);
+            uint64_t cy = EMIT ? yc[e0 + a] : 0;
+            for (uint64_t d = threadIdx.x; d < nzg; d += 64) {
+                uint32_t Cz = kset(zk[z0 + d], L);
+                if ((Cy & Cz) != bagcol) continue;
+                uint32_t C = Cy | Cz;
+                atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
+                if (EMIT) {
+                    uint64_t cz = zc[z0 + d];
+                    uint64_t prod = cy * cz;
+                    over |= __umul64hi(cy, cz) != 0;
+                    uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)prod);
+                    over |= (old + prod < old);
+                }
+            }
+        }
+        __syncthreads();
+        if (EMIT) {
+            if (__ballot(over) && threadIdx.x == 0) atomicOr(&ovf[bid], 1u);
+            acc_emit<K>(acc, p << L.kb, goff[grp], okeys, ocnt);
+        } else {
+            uint32_t c = acc_count(acc);
+            if (threadIdx.x == 0) gcount[grp] = c;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool EMIT>
+static void join_dispatch(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
+                          const uint8_t* colors, uint32_t* gcount, const uint64_t* goff, DevTable* out, uint32_t* ovf,
+                          hipStream_t s) {
+    if (!G) return;
+    unsigned grid = unsigned(G < (1u << 20) ? G : (1u << 20));
+    size_t lds = acc_bytes(y.lay.kb, EMIT);
+    void* okk = out ? out->keys : nullptr;
+    uint64_t* oc = out ? out->cnt : nullptr;
+    if (y.lay.kw() == 1)
+        k_join<uint64_t, EMIT><<<grid, 64, lds, s>>>((const uint64_t*)y.keys, y.cnt, (const uint64_t*)z.keys, z.cnt, z.n,
+                                                     y.lay, gstart, G, n, colors, gcount, goff, (uint64_t*)okk, oc, ovf);
+    else
+        k_join<u128, EMIT><<<grid, 64, lds, s>>>((const u128*)y.keys, y.cnt, (const u128*)z.keys, z.cnt, z.n, y.lay, gstart,
+                                                 G, n, colors, gcount, goff, (u128*)okk, oc, ovf);
+}
+
+void launch_join_count(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
+                       const uint8_t* colors, uint32_t* gcount, hipStream_t s) {
+    join_dispatch<false>(y, z, gstart, G, n, colors, gcount, nullptr, nullptr, nullptr, s);
+}
+void launch_join_emit(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
+                      const uint8_t* colors, const uint64_t* goff, DevTable& out, uint32_t* ovf, hipStream_t s) {
+    join_dispatch<true>(y, z, gstart, G, n, colors, nullptr, goff, &out, ovf, s);
+}
+
+// ---------------------------------------------------------------------------
+// column permutation + LSD radix sort (stable, 8-bit digits)
+
+struct Perm {
+    int p[4];
+};
+
+template <class KI, class KO>
+__global__ void k_permute(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, uint64_t N, Lay L, Perm pm,
+                          Lay LO, KO* okeys, uint64_t* ocnt) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += uint64_t(gridDim.x) * blockDim.x) {
+        KI k = keys[i];
+        uint32_t cols[4];
+        for (int j = 0; j < LO.b; j++) cols[j] = kcol(k, L, pm.p[j]);
+        okeys[i] = kpack<KO>(kbid(k, L), cols, LO.b, kset(k, L), LO);
+        ocnt[i] = cnt[i];
+    }
+}
+
+void launch_permute(const DevTable& in, const int* perm, DevTable& out, hipStream_t s) {
+    if (!in.n) return;
+    Perm pm{{perm[0], perm[1], perm[2], perm[3]}};
+    unsigned grid = grid_for(in.n);
+    int ki = in.lay.kw(), ko = out.lay.kw();
+    if (ki == 1 && ko == 1)
+        k_permute<uint64_t, uint64_t><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, pm, out.lay,
+                                                              (uint64_t*)out.keys, out.cnt);
+    else if (ki == 2 && ko == 2)
+        k_permute<u128, u128><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, pm, out.lay,
+                                                      (u128*)out.keys, out.cnt);
+    else if (ki == 1)
+        k_permute<uint64_t, u128><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, pm, out.lay,
+                                                          (u128*)out.keys, out.cnt);
+    else
+        k_permute<u128, uint64_t><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, pm, out.lay,
+                                                          (uint64_t*)out.keys, out.cnt);
+}
+
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kBlock * kRadixItems;
+
+template <class K>
+__global__ void __launch_bounds__(kBlock) k_radix_hist(const K* __restrict__ keys, uint64_t n, int shift, uint32_t* hist,
+                                                       uint64_t nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t base = uint64_t(blockIdx.x) * kRadixTile;
+    for (int r = 0; r < kRadixItems; r++) {
+        uint64_t i = base + uint64_t(r) * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[uint32_t(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[uint64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// stable scatter: items are ranked in (round, wave, lane) order, which is
+// their order in the input
+template <class K>
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const K* __restrict__ keys, const uint64_t* __restrict__ vals,
+                                                          uint64_t n, int shift, const uint64_t* __restrict__ offs,
+                                                          uint64_t nblk, K* okeys, uint64_t* ovals) {
+    __shared__ uint64_t run[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    run[threadIdx.x] = offs[uint64_t(threadIdx.x) * nblk + blockIdx.x];
+    for (int i = lane; i < 256; i += 64) wcnt[w][i] = 0;
+    __syncthreads();
+    uint64_t base = uint64_t(blockIdx.x) * kRadixTile;
+    for (int r = 0; r < kRadixItems; r++) {
+        uint64_t i = base + uint64_t(r) * kBlock + threadIdx.x;
+        bool valid = i < n;
+        K k = valid ? keys[i] : K(0);
+        uint32_t d = valid ? (uint32_t(k >> shift) & 255u) : 0u;
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; bit++) {
+            bool on = (d >> bit) & 1u;
+            uint64_t m = __ballot(on);
+            same &= on ? m : ~m;
+        }
+        uint32_t rank_in_wave = __popcll(same & lanemask_lt());
+        bool leader = valid && rank_in_wave == 0;
+        if (leader) wcnt[w][d] = __popcll(same);
+        __syncthreads();
+        uint64_t dest = 0;
+        if (valid) {
+            dest = run[d] + rank_in_wave;
+            for (int q = 0; q < w; q++) dest += wcnt[q][d];
+        }
+        __syncthreads();
+        {
+            uint32_t t = 0;
+            for (int q = 0; q < kBlock / 64; q++) {
+                t += wcnt[q][threadIdx.x];
+            }
+            run[threadIdx.x] += t;
+            for (int q = 0; q < kBlock / 64; q++) wcnt[q][threadIdx.x] = 0;
+        }
+        __syncthreads();
+        if (valid) {
+            okeys[dest] = k;
+            ovals[dest] = vals[i];
+        }
+    }
+}
+
+size_t radix_tmp_bytes(uint64_t n) {
+    uint64_t nblk = (n + kRadixTile - 1) / kRadixTile;
+    uint64_t h = 256 * nblk;
+    return h * 4 + (h + 1) * 8 + scan_tmp_bytes(h) + 256;
+}
+
+void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, void* tmp,
+                hipStream_t s) {
+    if (n <= 1 || bits <= 0) return;
+    uint64_t nblk = (n + kRadixTile - 1) / kRadixTile;
+    uint64_t h = 256 * nblk;
+    uint32_t* hist = (uint32_t*)tmp;
+    uint64_t* offs = (uint64_t*)((char*)tmp + ((h * 4 + 255) / 256) * 256);
+    uint64_t* stmp = offs + h + 1;
+    int passes = (bits + 7) / 8;
+    void* src_k = keys_a;
+    uint64_t* src_v = vals_a;
+    void* dst_k = keys_b;
+    uint64_t* dst_v = vals_b;
+    for (int p = 0; p < passes; p++) {
+        int shift = 8 * p;
+        if (kw == 1) {
+            k_radix_hist<uint64_t><<<unsigned(nblk), kBlock, 0, s>>>((const uint64_t*)src_k, n, shift, hist, nblk);
+        } else {
+            k_radix_hist<u128><<<unsigned(nblk), kBlock, 0, s>>>((const u128*)src_k, n, shift, hist, nblk);
+        }
+        launch_scan_u32(hist, offs, h, stmp, s);
+        if (kw == 1)
+            k_radix_scatter<uint64_t><<<unsigned(nblk), kBlock, 0, s>>>((const uint64_t*)src_k, src_v, n, shift, offs, nblk,
+                                                                        (uint64_t*)dst_k, dst_v);
+        else
+            k_radix_scatter<u128><<<unsigned(nblk), kBlock, 0, s>>>((const u128*)src_k, src_v, n, shift, offs, nblk,
+                                                                    (u128*)dst_k, dst_v);
+        void* tk = src_k;
+        src_k = dst_k;
+        dst_k = tk;
+        uint64_t* tv = src_v;
+        src_v = dst_v;
+        dst_v = tv;
+    }
+    if (src_k != keys_a) {
+        (void)hipMemcpyAsync(keys_a, src_k, n * (kw == 1 ? 8 : 16), hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(vals_a, src_v, n * 8, hipMemcpyDeviceToDevice, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// root (Sec. 3.1, last paragraph): the count of colouring b is the sum of the
+// entries of the node below the root (bag {r0}) for that colouring.
+
+template <class K>
+__global__ void k_root(const K* __restrict__ keys, const uint64_t* __restrict__ cnt, uint64_t N, Lay L, int32_t n,
+                       uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += uint64_t(gridDim.x) * blockDim.x) {
+        K k = keys[i];
+        uint32_t bid = kbid(k, L);
+        uint64_t c = cnt[i];
+        uint64_t old = atomicAdd((unsigned long long*)&counts[bid], (unsigned long long)c);
+        if (old + c < old) atomicOr(&ovf[bid], 1u);
+        if (per_vertex) atomicAdd((unsigned long long*)&per_vertex[uint64_t(bid) * n + kcol(k, L, 0)], (unsigned long long)c);
+    }
+}
+
+void launch_root(const DevTable& in, int32_t n, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, hipStream_t s) {
+    if (!in.n) return;
+    if (in.lay.kw() == 1)
+        k_root<uint64_t><<<grid_for(in.n), kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, n, counts, ovf,
+                                                           per_vertex);
+    else
+        k_root<u128><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, n, counts, ovf, per_vertex);
+}
+
+}  // namespace ccg
