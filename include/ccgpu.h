@@ -144,6 +144,21 @@ int cc_enumerate(cc_context *ctx, const cc_graph *g, const cc_coloring *c, int32
  * up to cap nodes; *n_nodes receives the node count. */
 int cc_last_table_sizes(const cc_context *ctx, int64_t *entries, size_t cap, size_t *n_nodes);
 
+/* Per-kernel timing.  cc_profile_enable(ctx, 1) clears the statistics and
+ * starts recording a HIP event pair around every kernel launch the library
+ * makes on the context's stream; cc_profile_read copies up to cap records
+ * (launches, total milliseconds, algorithmic bytes summed over launches:
+ * the bytes the kernel's rule must read and write, not the bytes the
+ * hardware moved).  Recording adds a little host overhead per launch. */
+typedef struct {
+    char name[32];
+    uint64_t launches;
+    double total_ms;
+    double algo_bytes;
+} cc_kernel_stat;
+int cc_profile_enable(cc_context *ctx, int enable);
+int cc_profile_read(cc_context *ctx, cc_kernel_stat *stats, size_t cap, size_t *n);
+
 /* ---------------------------------------------------------------------- */
 /* Batched queries: many (decomposition, colouring) pairs over one graph,
  * scheduled together.  counts_flat / overflow_flat receive, query after

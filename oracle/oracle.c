@@ -591,7 +591,7 @@ static int bag_pos(const table_t *t, int v) {
 }
 
 /* sort by (phi, C) and add the counts of equal keys (mod 2^64). */
-static const table_t *g_sort_tab;
+static _Thread_local const table_t *g_sort_tab; /* qsort context, one per thread */
 static int cmp_entry(const void *pa, const void *pb) {
     size_t a = *(const size_t *)pa, b = *(const size_t *)pb;
     const table_t *t = g_sort_tab;
@@ -1144,7 +1144,7 @@ static int R(rec_t *s, int x, const mset_t *M, llist_t *L) {
     return rc;
 }
 
-static int g_nF_cmp;
+static _Thread_local int g_nF_cmp;
 static int cmp_row(const void *a, const void *b) {
     const int32_t *x = a, *y = b;
     for (int i = 0; i < g_nF_cmp; i++)

@@ -32,6 +32,7 @@ EXPORTS = [
     "cc_graph_num_vertices", "cc_color", "cc_color_explicit", "cc_coloring_download", "cc_coloring_free",
     "cc_build_decomposition", "cc_decomp_export", "cc_decomp_import", "cc_decomp_width", "cc_decomp_free",
     "cc_count", "cc_count_by_vertex", "cc_enumerate", "cc_last_table_sizes", "cc_count_batch",
+    "cc_profile_enable", "cc_profile_read",
 ]
 
 
@@ -77,6 +78,8 @@ def lib():
             "cc_enumerate": (ctypes.c_int, [P, P, P, I32, P, U64, P, P, P]),
             "cc_last_table_sizes": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
             "cc_count_batch": (ctypes.c_int, [P, P, I32, P, U32, P, P]),
+            "cc_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
+            "cc_profile_read": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -159,6 +162,11 @@ class Decomp(_Handle):
         return buf
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("algo_bytes", ctypes.c_double)]
+
+
 class Context(_Handle):
     _free = None
 
@@ -177,6 +185,19 @@ class Context(_Handle):
 
     def __exit__(self, *a):
         self.close()
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().cc_profile_enable(self.ptr, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel name: (launches, total_ms, algo_bytes)}"""
+        arr = (KernelStat * 256)()
+        n = ctypes.c_size_t(0)
+        _check(lib().cc_profile_read(self.ptr, ctypes.cast(arr, ctypes.c_void_p), 256, ctypes.byref(n)))
+        out = {}
+        for i in range(min(n.value, 256)):
+            out[arr[i].name.decode()] = (int(arr[i].launches), float(arr[i].total_ms), float(arr[i].algo_bytes))
+        return out
 
     def last_table_sizes(self) -> np.ndarray:
         n = ctypes.c_size_t(0)

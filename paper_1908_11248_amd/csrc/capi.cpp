@@ -403,6 +403,30 @@ int cc_count_batch(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_quer
     });
 }
 
+int cc_profile_enable(cc_context* ctx, int enable) {
+    return guarded([&] {
+        need(ctx != nullptr, CC_EINVAL, "ctx is NULL");
+        ctx->prof.reset();
+        ctx->prof.on = enable != 0;
+    });
+}
+
+int cc_profile_read(cc_context* ctx, cc_kernel_stat* stats, size_t cap, size_t* n) {
+    return guarded([&] {
+        need(ctx && n, CC_EINVAL, "bad arguments");
+        ctx->prof.resolve();
+        const auto& st = ctx->prof.stats();
+        *n = st.size();
+        for (size_t i = 0; i < std::min(cap, st.size()); i++) {
+            std::memset(stats[i].name, 0, sizeof stats[i].name);
+            std::strncpy(stats[i].name, st[i].name.c_str(), sizeof stats[i].name - 1);
+            stats[i].launches = st[i].launches;
+            stats[i].total_ms = st[i].ms;
+            stats[i].algo_bytes = st[i].bytes;
+        }
+    });
+}
+
 int cc_enumerate(cc_context* ctx, const cc_graph* g, const cc_coloring* c, int32_t b, const cc_decomp* d,
                  uint64_t cap, int32_t* rows, uint64_t* n_rows, uint64_t* total) {
     (void)ctx; (void)g; (void)c; (void)b; (void)d; (void)cap; (void)rows; (void)n_rows; (void)total;

@@ -42,6 +42,38 @@ class Arena {
     std::unordered_map<size_t, size_t> live_;  // offset -> bytes
 };
 
+// Per-kernel timing with HIP events on the context's stream (enabled on
+// request; resolved after the stream synchronises at the end of a call).
+struct KernelStat {
+    std::string name;
+    uint64_t launches = 0;
+    double ms = 0;
+    double bytes = 0;  // algorithmic bytes summed over launches
+};
+
+class Profiler {
+   public:
+    bool on = false;
+    void reset();
+    void begin(hipStream_t s, const char* name, double bytes);
+    void end(hipStream_t s);
+    void resolve();  // call after the stream has synchronised
+    const std::vector<KernelStat>& stats() const { return stats_; }
+    ~Profiler();
+
+   private:
+    struct Pending {
+        int stat;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    std::vector<KernelStat> stats_;
+    std::map<std::string, int> index_;
+    std::vector<Pending> pending_;
+    std::vector<hipEvent_t> pool_;
+    hipEvent_t take();
+};
+
 }  // namespace ccg
 
 struct cc_context {
@@ -52,6 +84,7 @@ struct cc_context {
     ccg::Arena arena;
     uint64_t* pinned = nullptr;  // small host staging buffer
     std::vector<int64_t> last_sizes;
+    ccg::Profiler prof;
 };
 
 struct cc_graph {

@@ -66,6 +66,69 @@ void Arena::release(void* p) {
 }
 
 // ---------------------------------------------------------------------------
+// profiler
+
+hipEvent_t Profiler::take() {
+    if (!pool_.empty()) {
+        hipEvent_t e = pool_.back();
+        pool_.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    return e;
+}
+
+void Profiler::reset() {
+    resolve();
+    stats_.clear();
+    index_.clear();
+}
+
+void Profiler::begin(hipStream_t s, const char* name, double bytes) {
+    if (!on) return;
+    auto it = index_.find(name);
+    int id;
+    if (it == index_.end()) {
+        id = int(stats_.size());
+        index_[name] = id;
+        stats_.push_back(KernelStat{name, 0, 0, 0});
+    } else {
+        id = it->second;
+    }
+    Pending p{id, bytes, take(), take()};
+    hip_check(hipEventRecord(p.a, s), "hipEventRecord");
+    pending_.push_back(p);
+}
+
+void Profiler::end(hipStream_t s) {
+    if (!on || pending_.empty()) return;
+    hip_check(hipEventRecord(pending_.back().b, s), "hipEventRecord");
+}
+
+void Profiler::resolve() {
+    for (auto& p : pending_) {
+        float ms = 0;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            stats_[p.stat].launches++;
+            stats_[p.stat].ms += ms;
+            stats_[p.stat].bytes += p.bytes;
+        }
+        pool_.push_back(p.a);
+        pool_.push_back(p.b);
+    }
+    pending_.clear();
+}
+
+Profiler::~Profiler() {
+    for (auto& p : pending_) {
+        pool_.push_back(p.a);
+        pool_.push_back(p.b);
+    }
+    for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------------------
 
 static int bits_for(uint64_t count) {  // bits to hold values 0 .. count-1
     int b = 0;
@@ -130,11 +193,18 @@ struct Exec {
         t.cnt = nullptr;
     }
 
+    template <class F>
+    void timed(const char* name, double bytes, F&& launch) {
+        ctx->prof.begin(s, name, bytes);
+        launch();
+        ctx->prof.end(s);
+    }
+
     // exclusive scan of n counts; returns offsets[n + 1] and the total
     uint64_t scan(const uint32_t* in, uint64_t n, uint64_t** offs) {
         *offs = alloc<uint64_t>(n + 1);
         uint64_t* tmp = (uint64_t*)raw(scan_tmp_bytes(n));
-        launch_scan_u32(in, *offs, n, tmp, s);
+        timed("scan", 4.0 * n + 8.0 * (n + 1), [&] { launch_scan_u32(in, *offs, n, tmp, s); });
         release(tmp);
         return read_u64(ctx, *offs + n);
     }
@@ -142,11 +212,11 @@ struct Exec {
     // runs of equal key >> shift; returns G and starts[G + 1]
     uint64_t groups(const DevTable& t, int shift, uint64_t** starts) {
         uint32_t* flags = alloc<uint32_t>(t.n);
-        launch_heads(t.keys, t.lay.kw(), t.n, shift, flags, s);
+        timed("heads", double(t.n) * (t.lay.key_bytes() + 4), [&] { launch_heads(t.keys, t.lay.kw(), t.n, shift, flags, s); });
         uint64_t* offs;
         uint64_t G = scan(flags, t.n, &offs);
         *starts = alloc<uint64_t>(G + 1);
-        launch_group_starts(flags, offs, t.n, *starts, s);
+        timed("group_starts", 12.0 * t.n + 8.0 * G, [&] { launch_group_starts(flags, offs, t.n, *starts, s); });
         release(flags);
         release(offs);
         return G;
@@ -204,12 +274,13 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                 case S_LEAF: {
                     uint64_t total = uint64_t(g.n) * B;
                     uint32_t* flags = X.alloc<uint32_t>(total);
-                    launch_leaf_count(g, B, ia.degF, flags, s);
+                    X.timed("leaf_count", 4.0 * total + 8.0 * g.n, [&] { launch_leaf_count(g, B, ia.degF, flags, s); });
                     uint64_t* offs;
                     uint64_t N = X.scan(flags, total, &offs);
                     X.release(flags);
                     o = X.table(lo, N);
-                    launch_leaf_emit(g, B, ia.degF, rq.colors, offs, lo, o.keys, o.cnt, s);
+                    X.timed("leaf_emit", 9.0 * total + 8.0 * g.n + double(N) * (lo.key_bytes() + 8),
+                            [&] { launch_leaf_emit(g, B, ia.degF, rq.colors, offs, lo, o.keys, o.cnt, s); });
                     X.release(offs);
                     break;
                 }
@@ -223,17 +294,20 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     uint64_t* gstart;
                     uint64_t G = X.groups(in, shift, &gstart);
                     uint32_t* wcount = X.alloc<uint32_t>(G);
-                    launch_push_work(in, gstart, G, g, ia, wcount, s);
+                    X.timed("push_work", 20.0 * G, [&] { launch_push_work(in, gstart, G, g, ia, wcount, s); });
                     uint64_t* woff;
                     uint64_t W = X.scan(wcount, G, &woff);
                     X.release(wcount);
                     uint32_t* ocount = X.alloc<uint32_t>(W);
-                    launch_push_count(in, gstart, woff, G, W, g, rq.colors, ia, ocount, s);
+                    X.timed("push_count", double(in.n) * in.lay.key_bytes() + 9.0 * W,
+                            [&] { launch_push_count(in, gstart, woff, G, W, g, rq.colors, ia, ocount, s); });
                     uint64_t* ooff;
                     uint64_t N = X.scan(ocount, W, &ooff);
                     X.release(ocount);
                     o = X.table(lo, N);
-                    if (N) launch_push_emit(in, gstart, woff, G, W, g, rq.colors, ia, ooff, o, s);
+                    if (N)
+                        X.timed("push_emit", double(in.n) * (in.lay.key_bytes() + 8) + 13.0 * W + double(N) * (lo.key_bytes() + 8),
+                                [&] { launch_push_emit(in, gstart, woff, G, W, g, rq.colors, ia, ooff, o, s); });
                     X.release(ooff);
                     X.release(woff);
                     X.release(gstart);
@@ -250,15 +324,18 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     uint64_t* rend = X.alloc<uint64_t>(slots);
                     launch_fill_u64(rstart, 0, slots, s);
                     launch_fill_u64(rend, 0, slots, s);
-                    launch_pull_index(in, g.n, rstart, rend, s);
+                    X.timed("pull_index", double(in.n) * in.lay.key_bytes(), [&] { launch_pull_index(in, g.n, rstart, rend, s); });
                     uint64_t W = uint64_t(B) * uint64_t(g.m2);
                     uint32_t* ocount = X.alloc<uint32_t>(W);
-                    launch_pull_count(in, rstart, rend, B, g, rq.colors, ia, ocount, s);
+                    X.timed("pull_count", double(in.n) * in.lay.key_bytes() + 13.0 * W,
+                            [&] { launch_pull_count(in, rstart, rend, B, g, rq.colors, ia, ocount, s); });
                     uint64_t* ooff;
                     uint64_t N = X.scan(ocount, W, &ooff);
                     X.release(ocount);
                     o = X.table(lo, N);
-                    if (N) launch_pull_emit(in, rstart, rend, B, g, rq.colors, ia, ooff, o, s);
+                    if (N)
+                        X.timed("pull_emit", double(in.n) * (in.lay.key_bytes() + 8) + 17.0 * W + double(N) * (lo.key_bytes() + 8),
+                                [&] { launch_pull_emit(in, rstart, rend, B, g, rq.colors, ia, ooff, o, s); });
                     X.release(ooff);
                     X.release(rstart);
                     X.release(rend);
@@ -273,12 +350,14 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     uint64_t* gstart;
                     uint64_t G = X.groups(in, in.lay.kb + in.lay.vb, &gstart);
                     uint32_t* gcount = X.alloc<uint32_t>(G);
-                    launch_forget_count(in, gstart, G, gcount, s);
+                    X.timed("forget_count", double(in.n) * in.lay.key_bytes() + 4.0 * G,
+                            [&] { launch_forget_count(in, gstart, G, gcount, s); });
                     uint64_t* goff;
                     uint64_t N = X.scan(gcount, G, &goff);
                     X.release(gcount);
                     o = X.table(lo, N);
-                    launch_forget_emit(in, gstart, G, goff, o, ovf, s);
+                    X.timed("forget_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8),
+                            [&] { launch_forget_emit(in, gstart, G, goff, o, ovf, s); });
                     X.release(goff);
                     X.release(gstart);
                     break;
@@ -293,12 +372,15 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     uint64_t* gstart;
                     uint64_t G = X.groups(y, y.lay.kb, &gstart);
                     uint32_t* gcount = X.alloc<uint32_t>(G);
-                    launch_join_count(y, z, gstart, G, g.n, rq.colors, gcount, s);
+                    X.timed("join_count", double(y.n + z.n) * y.lay.key_bytes() + 4.0 * G,
+                            [&] { launch_join_count(y, z, gstart, G, g.n, rq.colors, gcount, s); });
                     uint64_t* goff;
                     uint64_t N = X.scan(gcount, G, &goff);
                     X.release(gcount);
                     o = X.table(lo, N);
-                    if (N) launch_join_emit(y, z, gstart, G, g.n, rq.colors, goff, o, ovf, s);
+                    if (N)
+                        X.timed("join_emit", double(y.n + z.n) * (y.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8),
+                                [&] { launch_join_emit(y, z, gstart, G, g.n, rq.colors, goff, o, ovf, s); });
                     X.release(goff);
                     X.release(gstart);
                     break;
@@ -307,11 +389,13 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     const DevTable& in = tab[st.in0];
                     o = X.table(lo, in.n);
                     if (in.n) {
-                        launch_permute(in, st.perm, o, s);
+                        X.timed("permute", double(in.n) * (in.lay.key_bytes() + lo.key_bytes() + 16),
+                                [&] { launch_permute(in, st.perm, o, s); });
                         void* kb2 = X.raw(in.n * lo.key_bytes());
                         uint64_t* vb2 = X.alloc<uint64_t>(in.n);
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
-                        radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), tmp, s);
+                        X.timed("radix_sort", double(in.n) * (lo.key_bytes() + 8) * 2,
+                                [&] { radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), tmp, s); });
                         X.release(tmp);
                         X.release(vb2);
                         X.release(kb2);
@@ -336,7 +420,7 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
             pv = X.alloc<uint64_t>(uint64_t(B) * g.n);
             launch_fill_u64(pv, 0, uint64_t(B) * g.n, s);
         }
-        launch_root(rc, g.n, counts, ovf, pv, s);
+        X.timed("root", double(rc.n) * (rc.lay.key_bytes() + 8), [&] { launch_root(rc, g.n, counts, ovf, pv, s); });
         out->counts.assign(B, 0);
         std::vector<uint32_t> of(B, 0);
         hip_check(hipMemcpyAsync(out->counts.data(), counts, 8 * size_t(B), hipMemcpyDeviceToHost, s), "copy counts");
@@ -347,6 +431,7 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                       "copy per-vertex");
         }
         hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        ctx->prof.resolve();
         out->overflow.assign(B, 0);
         for (int b = 0; b < B; b++) out->overflow[b] = of[b] ? 1 : 0;
         int root_node = int(dec.nodes.size()) - 1;
