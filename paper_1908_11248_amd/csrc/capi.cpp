@@ -429,9 +429,15 @@ int cc_profile_read(cc_context* ctx, cc_kernel_stat* stats, size_t cap, size_t* 
 
 int cc_enumerate(cc_context* ctx, const cc_graph* g, const cc_coloring* c, int32_t b, const cc_decomp* d,
                  uint64_t cap, int32_t* rows, uint64_t* n_rows, uint64_t* total) {
-    (void)ctx; (void)g; (void)c; (void)b; (void)d; (void)cap; (void)rows; (void)n_rows; (void)total;
-    g_last_error = "cc_enumerate is not available yet";
-    return CC_EINVAL;
+    return guarded([&] {
+        check_run_args(ctx, g, c, d);
+        need(b >= 0 && b < c->B, CC_EINVAL, "colouring index out of range");
+        need(n_rows && total && (cap == 0 || rows), CC_EINVAL, "bad arguments");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        std::vector<int32_t> out;
+        run_enumerate(ctx, g, c->colors + size_t(b) * g->n, c->k, d, cap, &out, n_rows, total);
+        if (!out.empty()) std::memcpy(rows, out.data(), out.size() * sizeof(int32_t));
+    });
 }
 
 }  // extern "C"

@@ -118,6 +118,16 @@ struct RunRequest {
     bool degree_mask = true;
     bool per_vertex = false;  // also the per-image split of the node below the root
     bool keep_tables = false;
+    bool links = false;  // record the contributor index the row decoder needs (implies keep_tables)
+};
+
+// contributor index of one step's table (enumeration)
+struct StepLinks {
+    uint64_t* src = nullptr;   // introduce / resort
+    uint64_t* seg = nullptr;   // forget / join: [N_out + 1]
+    uint64_t* wcum = nullptr;  // forget / join: [contributors + 1]
+    uint64_t* ca = nullptr;
+    uint64_t* cb = nullptr;
 };
 
 struct RunResult {
@@ -125,11 +135,15 @@ struct RunResult {
     std::vector<uint8_t> overflow;     // [B]
     std::vector<uint64_t> per_vertex;  // [B * n] if requested
     std::vector<DevTable> tables;      // per plan step, when kept (arena-owned)
+    std::vector<StepLinks> links;      // per plan step, when recorded (arena-owned)
     std::vector<int64_t> node_sizes;   // per TD node: sum over colourings of |D_x|
 };
 
 void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out);
 void release_tables(cc_context* ctx, RunResult* r);
+// the first min(total, cap) mappings of one colouring in lexicographic order
+void run_enumerate(cc_context* ctx, const cc_graph* g, const uint8_t* colors, int k, const cc_decomp* dec,
+                   uint64_t cap, std::vector<int32_t>* rows, uint64_t* n_rows, uint64_t* total);
 uint64_t read_u64(cc_context* ctx, const uint64_t* dev);
 Lay table_layout(int b, int32_t n, int B, int k);
 

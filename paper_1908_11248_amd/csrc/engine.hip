@@ -223,6 +223,20 @@ struct Exec {
     }
 };
 
+// sorts (keys, vals) by keys < nkeys (stable)
+void sort_pairs(Exec& X, uint64_t* keys, uint64_t* vals, uint64_t n, uint64_t nkeys) {
+    if (n <= 1) return;
+    int bits = 1;
+    while (bits < 63 && (uint64_t(1) << bits) < nkeys) bits++;
+    uint64_t* k2 = X.alloc<uint64_t>(n);
+    uint64_t* v2 = X.alloc<uint64_t>(n);
+    void* tmp = X.raw(radix_tmp_bytes(n));
+    radix_sort(keys, vals, k2, v2, n, 1, bits, tmp, X.s);
+    X.release(tmp);
+    X.release(v2);
+    X.release(k2);
+}
+
 }  // namespace
 
 void release_tables(cc_context* ctx, RunResult* r) {
@@ -232,7 +246,12 @@ void release_tables(cc_context* ctx, RunResult* r) {
         t.keys = nullptr;
         t.cnt = nullptr;
     }
+    for (auto& l : r->links) {
+        for (void* p : {(void*)l.src, (void*)l.seg, (void*)l.wcum, (void*)l.ca, (void*)l.cb}) ctx->arena.release(p);
+        l = StepLinks();
+    }
     r->tables.clear();
+    r->links.clear();
 }
 
 void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
@@ -250,6 +269,9 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
     hipStream_t s = ctx->stream;
     const size_t S = plan.steps.size();
     std::vector<DevTable> tab(S);
+    std::vector<StepLinks> lk(S);
+    const bool links = rq.links;
+    const bool keep = rq.keep_tables || rq.links;
     std::vector<int> uses(S, 0);
     for (const Step& st : plan.steps) {
         if (st.in0 >= 0) uses[st.in0]++;
@@ -305,9 +327,10 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     uint64_t N = X.scan(ocount, W, &ooff);
                     X.release(ocount);
                     o = X.table(lo, N);
+                    if (links) lk[i].src = X.alloc<uint64_t>(N);
                     if (N)
                         X.timed("push_emit", double(in.n) * (in.lay.key_bytes() + 8) + 13.0 * W + double(N) * (lo.key_bytes() + 8),
-                                [&] { launch_push_emit(in, gstart, woff, G, W, g, rq.colors, ia, ooff, o, s); });
+                                [&] { launch_push_emit(in, gstart, woff, G, W, g, rq.colors, ia, ooff, o, lk[i].src, s); });
                     X.release(ooff);
                     X.release(woff);
                     X.release(gstart);
@@ -333,9 +356,10 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     uint64_t N = X.scan(ocount, W, &ooff);
                     X.release(ocount);
                     o = X.table(lo, N);
+                    if (links) lk[i].src = X.alloc<uint64_t>(N);
                     if (N)
                         X.timed("pull_emit", double(in.n) * (in.lay.key_bytes() + 8) + 17.0 * W + double(N) * (lo.key_bytes() + 8),
-                                [&] { launch_pull_emit(in, rstart, rend, B, g, rq.colors, ia, ooff, o, s); });
+                                [&] { launch_pull_emit(in, rstart, rend, B, g, rq.colors, ia, ooff, o, lk[i].src, s); });
                     X.release(ooff);
                     X.release(rstart);
                     X.release(rend);
@@ -358,6 +382,26 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     o = X.table(lo, N);
                     X.timed("forget_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8),
                             [&] { launch_forget_emit(in, gstart, G, goff, o, ovf, s); });
+                    if (links) {
+                        // contributors of every output entry: child entries sorted by output position
+                        uint64_t* dst = X.alloc<uint64_t>(in.n);
+                        launch_forget_dst(in, gstart, G, goff, dst, s);
+                        uint64_t* ca = X.alloc<uint64_t>(in.n);
+                        launch_iota(ca, in.n, s);
+                        sort_pairs(X, dst, ca, in.n, N);
+                        StepLinks& L = lk[i];
+                        L.ca = ca;
+                        L.seg = X.alloc<uint64_t>(N + 1);
+                        launch_segment_starts(dst, in.n, N, L.seg, s);
+                        uint64_t* w = X.alloc<uint64_t>(in.n);
+                        launch_gather_u64(in.cnt, ca, in.n, w, s);
+                        L.wcum = X.alloc<uint64_t>(in.n + 1);
+                        uint64_t* tmp = (uint64_t*)X.raw(scan_tmp_bytes(in.n));
+                        launch_scan_u64(w, L.wcum, in.n, tmp, s);
+                        X.release(tmp);
+                        X.release(w);
+                        X.release(dst);
+                    }
                     X.release(goff);
                     X.release(gstart);
                     break;
@@ -381,6 +425,39 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     if (N)
                         X.timed("join_emit", double(y.n + z.n) * (y.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8),
                                 [&] { launch_join_emit(y, z, gstart, G, g.n, rq.colors, goff, o, ovf, s); });
+                    if (links && N) {
+                        uint32_t* pc = X.alloc<uint32_t>(G);
+                        launch_join_pairs_count(y, z, gstart, G, g.n, rq.colors, pc, s);
+                        uint64_t* poff;
+                        uint64_t P = X.scan(pc, G, &poff);
+                        X.release(pc);
+                        uint64_t* pdst = X.alloc<uint64_t>(P);
+                        uint64_t* pa = X.alloc<uint64_t>(P);
+                        uint64_t* pd = X.alloc<uint64_t>(P);
+                        launch_join_pairs_emit(y, z, gstart, G, g.n, rq.colors, goff, poff, pdst, pa, pd, s);
+                        X.release(poff);
+                        uint64_t* perm = X.alloc<uint64_t>(P);
+                        launch_iota(perm, P, s);
+                        sort_pairs(X, pdst, perm, P, N);
+                        StepLinks& L = lk[i];
+                        L.ca = X.alloc<uint64_t>(P);
+                        L.cb = X.alloc<uint64_t>(P);
+                        launch_gather_u64(pa, perm, P, L.ca, s);
+                        launch_gather_u64(pd, perm, P, L.cb, s);
+                        L.seg = X.alloc<uint64_t>(N + 1);
+                        launch_segment_starts(pdst, P, N, L.seg, s);
+                        uint64_t* w = X.alloc<uint64_t>(P);
+                        launch_gather_product(y.cnt, L.ca, z.cnt, L.cb, P, w, s);
+                        L.wcum = X.alloc<uint64_t>(P + 1);
+                        uint64_t* tmp = (uint64_t*)X.raw(scan_tmp_bytes(P));
+                        launch_scan_u64(w, L.wcum, P, tmp, s);
+                        X.release(tmp);
+                        X.release(w);
+                        X.release(perm);
+                        X.release(pa);
+                        X.release(pd);
+                        X.release(pdst);
+                    }
                     X.release(goff);
                     X.release(gstart);
                     break;
@@ -388,9 +465,24 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                 case S_RESORT: {
                     const DevTable& in = tab[st.in0];
                     o = X.table(lo, in.n);
-                    if (in.n) {
+                    if (in.n && links) {
+                        // sort (key, input position), then gather the counts
+                        uint64_t* idx = X.alloc<uint64_t>(in.n);
+                        DevTable t2 = o;
+                        t2.cnt = idx;
+                        launch_permute(in, st.perm, t2, true, s);
+                        void* kb2 = X.raw(in.n * lo.key_bytes());
+                        uint64_t* vb2 = X.alloc<uint64_t>(in.n);
+                        void* tmp = X.raw(radix_tmp_bytes(in.n));
+                        radix_sort(o.keys, idx, kb2, vb2, in.n, lo.kw(), lo.bits(), tmp, s);
+                        X.release(tmp);
+                        X.release(vb2);
+                        X.release(kb2);
+                        launch_gather_u64(in.cnt, idx, in.n, o.cnt, s);
+                        lk[i].src = idx;
+                    } else if (in.n) {
                         X.timed("permute", double(in.n) * (in.lay.key_bytes() + lo.key_bytes() + 16),
-                                [&] { launch_permute(in, st.perm, o, s); });
+                                [&] { launch_permute(in, st.perm, o, false, s); });
                         void* kb2 = X.raw(in.n * lo.key_bytes());
                         uint64_t* vb2 = X.alloc<uint64_t>(in.n);
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
@@ -404,7 +496,7 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                 }
             }
             if (st.node >= 0) out->node_sizes[st.node] = int64_t(o.n);
-            if (!rq.keep_tables) {
+            if (!keep) {
                 for (int in : {st.in0, st.in1})
                     if (in >= 0 && --uses[in] == 0) X.drop(tab[in]);
             }
@@ -441,8 +533,9 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
         X.release(counts);
         X.release(pv);
         X.release(ovf);
-        if (rq.keep_tables) {
+        if (keep) {
             out->tables = tab;
+            out->links = lk;
         } else {
             X.drop(tab[plan.root_child]);
         }
@@ -451,6 +544,146 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
         X.release_all();
         throw;
     }
+}
+
+}  // namespace ccg
+
+namespace ccg {
+
+// Enumeration (Sec. 4) of one colouring: forward DP keeping every table and
+// its contributor index, lexicographic cut on the image of vertex 0 (the
+// node below the root holds bag {0}, sorted by that image), row decoding on
+// the device, a radix sort of the packed rows and truncation to `cap`.
+void run_enumerate(cc_context* ctx, const cc_graph* g, const uint8_t* colors, int k, const cc_decomp* dec,
+                   uint64_t cap, std::vector<int32_t>* rows, uint64_t* n_rows, uint64_t* total) {
+    const Plan& plan = dec->plan;
+    const int nF = dec->d.n;
+    const TdNode& below_root = dec->d.nodes[dec->d.nodes[dec->d.nodes.size() - 1].c0];
+    if (below_root.bag != 1u) fail(CC_EINVAL, "enumeration needs pattern vertex 0 forgotten last");
+    const int vb = table_layout(1, g->n, 1, k).vb;
+    if (nF * vb > 128) fail(CC_ERANGE, "packed rows (n_F x vertex bits) exceed 128 bits");
+    RunRequest rq;
+    rq.g = g;
+    rq.colors = colors;
+    rq.B = 1;
+    rq.k = k;
+    rq.dec = dec;
+    rq.links = true;
+    RunResult r;
+    run_dp(ctx, rq, &r);
+    hipStream_t s = ctx->stream;
+    Arena& A = ctx->arena;
+    std::vector<void*> extra;
+    auto alloc = [&](size_t bytes) {
+        void* p = A.alloc(bytes);
+        extra.push_back(p);
+        return p;
+    };
+    try {
+        ctx->last_sizes = r.node_sizes;
+        if (r.overflow[0]) fail(CC_ERANGE, "the count overflowed 64 bits; rows cannot be decoded");
+        *total = r.counts[0];
+        rows->clear();
+        *n_rows = 0;
+        const DevTable& rc = r.tables[plan.root_child];
+        if (cap == 0 || r.counts[0] == 0 || rc.n == 0) {
+            release_tables(ctx, &r);
+            return;
+        }
+        // lexicographic cut: keep the entries with Phi(0) <= t for the least t
+        // whose rows reach cap (all entries when the count is at most cap)
+        std::vector<uint64_t> hk(rc.n * (rc.lay.kw() == 1 ? 1 : 2)), hc(rc.n);
+        hip_check(hipMemcpyAsync(hk.data(), rc.keys, rc.n * rc.lay.key_bytes(), hipMemcpyDeviceToHost, s), "copy");
+        hip_check(hipMemcpyAsync(hc.data(), rc.cnt, rc.n * 8, hipMemcpyDeviceToHost, s), "copy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        auto v0_of = [&](uint64_t e) -> uint64_t {
+            u128 key = rc.lay.kw() == 1 ? u128(hk[e]) : ((u128(hk[2 * e + 1]) << 64) | hk[2 * e]);
+            return uint64_t(key >> rc.lay.kb) & ((uint64_t(1) << rc.lay.vb) - 1);
+        };
+        std::vector<uint64_t> rcum(rc.n + 1, 0);
+        for (uint64_t e = 0; e < rc.n; e++) rcum[e + 1] = rcum[e] + hc[e];
+        uint64_t E = rc.n;
+        if (r.counts[0] > cap) {
+            uint64_t e = 0;
+            while (rcum[e + 1] < cap) e++;  // entry where the cap is reached
+            uint64_t t = v0_of(e);
+            E = e + 1;
+            while (E < rc.n && v0_of(E) == t) E++;
+        }
+        const uint64_t R = rcum[E];
+        uint64_t* d_rcum = (uint64_t*)alloc(8 * (E + 1));
+        hip_check(hipMemcpyAsync(d_rcum, rcum.data(), 8 * (E + 1), hipMemcpyHostToDevice, s), "copy");
+        // step descriptors
+        std::vector<EnumStep> es(plan.steps.size());
+        for (size_t i = 0; i < plan.steps.size(); i++) {
+            const Step& st = plan.steps[i];
+            EnumStep& d = es[i];
+            d.in0 = st.in0;
+            d.in1 = st.in1;
+            d.ucol = -1;
+            d.u = st.u;
+            d.lay = r.tables[i].lay;
+            d.keys = r.tables[i].keys;
+            d.cnt = r.tables[i].cnt;
+            d.src = r.links[i].src;
+            d.seg = r.links[i].seg;
+            d.wcum = r.links[i].wcum;
+            d.ca = r.links[i].ca;
+            d.cb = r.links[i].cb;
+            switch (st.kind) {
+                case S_LEAF: d.kind = EK_LEAF; d.ucol = 0; break;
+                case S_INTRO_PUSH:
+                case S_INTRO_PULL: d.kind = EK_INTRO; d.ucol = st.pos; break;
+                case S_FORGET_LAST: d.kind = EK_FORGET; break;
+                case S_JOIN: d.kind = EK_JOIN; break;
+                case S_RESORT: d.kind = EK_RESORT; break;
+            }
+        }
+        EnumStep* d_steps = (EnumStep*)alloc(sizeof(EnumStep) * es.size());
+        hip_check(hipMemcpyAsync(d_steps, es.data(), sizeof(EnumStep) * es.size(), hipMemcpyHostToDevice, s), "copy");
+        uint32_t* err = (uint32_t*)alloc(4);
+        launch_fill_u32(err, 0, 1, s);
+        const int rbits = nF * vb;
+        const int rkw = rbits <= 64 ? 1 : 2;
+        const size_t rkb = rkw == 1 ? 8 : 16;
+        void* keys = alloc(std::max<uint64_t>(R, 1) * rkb);
+        ctx->prof.begin(s, "unrank", double(R) * rkb);
+        launch_unrank(d_steps, plan.root_child, d_rcum, E, R, nF, vb, rkw, keys, err, s);
+        ctx->prof.end(s);
+        uint64_t* vals = (uint64_t*)alloc(std::max<uint64_t>(R, 1) * 8);
+        launch_fill_u64(vals, 0, R, s);
+        void* k2 = alloc(std::max<uint64_t>(R, 1) * rkb);
+        uint64_t* v2 = (uint64_t*)alloc(std::max<uint64_t>(R, 1) * 8);
+        void* tmp = alloc(radix_tmp_bytes(R));
+        ctx->prof.begin(s, "row_sort", double(R) * (rkb + 8) * 2);
+        radix_sort(keys, vals, k2, v2, R, rkw, rbits, tmp, s);
+        ctx->prof.end(s);
+        const uint64_t m = std::min(R, cap);
+        std::vector<uint64_t> hrows(m * (rkw == 1 ? 1 : 2));
+        uint32_t herr = 0;
+        hip_check(hipMemcpyAsync(hrows.data(), keys, m * rkb, hipMemcpyDeviceToHost, s), "copy rows");
+        hip_check(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s), "copy err");
+        hip_check(hipStreamSynchronize(s), "sync");
+        ctx->prof.resolve();
+        if (herr) fail(CC_EDEVICE, "row decoder reported an inconsistent index");
+        rows->resize(m * size_t(nF));
+        const uint64_t vmask = (uint64_t(1) << vb) - 1;
+        for (uint64_t i = 0; i < m; i++) {
+            u128 key = rkw == 1 ? u128(hrows[i]) : ((u128(hrows[2 * i + 1]) << 64) | hrows[2 * i]);
+            for (int j = nF - 1; j >= 0; j--) {
+                (*rows)[i * nF + j] = int32_t(uint64_t(key) & vmask);
+                key >>= vb;
+            }
+        }
+        *n_rows = m;
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        for (void* p : extra) A.release(p);
+        release_tables(ctx, &r);
+        throw;
+    }
+    for (void* p : extra) A.release(p);
+    release_tables(ctx, &r);
 }
 
 }  // namespace ccg

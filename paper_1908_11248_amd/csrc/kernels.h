@@ -46,6 +46,7 @@ struct DevTable {
 // ---- launchers (all asynchronous on `s`) ----
 // scan: out[i] = sum_{j<i} in[j] for i <= n (out has n + 1 slots)
 void launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
+void launch_scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
 size_t scan_tmp_bytes(uint64_t n);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
@@ -78,7 +79,7 @@ void launch_push_count(const DevTable& in, const uint64_t* gstart, const uint64_
                        uint32_t* ocount, hipStream_t s);
 void launch_push_emit(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
                       uint64_t W, DevGraph g, const uint8_t* colors, const IntroArgs& a,
-                      const uint64_t* ooff, DevTable& out, hipStream_t s);
+                      const uint64_t* ooff, DevTable& out, uint64_t* osrc, hipStream_t s);
 
 // introduce, pull form (child column 0 is the anchor)
 void launch_pull_index(const DevTable& in, int32_t n, uint64_t* rstart, uint64_t* rend, hipStream_t s);
@@ -87,7 +88,7 @@ void launch_pull_count(const DevTable& in, const uint64_t* rstart, const uint64_
                        hipStream_t s);
 void launch_pull_emit(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B,
                       DevGraph g, const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff,
-                      DevTable& out, hipStream_t s);
+                      DevTable& out, uint64_t* osrc, hipStream_t s);
 
 // forget of the last column, reduced per group with a dense colour-set accumulator
 void launch_forget_count(const DevTable& in, const uint64_t* gstart, uint64_t G, uint32_t* gcount,
@@ -103,11 +104,51 @@ void launch_join_emit(const DevTable& y, const DevTable& z, const uint64_t* gsta
                       hipStream_t s);
 
 // column permutation (out column j <- in column perm[j]) into tmp, then sort
-void launch_permute(const DevTable& in, const int* perm, DevTable& out, hipStream_t s);
+// index_values: the values become the input positions instead of the counts
+void launch_permute(const DevTable& in, const int* perm, DevTable& out, bool index_values, hipStream_t s);
 // LSD radix sort of (keys, vals) on the low `bits` bits; result in the a-buffers
 size_t radix_tmp_bytes(uint64_t n);
 void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw,
                 int bits, void* tmp, hipStream_t s);
+
+// enumeration support (enumerate.hip)
+// forget: dst[e] = output position of child entry e
+void launch_forget_dst(const DevTable& in, const uint64_t* gstart, uint64_t G, const uint64_t* goff, uint64_t* dst,
+                       hipStream_t s);
+// join: admissible pairs per group (count pass), then (dst, a, d) per pair
+void launch_join_pairs_count(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
+                             const uint8_t* colors, uint32_t* pcount, hipStream_t s);
+void launch_join_pairs_emit(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
+                            const uint8_t* colors, const uint64_t* goff, const uint64_t* poff, uint64_t* pdst,
+                            uint64_t* pa, uint64_t* pd, hipStream_t s);
+// segment starts of a sorted uint64 array: starts[key[j]] = first j
+void launch_segment_starts(const uint64_t* keys, uint64_t n, uint64_t nseg, uint64_t* starts, hipStream_t s);
+// gathers: out[j] = src[idx[j]]; out[j] = a[i[j]] * b[k[j]]
+void launch_gather_u64(const uint64_t* src, const uint64_t* idx, uint64_t n, uint64_t* out, hipStream_t s);
+void launch_iota(uint64_t* p, uint64_t n, hipStream_t s);
+void launch_gather_product(const uint64_t* a, const uint64_t* ia, const uint64_t* b, const uint64_t* ib, uint64_t n,
+                           uint64_t* out, hipStream_t s);
+
+// one descriptor per plan step for the row decoder
+enum EnumKind { EK_LEAF = 0, EK_INTRO = 1, EK_FORGET = 2, EK_JOIN = 3, EK_RESORT = 4 };
+struct EnumStep {
+    int kind;       // EnumKind
+    int in0, in1;   // input steps
+    int ucol;       // column of the step's vertex in its output (leaf / introduce), else -1
+    int u;          // pattern vertex of that column
+    Lay lay;
+    const void* keys;
+    const uint64_t* cnt;
+    const uint64_t* src;     // introduce / resort: child entry of every output entry
+    const uint64_t* seg;     // forget / join: contributor segment starts, per output entry (+1)
+    const uint64_t* wcum;    // forget / join: exclusive prefix sums of contributor weights
+    const uint64_t* ca;      // forget: contributing child entry; join: first-child entry
+    const uint64_t* cb;      // join: second-child entry
+};
+// decodes rows r in [0, R): starting entry by prefix sums rcum over the
+// first entries of the root's child table, then descends every step
+void launch_unrank(const EnumStep* steps, int root_step, const uint64_t* rcum, uint64_t E, uint64_t R, int nF,
+                   int vb, int rkw, void* rowkeys, uint32_t* err, hipStream_t s);
 
 // root: counts[bid] += cnt for every entry of a one-column table; per-vertex optional
 void launch_root(const DevTable& in, int32_t n, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex,

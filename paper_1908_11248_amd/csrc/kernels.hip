@@ -9,123 +9,11 @@
 // the output is sorted without a sort and is identical from run to run.
 #include <hip/hip_runtime.h>
 
+#include "device.h"
 #include "kernels.h"
 
 namespace ccg {
 
-namespace {
-
-constexpr int kBlock = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kBlock * kScanItems;
-
-inline unsigned grid_for(uint64_t items, int per_block = kBlock, unsigned cap = 1u << 20) {
-    uint64_t b = (items + per_block - 1) / per_block;
-    if (b < 1) b = 1;
-    if (b > cap) b = cap;
-    return unsigned(b);
-}
-
-// ---- packed key fields ----
-template <class K>
-__device__ __forceinline__ uint32_t kcol(K key, const Lay& L, int j) {
-    return uint32_t(key >> (L.kb + (L.b - 1 - j) * L.vb)) & ((1u << L.vb) - 1u);
-}
-template <class K>
-__device__ __forceinline__ uint32_t kset(K key, const Lay& L) {
-    return uint32_t(key) & ((1u << L.kb) - 1u);
-}
-template <class K>
-__device__ __forceinline__ uint32_t kbid(K key, const Lay& L) {
-    int sh = L.kb + L.b * L.vb;
-    return sh >= int(8 * sizeof(K)) ? 0u : uint32_t(key >> sh);
-}
-template <class K>
-__device__ __forceinline__ K kpack(uint32_t bid, const uint32_t* cols, int b, uint32_t C, const Lay& L) {
-    K k = K(bid);
-    for (int j = 0; j < b; j++) k = (k << L.vb) | K(cols[j]);
-    return (k << L.kb) | K(C);
-}
-template <class K>
-__device__ __forceinline__ K shr(K key, int sh) {
-    return sh >= int(8 * sizeof(K)) ? K(0) : (key >> sh);
-}
-
-__device__ __forceinline__ int64_t gdeg(const DevGraph& g, uint32_t v) { return g.rp[v + 1] - g.rp[v]; }
-
-// {a, b} in E(G): binary search in the shorter of the two sorted rows
-__device__ __forceinline__ bool has_edge(const DevGraph& g, uint32_t a, uint32_t b) {
-    int64_t la = g.rp[a], ha = g.rp[a + 1], lb = g.rp[b], hb = g.rp[b + 1];
-    int64_t lo, hi;
-    int32_t t;
-    if (ha - la <= hb - lb) {
-        lo = la;
-        hi = ha;
-        t = int32_t(b);
-    } else {
-        lo = lb;
-        hi = hb;
-        t = int32_t(a);
-    }
-    int64_t end = hi;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (g.col[mid] < t) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo < end && g.col[lo] == t;
-}
-
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    unsigned lane = __lane_id();
-    return lane ? ((~0ull) >> (64 - lane)) : 0ull;
-}
-
-__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
-    int lane = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint64_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-// exclusive scan across a 256-thread block; *total = block sum
-__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t* total) {
-    __shared__ uint64_t wsum[kBlock / 64];
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t inc = wave_incl_scan(v);
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    uint64_t off = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < kBlock / 64; i++) {
-        if (i < w) off += wsum[i];
-        tot += wsum[i];
-    }
-    __syncthreads();
-    *total = tot;
-    return off + inc - v;
-}
-
-// first index in [lo, hi) of a non-decreasing array with a[i] > x
-__device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t* a, uint64_t lo, uint64_t hi, uint64_t x) {
-    while (lo < hi) {
-        uint64_t mid = (lo + hi) >> 1;
-        if (a[mid] <= x) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // scan (reduce, scan of block sums, down-sweep)
@@ -190,6 +78,10 @@ static void scan_rec(const T* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipS
 
 void launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
     scan_rec<uint32_t>(in, out, n, tmp, s);
+}
+
+void launch_scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
+    scan_rec<uint64_t>(in, out, n, tmp, s);
 }
 
 __global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
@@ -326,7 +218,8 @@ template <class KI, class KO, bool EMIT>
 __global__ void __launch_bounds__(kBlock)
 k_push(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ gstart,
        const uint64_t* __restrict__ woff, uint64_t G, uint64_t W, DevGraph g, const uint8_t* __restrict__ colors,
-       IntroArgs a, uint32_t* ocount, const uint64_t* __restrict__ ooff, KO* okeys, uint64_t* ocnt, Lay LO) {
+       IntroArgs a, uint32_t* ocount, const uint64_t* __restrict__ ooff, KO* okeys, uint64_t* ocnt, Lay LO,
+       uint64_t* osrc) {
     for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < W; w += uint64_t(gridDim.x) * blockDim.x) {
         uint64_t grp = upper_bound_u64(woff, 0, G + 1, w) - 1;
         uint64_t t = w - woff[grp];
@@ -354,6 +247,7 @@ k_push(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, con
                     for (int j = 0, s = 0; j < LO.b; j++) cols[j] = (j == a.pos) ? v : kcol(k, L, s++);
                     okeys[o] = kpack<KO>(bid, cols, LO.b, C | cb, LO);
                     ocnt[o] = cnt[e];
+                    if (osrc) osrc[o] = e;
                     o++;
                 } else {
                     produced++;
@@ -376,7 +270,7 @@ void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, De
 template <bool EMIT>
 static void push_dispatch(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
                           DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount,
-                          const uint64_t* ooff, DevTable* out, hipStream_t s) {
+                          const uint64_t* ooff, DevTable* out, uint64_t* osrc, hipStream_t s) {
     if (!W) return;
     Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
     void* ok = out ? out->keys : nullptr;
@@ -385,23 +279,23 @@ static void push_dispatch(const DevTable& in, const uint64_t* gstart, const uint
     int ki = in.lay.kw(), ko = LO.kw();
     if (ki == 1 && ko == 1)
         k_push<uint64_t, uint64_t, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff, G, W,
-                                                                 g, colors, a, ocount, ooff, (uint64_t*)ok, oc, LO);
+                                                                 g, colors, a, ocount, ooff, (uint64_t*)ok, oc, LO, osrc);
     else if (ki == 1 && ko == 2)
         k_push<uint64_t, u128, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff, G, W,
-                                                             g, colors, a, ocount, ooff, (u128*)ok, oc, LO);
+                                                             g, colors, a, ocount, ooff, (u128*)ok, oc, LO, osrc);
     else
         k_push<u128, u128, EMIT><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, gstart, woff, G, W, g,
-                                                         colors, a, ocount, ooff, (u128*)ok, oc, LO);
+                                                         colors, a, ocount, ooff, (u128*)ok, oc, LO, osrc);
 }
 
 void launch_push_count(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
                        DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, hipStream_t s) {
-    push_dispatch<false>(in, gstart, woff, G, W, g, colors, a, ocount, nullptr, nullptr, s);
+    push_dispatch<false>(in, gstart, woff, G, W, g, colors, a, ocount, nullptr, nullptr, nullptr, s);
 }
 void launch_push_emit(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
                       DevGraph g, const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff, DevTable& out,
-                      hipStream_t s) {
-    push_dispatch<true>(in, gstart, woff, G, W, g, colors, a, nullptr, ooff, &out, s);
+                      uint64_t* osrc, hipStream_t s) {
+    push_dispatch<true>(in, gstart, woff, G, W, g, colors, a, nullptr, ooff, &out, osrc, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,7 +328,7 @@ template <class KI, class KO, bool EMIT>
 __global__ void __launch_bounds__(kBlock)
 k_pull(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ rstart,
        const uint64_t* __restrict__ rend, int B, DevGraph g, const uint8_t* __restrict__ colors, IntroArgs a,
-       uint32_t* ocount, const uint64_t* __restrict__ ooff, KO* okeys, uint64_t* ocnt, Lay LO) {
+       uint32_t* ocount, const uint64_t* __restrict__ ooff, KO* okeys, uint64_t* ocnt, Lay LO, uint64_t* osrc) {
     uint64_t W = uint64_t(B) * uint64_t(g.m2);
     for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < W; w += uint64_t(gridDim.x) * blockDim.x) {
         uint32_t bid = uint32_t(w / uint64_t(g.m2));
@@ -460,6 +354,7 @@ k_pull(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, con
                     for (int j = 1; j < LO.b; j++) cols[j] = kcol(k, L, j - 1);
                     okeys[o] = kpack<KO>(bid, cols, LO.b, C | cb, LO);
                     ocnt[o] = cnt[i];
+                    if (osrc) osrc[o] = i;
                     o++;
                 } else {
                     produced++;
@@ -473,7 +368,7 @@ k_pull(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, con
 template <bool EMIT>
 static void pull_dispatch(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
                           const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, const uint64_t* ooff,
-                          DevTable* out, hipStream_t s) {
+                          DevTable* out, uint64_t* osrc, hipStream_t s) {
     uint64_t W = uint64_t(B) * uint64_t(g.m2);
     if (!W) return;
     Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
@@ -483,82 +378,23 @@ static void pull_dispatch(const DevTable& in, const uint64_t* rstart, const uint
     int ki = in.lay.kw(), ko = LO.kw();
     if (ki == 1 && ko == 1)
         k_pull<uint64_t, uint64_t, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, rstart, rend, B, g,
-                                                                 colors, a, ocount, ooff, (uint64_t*)ok, oc, LO);
+                                                                 colors, a, ocount, ooff, (uint64_t*)ok, oc, LO, osrc);
     else if (ki == 1 && ko == 2)
         k_pull<uint64_t, u128, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, rstart, rend, B, g,
-                                                             colors, a, ocount, ooff, (u128*)ok, oc, LO);
+                                                             colors, a, ocount, ooff, (u128*)ok, oc, LO, osrc);
     else
         k_pull<u128, u128, EMIT><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, rstart, rend, B, g, colors,
-                                                         a, ocount, ooff, (u128*)ok, oc, LO);
+                                                         a, ocount, ooff, (u128*)ok, oc, LO, osrc);
 }
 
 void launch_pull_count(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
                        const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, hipStream_t s) {
-    pull_dispatch<false>(in, rstart, rend, B, g, colors, a, ocount, nullptr, nullptr, s);
+    pull_dispatch<false>(in, rstart, rend, B, g, colors, a, ocount, nullptr, nullptr, nullptr, s);
 }
 void launch_pull_emit(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
-                      const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff, DevTable& out, hipStream_t s) {
-    pull_dispatch<true>(in, rstart, rend, B, g, colors, a, nullptr, ooff, &out, s);
-}
-
-// ---------------------------------------------------------------------------
-// Dense colour-set accumulator, one 64-lane workgroup per group: 2^k uint64
-// counters plus a 2^k-bit presence mask in LDS.  Presence is tracked apart
-// from the counters because a count may be 0 modulo 2^64 while the entry
-// exists (the paper's nonzero configuration).
-
-struct Acc {
-    uint64_t* val;   // [1 << kb]
-    uint32_t* bits;  // [max(1, (1 << kb) / 32)]
-    int kb;
-    __device__ int slots() const { return 1 << kb; }
-    __device__ int words() const { return kb >= 5 ? (1 << (kb - 5)) : 1; }
-};
-
-// with values == false only the presence mask is allocated (count passes)
-__device__ __forceinline__ Acc acc_bind(int kb, bool values) {
-    extern __shared__ uint64_t smem[];
-    Acc a;
-    a.kb = kb;
-    a.val = values ? smem : nullptr;
-    a.bits = reinterpret_cast<uint32_t*>(values ? smem + (1 << kb) : smem);
-    return a;
-}
-
-static size_t acc_bytes(int kb, bool values) {
-    size_t words = kb >= 5 ? (size_t(1) << (kb - 5)) : 1;
-    return (values ? (size_t(8) << kb) : 0) + 4 * words;
-}
-
-__device__ __forceinline__ void acc_clear(Acc& a, bool values) {
-    int lane = threadIdx.x;
-    if (values)
-        for (int i = lane; i < a.slots(); i += 64) a.val[i] = 0;
-    for (int i = lane; i < a.words(); i += 64) a.bits[i] = 0;
-}
-
-__device__ __forceinline__ uint32_t acc_count(const Acc& a) {
-    uint64_t c = 0;
-    for (int i = threadIdx.x; i < a.words(); i += 64) c += __popc(a.bits[i]);
-    return uint32_t(wave_sum(c));
-}
-
-// writes the present slots in increasing colour-set order
-template <class KO>
-__device__ __forceinline__ void acc_emit(const Acc& a, KO prefix, uint64_t base, KO* okeys, uint64_t* ocnt) {
-    uint64_t run = 0;
-    int lane = threadIdx.x;
-    for (int c0 = 0; c0 < a.slots(); c0 += 64) {
-        int C = c0 + lane;
-        bool present = C < a.slots() && ((a.bits[C >> 5] >> (C & 31)) & 1u);
-        uint64_t m = __ballot(present);
-        if (present) {
-            uint64_t o = base + run + __popcll(m & lanemask_lt());
-            okeys[o] = prefix | KO(C);
-            ocnt[o] = a.val[C];
-        }
-        run += __popcll(m);
-    }
+                      const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff, DevTable& out, uint64_t* osrc,
+                      hipStream_t s) {
+    pull_dispatch<true>(in, rstart, rend, B, g, colors, a, nullptr, ooff, &out, osrc, s);
 }
 
 // forget of the last column (Sec. 3.1 forget rule): per run of equal
@@ -733,33 +569,33 @@ struct Perm {
 
 template <class KI, class KO>
 __global__ void k_permute(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, uint64_t N, Lay L, Perm pm,
-                          Lay LO, KO* okeys, uint64_t* ocnt) {
+                          Lay LO, KO* okeys, uint64_t* ocnt, bool index_values) {
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += uint64_t(gridDim.x) * blockDim.x) {
         KI k = keys[i];
         uint32_t cols[4];
         for (int j = 0; j < LO.b; j++) cols[j] = kcol(k, L, pm.p[j]);
         okeys[i] = kpack<KO>(kbid(k, L), cols, LO.b, kset(k, L), LO);
-        ocnt[i] = cnt[i];
+        ocnt[i] = index_values ? i : cnt[i];
     }
 }
 
-void launch_permute(const DevTable& in, const int* perm, DevTable& out, hipStream_t s) {
+void launch_permute(const DevTable& in, const int* perm, DevTable& out, bool index_values, hipStream_t s) {
     if (!in.n) return;
     Perm pm{{perm[0], perm[1], perm[2], perm[3]}};
     unsigned grid = grid_for(in.n);
     int ki = in.lay.kw(), ko = out.lay.kw();
     if (ki == 1 && ko == 1)
         k_permute<uint64_t, uint64_t><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, pm, out.lay,
-                                                              (uint64_t*)out.keys, out.cnt);
+                                                              (uint64_t*)out.keys, out.cnt, index_values);
     else if (ki == 2 && ko == 2)
         k_permute<u128, u128><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, pm, out.lay,
-                                                      (u128*)out.keys, out.cnt);
+                                                      (u128*)out.keys, out.cnt, index_values);
     else if (ki == 1)
         k_permute<uint64_t, u128><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, pm, out.lay,
-                                                          (u128*)out.keys, out.cnt);
+                                                          (u128*)out.keys, out.cnt, index_values);
     else
         k_permute<u128, uint64_t><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, pm, out.lay,
-                                                          (uint64_t*)out.keys, out.cnt);
+                                                          (uint64_t*)out.keys, out.cnt, index_values);
 }
 
 constexpr int kRadixItems = 16;
