@@ -113,6 +113,10 @@ int cc_decomp_export(const cc_decomp *d, int32_t *buf, size_t cap, size_t *len);
 int cc_decomp_import(int32_t n_F, int32_t m_F, const int32_t *edges, const int32_t *buf,
                      size_t len, cc_decomp **out);
 int32_t cc_decomp_width(const cc_decomp *d);
+/* Human-readable device plan of the decomposition (one line per step: the
+ * node rule, its variant, the table's column order).  *len receives the
+ * length including the terminating NUL; CC_ERANGE if cap is smaller. */
+int cc_decomp_describe(const cc_decomp *d, char *buf, size_t cap, size_t *len);
 void cc_decomp_free(cc_decomp *d);
 
 /* Runs the DP (Sec. 3.1) for every colouring of `c` in one batch and writes

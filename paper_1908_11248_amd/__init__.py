@@ -32,7 +32,7 @@ EXPORTS = [
     "cc_graph_num_vertices", "cc_color", "cc_color_explicit", "cc_coloring_download", "cc_coloring_free",
     "cc_build_decomposition", "cc_decomp_export", "cc_decomp_import", "cc_decomp_width", "cc_decomp_free",
     "cc_count", "cc_count_by_vertex", "cc_enumerate", "cc_last_table_sizes", "cc_count_batch",
-    "cc_profile_enable", "cc_profile_read",
+    "cc_profile_enable", "cc_profile_read", "cc_decomp_describe",
 ]
 
 
@@ -80,6 +80,7 @@ def lib():
             "cc_count_batch": (ctypes.c_int, [P, P, I32, P, U32, P, P]),
             "cc_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
             "cc_profile_read": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
+            "cc_decomp_describe": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -153,6 +154,13 @@ class Decomp(_Handle):
     @property
     def width(self) -> int:
         return int(lib().cc_decomp_width(self.ptr))
+
+    def describe(self) -> str:
+        ln = ctypes.c_size_t(0)
+        lib().cc_decomp_describe(self.ptr, None, 0, ctypes.byref(ln))
+        buf = ctypes.create_string_buffer(ln.value)
+        _check(lib().cc_decomp_describe(self.ptr, buf, ln.value, ctypes.byref(ln)))
+        return buf.value.decode()
 
     def export(self) -> np.ndarray:
         ln = ctypes.c_size_t(0)

@@ -146,6 +146,9 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
         g->ctx = ctx;
         g->n = n;
         g->m2 = m2;
+        g->sorted_deg.resize(n);
+        for (int32_t v = 0; v < n; v++) g->sorted_deg[v] = rp[v + 1] - rp[v];
+        std::sort(g->sorted_deg.begin(), g->sorted_deg.end());
         try {
             hip_check(hipMalloc(&g->rp, 8 * size_t(n + 1)), "hipMalloc");
             hip_check(hipMalloc(&g->col, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
@@ -324,6 +327,16 @@ int cc_decomp_import(int32_t n_F, int32_t m_F, const int32_t* edges, const int32
 }
 
 int32_t cc_decomp_width(const cc_decomp* d) { return d ? d->d.width : -1; }
+
+int cc_decomp_describe(const cc_decomp* d, char* buf, size_t cap, size_t* len) {
+    return guarded([&] {
+        need(d && len, CC_EINVAL, "bad arguments");
+        std::string out = describe_plan(d->d, d->plan);
+        *len = out.size() + 1;
+        need(buf && cap >= *len, CC_ERANGE, "buffer too small");
+        std::memcpy(buf, out.c_str(), out.size() + 1);
+    });
+}
 
 void cc_decomp_free(cc_decomp* d) { delete d; }
 

@@ -94,6 +94,9 @@ struct cc_graph {
     int64_t* rp = nullptr;
     int32_t* col = nullptr;
     int32_t* esrc = nullptr;
+    std::vector<int64_t> sorted_deg;  // host copy, ascending
+    // vertices with degree >= d
+    int64_t count_deg_at_least(int64_t d) const;
     ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc}; }
 };
 

@@ -5,6 +5,10 @@
 
 #include "engine.h"
 
+int64_t cc_graph::count_deg_at_least(int64_t d) const {
+    return int64_t(sorted_deg.end() - std::lower_bound(sorted_deg.begin(), sorted_deg.end(), d));
+}
+
 namespace ccg {
 
 void fail(int code, const std::string& msg) { throw CcError{code, msg}; }
@@ -277,6 +281,22 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
         if (st.in0 >= 0) uses[st.in0]++;
         if (st.in1 >= 0) uses[st.in1]++;
     }
+    // Fusions (not when the contributor index is recorded): an introduce in
+    // pull form over a one-column child followed by the forget of that column
+    // runs as one gather (fused.hip); a leaf consumed only by such a step is
+    // never materialised.
+    std::vector<char> fuse(S, 0), virt(S, 0);
+    if (!keep) {
+        for (size_t i = 0; i + 1 < S; i++) {
+            const Step& a = plan.steps[i];
+            const Step& f = plan.steps[i + 1];
+            if (a.kind == S_INTRO_PULL && a.b_in == 1 && a.nchk == 0 && f.kind == S_FORGET_LAST && f.in0 == int(i) &&
+                uses[i] == 1 && k <= 12) {
+                fuse[i] = 1;
+                if (plan.steps[a.in0].kind == S_LEAF && uses[a.in0] == 1) virt[a.in0] = 1;
+            }
+        }
+    }
     out->node_sizes.assign(dec.nodes.size(), 0);
     uint32_t* ovf = X.alloc<uint32_t>(B);
     launch_fill_u32(ovf, 0, B, s);
@@ -284,6 +304,54 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
     try {
         for (size_t i = 0; i < S; i++) {
             const Step& st = plan.steps[i];
+            if (virt[i]) {  // consumed by a fused edge step
+                if (st.node >= 0)
+                    out->node_sizes[st.node] = int64_t(B) * rq.g->count_deg_at_least(rq.degree_mask ? st.degF : 0);
+                continue;
+            }
+            if (fuse[i]) {
+                const Step& f = plan.steps[i + 1];
+                Lay lo = table_layout(f.b_out, g.n, B, k);
+                const bool leafc = virt[st.in0] != 0;
+                const DevTable* in = leafc ? nullptr : &tab[st.in0];
+                const int degF_u = rq.degree_mask ? st.degF : 0;
+                const int degF_c = rq.degree_mask ? plan.steps[st.in0].degF : 0;
+                uint64_t slots = uint64_t(B) * g.n;
+                uint64_t *rstart = nullptr, *rend = nullptr;
+                if (!leafc) {
+                    rstart = X.alloc<uint64_t>(slots);
+                    rend = X.alloc<uint64_t>(slots);
+                    launch_fill_u64(rstart, 0, slots, s);
+                    launch_fill_u64(rend, 0, slots, s);
+                    X.timed("pull_index", double(in->n) * in->lay.key_bytes(),
+                            [&] { launch_pull_index(*in, g.n, rstart, rend, s); });
+                }
+                uint32_t* gcount = X.alloc<uint32_t>(slots);
+                uint32_t* icount = X.alloc<uint32_t>(slots);
+                double in_bytes = leafc ? double(slots) : double(in->n) * (in->lay.key_bytes() + 8);
+                X.timed("edge_count", in_bytes + 16.0 * slots + 8.0 * g.m2,
+                        [&] { launch_edge_count(in, rstart, rend, B, g, rq.colors, degF_u, degF_c, lo, gcount, icount, s); });
+                uint64_t* ioff;
+                uint64_t NI = X.scan(icount, slots, &ioff);
+                X.release(ioff);
+                X.release(icount);
+                uint64_t* goff;
+                uint64_t N = X.scan(gcount, slots, &goff);
+                X.release(gcount);
+                DevTable& o = tab[i + 1];
+                o = X.table(lo, N);
+                if (N)
+                    X.timed("edge_emit", in_bytes + 16.0 * slots + 8.0 * g.m2 + double(N) * (lo.key_bytes() + 8),
+                            [&] { launch_edge_emit(in, rstart, rend, B, g, rq.colors, degF_u, degF_c, goff, o, ovf, s); });
+                X.release(goff);
+                X.release(rstart);
+                X.release(rend);
+                if (st.node >= 0) out->node_sizes[st.node] = int64_t(NI);
+                if (f.node >= 0) out->node_sizes[f.node] = int64_t(N);
+                if (!leafc && --uses[st.in0] == 0) X.drop(tab[st.in0]);
+                i++;  // the forget step is done
+                continue;
+            }
             Lay lo = table_layout(st.b_out, g.n, B, k);
             IntroArgs ia;
             ia.pos = st.pos;
@@ -415,16 +483,24 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                     }
                     uint64_t* gstart;
                     uint64_t G = X.groups(y, y.lay.kb, &gstart);
+                    uint64_t slots = uint64_t(B) * g.n;
+                    uint64_t* zlo = X.alloc<uint64_t>(slots);
+                    uint64_t* zhi = X.alloc<uint64_t>(slots);
+                    launch_fill_u64(zlo, 0, slots, s);
+                    launch_fill_u64(zhi, 0, slots, s);
+                    X.timed("join_index", double(z.n) * z.lay.key_bytes(), [&] { launch_pull_index(z, g.n, zlo, zhi, s); });
                     uint32_t* gcount = X.alloc<uint32_t>(G);
                     X.timed("join_count", double(y.n + z.n) * y.lay.key_bytes() + 4.0 * G,
-                            [&] { launch_join_count(y, z, gstart, G, g.n, rq.colors, gcount, s); });
+                            [&] { launch_join_count(y, z, gstart, G, g.n, rq.colors, zlo, zhi, gcount, s); });
                     uint64_t* goff;
                     uint64_t N = X.scan(gcount, G, &goff);
                     X.release(gcount);
                     o = X.table(lo, N);
                     if (N)
                         X.timed("join_emit", double(y.n + z.n) * (y.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8),
-                                [&] { launch_join_emit(y, z, gstart, G, g.n, rq.colors, goff, o, ovf, s); });
+                                [&] { launch_join_emit(y, z, gstart, G, g.n, rq.colors, zlo, zhi, goff, o, ovf, s); });
+                    X.release(zlo);
+                    X.release(zhi);
                     if (links && N) {
                         uint32_t* pc = X.alloc<uint32_t>(G);
                         launch_join_pairs_count(y, z, gstart, G, g.n, rq.colors, pc, s);

@@ -68,6 +68,7 @@ int build_decomposition(int nF, const std::vector<std::pair<int, int>>& edges, D
                         std::string* err);
 int validate_decomposition(const Decomp& d, std::string* err);
 int make_plan(const Decomp& d, Plan* plan, std::string* err);
+std::string describe_plan(const Decomp& d, const Plan& plan);
 
 // errors
 void set_error(const std::string& msg);

@@ -81,7 +81,9 @@ void launch_push_emit(const DevTable& in, const uint64_t* gstart, const uint64_t
                       uint64_t W, DevGraph g, const uint8_t* colors, const IntroArgs& a,
                       const uint64_t* ooff, DevTable& out, uint64_t* osrc, hipStream_t s);
 
-// introduce, pull form (child column 0 is the anchor)
+// introduce, pull form (child column 0 is the anchor).  launch_pull_index
+// writes the (colouring, column 0) run index rstart/rend[b * n + v] of a
+// table (slots must be zero beforehand); the join uses it too.
 void launch_pull_index(const DevTable& in, int32_t n, uint64_t* rstart, uint64_t* rend, hipStream_t s);
 void launch_pull_count(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B,
                        DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount,
@@ -96,12 +98,14 @@ void launch_forget_count(const DevTable& in, const uint64_t* gstart, uint64_t G,
 void launch_forget_emit(const DevTable& in, const uint64_t* gstart, uint64_t G, const uint64_t* goff,
                         DevTable& out, uint32_t* ovf, hipStream_t s);
 
-// join of two tables with the same layout
+// join of two tables with the same layout; zlo/zhi index the second child
+// by (colouring, image of column 0) (launch_pull_index builds it)
 void launch_join_count(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
-                       const uint8_t* colors, uint32_t* gcount, hipStream_t s);
+                       const uint8_t* colors, const uint64_t* zlo, const uint64_t* zhi, uint32_t* gcount,
+                       hipStream_t s);
 void launch_join_emit(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
-                      const uint8_t* colors, const uint64_t* goff, DevTable& out, uint32_t* ovf,
-                      hipStream_t s);
+                      const uint8_t* colors, const uint64_t* zlo, const uint64_t* zhi, const uint64_t* goff,
+                      DevTable& out, uint32_t* ovf, hipStream_t s);
 
 // column permutation (out column j <- in column perm[j]) into tmp, then sort
 // index_values: the values become the input positions instead of the counts
@@ -110,6 +114,16 @@ void launch_permute(const DevTable& in, const int* perm, DevTable& out, bool ind
 size_t radix_tmp_bytes(uint64_t n);
 void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw,
                 int bits, void* tmp, hipStream_t s);
+
+// fused introduce (pull, one-column child) + forget of the child's column
+// (fused.hip); in == nullptr means the child is a leaf synthesised from the
+// colouring.  gcount: output entries per (b, v); icount: introduce entries.
+void launch_edge_count(const DevTable* in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
+                       const uint8_t* colors, int degF_u, int degF_child, Lay LO, uint32_t* gcount, uint32_t* icount,
+                       hipStream_t s);
+void launch_edge_emit(const DevTable* in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
+                      const uint8_t* colors, int degF_u, int degF_child, const uint64_t* goff, DevTable& out,
+                      uint32_t* ovf, hipStream_t s);
 
 // enumeration support (enumerate.hip)
 // forget: dst[e] = output position of child entry e

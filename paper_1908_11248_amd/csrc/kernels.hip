@@ -465,12 +465,17 @@ void launch_forget_emit(const DevTable& in, const uint64_t* gstart, uint64_t G, 
 // ---------------------------------------------------------------------------
 // join (Sec. 3.1 join rule): for equal (colouring, images) in both children,
 // every pair with C' n C'' equal to the colour set of the bag's images gives
-// C' u C'' with count c' c''; equal results add.  One workgroup per run of
-// the first child; the matching run of the second is found by binary search.
+// C' u C'' with count c' c''; equal results add.  One 64-lane workgroup per
+// run of the first child.  The matching run of the second child is found
+// through a dense index over (colouring, image of column 0), narrowed by a
+// binary search only when the bag has more than one column.  Colour sets and
+// counts of both runs are staged in LDS in chunks and the |Y| x |Z| pair loop
+// is spread over all lanes.
+
+constexpr int kJoinChunk = 256;
 
 template <class K>
-__device__ __forceinline__ uint64_t lower_bound_prefix(const K* keys, uint64_t n, K p, int sh, bool strict) {
-    uint64_t lo = 0, hi = n;
+__device__ __forceinline__ uint64_t lower_bound_prefix(const K* keys, uint64_t lo, uint64_t hi, K p, int sh, bool strict) {
     while (lo < hi) {
         uint64_t mid = (lo + hi) >> 1;
         K q = shr(keys[mid], sh);
@@ -483,42 +488,61 @@ __device__ __forceinline__ uint64_t lower_bound_prefix(const K* keys, uint64_t n
 template <class K, bool EMIT>
 __global__ void __launch_bounds__(64)
 k_join(const K* __restrict__ yk, const uint64_t* __restrict__ yc, const K* __restrict__ zk,
-       const uint64_t* __restrict__ zc, uint64_t nz, Lay L, const uint64_t* __restrict__ gstart, uint64_t G, int32_t n,
-       const uint8_t* __restrict__ colors, uint32_t* gcount, const uint64_t* __restrict__ goff, K* okeys,
-       uint64_t* ocnt, uint32_t* ovf) {
+       const uint64_t* __restrict__ zc, Lay L, const uint64_t* __restrict__ gstart, uint64_t G, int32_t n,
+       const uint8_t* __restrict__ colors, const uint64_t* __restrict__ zlo, const uint64_t* __restrict__ zhi,
+       uint32_t* gcount, const uint64_t* __restrict__ goff, K* okeys, uint64_t* ocnt, uint32_t* ovf) {
     Acc acc = acc_bind(L.kb, EMIT);
+    __shared__ uint32_t ys[kJoinChunk], zs[kJoinChunk];
+    __shared__ uint64_t yv[EMIT ? kJoinChunk : 1], zv[EMIT ? kJoinChunk : 1];
     const int sh = L.kb;
     for (uint64_t grp = blockIdx.x; grp < G; grp += gridDim.x) {
         uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
         K k0 = yk[e0];
         K p = shr(k0, sh);
-        uint64_t z0 = lower_bound_prefix(zk, nz, p, sh, false);
-        uint64_t z1 = lower_bound_prefix(zk, nz, p, sh, true);
+        uint32_t bid = kbid(k0, L);
+        uint64_t slot = uint64_t(bid) * uint64_t(n) + kcol(k0, L, 0);
+        uint64_t z0 = zlo[slot], z1 = zhi[slot];
+        if (L.b > 1 && z0 < z1) {
+            uint64_t a0 = lower_bound_prefix(zk, z0, z1, p, sh, false);
+            z1 = lower_bound_prefix(zk, a0, z1, p, sh, true);
+            z0 = a0;
+        }
         if (z0 == z1) {  // no matching mapping in the second child
             if (!EMIT && threadIdx.x == 0) gcount[grp] = 0;
             continue;
         }
-        uint32_t bid = kbid(k0, L);
         uint32_t bagcol = 0;
         for (int j = 0; j < L.b; j++) bagcol |= 1u << colors[uint64_t(bid) * n + kcol(k0, L, j)];
         acc_clear(acc, EMIT);
-        __syncthreads();
         bool over = false;
-        uint64_t ny = e1 - e0, nzg = z1 - z0;
-        for (uint64_t a = 0; a < ny; a++) {
-            uint32_t Cy = kset(yk[e0 + a], L);
-            uint64_t cy = EMIT ? yc[e0 + a] : 0;
-            for (uint64_t d = threadIdx.x; d < nzg; d += 64) {
-                uint32_t Cz = kset(zk[z0 + d], L);
-                if ((Cy & Cz) != bagcol) continue;
-                uint32_t C = Cy | Cz;
-                atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
-                if (EMIT) {
-                    uint64_t cz = zc[z0 + d];
-                    uint64_t prod = cy * cz;
-                    over |= __umul64hi(cy, cz) != 0;
-                    uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)prod);
-                    over |= (old + prod < old);
+        for (uint64_t ya = e0; ya < e1; ya += kJoinChunk) {
+            uint32_t ny = uint32_t(e1 - ya < kJoinChunk ? e1 - ya : kJoinChunk);
+            for (uint64_t za = z0; za < z1; za += kJoinChunk) {
+                uint32_t nz = uint32_t(z1 - za < kJoinChunk ? z1 - za : kJoinChunk);
+                __syncthreads();
+                for (uint32_t i = threadIdx.x; i < ny; i += 64) {
+                    ys[i] = kset(yk[ya + i], L);
+                    if (EMIT) yv[i] = yc[ya + i];
+                }
+                for (uint32_t i = threadIdx.x; i < nz; i += 64) {
+                    zs[i] = kset(zk[za + i], L);
+                    if (EMIT) zv[i] = zc[za + i];
+                }
+                __syncthreads();
+                uint32_t P = ny * nz;
+                for (uint32_t q = threadIdx.x; q < P; q += 64) {
+                    uint32_t a = q / nz, d = q - a * nz;
+                    uint32_t Cy = ys[a], Cz = zs[d];
+                    if ((Cy & Cz) != bagcol) continue;
+                    uint32_t C = Cy | Cz;
+                    atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
+                    if (EMIT) {
+                        uint64_t cy = yv[a], cz = zv[d];
+                        uint64_t prod = cy * cz;
+                        over |= __umul64hi(cy, cz) != 0;
+                        uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)prod);
+                        over |= (old + prod < old);
+                    }
                 }
             }
         }
@@ -536,28 +560,29 @@ k_join(const K* __restrict__ yk, const uint64_t* __restrict__ yc, const K* __res
 
 template <bool EMIT>
 static void join_dispatch(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
-                          const uint8_t* colors, uint32_t* gcount, const uint64_t* goff, DevTable* out, uint32_t* ovf,
-                          hipStream_t s) {
+                          const uint8_t* colors, const uint64_t* zlo, const uint64_t* zhi, uint32_t* gcount,
+                          const uint64_t* goff, DevTable* out, uint32_t* ovf, hipStream_t s) {
     if (!G) return;
     unsigned grid = unsigned(G < (1u << 20) ? G : (1u << 20));
     size_t lds = acc_bytes(y.lay.kb, EMIT);
     void* okk = out ? out->keys : nullptr;
     uint64_t* oc = out ? out->cnt : nullptr;
     if (y.lay.kw() == 1)
-        k_join<uint64_t, EMIT><<<grid, 64, lds, s>>>((const uint64_t*)y.keys, y.cnt, (const uint64_t*)z.keys, z.cnt, z.n,
-                                                     y.lay, gstart, G, n, colors, gcount, goff, (uint64_t*)okk, oc, ovf);
+        k_join<uint64_t, EMIT><<<grid, 64, lds, s>>>((const uint64_t*)y.keys, y.cnt, (const uint64_t*)z.keys, z.cnt, y.lay,
+                                                     gstart, G, n, colors, zlo, zhi, gcount, goff, (uint64_t*)okk, oc, ovf);
     else
-        k_join<u128, EMIT><<<grid, 64, lds, s>>>((const u128*)y.keys, y.cnt, (const u128*)z.keys, z.cnt, z.n, y.lay, gstart,
-                                                 G, n, colors, gcount, goff, (u128*)okk, oc, ovf);
+        k_join<u128, EMIT><<<grid, 64, lds, s>>>((const u128*)y.keys, y.cnt, (const u128*)z.keys, z.cnt, y.lay, gstart, G,
+                                                 n, colors, zlo, zhi, gcount, goff, (u128*)okk, oc, ovf);
 }
 
 void launch_join_count(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
-                       const uint8_t* colors, uint32_t* gcount, hipStream_t s) {
-    join_dispatch<false>(y, z, gstart, G, n, colors, gcount, nullptr, nullptr, nullptr, s);
+                       const uint8_t* colors, const uint64_t* zlo, const uint64_t* zhi, uint32_t* gcount, hipStream_t s) {
+    join_dispatch<false>(y, z, gstart, G, n, colors, zlo, zhi, gcount, nullptr, nullptr, nullptr, s);
 }
 void launch_join_emit(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
-                      const uint8_t* colors, const uint64_t* goff, DevTable& out, uint32_t* ovf, hipStream_t s) {
-    join_dispatch<true>(y, z, gstart, G, n, colors, nullptr, goff, &out, ovf, s);
+                      const uint8_t* colors, const uint64_t* zlo, const uint64_t* zhi, const uint64_t* goff,
+                      DevTable& out, uint32_t* ovf, hipStream_t s) {
+    join_dispatch<true>(y, z, gstart, G, n, colors, zlo, zhi, nullptr, goff, &out, ovf, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,23 +745,42 @@ void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, 
 template <class K>
 __global__ void k_root(const K* __restrict__ keys, const uint64_t* __restrict__ cnt, uint64_t N, Lay L, int32_t n,
                        uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex) {
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += uint64_t(gridDim.x) * blockDim.x) {
-        K k = keys[i];
-        uint32_t bid = kbid(k, L);
-        uint64_t c = cnt[i];
-        uint64_t old = atomicAdd((unsigned long long*)&counts[bid], (unsigned long long)c);
-        if (old + c < old) atomicOr(&ovf[bid], 1u);
-        if (per_vertex) atomicAdd((unsigned long long*)&per_vertex[uint64_t(bid) * n + kcol(k, L, 0)], (unsigned long long)c);
+    // entries are sorted by colouring: every thread sums a contiguous chunk
+    // and flushes one atomic per colouring it sees
+    constexpr uint64_t kChunk = 32;
+    uint64_t chunks = (N + kChunk - 1) / kChunk;
+    for (uint64_t c = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < chunks; c += uint64_t(gridDim.x) * blockDim.x) {
+        uint64_t i0 = c * kChunk, i1 = i0 + kChunk < N ? i0 + kChunk : N;
+        uint32_t cur = kbid(keys[i0], L);
+        uint64_t sum = 0;
+        bool over = false;
+        for (uint64_t i = i0; i < i1; i++) {
+            K k = keys[i];
+            uint32_t bid = kbid(k, L);
+            uint64_t v = cnt[i];
+            if (bid != cur) {
+                uint64_t old = atomicAdd((unsigned long long*)&counts[cur], (unsigned long long)sum);
+                if (over || old + sum < old) atomicOr(&ovf[cur], 1u);
+                cur = bid;
+                sum = 0;
+                over = false;
+            }
+            over |= (sum + v < sum);
+            sum += v;
+            if (per_vertex) atomicAdd((unsigned long long*)&per_vertex[uint64_t(bid) * n + kcol(k, L, 0)], (unsigned long long)v);
+        }
+        uint64_t old = atomicAdd((unsigned long long*)&counts[cur], (unsigned long long)sum);
+        if (over || old + sum < old) atomicOr(&ovf[cur], 1u);
     }
 }
 
 void launch_root(const DevTable& in, int32_t n, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, hipStream_t s) {
     if (!in.n) return;
     if (in.lay.kw() == 1)
-        k_root<uint64_t><<<grid_for(in.n), kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, n, counts, ovf,
+        k_root<uint64_t><<<grid_for((in.n + 31) / 32), kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, n, counts, ovf,
                                                            per_vertex);
     else
-        k_root<u128><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, n, counts, ovf, per_vertex);
+        k_root<u128><<<grid_for((in.n + 31) / 32), kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, n, counts, ovf, per_vertex);
 }
 
 }  // namespace ccg

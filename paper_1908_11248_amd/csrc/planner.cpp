@@ -156,22 +156,31 @@ static int build_one(const Decomp& base, std::mt19937* rng, Decomp* out) {
         if (parent[v] < 0) parent[v] = 0;  // other components hang below vertex 0
 
     NiceBuilder nb{base.adj, {}, rng};
+    // Branches are joined at the smallest bag they can share (the union of
+    // their bags' intersections with the parent's bag); the parent's other
+    // vertices are introduced once, after the join.  Join tables then key on
+    // as few images as possible.
     std::function<int(int)> below = [&](int v) -> int {
-        std::vector<int> branches;
+        std::vector<std::pair<int, uint32_t>> branches;  // (top node, bag)
         for (int c = 0; c < n; c++) {
             if (c == v || parent[c] != v) continue;
             int top = below(c);
             top = nb.forget_to(top, bag[c], bag[v]);
-            top = nb.introduce_to(top, bag[c] & bag[v], bag[v]);
-            branches.push_back(top);
+            branches.push_back({top, bag[c] & bag[v]});
         }
         if (branches.empty()) {
             int top = nb.add(LEAF, v, -1, -1, 1u << v);
             return nb.introduce_to(top, 1u << v, bag[v]);
         }
-        int top = branches[0];
-        for (size_t i = 1; i < branches.size(); i++) top = nb.add(JOIN, -1, top, branches[i], bag[v]);
-        return top;
+        uint32_t common = 0;
+        for (auto& b : branches) common |= b.second;
+        if (common == 0) common = 1u << v;  // only fully forgotten branches: meet at {v}
+        int top = -1;
+        for (auto& b : branches) {
+            int t = nb.introduce_to(b.first, b.second, common);
+            top = top < 0 ? t : nb.add(JOIN, -1, top, t, common);
+        }
+        return nb.introduce_to(top, common, bag[v]);
     };
     int top = below(0);
     top = nb.forget_to(top, bag[0], 1u);  // bag[0] == {0}: nothing to do
@@ -448,6 +457,29 @@ int validate_decomposition(const Decomp& d, std::string* err) {
         if (tops != 1) return fail("the nodes of a vertex are not connected");
     }
     return CC_OK;
+}
+
+std::string describe_plan(const Decomp& d, const Plan& plan) {
+    static const char* names[] = {"leaf", "intro-push", "intro-pull", "forget-last", "join", "resort"};
+    std::string out;
+    char line[256];
+    for (size_t i = 0; i < plan.steps.size(); i++) {
+        const Step& s = plan.steps[i];
+        std::string cols = "(";
+        for (int j = 0; j < s.b_out; j++) cols += (j ? "," : "") + std::to_string(s.cols[j]);
+        cols += ")";
+        snprintf(line, sizeof line, "%2zu %-11s u=%-2d in=%d,%d node=%d cols=%s", i, names[s.kind], s.u, s.in0, s.in1,
+                 s.node, cols.c_str());
+        out += line;
+        if (s.kind == S_INTRO_PUSH || s.kind == S_INTRO_PULL) {
+            snprintf(line, sizeof line, " pos=%d anchor=%d checks=%d", s.pos, s.anchor, s.nchk);
+            out += line;
+        }
+        out += "\n";
+    }
+    snprintf(line, sizeof line, "root <- step %d; width %d\n", plan.root_child, d.width);
+    out += line;
+    return out;
 }
 
 int make_plan(const Decomp& d, Plan* plan, std::string* err) {
