@@ -173,6 +173,53 @@ typedef struct {
 } cc_query;
 int cc_count_batch(cc_context *ctx, const cc_graph *g, int32_t nq, const cc_query *q,
                    uint32_t flags, uint64_t *counts_flat, uint8_t *overflow_flat);
+/* The queries run on `lanes` concurrent HIP streams of the context (0: the
+ * tuned or default number), scheduled largest-plan first; a query that runs
+ * out of arena memory while others hold it is re-run alone.  Results are
+ * identical to one cc_count per query. */
+int cc_set_batch_lanes(cc_context *ctx, int32_t lanes);
+/* Autotuner: times cc_count_batch on the given queries with 1, 2, 4 and 8
+ * lanes and keeps the fastest for the context; *best receives it. */
+int cc_tune_batch(cc_context *ctx, const cc_graph *g, int32_t nq, const cc_query *q, uint32_t flags,
+                  int32_t *best);
+/* Work budget: with max_entries > 0 no DP table of one launch may hold more
+ * entries.  A call whose tables would exceed it runs its colourings in waves
+ * (halving recursively; results are unchanged) and fails with CC_ERANGE
+ * only when a single colouring exceeds the budget. */
+int cc_set_table_budget(cc_context *ctx, uint64_t max_entries);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: a request loop over a resident graph.  Submitted queries wait
+ * in FIFO order and are admitted while a worker lane is free and their
+ * estimated arena footprint fits the memory budget (the measured peak of an
+ * earlier query with the same decomposition and colouring count, else an
+ * equal share of the budget); admitted queries run concurrently on their own
+ * streams.  A query that runs out of memory is re-queued to run alone.
+ * Latency is measured from submission to completion. */
+typedef struct {
+    int32_t max_inflight;  /* worker lanes (concurrent queries), >= 1 */
+    size_t mem_budget;     /* bytes of the arena the server may use (0: all) */
+    uint64_t max_entries;  /* per-table budget of each query (0: none) */
+} cc_server_opts;
+typedef struct {
+    uint64_t submitted, completed, failed, requeued;
+    double wall_s;   /* first submission to last completion */
+    double qps;      /* completed / wall_s */
+    double p50_ms, p99_ms, mean_ms, max_ms;
+} cc_server_stats;
+typedef struct cc_server cc_server;
+int cc_server_start(cc_context *ctx, const cc_graph *g, const cc_server_opts *opts, cc_server **out);
+/* Queues count(F, zeta_b) for b < num_colorings with colourings drawn as in
+ * cc_color(k, seed); the decomposition must outlive the request. */
+int cc_server_submit(cc_server *srv, const cc_decomp *d, int32_t k, uint64_t seed, int32_t num_colorings,
+                     uint64_t *ticket);
+/* *state: 0 queued or running, 1 done (counts[num_colorings] and overflow
+ * written), or a negative CC_E* code of a failed query. */
+int cc_server_poll(cc_server *srv, uint64_t ticket, uint64_t *counts, uint8_t *overflow, int32_t *state);
+/* Blocks until the ticket is done; same outputs as cc_server_poll. */
+int cc_server_wait(cc_server *srv, uint64_t ticket, uint64_t *counts, uint8_t *overflow, int32_t *state);
+/* Drains the queue, stops the workers and frees the server. */
+int cc_server_stop(cc_server *srv, cc_server_stats *stats);
 
 #ifdef __cplusplus
 }

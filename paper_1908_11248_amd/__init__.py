@@ -33,6 +33,8 @@ EXPORTS = [
     "cc_build_decomposition", "cc_decomp_export", "cc_decomp_import", "cc_decomp_width", "cc_decomp_free",
     "cc_count", "cc_count_by_vertex", "cc_enumerate", "cc_last_table_sizes", "cc_count_batch",
     "cc_profile_enable", "cc_profile_read", "cc_decomp_describe",
+    "cc_set_batch_lanes", "cc_tune_batch", "cc_set_table_budget",
+    "cc_server_start", "cc_server_submit", "cc_server_poll", "cc_server_wait", "cc_server_stop",
 ]
 
 
@@ -81,6 +83,14 @@ def lib():
             "cc_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
             "cc_profile_read": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
             "cc_decomp_describe": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
+            "cc_set_batch_lanes": (ctypes.c_int, [P, I32]),
+            "cc_tune_batch": (ctypes.c_int, [P, P, I32, P, U32, P]),
+            "cc_set_table_budget": (ctypes.c_int, [P, U64]),
+            "cc_server_start": (ctypes.c_int, [P, P, P, PP]),
+            "cc_server_submit": (ctypes.c_int, [P, P, I32, U64, I32, P]),
+            "cc_server_poll": (ctypes.c_int, [P, U64, P, P, P]),
+            "cc_server_wait": (ctypes.c_int, [P, U64, P, P, P]),
+            "cc_server_stop": (ctypes.c_int, [P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -207,6 +217,12 @@ class Context(_Handle):
             out[arr[i].name.decode()] = (int(arr[i].launches), float(arr[i].total_ms), float(arr[i].algo_bytes))
         return out
 
+    def set_batch_lanes(self, lanes: int):
+        _check(lib().cc_set_batch_lanes(self.ptr, lanes))
+
+    def set_table_budget(self, max_entries: int):
+        _check(lib().cc_set_table_budget(self.ptr, max_entries))
+
     def last_table_sizes(self) -> np.ndarray:
         n = ctypes.c_size_t(0)
         buf = np.zeros(4096, dtype=np.int64)
@@ -286,14 +302,32 @@ def enumerate(ctx: Context, g: Graph, c: Coloring, b: int, d: Decomp, cap: int):
     return rows[: int(nr[0])].copy(), int(tot[0])
 
 
+class _Q(ctypes.Structure):
+    _fields_ = [("decomp", ctypes.c_void_p), ("coloring", ctypes.c_void_p)]
+
+
+def _query_array(queries):
+    nq = len(queries)
+    arr = (_Q * max(nq, 1))()
+    for i in range(nq):
+        arr[i].decomp = queries[i][0].ptr
+        arr[i].coloring = queries[i][1].ptr
+    return arr
+
+
+def tune_batch(ctx: Context, g: Graph, queries, flags: int = 0) -> int:
+    """Times the batch with 1, 2, 4 and 8 lanes; keeps and returns the best."""
+    best = ctypes.c_int32(0)
+    arr = _query_array(queries)
+    _check(lib().cc_tune_batch(ctx.ptr, g.ptr, len(queries), ctypes.cast(arr, ctypes.c_void_p), flags,
+                               ctypes.byref(best)))
+    return best.value
+
+
 def count_batch(ctx: Context, g: Graph, queries: Sequence[Tuple[Decomp, Coloring]], flags: int = 0):
     """Counts of many (decomposition, colouring) queries: list of (counts, overflow)."""
     nq = len(queries)
-
-    class Q(ctypes.Structure):
-        _fields_ = [("decomp", ctypes.c_void_p), ("coloring", ctypes.c_void_p)]
-
-    arr = (Q * max(nq, 1))()
+    arr = (_Q * max(nq, 1))()
     total = 0
     for i in range(nq):
         d, c = queries[i]
@@ -309,3 +343,53 @@ def count_batch(ctx: Context, g: Graph, queries: Sequence[Tuple[Decomp, Coloring
         out.append((counts[off:off + c.num].copy(), ovf[off:off + c.num].astype(bool)))
         off += c.num
     return out
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("max_entries", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("requeued", ctypes.c_uint64), ("wall_s", ctypes.c_double), ("qps", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
+
+
+class Server:
+    """Request loop over a resident graph (cc_server_*)."""
+
+    def __init__(self, ctx: Context, g: Graph, max_inflight: int = 4, mem_budget: int = 0, max_entries: int = 0):
+        self.ctx, self.g = ctx, g
+        opts = ServerOpts(max_inflight, mem_budget, max_entries)
+        out = ctypes.c_void_p()
+        _check(lib().cc_server_start(ctx.ptr, g.ptr, ctypes.byref(opts), ctypes.byref(out)))
+        self.ptr = out.value
+        self._keep = {}
+
+    def submit(self, d: Decomp, k: int, seed: int, num_colorings: int) -> int:
+        t = ctypes.c_uint64(0)
+        _check(lib().cc_server_submit(self.ptr, d.ptr, k, seed & (2**64 - 1), num_colorings, ctypes.byref(t)))
+        self._keep[t.value] = (d, num_colorings)
+        return t.value
+
+    def _res(self, fn, ticket):
+        d, nc = self._keep[ticket]
+        counts = np.zeros(nc, dtype=np.uint64)
+        ovf = np.zeros(nc, dtype=np.uint8)
+        st = ctypes.c_int32(0)
+        _check(fn(self.ptr, ticket, _p(counts), _p(ovf), ctypes.byref(st)))
+        return st.value, counts, ovf.astype(bool)
+
+    def poll(self, ticket: int):
+        """(state, counts, overflow): state 0 pending, 1 done, < 0 error code."""
+        return self._res(lib().cc_server_poll, ticket)
+
+    def wait(self, ticket: int):
+        return self._res(lib().cc_server_wait, ticket)
+
+    def stop(self) -> dict:
+        st = ServerStats()
+        _check(lib().cc_server_stop(self.ptr, ctypes.byref(st)))
+        self.ptr = None
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}

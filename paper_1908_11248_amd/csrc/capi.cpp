@@ -56,12 +56,7 @@ int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_conte
         auto* c = new cc_context();
         c->device = device;
         try {
-            if (hip_stream) {
-                c->stream = (hipStream_t)hip_stream;
-            } else {
-                hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
-                c->own_stream = true;
-            }
+            c->main.create((hipStream_t)hip_stream);
             if (arena_bytes == 0) {
                 size_t freeb = 0, total = 0;
                 hip_check(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
@@ -69,10 +64,9 @@ int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_conte
             }
             hip_check(hipMalloc(&c->arena_mem, arena_bytes), "arena hipMalloc");
             c->arena.init((char*)c->arena_mem, arena_bytes);
-            hip_check(hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault), "hipHostMalloc");
         } catch (...) {
             if (c->arena_mem) (void)hipFree(c->arena_mem);
-            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            c->main.destroy();
             delete c;
             throw;
         }
@@ -84,10 +78,9 @@ int cc_context_destroy(cc_context* ctx) {
     if (!ctx) return CC_OK;
     return guarded([&] {
         (void)hipSetDevice(ctx->device);
-        (void)hipStreamSynchronize(ctx->stream);
+        for (auto& w : ctx->workers) w->destroy();
+        ctx->main.destroy();
         if (ctx->arena_mem) (void)hipFree(ctx->arena_mem);
-        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
         delete ctx;
     });
 }
@@ -194,8 +187,8 @@ int cc_color(cc_context* ctx, const cc_graph* g, int32_t k, uint64_t seed, int32
             delete c;
             hip_check(e, "hipMalloc colours");
         }
-        launch_color_hash(c->colors, g->n, num_colorings, k, seed, ctx->stream);
-        hip_check(hipStreamSynchronize(ctx->stream), "colour kernel");
+        launch_color_hash(c->colors, g->n, num_colorings, k, seed, ctx->main.stream);
+        hip_check(hipStreamSynchronize(ctx->main.stream), "colour kernel");
         *out = c;
     });
 }
@@ -360,8 +353,9 @@ int cc_count(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_
         rq.k = c->k;
         rq.dec = d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
+        rq.max_entries = ctx->max_entries;
         RunResult r;
-        run_dp(ctx, rq, &r);
+        run_dp_waves(ctx, ctx->main, rq, &r);
         std::copy(r.counts.begin(), r.counts.end(), counts);
         if (overflow) std::copy(r.overflow.begin(), r.overflow.end(), overflow);
         ctx->last_sizes = r.node_sizes;
@@ -385,8 +379,9 @@ int cc_count_by_vertex(cc_context* ctx, const cc_graph* g, const cc_coloring* c,
         rq.dec = d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
         rq.per_vertex = true;
+        rq.max_entries = ctx->max_entries;
         RunResult r;
-        run_dp(ctx, rq, &r);
+        run_dp(ctx, ctx->main, rq, &r);
         std::copy(r.per_vertex.begin(), r.per_vertex.end(), per_vertex);
         if (count) *count = r.counts[0];
         if (overflow) *overflow = r.overflow[0];
@@ -402,33 +397,38 @@ int cc_last_table_sizes(const cc_context* ctx, int64_t* entries, size_t cap, siz
     });
 }
 
-int cc_count_batch(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query* q, uint32_t flags,
-                   uint64_t* counts_flat, uint8_t* overflow_flat) {
-    return guarded([&] {
-        need(ctx && g && (nq == 0 || q) && counts_flat, CC_EINVAL, "bad arguments");
-        size_t off = 0;
-        for (int32_t i = 0; i < nq; i++) {
-            int rc = cc_count(ctx, g, q[i].coloring, q[i].decomp, flags, counts_flat + off,
-                              overflow_flat ? overflow_flat + off : nullptr);
-            if (rc != CC_OK) fail(rc, "query " + std::to_string(i) + ": " + g_last_error);
-            off += size_t(q[i].coloring->B);
-        }
-    });
-}
-
 int cc_profile_enable(cc_context* ctx, int enable) {
     return guarded([&] {
         need(ctx != nullptr, CC_EINVAL, "ctx is NULL");
-        ctx->prof.reset();
-        ctx->prof.on = enable != 0;
+        ctx->main.prof.reset();
+        ctx->main.prof.on = enable != 0;
+        for (auto& w : ctx->workers) {
+            w->prof.reset();
+            w->prof.on = enable != 0;
+        }
     });
 }
 
 int cc_profile_read(cc_context* ctx, cc_kernel_stat* stats, size_t cap, size_t* n) {
     return guarded([&] {
         need(ctx && n, CC_EINVAL, "bad arguments");
-        ctx->prof.resolve();
-        const auto& st = ctx->prof.stats();
+        // statistics of every lane, merged by kernel name
+        std::vector<KernelStat> st;
+        auto merge = [&](Profiler& p) {
+            p.resolve();
+            for (const auto& k : p.stats()) {
+                auto it = std::find_if(st.begin(), st.end(), [&](const KernelStat& x) { return x.name == k.name; });
+                if (it == st.end()) {
+                    st.push_back(k);
+                } else {
+                    it->launches += k.launches;
+                    it->ms += k.ms;
+                    it->bytes += k.bytes;
+                }
+            }
+        };
+        merge(ctx->main.prof);
+        for (auto& w : ctx->workers) merge(w->prof);
         *n = st.size();
         for (size_t i = 0; i < std::min(cap, st.size()); i++) {
             std::memset(stats[i].name, 0, sizeof stats[i].name);
@@ -448,7 +448,7 @@ int cc_enumerate(cc_context* ctx, const cc_graph* g, const cc_coloring* c, int32
         need(n_rows && total && (cap == 0 || rows), CC_EINVAL, "bad arguments");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         std::vector<int32_t> out;
-        run_enumerate(ctx, g, c->colors + size_t(b) * g->n, c->k, d, cap, &out, n_rows, total);
+        run_enumerate(ctx, ctx->main, g, c->colors + size_t(b) * g->n, c->k, d, cap, &out, n_rows, total);
         if (!out.empty()) std::memcpy(rows, out.data(), out.size() * sizeof(int32_t));
     });
 }

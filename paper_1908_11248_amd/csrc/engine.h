@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -17,25 +19,34 @@ namespace ccg {
 struct CcError {
     int code;
     std::string msg;
+    bool budget = false;  // CC_ERANGE raised by the per-table work budget
 };
 
 [[noreturn]] void fail(int code, const std::string& msg);
 void hip_check(hipError_t e, const char* what);
 
-// First-fit allocator over one device buffer.  Allocation and release happen
-// on the host in stream order, so a released block may be handed out again
-// while earlier kernels that used it are still queued: they run first.
+// First-fit allocator over one device buffer, shared by every lane of a
+// context (calls are serialised by a mutex).  A lane releases a block only
+// after the kernels of that lane that use it were enqueued; a block released
+// by a lane is reused by the same lane in stream order, and by another lane
+// only after the owner synchronised its stream (every run synchronises its
+// stream before it returns its scratch and tables).
 class Arena {
    public:
     void init(char* base, size_t size);
     void* alloc(size_t bytes);
     void release(void* p);
     size_t in_use() const { return in_use_; }
+    size_t free_bytes() {
+        std::lock_guard<std::mutex> g(mu_);
+        return size_ - in_use_;
+    }
     size_t peak() const { return peak_; }
     size_t size() const { return size_; }
     void reset_peak() { peak_ = in_use_; }
 
    private:
+    std::mutex mu_;
     char* base_ = nullptr;
     size_t size_ = 0, in_use_ = 0, peak_ = 0;
     std::map<size_t, size_t> free_;            // offset -> bytes
@@ -74,17 +85,29 @@ class Profiler {
     hipEvent_t take();
 };
 
+// One independent execution lane: a stream, a pinned staging word for the
+// sizes read back between steps, and the lane's kernel timings.
+struct Lane {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t* pinned = nullptr;
+    Profiler prof;
+    void create(hipStream_t given);
+    void destroy();
+};
+
 }  // namespace ccg
 
 struct cc_context {
     int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
     void* arena_mem = nullptr;
     ccg::Arena arena;
-    uint64_t* pinned = nullptr;  // small host staging buffer
+    ccg::Lane main;  // the lane of the single-query calls
+    std::vector<std::unique_ptr<ccg::Lane>> workers;  // lanes of batched and served queries
     std::vector<int64_t> last_sizes;
-    ccg::Profiler prof;
+    uint64_t max_entries = 0;  // per-table budget (0: none)
+    int batch_lanes = 0;       // lanes for cc_count_batch (0: tuned on first use)
+    ccg::Lane& worker(size_t i);
 };
 
 struct cc_graph {
@@ -122,6 +145,7 @@ struct RunRequest {
     bool per_vertex = false;  // also the per-image split of the node below the root
     bool keep_tables = false;
     bool links = false;  // record the contributor index the row decoder needs (implies keep_tables)
+    uint64_t max_entries = 0;  // fail with CC_ERANGE when a table would exceed this (0: no limit)
 };
 
 // contributor index of one step's table (enumeration)
@@ -140,14 +164,19 @@ struct RunResult {
     std::vector<DevTable> tables;      // per plan step, when kept (arena-owned)
     std::vector<StepLinks> links;      // per plan step, when recorded (arena-owned)
     std::vector<int64_t> node_sizes;   // per TD node: sum over colourings of |D_x|
+    size_t peak_bytes = 0;             // largest arena footprint of the run
 };
 
-void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out);
+void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out);
+// run_dp, with the colourings split into waves (halves, recursively) while a
+// table exceeds the per-table budget; colourings are independent, so the
+// results equal one run.  Fails only when a single colouring exceeds it.
+void run_dp_waves(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out);
 void release_tables(cc_context* ctx, RunResult* r);
 // the first min(total, cap) mappings of one colouring in lexicographic order
-void run_enumerate(cc_context* ctx, const cc_graph* g, const uint8_t* colors, int k, const cc_decomp* dec,
+void run_enumerate(cc_context* ctx, Lane& lane, const cc_graph* g, const uint8_t* colors, int k, const cc_decomp* dec,
                    uint64_t cap, std::vector<int32_t>* rows, uint64_t* n_rows, uint64_t* total);
-uint64_t read_u64(cc_context* ctx, const uint64_t* dev);
+uint64_t read_u64(Lane& lane, const uint64_t* dev);
 Lay table_layout(int b, int32_t n, int B, int k);
 
 }  // namespace ccg

@@ -5,6 +5,14 @@
 
 #include "engine.h"
 
+ccg::Lane& cc_context::worker(size_t i) {
+    while (workers.size() <= i) {
+        workers.emplace_back(new ccg::Lane());
+        workers.back()->create(nullptr);
+    }
+    return *workers[i];
+}
+
 int64_t cc_graph::count_deg_at_least(int64_t d) const {
     return int64_t(sorted_deg.end() - std::lower_bound(sorted_deg.begin(), sorted_deg.end(), d));
 }
@@ -30,6 +38,7 @@ void Arena::init(char* base, size_t size) {
 }
 
 void* Arena::alloc(size_t bytes) {
+    std::lock_guard<std::mutex> guard(mu_);
     bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
     for (auto it = free_.begin(); it != free_.end(); ++it) {
         if (it->second < bytes) continue;
@@ -47,6 +56,7 @@ void* Arena::alloc(size_t bytes) {
 
 void Arena::release(void* p) {
     if (!p) return;
+    std::lock_guard<std::mutex> guard(mu_);
     size_t off = size_t((char*)p - base_);
     auto it = live_.find(off);
     if (it == live_.end()) return;
@@ -149,40 +159,84 @@ Lay table_layout(int b, int32_t n, int B, int k) {
     return L;
 }
 
-uint64_t read_u64(cc_context* ctx, const uint64_t* dev) {
-    hip_check(hipMemcpyAsync(ctx->pinned, dev, 8, hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync");
-    hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    return ctx->pinned[0];
+uint64_t read_u64(Lane& lane, const uint64_t* dev) {
+    hip_check(hipMemcpyAsync(lane.pinned, dev, 8, hipMemcpyDeviceToHost, lane.stream), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(lane.stream), "hipStreamSynchronize");
+    return lane.pinned[0];
+}
+
+void Lane::create(hipStream_t given) {
+    if (given) {
+        stream = given;
+    } else {
+        hip_check(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "hipStreamCreate");
+        own_stream = true;
+    }
+    hip_check(hipHostMalloc((void**)&pinned, 64, hipHostMallocDefault), "hipHostMalloc");
+}
+
+void Lane::destroy() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (pinned) (void)hipHostFree(pinned);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    pinned = nullptr;
+    stream = nullptr;
 }
 
 namespace {
 
 struct Exec {
-    cc_context* ctx;
+    Lane& lane;
     hipStream_t s;
     Arena& A;
-    std::unordered_map<void*, int> live;  // everything this run holds in the arena
+    uint64_t max_entries;
+    std::unordered_map<void*, size_t> live;  // everything this run holds in the arena
+    std::vector<void*> pending;              // released, returned to the arena at the next synchronisation
+    size_t held = 0, peak = 0;               // bytes held by this run (released blocks leave at once)
 
     void* raw(size_t bytes) {
         void* p = A.alloc(bytes);
-        live[p] = 1;
+        live[p] = bytes;
+        held += bytes;
+        peak = std::max(peak, held);
         return p;
     }
     template <class T>
     T* alloc(uint64_t count) {
         return (T*)raw(std::max<uint64_t>(count, 1) * sizeof(T));
     }
+    // Kernels already enqueued on this lane may still use p, and other lanes
+    // share the arena: the block goes back only after this lane synchronises.
     void release(const void* p) {
         if (!p) return;
-        live.erase(const_cast<void*>(p));
-        A.release(const_cast<void*>(p));
+        auto it = live.find(const_cast<void*>(p));
+        if (it != live.end()) {
+            held -= it->second;
+            live.erase(it);
+        }
+        pending.push_back(const_cast<void*>(p));
     }
-    void release_all() {
+    void synced() {  // call right after the lane's stream synchronised
+        for (void* p : pending) A.release(p);
+        pending.clear();
+    }
+    void release_all() {  // after a synchronisation, on failure
+        synced();
         for (auto& kv : live) A.release(kv.first);
         live.clear();
     }
+    uint64_t read(const uint64_t* dev) {
+        uint64_t v = read_u64(lane, dev);
+        synced();
+        return v;
+    }
 
     DevTable table(Lay lay, uint64_t n) {
+        if (max_entries && n > max_entries)
+            throw CcError{CC_ERANGE,
+                          "a DP table of " + std::to_string(n) + " entries exceeds the per-table budget of " +
+                              std::to_string(max_entries),
+                          true};
         DevTable t;
         t.lay = lay;
         t.n = n;
@@ -196,12 +250,11 @@ struct Exec {
         t.keys = nullptr;
         t.cnt = nullptr;
     }
-
     template <class F>
     void timed(const char* name, double bytes, F&& launch) {
-        ctx->prof.begin(s, name, bytes);
+        lane.prof.begin(s, name, bytes);
         launch();
-        ctx->prof.end(s);
+        lane.prof.end(s);
     }
 
     // exclusive scan of n counts; returns offsets[n + 1] and the total
@@ -210,7 +263,7 @@ struct Exec {
         uint64_t* tmp = (uint64_t*)raw(scan_tmp_bytes(n));
         timed("scan", 4.0 * n + 8.0 * (n + 1), [&] { launch_scan_u32(in, *offs, n, tmp, s); });
         release(tmp);
-        return read_u64(ctx, *offs + n);
+        return read(*offs + n);
     }
 
     // runs of equal key >> shift; returns G and starts[G + 1]
@@ -258,7 +311,7 @@ void release_tables(cc_context* ctx, RunResult* r) {
     r->links.clear();
 }
 
-void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
+void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     const Plan& plan = rq.dec->plan;
     const Decomp& dec = rq.dec->d;
     const DevGraph g = rq.g->dev();
@@ -269,8 +322,8 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
         if (table_layout(b, g.n, B, k).bits() > 128)
             fail(CC_ERANGE, "packed key (colouring, bag images, colour set) exceeds 128 bits");
 
-    Exec X{ctx, ctx->stream, ctx->arena};
-    hipStream_t s = ctx->stream;
+    Exec X{lane, lane.stream, ctx->arena, rq.max_entries};
+    hipStream_t s = lane.stream;
     const size_t S = plan.steps.size();
     std::vector<DevTable> tab(S);
     std::vector<StepLinks> lk(S);
@@ -599,7 +652,8 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
                       "copy per-vertex");
         }
         hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-        ctx->prof.resolve();
+        X.synced();
+        lane.prof.resolve();
         out->overflow.assign(B, 0);
         for (int b = 0; b < B; b++) out->overflow[b] = of[b] ? 1 : 0;
         int root_node = int(dec.nodes.size()) - 1;
@@ -615,6 +669,8 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
         } else {
             X.drop(tab[plan.root_child]);
         }
+        X.synced();  // the stream is idle: everything released goes back
+        out->peak_bytes = X.peak;
     } catch (...) {
         (void)hipStreamSynchronize(s);
         X.release_all();
@@ -626,11 +682,39 @@ void run_dp(cc_context* ctx, const RunRequest& rq, RunResult* out) {
 
 namespace ccg {
 
+void run_dp_waves(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
+    try {
+        run_dp(ctx, lane, rq, out);
+        return;
+    } catch (const CcError& e) {
+        if (!e.budget || rq.B <= 1 || rq.keep_tables || rq.links) throw;
+    }
+    const int B1 = rq.B / 2;
+    RunRequest a = rq, b = rq;
+    a.B = B1;
+    b.B = rq.B - B1;
+    b.colors = rq.colors + size_t(B1) * size_t(rq.g->n);
+    RunResult ra, rb;
+    run_dp_waves(ctx, lane, a, &ra);
+    run_dp_waves(ctx, lane, b, &rb);
+    out->counts = ra.counts;
+    out->counts.insert(out->counts.end(), rb.counts.begin(), rb.counts.end());
+    out->overflow = ra.overflow;
+    out->overflow.insert(out->overflow.end(), rb.overflow.begin(), rb.overflow.end());
+    if (rq.per_vertex) {
+        out->per_vertex = ra.per_vertex;
+        out->per_vertex.insert(out->per_vertex.end(), rb.per_vertex.begin(), rb.per_vertex.end());
+    }
+    out->node_sizes = ra.node_sizes;
+    for (size_t i = 0; i < out->node_sizes.size() && i < rb.node_sizes.size(); i++) out->node_sizes[i] += rb.node_sizes[i];
+    out->peak_bytes = std::max(ra.peak_bytes, rb.peak_bytes);
+}
+
 // Enumeration (Sec. 4) of one colouring: forward DP keeping every table and
 // its contributor index, lexicographic cut on the image of vertex 0 (the
 // node below the root holds bag {0}, sorted by that image), row decoding on
 // the device, a radix sort of the packed rows and truncation to `cap`.
-void run_enumerate(cc_context* ctx, const cc_graph* g, const uint8_t* colors, int k, const cc_decomp* dec,
+void run_enumerate(cc_context* ctx, Lane& lane, const cc_graph* g, const uint8_t* colors, int k, const cc_decomp* dec,
                    uint64_t cap, std::vector<int32_t>* rows, uint64_t* n_rows, uint64_t* total) {
     const Plan& plan = dec->plan;
     const int nF = dec->d.n;
@@ -645,9 +729,10 @@ void run_enumerate(cc_context* ctx, const cc_graph* g, const uint8_t* colors, in
     rq.k = k;
     rq.dec = dec;
     rq.links = true;
+    rq.max_entries = ctx->max_entries;
     RunResult r;
-    run_dp(ctx, rq, &r);
-    hipStream_t s = ctx->stream;
+    run_dp(ctx, lane, rq, &r);
+    hipStream_t s = lane.stream;
     Arena& A = ctx->arena;
     std::vector<void*> extra;
     auto alloc = [&](size_t bytes) {
@@ -723,24 +808,24 @@ void run_enumerate(cc_context* ctx, const cc_graph* g, const uint8_t* colors, in
         const int rkw = rbits <= 64 ? 1 : 2;
         const size_t rkb = rkw == 1 ? 8 : 16;
         void* keys = alloc(std::max<uint64_t>(R, 1) * rkb);
-        ctx->prof.begin(s, "unrank", double(R) * rkb);
+        lane.prof.begin(s, "unrank", double(R) * rkb);
         launch_unrank(d_steps, plan.root_child, d_rcum, E, R, nF, vb, rkw, keys, err, s);
-        ctx->prof.end(s);
+        lane.prof.end(s);
         uint64_t* vals = (uint64_t*)alloc(std::max<uint64_t>(R, 1) * 8);
         launch_fill_u64(vals, 0, R, s);
         void* k2 = alloc(std::max<uint64_t>(R, 1) * rkb);
         uint64_t* v2 = (uint64_t*)alloc(std::max<uint64_t>(R, 1) * 8);
         void* tmp = alloc(radix_tmp_bytes(R));
-        ctx->prof.begin(s, "row_sort", double(R) * (rkb + 8) * 2);
+        lane.prof.begin(s, "row_sort", double(R) * (rkb + 8) * 2);
         radix_sort(keys, vals, k2, v2, R, rkw, rbits, tmp, s);
-        ctx->prof.end(s);
+        lane.prof.end(s);
         const uint64_t m = std::min(R, cap);
         std::vector<uint64_t> hrows(m * (rkw == 1 ? 1 : 2));
         uint32_t herr = 0;
         hip_check(hipMemcpyAsync(hrows.data(), keys, m * rkb, hipMemcpyDeviceToHost, s), "copy rows");
         hip_check(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s), "copy err");
         hip_check(hipStreamSynchronize(s), "sync");
-        ctx->prof.resolve();
+        lane.prof.resolve();
         if (herr) fail(CC_EDEVICE, "row decoder reported an inconsistent index");
         rows->resize(m * size_t(nF));
         const uint64_t vmask = (uint64_t(1) << vb) - 1;

@@ -1,0 +1,452 @@
+// Multi-query runtime: concurrent batches over worker lanes, the lane-count
+// autotuner, and the serving loop (continuous batching with memory-gated
+// admission).  Every query is one run of the DP executor on one lane; lanes
+// are independent HIP streams sharing the context's arena, so the kernels of
+// concurrent queries overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "engine.h"
+
+using namespace ccg;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct QueryRun {
+    const cc_decomp* d;
+    const uint8_t* colors;
+    int B, k;
+};
+
+// one query on one lane; returns CC_OK or the error code (message in *err)
+int run_one(cc_context* ctx, Lane& lane, const cc_graph* g, const QueryRun& q, uint32_t flags, uint64_t max_entries,
+            RunResult* r, std::string* err) {
+    try {
+        RunRequest rq;
+        rq.g = g;
+        rq.colors = q.colors;
+        rq.B = q.B;
+        rq.k = q.k;
+        rq.dec = q.d;
+        rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
+        rq.max_entries = max_entries;
+        run_dp_waves(ctx, lane, rq, r);
+        return CC_OK;
+    } catch (const CcError& e) {
+        *err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        *err = "host allocation failed";
+        return CC_ENOMEM;
+    }
+}
+
+// plan size proxy for scheduling: more and wider bags first
+double plan_weight(const cc_decomp* d, int B) {
+    double w = 0;
+    for (const Step& s : d->plan.steps) w += double(1 << (2 * s.b_out));
+    return w * B;
+}
+
+int batch_run(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query* q, uint32_t flags, uint64_t* counts,
+              uint8_t* ovf, int lanes, std::string* err) {
+    std::vector<size_t> off(nq + 1, 0);
+    for (int32_t i = 0; i < nq; i++) off[i + 1] = off[i] + size_t(q[i].coloring->B);
+    std::vector<int32_t> order(nq);
+    for (int32_t i = 0; i < nq; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return plan_weight(q[a].decomp, q[a].coloring->B) > plan_weight(q[b].decomp, q[b].coloring->B);
+    });
+    lanes = std::max(1, std::min(lanes, int(nq)));
+    for (int l = 0; l < lanes; l++) ctx->worker(l);
+    std::atomic<int32_t> next{0};
+    std::mutex mu;
+    int first_rc = CC_OK;
+    std::string first_err;
+    std::vector<int32_t> retry;
+    int64_t sizes_total = 0;
+    std::vector<int64_t> sizes_sum;
+    auto worker = [&](int l) {
+        (void)hipSetDevice(ctx->device);
+        Lane& lane = ctx->worker(l);
+        for (;;) {
+            int32_t t = next.fetch_add(1);
+            if (t >= nq) break;
+            int32_t i = order[t];
+            QueryRun qr{q[i].decomp, q[i].coloring->colors, q[i].coloring->B, q[i].coloring->k};
+            RunResult r;
+            std::string e;
+            int rc = run_one(ctx, lane, g, qr, flags, ctx->max_entries, &r, &e);
+            std::lock_guard<std::mutex> guard(mu);
+            if (rc == CC_ENOMEM && lanes > 1) {
+                retry.push_back(i);  // memory was held by concurrent queries
+            } else if (rc != CC_OK) {
+                if (first_rc == CC_OK) {
+                    first_rc = rc;
+                    first_err = "query " + std::to_string(i) + ": " + e;
+                }
+            } else {
+                std::copy(r.counts.begin(), r.counts.end(), counts + off[i]);
+                if (ovf) std::copy(r.overflow.begin(), r.overflow.end(), ovf + off[i]);
+                for (int64_t x : r.node_sizes) sizes_total += x;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int l = 1; l < lanes; l++) th.emplace_back(worker, l);
+    worker(0);
+    for (auto& t : th) t.join();
+    std::sort(retry.begin(), retry.end());
+    for (int32_t i : retry) {  // alone now
+        if (first_rc != CC_OK) break;
+        QueryRun qr{q[i].decomp, q[i].coloring->colors, q[i].coloring->B, q[i].coloring->k};
+        RunResult r;
+        std::string e;
+        int rc = run_one(ctx, ctx->main, g, qr, flags, ctx->max_entries, &r, &e);
+        if (rc != CC_OK) {
+            first_rc = rc;
+            first_err = "query " + std::to_string(i) + ": " + e;
+            break;
+        }
+        std::copy(r.counts.begin(), r.counts.end(), counts + off[i]);
+        if (ovf) std::copy(r.overflow.begin(), r.overflow.end(), ovf + off[i]);
+        for (int64_t x : r.node_sizes) sizes_total += x;
+    }
+    ctx->last_sizes.assign(1, sizes_total);  // batches report the total over all nodes and queries
+    if (first_rc != CC_OK) *err = first_err;
+    return first_rc;
+}
+
+double percentile(std::vector<double> v, double p) {
+    if (v.empty()) return 0;
+    std::sort(v.begin(), v.end());
+    double idx = p * double(v.size() - 1);
+    size_t lo = size_t(idx), hi = std::min(v.size() - 1, lo + 1);
+    return v[lo] + (v[hi] - v[lo]) * (idx - double(lo));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// serving
+
+struct cc_server {
+    struct Req {
+        uint64_t id;
+        const cc_decomp* d;
+        int32_t k;
+        uint64_t seed;
+        int32_t B;
+        size_t est = 0;
+        Clock::time_point arrival, done_at;
+        int state = 0;  // 0 waiting/running, 1 done, < 0 error
+        bool alone = false;
+        std::vector<uint64_t> counts;
+        std::vector<uint8_t> ovf;
+    };
+    cc_context* ctx;
+    const cc_graph* g;
+    cc_server_opts opts;
+    size_t budget = 0, reserved = 0;
+    int running = 0, running_alone = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Req> reqs;
+    std::map<std::pair<const cc_decomp*, int32_t>, size_t> peak_seen;
+    uint64_t next_id = 1;
+    bool stopping = false;
+    std::vector<std::thread> workers;
+    uint64_t submitted = 0, completed = 0, failed = 0, requeued = 0;
+    std::vector<double> latencies_ms;
+    bool have_first = false;
+    Clock::time_point first_arrival, last_done;
+
+    size_t estimate(const Req& r) {
+        auto it = peak_seen.find({r.d, r.B});
+        if (it != peak_seen.end()) return it->second + it->second / 8;
+        return budget / size_t(std::max(1, opts.max_inflight));
+    }
+
+    // oldest admissible request (lock held); 0 if none
+    uint64_t pick() {
+        if (running_alone) return 0;
+        for (size_t i = 0; i < queue.size(); i++) {
+            Req& r = reqs[queue[i]];
+            if (r.alone) {
+                if (running == 0 && i == 0) return queue[i];
+                if (i == 0) return 0;  // waits for the device to drain
+                continue;
+            }
+            if (reserved + r.est <= budget || running == 0) return queue[i];
+        }
+        return 0;
+    }
+
+    void work(int lane_index) {
+        (void)hipSetDevice(ctx->device);
+        Lane& lane = ctx->worker(size_t(lane_index));
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            uint64_t id = 0;
+            cv_work.wait(lk, [&] { return (id = pick()) != 0 || (stopping && queue.empty()); });
+            if (id == 0) return;
+            queue.erase(std::find(queue.begin(), queue.end(), id));
+            Req& r = reqs[id];
+            r.est = estimate(r);
+            size_t hold = r.alone ? budget : r.est;
+            reserved += hold;
+            running++;
+            if (r.alone) running_alone++;
+            const cc_decomp* d = r.d;
+            int32_t k = r.k, B = r.B;
+            uint64_t seed = r.seed;
+            lk.unlock();
+
+            RunResult res;
+            std::string err;
+            int rc = CC_OK;
+            uint8_t* colors = nullptr;
+            try {
+                colors = (uint8_t*)ctx->arena.alloc(size_t(g->n) * size_t(B));
+                launch_color_hash(colors, g->n, B, k, seed, lane.stream);
+            } catch (const CcError& e) {
+                rc = e.code;
+                err = e.msg;
+            }
+            if (rc == CC_OK) {
+                QueryRun qr{d, colors, B, k};
+                rc = run_one(ctx, lane, g, qr, 0, opts.max_entries, &res, &err);
+            }
+            (void)hipStreamSynchronize(lane.stream);
+            if (colors) ctx->arena.release(colors);
+
+            lk.lock();
+            reserved -= hold;
+            running--;
+            if (r.alone) running_alone--;
+            Req& rr = reqs[id];
+            if (rc == CC_ENOMEM && !rr.alone) {
+                rr.alone = true;  // run again when nothing else holds memory
+                queue.push_front(id);
+                requeued++;
+            } else {
+                rr.done_at = Clock::now();
+                if (rc == CC_OK) {
+                    rr.state = 1;
+                    rr.counts = res.counts;
+                    rr.ovf = res.overflow;
+                    peak_seen[{d, B}] = std::max(peak_seen[{d, B}], res.peak_bytes + size_t(g->n) * size_t(B));
+                    completed++;
+                    latencies_ms.push_back(std::chrono::duration<double, std::milli>(rr.done_at - rr.arrival).count());
+                    last_done = rr.done_at;
+                } else {
+                    rr.state = rc;
+                    failed++;
+                }
+                cv_done.notify_all();
+            }
+            cv_work.notify_all();
+        }
+    }
+};
+
+extern "C" {
+
+int cc_set_batch_lanes(cc_context* ctx, int32_t lanes) {
+    if (!ctx || lanes < 0 || lanes > 64) return CC_EINVAL;
+    ctx->batch_lanes = lanes;
+    return CC_OK;
+}
+
+int cc_set_table_budget(cc_context* ctx, uint64_t max_entries) {
+    if (!ctx) return CC_EINVAL;
+    ctx->max_entries = max_entries;
+    return CC_OK;
+}
+
+int cc_count_batch(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query* q, uint32_t flags,
+                   uint64_t* counts_flat, uint8_t* overflow_flat) {
+    if (!ctx || !g || nq < 0 || (nq && !q) || !counts_flat) {
+        set_error("bad arguments");
+        return CC_EINVAL;
+    }
+    for (int32_t i = 0; i < nq; i++) {
+        if (!q[i].decomp || !q[i].coloring || q[i].coloring->ctx != ctx || q[i].coloring->n != g->n ||
+            q[i].coloring->k < q[i].decomp->d.n) {
+            set_error("query " + std::to_string(i) + ": bad decomposition or colouring");
+            return CC_EINVAL;
+        }
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return CC_EDEVICE;
+    }
+    std::string err;
+    int lanes = ctx->batch_lanes > 0 ? ctx->batch_lanes : 4;
+    int rc = batch_run(ctx, g, nq, q, flags, counts_flat, overflow_flat, lanes, &err);
+    set_error(rc == CC_OK ? "" : err);
+    return rc;
+}
+
+int cc_tune_batch(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query* q, uint32_t flags, int32_t* best) {
+    if (!ctx || !g || !best || nq <= 0 || !q) {
+        set_error("bad arguments");
+        return CC_EINVAL;
+    }
+    size_t total = 0;
+    for (int32_t i = 0; i < nq; i++) total += size_t(q[i].coloring->B);
+    std::vector<uint64_t> counts(total);
+    double best_t = 1e300;
+    int best_l = 1;
+    for (int l : {1, 2, 4, 8}) {
+        ctx->batch_lanes = l;
+        auto t0 = Clock::now();
+        int rc = cc_count_batch(ctx, g, nq, q, flags, counts.data(), nullptr);
+        double dt = std::chrono::duration<double>(Clock::now() - t0).count();
+        if (rc != CC_OK) return rc;
+        if (dt < best_t) {
+            best_t = dt;
+            best_l = l;
+        }
+    }
+    ctx->batch_lanes = best_l;
+    *best = best_l;
+    return CC_OK;
+}
+
+int cc_server_start(cc_context* ctx, const cc_graph* g, const cc_server_opts* opts, cc_server** out) {
+    if (!ctx || !g || !opts || !out || opts->max_inflight < 1 || opts->max_inflight > 64) {
+        set_error("bad arguments");
+        return CC_EINVAL;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return CC_EDEVICE;
+    }
+    auto* s = new cc_server();
+    s->ctx = ctx;
+    s->g = g;
+    s->opts = *opts;
+    s->budget = opts->mem_budget ? std::min(opts->mem_budget, ctx->arena.size()) : ctx->arena.size();
+    try {
+        for (int l = 0; l < opts->max_inflight; l++) ctx->worker(size_t(l));
+    } catch (const CcError& e) {
+        set_error(e.msg);
+        delete s;
+        return e.code;
+    }
+    for (int l = 0; l < opts->max_inflight; l++) s->workers.emplace_back([s, l] { s->work(l); });
+    *out = s;
+    return CC_OK;
+}
+
+int cc_server_submit(cc_server* srv, const cc_decomp* d, int32_t k, uint64_t seed, int32_t num_colorings,
+                     uint64_t* ticket) {
+    if (!srv || !d || !ticket || num_colorings < 1 || k < d->d.n || k > 12) {
+        set_error("bad arguments");
+        return CC_EINVAL;
+    }
+    std::lock_guard<std::mutex> guard(srv->mu);
+    if (srv->stopping) {
+        set_error("server is stopping");
+        return CC_ECANCELLED;
+    }
+    cc_server::Req r;
+    r.id = srv->next_id++;
+    r.d = d;
+    r.k = k;
+    r.seed = seed;
+    r.B = num_colorings;
+    r.arrival = Clock::now();
+    r.est = srv->estimate(r);
+    if (!srv->have_first) {
+        srv->have_first = true;
+        srv->first_arrival = r.arrival;
+    }
+    srv->reqs[r.id] = r;
+    srv->queue.push_back(r.id);
+    srv->submitted++;
+    *ticket = r.id;
+    srv->cv_work.notify_all();
+    return CC_OK;
+}
+
+static int copy_result(cc_server::Req& r, uint64_t* counts, uint8_t* overflow, int32_t* state) {
+    *state = r.state;
+    if (r.state == 1) {
+        if (counts) std::copy(r.counts.begin(), r.counts.end(), counts);
+        if (overflow) std::copy(r.ovf.begin(), r.ovf.end(), overflow);
+    }
+    return CC_OK;
+}
+
+int cc_server_poll(cc_server* srv, uint64_t ticket, uint64_t* counts, uint8_t* overflow, int32_t* state) {
+    if (!srv || !state) return CC_EINVAL;
+    std::lock_guard<std::mutex> guard(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) {
+        set_error("unknown ticket");
+        return CC_EINVAL;
+    }
+    return copy_result(it->second, counts, overflow, state);
+}
+
+int cc_server_wait(cc_server* srv, uint64_t ticket, uint64_t* counts, uint8_t* overflow, int32_t* state) {
+    if (!srv || !state) return CC_EINVAL;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) {
+        set_error("unknown ticket");
+        return CC_EINVAL;
+    }
+    srv->cv_done.wait(lk, [&] { return it->second.state != 0; });
+    return copy_result(it->second, counts, overflow, state);
+}
+
+int cc_server_stop(cc_server* srv, cc_server_stats* stats) {
+    if (!srv) return CC_OK;
+    {
+        std::lock_guard<std::mutex> guard(srv->mu);
+        srv->stopping = true;
+        srv->cv_work.notify_all();
+    }
+    for (auto& t : srv->workers) t.join();
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->submitted = srv->submitted;
+        stats->completed = srv->completed;
+        stats->failed = srv->failed;
+        stats->requeued = srv->requeued;
+        if (srv->completed) {
+            stats->wall_s = std::chrono::duration<double>(srv->last_done - srv->first_arrival).count();
+            stats->qps = stats->wall_s > 0 ? double(srv->completed) / stats->wall_s : 0;
+            stats->p50_ms = percentile(srv->latencies_ms, 0.50);
+            stats->p99_ms = percentile(srv->latencies_ms, 0.99);
+            double sum = 0, mx = 0;
+            for (double x : srv->latencies_ms) {
+                sum += x;
+                mx = std::max(mx, x);
+            }
+            stats->mean_ms = sum / double(srv->latencies_ms.size());
+            stats->max_ms = mx;
+        }
+    }
+    delete srv;
+    return CC_OK;
+}
+
+}  // extern "C"

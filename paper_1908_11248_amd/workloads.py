@@ -389,6 +389,37 @@ def random_query(seed: int) -> Pattern:
     return p
 
 
+def select_queries(index: int, count: int, fits, max_redraws: int = 200):
+    """The query stream of a batched/served workload under a work budget.
+
+    Query i starts from seed query_seeds(index, count)[i]; while
+    fits(pattern, seed) is False the query is redrawn from seed + 1 (a fresh
+    size and family draw).  `fits` is the caller's budget test (the per-table
+    entry budget on the query's first colouring).  Returns a list of
+    (pattern, seed) and a dict of redraw counts keyed by (family, size) of
+    the rejected draws."""
+    out = []
+    redraws = {}
+    for s0 in query_seeds(index, count):
+        s = s0
+        for _ in range(max_redraws):
+            p = random_query(s)
+            if fits(p, s):
+                break
+            key = (p.family, p.n)
+            redraws[key] = redraws.get(key, 0) + 1
+            s += 1
+        else:
+            raise RuntimeError("no query within the budget after %d redraws" % max_redraws)
+        out.append((p, s))
+    return out, redraws
+
+
+def colouring_seed(query_seed: int) -> int:
+    """Seed of a query's colourings."""
+    return query_seed ^ 0xC0
+
+
 # ---------------------------------------------------------------------------
 # the five standard workloads
 
