@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libccgpu.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["kernels.hip", "fused.hip", "enumerate.hip", "engine.hip", "capi.cpp", "runtime.cpp", "planner.cpp"]
+SOURCES = ["kernels.hip", "expand.hip", "fused.hip", "enumerate.hip", "engine.hip", "capi.cpp", "runtime.cpp", "planner.cpp"]
 ARCH = os.environ.get("CCGPU_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -48,6 +48,12 @@ def build(verbose: bool = False) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
+    # every library-internal symbol must be defined in the link
+    und = subprocess.run(["nm", "-D", "--undefined-only", tmp], capture_output=True, text=True).stdout
+    missing = [l.split()[-1] for l in und.splitlines() if "3ccg" in l]
+    if missing:
+        os.remove(tmp)
+        raise RuntimeError("undefined library symbols: %s" % ", ".join(missing))
     os.replace(tmp, OUT)
     if verbose:
         print(OUT)

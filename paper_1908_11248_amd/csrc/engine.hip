@@ -441,18 +441,28 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     uint64_t* woff;
                     uint64_t W = X.scan(wcount, G, &woff);
                     X.release(wcount);
-                    uint32_t* ocount = X.alloc<uint32_t>(W);
-                    X.timed("push_count", double(in.n) * in.lay.key_bytes() + 9.0 * W,
-                            [&] { launch_push_count(in, gstart, woff, G, W, g, rq.colors, ia, ocount, s); });
-                    uint64_t* ooff;
-                    uint64_t N = X.scan(ocount, W, &ooff);
-                    X.release(ocount);
+                    uint32_t* slen = X.alloc<uint32_t>(W);
+                    X.timed("push_seglen", 24.0 * W, [&] { launch_push_seglen(in, gstart, woff, G, W, g, ia, slen, s); });
+                    uint64_t* soff;
+                    uint64_t T = X.scan(slen, W, &soff);
+                    X.release(slen);
+                    uint64_t tiles = expand_tiles(T);
+                    uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                    X.timed("push_count", double(T) * in.lay.key_bytes(), [&] {
+                        launch_expand_count(false, in, gstart, woff, G, nullptr, soff, W, T, g, rq.colors, ia, tcount, s);
+                    });
+                    uint64_t* toff;
+                    uint64_t N = X.scan(tcount, tiles, &toff);
+                    X.release(tcount);
                     o = X.table(lo, N);
                     if (links) lk[i].src = X.alloc<uint64_t>(N);
                     if (N)
-                        X.timed("push_emit", double(in.n) * (in.lay.key_bytes() + 8) + 13.0 * W + double(N) * (lo.key_bytes() + 8),
-                                [&] { launch_push_emit(in, gstart, woff, G, W, g, rq.colors, ia, ooff, o, lk[i].src, s); });
-                    X.release(ooff);
+                        X.timed("push_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8), [&] {
+                            launch_expand_emit(false, in, gstart, woff, G, nullptr, soff, W, T, g, rq.colors, ia, toff, o,
+                                               lk[i].src, s);
+                        });
+                    X.release(toff);
+                    X.release(soff);
                     X.release(woff);
                     X.release(gstart);
                     break;
@@ -469,19 +479,29 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     launch_fill_u64(rstart, 0, slots, s);
                     launch_fill_u64(rend, 0, slots, s);
                     X.timed("pull_index", double(in.n) * in.lay.key_bytes(), [&] { launch_pull_index(in, g.n, rstart, rend, s); });
-                    uint64_t W = uint64_t(B) * uint64_t(g.m2);
-                    uint32_t* ocount = X.alloc<uint32_t>(W);
-                    X.timed("pull_count", double(in.n) * in.lay.key_bytes() + 13.0 * W,
-                            [&] { launch_pull_count(in, rstart, rend, B, g, rq.colors, ia, ocount, s); });
-                    uint64_t* ooff;
-                    uint64_t N = X.scan(ocount, W, &ooff);
-                    X.release(ocount);
+                    uint64_t S = uint64_t(B) * uint64_t(g.m2);
+                    uint32_t* slen = X.alloc<uint32_t>(S);
+                    X.timed("pull_seglen", 32.0 * S, [&] { launch_pull_seglen(rstart, rend, B, g, ia.degF, slen, s); });
+                    uint64_t* soff;
+                    uint64_t T = X.scan(slen, S, &soff);
+                    X.release(slen);
+                    uint64_t tiles = expand_tiles(T);
+                    uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                    X.timed("pull_count", double(T) * in.lay.key_bytes(), [&] {
+                        launch_expand_count(true, in, nullptr, nullptr, 0, rstart, soff, S, T, g, rq.colors, ia, tcount, s);
+                    });
+                    uint64_t* toff;
+                    uint64_t N = X.scan(tcount, tiles, &toff);
+                    X.release(tcount);
                     o = X.table(lo, N);
                     if (links) lk[i].src = X.alloc<uint64_t>(N);
                     if (N)
-                        X.timed("pull_emit", double(in.n) * (in.lay.key_bytes() + 8) + 17.0 * W + double(N) * (lo.key_bytes() + 8),
-                                [&] { launch_pull_emit(in, rstart, rend, B, g, rq.colors, ia, ooff, o, lk[i].src, s); });
-                    X.release(ooff);
+                        X.timed("pull_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8), [&] {
+                            launch_expand_emit(true, in, nullptr, nullptr, 0, rstart, soff, S, T, g, rq.colors, ia, toff, o,
+                                               lk[i].src, s);
+                        });
+                    X.release(toff);
+                    X.release(soff);
                     X.release(rstart);
                     X.release(rend);
                     break;

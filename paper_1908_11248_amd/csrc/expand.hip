@@ -1,0 +1,241 @@
+// Introduce (Sec. 3.1 introduce rule) as a load-balanced expand.
+//
+// The candidate pairs of an introduce node form segments: in the push form a
+// segment is (prefix group of the child, one candidate image v of the new
+// vertex taken from the adjacency list of the anchor's image); in the pull
+// form it is (colouring b, stored edge (v, y) of G), the run of child entries
+// whose column 0 is y.  An item is (segment, child entry).  A first kernel
+// writes every segment's length (0 when v fails the degree mask, Sec. 3.2,
+// or an adjacency check that does not depend on the entry), a scan gives the
+// item offsets, and the expand kernels walk fixed tiles of 4096 items, 16
+// consecutive items per thread, so a hub's long run is spread over many
+// threads and blocks.  Items are tested for the colour of v (not in C) and
+// the remaining adjacency checks; survivors are compacted in item order,
+// which is the key order of the output.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace ccg {
+
+constexpr int kExpItems = 16;
+constexpr int kExpTile = kBlock * kExpItems;
+
+// ---- segment lengths -------------------------------------------------------
+
+template <class K>
+__global__ void k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gstart,
+                              const uint64_t* __restrict__ woff, uint64_t G, uint64_t W, DevGraph g, IntroArgs a,
+                              uint32_t* slen) {
+    for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < W; s += uint64_t(gridDim.x) * blockDim.x) {
+        uint64_t grp = upper_bound_u64(woff, 0, G + 1, s) - 1;
+        uint64_t t = s - woff[grp];
+        K k0 = keys[gstart[grp]];
+        uint32_t v = a.anchor >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, a.anchor)] + int64_t(t)]) : uint32_t(t);
+        bool ok = gdeg(g, v) >= a.degF;
+        for (int c = 0; c < a.nchk && ok; c++)
+            if (a.chk[c] < a.pos) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
+        slen[s] = ok ? uint32_t(gstart[grp + 1] - gstart[grp]) : 0u;
+    }
+}
+
+__global__ void k_pull_seglen(const uint64_t* __restrict__ rstart, const uint64_t* __restrict__ rend, int B, DevGraph g,
+                              int degF, uint32_t* slen) {
+    uint64_t W = uint64_t(B) * uint64_t(g.m2);
+    for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < W; s += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t bid = uint32_t(s / uint64_t(g.m2));
+        uint64_t e = s % uint64_t(g.m2);
+        uint32_t v = uint32_t(g.esrc[e]);
+        uint64_t slot = uint64_t(bid) * uint64_t(g.n) + uint32_t(g.col[e]);
+        slen[s] = gdeg(g, v) >= degF ? uint32_t(rend[slot] - rstart[slot]) : 0u;
+    }
+}
+
+// ---- the expand ----------------------------------------------------------
+
+struct SegState {
+    uint32_t bid, v, cb;
+    uint64_t base;  // child index of the segment's first item
+};
+
+// state of segment s; in the push form *grp is the segment's prefix group,
+// advanced linearly from its previous value (segments and groups are both
+// in increasing order)
+template <class K, bool PULL>
+__device__ __forceinline__ SegState seg_state(uint64_t s, uint64_t* grp, const K* keys, const Lay& L,
+                                              const uint64_t* gstart, const uint64_t* woff, const uint64_t* rstart,
+                                              const DevGraph& g, const uint8_t* colors, const IntroArgs& a) {
+    SegState st;
+    if (PULL) {
+        st.bid = uint32_t(s / uint64_t(g.m2));
+        uint64_t e = s % uint64_t(g.m2);
+        st.v = uint32_t(g.esrc[e]);
+        st.base = rstart[uint64_t(st.bid) * uint64_t(g.n) + uint32_t(g.col[e])];
+    } else {
+        while (woff[*grp + 1] <= s) (*grp)++;
+        uint64_t t = s - woff[*grp];
+        st.base = gstart[*grp];
+        K k0 = keys[st.base];
+        st.bid = kbid(k0, L);
+        st.v = a.anchor >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, a.anchor)] + int64_t(t)]) : uint32_t(t);
+    }
+    st.cb = 1u << colors[uint64_t(st.bid) * g.n + st.v];
+    return st;
+}
+
+template <class KI, class KO, bool EMIT, bool PULL>
+__global__ void __launch_bounds__(kBlock)
+k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ gstart,
+         const uint64_t* __restrict__ woff, uint64_t G, const uint64_t* __restrict__ rstart,
+         const uint64_t* __restrict__ soff, uint64_t S, uint64_t T, DevGraph g, const uint8_t* __restrict__ colors,
+         IntroArgs a, uint32_t* tcount, const uint64_t* __restrict__ toff, KO* okeys, uint64_t* ocnt, Lay LO,
+         uint64_t* osrc) {
+    __shared__ uint64_t bounds[4];  // segment and group ranges of the tile
+    const uint64_t tiles = (T + kExpTile - 1) / kExpTile;
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint64_t tile0 = tile * kExpTile;
+        const uint64_t tile1 = tile0 + kExpTile < T ? tile0 + kExpTile : T;
+        if (threadIdx.x == 0) {
+            uint64_t s_lo = upper_bound_u64(soff, 0, S + 1, tile0) - 1;
+            uint64_t s_hi = upper_bound_u64(soff, s_lo, S + 1, tile1 - 1);  // one past the last segment
+            bounds[0] = s_lo;
+            bounds[1] = s_hi;
+            if (!PULL) {
+                bounds[2] = upper_bound_u64(woff, 0, G + 1, s_lo) - 1;
+                bounds[3] = upper_bound_u64(woff, bounds[2], G + 1, s_hi - 1);
+            }
+        }
+        __syncthreads();
+        const uint64_t s_lo = bounds[0], s_hi = bounds[1];
+        const uint64_t g_lo = PULL ? 0 : bounds[2], g_hi = PULL ? 0 : bounds[3];
+        __syncthreads();
+        const uint64_t t0 = tile0 + uint64_t(threadIdx.x) * kExpItems;
+        const uint64_t t1 = t0 + kExpItems < tile1 ? t0 + kExpItems : tile1;
+        uint32_t pass = 0;  // bit j: item t0 + j survives
+        uint32_t n_pass = 0;
+        uint64_t seg0 = 0, grp0 = g_lo;
+        if (t0 < tile1) {
+            seg0 = upper_bound_u64(soff, s_lo, s_hi + 1, t0) - 1;
+            if (!PULL) grp0 = upper_bound_u64(woff, g_lo, g_hi + 1, seg0) - 1;
+            uint64_t seg = seg0, grp = grp0;
+            SegState st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
+            grp0 = grp;
+            for (uint64_t t = t0; t < t1; t++) {
+                if (soff[seg + 1] <= t) {
+                    do seg++;
+                    while (soff[seg + 1] <= t);
+                    st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
+                }
+                KI k = keys[st.base + (t - soff[seg])];
+                if (kset(k, L) & st.cb) continue;
+                bool ok = true;
+                for (int c = 0; c < a.nchk && ok; c++)
+                    if (PULL || a.chk[c] >= a.pos) ok = has_edge(g, kcol(k, L, a.chk[c]), st.v);
+                if (!ok) continue;
+                pass |= 1u << (t - t0);
+                n_pass++;
+            }
+        }
+        uint64_t total;
+        uint64_t my = block_excl_scan(n_pass, &total);
+        if (!EMIT) {
+            if (threadIdx.x == 0) tcount[tile] = uint32_t(total);
+            continue;
+        }
+        if (!pass) continue;
+        uint64_t o = toff[tile] + my;
+        uint64_t seg = seg0, grp = grp0;
+        SegState st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
+        for (uint64_t t = t0; t < t1; t++) {
+            if (!(pass >> (t - t0) & 1u)) continue;
+            if (soff[seg + 1] <= t) {
+                do seg++;
+                while (soff[seg + 1] <= t);
+                st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
+            }
+            uint64_t i = st.base + (t - soff[seg]);
+            KI k = keys[i];
+            uint32_t cols[5];
+            if (PULL) {
+                cols[0] = st.v;
+                for (int j = 1; j < LO.b; j++) cols[j] = kcol(k, L, j - 1);
+            } else {
+                for (int j = 0, s2 = 0; j < LO.b; j++) cols[j] = (j == a.pos) ? st.v : kcol(k, L, s2++);
+            }
+            okeys[o] = kpack<KO>(st.bid, cols, LO.b, kset(k, L) | st.cb, LO);
+            ocnt[o] = cnt[i];
+            if (osrc) osrc[o] = i;
+            o++;
+        }
+    }
+}
+
+// ---- launchers -------------------------------------------------------------
+
+void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
+                        DevGraph g, const IntroArgs& a, uint32_t* slen, hipStream_t s) {
+    if (!W) return;
+    if (in.lay.kw() == 1)
+        k_push_seglen<uint64_t><<<grid_for(W), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, gstart, woff, G, W, g, a,
+                                                               slen);
+    else
+        k_push_seglen<u128><<<grid_for(W), kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, woff, G, W, g, a, slen);
+}
+
+void launch_pull_seglen(const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g, int degF, uint32_t* slen,
+                        hipStream_t s) {
+    uint64_t W = uint64_t(B) * uint64_t(g.m2);
+    if (W) k_pull_seglen<<<grid_for(W), kBlock, 0, s>>>(rstart, rend, B, g, degF, slen);
+}
+
+uint64_t expand_tiles(uint64_t T) { return (T + kExpTile - 1) / kExpTile; }
+
+template <bool EMIT, bool PULL>
+static void expand_dispatch(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
+                            const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
+                            const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, const uint64_t* toff,
+                            DevTable* out, uint64_t* osrc, hipStream_t s) {
+    uint64_t tiles = expand_tiles(T);
+    if (!tiles) return;
+    unsigned grid = unsigned(tiles < (1u << 20) ? tiles : (1u << 20));
+    Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
+    void* ok = out ? out->keys : nullptr;
+    uint64_t* oc = out ? out->cnt : nullptr;
+    int ki = in.lay.kw(), ko = LO.kw();
+    if (ki == 1 && ko == 1)
+        k_expand<uint64_t, uint64_t, EMIT, PULL><<<grid, kBlock, 0, s>>>(
+            (const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff, G, rstart, soff, S, T, g, colors, a, tcount, toff,
+            (uint64_t*)ok, oc, LO, osrc);
+    else if (ki == 1)
+        k_expand<uint64_t, u128, EMIT, PULL><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff,
+                                                                      G, rstart, soff, S, T, g, colors, a, tcount, toff,
+                                                                      (u128*)ok, oc, LO, osrc);
+    else
+        k_expand<u128, u128, EMIT, PULL><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, gstart, woff, G,
+                                                                  rstart, soff, S, T, g, colors, a, tcount, toff,
+                                                                  (u128*)ok, oc, LO, osrc);
+}
+
+void launch_expand_count(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
+                         const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
+                         const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, hipStream_t s) {
+    if (pull)
+        expand_dispatch<false, true>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, tcount, nullptr, nullptr,
+                                     nullptr, s);
+    else
+        expand_dispatch<false, false>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, tcount, nullptr, nullptr,
+                                      nullptr, s);
+}
+
+void launch_expand_emit(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
+                        const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
+                        const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, DevTable& out, uint64_t* osrc,
+                        hipStream_t s) {
+    if (pull)
+        expand_dispatch<true, true>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, nullptr, toff, &out, osrc, s);
+    else
+        expand_dispatch<true, false>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, nullptr, toff, &out, osrc, s);
+}
+
+}  // namespace ccg

@@ -74,23 +74,25 @@ struct IntroArgs {
 };
 void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, DevGraph g,
                       const IntroArgs& a, uint32_t* wcount, hipStream_t s);
-void launch_push_count(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
-                       uint64_t W, DevGraph g, const uint8_t* colors, const IntroArgs& a,
-                       uint32_t* ocount, hipStream_t s);
-void launch_push_emit(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
-                      uint64_t W, DevGraph g, const uint8_t* colors, const IntroArgs& a,
-                      const uint64_t* ooff, DevTable& out, uint64_t* osrc, hipStream_t s);
+// load-balanced expand of introduce candidates (expand.hip): segment
+// lengths, then count and emit over tiles of expand_tiles(T) items
+void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
+                        DevGraph g, const IntroArgs& a, uint32_t* slen, hipStream_t s);
+void launch_pull_seglen(const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g, int degF, uint32_t* slen,
+                        hipStream_t s);
+uint64_t expand_tiles(uint64_t T);
+void launch_expand_count(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
+                         const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
+                         const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, hipStream_t s);
+void launch_expand_emit(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
+                        const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
+                        const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, DevTable& out, uint64_t* osrc,
+                        hipStream_t s);
 
 // introduce, pull form (child column 0 is the anchor).  launch_pull_index
 // writes the (colouring, column 0) run index rstart/rend[b * n + v] of a
 // table (slots must be zero beforehand); the join uses it too.
 void launch_pull_index(const DevTable& in, int32_t n, uint64_t* rstart, uint64_t* rend, hipStream_t s);
-void launch_pull_count(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B,
-                       DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount,
-                       hipStream_t s);
-void launch_pull_emit(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B,
-                      DevGraph g, const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff,
-                      DevTable& out, uint64_t* osrc, hipStream_t s);
 
 // forget of the last column, reduced per group with a dense colour-set accumulator
 void launch_forget_count(const DevTable& in, const uint64_t* gstart, uint64_t G, uint32_t* gcount,

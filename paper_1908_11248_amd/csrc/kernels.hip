@@ -196,10 +196,10 @@ void launch_leaf_emit(DevGraph g, int B, int degF, const uint8_t* colors, const 
 }
 
 // ---------------------------------------------------------------------------
-// introduce, push form (Sec. 3.1 introduce rule, candidates from the adjacency
-// list of a mapped bag neighbour, Sec. 3.2).  Work unit = (prefix group,
-// candidate); the group holds every child entry sharing the images of the
-// columns before the insertion point.
+// introduce, push form: candidates per prefix group (the child entries that
+// share the images of the columns before the insertion point) come from the
+// adjacency list of a mapped bag neighbour (Sec. 3.2); expand.hip does the
+// rest.
 
 template <class K>
 __global__ void k_push_work(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gstart, uint64_t G,
@@ -214,50 +214,6 @@ __global__ void k_push_work(const K* __restrict__ keys, Lay L, const uint64_t* _
     }
 }
 
-template <class KI, class KO, bool EMIT>
-__global__ void __launch_bounds__(kBlock)
-k_push(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ gstart,
-       const uint64_t* __restrict__ woff, uint64_t G, uint64_t W, DevGraph g, const uint8_t* __restrict__ colors,
-       IntroArgs a, uint32_t* ocount, const uint64_t* __restrict__ ooff, KO* okeys, uint64_t* ocnt, Lay LO,
-       uint64_t* osrc) {
-    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < W; w += uint64_t(gridDim.x) * blockDim.x) {
-        uint64_t grp = upper_bound_u64(woff, 0, G + 1, w) - 1;
-        uint64_t t = w - woff[grp];
-        uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
-        KI k0 = keys[e0];
-        uint32_t bid = kbid(k0, L);
-        uint32_t v = a.anchor >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, a.anchor)] + int64_t(t)]) : uint32_t(t);
-        uint32_t produced = 0;
-        bool ok = gdeg(g, v) >= a.degF;
-        for (int c = 0; c < a.nchk && ok; c++)
-            if (a.chk[c] < a.pos) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
-        uint64_t o = EMIT ? ooff[w] : 0;
-        if (ok) {
-            uint32_t cb = 1u << colors[uint64_t(bid) * g.n + v];
-            for (uint64_t e = e0; e < e1; e++) {
-                KI k = keys[e];
-                uint32_t C = kset(k, L);
-                if (C & cb) continue;
-                bool fine = true;
-                for (int c = 0; c < a.nchk && fine; c++)
-                    if (a.chk[c] >= a.pos) fine = has_edge(g, kcol(k, L, a.chk[c]), v);
-                if (!fine) continue;
-                if (EMIT) {
-                    uint32_t cols[5];
-                    for (int j = 0, s = 0; j < LO.b; j++) cols[j] = (j == a.pos) ? v : kcol(k, L, s++);
-                    okeys[o] = kpack<KO>(bid, cols, LO.b, C | cb, LO);
-                    ocnt[o] = cnt[e];
-                    if (osrc) osrc[o] = e;
-                    o++;
-                } else {
-                    produced++;
-                }
-            }
-        }
-        if (!EMIT) ocount[w] = produced;
-    }
-}
-
 void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, DevGraph g, const IntroArgs& a,
                       uint32_t* wcount, hipStream_t s) {
     if (!G) return;
@@ -267,41 +223,11 @@ void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, De
         k_push_work<u128><<<grid_for(G), kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, G, g, a.anchor, wcount);
 }
 
-template <bool EMIT>
-static void push_dispatch(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
-                          DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount,
-                          const uint64_t* ooff, DevTable* out, uint64_t* osrc, hipStream_t s) {
-    if (!W) return;
-    Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
-    void* ok = out ? out->keys : nullptr;
-    uint64_t* oc = out ? out->cnt : nullptr;
-    unsigned grid = grid_for(W);
-    int ki = in.lay.kw(), ko = LO.kw();
-    if (ki == 1 && ko == 1)
-        k_push<uint64_t, uint64_t, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff, G, W,
-                                                                 g, colors, a, ocount, ooff, (uint64_t*)ok, oc, LO, osrc);
-    else if (ki == 1 && ko == 2)
-        k_push<uint64_t, u128, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff, G, W,
-                                                             g, colors, a, ocount, ooff, (u128*)ok, oc, LO, osrc);
-    else
-        k_push<u128, u128, EMIT><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, gstart, woff, G, W, g,
-                                                         colors, a, ocount, ooff, (u128*)ok, oc, LO, osrc);
-}
-
-void launch_push_count(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
-                       DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, hipStream_t s) {
-    push_dispatch<false>(in, gstart, woff, G, W, g, colors, a, ocount, nullptr, nullptr, nullptr, s);
-}
-void launch_push_emit(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
-                      DevGraph g, const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff, DevTable& out,
-                      uint64_t* osrc, hipStream_t s) {
-    push_dispatch<true>(in, gstart, woff, G, W, g, colors, a, nullptr, ooff, &out, osrc, s);
-}
-
 // ---------------------------------------------------------------------------
 // introduce, pull form: u inserted as column 0.  For every colouring b and
 // every stored edge (v, y) of G (rows ascending), the child's run of entries
-// with column 0 = y is extended by u -> v.  Output order: (b, v, y, rest, C).
+// with column 0 = y is extended by u -> v (expand.hip); output order
+// (b, v, y, rest, C).  The run index below locates those runs.
 
 template <class K>
 __global__ void k_pull_index(const K* __restrict__ keys, uint64_t N, Lay L, int32_t n, uint64_t* rstart,
@@ -324,79 +250,7 @@ void launch_pull_index(const DevTable& in, int32_t n, uint64_t* rstart, uint64_t
         k_pull_index<u128><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.n, in.lay, n, rstart, rend);
 }
 
-template <class KI, class KO, bool EMIT>
-__global__ void __launch_bounds__(kBlock)
-k_pull(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ rstart,
-       const uint64_t* __restrict__ rend, int B, DevGraph g, const uint8_t* __restrict__ colors, IntroArgs a,
-       uint32_t* ocount, const uint64_t* __restrict__ ooff, KO* okeys, uint64_t* ocnt, Lay LO, uint64_t* osrc) {
-    uint64_t W = uint64_t(B) * uint64_t(g.m2);
-    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < W; w += uint64_t(gridDim.x) * blockDim.x) {
-        uint32_t bid = uint32_t(w / uint64_t(g.m2));
-        uint64_t e = w % uint64_t(g.m2);
-        uint32_t v = uint32_t(g.esrc[e]);
-        uint32_t y = uint32_t(g.col[e]);
-        uint32_t produced = 0;
-        uint64_t o = EMIT ? ooff[w] : 0;
-        if (gdeg(g, v) >= a.degF) {
-            uint64_t slot = uint64_t(bid) * uint64_t(g.n) + y;
-            uint64_t r0 = rstart[slot], r1 = rend[slot];
-            uint32_t cb = 1u << colors[uint64_t(bid) * g.n + v];
-            for (uint64_t i = r0; i < r1; i++) {
-                KI k = keys[i];
-                uint32_t C = kset(k, L);
-                if (C & cb) continue;
-                bool fine = true;
-                for (int c = 0; c < a.nchk && fine; c++) fine = has_edge(g, kcol(k, L, a.chk[c]), v);
-                if (!fine) continue;
-                if (EMIT) {
-                    uint32_t cols[5];
-                    cols[0] = v;
-                    for (int j = 1; j < LO.b; j++) cols[j] = kcol(k, L, j - 1);
-                    okeys[o] = kpack<KO>(bid, cols, LO.b, C | cb, LO);
-                    ocnt[o] = cnt[i];
-                    if (osrc) osrc[o] = i;
-                    o++;
-                } else {
-                    produced++;
-                }
-            }
-        }
-        if (!EMIT) ocount[w] = produced;
-    }
-}
-
-template <bool EMIT>
-static void pull_dispatch(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
-                          const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, const uint64_t* ooff,
-                          DevTable* out, uint64_t* osrc, hipStream_t s) {
-    uint64_t W = uint64_t(B) * uint64_t(g.m2);
-    if (!W) return;
-    Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
-    void* ok = out ? out->keys : nullptr;
-    uint64_t* oc = out ? out->cnt : nullptr;
-    unsigned grid = grid_for(W);
-    int ki = in.lay.kw(), ko = LO.kw();
-    if (ki == 1 && ko == 1)
-        k_pull<uint64_t, uint64_t, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, rstart, rend, B, g,
-                                                                 colors, a, ocount, ooff, (uint64_t*)ok, oc, LO, osrc);
-    else if (ki == 1 && ko == 2)
-        k_pull<uint64_t, u128, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, rstart, rend, B, g,
-                                                             colors, a, ocount, ooff, (u128*)ok, oc, LO, osrc);
-    else
-        k_pull<u128, u128, EMIT><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, rstart, rend, B, g, colors,
-                                                         a, ocount, ooff, (u128*)ok, oc, LO, osrc);
-}
-
-void launch_pull_count(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
-                       const uint8_t* colors, const IntroArgs& a, uint32_t* ocount, hipStream_t s) {
-    pull_dispatch<false>(in, rstart, rend, B, g, colors, a, ocount, nullptr, nullptr, nullptr, s);
-}
-void launch_pull_emit(const DevTable& in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
-                      const uint8_t* colors, const IntroArgs& a, const uint64_t* ooff, DevTable& out, uint64_t* osrc,
-                      hipStream_t s) {
-    pull_dispatch<true>(in, rstart, rend, B, g, colors, a, nullptr, ooff, &out, osrc, s);
-}
-
+// ---------------------------------------------------------------------------
 // forget of the last column (Sec. 3.1 forget rule): per run of equal
 // (colouring, first b-1 images), add the counts of equal colour sets.
 template <class KI, class KO, bool EMIT>

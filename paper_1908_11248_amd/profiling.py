@@ -1,0 +1,122 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+    python -m paper_1908_11248_amd.profiling stats  <kernel_stats.csv> <out.md> <command...>
+    python -m paper_1908_11248_amd.profiling traffic <fetch_dir> <write_dir> <copy_mib> <out.json> <command...>
+
+`stats` turns a --kernel-trace --stats CSV into a short table.  `traffic`
+reads two --pmc runs (FETCH_SIZE, WRITE_SIZE; values in KiB per dispatch),
+scales every dispatch by the factor measured on the calibration copy kernel
+(bytes it must move / bytes counted) and writes bytes per launch per kernel,
+keyed by the short kernel names the library's profiler uses, together with a
+hash of the kernel sources the counters were taken on.
+"""
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# device kernel -> library profiler name
+KERNEL_NAMES = [
+    (r"k_edge<.*true, true>", "edge_emit"), (r"k_edge<.*true, false>", "edge_emit"),
+    (r"k_edge<.*false, true>", "edge_count"), (r"k_edge<.*false, false>", "edge_count"),
+    (r"k_join<.*true>", "join_emit"), (r"k_join<.*false>", "join_count"),
+    (r"k_forget<.*true>", "forget_emit"), (r"k_forget<.*false>", "forget_count"),
+    (r"k_expand<.*true, true>", "pull_emit"), (r"k_expand<.*false, true>", "pull_count"),
+    (r"k_expand<.*true, false>", "push_emit"), (r"k_expand<.*false, false>", "push_count"),
+    (r"k_pull_index", "pull_index"), (r"k_root", "root"), (r"k_heads", "heads"),
+    (r"k_group_starts", "group_starts"), (r"k_scan", "scan"), (r"k_radix", "radix_sort"),
+    (r"k_permute", "permute"), (r"k_leaf_emit", "leaf_emit"), (r"k_leaf_count", "leaf_count"),
+]
+
+
+def short_name(full):
+    for pat, name in KERNEL_NAMES:
+        if re.search(pat, full):
+            return name
+    return None
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stats(csv_path, out_md, command):
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = ["# rocprofv3 kernel statistics", "", "Command:", "", "    " + command, "",
+             "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in rows[:25]:
+        name = r.get("Name") or r.get("KernelName") or r.get("Kernel_Name")
+        calls = int(r.get("Calls") or r.get("TotalCalls") or 0)
+        tot = float(r.get("TotalDurationNs") or r.get("TotalDuration") or 0)
+        avg = float(r.get("AverageNs") or r.get("Average") or 0)
+        pct = float(r.get("Percentage") or 0)
+        lines.append("| %s | %d | %.3f | %.1f | %.1f |" % (name.split("(")[0][:110], calls, tot / 1e6, avg / 1e3, pct))
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def _counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    out = []
+    for f in files:
+        out.extend(csv.DictReader(open(f)))
+    return out
+
+
+def _per_dispatch(rows):
+    """(kernel name, dispatch id) -> counter value in bytes"""
+    acc = defaultdict(float)
+    for r in rows:
+        name = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("KernelName")
+        disp = r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("DispatchId")
+        acc[(name, disp)] += float(r.get("Counter_Value") or r.get("Counter-Value") or 0) * 1024.0
+    return acc
+
+
+def traffic(fetch_dir, write_dir, copy_mib, out_json, command):
+    f = _per_dispatch(_counter_rows(fetch_dir))
+    w = _per_dispatch(_counter_rows(write_dir))
+    copy_bytes = float(copy_mib) * (1 << 20)
+    # the calibration copy: the largest dispatch of a kernel outside the library
+    def calib(acc):
+        cands = [(v, k) for k, v in acc.items() if short_name(k[0]) is None]
+        return max(cands)[0] if cands else None
+    fc, wc = calib(f), calib(w)
+    sf = copy_bytes / fc if fc else 1.0
+    sw = copy_bytes / wc if wc else 1.0
+    per = defaultdict(lambda: [0.0, 0.0, 0])
+    for (name, disp), v in f.items():
+        s = short_name(name)
+        if s:
+            per[s][0] += v * sf
+            per[s][2] += 1
+    for (name, disp), v in w.items():
+        s = short_name(name)
+        if s:
+            per[s][1] += v * sw
+    kernels = {k: {"fetch_bytes_per_launch": round(v[0] / max(v[2], 1)),
+                   "write_bytes_per_launch": round(v[1] / max(v[2], 1)),
+                   "bytes_per_launch": round((v[0] + v[1]) / max(v[2], 1)), "launches": v[2]}
+               for k, v in per.items()}
+    out = {"command": command, "source_hash": kernel_source_hash(), "copy_calibration_bytes": copy_bytes,
+           "fetch_scale": sf, "write_scale": sw, "kernels": kernels}
+    json.dump(out, open(out_json, "w"), indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], " ".join(sys.argv[6:]))
+    else:
+        raise SystemExit(__doc__)
