@@ -134,6 +134,9 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
         std::vector<int32_t> src(m2);
         for (int32_t v = 0; v < n; v++)
             for (int64_t e = rp[v]; e < rp[v + 1]; e++) src[e] = v;
+        std::vector<int32_t> heavy;
+        for (int32_t v = 0; v < n; v++)
+            if (rp[v + 1] - rp[v] > kHeavyDegree) heavy.push_back(v);
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         auto* g = new cc_graph();
         g->ctx = ctx;
@@ -146,6 +149,10 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
             hip_check(hipMalloc(&g->rp, 8 * size_t(n + 1)), "hipMalloc");
             hip_check(hipMalloc(&g->col, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
             hip_check(hipMalloc(&g->esrc, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
+            hip_check(hipMalloc(&g->heavy, 4 * std::max<size_t>(heavy.size(), 1)), "hipMalloc");
+            g->nheavy = int32_t(heavy.size());
+            if (!heavy.empty())
+                hip_check(hipMemcpy(g->heavy, heavy.data(), 4 * heavy.size(), hipMemcpyHostToDevice), "hipMemcpy");
             hip_check(hipMemcpy(g->rp, rp.data(), 8 * size_t(n + 1), hipMemcpyHostToDevice), "hipMemcpy");
             if (m2) {
                 hip_check(hipMemcpy(g->col, cl.data(), 4 * size_t(m2), hipMemcpyHostToDevice), "hipMemcpy");
@@ -164,6 +171,7 @@ void cc_graph_free(cc_graph* g) {
     if (g->rp) (void)hipFree(g->rp);
     if (g->col) (void)hipFree(g->col);
     if (g->esrc) (void)hipFree(g->esrc);
+    if (g->heavy) (void)hipFree(g->heavy);
     delete g;
 }
 

@@ -117,10 +117,12 @@ struct cc_graph {
     int64_t* rp = nullptr;
     int32_t* col = nullptr;
     int32_t* esrc = nullptr;
+    int32_t* heavy = nullptr;
+    int32_t nheavy = 0;
     std::vector<int64_t> sorted_deg;  // host copy, ascending
     // vertices with degree >= d
     int64_t count_deg_at_least(int64_t d) const;
-    ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc}; }
+    ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc, heavy, nheavy}; }
 };
 
 struct cc_coloring {

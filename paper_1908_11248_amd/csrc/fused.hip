@@ -12,42 +12,65 @@
 // read.  Units are (b, v) in key order, so the output is sorted.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 
 namespace ccg {
 
-template <class KI, class KO, bool EMIT, bool LEAFCHILD>
+// U units per 64-lane workgroup, 64 / U lanes each: the dependent loads of
+// U units are in flight together.  Loop trip counts are made uniform across
+// the wave (maxima over the U units), so the workgroup barriers stay legal.
+template <class KI, class KO, bool EMIT, bool LEAFCHILD, int U>
 __global__ void __launch_bounds__(64)
 k_edge(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ rstart,
        const uint64_t* __restrict__ rend, int B, DevGraph g, const uint8_t* __restrict__ colors, int degF_u,
        int degF_child, uint32_t* gcount, uint32_t* icount, const uint64_t* __restrict__ goff, KO* okeys,
-       uint64_t* ocnt, Lay LO, uint32_t* ovf) {
-    Acc acc = acc_bind(LO.kb, EMIT);
-    __shared__ uint64_t pre[65];
-    __shared__ uint64_t r0s[64];
-    __shared__ uint32_t ys[64];
-    const uint64_t units = uint64_t(B) * uint64_t(g.n);
-    const int lane = threadIdx.x;
-    for (uint64_t w = blockIdx.x; w < units; w += gridDim.x) {
-        const uint32_t bid = uint32_t(w / uint64_t(g.n));
-        const uint32_t v = uint32_t(w % uint64_t(g.n));
-        const int64_t rb = g.rp[v], re = g.rp[v + 1];
-        if (re - rb < degF_u) {
-            if (!EMIT && lane == 0) {
-                gcount[w] = 0;
-                icount[w] = 0;
-            }
-            continue;
+       uint64_t* ocnt, Lay LO, uint32_t* ovf, bool heavy_only, int skip_above) {
+    // heavy_only: the units are (b, heavy vertex); otherwise (b, v) for all v,
+    // skipping (no writes at all) vertices of degree > skip_above when > 0
+    constexpr int LN = 64 / U;  // lanes per unit
+    extern __shared__ uint64_t smem[];
+    const int slots = 1 << LO.kb;
+    const int words = LO.kb >= 5 ? (1 << (LO.kb - 5)) : 1;
+    const int lane = threadIdx.x, sub = lane / LN, sl = lane % LN;
+    uint64_t* val = EMIT ? smem + size_t(sub) * slots : nullptr;
+    uint32_t* bits = reinterpret_cast<uint32_t*>(smem + (EMIT ? size_t(U) * slots : 0)) + sub * words;
+    __shared__ uint64_t pre[U][LN + 1];
+    __shared__ uint64_t r0s[U][LN];
+    __shared__ uint32_t ys[U][LN];
+    const uint64_t nv = heavy_only ? uint64_t(g.nheavy) : uint64_t(g.n);
+    const uint64_t units = uint64_t(B) * nv;
+    const uint64_t subgroup_mask = (LN == 64) ? ~0ull : ((1ull << LN) - 1ull);
+    for (uint64_t w0 = uint64_t(blockIdx.x) * U; w0 < units; w0 += uint64_t(gridDim.x) * U) {
+        bool mine = w0 + sub < units;  // this launch owns the unit (writes its results)
+        bool active = mine;
+        uint32_t bid = 0, v = 0, cb = 0;
+        int64_t rb = 0, re = 0;
+        if (active) {
+            bid = uint32_t((w0 + sub) / nv);
+            uint64_t j = (w0 + sub) % nv;
+            v = heavy_only ? uint32_t(g.heavy[j]) : uint32_t(j);
+            rb = g.rp[v];
+            re = g.rp[v + 1];
+            if (skip_above > 0 && re - rb > skip_above) mine = active = false;
+            if (re - rb < degF_u) active = false;
         }
+        const uint64_t w = uint64_t(bid) * uint64_t(g.n) + v;  // the unit's output slot
+        if (!active) re = rb;
         const uint8_t* col_b = colors + uint64_t(bid) * g.n;
-        const uint32_t cb = 1u << col_b[v];
-        acc_clear(acc, EMIT);
+        if (active) cb = 1u << col_b[v];
+        for (int i = sl; i < slots && EMIT; i += LN) val[i] = 0;
+        for (int i = sl; i < words; i += LN) bits[i] = 0;
         bool over = false;
         uint32_t passed = 0;
-        for (int64_t nb0 = rb; nb0 < re; nb0 += 64) {
+        // neighbour chunks of LN: the wave runs the largest count over its units
+        int64_t nch = (re - rb + LN - 1) / LN;
+        for (int d = 32; d >= 1; d >>= 1) nch = max(nch, (int64_t)__shfl_xor(nch, d, 64));
+        for (int64_t c = 0; c < nch; c++) {
             __syncthreads();
-            int64_t e = nb0 + lane;
+            int64_t e = rb + c * LN + sl;
             uint64_t len = 0, r0 = 0;
             uint32_t y = 0;
             if (e < re) {
@@ -60,67 +83,94 @@ k_edge(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, con
                     len = rend[slot] - r0;
                 }
             }
-            uint64_t inc = wave_incl_scan(len);
-            pre[lane] = inc - len;
-            r0s[lane] = r0;
-            ys[lane] = y;
-            if (lane == 63) pre[64] = inc;
+            uint64_t inc = len;
+            for (int d = 1; d < LN; d <<= 1) {
+                uint64_t t = __shfl_up(inc, d, LN);
+                if (sl >= d) inc += t;
+            }
+            pre[sub][sl] = inc - len;
+            r0s[sub][sl] = r0;
+            ys[sub][sl] = y;
+            if (sl == LN - 1) pre[sub][LN] = inc;
             __syncthreads();
-            const uint64_t T = pre[64];
-            for (uint64_t t = lane; t < T; t += 64) {
-                // neighbour j with pre[j] <= t < pre[j + 1]
-                int lo = 0, hi = 64;
+            const uint64_t T = pre[sub][LN];
+            uint64_t Tmax = T;
+            for (int d = 32; d >= 1; d >>= 1) Tmax = max(Tmax, (uint64_t)__shfl_xor(Tmax, d, 64));
+            for (uint64_t t0 = 0; t0 < Tmax; t0 += LN) {
+                uint64_t t = t0 + sl;
+                if (t >= T) continue;
+                int lo = 0, hi = LN;
                 while (hi - lo > 1) {
                     int mid = (lo + hi) >> 1;
-                    if (pre[mid] <= t) lo = mid;
+                    if (pre[sub][mid] <= t) lo = mid;
                     else hi = mid;
                 }
                 uint32_t C;
-                uint64_t c;
+                uint64_t cv;
                 if (LEAFCHILD) {
-                    C = 1u << col_b[ys[lo]];
-                    c = 1;
+                    C = 1u << col_b[ys[sub][lo]];
+                    cv = 1;
                 } else {
-                    uint64_t i = r0s[lo] + (t - pre[lo]);
+                    uint64_t i = r0s[sub][lo] + (t - pre[sub][lo]);
                     C = kset(keys[i], L);
-                    c = cnt[i];
+                    cv = cnt[i];
                 }
                 if (C & cb) continue;
                 C |= cb;
                 passed++;
-                atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
+                atomicOr(&bits[C >> 5], 1u << (C & 31));
                 if (EMIT) {
-                    uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)c);
-                    over |= (old + c < old);
+                    uint64_t old = atomicAdd((unsigned long long*)&val[C], (unsigned long long)cv);
+                    over |= (old + cv < old);
                 }
             }
         }
         __syncthreads();
         if (EMIT) {
-            if (__ballot(over) && lane == 0) atomicOr(&ovf[bid], 1u);
-            uint32_t cols[1] = {v};
-            KO prefix = kpack<KO>(bid, cols, 1, 0u, LO);
-            acc_emit<KO>(acc, prefix, goff[w], okeys, ocnt);
+            uint64_t ob = __ballot(over);
+            if (((ob >> (sub * LN)) & subgroup_mask) && sl == 0) atomicOr(&ovf[bid], 1u);
+            uint32_t colv[1] = {v};
+            KO prefix = kpack<KO>(bid, colv, 1, 0u, LO);
+            uint64_t run = active ? goff[w] : 0;
+            for (int c0 = 0; c0 < slots; c0 += LN) {
+                int C = c0 + sl;
+                bool present = active && C < slots && ((bits[C >> 5] >> (C & 31)) & 1u);
+                uint64_t m = (__ballot(present) >> (sub * LN)) & subgroup_mask;
+                if (present) {
+                    uint64_t o = run + __popcll(m & ((1ull << sl) - 1ull));
+                    okeys[o] = prefix | KO(C);
+                    ocnt[o] = val[C];
+                }
+                run += __popcll(m);
+            }
         } else {
-            uint32_t c = acc_count(acc);
-            uint32_t p = uint32_t(wave_sum(passed));
-            if (lane == 0) {
-                gcount[w] = c;
-                icount[w] = p;
+            uint64_t c = 0;
+            for (int i = sl; i < words; i += LN) c += __popc(bits[i]);
+            uint64_t p = passed;
+            for (int d = LN / 2; d >= 1; d >>= 1) {
+                c += __shfl_xor(c, d, LN);
+                p += __shfl_xor(p, d, LN);
+            }
+            if (mine && sl == 0) {
+                gcount[w] = active ? uint32_t(c) : 0u;
+                icount[w] = active ? uint32_t(p) : 0u;
             }
         }
         __syncthreads();
     }
 }
 
-template <bool EMIT, bool LEAFCHILD>
-static void edge_launch(const DevTable* in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
-                        const uint8_t* colors, int degF_u, int degF_child, uint32_t* gcount, uint32_t* icount,
-                        const uint64_t* goff, DevTable* out, Lay LO, uint32_t* ovf, hipStream_t s) {
-    uint64_t units = uint64_t(B) * uint64_t(g.n);
+template <bool EMIT, bool LEAFCHILD, int U>
+static void edge_launch_u(const DevTable* in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
+                          const uint8_t* colors, int degF_u, int degF_child, uint32_t* gcount, uint32_t* icount,
+                          const uint64_t* goff, DevTable* out, Lay LO, uint32_t* ovf, bool heavy_only, int skip_above,
+                          hipStream_t s) {
+    uint64_t units = uint64_t(B) * uint64_t(heavy_only ? g.nheavy : g.n);
     if (!units) return;
-    unsigned grid = unsigned(units < (1u << 20) ? units : (1u << 20));
-    size_t lds = acc_bytes(LO.kb, EMIT);
+    uint64_t blocks = (units + U - 1) / U;
+    unsigned grid = unsigned(blocks < (1u << 20) ? blocks : (1u << 20));
+    size_t words = LO.kb >= 5 ? (size_t(1) << (LO.kb - 5)) : 1;
+    size_t lds = (EMIT ? size_t(U) * (size_t(8) << LO.kb) : 0) + size_t(U) * 4 * words;
     const void* ik = in ? in->keys : nullptr;
     const uint64_t* ic = in ? in->cnt : nullptr;
     Lay LI = in ? in->lay : LO;
@@ -128,21 +178,51 @@ static void edge_launch(const DevTable* in, const uint64_t* rstart, const uint64
     uint64_t* oc = out ? out->cnt : nullptr;
     int ki = LI.kw(), ko = LO.kw();
     if (ki == 1 && ko == 1)
-        k_edge<uint64_t, uint64_t, EMIT, LEAFCHILD><<<grid, 64, lds, s>>>(
+        k_edge<uint64_t, uint64_t, EMIT, LEAFCHILD, U><<<grid, 64, lds, s>>>(
             (const uint64_t*)ik, ic, LI, rstart, rend, B, g, colors, degF_u, degF_child, gcount, icount, goff,
-            (uint64_t*)ok, oc, LO, ovf);
+            (uint64_t*)ok, oc, LO, ovf, heavy_only, skip_above);
     else if (ki == 1)
-        k_edge<uint64_t, u128, EMIT, LEAFCHILD><<<grid, 64, lds, s>>>(
+        k_edge<uint64_t, u128, EMIT, LEAFCHILD, U><<<grid, 64, lds, s>>>(
             (const uint64_t*)ik, ic, LI, rstart, rend, B, g, colors, degF_u, degF_child, gcount, icount, goff,
-            (u128*)ok, oc, LO, ovf);
+            (u128*)ok, oc, LO, ovf, heavy_only, skip_above);
     else if (ko == 1)
-        k_edge<u128, uint64_t, EMIT, LEAFCHILD><<<grid, 64, lds, s>>>(
+        k_edge<u128, uint64_t, EMIT, LEAFCHILD, U><<<grid, 64, lds, s>>>(
             (const u128*)ik, ic, LI, rstart, rend, B, g, colors, degF_u, degF_child, gcount, icount, goff,
-            (uint64_t*)ok, oc, LO, ovf);
+            (uint64_t*)ok, oc, LO, ovf, heavy_only, skip_above);
     else
-        k_edge<u128, u128, EMIT, LEAFCHILD><<<grid, 64, lds, s>>>((const u128*)ik, ic, LI, rstart, rend, B, g, colors,
-                                                                  degF_u, degF_child, gcount, icount, goff, (u128*)ok,
-                                                                  oc, LO, ovf);
+        k_edge<u128, u128, EMIT, LEAFCHILD, U><<<grid, 64, lds, s>>>((const u128*)ik, ic, LI, rstart, rend, B, g, colors,
+                                                                     degF_u, degF_child, gcount, icount, goff,
+                                                                     (u128*)ok, oc, LO, ovf, heavy_only, skip_above);
+}
+
+// Units per workgroup: as many as the LDS accumulators allow.  Vertices of
+// degree > kHeavyDegree would stall the other units of their workgroup; they
+// run in a second launch with one unit per workgroup.
+static int edge_units(int kb) { return kb <= 9 ? 4 : (kb <= 11 ? 2 : 1); }
+
+template <bool EMIT, bool LEAFCHILD>
+static void edge_launch(const DevTable* in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
+                        const uint8_t* colors, int degF_u, int degF_child, uint32_t* gcount, uint32_t* icount,
+                        const uint64_t* goff, DevTable* out, Lay LO, uint32_t* ovf, hipStream_t s) {
+    if (!(uint64_t(B) * uint64_t(g.n))) return;
+    int u = edge_units(LO.kb);
+    int skip = (u > 1 && g.nheavy > 0) ? kHeavyDegree : 0;
+    switch (u) {
+        case 4:
+            edge_launch_u<EMIT, LEAFCHILD, 4>(in, rstart, rend, B, g, colors, degF_u, degF_child, gcount, icount, goff,
+                                              out, LO, ovf, false, skip, s);
+            break;
+        case 2:
+            edge_launch_u<EMIT, LEAFCHILD, 2>(in, rstart, rend, B, g, colors, degF_u, degF_child, gcount, icount, goff,
+                                              out, LO, ovf, false, skip, s);
+            break;
+        default:
+            edge_launch_u<EMIT, LEAFCHILD, 1>(in, rstart, rend, B, g, colors, degF_u, degF_child, gcount, icount, goff,
+                                              out, LO, ovf, false, 0, s);
+    }
+    if (skip)
+        edge_launch_u<EMIT, LEAFCHILD, 1>(in, rstart, rend, B, g, colors, degF_u, degF_child, gcount, icount, goff, out,
+                                          LO, ovf, true, 0, s);
 }
 
 void launch_edge_count(const DevTable* in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,

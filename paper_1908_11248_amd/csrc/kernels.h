@@ -34,7 +34,11 @@ struct DevGraph {
     const int64_t* rp;    // [n + 1]
     const int32_t* col;   // [2m], rows ascending
     const int32_t* esrc;  // [2m], source vertex of every stored edge
+    const int32_t* heavy; // vertices of degree > kHeavyDegree, ascending
+    int32_t nheavy;
 };
+
+constexpr int kHeavyDegree = 64;
 
 struct DevTable {
     void* keys = nullptr;

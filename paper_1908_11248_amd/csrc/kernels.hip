@@ -339,62 +339,93 @@ __device__ __forceinline__ uint64_t lower_bound_prefix(const K* keys, uint64_t l
     return lo;
 }
 
-template <class K, bool EMIT>
+template <class K, bool EMIT, int U>
 __global__ void __launch_bounds__(64)
 k_join(const K* __restrict__ yk, const uint64_t* __restrict__ yc, const K* __restrict__ zk,
        const uint64_t* __restrict__ zc, Lay L, const uint64_t* __restrict__ gstart, uint64_t G, int32_t n,
        const uint8_t* __restrict__ colors, const uint64_t* __restrict__ zlo, const uint64_t* __restrict__ zhi,
        uint32_t* gcount, const uint64_t* __restrict__ goff, K* okeys, uint64_t* ocnt, uint32_t* ovf) {
-    Acc acc = acc_bind(L.kb, EMIT);
-    __shared__ uint32_t ys[kJoinChunk], zs[kJoinChunk];
-    __shared__ uint64_t yv[EMIT ? kJoinChunk : 1], zv[EMIT ? kJoinChunk : 1];
+    // U runs per 64-lane workgroup, LN lanes each; trip counts are wave-uniform
+    constexpr int LN = 64 / U;
+    constexpr int CH = kJoinChunk / U;  // staged entries per run and side
+    extern __shared__ uint64_t smem[];
+    const int slots = 1 << L.kb;
+    const int words = L.kb >= 5 ? (1 << (L.kb - 5)) : 1;
+    const int lane = threadIdx.x, sub = lane / LN, sl = lane % LN;
+    uint64_t* val = EMIT ? smem + size_t(sub) * slots : nullptr;
+    uint32_t* bits = reinterpret_cast<uint32_t*>(smem + (EMIT ? size_t(U) * slots : 0)) + sub * words;
+    __shared__ uint32_t ys[U][CH], zs[U][CH];
+    __shared__ uint64_t yv[U][EMIT ? CH : 1], zv[U][EMIT ? CH : 1];
+    const uint64_t subgroup_mask = (LN == 64) ? ~0ull : ((1ull << LN) - 1ull);
     const int sh = L.kb;
-    for (uint64_t grp = blockIdx.x; grp < G; grp += gridDim.x) {
-        uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
-        K k0 = yk[e0];
-        K p = shr(k0, sh);
-        uint32_t bid = kbid(k0, L);
-        uint64_t slot = uint64_t(bid) * uint64_t(n) + kcol(k0, L, 0);
-        uint64_t z0 = zlo[slot], z1 = zhi[slot];
-        if (L.b > 1 && z0 < z1) {
-            uint64_t a0 = lower_bound_prefix(zk, z0, z1, p, sh, false);
-            z1 = lower_bound_prefix(zk, a0, z1, p, sh, true);
-            z0 = a0;
+    for (uint64_t g0 = uint64_t(blockIdx.x) * U; g0 < G; g0 += uint64_t(gridDim.x) * U) {
+        const uint64_t grp = g0 + sub;
+        bool active = grp < G;
+        uint64_t e0 = 0, e1 = 0, z0 = 0, z1 = 0;
+        uint32_t bid = 0, bagcol = 0;
+        K p = 0;
+        if (active) {
+            e0 = gstart[grp];
+            e1 = gstart[grp + 1];
+            K k0 = yk[e0];
+            p = shr(k0, sh);
+            bid = kbid(k0, L);
+            uint64_t slot = uint64_t(bid) * uint64_t(n) + kcol(k0, L, 0);
+            z0 = zlo[slot];
+            z1 = zhi[slot];
+            if (L.b > 1 && z0 < z1) {
+                uint64_t a0 = lower_bound_prefix(zk, z0, z1, p, sh, false);
+                z1 = lower_bound_prefix(zk, a0, z1, p, sh, true);
+                z0 = a0;
+            }
+            if (z0 == z1) active = false;
+            for (int j = 0; j < L.b && active; j++) bagcol |= 1u << colors[uint64_t(bid) * n + kcol(k0, L, j)];
         }
-        if (z0 == z1) {  // no matching mapping in the second child
-            if (!EMIT && threadIdx.x == 0) gcount[grp] = 0;
-            continue;
+        if (!active) {
+            e1 = e0;
+            z1 = z0;
         }
-        uint32_t bagcol = 0;
-        for (int j = 0; j < L.b; j++) bagcol |= 1u << colors[uint64_t(bid) * n + kcol(k0, L, j)];
-        acc_clear(acc, EMIT);
+        for (int i = sl; i < slots && EMIT; i += LN) val[i] = 0;
+        for (int i = sl; i < words; i += LN) bits[i] = 0;
         bool over = false;
-        for (uint64_t ya = e0; ya < e1; ya += kJoinChunk) {
-            uint32_t ny = uint32_t(e1 - ya < kJoinChunk ? e1 - ya : kJoinChunk);
-            for (uint64_t za = z0; za < z1; za += kJoinChunk) {
-                uint32_t nz = uint32_t(z1 - za < kJoinChunk ? z1 - za : kJoinChunk);
+        // chunk loops, wave-uniform: the largest chunk counts over the U runs
+        uint64_t ncy = (e1 - e0 + CH - 1) / CH, ncz = (z1 - z0 + CH - 1) / CH;
+        for (int d = 32; d >= 1; d >>= 1) {
+            ncy = max(ncy, (uint64_t)__shfl_xor(ncy, d, 64));
+            ncz = max(ncz, (uint64_t)__shfl_xor(ncz, d, 64));
+        }
+        for (uint64_t cy = 0; cy < ncy; cy++) {
+            uint64_t ya = e0 + cy * CH;
+            uint32_t ny = ya < e1 ? uint32_t(e1 - ya < CH ? e1 - ya : CH) : 0u;
+            for (uint64_t cz = 0; cz < ncz; cz++) {
+                uint64_t za = z0 + cz * CH;
+                uint32_t nz = za < z1 ? uint32_t(z1 - za < CH ? z1 - za : CH) : 0u;
                 __syncthreads();
-                for (uint32_t i = threadIdx.x; i < ny; i += 64) {
-                    ys[i] = kset(yk[ya + i], L);
-                    if (EMIT) yv[i] = yc[ya + i];
+                for (uint32_t i = sl; i < ny; i += LN) {
+                    ys[sub][i] = kset(yk[ya + i], L);
+                    if (EMIT) yv[sub][i] = yc[ya + i];
                 }
-                for (uint32_t i = threadIdx.x; i < nz; i += 64) {
-                    zs[i] = kset(zk[za + i], L);
-                    if (EMIT) zv[i] = zc[za + i];
+                for (uint32_t i = sl; i < nz; i += LN) {
+                    zs[sub][i] = kset(zk[za + i], L);
+                    if (EMIT) zv[sub][i] = zc[za + i];
                 }
                 __syncthreads();
                 uint32_t P = ny * nz;
-                for (uint32_t q = threadIdx.x; q < P; q += 64) {
+                uint32_t Pmax = P;
+                for (int d = 32; d >= 1; d >>= 1) Pmax = max(Pmax, (uint32_t)__shfl_xor(Pmax, d, 64));
+                for (uint32_t q0 = 0; q0 < Pmax; q0 += LN) {
+                    uint32_t q = q0 + sl;
+                    if (q >= P) continue;
                     uint32_t a = q / nz, d = q - a * nz;
-                    uint32_t Cy = ys[a], Cz = zs[d];
+                    uint32_t Cy = ys[sub][a], Cz = zs[sub][d];
                     if ((Cy & Cz) != bagcol) continue;
                     uint32_t C = Cy | Cz;
-                    atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
+                    atomicOr(&bits[C >> 5], 1u << (C & 31));
                     if (EMIT) {
-                        uint64_t cy = yv[a], cz = zv[d];
-                        uint64_t prod = cy * cz;
-                        over |= __umul64hi(cy, cz) != 0;
-                        uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)prod);
+                        uint64_t cyv = yv[sub][a], czv = zv[sub][d];
+                        uint64_t prod = cyv * czv;
+                        over |= __umul64hi(cyv, czv) != 0;
+                        uint64_t old = atomicAdd((unsigned long long*)&val[C], (unsigned long long)prod);
                         over |= (old + prod < old);
                     }
                 }
@@ -402,14 +433,48 @@ k_join(const K* __restrict__ yk, const uint64_t* __restrict__ yc, const K* __res
         }
         __syncthreads();
         if (EMIT) {
-            if (__ballot(over) && threadIdx.x == 0) atomicOr(&ovf[bid], 1u);
-            acc_emit<K>(acc, p << L.kb, goff[grp], okeys, ocnt);
+            uint64_t ob = __ballot(over);
+            if (((ob >> (sub * LN)) & subgroup_mask) && sl == 0) atomicOr(&ovf[bid], 1u);
+            uint64_t run = active ? goff[grp] : 0;
+            K prefix = p << L.kb;
+            for (int c0 = 0; c0 < slots; c0 += LN) {
+                int C = c0 + sl;
+                bool present = active && C < slots && ((bits[C >> 5] >> (C & 31)) & 1u);
+                uint64_t m = (__ballot(present) >> (sub * LN)) & subgroup_mask;
+                if (present) {
+                    uint64_t o = run + __popcll(m & ((1ull << sl) - 1ull));
+                    okeys[o] = prefix | K(C);
+                    ocnt[o] = val[C];
+                }
+                run += __popcll(m);
+            }
         } else {
-            uint32_t c = acc_count(acc);
-            if (threadIdx.x == 0) gcount[grp] = c;
+            uint64_t c = 0;
+            for (int i = sl; i < words; i += LN) c += __popc(bits[i]);
+            for (int d = LN / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, LN);
+            if (grp < G && sl == 0) gcount[grp] = active ? uint32_t(c) : 0u;
         }
         __syncthreads();
     }
+}
+
+template <bool EMIT, int U>
+static void join_launch_u(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
+                          const uint8_t* colors, const uint64_t* zlo, const uint64_t* zhi, uint32_t* gcount,
+                          const uint64_t* goff, DevTable* out, uint32_t* ovf, hipStream_t s) {
+    uint64_t blocks = (G + U - 1) / U;
+    unsigned grid = unsigned(blocks < (1u << 20) ? blocks : (1u << 20));
+    size_t words = y.lay.kb >= 5 ? (size_t(1) << (y.lay.kb - 5)) : 1;
+    size_t lds = (EMIT ? size_t(U) * (size_t(8) << y.lay.kb) : 0) + size_t(U) * 4 * words;
+    void* okk = out ? out->keys : nullptr;
+    uint64_t* oc = out ? out->cnt : nullptr;
+    if (y.lay.kw() == 1)
+        k_join<uint64_t, EMIT, U><<<grid, 64, lds, s>>>((const uint64_t*)y.keys, y.cnt, (const uint64_t*)z.keys, z.cnt,
+                                                        y.lay, gstart, G, n, colors, zlo, zhi, gcount, goff,
+                                                        (uint64_t*)okk, oc, ovf);
+    else
+        k_join<u128, EMIT, U><<<grid, 64, lds, s>>>((const u128*)y.keys, y.cnt, (const u128*)z.keys, z.cnt, y.lay, gstart,
+                                                    G, n, colors, zlo, zhi, gcount, goff, (u128*)okk, oc, ovf);
 }
 
 template <bool EMIT>
@@ -417,16 +482,15 @@ static void join_dispatch(const DevTable& y, const DevTable& z, const uint64_t* 
                           const uint8_t* colors, const uint64_t* zlo, const uint64_t* zhi, uint32_t* gcount,
                           const uint64_t* goff, DevTable* out, uint32_t* ovf, hipStream_t s) {
     if (!G) return;
-    unsigned grid = unsigned(G < (1u << 20) ? G : (1u << 20));
-    size_t lds = acc_bytes(y.lay.kb, EMIT);
-    void* okk = out ? out->keys : nullptr;
-    uint64_t* oc = out ? out->cnt : nullptr;
-    if (y.lay.kw() == 1)
-        k_join<uint64_t, EMIT><<<grid, 64, lds, s>>>((const uint64_t*)y.keys, y.cnt, (const uint64_t*)z.keys, z.cnt, y.lay,
-                                                     gstart, G, n, colors, zlo, zhi, gcount, goff, (uint64_t*)okk, oc, ovf);
+    // runs per workgroup from the average run length of both children
+    double avg = double(y.n + z.n) / double(G);
+    int kb = y.lay.kb;
+    if (kb <= 9 && avg <= 96)
+        join_launch_u<EMIT, 4>(y, z, gstart, G, n, colors, zlo, zhi, gcount, goff, out, ovf, s);
+    else if (kb <= 11 && avg <= 256)
+        join_launch_u<EMIT, 2>(y, z, gstart, G, n, colors, zlo, zhi, gcount, goff, out, ovf, s);
     else
-        k_join<u128, EMIT><<<grid, 64, lds, s>>>((const u128*)y.keys, y.cnt, (const u128*)z.keys, z.cnt, y.lay, gstart, G,
-                                                 n, colors, zlo, zhi, gcount, goff, (u128*)okk, oc, ovf);
+        join_launch_u<EMIT, 1>(y, z, gstart, G, n, colors, zlo, zhi, gcount, goff, out, ovf, s);
 }
 
 void launch_join_count(const DevTable& y, const DevTable& z, const uint64_t* gstart, uint64_t G, int32_t n,
