@@ -170,6 +170,8 @@ def main():
             cc.count(ctx, G, C, D)
         plain_rate = args.plain / (time.perf_counter() - t1)
 
+    if not prof:
+        raise SystemExit("no kernel timings were recorded")
     dom = max(prof.items(), key=lambda kv: kv[1][1])
     name, (launches, ms, byts) = dom
     achieved = (byts / launches) / ((ms / launches) * 1e-3) / 1e9
@@ -338,6 +340,8 @@ def bench_queries(args):
         value = st_b["qps"]
         dt = st_b["wall_s"]
         ms_per_step = dt * 1e3
+    if not prof:
+        raise SystemExit("no kernel timings were recorded")
     dom = max(prof.items(), key=lambda kv: kv[1][1])
     name, (launches, ms, byts) = dom
     achieved = (byts / launches) / ((ms / launches) * 1e-3) / 1e9

@@ -122,8 +122,13 @@ void cc_decomp_free(cc_decomp *d);
 /* Runs the DP (Sec. 3.1) for every colouring of `c` in one batch and writes
  * counts[b] and (if not NULL) overflow[b] for b < num_colorings.
  * flags: CC_NO_DEGREE_MASK disables the degree mask of Sec. 3.2 (same
- * counts, bigger tables). */
+ * counts, bigger tables).  When every table of the plan has a one-vertex bag
+ * (tree patterns) and the dense form fits the arena, tables are kept dense
+ * over (colouring, bag image, colour set of the node's size); CC_SPARSE_TABLES
+ * keeps them as sorted entry lists instead (same counts, table sizes and
+ * overflow flags). */
 #define CC_NO_DEGREE_MASK 1u
+#define CC_SPARSE_TABLES 2u
 int cc_count(cc_context *ctx, const cc_graph *g, const cc_coloring *c, const cc_decomp *d,
              uint32_t flags, uint64_t *counts, uint8_t *overflow);
 

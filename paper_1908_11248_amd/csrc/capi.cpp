@@ -64,7 +64,11 @@ int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_conte
             }
             hip_check(hipMalloc(&c->arena_mem, arena_bytes), "arena hipMalloc");
             c->arena.init((char*)c->arena_mem, arena_bytes);
+            std::vector<uint16_t> st = slot_rank_tables();
+            hip_check(hipMalloc(&c->slot_tables, st.size() * 2), "hipMalloc");
+            hip_check(hipMemcpy(c->slot_tables, st.data(), st.size() * 2, hipMemcpyHostToDevice), "hipMemcpy");
         } catch (...) {
+            if (c->slot_tables) (void)hipFree(c->slot_tables);
             if (c->arena_mem) (void)hipFree(c->arena_mem);
             c->main.destroy();
             delete c;
@@ -80,6 +84,7 @@ int cc_context_destroy(cc_context* ctx) {
         (void)hipSetDevice(ctx->device);
         for (auto& w : ctx->workers) w->destroy();
         ctx->main.destroy();
+        if (ctx->slot_tables) (void)hipFree(ctx->slot_tables);
         if (ctx->arena_mem) (void)hipFree(ctx->arena_mem);
         delete ctx;
     });
@@ -361,6 +366,7 @@ int cc_count(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_
         rq.k = c->k;
         rq.dec = d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
+        rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
         rq.max_entries = ctx->max_entries;
         RunResult r;
         run_dp_waves(ctx, ctx->main, rq, &r);
@@ -386,6 +392,7 @@ int cc_count_by_vertex(cc_context* ctx, const cc_graph* g, const cc_coloring* c,
         rq.k = c->k;
         rq.dec = d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
+        rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
         rq.per_vertex = true;
         rq.max_entries = ctx->max_entries;
         RunResult r;

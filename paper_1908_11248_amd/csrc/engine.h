@@ -107,6 +107,7 @@ struct cc_context {
     std::vector<int64_t> last_sizes;
     uint64_t max_entries = 0;  // per-table budget (0: none)
     int batch_lanes = 0;       // lanes for cc_count_batch (0: tuned on first use)
+    uint16_t* slot_tables = nullptr;  // device: rank[2048] then unrank[2048] (slots.hip)
     ccg::Lane& worker(size_t i);
 };
 
@@ -144,6 +145,7 @@ struct RunRequest {
     int B = 0, k = 0;
     const cc_decomp* dec = nullptr;
     bool degree_mask = true;
+    bool sparse_only = false;  // never use dense one-column tables
     bool per_vertex = false;  // also the per-image split of the node below the root
     bool keep_tables = false;
     bool links = false;  // record the contributor index the row decoder needs (implies keep_tables)

@@ -9,6 +9,7 @@ ccg::Lane& cc_context::worker(size_t i) {
     while (workers.size() <= i) {
         workers.emplace_back(new ccg::Lane());
         workers.back()->create(nullptr);
+        workers.back()->prof.on = main.prof.on;  // lanes made while profiling take part in it
     }
     return *workers[i];
 }
@@ -294,6 +295,213 @@ void sort_pairs(Exec& X, uint64_t* keys, uint64_t* vals, uint64_t n, uint64_t nk
     X.release(k2);
 }
 
+int binom(int a, int b) {
+    if (b < 0 || b > a) return 0;
+    int64_t c = 1;
+    for (int i = 0; i < b; i++) c = c * (a - i) / (i + 1);
+    return int(c);
+}
+
+// Colour-set size s of every step's output when every table of the plan has a
+// one-vertex bag (leaves, fused introduce+forget pairs, one-vertex joins);
+// false otherwise.
+bool slot_plan(const Plan& plan, const std::vector<char>& fuse, std::vector<int>* sz) {
+    const size_t S = plan.steps.size();
+    sz->assign(S, 0);
+    for (size_t i = 0; i < S; i++) {
+        const Step& st = plan.steps[i];
+        if (st.kind == S_LEAF) {
+            (*sz)[i] = 1;
+        } else if (fuse[i]) {
+            (*sz)[i] = (*sz)[st.in0] + 1;
+            (*sz)[i + 1] = (*sz)[i];
+            i++;
+        } else if (st.kind == S_JOIN && st.b_out == 1) {
+            (*sz)[i] = (*sz)[st.in0] + (*sz)[st.in1] - 1;
+        } else {
+            return false;
+        }
+    }
+    return plan.root_child >= 0 && plan.steps[plan.root_child].b_out == 1;
+}
+
+// Peak bytes of the dense tables of a slot plan, in step order.
+uint64_t slot_peak_bytes(const Plan& plan, const std::vector<char>& fuse, const std::vector<char>& virt,
+                         const std::vector<int>& sz, uint64_t units, int k) {
+    const size_t S = plan.steps.size();
+    std::vector<int> uses(S, 0);
+    for (const Step& st : plan.steps) {
+        if (st.in0 >= 0) uses[st.in0]++;
+        if (st.in1 >= 0) uses[st.in1]++;
+    }
+    auto bytes = [&](size_t i) { return units * uint64_t(binom(k - 1, sz[i] - 1)) * 9u + 512; };
+    uint64_t live = 0, peak = 0;
+    for (size_t i = 0; i < S; i++) {
+        const Step& st = plan.steps[i];
+        if (virt[i]) continue;
+        size_t o = fuse[i] ? i + 1 : i;
+        live += bytes(o);
+        peak = std::max(peak, live);
+        for (int in : {st.in0, st.in1})
+            if (in >= 0 && !virt[in] && --uses[in] == 0) live -= bytes(size_t(in));
+        if (fuse[i]) i++;
+    }
+    return peak;
+}
+
+struct SlotTab {
+    uint64_t* cnt = nullptr;
+    uint8_t* flag = nullptr;
+    int s = 0, R = 0;
+};
+
+// Runs a slot plan on dense one-column tables (slots.hip): no count passes,
+// scans or host round trips between steps.  Fills counts, flags and node
+// sizes like the sparse path; the per-table budget is checked on the sizes
+// afterwards (same outcome as the check before each sparse allocation).
+void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector<char>& fuse,
+               const std::vector<char>& virt, const std::vector<int>& sz, uint32_t* ovf, RunResult* out) {
+    const Plan& plan = rq.dec->plan;
+    const Decomp& dec = rq.dec->d;
+    const DevGraph g = rq.g->dev();
+    const int B = rq.B, k = rq.k;
+    hipStream_t s = X.s;
+    const size_t S = plan.steps.size();
+    const uint64_t units = uint64_t(B) * uint64_t(g.n);
+    std::vector<int> uses(S, 0);
+    for (const Step& st : plan.steps) {
+        if (st.in0 >= 0) uses[st.in0]++;
+        if (st.in1 >= 0) uses[st.in1]++;
+    }
+    std::vector<SlotTab> tab(S);
+    // per step: introduce entries, output entries (spread counters, summed at the end)
+    const uint64_t per_step = uint64_t(kSlotCounters) * kSlotCounterStride;
+    uint64_t* spread = X.alloc<uint64_t>(S * per_step);
+    launch_fill_u64(spread, 0, S * per_step, s);
+    uint64_t* nsz = X.alloc<uint64_t>(2 * S);
+    auto nz_of = [&](size_t i) { return reinterpret_cast<unsigned long long*>(spread + i * per_step); };
+    const uint16_t* rank = ctx->slot_tables;
+    const uint16_t* unrank = ctx->slot_tables + (1 << kSlotBits);
+    const double csr = double(B) * (9.0 * g.n + 4.0 * g.m2);
+    auto make = [&](int set) {
+        SlotTab t;
+        t.s = set;
+        t.R = binom(k - 1, set - 1);
+        t.cnt = X.alloc<uint64_t>(units * t.R);
+        t.flag = X.alloc<uint8_t>(units * t.R);
+        return t;
+    };
+    auto drop = [&](SlotTab& t) {
+        X.release(t.cnt);
+        X.release(t.flag);
+        t = SlotTab();
+    };
+    auto done_with = [&](int in) {
+        if (in >= 0 && !virt[in] && --uses[in] == 0) drop(tab[in]);
+    };
+    std::vector<std::pair<int, int>> node_of;  // (TD node, nsz index)
+    std::vector<int> budgeted;                 // nsz indices of tables under the budget
+    for (size_t i = 0; i < S; i++) {
+        const Step& st = plan.steps[i];
+        if (virt[i]) {
+            if (st.node >= 0)
+                out->node_sizes[st.node] = int64_t(B) * rq.g->count_deg_at_least(rq.degree_mask ? st.degF : 0);
+            continue;
+        }
+        if (fuse[i]) {
+            const Step& f = plan.steps[i + 1];
+            const bool leafc = virt[st.in0] != 0;
+            const SlotTab in = leafc ? SlotTab() : tab[st.in0];
+            SlotTab o = make(sz[i + 1]);
+            SlotGrid G = slot_grid(g.n, B, o.R);
+            const int degF_u = rq.degree_mask ? st.degF : 0;
+            const int degF_c = rq.degree_mask ? plan.steps[st.in0].degF : 0;
+            X.timed("slot_edge", double(units) * 9.0 * (in.R + o.R) + csr, [&] {
+                launch_slot_edge(in.cnt, in.flag, in.R, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
+                                 slot_unrank_offset(o.s - 1), o.cnt, o.flag, nz_of(i), ovf, s);
+            });
+            tab[i + 1] = o;
+            if (st.node >= 0) node_of.push_back({st.node, int(2 * i)});
+            if (f.node >= 0) node_of.push_back({f.node, int(2 * i + 1)});
+            budgeted.push_back(int(2 * i + 1));
+            done_with(st.in0);
+            i++;
+            continue;
+        }
+        if (st.kind == S_LEAF) {
+            SlotTab o = make(1);
+            SlotGrid G = slot_grid(g.n, B, 1);
+            X.timed("slot_leaf", double(units) * 9.0 + 8.0 * g.n,
+                    [&] { launch_slot_leaf(G, g, rq.degree_mask ? st.degF : 0, o.cnt, o.flag, nz_of(i), s); });
+            tab[i] = o;
+        } else {  // one-vertex join
+            const SlotTab& y = tab[st.in0];
+            const SlotTab& z = tab[st.in1];
+            SlotTab o = make(y.s + z.s - 1);
+            SlotGrid G = slot_grid(g.n, B, o.R);
+            X.timed("slot_join", double(units) * 9.0 * (y.R + z.R + o.R), [&] {
+                launch_slot_join(y.cnt, y.flag, y.R, z.cnt, z.flag, z.R, y.s - 1, k, G, rank, unrank,
+                                 slot_unrank_offset(o.s - 1), o.cnt, o.flag, nz_of(i), ovf, s);
+            });
+            tab[i] = o;
+            done_with(st.in0);
+            done_with(st.in1);
+        }
+        if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
+        budgeted.push_back(int(2 * i + 1));
+    }
+    launch_slot_counters(reinterpret_cast<const unsigned long long*>(spread), int(S), nsz, s);
+    hip_check(hipGetLastError(), "kernel launch");
+
+    const SlotTab& rc = tab[plan.root_child];
+    uint64_t* counts = X.alloc<uint64_t>(B);
+    launch_fill_u64(counts, 0, B, s);
+    uint64_t* pv = nullptr;
+    if (rq.per_vertex) pv = X.alloc<uint64_t>(units);  // every entry is written
+    const int cwords = k >= 5 ? 1 << (k - 5) : 1;
+    uint32_t* csets = X.alloc<uint32_t>(uint64_t(B) * cwords);
+    launch_fill_u32(csets, 0, uint64_t(B) * cwords, s);
+    X.timed("slot_root", double(units) * 9.0 * rc.R, [&] {
+        launch_slot_root(rc.cnt, rc.flag, rc.R, rc.s, g.n, B, rq.colors, unrank, counts, ovf, pv, csets, cwords, s);
+    });
+    out->counts.assign(B, 0);
+    std::vector<uint32_t> of(B, 0);
+    std::vector<uint64_t> sizes(2 * S, 0);
+    hip_check(hipMemcpyAsync(out->counts.data(), counts, 8 * size_t(B), hipMemcpyDeviceToHost, s), "copy counts");
+    hip_check(hipMemcpyAsync(of.data(), ovf, 4 * size_t(B), hipMemcpyDeviceToHost, s), "copy flags");
+    hip_check(hipMemcpyAsync(sizes.data(), nsz, 8 * 2 * S, hipMemcpyDeviceToHost, s), "copy sizes");
+    std::vector<uint32_t> cs(uint64_t(B) * cwords);
+    hip_check(hipMemcpyAsync(cs.data(), csets, 4 * cs.size(), hipMemcpyDeviceToHost, s), "copy colour sets");
+    if (pv) {
+        out->per_vertex.assign(units, 0);
+        hip_check(hipMemcpyAsync(out->per_vertex.data(), pv, 8 * units, hipMemcpyDeviceToHost, s), "copy per-vertex");
+    }
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    X.synced();
+    X.lane.prof.resolve();
+    for (int j : budgeted)
+        if (rq.max_entries && sizes[j] > rq.max_entries)
+            throw CcError{CC_ERANGE,
+                          "a DP table of " + std::to_string(sizes[j]) + " entries exceeds the per-table budget of " +
+                              std::to_string(rq.max_entries),
+                          true};
+    for (auto& nd : node_of) out->node_sizes[nd.first] = int64_t(sizes[nd.second]);
+    out->overflow.assign(B, 0);
+    for (int b = 0; b < B; b++) out->overflow[b] = of[b] ? 1 : 0;
+    int64_t nzr = 0;
+    for (uint32_t w : cs) nzr += __builtin_popcount(w);
+    out->node_sizes[dec.nodes.size() - 1] = nzr;
+    X.release(csets);
+    X.release(counts);
+    X.release(pv);
+    X.release(nsz);
+    X.release(spread);
+    X.release(ovf);
+    drop(tab[plan.root_child]);
+    X.synced();
+    out->peak_bytes = X.peak;
+}
+
 }  // namespace
 
 void release_tables(cc_context* ctx, RunResult* r) {
@@ -353,6 +561,26 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     out->node_sizes.assign(dec.nodes.size(), 0);
     uint32_t* ovf = X.alloc<uint32_t>(B);
     launch_fill_u32(ovf, 0, B, s);
+
+    // dense one-column tables when the plan allows them and they fit a
+    // quarter of the arena
+    std::vector<int> sz;
+    if (!keep && !rq.sparse_only && slot_plan(plan, fuse, &sz)) {
+        const uint64_t units = uint64_t(B) * uint64_t(g.n);
+        bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= ctx->arena.size() / 4;
+        for (size_t i = 0; i < S && fits; i++)
+            if (sz[i] > 0 && slot_grid(g.n, B, binom(k - 1, sz[i] - 1)).blocks >= (uint64_t(1) << 32)) fits = false;
+        if (fits) {
+            try {
+                run_slots(ctx, X, rq, fuse, virt, sz, ovf, out);
+            } catch (...) {
+                (void)hipStreamSynchronize(s);
+                X.release_all();
+                throw;
+            }
+            return;
+        }
+    }
 
     try {
         for (size_t i = 0; i < S; i++) {
@@ -661,7 +889,13 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
             pv = X.alloc<uint64_t>(uint64_t(B) * g.n);
             launch_fill_u64(pv, 0, uint64_t(B) * g.n, s);
         }
-        X.timed("root", double(rc.n) * (rc.lay.key_bytes() + 8), [&] { launch_root(rc, g.n, counts, ovf, pv, s); });
+        const int cwords = k >= 5 ? 1 << (k - 5) : 1;
+        uint32_t* csets = X.alloc<uint32_t>(uint64_t(B) * cwords);
+        launch_fill_u32(csets, 0, uint64_t(B) * cwords, s);
+        X.timed("root", double(rc.n) * (rc.lay.key_bytes() + 8),
+                [&] { launch_root(rc, g.n, counts, ovf, pv, csets, cwords, s); });
+        std::vector<uint32_t> cs(uint64_t(B) * cwords);
+        hip_check(hipMemcpyAsync(cs.data(), csets, 4 * cs.size(), hipMemcpyDeviceToHost, s), "copy colour sets");
         out->counts.assign(B, 0);
         std::vector<uint32_t> of(B, 0);
         hip_check(hipMemcpyAsync(out->counts.data(), counts, 8 * size_t(B), hipMemcpyDeviceToHost, s), "copy counts");
@@ -678,8 +912,9 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         for (int b = 0; b < B; b++) out->overflow[b] = of[b] ? 1 : 0;
         int root_node = int(dec.nodes.size()) - 1;
         int64_t nz = 0;
-        for (int b = 0; b < B; b++) nz += out->counts[b] || of[b];
+        for (uint32_t w : cs) nz += __builtin_popcount(w);
         out->node_sizes[root_node] = nz;
+        X.release(csets);
         X.release(counts);
         X.release(pv);
         X.release(ovf);

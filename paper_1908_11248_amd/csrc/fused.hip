@@ -96,32 +96,49 @@ k_edge(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, con
             const uint64_t T = pre[sub][LN];
             uint64_t Tmax = T;
             for (int d = 32; d >= 1; d >>= 1) Tmax = max(Tmax, (uint64_t)__shfl_xor(Tmax, d, 64));
-            for (uint64_t t0 = 0; t0 < Tmax; t0 += LN) {
-                uint64_t t = t0 + sl;
-                if (t >= T) continue;
-                int lo = 0, hi = LN;
-                while (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (pre[sub][mid] <= t) lo = mid;
-                    else hi = mid;
+            // NB items per lane and round: their searches and loads are all
+            // issued before the first accumulator update, so one round costs
+            // about one memory latency instead of NB
+            constexpr int NB = 4;
+            for (uint64_t t0 = 0; t0 < Tmax; t0 += NB * LN) {
+                uint32_t Cs[NB];
+                uint64_t cvs[NB];
+                uint32_t okm = 0;
+#pragma unroll
+                for (int j = 0; j < NB; j++) {
+                    const uint64_t t = t0 + uint64_t(j * LN + sl);
+                    const bool ok = t < T;
+                    okm |= uint32_t(ok) << j;
+                    int lo = 0, hi = LN;
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) >> 1;
+                        if (pre[sub][mid] <= t) lo = mid;
+                        else hi = mid;
+                    }
+                    if (LEAFCHILD) {
+                        Cs[j] = 1u << col_b[ys[sub][lo]];
+                        cvs[j] = 1;
+                    } else {
+                        // rows outside this unit's items read entry 0 (the table is
+                        // not empty whenever some unit of the wave has items)
+                        const uint64_t i = ok ? r0s[sub][lo] + (t - pre[sub][lo]) : 0;
+                        const uint32_t C = kset(keys[i], L);
+                        Cs[j] = C;
+                        cvs[j] = EMIT ? cnt[i] : 0;
+                    }
                 }
-                uint32_t C;
-                uint64_t cv;
-                if (LEAFCHILD) {
-                    C = 1u << col_b[ys[sub][lo]];
-                    cv = 1;
-                } else {
-                    uint64_t i = r0s[sub][lo] + (t - pre[sub][lo]);
-                    C = kset(keys[i], L);
-                    cv = cnt[i];
-                }
-                if (C & cb) continue;
-                C |= cb;
-                passed++;
-                atomicOr(&bits[C >> 5], 1u << (C & 31));
-                if (EMIT) {
-                    uint64_t old = atomicAdd((unsigned long long*)&val[C], (unsigned long long)cv);
-                    over |= (old + cv < old);
+#pragma unroll
+                for (int j = 0; j < NB; j++) {
+                    uint32_t C = Cs[j];
+                    if (!((okm >> j) & 1u) || (C & cb)) continue;
+                    C |= cb;
+                    passed++;
+                    atomicOr(&bits[C >> 5], 1u << (C & 31));
+                    if (EMIT) {
+                        const uint64_t cv = cvs[j];
+                        uint64_t old = atomicAdd((unsigned long long*)&val[C], (unsigned long long)cv);
+                        over |= (old + cv < old);
+                    }
                 }
             }
         }

@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -171,7 +173,46 @@ void launch_unrank(const EnumStep* steps, int root_step, const uint64_t* rcum, u
                    int vb, int rkw, void* rowkeys, uint32_t* err, hipStream_t s);
 
 // root: counts[bid] += cnt for every entry of a one-column table; per-vertex optional
+// Dense one-column tables (slots.hip).  Slot r of colour-set size s is the
+// r-th mask of popcount s - 1 (increasing) over the k - 1 colours other than
+// the bag vertex's; R(s) = C(k - 1, s - 1) slots per (colouring, vertex).
+constexpr int kSlotBlock = 256;
+constexpr int kSlotCounters = 256;      // spread entry counters per step
+constexpr int kSlotCounterStride = 16;  // uint64 words between counters (one 128-byte line)
+constexpr int kSlotBits = 11;  // k - 1 <= 11
+struct SlotGrid {
+    int32_t n = 0;
+    int B = 0, R = 1;
+    int upb = 0;        // units (colouring, vertex) per block when R <= kSlotBlock, else 0
+    int bpu = 0;        // blocks per unit when R > kSlotBlock
+    uint32_t nbx = 0;   // blocks per colouring
+    bool xcd = false;   // colourings dealt to XCDs in turn
+    uint64_t blocks = 0;
+};
+SlotGrid slot_grid(int32_t n, int B, int R);
+// sums the spread counters of `steps` steps into nsz[2 * steps]
+void launch_slot_counters(const unsigned long long* spread, int steps, uint64_t* nsz, hipStream_t s);
+std::vector<uint16_t> slot_rank_tables();  // rank[2^11] then unrank[2^11], by popcount
+int slot_unrank_offset(int popcount);
+void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag,
+                      unsigned long long* nsz, hipStream_t s);
+void launch_slot_edge(const uint64_t* icnt, const uint8_t* iflag, int R_in, const SlotGrid& G, DevGraph g,
+                      const uint8_t* colors, int k, int degF_u, int degF_child, const uint16_t* rank,
+                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
+                      uint32_t* ovf, hipStream_t s);
+constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
+void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const uint64_t* zcnt,
+                      const uint8_t* zflag, int R_z, int q, int k, const SlotGrid& G, const uint16_t* rank,
+                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
+                      uint32_t* ovf, hipStream_t s);
+void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int s_in, int32_t n, int B,
+                      const uint8_t* colors, const uint16_t* unrank, uint64_t* counts, uint32_t* ovf,
+                      uint64_t* per_vertex, uint32_t* csets, int cwords, hipStream_t s);
+
+// root: per colouring the sum of the entries (counts), a sticky overflow flag,
+// optionally the per-image sums of the bag vertex, and a bitmap of the colour
+// sets present (cwords 32-bit words per colouring)
 void launch_root(const DevTable& in, int32_t n, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex,
-                 hipStream_t s);
+                 uint32_t* csets, int cwords, hipStream_t s);
 
 }  // namespace ccg

@@ -413,10 +413,13 @@ k_join(const K* __restrict__ yk, const uint64_t* __restrict__ yc, const K* __res
                 uint32_t P = ny * nz;
                 uint32_t Pmax = P;
                 for (int d = 32; d >= 1; d >>= 1) Pmax = max(Pmax, (uint32_t)__shfl_xor(Pmax, d, 64));
+                // q / nz as a multiply by ceil(2^32 / nz): exact while q * nz < 2^32,
+                // which holds for q < CH^2 and nz <= CH
+                const uint64_t rz = nz ? ((uint64_t(1) << 32) + nz - 1) / nz : 0;
                 for (uint32_t q0 = 0; q0 < Pmax; q0 += LN) {
                     uint32_t q = q0 + sl;
                     if (q >= P) continue;
-                    uint32_t a = q / nz, d = q - a * nz;
+                    uint32_t a = uint32_t((uint64_t(q) * rz) >> 32), d = q - a * nz;
                     uint32_t Cy = ys[sub][a], Cz = zs[sub][d];
                     if ((Cy & Cz) != bagcol) continue;
                     uint32_t C = Cy | Cz;
@@ -662,7 +665,8 @@ void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, 
 
 template <class K>
 __global__ void k_root(const K* __restrict__ keys, const uint64_t* __restrict__ cnt, uint64_t N, Lay L, int32_t n,
-                       uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex) {
+                       uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, uint32_t* csets, int cwords) {
+    // csets: per colouring, a bitmap over colour sets of the root's entries
     // entries are sorted by colouring: every thread sums a contiguous chunk
     // and flushes one atomic per colouring it sees
     constexpr uint64_t kChunk = 32;
@@ -685,6 +689,9 @@ __global__ void k_root(const K* __restrict__ keys, const uint64_t* __restrict__ 
             }
             over |= (sum + v < sum);
             sum += v;
+            const uint32_t C = kset(k, L);
+            uint32_t* w = &csets[uint64_t(bid) * cwords + (C >> 5)];
+            if (!(__atomic_load_n(w, __ATOMIC_RELAXED) & (1u << (C & 31)))) atomicOr(w, 1u << (C & 31));
             if (per_vertex) atomicAdd((unsigned long long*)&per_vertex[uint64_t(bid) * n + kcol(k, L, 0)], (unsigned long long)v);
         }
         uint64_t old = atomicAdd((unsigned long long*)&counts[cur], (unsigned long long)sum);
@@ -692,13 +699,15 @@ __global__ void k_root(const K* __restrict__ keys, const uint64_t* __restrict__ 
     }
 }
 
-void launch_root(const DevTable& in, int32_t n, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, hipStream_t s) {
+void launch_root(const DevTable& in, int32_t n, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex,
+                 uint32_t* csets, int cwords, hipStream_t s) {
     if (!in.n) return;
     if (in.lay.kw() == 1)
-        k_root<uint64_t><<<grid_for((in.n + 31) / 32), kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, n, counts, ovf,
-                                                           per_vertex);
+        k_root<uint64_t><<<grid_for((in.n + 31) / 32), kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.n, in.lay, n,
+                                                                       counts, ovf, per_vertex, csets, cwords);
     else
-        k_root<u128><<<grid_for((in.n + 31) / 32), kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, n, counts, ovf, per_vertex);
+        k_root<u128><<<grid_for((in.n + 31) / 32), kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.n, in.lay, n, counts,
+                                                                   ovf, per_vertex, csets, cwords);
 }
 
 }  // namespace ccg

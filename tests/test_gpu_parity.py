@@ -62,10 +62,15 @@ def test_zoo_counts_match_oracle(ctx, gname, make):
             D = cc.build_decomposition(pat.n, pat.edges)
             td = D.export()
             counts, ovf, _ = run_gpu(ctx, g, pat, k, colors, td=td)
+            sizes = ctx.last_table_sizes()
+            ref_sizes = 0
             for b in range(B):
-                ref = O.dp_count(g, pat, k, colors[b], td=td)
+                ref = O.dp_count(g, pat, k, colors[b], td=td, sizes=True)
                 assert int(counts[b]) == ref["count"], (gname, pat.name, k, b)
                 assert bool(ovf[b]) == ref["overflow"]
+                ref_sizes = ref_sizes + ref["sizes"]
+            # |D_x| of every node, summed over the colourings
+            assert np.array_equal(sizes, ref_sizes), (gname, pat.name, k)
 
 
 def test_oracle_td_imported_gives_same_counts(ctx):
