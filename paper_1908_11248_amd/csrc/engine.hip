@@ -440,7 +440,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             SlotTab o = make(y.s + z.s - 1);
             SlotGrid G = slot_grid(g.n, B, o.R);
             X.timed("slot_join", double(units) * 9.0 * (y.R + z.R + o.R), [&] {
-                launch_slot_join(y.cnt, y.flag, y.R, z.cnt, z.flag, z.R, y.s - 1, k, G, rank, unrank,
+                launch_slot_join(y.cnt, y.flag, y.R, z.cnt, z.flag, z.R, y.s - 1, o.s - 1, k, G, rank, unrank,
                                  slot_unrank_offset(o.s - 1), o.cnt, o.flag, nz_of(i), ovf, s);
             });
             tab[i] = o;

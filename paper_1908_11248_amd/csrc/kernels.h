@@ -202,7 +202,7 @@ void launch_slot_edge(const uint64_t* icnt, const uint8_t* iflag, int R_in, cons
                       uint32_t* ovf, hipStream_t s);
 constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
 void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const uint64_t* zcnt,
-                      const uint8_t* zflag, int R_z, int q, int k, const SlotGrid& G, const uint16_t* rank,
+                      const uint8_t* zflag, int R_z, int q, int p, int k, const SlotGrid& G, const uint16_t* rank,
                       const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
                       uint32_t* ovf, hipStream_t s);
 void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int s_in, int32_t n, int B,

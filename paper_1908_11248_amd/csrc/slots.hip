@@ -153,6 +153,9 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
     }
     uint64_t sum = 0, nin = 0;
     bool pres = false, over = false;
+    // the child table of colouring b is exact (no count wrapped while it was
+    // built) when b's overflow flag is still clear; then presence is count != 0
+    const bool exact = LEAFCHILD || (v1 > v0 && ovf[b] == 0);
     const int64_t e_lo = v1 > v0 ? g.rp[v0] : 0, e_hi = v1 > v0 ? g.rp[v1] : 0;
     for (int64_t c0 = e_lo; c0 < e_hi; c0 += kEdgeChunk) {
         const int cn = int(min(int64_t(kEdgeChunk), e_hi - c0));
@@ -167,22 +170,43 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
         __syncthreads();
         if (!act) continue;
         const int a = int(max(rb, c0) - c0), z = int(min(re, c0 + cn) - c0);
-        for (int i = a; i < z; i++) {
-            const uint32_t c = s_c[i], cy = c & 0x7fu;
-            if (!((Cx >> cy) & 1u)) continue;
-            if (LEAFCHILD) {
-                if (c & 0x80u) {
+        if (LEAFCHILD) {
+            for (int i = a; i < z; i++) {
+                const uint32_t c = s_c[i];
+                if (((Cx >> (c & 0x7fu)) & 1u) && (c & 0x80u)) {
                     sum += 1;
                     nin++;
                     pres = true;
                 }
+            }
+            continue;
+        }
+        // four neighbours per round: their slot loads are in flight together
+        for (int i = a; i < z; i += 4) {
+            uint64_t idx[4], cv[4];
+            uint32_t ok = 0, fl = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int ii = min(i + j, z - 1);
+                const uint32_t cy = s_c[ii] & 0x7fu;
+                ok |= uint32_t((i + j < z) && ((Cx >> cy) & 1u)) << j;
+                idx[j] = (row0 + s_y[ii]) * uint32_t(R_in) + s_rank[bit_close(Cx, cy)];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) cv[j] = ((ok >> j) & 1u) ? icnt[idx[j]] : 0;
+            if (exact) {
+                // no count of this colouring has wrapped: present entries hold >= 1
+#pragma unroll
+                for (int j = 0; j < 4; j++) fl |= uint32_t(cv[j] != 0) << j;
             } else {
-                const uint64_t idx = (row0 + s_y[i]) * uint32_t(R_in) + s_rank[bit_close(Cx, cy)];
-                const uint8_t f = iflag[idx];
-                const uint64_t cv = icnt[idx];  // issued with the flag: absent entries hold 0
-                if (f) {
-                    sum += cv;
-                    over |= sum < cv;
+#pragma unroll
+                for (int j = 0; j < 4; j++) fl |= uint32_t(((ok >> j) & 1u) && iflag[idx[j]]) << j;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if ((fl >> j) & 1u) {
+                    sum += cv[j];
+                    over |= sum < cv[j];
                     nin++;
                     pres = true;
                 }
@@ -200,20 +224,25 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
 
 // Join on a one-vertex bag (Sec. 3, join nodes): output slot (b, v, C) sums
 // y(C_y) * z(C_z) over the splits of C - colour(v) into disjoint parts of the
-// children's sizes (q bits for the first child).  With STAGE the children's
-// rows of the block's vertices (contiguous in both tables) are staged in LDS.
+// children's sizes (q of its p bits for the first child).  The splits are the
+// q-subsets of bit positions, the same for every thread (Gosper's successor
+// on a wave-uniform index), deposited into each thread's own mask.  With
+// STAGE the children's rows of the block's vertices (contiguous in both
+// tables) are staged in LDS; presence bytes are read only for a colouring
+// whose counts have wrapped.
 template <bool STAGE>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag, int R_y,
-            const uint64_t* __restrict__ zcnt, const uint8_t* __restrict__ zflag, int R_z, int q, int k, SlotGrid G,
-            const uint16_t* __restrict__ rank, const uint16_t* __restrict__ unrank, int uoff, uint64_t* ocnt,
-            uint8_t* oflag, unsigned long long* nsz, uint32_t* ovf) {
+            const uint64_t* __restrict__ zcnt, const uint8_t* __restrict__ zflag, int R_z, int q, int p, int k,
+            SlotGrid G, const uint16_t* __restrict__ rank, const uint16_t* __restrict__ unrank, int uoff,
+            uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz, uint32_t* ovf) {
     extern __shared__ uint64_t s_mem[];
     uint32_t b, v0, v1, v, r;
     block_range(G, &b, &v0, &v1);
     const bool valid = slot_in(G, v0, v1, &v, &r);
     const uint32_t nu = v1 - v0;
     const uint64_t base = uint64_t(b) * uint32_t(G.n) + v0;  // first unit of the block
+    const bool exact = v1 > v0 && ovf[b] == 0;
     // layout: [y counts][z counts][rank table][y flags][z flags]
     const size_t cap = size_t(G.upb > 0 ? G.upb : 1);
     uint64_t* s_yc = s_mem;
@@ -224,13 +253,11 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
     stage_rank(s_rank, rank, k);
     if (STAGE) {
         const uint32_t ny = nu * uint32_t(R_y), nz = nu * uint32_t(R_z);
-        for (uint32_t i = threadIdx.x; i < ny; i += kSlotBlock) {
-            s_yc[i] = ycnt[base * uint32_t(R_y) + i];
-            s_yf[i] = yflag[base * uint32_t(R_y) + i];
-        }
-        for (uint32_t i = threadIdx.x; i < nz; i += kSlotBlock) {
-            s_zc[i] = zcnt[base * uint32_t(R_z) + i];
-            s_zf[i] = zflag[base * uint32_t(R_z) + i];
+        for (uint32_t i = threadIdx.x; i < ny; i += kSlotBlock) s_yc[i] = ycnt[base * uint32_t(R_y) + i];
+        for (uint32_t i = threadIdx.x; i < nz; i += kSlotBlock) s_zc[i] = zcnt[base * uint32_t(R_z) + i];
+        if (!exact) {
+            for (uint32_t i = threadIdx.x; i < ny; i += kSlotBlock) s_yf[i] = yflag[base * uint32_t(R_y) + i];
+            for (uint32_t i = threadIdx.x; i < nz; i += kSlotBlock) s_zf[i] = zflag[base * uint32_t(R_z) + i];
         }
     }
     __syncthreads();
@@ -241,21 +268,66 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
         const uint64_t u = v - v0;
         const uint64_t by = STAGE ? u * uint32_t(R_y) : (base + u) * uint32_t(R_y);
         const uint64_t bz = STAGE ? u * uint32_t(R_z) : (base + u) * uint32_t(R_z);
-        // every submask A of m with q bits; the rest of m is the other part
-        for (uint32_t A = m;; A = (A - 1u) & m) {
-            if (__popc(A) == q) {
-                const uint64_t iy = by + s_rank[A], iz = bz + s_rank[m ^ A];
-                const bool f = STAGE ? (s_yf[iy] && s_zf[iz]) : (yflag[iy] && zflag[iz]);
+        uint32_t bitpos[kSlotBits];  // one-hot j-th set bit of m
+        {
+            uint32_t mm = m;
+#pragma unroll
+            for (int j = 0; j < kSlotBits; j++) {
+                bitpos[j] = mm & (0u - mm);
+                mm &= mm - 1u;
+            }
+        }
+        const uint32_t lim = 1u << p;
+        uint32_t x = (1u << q) - 1u;
+        bool more = true;
+        while (more) {
+            // up to four q-subsets x of the p positions (wave-uniform)
+            uint32_t xs[4];
+            int nx = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (more) {
+                    xs[j] = x;
+                    nx = j + 1;
+                    if (x == 0) {
+                        more = false;  // q = 0: the empty set only
+                    } else {
+                        const uint32_t c = x & (0u - x), rr = x + c;
+                        x = (((rr ^ x) >> 2) >> (__ffs(c) - 1)) | rr;
+                        more = x < lim;
+                    }
+                } else {
+                    xs[j] = 0;
+                }
+            }
+            uint64_t iy[4], iz[4], ya[4], zc[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                uint32_t A = 0;
+#pragma unroll
+                for (int t = 0; t < kSlotBits; t++)
+                    if ((xs[j] >> t) & 1u) A |= bitpos[t];
+                iy[j] = by + s_rank[A];
+                iz[j] = bz + s_rank[m ^ A];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                ya[j] = j < nx ? (STAGE ? s_yc[iy[j]] : ycnt[iy[j]]) : 0;
+                zc[j] = j < nx ? (STAGE ? s_zc[iz[j]] : zcnt[iz[j]]) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (j >= nx) break;
+                const bool f = exact ? (ya[j] != 0 && zc[j] != 0)
+                                     : (STAGE ? (s_yf[iy[j]] && s_zf[iz[j]]) : (yflag[iy[j]] && zflag[iz[j]]));
                 if (f) {
-                    const uint64_t a = STAGE ? s_yc[iy] : ycnt[iy], c = STAGE ? s_zc[iz] : zcnt[iz];
-                    const uint64_t p = a * c;
-                    over |= __umul64hi(a, c) != 0;
-                    sum += p;
-                    over |= sum < p;
+                    const uint64_t pr = ya[j] * zc[j];
+                    over |= __umul64hi(ya[j], zc[j]) != 0;
+                    sum += pr;
+                    over |= sum < pr;
                     pres = true;
                 }
             }
-            if (A == 0) break;
         }
         const uint64_t o = (base + u) * uint32_t(G.R) + r;
         ocnt[o] = sum;
@@ -404,7 +476,7 @@ void launch_slot_edge(const uint64_t* icnt, const uint8_t* iflag, int R_in, cons
 }
 
 void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const uint64_t* zcnt,
-                      const uint8_t* zflag, int R_z, int q, int k, const SlotGrid& G, const uint16_t* rank,
+                      const uint8_t* zflag, int R_z, int q, int p, int k, const SlotGrid& G, const uint16_t* rank,
                       const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
                       uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
@@ -413,10 +485,10 @@ void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const
     const size_t ranks = size_t(2) << (k - 1);
     if (staged + ranks <= kSlotJoinLds)
         k_slot_join<true><<<slot_dims(G.blocks), kSlotBlock, staged + ranks, s>>>(
-            ycnt, yflag, R_y, zcnt, zflag, R_z, q, k, G, rank, unrank, uoff, ocnt, oflag, nsz, ovf);
+            ycnt, yflag, R_y, zcnt, zflag, R_z, q, p, k, G, rank, unrank, uoff, ocnt, oflag, nsz, ovf);
     else
         k_slot_join<false><<<slot_dims(G.blocks), kSlotBlock, ranks, s>>>(
-            ycnt, yflag, R_y, zcnt, zflag, R_z, q, k, G, rank, unrank, uoff, ocnt, oflag, nsz, ovf);
+            ycnt, yflag, R_y, zcnt, zflag, R_z, q, p, k, G, rank, unrank, uoff, ocnt, oflag, nsz, ovf);
 }
 
 void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int s_in, int32_t n, int B,
