@@ -67,8 +67,12 @@ int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_conte
             std::vector<uint16_t> st = slot_rank_tables();
             hip_check(hipMalloc(&c->slot_tables, st.size() * 2), "hipMalloc");
             hip_check(hipMemcpy(c->slot_tables, st.data(), st.size() * 2, hipMemcpyHostToDevice), "hipMemcpy");
+            std::vector<uint32_t> sp = slot_split_tables();
+            hip_check(hipMalloc(&c->slot_splits, sp.size() * 4), "hipMalloc");
+            hip_check(hipMemcpy(c->slot_splits, sp.data(), sp.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
         } catch (...) {
             if (c->slot_tables) (void)hipFree(c->slot_tables);
+            if (c->slot_splits) (void)hipFree(c->slot_splits);
             if (c->arena_mem) (void)hipFree(c->arena_mem);
             c->main.destroy();
             delete c;
@@ -85,6 +89,7 @@ int cc_context_destroy(cc_context* ctx) {
         for (auto& w : ctx->workers) w->destroy();
         ctx->main.destroy();
         if (ctx->slot_tables) (void)hipFree(ctx->slot_tables);
+        if (ctx->slot_splits) (void)hipFree(ctx->slot_splits);
         if (ctx->arena_mem) (void)hipFree(ctx->arena_mem);
         delete ctx;
     });

@@ -108,6 +108,7 @@ struct cc_context {
     uint64_t max_entries = 0;  // per-table budget (0: none)
     int batch_lanes = 0;       // lanes for cc_count_batch (0: tuned on first use)
     uint16_t* slot_tables = nullptr;  // device: rank[2048] then unrank[2048] (slots.hip)
+    uint32_t* slot_splits = nullptr;  // device: join split tables (slots.hip)
     ccg::Lane& worker(size_t i);
 };
 

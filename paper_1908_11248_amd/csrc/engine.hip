@@ -374,12 +374,14 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (st.in1 >= 0) uses[st.in1]++;
     }
     std::vector<SlotTab> tab(S);
-    // per step: introduce entries, output entries (spread counters, summed at the end)
-    const uint64_t per_step = uint64_t(kSlotCounters) * kSlotCounterStride;
-    uint64_t* spread = X.alloc<uint64_t>(S * per_step);
-    launch_fill_u64(spread, 0, S * per_step, s);
-    uint64_t* nsz = X.alloc<uint64_t>(2 * S);
-    auto nz_of = [&](size_t i) { return reinterpret_cast<unsigned long long*>(spread + i * per_step); };
+    // per step: introduce entries, output entries, added up from per-block
+    // partials (one scratch buffer, reused step after step on the stream)
+    uint64_t nsz_words = 2 * S, part_words = slot_root_partials(g.n, B);
+    for (size_t i = 0; i < S; i++)
+        if (sz[i] > 0) part_words = std::max(part_words, 2 * slot_grid(g.n, B, binom(k - 1, sz[i] - 1), 1).blocks);
+    uint64_t* nsz = X.alloc<uint64_t>(nsz_words);
+    launch_fill_u64(nsz, 0, nsz_words, s);
+    uint64_t* part = X.alloc<uint64_t>(part_words);
     const uint16_t* rank = ctx->slot_tables;
     const uint16_t* unrank = ctx->slot_tables + (1 << kSlotBits);
     const double csr = double(B) * (9.0 * g.n + 4.0 * g.m2);
@@ -413,13 +415,14 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const bool leafc = virt[st.in0] != 0;
             const SlotTab in = leafc ? SlotTab() : tab[st.in0];
             SlotTab o = make(sz[i + 1]);
-            SlotGrid G = slot_grid(g.n, B, o.R);
+            SlotGrid G = slot_grid(g.n, B, o.R, 4);
             const int degF_u = rq.degree_mask ? st.degF : 0;
             const int degF_c = rq.degree_mask ? plan.steps[st.in0].degF : 0;
             X.timed("slot_edge", double(units) * 9.0 * (in.R + o.R) + csr, [&] {
                 launch_slot_edge(in.cnt, in.flag, in.R, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
-                                 slot_unrank_offset(o.s - 1), o.cnt, o.flag, nz_of(i), ovf, s);
+                                 slot_unrank_offset(o.s - 1), o.cnt, o.flag, part, ovf, s);
             });
+            launch_slot_sum(part, G.blocks, nsz + 2 * i, s);
             tab[i + 1] = o;
             if (st.node >= 0) node_of.push_back({st.node, int(2 * i)});
             if (f.node >= 0) node_of.push_back({f.node, int(2 * i + 1)});
@@ -430,19 +433,23 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         }
         if (st.kind == S_LEAF) {
             SlotTab o = make(1);
-            SlotGrid G = slot_grid(g.n, B, 1);
+            SlotGrid G = slot_grid(g.n, B, 1, 4);
             X.timed("slot_leaf", double(units) * 9.0 + 8.0 * g.n,
-                    [&] { launch_slot_leaf(G, g, rq.degree_mask ? st.degF : 0, o.cnt, o.flag, nz_of(i), s); });
+                    [&] { launch_slot_leaf(G, g, rq.degree_mask ? st.degF : 0, o.cnt, o.flag, part, s); });
+            launch_slot_sum(part, G.blocks, nsz + 2 * i, s);
             tab[i] = o;
         } else {  // one-vertex join
             const SlotTab& y = tab[st.in0];
             const SlotTab& z = tab[st.in1];
             SlotTab o = make(y.s + z.s - 1);
-            SlotGrid G = slot_grid(g.n, B, o.R);
+            const int p = o.s - 1, q = y.s - 1;
+            const int nsplit = binom(p, q);
+            SlotGrid G = slot_grid(g.n, B, o.R, std::max(1, slot_join_m(o.R, y.R, z.R, nsplit)));
             X.timed("slot_join", double(units) * 9.0 * (y.R + z.R + o.R), [&] {
-                launch_slot_join(y.cnt, y.flag, y.R, z.cnt, z.flag, z.R, y.s - 1, o.s - 1, k, G, rank, unrank,
-                                 slot_unrank_offset(o.s - 1), o.cnt, o.flag, nz_of(i), ovf, s);
+                launch_slot_join(y.cnt, y.flag, y.R, z.cnt, z.flag, z.R, ctx->slot_splits + slot_split_offset(p, q),
+                                 nsplit, binom(kSlotBits, p), G, o.cnt, o.flag, part, ovf, s);
             });
+            launch_slot_sum(part, G.blocks, nsz + 2 * i, s);
             tab[i] = o;
             done_with(st.in0);
             done_with(st.in1);
@@ -450,19 +457,18 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
         budgeted.push_back(int(2 * i + 1));
     }
-    launch_slot_counters(reinterpret_cast<const unsigned long long*>(spread), int(S), nsz, s);
     hip_check(hipGetLastError(), "kernel launch");
 
     const SlotTab& rc = tab[plan.root_child];
-    uint64_t* counts = X.alloc<uint64_t>(B);
-    launch_fill_u64(counts, 0, B, s);
+    uint64_t* counts = X.alloc<uint64_t>(B);  // written by the root
     uint64_t* pv = nullptr;
     if (rq.per_vertex) pv = X.alloc<uint64_t>(units);  // every entry is written
     const int cwords = k >= 5 ? 1 << (k - 5) : 1;
     uint32_t* csets = X.alloc<uint32_t>(uint64_t(B) * cwords);
     launch_fill_u32(csets, 0, uint64_t(B) * cwords, s);
     X.timed("slot_root", double(units) * 9.0 * rc.R, [&] {
-        launch_slot_root(rc.cnt, rc.flag, rc.R, rc.s, g.n, B, rq.colors, unrank, counts, ovf, pv, csets, cwords, s);
+        launch_slot_root(rc.cnt, rc.flag, rc.R, rc.s, g.n, B, rq.colors, unrank, part, counts, ovf, pv, csets, cwords,
+                         s);
     });
     out->counts.assign(B, 0);
     std::vector<uint32_t> of(B, 0);
@@ -495,7 +501,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     X.release(counts);
     X.release(pv);
     X.release(nsz);
-    X.release(spread);
+    X.release(part);
     X.release(ovf);
     drop(tab[plan.root_child]);
     X.synced();
@@ -569,7 +575,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         const uint64_t units = uint64_t(B) * uint64_t(g.n);
         bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= ctx->arena.size() / 4;
         for (size_t i = 0; i < S && fits; i++)
-            if (sz[i] > 0 && slot_grid(g.n, B, binom(k - 1, sz[i] - 1)).blocks >= (uint64_t(1) << 32)) fits = false;
+            if (sz[i] > 0 && slot_grid(g.n, B, binom(k - 1, sz[i] - 1), 1).blocks >= (uint64_t(1) << 32)) fits = false;
         if (fits) {
             try {
                 run_slots(ctx, X, rq, fuse, virt, sz, ovf, out);

@@ -177,36 +177,45 @@ void launch_unrank(const EnumStep* steps, int root_step, const uint64_t* rcum, u
 // r-th mask of popcount s - 1 (increasing) over the k - 1 colours other than
 // the bag vertex's; R(s) = C(k - 1, s - 1) slots per (colouring, vertex).
 constexpr int kSlotBlock = 256;
-constexpr int kSlotCounters = 256;      // spread entry counters per step
-constexpr int kSlotCounterStride = 16;  // uint64 words between counters (one 128-byte line)
 constexpr int kSlotBits = 11;  // k - 1 <= 11
 struct SlotGrid {
     int32_t n = 0;
     int B = 0, R = 1;
-    int upb = 0;        // units (colouring, vertex) per block when R <= kSlotBlock, else 0
+    int upb = 0;        // units (colouring, vertex) per block and thread row when R <= kSlotBlock, else 0
+    int m = 1;          // vertices per thread (upb * m per block)
     int bpu = 0;        // blocks per unit when R > kSlotBlock
     uint32_t nbx = 0;   // blocks per colouring
     bool xcd = false;   // colourings dealt to XCDs in turn
     uint64_t blocks = 0;
 };
-SlotGrid slot_grid(int32_t n, int B, int R);
-// sums the spread counters of `steps` steps into nsz[2 * steps]
-void launch_slot_counters(const unsigned long long* spread, int steps, uint64_t* nsz, hipStream_t s);
+SlotGrid slot_grid(int32_t n, int B, int R, int m_max);
+// vertices per thread with which a join block stages its children's rows in LDS (0: none fit)
+int slot_join_m(int R_out, int R_y, int R_z, int nsplit);
 std::vector<uint16_t> slot_rank_tables();  // rank[2^11] then unrank[2^11], by popcount
 int slot_unrank_offset(int popcount);
-void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag,
-                      unsigned long long* nsz, hipStream_t s);
+// Slot kernels store per-block partial entry counts (introduce entries,
+// output entries) at part[2L], part[2L + 1]; launch_slot_sum adds those of
+// `blocks` blocks into out[0], out[1].
+void launch_slot_sum(const uint64_t* part, uint64_t blocks, uint64_t* out, hipStream_t s);
+void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
+                      hipStream_t s);
 void launch_slot_edge(const uint64_t* icnt, const uint8_t* iflag, int R_in, const SlotGrid& G, DevGraph g,
                       const uint8_t* colors, int k, int degF_u, int degF_child, const uint16_t* rank,
-                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
+                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
                       uint32_t* ovf, hipStream_t s);
 constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
+// split table rows of (p, q) (see slots.hip) start at slot_split_offset(p, q);
+// row stride C(kSlotBits, p)
+std::vector<uint32_t> slot_split_tables();
+int slot_split_offset(int p, int q);
 void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const uint64_t* zcnt,
-                      const uint8_t* zflag, int R_z, int q, int p, int k, const SlotGrid& G, const uint16_t* rank,
-                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
-                      uint32_t* ovf, hipStream_t s);
+                      const uint8_t* zflag, int R_z, const uint32_t* splits, int nsplit, int sstride,
+                      const SlotGrid& G, uint64_t* ocnt, uint8_t* oflag, uint64_t* part, uint32_t* ovf,
+                      hipStream_t s);
+// rpart: slot_root_partials(n, B) words of scratch
+uint64_t slot_root_partials(int32_t n, int B);
 void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int s_in, int32_t n, int B,
-                      const uint8_t* colors, const uint16_t* unrank, uint64_t* counts, uint32_t* ovf,
+                      const uint8_t* colors, const uint16_t* unrank, uint64_t* rpart, uint64_t* counts, uint32_t* ovf,
                       uint64_t* per_vertex, uint32_t* csets, int cwords, hipStream_t s);
 
 // root: per colouring the sum of the entries (counts), a sticky overflow flag,

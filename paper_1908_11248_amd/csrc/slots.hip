@@ -19,6 +19,8 @@
 // is staged in LDS once per block.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 
@@ -26,7 +28,7 @@ namespace ccg {
 
 namespace {
 
-constexpr int kEdgeChunk = 1024;  // neighbours staged per round
+constexpr int kEdgeChunk = 2048;  // neighbours staged per round
 
 __device__ __forceinline__ uint32_t bit_open(uint32_t m, uint32_t c) {  // insert a 0 at bit c
     return ((m >> c) << (c + 1)) | (m & ((1u << c) - 1u));
@@ -37,13 +39,16 @@ __device__ __forceinline__ uint32_t bit_close(uint32_t m, uint32_t c) {  // dele
 
 __device__ __forceinline__ uint32_t block_index() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
-// block -> (colouring, vertices [v0, v1)).  With xcd set, consecutive blocks
-// (which the dispatcher deals round-robin to the eight XCDs) take eight
-// different colourings, so each XCD's L2 holds the rows of the colouring it
-// works on.  An empty range marks a block past the end.
-__device__ __forceinline__ void block_range(const SlotGrid& G, uint32_t* b, uint32_t* v0, uint32_t* v1) {
+// block -> (colouring, vertices [v0, v1), place j within the colouring).
+// With xcd set, consecutive blocks (which the dispatcher deals round-robin to
+// the eight XCDs) take eight different colourings, so each XCD's L2 holds
+// the rows of the colouring it works on.  An empty range marks a block past
+// the end.
+__device__ __forceinline__ void block_range(const SlotGrid& G, uint32_t* b, uint32_t* v0, uint32_t* v1,
+                                            uint32_t* jb) {
     *b = 0;
     *v0 = *v1 = 0;
+    *jb = 0;
     const uint32_t L = block_index();
     if (L >= G.blocks) return;
     uint32_t bb, j;
@@ -57,102 +62,174 @@ __device__ __forceinline__ void block_range(const SlotGrid& G, uint32_t* b, uint
     }
     if (bb >= uint32_t(G.B)) return;
     *b = bb;
+    *jb = j;
     if (G.upb > 0) {
-        *v0 = j * uint32_t(G.upb);
-        *v1 = min(*v0 + uint32_t(G.upb), uint32_t(G.n));
+        *v0 = j * uint32_t(G.upb * G.m);
+        *v1 = min(*v0 + uint32_t(G.upb * G.m), uint32_t(G.n));
     } else {
         *v0 = j / uint32_t(G.bpu);
         *v1 = *v0 + 1;
     }
 }
 
-// this thread's (vertex, slot) inside the block's range; false if none
-__device__ __forceinline__ bool slot_in(const SlotGrid& G, uint32_t v0, uint32_t v1, uint32_t* v, uint32_t* r) {
-    uint32_t vv, rr;
+// this thread's slot r and first vertex; its i-th vertex is v + i * upb
+__device__ __forceinline__ void slot_of(const SlotGrid& G, uint32_t v0, uint32_t jb, uint32_t* v, uint32_t* r,
+                                        bool* lane_ok) {
     if (G.upb > 0) {
         const uint32_t u = threadIdx.x / uint32_t(G.R);
-        vv = v0 + u;
-        rr = threadIdx.x - u * uint32_t(G.R);
+        *v = v0 + u;
+        *r = threadIdx.x - u * uint32_t(G.R);
+        *lane_ok = u < uint32_t(G.upb);
     } else {
-        vv = v0;
-        rr = ((block_index() >> (G.xcd ? 3 : 0)) % G.nbx % uint32_t(G.bpu)) * kSlotBlock + threadIdx.x;
+        *v = v0;
+        *r = (jb % uint32_t(G.bpu)) * kSlotBlock + threadIdx.x;
+        *lane_ok = *r < uint32_t(G.R);
     }
-    *v = vv;
-    *r = rr;
-    return vv < v1 && rr < uint32_t(G.R);
 }
 
-// Entry counters of a step: kSlotCounters pairs (extra, present), each in
-// its own 128-byte line; a wave adds into the pair of its block, so no
-// single address takes every wave's atomic.
-__device__ __forceinline__ void count_entries(bool present, uint64_t extra, unsigned long long* nsz) {
-    const uint64_t pm = __ballot(present);
+// Entry counts of a block: (extra, present) summed over its threads and
+// stored at part[2L], part[2L + 1] (L = block index); k_slot_sum adds them
+// up.  Plain stores: no address is shared between blocks.
+__device__ __forceinline__ void count_entries(uint32_t present, uint64_t extra, uint64_t* part, uint64_t blocks) {
+    __shared__ uint64_t s_p[2][kSlotBlock / 64];
+    const uint64_t pr = wave_sum(present);
     const uint64_t ex = wave_sum(extra);
     if (__lane_id() == 0) {
-        unsigned long long* c = nsz + uint64_t(block_index() % kSlotCounters) * kSlotCounterStride;
-        if (pm) atomicAdd(&c[1], (unsigned long long)__popcll(pm));
-        if (ex) atomicAdd(&c[0], (unsigned long long)ex);
+        s_p[0][threadIdx.x >> 6] = ex;
+        s_p[1][threadIdx.x >> 6] = pr;
     }
+    __syncthreads();
+    const uint32_t L = block_index();
+    if (threadIdx.x < 2 && L < blocks) {
+        uint64_t t = 0;
+        for (int i = 0; i < kSlotBlock / 64; i++) t += s_p[threadIdx.x][i];
+        part[2 * uint64_t(L) + threadIdx.x] = t;
+    }
+}
+
+// (sum, wrapped) over a block, sums mod 2^64: every lane of a butterfly sums
+// all 64 values, and a total of 2^64 or more wraps in every lane's tree
+__device__ __forceinline__ void block_sum_wrap(uint64_t* sum, bool* over) {
+    __shared__ uint64_t s_s[kSlotBlock / 64];
+    __shared__ uint32_t s_o[kSlotBlock / 64];
+    uint64_t v = *sum;
+    bool o = *over;
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint64_t x = __shfl_xor(v, d, 64);
+        const uint64_t t = v + x;
+        o |= t < v;
+        v = t;
+    }
+    const bool wo = __ballot(o) != 0;
+    if (__lane_id() == 0) {
+        s_s[threadIdx.x >> 6] = v;
+        s_o[threadIdx.x >> 6] = wo;
+    }
+    __syncthreads();
+    v = 0;
+    o = false;
+    for (int i = 0; i < int(blockDim.x >> 6); i++) {
+        const uint64_t t = v + s_s[i];
+        o |= (t < v) || s_o[i];
+        v = t;
+    }
+    *sum = v;
+    *over = o;
 }
 
 __device__ __forceinline__ void stage_rank(uint16_t* s_rank, const uint16_t* __restrict__ rank, int k) {
     for (int i = threadIdx.x; i < (1 << (k - 1)); i += kSlotBlock) s_rank[i] = rank[i];
 }
 
+// dst[i] = src[i] for i < n by the block, four loads per thread in flight
+template <class T>
+__device__ __forceinline__ void stage_copy(T* dst, const T* __restrict__ src, uint32_t n) {
+    for (uint32_t i0 = 0; i0 < n; i0 += 4 * kSlotBlock) {
+        T v[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
+            v[j] = i < n ? src[i] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
+            if (i < n) dst[i] = v[j];
+        }
+    }
+}
+
 }  // namespace
 
 // Leaf (Sec. 3, leaf nodes; degree mask of Sec. 4): one slot per (b, v).
+template <int M>
 __global__ void __launch_bounds__(kSlotBlock)
-k_slot_leaf(SlotGrid G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz) {
-    uint32_t b, v0, v1, v, r;
-    block_range(G, &b, &v0, &v1);
-    const bool valid = slot_in(G, v0, v1, &v, &r);
-    bool pres = false;
-    if (valid) {
-        pres = g.rp[v + 1] - g.rp[v] >= degF;
-        const uint64_t o = uint64_t(b) * uint32_t(g.n) + v;
-        ocnt[o] = pres ? 1 : 0;
-        oflag[o] = pres;
+k_slot_leaf(SlotGrid G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, uint64_t* part) {
+    uint32_t b, v0, v1, jb, v, r;
+    bool lane_ok;
+    block_range(G, &b, &v0, &v1, &jb);
+    slot_of(G, v0, jb, &v, &r, &lane_ok);
+    uint32_t npres = 0;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        const uint32_t vi = v + uint32_t(i * G.upb);
+        if (lane_ok && vi < v1) {
+            const bool pres = g.rp[vi + 1] - g.rp[vi] >= degF;
+            const uint64_t o = uint64_t(b) * uint32_t(g.n) + vi;
+            ocnt[o] = pres ? 1 : 0;
+            oflag[o] = pres;
+            npres += pres;
+        }
     }
-    count_entries(pres, 0, nsz);
+    count_entries(npres, 0, part, G.blocks);
 }
 
 // Introduce u (image v, every neighbour y of v is a candidate for the child's
 // bag vertex) followed by the forget of the child's vertex: output slot
 // (b, v, C) sums the child entries (b, y, C - colour(v)) over neighbours y,
-// which requires colour(y) in C - colour(v).  nsz[0] receives the number of
-// introduce entries (child entries that pass), nsz[1] the output entries.
+// which requires colour(y) in C - colour(v).  The block partials count the
+// introduce entries (child entries that pass) and the output entries.
 // The neighbour lists of the block's vertices are one CSR range; it is
 // staged in rounds of kEdgeChunk (ids, and colours with the leaf child's
-// degree test in bit 7).
-template <bool LEAFCHILD>
+// degree test in bit 7).  A thread serves the same slot of M vertices.
+template <bool LEAFCHILD, int M>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag, int R_in, SlotGrid G, DevGraph g,
             const uint8_t* __restrict__ colors, int k, int degF_u, int degF_child, const uint16_t* __restrict__ rank,
-            const uint16_t* __restrict__ unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
+            const uint16_t* __restrict__ unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
             uint32_t* ovf) {
     extern __shared__ uint16_t s_rank[];  // rank of every mask over k - 1 bits
     __shared__ uint32_t s_y[kEdgeChunk];
     __shared__ uint8_t s_c[kEdgeChunk];
-    uint32_t b, v0, v1, v, r;
-    block_range(G, &b, &v0, &v1);
-    const bool valid = slot_in(G, v0, v1, &v, &r);
+    uint32_t b, v0, v1, jb, v, r;
+    bool lane_ok;
+    block_range(G, &b, &v0, &v1, &jb);
+    slot_of(G, v0, jb, &v, &r, &lane_ok);
     stage_rank(s_rank, rank, k);
     const uint32_t n = uint32_t(g.n);
     const uint8_t* cb = colors + uint64_t(b) * n;
     const uint64_t row0 = uint64_t(b) * n;
-    int64_t rb = 0, re = 0;
-    uint32_t Cx = 0;
-    bool act = false;
-    if (valid) {
-        rb = g.rp[v];
-        re = g.rp[v + 1];
-        act = re - rb >= degF_u;
-        // the output set without colour(v), as a k-bit mask: the child's set
-        if (act) Cx = bit_open(unrank[uoff + r], cb[v]);
+    int64_t rb[M], re[M];
+    uint32_t Cx[M];
+    uint64_t sum[M], nin = 0;
+    uint32_t pres = 0, over = 0;  // bit i: the i-th vertex
+    const uint32_t mr = lane_ok ? unrank[uoff + r] : 0;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        const uint32_t vi = v + uint32_t(i * G.upb);
+        rb[i] = re[i] = 0;
+        Cx[i] = 0;
+        sum[i] = 0;
+        if (lane_ok && vi < v1) {
+            const int64_t a = g.rp[vi], z = g.rp[vi + 1];
+            if (z - a >= degF_u) {
+                rb[i] = a;
+                re[i] = z;
+                // the output set without colour(v), as a k-bit mask: the child's set
+                Cx[i] = bit_open(mr, cb[vi]);
+            }
+        }
     }
-    uint64_t sum = 0, nin = 0;
-    bool pres = false, over = false;
     // the child table of colouring b is exact (no count wrapped while it was
     // built) when b's overflow flag is still clear; then presence is count != 0
     const bool exact = LEAFCHILD || (v1 > v0 && ovf[b] == 0);
@@ -160,247 +237,284 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
     for (int64_t c0 = e_lo; c0 < e_hi; c0 += kEdgeChunk) {
         const int cn = int(min(int64_t(kEdgeChunk), e_hi - c0));
         __syncthreads();
-        for (int i = threadIdx.x; i < cn; i += kSlotBlock) {
-            const uint32_t y = uint32_t(g.col[c0 + i]);
-            uint32_t c = cb[y];
-            if (LEAFCHILD && g.rp[y + 1] - g.rp[y] >= degF_child) c |= 0x80u;
-            s_y[i] = y;
-            s_c[i] = uint8_t(c);
+        for (int i0 = 0; i0 < cn; i0 += 4 * kSlotBlock) {
+            // four neighbours per thread: their loads are in flight together
+            uint32_t y[4], c[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int i = i0 + j * kSlotBlock + int(threadIdx.x);
+                y[j] = i < cn ? uint32_t(g.col[c0 + i]) : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) c[j] = cb[y[j]];
+            // (a neighbour has degree >= 1 already: no lookup for degF_child <= 1)
+            if (LEAFCHILD) {
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (degF_child <= 1 || g.rp[y[j] + 1] - g.rp[y[j]] >= degF_child) c[j] |= 0x80u;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int i = i0 + j * kSlotBlock + int(threadIdx.x);
+                if (i < cn) {
+                    s_y[i] = y[j];
+                    s_c[i] = uint8_t(c[j]);
+                }
+            }
         }
         __syncthreads();
-        if (!act) continue;
-        const int a = int(max(rb, c0) - c0), z = int(min(re, c0 + cn) - c0);
-        if (LEAFCHILD) {
-            for (int i = a; i < z; i++) {
-                const uint32_t c = s_c[i];
-                if (((Cx >> (c & 0x7fu)) & 1u) && (c & 0x80u)) {
-                    sum += 1;
-                    nin++;
-                    pres = true;
+#pragma unroll
+        for (int u = 0; u < M; u++) {
+            const int a = int(max(rb[u], c0) - c0), z = int(min(re[u], c0 + cn) - c0);
+            if (LEAFCHILD) {
+                for (int i = a; i < z; i++) {
+                    const uint32_t c = s_c[i];
+                    if (((Cx[u] >> (c & 0x7fu)) & 1u) && (c & 0x80u)) {
+                        sum[u] += 1;
+                        nin++;
+                        pres |= 1u << u;
+                    }
                 }
+                continue;
             }
-            continue;
-        }
-        // four neighbours per round: their slot loads are in flight together
-        for (int i = a; i < z; i += 4) {
-            uint64_t idx[4], cv[4];
-            uint32_t ok = 0, fl = 0;
+            // four neighbours per round: their slot loads are in flight together
+            for (int i = a; i < z; i += 4) {
+                uint64_t idx[4], cv[4];
+                uint32_t ok = 0, fl = 0;
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int ii = min(i + j, z - 1);
-                const uint32_t cy = s_c[ii] & 0x7fu;
-                ok |= uint32_t((i + j < z) && ((Cx >> cy) & 1u)) << j;
-                idx[j] = (row0 + s_y[ii]) * uint32_t(R_in) + s_rank[bit_close(Cx, cy)];
-            }
+                for (int j = 0; j < 4; j++) {
+                    const int ii = min(i + j, z - 1);
+                    const uint32_t cy = s_c[ii] & 0x7fu;
+                    ok |= uint32_t((i + j < z) && ((Cx[u] >> cy) & 1u)) << j;
+                    idx[j] = (row0 + s_y[ii]) * uint32_t(R_in) + s_rank[bit_close(Cx[u], cy)];
+                }
 #pragma unroll
-            for (int j = 0; j < 4; j++) cv[j] = ((ok >> j) & 1u) ? icnt[idx[j]] : 0;
-            if (exact) {
-                // no count of this colouring has wrapped: present entries hold >= 1
+                for (int j = 0; j < 4; j++) cv[j] = ((ok >> j) & 1u) ? icnt[idx[j]] : 0;
+                if (exact) {
+                    // no count of this colouring has wrapped: present entries hold >= 1
 #pragma unroll
-                for (int j = 0; j < 4; j++) fl |= uint32_t(cv[j] != 0) << j;
-            } else {
+                    for (int j = 0; j < 4; j++) fl |= uint32_t(cv[j] != 0) << j;
+                } else {
 #pragma unroll
-                for (int j = 0; j < 4; j++) fl |= uint32_t(((ok >> j) & 1u) && iflag[idx[j]]) << j;
-            }
+                    for (int j = 0; j < 4; j++) fl |= uint32_t(((ok >> j) & 1u) && iflag[idx[j]]) << j;
+                }
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                if ((fl >> j) & 1u) {
-                    sum += cv[j];
-                    over |= sum < cv[j];
-                    nin++;
-                    pres = true;
+                for (int j = 0; j < 4; j++) {
+                    if ((fl >> j) & 1u) {
+                        sum[u] += cv[j];
+                        over |= uint32_t(sum[u] < cv[j]);
+                        nin++;
+                        pres |= 1u << u;
+                    }
                 }
             }
         }
     }
-    if (valid) {
-        const uint64_t o = (row0 + v) * uint32_t(G.R) + r;
-        ocnt[o] = sum;
-        oflag[o] = pres;
-        if (over) atomicOr(&ovf[b], 1u);
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        const uint32_t vi = v + uint32_t(i * G.upb);
+        if (lane_ok && vi < v1) {
+            const uint64_t o = (row0 + vi) * uint32_t(G.R) + r;
+            ocnt[o] = sum[i];
+            oflag[o] = (pres >> i) & 1u;
+        }
     }
-    count_entries(pres, nin, nsz);
+    if (over) atomicOr(&ovf[b], 1u);
+    count_entries(__popc(pres), nin, part, G.blocks);
 }
 
 // Join on a one-vertex bag (Sec. 3, join nodes): output slot (b, v, C) sums
 // y(C_y) * z(C_z) over the splits of C - colour(v) into disjoint parts of the
-// children's sizes (q of its p bits for the first child).  The splits are the
-// q-subsets of bit positions, the same for every thread (Gosper's successor
-// on a wave-uniform index), deposited into each thread's own mask.  With
-// STAGE the children's rows of the block's vertices (contiguous in both
-// tables) are staged in LDS; presence bytes are read only for a colouring
-// whose counts have wrapped.
-template <bool STAGE>
+// children's sizes.  The splits of slot r are the same for every vertex and
+// colouring: row t of the split table holds (rank of C_y, rank of C_z) for
+// every r (slot_split_tables), so a thread walks the rows once for its M
+// vertices.  With STAGE the children's rows of the block's vertices
+// (contiguous in both tables) and the split table are staged in LDS;
+// presence bytes are read only for a colouring whose counts have wrapped.
+template <bool STAGE, int M>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag, int R_y,
-            const uint64_t* __restrict__ zcnt, const uint8_t* __restrict__ zflag, int R_z, int q, int p, int k,
-            SlotGrid G, const uint16_t* __restrict__ rank, const uint16_t* __restrict__ unrank, int uoff,
-            uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz, uint32_t* ovf) {
+            const uint64_t* __restrict__ zcnt, const uint8_t* __restrict__ zflag, int R_z,
+            const uint32_t* __restrict__ splits, int nsplit, int sstride, SlotGrid G, uint64_t* ocnt, uint8_t* oflag,
+            uint64_t* part, uint32_t* ovf) {
     extern __shared__ uint64_t s_mem[];
-    uint32_t b, v0, v1, v, r;
-    block_range(G, &b, &v0, &v1);
-    const bool valid = slot_in(G, v0, v1, &v, &r);
+    uint32_t b, v0, v1, jb, v, r;
+    bool lane_ok;
+    block_range(G, &b, &v0, &v1, &jb);
+    slot_of(G, v0, jb, &v, &r, &lane_ok);
     const uint32_t nu = v1 - v0;
     const uint64_t base = uint64_t(b) * uint32_t(G.n) + v0;  // first unit of the block
     const bool exact = v1 > v0 && ovf[b] == 0;
-    // layout: [y counts][z counts][rank table][y flags][z flags]
-    const size_t cap = size_t(G.upb > 0 ? G.upb : 1);
+    const int R = G.R;
+    // layout: [y counts][z counts][split rows][y flags][z flags]
+    const size_t cap = STAGE ? size_t(G.upb) * M : 0;
     uint64_t* s_yc = s_mem;
-    uint64_t* s_zc = s_yc + (STAGE ? cap * R_y : 0);
-    uint16_t* s_rank = reinterpret_cast<uint16_t*>(s_zc + (STAGE ? cap * R_z : 0));
-    uint8_t* s_yf = reinterpret_cast<uint8_t*>(s_rank + (1 << (k - 1)));
-    uint8_t* s_zf = s_yf + (STAGE ? cap * R_y : 0);
-    stage_rank(s_rank, rank, k);
+    uint64_t* s_zc = s_yc + cap * R_y;
+    uint32_t* s_sp = reinterpret_cast<uint32_t*>(s_zc + cap * R_z);
+    uint8_t* s_yf = reinterpret_cast<uint8_t*>(s_sp + (STAGE ? size_t(nsplit) * R : 0));
+    uint8_t* s_zf = s_yf + cap * R_y;
     if (STAGE) {
         const uint32_t ny = nu * uint32_t(R_y), nz = nu * uint32_t(R_z);
-        for (uint32_t i = threadIdx.x; i < ny; i += kSlotBlock) s_yc[i] = ycnt[base * uint32_t(R_y) + i];
-        for (uint32_t i = threadIdx.x; i < nz; i += kSlotBlock) s_zc[i] = zcnt[base * uint32_t(R_z) + i];
+        stage_copy(s_yc, ycnt + base * uint32_t(R_y), ny);
+        stage_copy(s_zc, zcnt + base * uint32_t(R_z), nz);
+        for (uint32_t i = threadIdx.x; i < uint32_t(nsplit * R); i += kSlotBlock) {
+            const uint32_t t = i / uint32_t(R);
+            s_sp[i] = splits[size_t(t) * sstride + (i - t * uint32_t(R))];
+        }
         if (!exact) {
-            for (uint32_t i = threadIdx.x; i < ny; i += kSlotBlock) s_yf[i] = yflag[base * uint32_t(R_y) + i];
-            for (uint32_t i = threadIdx.x; i < nz; i += kSlotBlock) s_zf[i] = zflag[base * uint32_t(R_z) + i];
+            stage_copy(s_yf, yflag + base * uint32_t(R_y), ny);
+            stage_copy(s_zf, zflag + base * uint32_t(R_z), nz);
         }
+        __syncthreads();
     }
-    __syncthreads();
-    uint64_t sum = 0;
-    bool pres = false, over = false;
-    if (valid) {
-        const uint32_t m = unrank[uoff + r];
-        const uint64_t u = v - v0;
-        const uint64_t by = STAGE ? u * uint32_t(R_y) : (base + u) * uint32_t(R_y);
-        const uint64_t bz = STAGE ? u * uint32_t(R_z) : (base + u) * uint32_t(R_z);
-        uint32_t bitpos[kSlotBits];  // one-hot j-th set bit of m
-        {
-            uint32_t mm = m;
+    uint64_t sum[M];
+    uint32_t pres = 0;
+    bool over = false;
+    uint64_t by[M], bz[M];
 #pragma unroll
-            for (int j = 0; j < kSlotBits; j++) {
-                bitpos[j] = mm & (0u - mm);
-                mm &= mm - 1u;
-            }
-        }
-        const uint32_t lim = 1u << p;
-        uint32_t x = (1u << q) - 1u;
-        bool more = true;
-        while (more) {
-            // up to four q-subsets x of the p positions (wave-uniform)
-            uint32_t xs[4];
-            int nx = 0;
+    for (int i = 0; i < M; i++) {
+        sum[i] = 0;
+        const uint64_t u = uint64_t(v - v0) + uint64_t(i) * G.upb;  // place within the block
+        by[i] = STAGE ? u * uint32_t(R_y) : (base + u) * uint32_t(R_y);
+        bz[i] = STAGE ? u * uint32_t(R_z) : (base + u) * uint32_t(R_z);
+    }
+    bool live[M];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                if (more) {
-                    xs[j] = x;
-                    nx = j + 1;
-                    if (x == 0) {
-                        more = false;  // q = 0: the empty set only
-                    } else {
-                        const uint32_t c = x & (0u - x), rr = x + c;
-                        x = (((rr ^ x) >> 2) >> (__ffs(c) - 1)) | rr;
-                        more = x < lim;
-                    }
+    for (int i = 0; i < M; i++) live[i] = lane_ok && v + uint32_t(i * G.upb) < v1;
+    if (live[0]) {
+        for (int t = 0; t < nsplit; t++) {
+            const uint32_t e = STAGE ? s_sp[t * R + r] : splits[size_t(t) * sstride + r];
+            const uint32_t ry = e & 0xffffu, rz = e >> 16;
+#pragma unroll
+            for (int i = 0; i < M; i++) {
+                if (!live[i]) continue;
+                const uint64_t iy = by[i] + ry, iz = bz[i] + rz;
+                const uint64_t a = STAGE ? s_yc[iy] : ycnt[iy], c = STAGE ? s_zc[iz] : zcnt[iz];
+                const bool f = exact ? (a != 0 && c != 0)
+                                     : (STAGE ? (s_yf[iy] && s_zf[iz]) : (yflag[iy] && zflag[iz]));
+                if (!f) continue;
+                uint64_t pr;
+                if (((a | c) >> 32) == 0) {
+                    pr = uint64_t(uint32_t(a)) * uint32_t(c);  // no wrap possible
                 } else {
-                    xs[j] = 0;
+                    pr = a * c;
+                    over |= __umul64hi(a, c) != 0;
                 }
-            }
-            uint64_t iy[4], iz[4], ya[4], zc[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                uint32_t A = 0;
-#pragma unroll
-                for (int t = 0; t < kSlotBits; t++)
-                    if ((xs[j] >> t) & 1u) A |= bitpos[t];
-                iy[j] = by + s_rank[A];
-                iz[j] = bz + s_rank[m ^ A];
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                ya[j] = j < nx ? (STAGE ? s_yc[iy[j]] : ycnt[iy[j]]) : 0;
-                zc[j] = j < nx ? (STAGE ? s_zc[iz[j]] : zcnt[iz[j]]) : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                if (j >= nx) break;
-                const bool f = exact ? (ya[j] != 0 && zc[j] != 0)
-                                     : (STAGE ? (s_yf[iy[j]] && s_zf[iz[j]]) : (yflag[iy[j]] && zflag[iz[j]]));
-                if (f) {
-                    const uint64_t pr = ya[j] * zc[j];
-                    over |= __umul64hi(ya[j], zc[j]) != 0;
-                    sum += pr;
-                    over |= sum < pr;
-                    pres = true;
-                }
+                sum[i] += pr;
+                over |= sum[i] < pr;
+                pres |= 1u << i;
             }
         }
-        const uint64_t o = (base + u) * uint32_t(G.R) + r;
-        ocnt[o] = sum;
-        oflag[o] = pres;
-        if (over) atomicOr(&ovf[b], 1u);
     }
-    count_entries(pres, 0, nsz);
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        if (!live[i]) continue;
+        const uint64_t o = (base + uint64_t(v - v0) + uint64_t(i) * G.upb) * uint32_t(R) + r;
+        ocnt[o] = sum[i];
+        oflag[o] = (pres >> i) & 1u;
+    }
+    if (over) atomicOr(&ovf[b], 1u);
+    count_entries(__popc(pres), 0, part, G.blocks);
 }
 
 // Root (Sec. 3, the root's value): per colouring, the sum of every entry of
-// the one-column table below the root; per_vertex (optional) gets the sum per
-// image of that bag vertex, and csets a bitmap of the colour sets present
-// (the entries of the root's own table), gathered per block in LDS.  One
-// thread per (b, v).
+// the one-column table below the root.  Each block stores its (sum, wrapped)
+// at rpart[2 (b nbx + j)] (j = the block's place within colouring b) and
+// k_slot_root_sum adds them; per_vertex (optional) gets the sum per image of
+// the bag vertex, and csets a bitmap of the colour sets present (the entries
+// of the root's own table), gathered per block in LDS.  One slot per vertex,
+// M vertices per thread.
+template <int M>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_root(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag, int R_in,
             const uint8_t* __restrict__ colors, const uint16_t* __restrict__ unrank, int uoff, SlotGrid G,
-            uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, uint32_t* csets, int cwords) {
+            uint64_t* rpart, uint64_t* per_vertex, uint32_t* csets, int cwords) {
     extern __shared__ uint32_t s_cs[];
-    uint32_t b, v0, v1, v, r;
-    block_range(G, &b, &v0, &v1);
-    const bool valid = slot_in(G, v0, v1, &v, &r);
+    uint32_t b, v0, v1, jb, v, r;
+    bool lane_ok;
+    block_range(G, &b, &v0, &v1, &jb);
+    slot_of(G, v0, jb, &v, &r, &lane_ok);
     for (int i = threadIdx.x; i < cwords; i += kSlotBlock) s_cs[i] = 0;
     __syncthreads();
     uint64_t sum = 0;
     bool over = false;
-    if (valid) {
-        const uint64_t unit = uint64_t(b) * uint32_t(G.n) + v;
-        const uint64_t* p = icnt + unit * uint32_t(R_in);
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        const uint32_t vi = v + uint32_t(i * G.upb);
+        if (!(lane_ok && vi < v1)) continue;
+        const uint64_t unit = uint64_t(b) * uint32_t(G.n) + vi;
+        const uint64_t* pc = icnt + unit * uint32_t(R_in);
         const uint8_t* f = iflag + unit * uint32_t(R_in);
         const uint32_t cv = colors[unit];
+        uint64_t us = 0;
         for (int j = 0; j < R_in; j++) {
-            const uint64_t c = p[j];
-            sum += c;
-            over |= sum < c;
+            const uint64_t c = pc[j];
+            us += c;
+            over |= us < c;
             if (f[j]) {
                 const uint32_t C = bit_open(unrank[uoff + j], cv) | (1u << cv);
                 atomicOr(&s_cs[C >> 5], 1u << (C & 31));
             }
         }
-        if (per_vertex) per_vertex[unit] = sum;
+        if (per_vertex) per_vertex[unit] = us;
+        sum += us;
+        over |= sum < us;
     }
-    // every lane of the butterfly sums all 64 values, and a total of 2^64 or
-    // more wraps in every lane's tree
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint64_t o = __shfl_xor(sum, d, 64);
-        const uint64_t t = sum + o;
-        over |= t < sum;
-        sum = t;
-    }
-    const bool wave_over = __ballot(over) != 0;
-    if (__lane_id() == 0 && __ballot(valid)) {
-        const uint64_t old = atomicAdd((unsigned long long*)&counts[b], (unsigned long long)sum);
-        if (wave_over || old + sum < old) atomicOr(&ovf[b], 1u);
-    }
-    __syncthreads();
-    if (v1 > v0)
+    block_sum_wrap(&sum, &over);
+    if (v1 > v0) {
+        if (threadIdx.x == 0) {
+            rpart[2 * (uint64_t(b) * G.nbx + jb)] = sum;
+            rpart[2 * (uint64_t(b) * G.nbx + jb) + 1] = over;
+        }
         for (int i = threadIdx.x; i < cwords; i += kSlotBlock)
             if (s_cs[i]) atomicOr(&csets[uint64_t(b) * cwords + i], s_cs[i]);
+    }
 }
 
-// nsz[j] = sum of the kSlotCounters spread counters j of each step
-__global__ void k_slot_counters(const unsigned long long* spread, uint64_t* nsz) {
-    const unsigned long long* c = spread + uint64_t(blockIdx.x >> 1) * kSlotCounters * kSlotCounterStride;
-    const int j = blockIdx.x & 1;
-    uint64_t v = 0;
-    for (int i = threadIdx.x; i < kSlotCounters; i += 64) v += c[uint64_t(i) * kSlotCounterStride + j];
-    v = wave_sum(v);
-    if (threadIdx.x == 0) nsz[blockIdx.x] = v;
+// counts[b] = the sum of colouring b's block partials; ovf[b] set if any wrapped
+__global__ void __launch_bounds__(kSlotBlock)
+k_slot_root_sum(const uint64_t* __restrict__ rpart, uint32_t nbx, uint64_t* counts, uint32_t* ovf) {
+    const uint32_t b = blockIdx.x;
+    uint64_t sum = 0;
+    bool over = false;
+    for (uint32_t j = threadIdx.x; j < nbx; j += kSlotBlock) {
+        const uint64_t c = rpart[2 * (uint64_t(b) * nbx + j)];
+        sum += c;
+        over |= (sum < c) || rpart[2 * (uint64_t(b) * nbx + j) + 1] != 0;
+    }
+    block_sum_wrap(&sum, &over);
+    if (threadIdx.x == 0) {
+        counts[b] = sum;
+        if (over) ovf[b] = 1u;
+    }
 }
 
-void launch_slot_counters(const unsigned long long* spread, int steps, uint64_t* nsz, hipStream_t s) {
-    if (steps) k_slot_counters<<<2 * steps, 64, 0, s>>>(spread, nsz);
+// out[0..1] += the (extra, present) partials of `blocks` blocks
+__global__ void __launch_bounds__(kSlotBlock) k_slot_sum(const uint64_t* __restrict__ part, uint64_t blocks, uint64_t* out) {
+    __shared__ uint64_t s_p[2][kSlotBlock / 64];
+    uint64_t a = 0, c = 0;
+    for (uint64_t i = uint64_t(blockIdx.x) * kSlotBlock + threadIdx.x; i < blocks; i += uint64_t(gridDim.x) * kSlotBlock) {
+        a += part[2 * i];
+        c += part[2 * i + 1];
+    }
+    a = wave_sum(a);
+    c = wave_sum(c);
+    if (__lane_id() == 0) {
+        s_p[0][threadIdx.x >> 6] = a;
+        s_p[1][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        uint64_t t = 0;
+        for (int i = 0; i < kSlotBlock / 64; i++) t += s_p[threadIdx.x][i];
+        if (t) atomicAdd((unsigned long long*)&out[threadIdx.x], (unsigned long long)t);
+    }
+}
+
+void launch_slot_sum(const uint64_t* part, uint64_t blocks, uint64_t* out, hipStream_t s) {
+    if (!blocks) return;
+    const uint64_t g = std::min<uint64_t>(256, (blocks + kSlotBlock - 1) / kSlotBlock);
+    k_slot_sum<<<unsigned(g), kSlotBlock, 0, s>>>(part, blocks, out);
 }
 
 std::vector<uint16_t> slot_rank_tables() {
@@ -430,75 +544,170 @@ static dim3 slot_dims(uint64_t blocks) {  // x a multiple of 8, so the XCD of a 
     return blocks <= X ? dim3(unsigned(blocks)) : dim3(unsigned(X), unsigned((blocks + X - 1) / X));
 }
 
-SlotGrid slot_grid(int32_t n, int B, int R) {
+SlotGrid slot_grid(int32_t n, int B, int R, int m_max) {
     SlotGrid G;
     G.n = n;
     G.B = B;
     G.R = R;
-    int64_t nbx;
-    if (R <= kSlotBlock) {
-        G.upb = kSlotBlock / R;
-        G.bpu = 0;
-        nbx = (int64_t(n) + G.upb - 1) / G.upb;
-    } else {
-        G.upb = 0;
-        G.bpu = (R + kSlotBlock - 1) / kSlotBlock;
-        nbx = int64_t(n) * G.bpu;
-    }
     G.xcd = B >= 8;
-    if (nbx >= (int64_t(1) << 32)) {  // beyond a 32-bit block index: callers take the sparse path
-        G.nbx = 0;
-        G.blocks = ~uint64_t(0);
-        return G;
+    // vertices per thread: as many as m_max allows while the grid keeps some
+    // 2048 blocks to spread over the chip
+    for (int m = (R <= kSlotBlock ? m_max : 1); m >= 1; m >>= 1) {
+        int64_t nbx;
+        G.m = m;
+        if (R <= kSlotBlock) {
+            G.upb = kSlotBlock / R;
+            G.bpu = 0;
+            nbx = (int64_t(n) + int64_t(G.upb) * m - 1) / (int64_t(G.upb) * m);
+        } else {
+            G.upb = 0;
+            G.bpu = (R + kSlotBlock - 1) / kSlotBlock;
+            nbx = int64_t(n) * G.bpu;
+        }
+        if (nbx >= (int64_t(1) << 32)) {  // beyond a 32-bit block index: callers take the sparse path
+            G.nbx = 0;
+            G.blocks = ~uint64_t(0);
+            return G;
+        }
+        G.nbx = uint32_t(nbx);
+        G.blocks = G.xcd ? uint64_t(nbx) * 8u * uint64_t((B + 7) / 8) : uint64_t(nbx) * uint64_t(B);
+        if (G.blocks >= 2048 || m == 1) break;
     }
-    G.nbx = uint32_t(nbx);
-    G.blocks = G.xcd ? uint64_t(nbx) * 8u * uint64_t((B + 7) / 8) : uint64_t(nbx) * uint64_t(B);
     return G;
 }
 
-void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag,
-                      unsigned long long* nsz, hipStream_t s) {
-    if (G.blocks) k_slot_leaf<<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(G, g, degF, ocnt, oflag, nsz);
+// Split tables: for colour-set masks of p bits (slot r = rank among them) and
+// every q-subset A of the mask (row t, Gosper order over bit positions):
+// rank(A) | rank(mask - A) << 16.  Rows of (p, q) have stride C(kSlotBits, p)
+// and start at slot_split_offset(p, q).
+static int binom11(int p) {
+    int c = 1;
+    for (int i = 0; i < p; i++) c = c * (kSlotBits - i) / (i + 1);
+    return c;
+}
+static int binom_pq(int p, int q) {
+    if (q < 0 || q > p) return 0;
+    int c = 1;
+    for (int i = 0; i < q; i++) c = c * (p - i) / (i + 1);
+    return c;
+}
+
+int slot_split_offset(int p, int q) {
+    int off = 0;
+    for (int pp = 0; pp <= kSlotBits; pp++)
+        for (int qq = 0; qq <= pp; qq++) {
+            if (pp == p && qq == q) return off;
+            off += binom_pq(pp, qq) * binom11(pp);
+        }
+    return off;
+}
+
+std::vector<uint32_t> slot_split_tables() {
+    std::vector<uint16_t> rt = slot_rank_tables();
+    const int M = 1 << kSlotBits;
+    std::vector<uint32_t> t(size_t(slot_split_offset(kSlotBits + 1, 0)));
+    for (int p = 0; p <= kSlotBits; p++) {
+        const int R = binom11(p);
+        for (int q = 0; q <= p; q++) {
+            const size_t off = size_t(slot_split_offset(p, q));
+            for (int r = 0; r < R; r++) {
+                const uint32_t m = rt[M + slot_unrank_offset(p) + r];
+                int pos[kSlotBits], np = 0;
+                for (int b = 0; b < kSlotBits; b++)
+                    if ((m >> b) & 1u) pos[np++] = b;
+                int row = 0;
+                for (uint32_t x = 0; x < (1u << p); x++) {  // q-subsets of the positions, increasing
+                    if (__builtin_popcount(x) != q) continue;
+                    uint32_t A = 0;
+                    for (int j = 0; j < p; j++)
+                        if ((x >> j) & 1u) A |= 1u << pos[j];
+                    t[off + size_t(row) * R + r] = uint32_t(rt[A]) | (uint32_t(rt[m ^ A]) << 16);
+                    row++;
+                }
+            }
+        }
+    }
+    return t;
+}
+
+// vertices per thread with which a join block stages its children's rows and
+// split rows in kSlotJoinLds (0: none fit)
+int slot_join_m(int R_out, int R_y, int R_z, int nsplit) {
+    if (R_out > kSlotBlock) return 0;
+    const size_t upb = size_t(kSlotBlock / R_out), spl = size_t(nsplit) * R_out * 4;
+    for (int m = 4; m >= 1; m >>= 1)
+        if (upb * m * size_t(R_y + R_z) * 9 + spl <= kSlotJoinLds) return m;
+    return 0;
+}
+
+#define SLOT_BY_M(MACRO) \
+    switch (G.m) {       \
+        case 4: MACRO(4); break; \
+        case 2: MACRO(2); break; \
+        default: MACRO(1); break; \
+    }
+
+void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
+                      hipStream_t s) {
+    if (!G.blocks) return;
+#define LEAF_M(M) k_slot_leaf<M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(G, g, degF, ocnt, oflag, part)
+    SLOT_BY_M(LEAF_M)
+#undef LEAF_M
 }
 
 void launch_slot_edge(const uint64_t* icnt, const uint8_t* iflag, int R_in, const SlotGrid& G, DevGraph g,
                       const uint8_t* colors, int k, int degF_u, int degF_child, const uint16_t* rank,
-                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
+                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
                       uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
     const size_t lds = size_t(2) << (k - 1);
-    if (icnt)
-        k_slot_edge<false><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(
-            icnt, iflag, R_in, G, g, colors, k, degF_u, degF_child, rank, unrank, uoff, ocnt, oflag, nsz, ovf);
-    else
-        k_slot_edge<true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(
-            icnt, iflag, R_in, G, g, colors, k, degF_u, degF_child, rank, unrank, uoff, ocnt, oflag, nsz, ovf);
+#define EDGE_M(M)                                                                                                    \
+    if (icnt)                                                                                                        \
+        k_slot_edge<false, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(                                          \
+            icnt, iflag, R_in, G, g, colors, k, degF_u, degF_child, rank, unrank, uoff, ocnt, oflag, part, ovf);     \
+    else                                                                                                             \
+        k_slot_edge<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(                                           \
+            icnt, iflag, R_in, G, g, colors, k, degF_u, degF_child, rank, unrank, uoff, ocnt, oflag, part, ovf)
+    SLOT_BY_M(EDGE_M)
+#undef EDGE_M
 }
 
 void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const uint64_t* zcnt,
-                      const uint8_t* zflag, int R_z, int q, int p, int k, const SlotGrid& G, const uint16_t* rank,
-                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, unsigned long long* nsz,
-                      uint32_t* ovf, hipStream_t s) {
+                      const uint8_t* zflag, int R_z, const uint32_t* splits, int nsplit, int sstride,
+                      const SlotGrid& G, uint64_t* ocnt, uint8_t* oflag, uint64_t* part, uint32_t* ovf,
+                      hipStream_t s) {
     if (!G.blocks) return;
-    const size_t units = size_t(G.upb > 0 ? G.upb : 1);
-    const size_t staged = units * size_t(R_y + R_z) * 9;
-    const size_t ranks = size_t(2) << (k - 1);
-    if (staged + ranks <= kSlotJoinLds)
-        k_slot_join<true><<<slot_dims(G.blocks), kSlotBlock, staged + ranks, s>>>(
-            ycnt, yflag, R_y, zcnt, zflag, R_z, q, p, k, G, rank, unrank, uoff, ocnt, oflag, nsz, ovf);
-    else
-        k_slot_join<false><<<slot_dims(G.blocks), kSlotBlock, ranks, s>>>(
-            ycnt, yflag, R_y, zcnt, zflag, R_z, q, p, k, G, rank, unrank, uoff, ocnt, oflag, nsz, ovf);
+    const bool stage = G.upb > 0 && slot_join_m(G.R, R_y, R_z, nsplit) >= G.m;
+    const size_t lds = stage ? size_t(G.upb) * G.m * size_t(R_y + R_z) * 9 + size_t(nsplit) * G.R * 4 : 0;
+#define JOIN_M(M)                                                                                             \
+    if (stage)                                                                                                \
+        k_slot_join<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(ycnt, yflag, R_y, zcnt, zflag, R_z,  \
+                                                                           splits, nsplit, sstride, G, ocnt,   \
+                                                                           oflag, part, ovf);                  \
+    else                                                                                                      \
+        k_slot_join<false, M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(ycnt, yflag, R_y, zcnt, zflag, R_z,   \
+                                                                          splits, nsplit, sstride, G, ocnt,    \
+                                                                          oflag, part, ovf)
+    SLOT_BY_M(JOIN_M)
+#undef JOIN_M
 }
 
 void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int s_in, int32_t n, int B,
-                      const uint8_t* colors, const uint16_t* unrank, uint64_t* counts, uint32_t* ovf,
+                      const uint8_t* colors, const uint16_t* unrank, uint64_t* rpart, uint64_t* counts, uint32_t* ovf,
                       uint64_t* per_vertex, uint32_t* csets, int cwords, hipStream_t s) {
-    SlotGrid G = slot_grid(n, B, 1);
-    if (G.blocks)
-        k_slot_root<<<slot_dims(G.blocks), kSlotBlock, size_t(4) * cwords, s>>>(
-            icnt, iflag, R_in, colors, unrank, slot_unrank_offset(s_in - 1), G, counts, ovf, per_vertex, csets,
-            cwords);
+    SlotGrid G = slot_grid(n, B, 1, 4);
+    if (!G.blocks) {
+        launch_fill_u64(counts, 0, uint64_t(B), s);
+        return;
+    }
+#define ROOT_M(M)                                                                                            \
+    k_slot_root<M><<<slot_dims(G.blocks), kSlotBlock, size_t(4) * cwords, s>>>(                              \
+        icnt, iflag, R_in, colors, unrank, slot_unrank_offset(s_in - 1), G, rpart, per_vertex, csets, cwords)
+    SLOT_BY_M(ROOT_M)
+#undef ROOT_M
+    k_slot_root_sum<<<unsigned(B), kSlotBlock, 0, s>>>(rpart, G.nbx, counts, ovf);
 }
+
+uint64_t slot_root_partials(int32_t n, int B) { return 2 * uint64_t(slot_grid(n, B, 1, 4).nbx) * uint64_t(B); }
 
 }  // namespace ccg
