@@ -233,6 +233,9 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
     // the child table of colouring b is exact (no count wrapped while it was
     // built) when b's overflow flag is still clear; then presence is count != 0
     const bool exact = LEAFCHILD || (v1 > v0 && ovf[b] == 0);
+    // colouring b's part of the child table (n * R_in < 2^32 slots)
+    const uint64_t* itab = LEAFCHILD ? nullptr : icnt + row0 * uint32_t(R_in);
+    const uint8_t* iftab = LEAFCHILD ? nullptr : iflag + row0 * uint32_t(R_in);
     const int64_t e_lo = v1 > v0 ? g.rp[v0] : 0, e_hi = v1 > v0 ? g.rp[v1] : 0;
     for (int64_t c0 = e_lo; c0 < e_hi; c0 += kEdgeChunk) {
         const int cn = int(min(int64_t(kEdgeChunk), e_hi - c0));
@@ -257,7 +260,7 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
             for (int j = 0; j < 4; j++) {
                 const int i = i0 + j * kSlotBlock + int(threadIdx.x);
                 if (i < cn) {
-                    s_y[i] = y[j];
+                    s_y[i] = LEAFCHILD ? y[j] : y[j] * uint32_t(R_in);  // the neighbour's row offset
                     s_c[i] = uint8_t(c[j]);
                 }
             }
@@ -278,28 +281,30 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
                 continue;
             }
             // four neighbours per round: their slot loads are in flight together
-            for (int i = a; i < z; i += 4) {
-                uint64_t idx[4], cv[4];
+            constexpr int NB = 4;
+            for (int i = a; i < z; i += NB) {
+                uint32_t idx[NB];
+                uint64_t cv[NB];
                 uint32_t ok = 0, fl = 0;
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
+                for (int j = 0; j < NB; j++) {
                     const int ii = min(i + j, z - 1);
                     const uint32_t cy = s_c[ii] & 0x7fu;
                     ok |= uint32_t((i + j < z) && ((Cx[u] >> cy) & 1u)) << j;
-                    idx[j] = (row0 + s_y[ii]) * uint32_t(R_in) + s_rank[bit_close(Cx[u], cy)];
+                    idx[j] = s_y[ii] + s_rank[bit_close(Cx[u], cy)];  // within colouring b's table
                 }
 #pragma unroll
-                for (int j = 0; j < 4; j++) cv[j] = ((ok >> j) & 1u) ? icnt[idx[j]] : 0;
+                for (int j = 0; j < NB; j++) cv[j] = ((ok >> j) & 1u) ? itab[idx[j]] : 0;
                 if (exact) {
                     // no count of this colouring has wrapped: present entries hold >= 1
 #pragma unroll
-                    for (int j = 0; j < 4; j++) fl |= uint32_t(cv[j] != 0) << j;
+                    for (int j = 0; j < NB; j++) fl |= uint32_t(cv[j] != 0) << j;
                 } else {
 #pragma unroll
-                    for (int j = 0; j < 4; j++) fl |= uint32_t(((ok >> j) & 1u) && iflag[idx[j]]) << j;
+                    for (int j = 0; j < NB; j++) fl |= uint32_t(((ok >> j) & 1u) && iftab[idx[j]]) << j;
                 }
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
+                for (int j = 0; j < NB; j++) {
                     if ((fl >> j) & 1u) {
                         sum[u] += cv[j];
                         over |= uint32_t(sum[u] < cv[j]);
@@ -635,13 +640,14 @@ std::vector<uint32_t> slot_split_tables() {
 int slot_join_m(int R_out, int R_y, int R_z, int nsplit) {
     if (R_out > kSlotBlock) return 0;
     const size_t upb = size_t(kSlotBlock / R_out), spl = size_t(nsplit) * R_out * 4;
-    for (int m = 4; m >= 1; m >>= 1)
+    for (int m = 8; m >= 1; m >>= 1)
         if (upb * m * size_t(R_y + R_z) * 9 + spl <= kSlotJoinLds) return m;
     return 0;
 }
 
 #define SLOT_BY_M(MACRO) \
     switch (G.m) {       \
+        case 8: MACRO(8); break; \
         case 4: MACRO(4); break; \
         case 2: MACRO(2); break; \
         default: MACRO(1); break; \
@@ -695,7 +701,7 @@ void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const
 void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int s_in, int32_t n, int B,
                       const uint8_t* colors, const uint16_t* unrank, uint64_t* rpart, uint64_t* counts, uint32_t* ovf,
                       uint64_t* per_vertex, uint32_t* csets, int cwords, hipStream_t s) {
-    SlotGrid G = slot_grid(n, B, 1, 4);
+    SlotGrid G = slot_grid(n, B, 1, 8);
     if (!G.blocks) {
         launch_fill_u64(counts, 0, uint64_t(B), s);
         return;
@@ -708,6 +714,6 @@ void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int 
     k_slot_root_sum<<<unsigned(B), kSlotBlock, 0, s>>>(rpart, G.nbx, counts, ovf);
 }
 
-uint64_t slot_root_partials(int32_t n, int B) { return 2 * uint64_t(slot_grid(n, B, 1, 4).nbx) * uint64_t(B); }
+uint64_t slot_root_partials(int32_t n, int B) { return 2 * uint64_t(slot_grid(n, B, 1, 8).nbx) * uint64_t(B); }
 
 }  // namespace ccg
