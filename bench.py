@@ -110,8 +110,8 @@ def cpu_baseline(workload, g, pat, k, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--queries", type=int, default=0, help="queries of workloads 4/5 (0: 256 / 120)")
     ap.add_argument("--budget", type=float, default=3e7, help="DP entries per table and colouring (workloads 4/5)")
