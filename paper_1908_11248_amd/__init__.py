@@ -33,7 +33,7 @@ EXPORTS = [
     "cc_graph_num_vertices", "cc_color", "cc_color_explicit", "cc_coloring_download", "cc_coloring_free",
     "cc_build_decomposition", "cc_decomp_export", "cc_decomp_import", "cc_decomp_width", "cc_decomp_free",
     "cc_count", "cc_count_by_vertex", "cc_enumerate", "cc_last_table_sizes", "cc_count_batch",
-    "cc_profile_enable", "cc_profile_read", "cc_decomp_describe",
+    "cc_profile_enable", "cc_profile_filter", "cc_profile_read", "cc_decomp_describe",
     "cc_set_batch_lanes", "cc_tune_batch", "cc_set_table_budget",
     "cc_server_start", "cc_server_submit", "cc_server_poll", "cc_server_wait", "cc_server_stop",
 ]
@@ -82,6 +82,7 @@ def lib():
             "cc_last_table_sizes": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
             "cc_count_batch": (ctypes.c_int, [P, P, I32, P, U32, P, P]),
             "cc_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
+            "cc_profile_filter": (ctypes.c_int, [P, ctypes.c_char_p]),
             "cc_profile_read": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
             "cc_decomp_describe": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
             "cc_set_batch_lanes": (ctypes.c_int, [P, I32]),
@@ -207,6 +208,10 @@ class Context(_Handle):
 
     def profile_enable(self, on: bool = True):
         _check(lib().cc_profile_enable(self.ptr, 1 if on else 0))
+
+    def profile_filter(self, name=None):
+        """Record only the kernel statistic `name` (None: every kernel)."""
+        _check(lib().cc_profile_filter(self.ptr, name.encode() if name else None))
 
     def profile_read(self):
         """{kernel name: (launches, total_ms, algo_bytes)}"""

@@ -429,6 +429,16 @@ int cc_profile_enable(cc_context* ctx, int enable) {
     });
 }
 
+int cc_profile_filter(cc_context* ctx, const char* name) {
+    return guarded([&] {
+        need(ctx != nullptr, CC_EINVAL, "ctx is NULL");
+        std::string n = name ? name : "";
+        need(n.size() < 32, CC_EINVAL, "kernel names are shorter than 32 characters");
+        ctx->main.prof.only = n;
+        for (auto& w : ctx->workers) w->prof.only = n;
+    });
+}
+
 int cc_profile_read(cc_context* ctx, cc_kernel_stat* stats, size_t cap, size_t* n) {
     return guarded([&] {
         need(ctx && n, CC_EINVAL, "bad arguments");

@@ -65,6 +65,7 @@ struct KernelStat {
 class Profiler {
    public:
     bool on = false;
+    std::string only;  // record only kernels of this name (empty: all)
     void reset();
     void begin(hipStream_t s, const char* name, double bytes);
     void end(hipStream_t s);
@@ -82,6 +83,7 @@ class Profiler {
     std::map<std::string, int> index_;
     std::vector<Pending> pending_;
     std::vector<hipEvent_t> pool_;
+    bool armed_ = false;  // begin() recorded the pending launch's first event
     hipEvent_t take();
 };
 

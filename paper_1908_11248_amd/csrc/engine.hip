@@ -10,6 +10,7 @@ ccg::Lane& cc_context::worker(size_t i) {
         workers.emplace_back(new ccg::Lane());
         workers.back()->create(nullptr);
         workers.back()->prof.on = main.prof.on;  // lanes made while profiling take part in it
+        workers.back()->prof.only = main.prof.only;
     }
     return *workers[i];
 }
@@ -101,7 +102,9 @@ void Profiler::reset() {
 }
 
 void Profiler::begin(hipStream_t s, const char* name, double bytes) {
-    if (!on) return;
+    armed_ = false;
+    if (!on || (!only.empty() && only != name)) return;
+    armed_ = true;
     auto it = index_.find(name);
     int id;
     if (it == index_.end()) {
@@ -117,7 +120,8 @@ void Profiler::begin(hipStream_t s, const char* name, double bytes) {
 }
 
 void Profiler::end(hipStream_t s) {
-    if (!on || pending_.empty()) return;
+    if (!on || !armed_ || pending_.empty()) return;
+    armed_ = false;
     hip_check(hipEventRecord(pending_.back().b, s), "hipEventRecord");
 }
 
@@ -376,12 +380,36 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     std::vector<SlotTab> tab(S);
     // per step: introduce entries, output entries, added up from per-block
     // partials (one scratch buffer, reused step after step on the stream)
-    uint64_t nsz_words = 2 * S, part_words = slot_root_partials(g.n, B);
+    // partials: one segment per step (summed by one launch at the end when
+    // the plan has at most kSlotSumSteps steps), then the root's
+    uint64_t nsz_words = 2 * S, part_words = 0, seg_max = 0;
     for (size_t i = 0; i < S; i++)
-        if (sz[i] > 0) part_words = std::max(part_words, 2 * slot_grid(g.n, B, binom(k - 1, sz[i] - 1), 1).blocks);
+        if (sz[i] > 0) {
+            const uint64_t w = 2 * slot_grid(g.n, B, binom(k - 1, sz[i] - 1), 1).blocks;
+            part_words += w;
+            seg_max = std::max(seg_max, w);
+        }
+    const bool one_sum = S <= size_t(kSlotSumSteps);
+    if (!one_sum) part_words = seg_max;
+    const uint64_t root_off = part_words;
+    part_words += slot_root_partials(g.n, B);
     uint64_t* nsz = X.alloc<uint64_t>(nsz_words);
     launch_fill_u64(nsz, 0, nsz_words, s);
-    uint64_t* part = X.alloc<uint64_t>(part_words);
+    uint64_t* part_base = X.alloc<uint64_t>(part_words);
+    uint64_t* part = part_base;  // this step's segment
+    SlotSums sums;
+    // after step i's kernel: record (or reduce) its partials, move to the next segment
+    auto partials_done = [&](size_t i, uint64_t blocks) {
+        if (one_sum) {
+            sums.step[sums.n] = uint32_t(i);
+            sums.off[sums.n] = uint64_t(part - part_base);
+            sums.blocks[sums.n] = blocks;
+            sums.n++;
+            part += 2 * blocks;
+        } else {
+            launch_slot_sum(part, blocks, nsz + 2 * i, s);
+        }
+    };
     const uint16_t* rank = ctx->slot_tables;
     const uint16_t* unrank = ctx->slot_tables + (1 << kSlotBits);
     const double csr = double(B) * (9.0 * g.n + 4.0 * g.m2);
@@ -422,7 +450,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                 launch_slot_edge(in.cnt, in.flag, in.R, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
                                  slot_unrank_offset(o.s - 1), o.cnt, o.flag, part, ovf, s);
             });
-            launch_slot_sum(part, G.blocks, nsz + 2 * i, s);
+            partials_done(i, G.blocks);
             tab[i + 1] = o;
             if (st.node >= 0) node_of.push_back({st.node, int(2 * i)});
             if (f.node >= 0) node_of.push_back({f.node, int(2 * i + 1)});
@@ -436,7 +464,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             SlotGrid G = slot_grid(g.n, B, 1, 4);
             X.timed("slot_leaf", double(units) * 9.0 + 8.0 * g.n,
                     [&] { launch_slot_leaf(G, g, rq.degree_mask ? st.degF : 0, o.cnt, o.flag, part, s); });
-            launch_slot_sum(part, G.blocks, nsz + 2 * i, s);
+            partials_done(i, G.blocks);
             tab[i] = o;
         } else {  // one-vertex join
             const SlotTab& y = tab[st.in0];
@@ -449,7 +477,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                 launch_slot_join(y.cnt, y.flag, y.R, z.cnt, z.flag, z.R, ctx->slot_splits + slot_split_offset(p, q),
                                  nsplit, binom(kSlotBits, p), G, o.cnt, o.flag, part, ovf, s);
             });
-            launch_slot_sum(part, G.blocks, nsz + 2 * i, s);
+            partials_done(i, G.blocks);
             tab[i] = o;
             done_with(st.in0);
             done_with(st.in1);
@@ -457,6 +485,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
         budgeted.push_back(int(2 * i + 1));
     }
+    if (one_sum) launch_slot_sums(part_base, sums, nsz, s);
     hip_check(hipGetLastError(), "kernel launch");
 
     const SlotTab& rc = tab[plan.root_child];
@@ -467,8 +496,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     uint32_t* csets = X.alloc<uint32_t>(uint64_t(B) * cwords);
     launch_fill_u32(csets, 0, uint64_t(B) * cwords, s);
     X.timed("slot_root", double(units) * 9.0 * rc.R, [&] {
-        launch_slot_root(rc.cnt, rc.flag, rc.R, rc.s, g.n, B, rq.colors, unrank, part, counts, ovf, pv, csets, cwords,
-                         s);
+        launch_slot_root(rc.cnt, rc.flag, rc.R, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv,
+                         csets, cwords, s);
     });
     out->counts.assign(B, 0);
     std::vector<uint32_t> of(B, 0);
@@ -501,7 +530,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     X.release(counts);
     X.release(pv);
     X.release(nsz);
-    X.release(part);
+    X.release(part_base);
     X.release(ovf);
     drop(tab[plan.root_child]);
     X.synced();

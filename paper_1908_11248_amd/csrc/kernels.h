@@ -197,6 +197,16 @@ int slot_unrank_offset(int popcount);
 // output entries) at part[2L], part[2L + 1]; launch_slot_sum adds those of
 // `blocks` blocks into out[0], out[1].
 void launch_slot_sum(const uint64_t* part, uint64_t blocks, uint64_t* out, hipStream_t s);
+// the partials of up to kSlotSumSteps steps, each in its own segment of part
+// (off[i] words from the start, blocks[i] blocks), added into nsz[2 step[i] ..]
+constexpr int kSlotSumSteps = 96;
+struct SlotSums {
+    uint32_t n = 0;
+    uint32_t step[kSlotSumSteps];
+    uint64_t off[kSlotSumSteps];
+    uint64_t blocks[kSlotSumSteps];
+};
+void launch_slot_sums(const uint64_t* part, const SlotSums& S, uint64_t* nsz, hipStream_t s);
 void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
                       hipStream_t s);
 void launch_slot_edge(const uint64_t* icnt, const uint8_t* iflag, int R_in, const SlotGrid& G, DevGraph g,

@@ -516,6 +516,35 @@ __global__ void __launch_bounds__(kSlotBlock) k_slot_sum(const uint64_t* __restr
     }
 }
 
+// the partials of several steps in one launch: blockIdx.y = step
+__global__ void __launch_bounds__(kSlotBlock) k_slot_sums(const uint64_t* __restrict__ part, SlotSums S, uint64_t* nsz) {
+    const int st = blockIdx.y;
+    const uint64_t* p = part + S.off[st];
+    const uint64_t blocks = S.blocks[st];
+    __shared__ uint64_t s_p[2][kSlotBlock / 64];
+    uint64_t a = 0, c = 0;
+    for (uint64_t i = uint64_t(blockIdx.x) * kSlotBlock + threadIdx.x; i < blocks; i += uint64_t(gridDim.x) * kSlotBlock) {
+        a += p[2 * i];
+        c += p[2 * i + 1];
+    }
+    a = wave_sum(a);
+    c = wave_sum(c);
+    if (__lane_id() == 0) {
+        s_p[0][threadIdx.x >> 6] = a;
+        s_p[1][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        uint64_t t = 0;
+        for (int i = 0; i < kSlotBlock / 64; i++) t += s_p[threadIdx.x][i];
+        if (t) atomicAdd((unsigned long long*)&nsz[2 * S.step[st] + threadIdx.x], (unsigned long long)t);
+    }
+}
+
+void launch_slot_sums(const uint64_t* part, const SlotSums& S, uint64_t* nsz, hipStream_t s) {
+    if (S.n) k_slot_sums<<<dim3(16, unsigned(S.n)), kSlotBlock, 0, s>>>(part, S, nsz);
+}
+
 void launch_slot_sum(const uint64_t* part, uint64_t blocks, uint64_t* out, hipStream_t s) {
     if (!blocks) return;
     const uint64_t g = std::min<uint64_t>(256, (blocks + kSlotBlock - 1) / kSlotBlock);
