@@ -603,10 +603,11 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     if (!keep && !rq.sparse_only && slot_plan(plan, fuse, &sz)) {
         const uint64_t units = uint64_t(B) * uint64_t(g.n);
         bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= ctx->arena.size() / 4;
-        // 32-bit block indices and slot offsets within one colouring's table
+        // 32-bit block indices; slot offsets within one colouring's table below
+        // 2^28 (they share a staged word with a colour)
         for (size_t i = 0; i < S && fits; i++)
             if (sz[i] > 0 && (slot_grid(g.n, B, binom(k - 1, sz[i] - 1), 1).blocks >= (uint64_t(1) << 32) ||
-                              uint64_t(g.n) * binom(k - 1, sz[i] - 1) >= (uint64_t(1) << 32)))
+                              uint64_t(g.n) * binom(k - 1, sz[i] - 1) >= (uint64_t(1) << 28)))
                 fits = false;
         if (fits) {
             try {

@@ -199,8 +199,10 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
             const uint16_t* __restrict__ unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
             uint32_t* ovf) {
     extern __shared__ uint16_t s_rank[];  // rank of every mask over k - 1 bits
-    __shared__ uint32_t s_y[kEdgeChunk];
-    __shared__ uint8_t s_c[kEdgeChunk];
+    // staged neighbours: LEAFCHILD: colour | passes-degree-mask << 7; otherwise
+    // the neighbour's row offset y R_in (< 2^28) | colour << 28.  Four entries
+    // of padding let a batch read past the end of a range.
+    __shared__ uint32_t s_nb[kEdgeChunk + 4];
     uint32_t b, v0, v1, jb, v, r;
     bool lane_ok;
     block_range(G, &b, &v0, &v1, &jb);
@@ -211,8 +213,9 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
     const uint64_t row0 = uint64_t(b) * n;
     int64_t rb[M], re[M];
     uint32_t Cx[M];
-    uint64_t sum[M], nin = 0;
-    uint32_t pres = 0, over = 0;  // bit i: the i-th vertex
+    uint64_t sum[M];
+    uint32_t cnt[M];  // child entries gathered per vertex: the introduce entries; > 0 iff present
+    uint32_t over = 0;
     const uint32_t mr = lane_ok ? unrank[uoff + r] : 0;
 #pragma unroll
     for (int i = 0; i < M; i++) {
@@ -220,6 +223,7 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
         rb[i] = re[i] = 0;
         Cx[i] = 0;
         sum[i] = 0;
+        cnt[i] = 0;
         if (lane_ok && vi < v1) {
             const int64_t a = g.rp[vi], z = g.rp[vi + 1];
             if (z - a >= degF_u) {
@@ -233,7 +237,8 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
     // the child table of colouring b is exact (no count wrapped while it was
     // built) when b's overflow flag is still clear; then presence is count != 0
     const bool exact = LEAFCHILD || (v1 > v0 && ovf[b] == 0);
-    // colouring b's part of the child table (n * R_in < 2^32 slots)
+    const uint32_t rmask = (1u << (k - 1)) - 1u;  // keeps rank reads of masked-out lanes in the table
+    // colouring b's part of the child table (n * R_in < 2^28 slots)
     const uint64_t* itab = LEAFCHILD ? nullptr : icnt + row0 * uint32_t(R_in);
     const uint8_t* iftab = LEAFCHILD ? nullptr : iflag + row0 * uint32_t(R_in);
     const int64_t e_lo = v1 > v0 ? g.rp[v0] : 0, e_hi = v1 > v0 ? g.rp[v1] : 0;
@@ -259,10 +264,7 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int i = i0 + j * kSlotBlock + int(threadIdx.x);
-                if (i < cn) {
-                    s_y[i] = LEAFCHILD ? y[j] : y[j] * uint32_t(R_in);  // the neighbour's row offset
-                    s_c[i] = uint8_t(c[j]);
-                }
+                if (i < cn) s_nb[i] = LEAFCHILD ? c[j] : y[j] * uint32_t(R_in) | (c[j] << 28);
             }
         }
         __syncthreads();
@@ -270,50 +272,53 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
         for (int u = 0; u < M; u++) {
             const int a = int(max(rb[u], c0) - c0), z = int(min(re[u], c0 + cn) - c0);
             if (LEAFCHILD) {
+                // leaf child: one entry of count 1 per neighbour of a wanted colour
+                uint32_t hits = 0;
                 for (int i = a; i < z; i++) {
-                    const uint32_t c = s_c[i];
-                    if (((Cx[u] >> (c & 0x7fu)) & 1u) && (c & 0x80u)) {
-                        sum[u] += 1;
-                        nin++;
-                        pres |= 1u << u;
-                    }
+                    const uint32_t c = s_nb[i];
+                    hits += (Cx[u] >> (c & 0x7fu)) & (c >> 7);
                 }
+                cnt[u] += hits;
                 continue;
             }
-            // four neighbours per round: their slot loads are in flight together
+            // four neighbours per round: their slot loads are in flight together.
+            // Absent child entries read as 0, so every loaded count is added.
             constexpr int NB = 4;
             for (int i = a; i < z; i += NB) {
                 uint32_t idx[NB];
                 uint64_t cv[NB];
-                uint32_t ok = 0, fl = 0;
+                bool ok[NB];
 #pragma unroll
                 for (int j = 0; j < NB; j++) {
-                    const int ii = min(i + j, z - 1);
-                    const uint32_t cy = s_c[ii] & 0x7fu;
-                    ok |= uint32_t((i + j < z) && ((Cx[u] >> cy) & 1u)) << j;
-                    idx[j] = s_y[ii] + s_rank[bit_close(Cx[u], cy)];  // within colouring b's table
+                    const uint32_t e = s_nb[i + j];  // past z: padding or other vertices, masked by ok
+                    const uint32_t cy = e >> 28;
+                    ok[j] = (i + j < z) && ((Cx[u] >> cy) & 1u);
+                    // slot offset within colouring b's table, in bytes (< 2^31)
+                    idx[j] = ((e & 0x0fffffffu) + s_rank[bit_close(Cx[u], cy) & rmask]) << 3;
                 }
 #pragma unroll
-                for (int j = 0; j < NB; j++) cv[j] = ((ok >> j) & 1u) ? itab[idx[j]] : 0;
+                for (int j = 0; j < NB; j++)
+                    cv[j] = ok[j] ? *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(itab) + idx[j]) : 0;
                 if (exact) {
                     // no count of this colouring has wrapped: present entries hold >= 1
 #pragma unroll
-                    for (int j = 0; j < NB; j++) fl |= uint32_t(cv[j] != 0) << j;
+                    for (int j = 0; j < NB; j++) cnt[u] += cv[j] != 0;
                 } else {
 #pragma unroll
-                    for (int j = 0; j < NB; j++) fl |= uint32_t(((ok >> j) & 1u) && iftab[idx[j]]) << j;
+                    for (int j = 0; j < NB; j++) cnt[u] += ok[j] && iftab[idx[j] >> 3] != 0;
                 }
 #pragma unroll
-                for (int j = 0; j < NB; j++) {
-                    if ((fl >> j) & 1u) {
-                        sum[u] += cv[j];
-                        over |= uint32_t(sum[u] < cv[j]);
-                        nin++;
-                        pres |= 1u << u;
-                    }
-                }
+                for (int j = 0; j < NB; j++) over |= uint32_t(__builtin_add_overflow(sum[u], cv[j], &sum[u]));
             }
         }
+    }
+    uint32_t npres = 0;
+    uint64_t nin = 0;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        if (LEAFCHILD) sum[i] = cnt[i];
+        nin += cnt[i];
+        npres += cnt[i] != 0;
     }
 #pragma unroll
     for (int i = 0; i < M; i++) {
@@ -321,11 +326,11 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
         if (lane_ok && vi < v1) {
             const uint64_t o = (row0 + vi) * uint32_t(G.R) + r;
             ocnt[o] = sum[i];
-            oflag[o] = (pres >> i) & 1u;
+            oflag[o] = cnt[i] != 0;
         }
     }
     if (over) atomicOr(&ovf[b], 1u);
-    count_entries(__popc(pres), nin, part, G.blocks);
+    count_entries(npres, nin, part, G.blocks);
 }
 
 // Join on a one-vertex bag (Sec. 3, join nodes): output slot (b, v, C) sums
