@@ -426,20 +426,56 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         X.release(t.flag);
         t = SlotTab();
     };
+    // Identical subtrees (same shape, same degree masks) give identical
+    // tables: a step whose signature was seen reuses that table.  phys maps a
+    // step to the step that holds its table, refs counts that table's
+    // remaining readers.
+    std::vector<std::string> sig(S);
+    std::map<std::string, size_t> seen;
+    std::vector<size_t> phys(S);
+    std::vector<int> refs(S, 0);
+    for (size_t i = 0; i < S; i++) phys[i] = i;
+    refs[plan.root_child] = 1;  // the root reads it last
     auto done_with = [&](int in) {
-        if (in >= 0 && !virt[in] && --uses[in] == 0) drop(tab[in]);
+        if (in < 0 || virt[in]) return;
+        const size_t t = phys[in];
+        if (--refs[t] == 0) drop(tab[t]);
+    };
+    // true when an earlier step's table, still held, can serve step i (and
+    // records the alias); otherwise step i becomes the holder of its signature
+    auto reuse = [&](size_t i) {
+        auto it = seen.find(sig[i]);
+        if (it == seen.end() || refs[phys[it->second]] == 0) {  // new, or already released
+            seen[sig[i]] = i;
+            refs[i] += uses[i];
+            return false;
+        }
+        phys[i] = phys[it->second];
+        refs[phys[i]] += uses[i] + (i == size_t(plan.root_child) ? 1 : 0);
+        tab[i] = tab[phys[i]];
+        return true;
     };
     std::vector<std::pair<int, int>> node_of;  // (TD node, nsz index)
     std::vector<int> budgeted;                 // nsz indices of tables under the budget
     for (size_t i = 0; i < S; i++) {
         const Step& st = plan.steps[i];
         if (virt[i]) {
+            sig[i] = "V" + std::to_string(rq.degree_mask ? st.degF : 0);
             if (st.node >= 0)
                 out->node_sizes[st.node] = int64_t(B) * rq.g->count_deg_at_least(rq.degree_mask ? st.degF : 0);
             continue;
         }
         if (fuse[i]) {
             const Step& f = plan.steps[i + 1];
+            sig[i + 1] = "E(" + sig[st.in0] + "," + std::to_string(rq.degree_mask ? st.degF : 0) + ")";
+            if (reuse(i + 1)) {
+                const size_t t = phys[i + 1];  // its fused pair is steps t - 1, t
+                if (st.node >= 0) node_of.push_back({st.node, int(2 * (t - 1))});
+                if (f.node >= 0) node_of.push_back({f.node, int(2 * (t - 1) + 1)});
+                done_with(st.in0);
+                i++;
+                continue;
+            }
             const bool leafc = virt[st.in0] != 0;
             const SlotTab in = leafc ? SlotTab() : tab[st.in0];
             SlotTab o = make(sz[i + 1]);
@@ -457,6 +493,18 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             budgeted.push_back(int(2 * i + 1));
             done_with(st.in0);
             i++;
+            continue;
+        }
+        if (st.kind == S_LEAF)
+            sig[i] = "L" + std::to_string(rq.degree_mask ? st.degF : 0);
+        else
+            sig[i] = "J(" + std::min(sig[st.in0], sig[st.in1]) + "," + std::max(sig[st.in0], sig[st.in1]) + ")";
+        if (reuse(i)) {
+            if (st.node >= 0) node_of.push_back({st.node, int(2 * phys[i] + 1)});
+            if (st.kind == S_JOIN) {
+                done_with(st.in0);
+                done_with(st.in1);
+            }
             continue;
         }
         if (st.kind == S_LEAF) {
