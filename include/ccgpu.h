@@ -167,9 +167,10 @@ typedef struct {
 } cc_kernel_stat;
 int cc_profile_enable(cc_context *ctx, int enable);
 /* Restricts recording to the kernel of the given statistic name (as in
- * cc_kernel_stat.name), so that the event pairs around other launches do
- * not add to a timed run; NULL or "" records every kernel again. */
-int cc_profile_filter(cc_context *ctx, const char *name);
+ * cc_kernel_stat.name), and to one launch in `every` of it (0 or 1: all), so
+ * that event pairs add little to a timed run; NULL or "" records every
+ * kernel again. */
+int cc_profile_filter(cc_context *ctx, const char *name, uint32_t every);
 int cc_profile_read(cc_context *ctx, cc_kernel_stat *stats, size_t cap, size_t *n);
 
 /* ---------------------------------------------------------------------- */

@@ -82,7 +82,7 @@ def lib():
             "cc_last_table_sizes": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
             "cc_count_batch": (ctypes.c_int, [P, P, I32, P, U32, P, P]),
             "cc_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
-            "cc_profile_filter": (ctypes.c_int, [P, ctypes.c_char_p]),
+            "cc_profile_filter": (ctypes.c_int, [P, ctypes.c_char_p, U32]),
             "cc_profile_read": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
             "cc_decomp_describe": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
             "cc_set_batch_lanes": (ctypes.c_int, [P, I32]),
@@ -209,9 +209,10 @@ class Context(_Handle):
     def profile_enable(self, on: bool = True):
         _check(lib().cc_profile_enable(self.ptr, 1 if on else 0))
 
-    def profile_filter(self, name=None):
-        """Record only the kernel statistic `name` (None: every kernel)."""
-        _check(lib().cc_profile_filter(self.ptr, name.encode() if name else None))
+    def profile_filter(self, name=None, every=1):
+        """Record only the kernel statistic `name`, one launch in `every`
+        (None: every kernel)."""
+        _check(lib().cc_profile_filter(self.ptr, name.encode() if name else None, int(every)))
 
     def profile_read(self):
         """{kernel name: (launches, total_ms, algo_bytes)}"""

@@ -429,13 +429,21 @@ int cc_profile_enable(cc_context* ctx, int enable) {
     });
 }
 
-int cc_profile_filter(cc_context* ctx, const char* name) {
+int cc_profile_filter(cc_context* ctx, const char* name, uint32_t every) {
     return guarded([&] {
         need(ctx != nullptr, CC_EINVAL, "ctx is NULL");
         std::string n = name ? name : "";
         need(n.size() < 32, CC_EINVAL, "kernel names are shorter than 32 characters");
-        ctx->main.prof.only = n;
-        for (auto& w : ctx->workers) w->prof.only = n;
+        for (ccg::Lane* l : {&ctx->main}) {
+            l->prof.only = n;
+            l->prof.every = every ? every : 1;
+            l->prof.seen_ = 0;
+        }
+        for (auto& w : ctx->workers) {
+            w->prof.only = n;
+            w->prof.every = every ? every : 1;
+            w->prof.seen_ = 0;
+        }
     });
 }
 

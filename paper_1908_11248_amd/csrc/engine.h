@@ -65,7 +65,9 @@ struct KernelStat {
 class Profiler {
    public:
     bool on = false;
-    std::string only;  // record only kernels of this name (empty: all)
+    std::string only;     // record only kernels of this name (empty: all)
+    uint32_t every = 1;   // of those, one launch in `every`
+    uint32_t seen_ = 0;
     void reset();
     void begin(hipStream_t s, const char* name, double bytes);
     void end(hipStream_t s);

@@ -11,6 +11,7 @@ ccg::Lane& cc_context::worker(size_t i) {
         workers.back()->create(nullptr);
         workers.back()->prof.on = main.prof.on;  // lanes made while profiling take part in it
         workers.back()->prof.only = main.prof.only;
+        workers.back()->prof.every = main.prof.every;
     }
     return *workers[i];
 }
@@ -104,6 +105,7 @@ void Profiler::reset() {
 void Profiler::begin(hipStream_t s, const char* name, double bytes) {
     armed_ = false;
     if (!on || (!only.empty() && only != name)) return;
+    if (every > 1 && (seen_++ % every) != 0) return;
     armed_ = true;
     auto it = index_.find(name);
     int id;
