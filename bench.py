@@ -19,6 +19,7 @@ import argparse
 import concurrent.futures as cf
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -157,8 +158,14 @@ def main():
     if not prof_all:
         raise SystemExit("no kernel timings were recorded")
     dom_name = max(prof_all.items(), key=lambda kv: kv[1][1])[0]
+    # one launch in `every`, with `every` coprime to the launches per step so
+    # that the sample visits every launch site of the step
+    per_step = max(1, prof_all[dom_name][0] // max(args.warmup, 1))
+    every = 4
+    while math.gcd(every, per_step) != 1:
+        every += 1
     ctx.profile_enable(True)
-    ctx.profile_filter(dom_name, 4)  # one launch in four: a sample with little event overhead
+    ctx.profile_filter(dom_name, every)
     entries = 0
     t0 = time.perf_counter()
     for i in range(args.steps):

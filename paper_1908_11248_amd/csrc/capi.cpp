@@ -144,6 +144,19 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
         std::vector<int32_t> src(m2);
         for (int32_t v = 0; v < n; v++)
             for (int64_t e = rp[v]; e < rp[v + 1]; e++) src[e] = v;
+        // edge set for adjacency tests: 4m cells or more, a power of two
+        uint64_t cells = 16;
+        while (cells < uint64_t(std::max<int64_t>(m2, 1)) * 2) cells <<= 1;
+        std::vector<uint64_t> eh(cells, kEdgeEmpty);
+        for (int32_t v = 0; v < n; v++)
+            for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+                const uint32_t w = uint32_t(col[e]);
+                if (w <= uint32_t(v)) continue;  // each edge once
+                const uint64_t key = edge_key(uint32_t(v), w);
+                uint64_t h = edge_cell(key, cells - 1);
+                while (eh[h] != kEdgeEmpty) h = (h + 1) & (cells - 1);
+                eh[h] = key;
+            }
         std::vector<int32_t> heavy;
         for (int32_t v = 0; v < n; v++)
             if (rp[v + 1] - rp[v] > kHeavyDegree) heavy.push_back(v);
@@ -159,6 +172,9 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
             hip_check(hipMalloc(&g->rp, 8 * size_t(n + 1)), "hipMalloc");
             hip_check(hipMalloc(&g->col, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
             hip_check(hipMalloc(&g->esrc, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
+            hip_check(hipMalloc(&g->ehash, 8 * cells), "hipMalloc");
+            hip_check(hipMemcpy(g->ehash, eh.data(), 8 * cells, hipMemcpyHostToDevice), "hipMemcpy");
+            g->ehmask = cells - 1;
             hip_check(hipMalloc(&g->heavy, 4 * std::max<size_t>(heavy.size(), 1)), "hipMalloc");
             g->nheavy = int32_t(heavy.size());
             if (!heavy.empty())
@@ -182,6 +198,7 @@ void cc_graph_free(cc_graph* g) {
     if (g->col) (void)hipFree(g->col);
     if (g->esrc) (void)hipFree(g->esrc);
     if (g->heavy) (void)hipFree(g->heavy);
+    if (g->ehash) (void)hipFree(g->ehash);
     delete g;
 }
 

@@ -48,27 +48,17 @@ __device__ __forceinline__ K shr(K key, int sh) {
 
 __device__ __forceinline__ int64_t gdeg(const DevGraph& g, uint32_t v) { return g.rp[v + 1] - g.rp[v]; }
 
-// {a, b} in E(G): binary search in the shorter of the two sorted rows
+// {a, b} in E(G): a probe of the edge set (usually one cell)
 __device__ __forceinline__ bool has_edge(const DevGraph& g, uint32_t a, uint32_t b) {
-    int64_t la = g.rp[a], ha = g.rp[a + 1], lb = g.rp[b], hb = g.rp[b + 1];
-    int64_t lo, hi;
-    int32_t t;
-    if (ha - la <= hb - lb) {
-        lo = la;
-        hi = ha;
-        t = int32_t(b);
-    } else {
-        lo = lb;
-        hi = hb;
-        t = int32_t(a);
+    if (a == b) return false;
+    const uint64_t key = edge_key(a, b);
+    uint64_t h = edge_cell(key, g.ehmask);
+    for (;;) {
+        const uint64_t x = g.eh[h];
+        if (x == key) return true;
+        if (x == kEdgeEmpty) return false;
+        h = (h + 1) & g.ehmask;
     }
-    int64_t end = hi;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (g.col[mid] < t) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo < end && g.col[lo] == t;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {

@@ -125,10 +125,12 @@ struct cc_graph {
     int32_t* esrc = nullptr;
     int32_t* heavy = nullptr;
     int32_t nheavy = 0;
+    uint64_t* ehash = nullptr;  // edge set (kernels.h edge_key / edge_cell)
+    uint64_t ehmask = 0;
     std::vector<int64_t> sorted_deg;  // host copy, ascending
     // vertices with degree >= d
     int64_t count_deg_at_least(int64_t d) const;
-    ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc, heavy, nheavy}; }
+    ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc, heavy, nheavy, ehash, ehmask}; }
 };
 
 struct cc_coloring {

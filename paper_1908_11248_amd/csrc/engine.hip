@@ -295,7 +295,7 @@ void sort_pairs(Exec& X, uint64_t* keys, uint64_t* vals, uint64_t n, uint64_t nk
     uint64_t* k2 = X.alloc<uint64_t>(n);
     uint64_t* v2 = X.alloc<uint64_t>(n);
     void* tmp = X.raw(radix_tmp_bytes(n));
-    radix_sort(keys, vals, k2, v2, n, 1, bits, tmp, X.s);
+    radix_sort(keys, vals, k2, v2, n, 1, bits, 0, tmp, X.s);
     X.release(tmp);
     X.release(v2);
     X.release(k2);
@@ -931,6 +931,24 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 case S_RESORT: {
                     const DevTable& in = tab[st.in0];
                     o = X.table(lo, in.n);
+                    // The input (introduce at the last column) is sorted by
+                    // (colouring, its columns, colour set).  When only that last
+                    // column moves, to output position p, a stable sort on the
+                    // key bits of (colouring, columns 0..p) gives the order.
+                    int sort_lo = 0;
+                    {
+                        int p = -1;
+                        bool moved_only = true;
+                        for (int j = 0, prev = -1; j < lo.b; j++) {
+                            if (st.perm[j] == lo.b - 1) {
+                                p = j;
+                            } else {
+                                moved_only &= st.perm[j] > prev;
+                                prev = st.perm[j];
+                            }
+                        }
+                        if (p >= 0 && moved_only) sort_lo = lo.kb + (lo.b - 1 - p) * lo.vb;
+                    }
                     if (in.n && links) {
                         // sort (key, input position), then gather the counts
                         uint64_t* idx = X.alloc<uint64_t>(in.n);
@@ -940,7 +958,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         void* kb2 = X.raw(in.n * lo.key_bytes());
                         uint64_t* vb2 = X.alloc<uint64_t>(in.n);
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
-                        radix_sort(o.keys, idx, kb2, vb2, in.n, lo.kw(), lo.bits(), tmp, s);
+                        radix_sort(o.keys, idx, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s);
                         X.release(tmp);
                         X.release(vb2);
                         X.release(kb2);
@@ -953,7 +971,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         uint64_t* vb2 = X.alloc<uint64_t>(in.n);
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
                         X.timed("radix_sort", double(in.n) * (lo.key_bytes() + 8) * 2,
-                                [&] { radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), tmp, s); });
+                                [&] { radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s); });
                         X.release(tmp);
                         X.release(vb2);
                         X.release(kb2);
@@ -1161,7 +1179,7 @@ void run_enumerate(cc_context* ctx, Lane& lane, const cc_graph* g, const uint8_t
         uint64_t* v2 = (uint64_t*)alloc(std::max<uint64_t>(R, 1) * 8);
         void* tmp = alloc(radix_tmp_bytes(R));
         lane.prof.begin(s, "row_sort", double(R) * (rkb + 8) * 2);
-        radix_sort(keys, vals, k2, v2, R, rkw, rbits, tmp, s);
+        radix_sort(keys, vals, k2, v2, R, rkw, rbits, 0, tmp, s);
         lane.prof.end(s);
         const uint64_t m = std::min(R, cap);
         std::vector<uint64_t> hrows(m * (rkw == 1 ? 1 : 2));

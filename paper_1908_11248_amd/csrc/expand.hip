@@ -121,20 +121,57 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
             uint64_t seg = seg0, grp = grp0;
             SegState st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
             grp0 = grp;
-            for (uint64_t t = t0; t < t1; t++) {
-                if (soff[seg + 1] <= t) {
-                    do seg++;
-                    while (soff[seg + 1] <= t);
-                    st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
+            // four items per round: their key loads and edge-set probes are in
+            // flight together
+            for (uint64_t tb = t0; tb < t1; tb += 4) {
+                uint64_t idx[4];
+                uint32_t vv[4], cb4[4], ok = 0;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint64_t t = tb + j;
+                    idx[j] = st.base;
+                    vv[j] = st.v;
+                    cb4[j] = ~0u;
+                    if (t < t1) {
+                        if (soff[seg + 1] <= t) {
+                            do seg++;
+                            while (soff[seg + 1] <= t);
+                            st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
+                        }
+                        idx[j] = st.base + (t - soff[seg]);
+                        vv[j] = st.v;
+                        cb4[j] = st.cb;
+                    }
                 }
-                KI k = keys[st.base + (t - soff[seg])];
-                if (kset(k, L) & st.cb) continue;
-                bool ok = true;
-                for (int c = 0; c < a.nchk && ok; c++)
-                    if (PULL || a.chk[c] >= a.pos) ok = has_edge(g, kcol(k, L, a.chk[c]), st.v);
-                if (!ok) continue;
-                pass |= 1u << (t - t0);
-                n_pass++;
+                KI kk[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) kk[j] = keys[idx[j]];
+#pragma unroll
+                for (int j = 0; j < 4; j++) ok |= uint32_t(!(kset(kk[j], L) & cb4[j])) << j;
+                for (int c = 0; c < a.nchk; c++) {
+                    if (!(PULL || a.chk[c] >= a.pos)) continue;
+                    uint64_t key[4], h[4], x[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const uint32_t u = kcol(kk[j], L, a.chk[c]);
+                        key[j] = edge_key(u, vv[j]);
+                        h[j] = edge_cell(key[j], g.ehmask);
+                        if (u == vv[j]) ok &= ~(1u << j);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; j++) x[j] = ((ok >> j) & 1u) ? g.eh[h[j]] : key[j];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if (!((ok >> j) & 1u)) continue;
+                        while (x[j] != key[j] && x[j] != kEdgeEmpty) {  // rare: probe on
+                            h[j] = (h[j] + 1) & g.ehmask;
+                            x[j] = g.eh[h[j]];
+                        }
+                        if (x[j] != key[j]) ok &= ~(1u << j);
+                    }
+                }
+                pass |= ok << (tb - t0);
+                n_pass += __popc(ok);
             }
         }
         uint64_t total;
@@ -147,26 +184,55 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
         uint64_t o = toff[tile] + my;
         uint64_t seg = seg0, grp = grp0;
         SegState st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
-        for (uint64_t t = t0; t < t1; t++) {
-            if (!(pass >> (t - t0) & 1u)) continue;
-            if (soff[seg + 1] <= t) {
-                do seg++;
-                while (soff[seg + 1] <= t);
-                st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
+        // four surviving items per round: their loads are in flight together
+        uint32_t rest = pass;
+        while (rest) {
+            uint64_t idx[4];
+            uint32_t vv[4], bid4[4], cb4[4];
+            int nb = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                idx[j] = st.base;
+                vv[j] = st.v;
+                bid4[j] = st.bid;
+                cb4[j] = st.cb;
+                if (rest) {
+                    const uint64_t t = t0 + uint64_t(__ffs(rest) - 1);
+                    rest &= rest - 1u;
+                    if (soff[seg + 1] <= t) {
+                        do seg++;
+                        while (soff[seg + 1] <= t);
+                        st = seg_state<KI, PULL>(seg, &grp, keys, L, gstart, woff, rstart, g, colors, a);
+                    }
+                    idx[j] = st.base + (t - soff[seg]);
+                    vv[j] = st.v;
+                    bid4[j] = st.bid;
+                    cb4[j] = st.cb;
+                    nb = j + 1;
+                }
             }
-            uint64_t i = st.base + (t - soff[seg]);
-            KI k = keys[i];
-            uint32_t cols[5];
-            if (PULL) {
-                cols[0] = st.v;
-                for (int j = 1; j < LO.b; j++) cols[j] = kcol(k, L, j - 1);
-            } else {
-                for (int j = 0, s2 = 0; j < LO.b; j++) cols[j] = (j == a.pos) ? st.v : kcol(k, L, s2++);
+            KI kk[4];
+            uint64_t cv[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                kk[j] = keys[idx[j]];
+                cv[j] = cnt[idx[j]];
             }
-            okeys[o] = kpack<KO>(st.bid, cols, LO.b, kset(k, L) | st.cb, LO);
-            ocnt[o] = cnt[i];
-            if (osrc) osrc[o] = i;
-            o++;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (j >= nb) break;
+                uint32_t cols[5];
+                if (PULL) {
+                    cols[0] = vv[j];
+                    for (int c = 1; c < LO.b; c++) cols[c] = kcol(kk[j], L, c - 1);
+                } else {
+                    for (int c = 0, s2 = 0; c < LO.b; c++) cols[c] = (c == a.pos) ? vv[j] : kcol(kk[j], L, s2++);
+                }
+                okeys[o] = kpack<KO>(bid4[j], cols, LO.b, kset(kk[j], L) | cb4[j], LO);
+                ocnt[o] = cv[j];
+                if (osrc) osrc[o] = idx[j];
+                o++;
+            }
         }
     }
 }

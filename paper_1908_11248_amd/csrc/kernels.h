@@ -38,7 +38,24 @@ struct DevGraph {
     const int32_t* esrc;  // [2m], source vertex of every stored edge
     const int32_t* heavy; // vertices of degree > kHeavyDegree, ascending
     int32_t nheavy;
+    const uint64_t* eh;   // edge set: open addressing, linear probing, kEdgeEmpty in free cells
+    uint64_t ehmask;      // cells - 1 (a power of two at least four times m)
 };
+
+// edge-set key of {a, b} (a != b): smaller id in the high half
+constexpr uint64_t kEdgeEmpty = ~uint64_t(0);
+__host__ __device__ inline uint64_t edge_key(uint32_t a, uint32_t b) {
+    return a < b ? (uint64_t(a) << 32) | b : (uint64_t(b) << 32) | a;
+}
+// cell of a key: the 64-bit finaliser of MurmurHash3 (Appleby)
+__host__ __device__ inline uint64_t edge_cell(uint64_t key, uint64_t mask) {
+    key ^= key >> 33;
+    key *= 0xff51afd7ed558ccdull;
+    key ^= key >> 33;
+    key *= 0xc4ceb9fe1a85ec53ull;
+    key ^= key >> 33;
+    return key & mask;
+}
 
 constexpr int kHeavyDegree = 64;
 
@@ -118,10 +135,10 @@ void launch_join_emit(const DevTable& y, const DevTable& z, const uint64_t* gsta
 // column permutation (out column j <- in column perm[j]) into tmp, then sort
 // index_values: the values become the input positions instead of the counts
 void launch_permute(const DevTable& in, const int* perm, DevTable& out, bool index_values, hipStream_t s);
-// LSD radix sort of (keys, vals) on the low `bits` bits; result in the a-buffers
+// stable LSD radix sort of (keys, vals) on key bits [lo, bits); result in the a-buffers
 size_t radix_tmp_bytes(uint64_t n);
-void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw,
-                int bits, void* tmp, hipStream_t s);
+void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, int lo,
+                void* tmp, hipStream_t s);
 
 // fused introduce (pull, one-column child) + forget of the child's column
 // (fused.hip); in == nullptr means the child is a leaf synthesised from the

@@ -619,21 +619,21 @@ size_t radix_tmp_bytes(uint64_t n) {
     return h * 4 + (h + 1) * 8 + scan_tmp_bytes(h) + 256;
 }
 
-void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, void* tmp,
-                hipStream_t s) {
-    if (n <= 1 || bits <= 0) return;
+void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, int lo,
+                void* tmp, hipStream_t s) {
+    if (n <= 1 || bits <= lo) return;
     uint64_t nblk = (n + kRadixTile - 1) / kRadixTile;
     uint64_t h = 256 * nblk;
     uint32_t* hist = (uint32_t*)tmp;
     uint64_t* offs = (uint64_t*)((char*)tmp + ((h * 4 + 255) / 256) * 256);
     uint64_t* stmp = offs + h + 1;
-    int passes = (bits + 7) / 8;
+    int passes = (bits - lo + 7) / 8;
     void* src_k = keys_a;
     uint64_t* src_v = vals_a;
     void* dst_k = keys_b;
     uint64_t* dst_v = vals_b;
     for (int p = 0; p < passes; p++) {
-        int shift = 8 * p;
+        int shift = lo + 8 * p;
         if (kw == 1) {
             k_radix_hist<uint64_t><<<unsigned(nblk), kBlock, 0, s>>>((const uint64_t*)src_k, n, shift, hist, nblk);
         } else {
