@@ -765,8 +765,9 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     X.release(slen);
                     uint64_t tiles = expand_tiles(T);
                     uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                    uint16_t* pbits = X.alloc<uint16_t>(expand_pass_words(T));
                     X.timed("push_count", double(T) * in.lay.key_bytes(), [&] {
-                        launch_expand_count(false, in, gstart, woff, G, nullptr, soff, W, T, g, rq.colors, ia, tcount, s);
+                        launch_expand_count(false, in, gstart, woff, G, nullptr, soff, W, T, g, rq.colors, ia, tcount, pbits, s);
                     });
                     uint64_t* toff;
                     uint64_t N = X.scan(tcount, tiles, &toff);
@@ -775,9 +776,10 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     if (links) lk[i].src = X.alloc<uint64_t>(N);
                     if (N)
                         X.timed("push_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8), [&] {
-                            launch_expand_emit(false, in, gstart, woff, G, nullptr, soff, W, T, g, rq.colors, ia, toff, o,
+                            launch_expand_emit(false, in, gstart, woff, G, nullptr, soff, W, T, g, rq.colors, ia, toff, pbits, o,
                                                lk[i].src, s);
                         });
+                    X.release(pbits);
                     X.release(toff);
                     X.release(soff);
                     X.release(woff);
@@ -804,8 +806,9 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     X.release(slen);
                     uint64_t tiles = expand_tiles(T);
                     uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                    uint16_t* pbits = X.alloc<uint16_t>(expand_pass_words(T));
                     X.timed("pull_count", double(T) * in.lay.key_bytes(), [&] {
-                        launch_expand_count(true, in, nullptr, nullptr, 0, rstart, soff, S, T, g, rq.colors, ia, tcount, s);
+                        launch_expand_count(true, in, nullptr, nullptr, 0, rstart, soff, S, T, g, rq.colors, ia, tcount, pbits, s);
                     });
                     uint64_t* toff;
                     uint64_t N = X.scan(tcount, tiles, &toff);
@@ -814,9 +817,10 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     if (links) lk[i].src = X.alloc<uint64_t>(N);
                     if (N)
                         X.timed("pull_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8), [&] {
-                            launch_expand_emit(true, in, nullptr, nullptr, 0, rstart, soff, S, T, g, rq.colors, ia, toff, o,
+                            launch_expand_emit(true, in, nullptr, nullptr, 0, rstart, soff, S, T, g, rq.colors, ia, toff, pbits, o,
                                                lk[i].src, s);
                         });
+                    X.release(pbits);
                     X.release(toff);
                     X.release(soff);
                     X.release(rstart);

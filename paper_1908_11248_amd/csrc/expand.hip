@@ -90,7 +90,8 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
          const uint64_t* __restrict__ woff, uint64_t G, const uint64_t* __restrict__ rstart,
          const uint64_t* __restrict__ soff, uint64_t S, uint64_t T, DevGraph g, const uint8_t* __restrict__ colors,
          IntroArgs a, uint32_t* tcount, const uint64_t* __restrict__ toff, KO* okeys, uint64_t* ocnt, Lay LO,
-         uint64_t* osrc) {
+         uint64_t* osrc, uint16_t* pbits) {
+    // pbits: the count pass stores every thread's survivor bits, the emit pass reads them
     __shared__ uint64_t bounds[4];  // segment and group ranges of the tile
     const uint64_t tiles = (T + kExpTile - 1) / kExpTile;
     for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -115,7 +116,12 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
         uint32_t pass = 0;  // bit j: item t0 + j survives
         uint32_t n_pass = 0;
         uint64_t seg0 = 0, grp0 = g_lo;
-        if (t0 < tile1) {
+        if (t0 < tile1 && EMIT) {
+            seg0 = upper_bound_u64(soff, s_lo, s_hi + 1, t0) - 1;
+            if (!PULL) grp0 = upper_bound_u64(woff, g_lo, g_hi + 1, seg0) - 1;
+            pass = pbits[tile * kBlock + threadIdx.x];
+            n_pass = __popc(pass);
+        } else if (t0 < tile1) {
             seg0 = upper_bound_u64(soff, s_lo, s_hi + 1, t0) - 1;
             if (!PULL) grp0 = upper_bound_u64(woff, g_lo, g_hi + 1, seg0) - 1;
             uint64_t seg = seg0, grp = grp0;
@@ -173,6 +179,7 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
                 pass |= ok << (tb - t0);
                 n_pass += __popc(ok);
             }
+            pbits[tile * kBlock + threadIdx.x] = uint16_t(pass);
         }
         uint64_t total;
         uint64_t my = block_excl_scan(n_pass, &total);
@@ -261,7 +268,7 @@ template <bool EMIT, bool PULL>
 static void expand_dispatch(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
                             const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
                             const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, const uint64_t* toff,
-                            DevTable* out, uint64_t* osrc, hipStream_t s) {
+                            DevTable* out, uint64_t* osrc, uint16_t* pbits, hipStream_t s) {
     uint64_t tiles = expand_tiles(T);
     if (!tiles) return;
     unsigned grid = unsigned(tiles < (1u << 20) ? tiles : (1u << 20));
@@ -272,36 +279,41 @@ static void expand_dispatch(const DevTable& in, const uint64_t* gstart, const ui
     if (ki == 1 && ko == 1)
         k_expand<uint64_t, uint64_t, EMIT, PULL><<<grid, kBlock, 0, s>>>(
             (const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff, G, rstart, soff, S, T, g, colors, a, tcount, toff,
-            (uint64_t*)ok, oc, LO, osrc);
+            (uint64_t*)ok, oc, LO, osrc, pbits);
     else if (ki == 1)
         k_expand<uint64_t, u128, EMIT, PULL><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, woff,
                                                                       G, rstart, soff, S, T, g, colors, a, tcount, toff,
-                                                                      (u128*)ok, oc, LO, osrc);
+                                                                      (u128*)ok, oc, LO, osrc, pbits);
     else
         k_expand<u128, u128, EMIT, PULL><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, gstart, woff, G,
                                                                   rstart, soff, S, T, g, colors, a, tcount, toff,
-                                                                  (u128*)ok, oc, LO, osrc);
+                                                                  (u128*)ok, oc, LO, osrc, pbits);
 }
+
+uint64_t expand_pass_words(uint64_t T) { return expand_tiles(T) * kBlock; }
 
 void launch_expand_count(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
                          const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
-                         const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, hipStream_t s) {
+                         const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, uint16_t* pbits, hipStream_t s) {
     if (pull)
         expand_dispatch<false, true>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, tcount, nullptr, nullptr,
-                                     nullptr, s);
+                                     nullptr, pbits, s);
     else
         expand_dispatch<false, false>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, tcount, nullptr, nullptr,
-                                      nullptr, s);
+                                      nullptr, pbits, s);
 }
 
 void launch_expand_emit(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
                         const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
-                        const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, DevTable& out, uint64_t* osrc,
-                        hipStream_t s) {
+                        const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, const uint16_t* pbits,
+                        DevTable& out, uint64_t* osrc, hipStream_t s) {
+    uint16_t* pb = const_cast<uint16_t*>(pbits);  // read only in the emit pass
     if (pull)
-        expand_dispatch<true, true>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, nullptr, toff, &out, osrc, s);
+        expand_dispatch<true, true>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, nullptr, toff, &out, osrc, pb,
+                                    s);
     else
-        expand_dispatch<true, false>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, nullptr, toff, &out, osrc, s);
+        expand_dispatch<true, false>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, nullptr, toff, &out, osrc,
+                                     pb, s);
 }
 
 }  // namespace ccg

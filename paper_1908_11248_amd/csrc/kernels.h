@@ -104,13 +104,15 @@ void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64
 void launch_pull_seglen(const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g, int degF, uint32_t* slen,
                         hipStream_t s);
 uint64_t expand_tiles(uint64_t T);
+// survivor bits of the count pass, read back by the emit pass: expand_pass_words(T) words
+uint64_t expand_pass_words(uint64_t T);
 void launch_expand_count(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
                          const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
-                         const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, hipStream_t s);
+                         const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, uint16_t* pbits, hipStream_t s);
 void launch_expand_emit(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
                         const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
-                        const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, DevTable& out, uint64_t* osrc,
-                        hipStream_t s);
+                        const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, const uint16_t* pbits,
+                        DevTable& out, uint64_t* osrc, hipStream_t s);
 
 // introduce, pull form (child column 0 is the anchor).  launch_pull_index
 // writes the (colouring, column 0) run index rstart/rend[b * n + v] of a
