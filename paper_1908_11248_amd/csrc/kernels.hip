@@ -253,6 +253,9 @@ void launch_pull_index(const DevTable& in, int32_t n, uint64_t* rstart, uint64_t
 // ---------------------------------------------------------------------------
 // forget of the last column (Sec. 3.1 forget rule): per run of equal
 // (colouring, first b-1 images), add the counts of equal colour sets.
+// Runs longer than kForgetSmall go through a dense LDS accumulator, one run
+// per 64-lane workgroup; shorter ones through k_forget_small.
+constexpr int kForgetSmall = 16;
 template <class KI, class KO, bool EMIT>
 __global__ void __launch_bounds__(64)
 k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ gstart,
@@ -261,6 +264,7 @@ k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
     const int sh = L.kb + L.vb;  // drop the colour set and the last column
     for (uint64_t grp = blockIdx.x; grp < G; grp += gridDim.x) {
         uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
+        if (e1 - e0 <= kForgetSmall) continue;  // k_forget_small's
         acc_clear(acc, EMIT);
         __syncthreads();
         bool over = false;
@@ -287,6 +291,70 @@ k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
     }
 }
 
+// Runs of at most kForgetSmall entries, four per wave (16 lanes each, one
+// entry per lane): equal colour sets are found by comparing all pairs with
+// lane shuffles, and a set's place in the output is the number of distinct
+// smaller sets, so the output stays sorted without an accumulator.
+template <class KI, class KO, bool EMIT, int LN>
+__global__ void __launch_bounds__(kBlock)
+k_forget_small(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L,
+               const uint64_t* __restrict__ gstart, uint64_t G, uint32_t* gcount, const uint64_t* __restrict__ goff,
+               KO* okeys, uint64_t* ocnt, uint32_t* ovf) {
+    // runs of m <= LN entries, 64 / LN per wave
+    const uint64_t m_lo = 1;
+    const int sh = L.kb + L.vb;  // drop the colour set and the last column
+    const int sl = threadIdx.x % LN;
+    const uint64_t units_per_block = kBlock / LN;
+    for (uint64_t grp0 = uint64_t(blockIdx.x) * units_per_block; grp0 < G; grp0 += uint64_t(gridDim.x) * units_per_block) {
+        const uint64_t grp = grp0 + threadIdx.x / LN;
+        uint64_t e0 = 0, m = 0;
+        if (grp < G) {
+            e0 = gstart[grp];
+            m = gstart[grp + 1] - e0;
+            if (m > uint64_t(LN) || m < m_lo) m = 0;  // another kernel's run
+        }
+        const bool valid = uint64_t(sl) < m;
+        KI k = valid ? keys[e0 + sl] : KI(0);
+        const uint32_t C = valid ? kset(k, L) : ~0u;
+        const uint64_t c = (valid && EMIT) ? cnt[e0 + sl] : 0;
+        // the wave runs the longest of its runs
+        uint32_t mm = uint32_t(m);
+        for (int d = 32; d >= 1; d >>= 1) mm = max(mm, (uint32_t)__shfl_xor(mm, d, 64));
+        bool first = valid, over = false;
+        uint64_t sum = 0;
+        for (uint32_t i = 0; i < mm; i++) {
+            const uint32_t Ci = __shfl(C, int(i), LN);
+            const uint64_t ci = EMIT ? __shfl(c, int(i), LN) : 0;
+            if (valid && Ci == C) {
+                if (i < uint32_t(sl)) first = false;
+                sum += ci;
+                over |= sum < ci;
+            }
+        }
+        uint32_t rank = 0;
+        for (uint32_t i = 0; i < mm; i++) {
+            const uint32_t Ci = __shfl(C, int(i), LN);
+            const int fi = __shfl(int(first), int(i), LN);
+            rank += (fi && Ci < C) ? 1u : 0u;
+        }
+        if (EMIT) {
+            if (first) {
+                const uint64_t o = goff[grp] + rank;
+                okeys[o] = (KO(shr(k, sh)) << L.kb) | KO(C);
+                ocnt[o] = sum;
+            }
+            if (over) atomicOr(&ovf[kbid(k, L)], 1u);
+        } else {
+            const uint64_t fb = __ballot(first);
+            if (sl == 0 && grp < G && m > 0) {
+                const int base = int(threadIdx.x % 64) / LN * LN;
+                const uint64_t lanes = LN == 64 ? ~0ull : ((1ull << LN) - 1ull);
+                gcount[grp] = uint32_t(__popcll((fb >> base) & lanes));
+            }
+        }
+    }
+}
+
 template <bool EMIT>
 static void forget_dispatch(const DevTable& in, const uint64_t* gstart, uint64_t G, uint32_t* gcount,
                             const uint64_t* goff, DevTable* out, uint32_t* ovf, hipStream_t s) {
@@ -297,6 +365,22 @@ static void forget_dispatch(const DevTable& in, const uint64_t* gstart, uint64_t
     int ki = in.lay.kw(), ko = LO.kw();
     void* okk = out ? out->keys : nullptr;
     uint64_t* oc = out ? out->cnt : nullptr;
+    // runs of 1-16 entries four per wave, longer ones k_forget
+    {
+        const uint64_t sblocks = (G + kBlock / kForgetSmall - 1) / (kBlock / kForgetSmall);
+        const unsigned sgrid = unsigned(sblocks < (1u << 20) ? sblocks : (1u << 20));
+#define FORGET_SMALL(KIT, KOT)                                                                                       \
+    k_forget_small<KIT, KOT, EMIT, kForgetSmall><<<sgrid, kBlock, 0, s>>>((const KIT*)in.keys, in.cnt, in.lay, gstart, \
+                                                                        G, gcount, goff, (KOT*)okk, oc, ovf)
+        if (ki == 1) {
+            FORGET_SMALL(uint64_t, uint64_t);
+        } else if (ko == 1) {
+            FORGET_SMALL(u128, uint64_t);
+        } else {
+            FORGET_SMALL(u128, u128);
+        }
+#undef FORGET_SMALL
+    }
     if (ki == 1)
         k_forget<uint64_t, uint64_t, EMIT><<<grid, 64, lds, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, gstart, G, gcount,
                                                                  goff, (uint64_t*)okk, oc, ovf);
