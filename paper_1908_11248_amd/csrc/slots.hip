@@ -143,7 +143,8 @@ __device__ __forceinline__ void stage_rank(uint16_t* s_rank, const uint16_t* __r
 
 // dst[i] = src[i] for i < n by the block, four loads per thread in flight
 template <class T>
-__device__ __forceinline__ void stage_copy(T* dst, const T* __restrict__ src, uint32_t n) {
+__device__ __forceinline__ void stage_copy(T* dst, const T* __restrict__ src, uint32_t n, T* ored = nullptr) {
+    T acc = 0;
     for (uint32_t i0 = 0; i0 < n; i0 += 4 * kSlotBlock) {
         T v[4];
 #pragma unroll
@@ -155,8 +156,10 @@ __device__ __forceinline__ void stage_copy(T* dst, const T* __restrict__ src, ui
         for (int j = 0; j < 4; j++) {
             const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
             if (i < n) dst[i] = v[j];
+            acc |= v[j];
         }
     }
+    if (ored) *ored |= acc;  // the OR of this thread's values
 }
 
 }  // namespace
@@ -363,10 +366,11 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
     uint32_t* s_sp = reinterpret_cast<uint32_t*>(s_zc + cap * R_z);
     uint8_t* s_yf = reinterpret_cast<uint8_t*>(s_sp + (STAGE ? size_t(nsplit) * R : 0));
     uint8_t* s_zf = s_yf + cap * R_y;
+    uint64_t ored = 0;  // OR of the staged counts: are they all below 2^32?
     if (STAGE) {
         const uint32_t ny = nu * uint32_t(R_y), nz = nu * uint32_t(R_z);
-        stage_copy(s_yc, ycnt + base * uint32_t(R_y), ny);
-        stage_copy(s_zc, zcnt + base * uint32_t(R_z), nz);
+        stage_copy(s_yc, ycnt + base * uint32_t(R_y), ny, &ored);
+        stage_copy(s_zc, zcnt + base * uint32_t(R_z), nz, &ored);
         for (uint32_t i = threadIdx.x; i < uint32_t(nsplit * R); i += kSlotBlock) {
             const uint32_t t = i / uint32_t(R);
             s_sp[i] = splits[size_t(t) * sstride + (i - t * uint32_t(R))];
@@ -375,8 +379,10 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
             stage_copy(s_yf, yflag + base * uint32_t(R_y), ny);
             stage_copy(s_zf, zflag + base * uint32_t(R_z), nz);
         }
-        __syncthreads();
     }
+    // the barrier that publishes the staged rows also tells whether every
+    // staged count fits 32 bits (then products fit 64 bits)
+    const bool narrow = STAGE ? !__syncthreads_or(int((ored >> 32) != 0)) : false;
     uint64_t sum[M];
     uint32_t pres = 0;
     bool over = false;
@@ -391,7 +397,51 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
     bool live[M];
 #pragma unroll
     for (int i = 0; i < M; i++) live[i] = lane_ok && v + uint32_t(i * G.upb) < v1;
-    if (live[0]) {
+    if (STAGE && exact && lane_ok) {
+        // Branch-free: every staged vertex row is read (rows past the block's
+        // vertices hold stale LDS and are dropped by `live` at the end).  An
+        // absent entry holds 0, so products of absent entries add nothing;
+        // wrap and presence are kept per vertex.
+        uint64_t wrap[M];
+        uint32_t seen[M];
+#pragma unroll
+        for (int i = 0; i < M; i++) {
+            wrap[i] = 0;
+            seen[i] = 0;
+        }
+        if (narrow) {
+            for (int t = 0; t < nsplit; t++) {
+                const uint32_t e = s_sp[t * R + r];
+                const uint32_t ry = e & 0xffffu, rz = e >> 16;
+#pragma unroll
+                for (int i = 0; i < M; i++) {
+                    const uint32_t a = uint32_t(s_yc[by[i] + ry]), c = uint32_t(s_zc[bz[i] + rz]);
+                    const uint64_t pr = uint64_t(a) * c;  // exact: both factors below 2^32
+                    wrap[i] |= uint64_t(__builtin_add_overflow(sum[i], pr, &sum[i]));
+                    seen[i] |= uint32_t(a != 0) & uint32_t(c != 0);
+                }
+            }
+        } else {
+            for (int t = 0; t < nsplit; t++) {
+                const uint32_t e = s_sp[t * R + r];
+                const uint32_t ry = e & 0xffffu, rz = e >> 16;
+#pragma unroll
+                for (int i = 0; i < M; i++) {
+                    const uint64_t a = s_yc[by[i] + ry], c = s_zc[bz[i] + rz];
+                    const uint64_t pr = a * c;
+                    wrap[i] |= __umul64hi(a, c);
+                    wrap[i] |= uint64_t(__builtin_add_overflow(sum[i], pr, &sum[i]));
+                    seen[i] |= uint32_t(a != 0) & uint32_t(c != 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < M; i++) {
+            if (!live[i]) continue;
+            over |= wrap[i] != 0;
+            pres |= seen[i] << i;
+        }
+    } else if (live[0]) {
         for (int t = 0; t < nsplit; t++) {
             const uint32_t e = STAGE ? s_sp[t * R + r] : splits[size_t(t) * sstride + r];
             const uint32_t ry = e & 0xffffu, rz = e >> 16;
