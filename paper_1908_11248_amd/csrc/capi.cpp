@@ -70,9 +70,13 @@ int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_conte
             std::vector<uint32_t> sp = slot_split_tables();
             hip_check(hipMalloc(&c->slot_splits, sp.size() * 4), "hipMalloc");
             hip_check(hipMemcpy(c->slot_splits, sp.data(), sp.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+            std::vector<uint64_t> pk = slot_pack_tables();
+            hip_check(hipMalloc(&c->slot_pack, pk.size() * 8), "hipMalloc");
+            hip_check(hipMemcpy(c->slot_pack, pk.data(), pk.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
         } catch (...) {
             if (c->slot_tables) (void)hipFree(c->slot_tables);
             if (c->slot_splits) (void)hipFree(c->slot_splits);
+            if (c->slot_pack) (void)hipFree(c->slot_pack);
             if (c->arena_mem) (void)hipFree(c->arena_mem);
             c->main.destroy();
             delete c;
@@ -90,6 +94,7 @@ int cc_context_destroy(cc_context* ctx) {
         ctx->main.destroy();
         if (ctx->slot_tables) (void)hipFree(ctx->slot_tables);
         if (ctx->slot_splits) (void)hipFree(ctx->slot_splits);
+        if (ctx->slot_pack) (void)hipFree(ctx->slot_pack);
         if (ctx->arena_mem) (void)hipFree(ctx->arena_mem);
         delete ctx;
     });

@@ -356,9 +356,8 @@ uint64_t slot_peak_bytes(const Plan& plan, const std::vector<char>& fuse, const 
 }
 
 struct SlotTab {
-    uint64_t* cnt = nullptr;
-    uint8_t* flag = nullptr;
-    int s = 0, R = 0;
+    SlotArrays a;  // counts (two 32-bit planes), presence bytes, wide flags, R
+    int s = 0;     // colour-set size
 };
 
 // Runs a slot plan on dense one-column tables (slots.hip): no count passes,
@@ -395,8 +394,10 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     if (!one_sum) part_words = seg_max;
     const uint64_t root_off = part_words;
     part_words += slot_root_partials(g.n, B);
-    uint64_t* nsz = X.alloc<uint64_t>(nsz_words);
-    launch_fill_u64(nsz, 0, nsz_words, s);
+    // node sizes, then the wide flags of every step's table (B words each)
+    uint64_t* nsz = X.alloc<uint64_t>(nsz_words + (uint64_t(S) * B + 1) / 2);
+    launch_fill_u64(nsz, 0, nsz_words + (uint64_t(S) * B + 1) / 2, s);
+    uint32_t* wide = reinterpret_cast<uint32_t*>(nsz + nsz_words);
     uint64_t* part_base = X.alloc<uint64_t>(part_words);
     uint64_t* part = part_base;  // this step's segment
     SlotSums sums;
@@ -415,17 +416,19 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     const uint16_t* rank = ctx->slot_tables;
     const uint16_t* unrank = ctx->slot_tables + (1 << kSlotBits);
     const double csr = double(B) * (9.0 * g.n + 4.0 * g.m2);
-    auto make = [&](int set) {
+    auto make = [&](int set, size_t step) {
         SlotTab t;
         t.s = set;
-        t.R = binom(k - 1, set - 1);
-        t.cnt = X.alloc<uint64_t>(units * t.R);
-        t.flag = X.alloc<uint8_t>(units * t.R);
+        t.a.R = binom(k - 1, set - 1);
+        t.a.wide = wide + step * B;
+        t.a.lo = X.alloc<uint32_t>(2 * units * t.a.R);
+        t.a.hi = t.a.lo + units * t.a.R;
+        t.a.flag = X.alloc<uint8_t>(units * t.a.R);
         return t;
     };
     auto drop = [&](SlotTab& t) {
-        X.release(t.cnt);
-        X.release(t.flag);
+        X.release(t.a.lo);
+        X.release(t.a.flag);
         t = SlotTab();
     };
     // Identical subtrees (same shape, same degree masks) give identical
@@ -480,13 +483,16 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             }
             const bool leafc = virt[st.in0] != 0;
             const SlotTab in = leafc ? SlotTab() : tab[st.in0];
-            SlotTab o = make(sz[i + 1]);
-            SlotGrid G = slot_grid(g.n, B, o.R, 4);
+            SlotTab o = make(sz[i + 1], i + 1);
+            SlotGrid G = slot_grid(g.n, B, o.a.R, 4);
             const int degF_u = rq.degree_mask ? st.degF : 0;
             const int degF_c = rq.degree_mask ? plan.steps[st.in0].degF : 0;
-            X.timed("slot_edge", double(units) * 9.0 * (in.R + o.R) + csr, [&] {
-                launch_slot_edge(in.cnt, in.flag, in.R, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
-                                 slot_unrank_offset(o.s - 1), o.cnt, o.flag, part, ovf, s);
+            const uint64_t* pack = !leafc && k <= kSlotPackK && g.n < (1 << 24) && G.upb > 0
+                                       ? ctx->slot_pack + slot_pack_offset(k, o.s - 1)
+                                       : nullptr;
+            X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
+                launch_slot_edge(in.a, G, g, rq.colors, k, degF_u, degF_c, rank, unrank, slot_unrank_offset(o.s - 1),
+                                 pack, o.a, part, ovf, s);
             });
             partials_done(i, G.blocks);
             tab[i + 1] = o;
@@ -510,22 +516,22 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             continue;
         }
         if (st.kind == S_LEAF) {
-            SlotTab o = make(1);
+            SlotTab o = make(1, i);
             SlotGrid G = slot_grid(g.n, B, 1, 4);
             X.timed("slot_leaf", double(units) * 9.0 + 8.0 * g.n,
-                    [&] { launch_slot_leaf(G, g, rq.degree_mask ? st.degF : 0, o.cnt, o.flag, part, s); });
+                    [&] { launch_slot_leaf(G, g, rq.degree_mask ? st.degF : 0, o.a, part, s); });
             partials_done(i, G.blocks);
             tab[i] = o;
         } else {  // one-vertex join
             const SlotTab& y = tab[st.in0];
             const SlotTab& z = tab[st.in1];
-            SlotTab o = make(y.s + z.s - 1);
+            SlotTab o = make(y.s + z.s - 1, i);
             const int p = o.s - 1, q = y.s - 1;
             const int nsplit = binom(p, q);
-            SlotGrid G = slot_grid(g.n, B, o.R, std::max(1, slot_join_m(o.R, y.R, z.R, nsplit)));
-            X.timed("slot_join", double(units) * 9.0 * (y.R + z.R + o.R), [&] {
-                launch_slot_join(y.cnt, y.flag, y.R, z.cnt, z.flag, z.R, ctx->slot_splits + slot_split_offset(p, q),
-                                 nsplit, binom(kSlotBits, p), G, o.cnt, o.flag, part, ovf, s);
+            SlotGrid G = slot_grid(g.n, B, o.a.R, std::max(1, slot_join_m(o.a.R, y.a.R, z.a.R, nsplit)));
+            X.timed("slot_join", double(units) * 9.0 * (y.a.R + z.a.R + o.a.R), [&] {
+                launch_slot_join(y.a, z.a, ctx->slot_splits + slot_split_offset(p, q), nsplit, binom(kSlotBits, p), G,
+                                 o.a, part, ovf, s);
             });
             partials_done(i, G.blocks);
             tab[i] = o;
@@ -545,9 +551,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     const int cwords = k >= 5 ? 1 << (k - 5) : 1;
     uint32_t* csets = X.alloc<uint32_t>(uint64_t(B) * cwords);
     launch_fill_u32(csets, 0, uint64_t(B) * cwords, s);
-    X.timed("slot_root", double(units) * 9.0 * rc.R, [&] {
-        launch_slot_root(rc.cnt, rc.flag, rc.R, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv,
-                         csets, cwords, s);
+    X.timed("slot_root", double(units) * 9.0 * rc.a.R, [&] {
+        launch_slot_root(rc.a, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv, csets, cwords, s);
     });
     out->counts.assign(B, 0);
     std::vector<uint32_t> of(B, 0);

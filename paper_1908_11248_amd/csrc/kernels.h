@@ -208,6 +208,16 @@ struct SlotGrid {
     uint64_t blocks = 0;
 };
 SlotGrid slot_grid(int32_t n, int B, int R, int m_max);
+// A slot table on the device: counts mod 2^64 as two planes of 32-bit words
+// (low, high), presence bytes, each [B][n][R], and wide[b], set when some
+// count of colouring b is 2^32 or more (then the high plane matters).
+struct SlotArrays {
+    uint32_t* lo = nullptr;
+    uint32_t* hi = nullptr;
+    uint8_t* flag = nullptr;
+    uint32_t* wide = nullptr;
+    int R = 0;
+};
 // vertices per thread with which a join block stages its children's rows in LDS (0: none fit)
 int slot_join_m(int R_out, int R_y, int R_z, int nsplit);
 std::vector<uint16_t> slot_rank_tables();  // rank[2^11] then unrank[2^11], by popcount
@@ -226,26 +236,33 @@ struct SlotSums {
     uint64_t blocks[kSlotSumSteps];
 };
 void launch_slot_sums(const uint64_t* part, const SlotSums& S, uint64_t* nsz, hipStream_t s);
-void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
-                      hipStream_t s);
-void launch_slot_edge(const uint64_t* icnt, const uint8_t* iflag, int R_in, const SlotGrid& G, DevGraph g,
-                      const uint8_t* colors, int k, int degF_u, int degF_child, const uint16_t* rank,
-                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
-                      uint32_t* ovf, hipStream_t s);
+void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, SlotArrays out, uint64_t* part, hipStream_t s);
+// Packed child slots of an edge step, for k <= kSlotPackK: the entry for
+// output colour-set size p + 1, bag colour cv and output slot r (index
+// slot_pack_offset(k, p) + cv C(k - 1, p) + r) holds in byte c, for every
+// colour c of C - {cv}, 0x80 | the child's slot of C - {cv} (whose own bag
+// colour is c); the other bytes are 0.
+constexpr int kSlotPackK = 8;
+std::vector<uint64_t> slot_pack_tables();
+size_t slot_pack_offset(int k, int p);
+// in.lo == nullptr: the child is a leaf (count 1 per vertex passing
+// degF_child).  pack: the entries of (k, p) above, or null (ranks from the
+// rank tables).  out.wide must be cleared beforehand.
+void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
+                      int degF_child, const uint16_t* rank, const uint16_t* unrank, int uoff, const uint64_t* pack,
+                      SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
 constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
 // split table rows of (p, q) (see slots.hip) start at slot_split_offset(p, q);
 // row stride C(kSlotBits, p)
 std::vector<uint32_t> slot_split_tables();
 int slot_split_offset(int p, int q);
-void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const uint64_t* zcnt,
-                      const uint8_t* zflag, int R_z, const uint32_t* splits, int nsplit, int sstride,
-                      const SlotGrid& G, uint64_t* ocnt, uint8_t* oflag, uint64_t* part, uint32_t* ovf,
-                      hipStream_t s);
+void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, const SlotGrid& G,
+                      SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
 // rpart: slot_root_partials(n, B) words of scratch
 uint64_t slot_root_partials(int32_t n, int B);
-void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int s_in, int32_t n, int B,
-                      const uint8_t* colors, const uint16_t* unrank, uint64_t* rpart, uint64_t* counts, uint32_t* ovf,
-                      uint64_t* per_vertex, uint32_t* csets, int cwords, hipStream_t s);
+void launch_slot_root(SlotArrays in, int s_in, int32_t n, int B, const uint8_t* colors, const uint16_t* unrank,
+                      uint64_t* rpart, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, uint32_t* csets,
+                      int cwords, hipStream_t s);
 
 // root: per colouring the sum of the entries (counts), a sticky overflow flag,
 // optionally the per-image sums of the bag vertex, and a bitmap of the colour

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <stdexcept>
 
 #include "device.h"
 #include "kernels.h"
@@ -30,10 +31,10 @@ namespace {
 
 constexpr int kEdgeChunk = 2048;  // neighbours staged per round
 
-__device__ __forceinline__ uint32_t bit_open(uint32_t m, uint32_t c) {  // insert a 0 at bit c
+__host__ __device__ __forceinline__ uint32_t bit_open(uint32_t m, uint32_t c) {  // insert a 0 at bit c
     return ((m >> c) << (c + 1)) | (m & ((1u << c) - 1u));
 }
-__device__ __forceinline__ uint32_t bit_close(uint32_t m, uint32_t c) {  // delete bit c
+__host__ __device__ __forceinline__ uint32_t bit_close(uint32_t m, uint32_t c) {  // delete bit c
     return ((m >> (c + 1)) << c) | (m & ((1u << c) - 1u));
 }
 
@@ -162,12 +163,102 @@ __device__ __forceinline__ void stage_copy(T* dst, const T* __restrict__ src, ui
     if (ored) *ored |= acc;  // the OR of this thread's values
 }
 
+// dst[i] = lo[i] | hi[i] << 32 for i < n by the block
+__device__ __forceinline__ void stage_pair(uint64_t* dst, const uint32_t* __restrict__ lo,
+                                           const uint32_t* __restrict__ hi, uint32_t n) {
+    for (uint32_t i0 = 0; i0 < n; i0 += 2 * kSlotBlock) {
+        uint32_t l[2], h[2];
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
+            l[j] = i < n ? lo[i] : 0u;
+            h[j] = i < n ? hi[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
+            if (i < n) dst[i] = uint64_t(l[j]) | (uint64_t(h[j]) << 32);
+        }
+    }
+}
+
+// stores a count into the two planes and its presence byte (streaming: the
+// output is not read again by the kernel that writes it)
+__device__ __forceinline__ void store_slot(const SlotArrays& o, uint64_t i, uint64_t c, bool present) {
+    __builtin_nontemporal_store(uint32_t(c), &o.lo[i]);
+    __builtin_nontemporal_store(uint32_t(c >> 32), &o.hi[i]);
+    __builtin_nontemporal_store(uint8_t(present), &o.flag[i]);
+}
+
+// Four staged neighbours of one vertex with packed child slots: entry e =
+// y | 8 colour(y) << 24 selects byte colour(y) of P, which holds 0x80 | the
+// child's slot when colour(y) is in the child's colour set (else 0).  Every
+// load is issued (a masked neighbour reads slot 0 of its own row, or of
+// vertex 0 for the zero padding past a range) and the value is dropped by
+// ok.  lo/hi/fl: colouring b's part of the child's planes.  NARROW: every
+// count of the child's colouring is below 2^32, so the low plane suffices and
+// no sum can wrap (fewer than 2^32 terms).  EXACT: no count of the colouring
+// has wrapped, so an entry is present iff its count is not 0.
+template <bool NARROW, bool EXACT, bool CHECK>
+__device__ __forceinline__ void pack_step(const uint32_t* __restrict__ lo, const uint32_t* __restrict__ hi,
+                                          const uint8_t* __restrict__ fl, const uint32_t* s_nb, int i, int z,
+                                          uint64_t P, uint32_t R_in, uint64_t& sum, uint32_t& cnt, uint32_t& over) {
+    uint32_t idx[4];
+    bool ok[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t e = s_nb[i + j];
+        const uint32_t f = uint32_t(P >> (e >> 24));
+        ok[j] = (f & 0x80u) != 0 && (!CHECK || i + j < z);
+        idx[j] = __umul24(e, R_in) + (f & 0x7fu);  // < n R_in < 2^28
+    }
+    if (NARROW) {
+        uint32_t cv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) cv[j] = lo[idx[j]];
+#pragma unroll
+        for (int j = 0; j < 4; j++) cv[j] = ok[j] ? cv[j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; j++) cnt += EXACT ? uint32_t(cv[j] != 0) : uint32_t(ok[j] && fl[idx[j]] != 0);
+        sum += (uint64_t(cv[0]) + cv[1]) + (uint64_t(cv[2]) + cv[3]);
+    } else {
+        uint32_t l[4], h[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            l[j] = lo[idx[j]];
+            h[j] = hi[idx[j]];
+        }
+        uint64_t cv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) cv[j] = ok[j] ? uint64_t(l[j]) | (uint64_t(h[j]) << 32) : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; j++) cnt += EXACT ? uint32_t(cv[j] != 0) : uint32_t(ok[j] && fl[idx[j]] != 0);
+#pragma unroll
+        for (int j = 0; j < 4; j++) over |= uint32_t(__builtin_add_overflow(sum, cv[j], &sum));
+    }
+}
+
+// neighbours [a, z) of the staged chunk: groups of four, the last one masked
+template <bool NARROW, bool EXACT>
+__device__ __forceinline__ void pack_gather(const uint32_t* __restrict__ lo, const uint32_t* __restrict__ hi,
+                                            const uint8_t* __restrict__ fl, const uint32_t* s_nb, int a, int z,
+                                            uint64_t P, uint32_t R_in, uint64_t& sum, uint32_t& cnt, uint32_t& over) {
+    int i = a;
+    for (; i + 4 <= z; i += 4) pack_step<NARROW, EXACT, false>(lo, hi, fl, s_nb, i, z, P, R_in, sum, cnt, over);
+    if (i < z) pack_step<NARROW, EXACT, true>(lo, hi, fl, s_nb, i, z, P, R_in, sum, cnt, over);
+}
+
+// sets flag[b] when some lane's value has a nonzero high word (one atomic per wave)
+__device__ __forceinline__ void flag_wide(uint32_t hi, uint32_t* flag) {
+    if (__ballot(hi != 0) != 0 && __lane_id() == 0) atomicOr(flag, 1u);
+}
+
 }  // namespace
 
 // Leaf (Sec. 3, leaf nodes; degree mask of Sec. 4): one slot per (b, v).
 template <int M>
-__global__ void __launch_bounds__(kSlotBlock)
-k_slot_leaf(SlotGrid G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, uint64_t* part) {
+__global__ void __launch_bounds__(kSlotBlock) k_slot_leaf(SlotGrid G, DevGraph g, int degF, SlotArrays out,
+                                                          uint64_t* part) {
     uint32_t b, v0, v1, jb, v, r;
     bool lane_ok;
     block_range(G, &b, &v0, &v1, &jb);
@@ -178,13 +269,91 @@ k_slot_leaf(SlotGrid G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, ui
         const uint32_t vi = v + uint32_t(i * G.upb);
         if (lane_ok && vi < v1) {
             const bool pres = g.rp[vi + 1] - g.rp[vi] >= degF;
-            const uint64_t o = uint64_t(b) * uint32_t(g.n) + vi;
-            ocnt[o] = pres ? 1 : 0;
-            oflag[o] = pres;
+            store_slot(out, uint64_t(b) * uint32_t(g.n) + vi, pres ? 1 : 0, pres);
             npres += pres;
         }
     }
     count_entries(npres, 0, part, G.blocks);
+}
+
+// Introduce u (image v) over a leaf child, followed by the forget of the
+// leaf's vertex (Sec. 3): the child table holds one entry, of count 1, per
+// vertex that passes the child's degree mask, so output slot (b, v,
+// {colour(v), c}) counts the neighbours of v of colour c that pass it.  The
+// block builds the colour histograms of its vertices' neighbourhoods in LDS
+// from its CSR range, split evenly over the threads (a hub costs no more than
+// its share), then every thread reads its slots from them.
+template <int M>
+__global__ void __launch_bounds__(kSlotBlock)
+k_slot_edge_leaf(SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u, int degF_child,
+                 SlotArrays out, uint64_t* part) {
+    // [upb M + 1] CSR offsets relative to the block's first vertex, then
+    // [upb M][k] neighbour counts by colour
+    extern __shared__ uint32_t s_leaf[];
+    uint32_t b, v0, v1, jb, v, r;
+    bool lane_ok;
+    block_range(G, &b, &v0, &v1, &jb);
+    slot_of(G, v0, jb, &v, &r, &lane_ok);
+    const uint32_t nv = v1 - v0;
+    const uint8_t* cb = colors + uint64_t(b) * uint32_t(g.n);
+    uint32_t* s_off = s_leaf;
+    uint32_t* s_hist = s_leaf + G.upb * M + 1;
+    const int64_t e_lo = nv ? g.rp[v0] : 0;
+    for (uint32_t i = threadIdx.x; nv && i <= nv; i += kSlotBlock) s_off[i] = uint32_t(g.rp[v0 + i] - e_lo);
+    for (uint32_t i = threadIdx.x; i < nv * uint32_t(k); i += kSlotBlock) s_hist[i] = 0;
+    __syncthreads();
+    const uint32_t E = nv ? s_off[nv] : 0;
+    const uint32_t per = (E + kSlotBlock - 1) / kSlotBlock;
+    uint32_t e = min(E, threadIdx.x * per);
+    const uint32_t e_end = min(E, e + per);
+    if (e < e_end) {
+        // the vertex whose range holds entry e: s_off[lo] <= e < s_off[hi]
+        uint32_t lo = 0, hi = nv;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= e)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        uint32_t lv = lo;
+        for (; e < e_end; e += 4) {
+            // four neighbours in flight: ids, then colours (and degrees)
+            uint32_t y[4], c[4];
+            bool pass[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) y[j] = e + j < e_end ? uint32_t(g.col[e_lo + e + j]) : 0u;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                c[j] = cb[y[j]];
+                pass[j] = e + j < e_end && (degF_child <= 1 || g.rp[y[j] + 1] - g.rp[y[j]] >= degF_child);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (e + j >= e_end) break;
+                while (e + j >= s_off[lv + 1]) lv++;
+                if (pass[j]) atomicAdd(&s_hist[lv * uint32_t(k) + c[j]], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t npres = 0;
+    uint64_t nin = 0;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        const uint32_t vi = v + uint32_t(i * G.upb);
+        if (lane_ok && vi < v1) {
+            const uint32_t lv = vi - v0;
+            const uint32_t cv = cb[vi];
+            // slot r of set size 2 is the r-th colour other than colour(v)
+            const uint32_t h =
+                s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u) ? s_hist[lv * uint32_t(k) + r + (r >= cv)] : 0u;
+            store_slot(out, (uint64_t(b) * uint32_t(g.n) + vi) * uint32_t(G.R) + r, h, h != 0);
+            npres += h != 0;
+            nin += h;
+        }
+    }
+    count_entries(npres, nin, part, G.blocks);
 }
 
 // Introduce u (image v, every neighbour y of v is a candidate for the child's
@@ -193,38 +362,46 @@ k_slot_leaf(SlotGrid G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, ui
 // which requires colour(y) in C - colour(v).  The block partials count the
 // introduce entries (child entries that pass) and the output entries.
 // The neighbour lists of the block's vertices are one CSR range; it is
-// staged in rounds of kEdgeChunk (ids, and colours with the leaf child's
-// degree test in bit 7).  A thread serves the same slot of M vertices.
-template <bool LEAFCHILD, int M>
+// staged in rounds of kEdgeChunk.  A thread serves the same slot of M
+// vertices.  PACK (k <= kSlotPackK): the child slot of every neighbour colour
+// comes from one packed word per vertex (slot_pack_tables) instead of a rank
+// lookup.
+template <int M, bool PACK>
 __global__ void __launch_bounds__(kSlotBlock)
-k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag, int R_in, SlotGrid G, DevGraph g,
-            const uint8_t* __restrict__ colors, int k, int degF_u, int degF_child, const uint16_t* __restrict__ rank,
-            const uint16_t* __restrict__ unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
-            uint32_t* ovf) {
+k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
+            const uint16_t* __restrict__ rank, const uint16_t* __restrict__ unrank, int uoff,
+            const uint64_t* __restrict__ pack, SlotArrays out, uint64_t* part, uint32_t* ovf) {
     extern __shared__ uint16_t s_rank[];  // rank of every mask over k - 1 bits
-    // staged neighbours: LEAFCHILD: colour | passes-degree-mask << 7; otherwise
-    // the neighbour's row offset y R_in (< 2^28) | colour << 28.  Four entries
-    // of padding let a batch read past the end of a range.
+    // staged neighbours: PACK: y | 8 colour << 24; otherwise the neighbour's
+    // row offset y R_in (< 2^28) | colour << 28.  Four entries of padding let
+    // a batch read past the end of a range.
     __shared__ uint32_t s_nb[kEdgeChunk + 4];
     uint32_t b, v0, v1, jb, v, r;
     bool lane_ok;
     block_range(G, &b, &v0, &v1, &jb);
     slot_of(G, v0, jb, &v, &r, &lane_ok);
-    stage_rank(s_rank, rank, k);
     const uint32_t n = uint32_t(g.n);
-    const uint8_t* cb = colors + uint64_t(b) * n;
+    const uint32_t R_in = uint32_t(in.R);
     const uint64_t row0 = uint64_t(b) * n;
+    // colouring b's part of the child table (n * R_in < 2^28 slots)
+    const uint32_t* ilo = in.lo + row0 * R_in;
+    const uint32_t* ihi = in.hi + row0 * R_in;
+    const uint8_t* ifl = in.flag + row0 * R_in;
+    if (!PACK) stage_rank(s_rank, rank, k);
+    const uint8_t* cb = colors + row0;
     int64_t rb[M], re[M];
     uint32_t Cx[M];
+    uint64_t P[M];
     uint64_t sum[M];
     uint32_t cnt[M];  // child entries gathered per vertex: the introduce entries; > 0 iff present
     uint32_t over = 0;
-    const uint32_t mr = lane_ok ? unrank[uoff + r] : 0;
+    const uint32_t mr = lane_ok && !PACK ? unrank[uoff + r] : 0;
 #pragma unroll
     for (int i = 0; i < M; i++) {
         const uint32_t vi = v + uint32_t(i * G.upb);
         rb[i] = re[i] = 0;
         Cx[i] = 0;
+        P[i] = 0;
         sum[i] = 0;
         cnt[i] = 0;
         if (lane_ok && vi < v1) {
@@ -232,18 +409,18 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
             if (z - a >= degF_u) {
                 rb[i] = a;
                 re[i] = z;
-                // the output set without colour(v), as a k-bit mask: the child's set
-                Cx[i] = bit_open(mr, cb[vi]);
+                if (PACK)
+                    P[i] = pack[uint32_t(cb[vi]) * uint32_t(G.R) + r];
+                else  // the output set without colour(v), as a k-bit mask: the child's set
+                    Cx[i] = bit_open(mr, cb[vi]);
             }
         }
     }
     // the child table of colouring b is exact (no count wrapped while it was
     // built) when b's overflow flag is still clear; then presence is count != 0
-    const bool exact = LEAFCHILD || (v1 > v0 && ovf[b] == 0);
+    const bool exact = v1 > v0 && ovf[b] == 0;
+    const bool narrow = in.wide[b] == 0;
     const uint32_t rmask = (1u << (k - 1)) - 1u;  // keeps rank reads of masked-out lanes in the table
-    // colouring b's part of the child table (n * R_in < 2^28 slots)
-    const uint64_t* itab = LEAFCHILD ? nullptr : icnt + row0 * uint32_t(R_in);
-    const uint8_t* iftab = LEAFCHILD ? nullptr : iflag + row0 * uint32_t(R_in);
     const int64_t e_lo = v1 > v0 ? g.rp[v0] : 0, e_hi = v1 > v0 ? g.rp[v1] : 0;
     for (int64_t c0 = e_lo; c0 < e_hi; c0 += kEdgeChunk) {
         const int cn = int(min(int64_t(kEdgeChunk), e_hi - c0));
@@ -258,30 +435,24 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
             }
 #pragma unroll
             for (int j = 0; j < 4; j++) c[j] = cb[y[j]];
-            // (a neighbour has degree >= 1 already: no lookup for degF_child <= 1)
-            if (LEAFCHILD) {
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    if (degF_child <= 1 || g.rp[y[j] + 1] - g.rp[y[j]] >= degF_child) c[j] |= 0x80u;
-            }
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int i = i0 + j * kSlotBlock + int(threadIdx.x);
-                if (i < cn) s_nb[i] = LEAFCHILD ? c[j] : y[j] * uint32_t(R_in) | (c[j] << 28);
+                if (i < cn) s_nb[i] = PACK ? y[j] | (c[j] << 27) : y[j] * R_in | (c[j] << 28);
             }
         }
+        if (threadIdx.x < 4) s_nb[cn + threadIdx.x] = 0;  // padding: vertex 0, colour 0
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < M; u++) {
             const int a = int(max(rb[u], c0) - c0), z = int(min(re[u], c0 + cn) - c0);
-            if (LEAFCHILD) {
-                // leaf child: one entry of count 1 per neighbour of a wanted colour
-                uint32_t hits = 0;
-                for (int i = a; i < z; i++) {
-                    const uint32_t c = s_nb[i];
-                    hits += (Cx[u] >> (c & 0x7fu)) & (c >> 7);
-                }
-                cnt[u] += hits;
+            if (PACK) {
+                if (narrow && exact)
+                    pack_gather<true, true>(ilo, ihi, ifl, s_nb, a, z, P[u], R_in, sum[u], cnt[u], over);
+                else if (exact)
+                    pack_gather<false, true>(ilo, ihi, ifl, s_nb, a, z, P[u], R_in, sum[u], cnt[u], over);
+                else
+                    pack_gather<false, false>(ilo, ihi, ifl, s_nb, a, z, P[u], R_in, sum[u], cnt[u], over);
                 continue;
             }
             // four neighbours per round: their slot loads are in flight together.
@@ -296,19 +467,20 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
                     const uint32_t e = s_nb[i + j];  // past z: padding or other vertices, masked by ok
                     const uint32_t cy = e >> 28;
                     ok[j] = (i + j < z) && ((Cx[u] >> cy) & 1u);
-                    // slot offset within colouring b's table, in bytes (< 2^31)
-                    idx[j] = ((e & 0x0fffffffu) + s_rank[bit_close(Cx[u], cy) & rmask]) << 3;
+                    // slot within colouring b's table (< 2^28)
+                    idx[j] = (e & 0x0fffffffu) + s_rank[bit_close(Cx[u], cy) & rmask];
                 }
 #pragma unroll
                 for (int j = 0; j < NB; j++)
-                    cv[j] = ok[j] ? *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(itab) + idx[j]) : 0;
+                    cv[j] = ok[j] ? (narrow ? uint64_t(ilo[idx[j]]) : uint64_t(ilo[idx[j]]) | (uint64_t(ihi[idx[j]]) << 32))
+                                  : 0;
                 if (exact) {
                     // no count of this colouring has wrapped: present entries hold >= 1
 #pragma unroll
                     for (int j = 0; j < NB; j++) cnt[u] += cv[j] != 0;
                 } else {
 #pragma unroll
-                    for (int j = 0; j < NB; j++) cnt[u] += ok[j] && iftab[idx[j] >> 3] != 0;
+                    for (int j = 0; j < NB; j++) cnt[u] += ok[j] && ifl[idx[j]] != 0;
                 }
 #pragma unroll
                 for (int j = 0; j < NB; j++) over |= uint32_t(__builtin_add_overflow(sum[u], cv[j], &sum[u]));
@@ -319,20 +491,19 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
     uint64_t nin = 0;
 #pragma unroll
     for (int i = 0; i < M; i++) {
-        if (LEAFCHILD) sum[i] = cnt[i];
         nin += cnt[i];
         npres += cnt[i] != 0;
     }
 #pragma unroll
     for (int i = 0; i < M; i++) {
         const uint32_t vi = v + uint32_t(i * G.upb);
-        if (lane_ok && vi < v1) {
-            const uint64_t o = (row0 + vi) * uint32_t(G.R) + r;
-            ocnt[o] = sum[i];
-            oflag[o] = cnt[i] != 0;
-        }
+        if (lane_ok && vi < v1) store_slot(out, (row0 + vi) * uint32_t(G.R) + r, sum[i], cnt[i] != 0);
     }
     if (over) atomicOr(&ovf[b], 1u);
+    uint32_t hi = 0;
+#pragma unroll
+    for (int i = 0; i < M; i++) hi |= uint32_t(sum[i] >> 32);
+    flag_wide(hi, &out.wide[b]);
     count_entries(npres, nin, part, G.blocks);
 }
 
@@ -342,14 +513,14 @@ k_slot_edge(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
 // colouring: row t of the split table holds (rank of C_y, rank of C_z) for
 // every r (slot_split_tables), so a thread walks the rows once for its M
 // vertices.  With STAGE the children's rows of the block's vertices
-// (contiguous in both tables) and the split table are staged in LDS;
-// presence bytes are read only for a colouring whose counts have wrapped.
+// (contiguous in both tables) and the split table are staged in LDS: only
+// the low planes when both children's counts of the colouring are below
+// 2^32 (then products are exact in 64 bits), else both planes combined.
+// Presence bytes are read only for a colouring whose counts have wrapped.
 template <bool STAGE, int M>
 __global__ void __launch_bounds__(kSlotBlock)
-k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag, int R_y,
-            const uint64_t* __restrict__ zcnt, const uint8_t* __restrict__ zflag, int R_z,
-            const uint32_t* __restrict__ splits, int nsplit, int sstride, SlotGrid G, uint64_t* ocnt, uint8_t* oflag,
-            uint64_t* part, uint32_t* ovf) {
+k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int nsplit, int sstride, SlotGrid G,
+            SlotArrays out, uint64_t* part, uint32_t* ovf) {
     extern __shared__ uint64_t s_mem[];
     uint32_t b, v0, v1, jb, v, r;
     bool lane_ok;
@@ -358,31 +529,37 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
     const uint32_t nu = v1 - v0;
     const uint64_t base = uint64_t(b) * uint32_t(G.n) + v0;  // first unit of the block
     const bool exact = v1 > v0 && ovf[b] == 0;
-    const int R = G.R;
-    // layout: [y counts][z counts][split rows][y flags][z flags]
+    const bool narrow = y.wide[b] == 0 && z.wide[b] == 0;
+    const int R = G.R, R_y = y.R, R_z = z.R;
+    // layout: [y counts][z counts][split rows][y flags][z flags]; narrow
+    // rows are 32-bit words at the start of the count regions
     const size_t cap = STAGE ? size_t(G.upb) * M : 0;
     uint64_t* s_yc = s_mem;
     uint64_t* s_zc = s_yc + cap * R_y;
+    uint32_t* s_y32 = reinterpret_cast<uint32_t*>(s_yc);
+    uint32_t* s_z32 = reinterpret_cast<uint32_t*>(s_zc);
     uint32_t* s_sp = reinterpret_cast<uint32_t*>(s_zc + cap * R_z);
     uint8_t* s_yf = reinterpret_cast<uint8_t*>(s_sp + (STAGE ? size_t(nsplit) * R : 0));
     uint8_t* s_zf = s_yf + cap * R_y;
-    uint64_t ored = 0;  // OR of the staged counts: are they all below 2^32?
     if (STAGE) {
         const uint32_t ny = nu * uint32_t(R_y), nz = nu * uint32_t(R_z);
-        stage_copy(s_yc, ycnt + base * uint32_t(R_y), ny, &ored);
-        stage_copy(s_zc, zcnt + base * uint32_t(R_z), nz, &ored);
+        if (narrow) {
+            stage_copy(s_y32, y.lo + base * uint32_t(R_y), ny);
+            stage_copy(s_z32, z.lo + base * uint32_t(R_z), nz);
+        } else {
+            stage_pair(s_yc, y.lo + base * uint32_t(R_y), y.hi + base * uint32_t(R_y), ny);
+            stage_pair(s_zc, z.lo + base * uint32_t(R_z), z.hi + base * uint32_t(R_z), nz);
+        }
         for (uint32_t i = threadIdx.x; i < uint32_t(nsplit * R); i += kSlotBlock) {
             const uint32_t t = i / uint32_t(R);
             s_sp[i] = splits[size_t(t) * sstride + (i - t * uint32_t(R))];
         }
         if (!exact) {
-            stage_copy(s_yf, yflag + base * uint32_t(R_y), ny);
-            stage_copy(s_zf, zflag + base * uint32_t(R_z), nz);
+            stage_copy(s_yf, y.flag + base * uint32_t(R_y), ny);
+            stage_copy(s_zf, z.flag + base * uint32_t(R_z), nz);
         }
+        __syncthreads();
     }
-    // the barrier that publishes the staged rows also tells whether every
-    // staged count fits 32 bits (then products fit 64 bits)
-    const bool narrow = STAGE ? !__syncthreads_or(int((ored >> 32) != 0)) : false;
     uint64_t sum[M];
     uint32_t pres = 0;
     bool over = false;
@@ -402,25 +579,38 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
         // vertices hold stale LDS and are dropped by `live` at the end).  An
         // absent entry holds 0, so products of absent entries add nothing;
         // wrap and presence are kept per vertex.
-        uint64_t wrap[M];
-        uint32_t seen[M];
+        uint32_t wrap[M], seen[M];
 #pragma unroll
         for (int i = 0; i < M; i++) {
             wrap[i] = 0;
             seen[i] = 0;
         }
         if (narrow) {
+            // products of 32-bit factors are exact and nonzero iff both factors
+            // are, so the OR of the products tells presence; wraps are counted
+            uint64_t orp[M];
+#pragma unroll
+            for (int i = 0; i < M; i++) orp[i] = 0;
             for (int t = 0; t < nsplit; t++) {
                 const uint32_t e = s_sp[t * R + r];
                 const uint32_t ry = e & 0xffffu, rz = e >> 16;
+                uint32_t a[M], c[M];
 #pragma unroll
                 for (int i = 0; i < M; i++) {
-                    const uint32_t a = uint32_t(s_yc[by[i] + ry]), c = uint32_t(s_zc[bz[i] + rz]);
-                    const uint64_t pr = uint64_t(a) * c;  // exact: both factors below 2^32
-                    wrap[i] |= uint64_t(__builtin_add_overflow(sum[i], pr, &sum[i]));
-                    seen[i] |= uint32_t(a != 0) & uint32_t(c != 0);
+                    a[i] = s_y32[by[i] + ry];
+                    c[i] = s_z32[bz[i] + rz];
+                }
+#pragma unroll
+                for (int i = 0; i < M; i++) {
+                    const uint64_t pr = uint64_t(a[i]) * c[i];
+                    const uint64_t t2 = sum[i] + pr;
+                    wrap[i] += t2 < pr;
+                    sum[i] = t2;
+                    orp[i] |= pr;
                 }
             }
+#pragma unroll
+            for (int i = 0; i < M; i++) seen[i] = orp[i] != 0;
         } else {
             for (int t = 0; t < nsplit; t++) {
                 const uint32_t e = s_sp[t * R + r];
@@ -429,8 +619,8 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
                 for (int i = 0; i < M; i++) {
                     const uint64_t a = s_yc[by[i] + ry], c = s_zc[bz[i] + rz];
                     const uint64_t pr = a * c;
-                    wrap[i] |= __umul64hi(a, c);
-                    wrap[i] |= uint64_t(__builtin_add_overflow(sum[i], pr, &sum[i]));
+                    wrap[i] |= __umul64hi(a, c) != 0;
+                    wrap[i] |= uint32_t(__builtin_add_overflow(sum[i], pr, &sum[i]));
                     seen[i] |= uint32_t(a != 0) & uint32_t(c != 0);
                 }
             }
@@ -449,9 +639,16 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
             for (int i = 0; i < M; i++) {
                 if (!live[i]) continue;
                 const uint64_t iy = by[i] + ry, iz = bz[i] + rz;
-                const uint64_t a = STAGE ? s_yc[iy] : ycnt[iy], c = STAGE ? s_zc[iz] : zcnt[iz];
+                uint64_t a, c;
+                if (STAGE) {
+                    a = narrow ? s_y32[iy] : s_yc[iy];
+                    c = narrow ? s_z32[iz] : s_zc[iz];
+                } else {
+                    a = uint64_t(y.lo[iy]) | (uint64_t(y.hi[iy]) << 32);
+                    c = uint64_t(z.lo[iz]) | (uint64_t(z.hi[iz]) << 32);
+                }
                 const bool f = exact ? (a != 0 && c != 0)
-                                     : (STAGE ? (s_yf[iy] && s_zf[iz]) : (yflag[iy] && zflag[iz]));
+                                     : (STAGE ? (s_yf[iy] && s_zf[iz]) : (y.flag[iy] && z.flag[iz]));
                 if (!f) continue;
                 uint64_t pr;
                 if (((a | c) >> 32) == 0) {
@@ -466,14 +663,15 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
             }
         }
     }
+    uint32_t hi = 0;
 #pragma unroll
     for (int i = 0; i < M; i++) {
         if (!live[i]) continue;
-        const uint64_t o = (base + uint64_t(v - v0) + uint64_t(i) * G.upb) * uint32_t(R) + r;
-        ocnt[o] = sum[i];
-        oflag[o] = (pres >> i) & 1u;
+        store_slot(out, (base + uint64_t(v - v0) + uint64_t(i) * G.upb) * uint32_t(R) + r, sum[i], (pres >> i) & 1u);
+        hi |= uint32_t(sum[i] >> 32);
     }
     if (over) atomicOr(&ovf[b], 1u);
+    flag_wide(hi, &out.wide[b]);
     count_entries(__popc(pres), 0, part, G.blocks);
 }
 
@@ -486,8 +684,7 @@ k_slot_join(const uint64_t* __restrict__ ycnt, const uint8_t* __restrict__ yflag
 // M vertices per thread.
 template <int M>
 __global__ void __launch_bounds__(kSlotBlock)
-k_slot_root(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag, int R_in,
-            const uint8_t* __restrict__ colors, const uint16_t* __restrict__ unrank, int uoff, SlotGrid G,
+k_slot_root(SlotArrays in, const uint8_t* __restrict__ colors, const uint16_t* __restrict__ unrank, int uoff, SlotGrid G,
             uint64_t* rpart, uint64_t* per_vertex, uint32_t* csets, int cwords) {
     extern __shared__ uint32_t s_cs[];
     uint32_t b, v0, v1, jb, v, r;
@@ -503,12 +700,14 @@ k_slot_root(const uint64_t* __restrict__ icnt, const uint8_t* __restrict__ iflag
         const uint32_t vi = v + uint32_t(i * G.upb);
         if (!(lane_ok && vi < v1)) continue;
         const uint64_t unit = uint64_t(b) * uint32_t(G.n) + vi;
-        const uint64_t* pc = icnt + unit * uint32_t(R_in);
-        const uint8_t* f = iflag + unit * uint32_t(R_in);
+        const int R_in = in.R;
+        const uint32_t* pl = in.lo + unit * uint32_t(R_in);
+        const uint32_t* ph = in.hi + unit * uint32_t(R_in);
+        const uint8_t* f = in.flag + unit * uint32_t(R_in);
         const uint32_t cv = colors[unit];
         uint64_t us = 0;
         for (int j = 0; j < R_in; j++) {
-            const uint64_t c = pc[j];
+            const uint64_t c = uint64_t(pl[j]) | (uint64_t(ph[j]) << 32);
             us += c;
             over |= us < c;
             if (f[j]) {
@@ -719,6 +918,37 @@ std::vector<uint32_t> slot_split_tables() {
     return t;
 }
 
+size_t slot_pack_offset(int k, int p) {
+    size_t off = 0;
+    for (int kk = 2; kk <= kSlotPackK; kk++)
+        for (int pp = 1; pp < kk; pp++) {
+            if (kk == k && pp == p) return off;
+            off += size_t(kk) * binom_pq(kk - 1, pp);
+        }
+    return off;  // past the last: the total
+}
+
+std::vector<uint64_t> slot_pack_tables() {
+    std::vector<uint16_t> rt = slot_rank_tables();
+    const int M = 1 << kSlotBits;
+    std::vector<uint64_t> t(slot_pack_offset(kSlotPackK + 1, 1));
+    for (int k = 2; k <= kSlotPackK; k++)
+        for (int p = 1; p < k; p++) {
+            const int R = binom_pq(k - 1, p);
+            const size_t off = slot_pack_offset(k, p);
+            for (int cv = 0; cv < k; cv++)
+                for (int r = 0; r < R; r++) {
+                    // the child's colour set: output slot r's set without cv, over k bits
+                    const uint32_t C = bit_open(rt[M + slot_unrank_offset(p) + r], uint32_t(cv));
+                    uint64_t w = 0;
+                    for (int c = 0; c < k; c++)
+                        if ((C >> c) & 1u) w |= uint64_t(0x80u | rt[bit_close(C, uint32_t(c))]) << (8 * c);
+                    t[off + size_t(cv) * R + r] = w;
+                }
+        }
+    return t;
+}
+
 // vertices per thread with which a join block stages its children's rows and
 // split rows in kSlotJoinLds (0: none fit)
 int slot_join_m(int R_out, int R_y, int R_z, int nsplit) {
@@ -737,62 +967,67 @@ int slot_join_m(int R_out, int R_y, int R_z, int nsplit) {
         default: MACRO(1); break; \
     }
 
-void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
-                      hipStream_t s) {
+void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, SlotArrays out, uint64_t* part, hipStream_t s) {
     if (!G.blocks) return;
-#define LEAF_M(M) k_slot_leaf<M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(G, g, degF, ocnt, oflag, part)
+#define LEAF_M(M) k_slot_leaf<M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(G, g, degF, out, part)
     SLOT_BY_M(LEAF_M)
 #undef LEAF_M
 }
 
-void launch_slot_edge(const uint64_t* icnt, const uint8_t* iflag, int R_in, const SlotGrid& G, DevGraph g,
-                      const uint8_t* colors, int k, int degF_u, int degF_child, const uint16_t* rank,
-                      const uint16_t* unrank, int uoff, uint64_t* ocnt, uint8_t* oflag, uint64_t* part,
-                      uint32_t* ovf, hipStream_t s) {
+void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
+                      int degF_child, const uint16_t* rank, const uint16_t* unrank, int uoff, const uint64_t* pack,
+                      SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
-    const size_t lds = size_t(2) << (k - 1);
-#define EDGE_M(M)                                                                                                    \
-    if (icnt)                                                                                                        \
-        k_slot_edge<false, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(                                          \
-            icnt, iflag, R_in, G, g, colors, k, degF_u, degF_child, rank, unrank, uoff, ocnt, oflag, part, ovf);     \
-    else                                                                                                             \
-        k_slot_edge<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(                                           \
-            icnt, iflag, R_in, G, g, colors, k, degF_u, degF_child, rank, unrank, uoff, ocnt, oflag, part, ovf)
+    if (!in.lo) {  // leaf child: output set size 2, R = k - 1
+        if (G.R != k - 1 || G.upb == 0) throw std::runtime_error("launch_slot_edge: a leaf child needs R = k - 1");
+        const size_t lds = 4 * (size_t(G.upb) * G.m * (k + 1) + 1);
+#define LEAF_EDGE_M(M) \
+    k_slot_edge_leaf<M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(G, g, colors, k, degF_u, degF_child, out, part)
+        SLOT_BY_M(LEAF_EDGE_M)
+#undef LEAF_EDGE_M
+        return;
+    }
+    if (pack && (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0))
+        throw std::runtime_error("launch_slot_edge: packed slots need k <= 8, n < 2^24 and R <= 256");
+    const size_t lds = pack ? 0 : size_t(2) << (k - 1);
+#define EDGE_ARGS in, G, g, colors, k, degF_u, rank, unrank, uoff, pack, out, part, ovf
+#define EDGE_M(M)                                                                     \
+    if (pack)                                                                         \
+        k_slot_edge<M, true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(EDGE_ARGS); \
+    else                                                                              \
+        k_slot_edge<M, false><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(EDGE_ARGS)
     SLOT_BY_M(EDGE_M)
 #undef EDGE_M
+#undef EDGE_ARGS
 }
 
-void launch_slot_join(const uint64_t* ycnt, const uint8_t* yflag, int R_y, const uint64_t* zcnt,
-                      const uint8_t* zflag, int R_z, const uint32_t* splits, int nsplit, int sstride,
-                      const SlotGrid& G, uint64_t* ocnt, uint8_t* oflag, uint64_t* part, uint32_t* ovf,
-                      hipStream_t s) {
+void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, const SlotGrid& G,
+                      SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
-    const bool stage = G.upb > 0 && slot_join_m(G.R, R_y, R_z, nsplit) >= G.m;
-    const size_t lds = stage ? size_t(G.upb) * G.m * size_t(R_y + R_z) * 9 + size_t(nsplit) * G.R * 4 : 0;
-#define JOIN_M(M)                                                                                             \
-    if (stage)                                                                                                \
-        k_slot_join<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(ycnt, yflag, R_y, zcnt, zflag, R_z,  \
-                                                                           splits, nsplit, sstride, G, ocnt,   \
-                                                                           oflag, part, ovf);                  \
-    else                                                                                                      \
-        k_slot_join<false, M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(ycnt, yflag, R_y, zcnt, zflag, R_z,   \
-                                                                          splits, nsplit, sstride, G, ocnt,    \
-                                                                          oflag, part, ovf)
+    const bool stage = G.upb > 0 && slot_join_m(G.R, y.R, z.R, nsplit) >= G.m;
+    const size_t lds = stage ? size_t(G.upb) * G.m * size_t(y.R + z.R) * 9 + size_t(nsplit) * G.R * 4 : 0;
+#define JOIN_M(M)                                                                                                      \
+    if (stage)                                                                                                         \
+        k_slot_join<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(y, z, splits, nsplit, sstride, G, out, part, \
+                                                                           ovf);                                       \
+    else                                                                                                               \
+        k_slot_join<false, M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(y, z, splits, nsplit, sstride, G, out, part,  \
+                                                                          ovf)
     SLOT_BY_M(JOIN_M)
 #undef JOIN_M
 }
 
-void launch_slot_root(const uint64_t* icnt, const uint8_t* iflag, int R_in, int s_in, int32_t n, int B,
-                      const uint8_t* colors, const uint16_t* unrank, uint64_t* rpart, uint64_t* counts, uint32_t* ovf,
-                      uint64_t* per_vertex, uint32_t* csets, int cwords, hipStream_t s) {
+void launch_slot_root(SlotArrays in, int s_in, int32_t n, int B, const uint8_t* colors, const uint16_t* unrank,
+                      uint64_t* rpart, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, uint32_t* csets,
+                      int cwords, hipStream_t s) {
     SlotGrid G = slot_grid(n, B, 1, 8);
     if (!G.blocks) {
         launch_fill_u64(counts, 0, uint64_t(B), s);
         return;
     }
-#define ROOT_M(M)                                                                                            \
-    k_slot_root<M><<<slot_dims(G.blocks), kSlotBlock, size_t(4) * cwords, s>>>(                              \
-        icnt, iflag, R_in, colors, unrank, slot_unrank_offset(s_in - 1), G, rpart, per_vertex, csets, cwords)
+#define ROOT_M(M)                                                                                                 \
+    k_slot_root<M><<<slot_dims(G.blocks), kSlotBlock, size_t(4) * cwords, s>>>(                                   \
+        in, colors, unrank, slot_unrank_offset(s_in - 1), G, rpart, per_vertex, csets, cwords)
     SLOT_BY_M(ROOT_M)
 #undef ROOT_M
     k_slot_root_sum<<<unsigned(B), kSlotBlock, 0, s>>>(rpart, G.nbx, counts, ovf);
