@@ -1,6 +1,7 @@
 // DP executor: runs a decomposition's plan (leaf / introduce / forget / join
 // steps in post-order, Sec. 3.1) over a batch of colourings on one stream.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "engine.h"
@@ -413,6 +414,12 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             launch_slot_sum(part, blocks, nsz + 2 * i, s);
         }
     };
+    // Every count of a table whose pattern subtree has s vertices is at most
+    // dmax^(s - 1): an embedding maps the subtree's vertices other than the
+    // bag vertex, parent before child, to neighbours of their parents'
+    // images.  log2 of that bound decides which arithmetic is exact.
+    const double ldmax = rq.g->sorted_deg.empty() ? 0.0 : std::log2(double(std::max<int64_t>(1, rq.g->sorted_deg.back())));
+    auto below = [&](int set, int bits) { return double(set - 1) * ldmax < double(bits) - 1e-9; };
     const uint16_t* rank = ctx->slot_tables;
     const uint16_t* unrank = ctx->slot_tables + (1 << kSlotBits);
     const double csr = double(B) * (9.0 * g.n + 4.0 * g.m2);
@@ -492,7 +499,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                                        : nullptr;
             X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 launch_slot_edge(in.a, G, g, rq.colors, k, degF_u, degF_c, rank, unrank, slot_unrank_offset(o.s - 1),
-                                 pack, o.a, part, ovf, s);
+                                 pack, !leafc && below(in.s, 32), o.a, part, ovf, s);
             });
             partials_done(i, G.blocks);
             tab[i + 1] = o;
@@ -530,8 +537,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const int nsplit = binom(p, q);
             SlotGrid G = slot_grid(g.n, B, o.a.R, std::max(1, slot_join_m(o.a.R, y.a.R, z.a.R, nsplit)));
             X.timed("slot_join", double(units) * 9.0 * (y.a.R + z.a.R + o.a.R), [&] {
-                launch_slot_join(y.a, z.a, ctx->slot_splits + slot_split_offset(p, q), nsplit, binom(kSlotBits, p), G,
-                                 o.a, part, ovf, s);
+                launch_slot_join(y.a, z.a, ctx->slot_splits + slot_split_offset(p, q), nsplit, binom(kSlotBits, p),
+                                 below(y.s, 32) && below(z.s, 32) && below(o.s, 64), G, o.a, part, ovf, s);
             });
             partials_done(i, G.blocks);
             tab[i] = o;

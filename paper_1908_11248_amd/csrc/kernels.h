@@ -247,17 +247,20 @@ std::vector<uint64_t> slot_pack_tables();
 size_t slot_pack_offset(int k, int p);
 // in.lo == nullptr: the child is a leaf (count 1 per vertex passing
 // degF_child).  pack: the entries of (k, p) above, or null (ranks from the
-// rank tables).  out.wide must be cleared beforehand.
+// rank tables).  in_narrow: every count of the child is known to be below
+// 2^32.  out.wide must be cleared beforehand.
 void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
                       int degF_child, const uint16_t* rank, const uint16_t* unrank, int uoff, const uint64_t* pack,
-                      SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
+                      bool in_narrow, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
 constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
 // split table rows of (p, q) (see slots.hip) start at slot_split_offset(p, q);
 // row stride C(kSlotBits, p)
 std::vector<uint32_t> slot_split_tables();
 int slot_split_offset(int p, int q);
-void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, const SlotGrid& G,
-                      SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
+// nowrap: both children's counts are known to be below 2^32 and the output's
+// below 2^64 (only honoured when the rows are staged)
+void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, bool nowrap,
+                      const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
 // rpart: slot_root_partials(n, B) words of scratch
 uint64_t slot_root_partials(int32_t n, int B);
 void launch_slot_root(SlotArrays in, int s_in, int32_t n, int B, const uint8_t* colors, const uint16_t* unrank,

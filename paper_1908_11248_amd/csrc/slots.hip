@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <stdexcept>
+#include <type_traits>
 
 #include "device.h"
 #include "kernels.h"
@@ -370,7 +371,7 @@ template <int M, bool PACK>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
             const uint16_t* __restrict__ rank, const uint16_t* __restrict__ unrank, int uoff,
-            const uint64_t* __restrict__ pack, SlotArrays out, uint64_t* part, uint32_t* ovf) {
+            const uint64_t* __restrict__ pack, bool in_narrow, SlotArrays out, uint64_t* part, uint32_t* ovf) {
     extern __shared__ uint16_t s_rank[];  // rank of every mask over k - 1 bits
     // staged neighbours: PACK: y | 8 colour << 24; otherwise the neighbour's
     // row offset y R_in (< 2^28) | colour << 28.  Four entries of padding let
@@ -419,7 +420,7 @@ k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ c
     // the child table of colouring b is exact (no count wrapped while it was
     // built) when b's overflow flag is still clear; then presence is count != 0
     const bool exact = v1 > v0 && ovf[b] == 0;
-    const bool narrow = in.wide[b] == 0;
+    const bool narrow = in_narrow || in.wide[b] == 0;
     const uint32_t rmask = (1u << (k - 1)) - 1u;  // keeps rank reads of masked-out lanes in the table
     const int64_t e_lo = v1 > v0 ? g.rp[v0] : 0, e_hi = v1 > v0 ? g.rp[v1] : 0;
     for (int64_t c0 = e_lo; c0 < e_hi; c0 += kEdgeChunk) {
@@ -517,10 +518,12 @@ k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ c
 // the low planes when both children's counts of the colouring are below
 // 2^32 (then products are exact in 64 bits), else both planes combined.
 // Presence bytes are read only for a colouring whose counts have wrapped.
+// nowrap (from a bound on the counts, see run_slots): both children are
+// narrow and no output sum can reach 2^64, so no wrap is tracked at all.
 template <bool STAGE, int M>
 __global__ void __launch_bounds__(kSlotBlock)
-k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int nsplit, int sstride, SlotGrid G,
-            SlotArrays out, uint64_t* part, uint32_t* ovf) {
+k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int nsplit, int sstride, bool nowrap,
+            SlotGrid G, SlotArrays out, uint64_t* part, uint32_t* ovf) {
     extern __shared__ uint64_t s_mem[];
     uint32_t b, v0, v1, jb, v, r;
     bool lane_ok;
@@ -529,7 +532,7 @@ k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int
     const uint32_t nu = v1 - v0;
     const uint64_t base = uint64_t(b) * uint32_t(G.n) + v0;  // first unit of the block
     const bool exact = v1 > v0 && ovf[b] == 0;
-    const bool narrow = y.wide[b] == 0 && z.wide[b] == 0;
+    const bool narrow = nowrap || (y.wide[b] == 0 && z.wide[b] == 0);
     const int R = G.R, R_y = y.R, R_z = z.R;
     // layout: [y counts][z counts][split rows][y flags][z flags]; narrow
     // rows are 32-bit words at the start of the count regions
@@ -563,13 +566,14 @@ k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int
     uint64_t sum[M];
     uint32_t pres = 0;
     bool over = false;
-    uint64_t by[M], bz[M];
+    using Idx = typename std::conditional<STAGE, uint32_t, uint64_t>::type;  // LDS or global row offsets
+    Idx by[M], bz[M];
 #pragma unroll
     for (int i = 0; i < M; i++) {
         sum[i] = 0;
         const uint64_t u = uint64_t(v - v0) + uint64_t(i) * G.upb;  // place within the block
-        by[i] = STAGE ? u * uint32_t(R_y) : (base + u) * uint32_t(R_y);
-        bz[i] = STAGE ? u * uint32_t(R_z) : (base + u) * uint32_t(R_z);
+        by[i] = Idx(STAGE ? u * uint32_t(R_y) : (base + u) * uint32_t(R_y));
+        bz[i] = Idx(STAGE ? u * uint32_t(R_z) : (base + u) * uint32_t(R_z));
     }
     bool live[M];
 #pragma unroll
@@ -585,7 +589,23 @@ k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int
             wrap[i] = 0;
             seen[i] = 0;
         }
-        if (narrow) {
+        if (nowrap) {
+            // exact sums of exact products: an entry is present iff its sum is not 0
+            for (int t = 0; t < nsplit; t++) {
+                const uint32_t e = s_sp[t * R + r];
+                const uint32_t ry = e & 0xffffu, rz = e >> 16;
+                uint32_t a[M], c[M];
+#pragma unroll
+                for (int i = 0; i < M; i++) {
+                    a[i] = s_y32[by[i] + ry];
+                    c[i] = s_z32[bz[i] + rz];
+                }
+#pragma unroll
+                for (int i = 0; i < M; i++) sum[i] += uint64_t(a[i]) * c[i];
+            }
+#pragma unroll
+            for (int i = 0; i < M; i++) seen[i] = sum[i] != 0;
+        } else if (narrow) {
             // products of 32-bit factors are exact and nonzero iff both factors
             // are, so the OR of the products tells presence; wraps are counted
             uint64_t orp[M];
@@ -976,7 +996,7 @@ void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, SlotArrays out, u
 
 void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
                       int degF_child, const uint16_t* rank, const uint16_t* unrank, int uoff, const uint64_t* pack,
-                      SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
+                      bool in_narrow, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
     if (!in.lo) {  // leaf child: output set size 2, R = k - 1
         if (G.R != k - 1 || G.upb == 0) throw std::runtime_error("launch_slot_edge: a leaf child needs R = k - 1");
@@ -990,7 +1010,7 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
     if (pack && (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0))
         throw std::runtime_error("launch_slot_edge: packed slots need k <= 8, n < 2^24 and R <= 256");
     const size_t lds = pack ? 0 : size_t(2) << (k - 1);
-#define EDGE_ARGS in, G, g, colors, k, degF_u, rank, unrank, uoff, pack, out, part, ovf
+#define EDGE_ARGS in, G, g, colors, k, degF_u, rank, unrank, uoff, pack, in_narrow, out, part, ovf
 #define EDGE_M(M)                                                                     \
     if (pack)                                                                         \
         k_slot_edge<M, true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(EDGE_ARGS); \
@@ -1001,18 +1021,18 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
 #undef EDGE_ARGS
 }
 
-void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, const SlotGrid& G,
-                      SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
+void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, bool nowrap,
+                      const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
     const bool stage = G.upb > 0 && slot_join_m(G.R, y.R, z.R, nsplit) >= G.m;
     const size_t lds = stage ? size_t(G.upb) * G.m * size_t(y.R + z.R) * 9 + size_t(nsplit) * G.R * 4 : 0;
 #define JOIN_M(M)                                                                                                      \
     if (stage)                                                                                                         \
-        k_slot_join<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(y, z, splits, nsplit, sstride, G, out, part, \
-                                                                           ovf);                                       \
+        k_slot_join<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(y, z, splits, nsplit, sstride, nowrap, G,   \
+                                                                           out, part, ovf);                            \
     else                                                                                                               \
-        k_slot_join<false, M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(y, z, splits, nsplit, sstride, G, out, part,  \
-                                                                          ovf)
+        k_slot_join<false, M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(y, z, splits, nsplit, sstride, false, G, out, \
+                                                                          part, ovf)
     SLOT_BY_M(JOIN_M)
 #undef JOIN_M
 }
