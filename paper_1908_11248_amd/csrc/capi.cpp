@@ -92,6 +92,12 @@ int cc_context_destroy(cc_context* ctx) {
         (void)hipSetDevice(ctx->device);
         for (auto& w : ctx->workers) w->destroy();
         ctx->main.destroy();
+        {
+            std::lock_guard<std::mutex> lk(ctx->color_pool->mu);
+            ctx->color_pool->alive = false;
+            for (auto& b : ctx->color_pool->idle) (void)hipFree(b.second);
+            ctx->color_pool->idle.clear();
+        }
         if (ctx->slot_tables) (void)hipFree(ctx->slot_tables);
         if (ctx->slot_splits) (void)hipFree(ctx->slot_splits);
         if (ctx->slot_pack) (void)hipFree(ctx->slot_pack);
@@ -209,6 +215,23 @@ void cc_graph_free(cc_graph* g) {
 
 int32_t cc_graph_num_vertices(const cc_graph* g) { return g ? g->n : -1; }
 
+// a device buffer of `bytes` for a colouring: an idle one of that size, else new
+static void color_buffer(cc_context* ctx, cc_coloring* c, size_t bytes) {
+    c->pool = ctx->color_pool;
+    c->bytes = bytes;
+    {
+        std::lock_guard<std::mutex> lk(c->pool->mu);
+        auto& idle = c->pool->idle;
+        for (size_t i = 0; i < idle.size(); i++)
+            if (idle[i].first == bytes) {
+                c->colors = idle[i].second;
+                idle.erase(idle.begin() + i);
+                return;
+            }
+    }
+    hip_check(hipMalloc(&c->colors, bytes), "hipMalloc colours");
+}
+
 int cc_color(cc_context* ctx, const cc_graph* g, int32_t k, uint64_t seed, int32_t num_colorings,
              cc_coloring** out) {
     return guarded([&] {
@@ -221,11 +244,11 @@ int cc_color(cc_context* ctx, const cc_graph* g, int32_t k, uint64_t seed, int32
         c->n = g->n;
         c->k = k;
         c->B = num_colorings;
-        size_t bytes = std::max<size_t>(1, size_t(g->n) * num_colorings);
-        hipError_t e = hipMalloc(&c->colors, bytes);
-        if (e != hipSuccess) {
+        try {
+            color_buffer(ctx, c, std::max<size_t>(1, size_t(g->n) * num_colorings));
+        } catch (...) {
             delete c;
-            hip_check(e, "hipMalloc colours");
+            throw;
         }
         launch_color_hash(c->colors, g->n, num_colorings, k, seed, ctx->main.stream);
         hip_check(hipStreamSynchronize(ctx->main.stream), "colour kernel");
@@ -247,13 +270,14 @@ int cc_color_explicit(cc_context* ctx, const cc_graph* g, int32_t k, int32_t num
         c->n = g->n;
         c->k = k;
         c->B = num_colorings;
-        hipError_t e = hipMalloc(&c->colors, std::max<size_t>(total, 1));
-        if (e != hipSuccess) {
+        try {
+            color_buffer(ctx, c, std::max<size_t>(total, 1));
+        } catch (...) {
             delete c;
-            hip_check(e, "hipMalloc colours");
+            throw;
         }
         if (total) {
-            e = hipMemcpy(c->colors, colors, total, hipMemcpyHostToDevice);
+            hipError_t e = hipMemcpy(c->colors, colors, total, hipMemcpyHostToDevice);
             if (e != hipSuccess) {
                 cc_coloring_free(c);
                 hip_check(e, "hipMemcpy colours");
@@ -275,7 +299,17 @@ int cc_coloring_download(const cc_coloring* c, int32_t b, uint8_t* colors_out) {
 
 void cc_coloring_free(cc_coloring* c) {
     if (!c) return;
-    if (c->colors) (void)hipFree(c->colors);
+    if (c->colors) {
+        bool kept = false;
+        if (c->pool) {
+            std::lock_guard<std::mutex> lk(c->pool->mu);
+            if (c->pool->alive && c->pool->idle.size() < ColorPool::kMax) {
+                c->pool->idle.push_back({c->bytes, c->colors});
+                kept = true;
+            }
+        }
+        if (!kept) (void)hipFree(c->colors);
+    }
     delete c;
 }
 

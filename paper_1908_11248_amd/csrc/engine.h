@@ -102,8 +102,20 @@ struct Lane {
 
 }  // namespace ccg
 
+// Device buffers of freed colourings, kept for the next colouring of the
+// same size (a hipMalloc and hipFree per colouring would stall every step).
+// Shared with the colourings, so a colouring freed after its context returns
+// its buffer to the device instead.
+struct ColorPool {
+    std::mutex mu;
+    bool alive = true;
+    std::vector<std::pair<size_t, uint8_t*>> idle;  // (bytes, buffer)
+    static constexpr size_t kMax = 8;
+};
+
 struct cc_context {
     int device = 0;
+    std::shared_ptr<ColorPool> color_pool = std::make_shared<ColorPool>();
     void* arena_mem = nullptr;
     ccg::Arena arena;
     ccg::Lane main;  // the lane of the single-query calls
@@ -138,6 +150,8 @@ struct cc_coloring {
     cc_context* ctx = nullptr;
     int32_t n = 0, k = 0, B = 0;
     uint8_t* colors = nullptr;  // [B][n] on the device
+    size_t bytes = 0;           // of the buffer
+    std::shared_ptr<ColorPool> pool;
 };
 
 struct cc_decomp {

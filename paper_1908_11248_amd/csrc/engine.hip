@@ -366,7 +366,7 @@ struct SlotTab {
 // sizes like the sparse path; the per-table budget is checked on the sizes
 // afterwards (same outcome as the check before each sparse allocation).
 void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector<char>& fuse,
-               const std::vector<char>& virt, const std::vector<int>& sz, uint32_t* ovf, RunResult* out) {
+               const std::vector<char>& virt, const std::vector<int>& sz, RunResult* out) {
     const Plan& plan = rq.dec->plan;
     const Decomp& dec = rq.dec->d;
     const DevGraph g = rq.g->dev();
@@ -395,10 +395,20 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     if (!one_sum) part_words = seg_max;
     const uint64_t root_off = part_words;
     part_words += slot_root_partials(g.n, B);
-    // node sizes, then the wide flags of every step's table (B words each)
-    uint64_t* nsz = X.alloc<uint64_t>(nsz_words + (uint64_t(S) * B + 1) / 2);
-    launch_fill_u64(nsz, 0, nsz_words + (uint64_t(S) * B + 1) / 2, s);
-    uint32_t* wide = reinterpret_cast<uint32_t*>(nsz + nsz_words);
+    // One block for everything the host reads back and every flag, cleared by
+    // one fill and copied back by one copy: counts (B words, written by the
+    // root), node sizes (nsz_words), then as 32-bit words the overflow flags
+    // (B), the root's colour-set bitmaps (B cwords) and, not copied back, the
+    // wide flags of every step's table (B each).
+    const int cwords = k >= 5 ? 1 << (k - 5) : 1;
+    const uint64_t res_words = B + nsz_words + (uint64_t(B) * (1 + cwords) + 1) / 2;
+    uint64_t* res = X.alloc<uint64_t>(res_words + (uint64_t(S) * B + 1) / 2);
+    launch_fill_u64(res, 0, res_words + (uint64_t(S) * B + 1) / 2, s);
+    uint64_t* counts = res;
+    uint64_t* nsz = res + B;
+    uint32_t* ovf = reinterpret_cast<uint32_t*>(nsz + nsz_words);
+    uint32_t* csets = ovf + B;
+    uint32_t* wide = reinterpret_cast<uint32_t*>(res + res_words);
     uint64_t* part_base = X.alloc<uint64_t>(part_words);
     uint64_t* part = part_base;  // this step's segment
     SlotSums sums;
@@ -552,23 +562,13 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     hip_check(hipGetLastError(), "kernel launch");
 
     const SlotTab& rc = tab[plan.root_child];
-    uint64_t* counts = X.alloc<uint64_t>(B);  // written by the root
     uint64_t* pv = nullptr;
     if (rq.per_vertex) pv = X.alloc<uint64_t>(units);  // every entry is written
-    const int cwords = k >= 5 ? 1 << (k - 5) : 1;
-    uint32_t* csets = X.alloc<uint32_t>(uint64_t(B) * cwords);
-    launch_fill_u32(csets, 0, uint64_t(B) * cwords, s);
     X.timed("slot_root", double(units) * 9.0 * rc.a.R, [&] {
         launch_slot_root(rc.a, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv, csets, cwords, s);
     });
-    out->counts.assign(B, 0);
-    std::vector<uint32_t> of(B, 0);
-    std::vector<uint64_t> sizes(2 * S, 0);
-    hip_check(hipMemcpyAsync(out->counts.data(), counts, 8 * size_t(B), hipMemcpyDeviceToHost, s), "copy counts");
-    hip_check(hipMemcpyAsync(of.data(), ovf, 4 * size_t(B), hipMemcpyDeviceToHost, s), "copy flags");
-    hip_check(hipMemcpyAsync(sizes.data(), nsz, 8 * 2 * S, hipMemcpyDeviceToHost, s), "copy sizes");
-    std::vector<uint32_t> cs(uint64_t(B) * cwords);
-    hip_check(hipMemcpyAsync(cs.data(), csets, 4 * cs.size(), hipMemcpyDeviceToHost, s), "copy colour sets");
+    std::vector<uint64_t> host(res_words);
+    hip_check(hipMemcpyAsync(host.data(), res, 8 * res_words, hipMemcpyDeviceToHost, s), "copy results");
     if (pv) {
         out->per_vertex.assign(units, 0);
         hip_check(hipMemcpyAsync(out->per_vertex.data(), pv, 8 * units, hipMemcpyDeviceToHost, s), "copy per-vertex");
@@ -576,6 +576,10 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     X.synced();
     X.lane.prof.resolve();
+    out->counts.assign(host.begin(), host.begin() + B);
+    const std::vector<uint64_t> sizes(host.begin() + B, host.begin() + B + nsz_words);
+    const uint32_t* of = reinterpret_cast<const uint32_t*>(host.data() + B + nsz_words);
+    const uint32_t* cs = of + B;
     for (int j : budgeted)
         if (rq.max_entries && sizes[j] > rq.max_entries)
             throw CcError{CC_ERANGE,
@@ -586,14 +590,11 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     out->overflow.assign(B, 0);
     for (int b = 0; b < B; b++) out->overflow[b] = of[b] ? 1 : 0;
     int64_t nzr = 0;
-    for (uint32_t w : cs) nzr += __builtin_popcount(w);
+    for (uint64_t i = 0; i < uint64_t(B) * cwords; i++) nzr += __builtin_popcount(cs[i]);
     out->node_sizes[dec.nodes.size() - 1] = nzr;
-    X.release(csets);
-    X.release(counts);
     X.release(pv);
-    X.release(nsz);
     X.release(part_base);
-    X.release(ovf);
+    X.release(res);
     drop(tab[plan.root_child]);
     X.synced();
     out->peak_bytes = X.peak;
@@ -656,8 +657,6 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         }
     }
     out->node_sizes.assign(dec.nodes.size(), 0);
-    uint32_t* ovf = X.alloc<uint32_t>(B);
-    launch_fill_u32(ovf, 0, B, s);
 
     // dense one-column tables when the plan allows them and they fit a
     // quarter of the arena
@@ -673,7 +672,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 fits = false;
         if (fits) {
             try {
-                run_slots(ctx, X, rq, fuse, virt, sz, ovf, out);
+                run_slots(ctx, X, rq, fuse, virt, sz, out);
             } catch (...) {
                 (void)hipStreamSynchronize(s);
                 X.release_all();
@@ -683,6 +682,8 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         }
     }
 
+    uint32_t* ovf = X.alloc<uint32_t>(B);
+    launch_fill_u32(ovf, 0, B, s);
     try {
         for (size_t i = 0; i < S; i++) {
             const Step& st = plan.steps[i];
