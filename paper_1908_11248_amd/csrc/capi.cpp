@@ -73,7 +73,11 @@ int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_conte
             std::vector<uint64_t> pk = slot_pack_tables();
             hip_check(hipMalloc(&c->slot_pack, pk.size() * 8), "hipMalloc");
             hip_check(hipMemcpy(c->slot_pack, pk.data(), pk.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
+            std::vector<uint16_t> pu = slot_push_tables();
+            hip_check(hipMalloc(&c->slot_push, pu.size() * 2), "hipMalloc");
+            hip_check(hipMemcpy(c->slot_push, pu.data(), pu.size() * 2, hipMemcpyHostToDevice), "hipMemcpy");
         } catch (...) {
+            if (c->slot_push) (void)hipFree(c->slot_push);
             if (c->slot_tables) (void)hipFree(c->slot_tables);
             if (c->slot_splits) (void)hipFree(c->slot_splits);
             if (c->slot_pack) (void)hipFree(c->slot_pack);
@@ -101,6 +105,7 @@ int cc_context_destroy(cc_context* ctx) {
         if (ctx->slot_tables) (void)hipFree(ctx->slot_tables);
         if (ctx->slot_splits) (void)hipFree(ctx->slot_splits);
         if (ctx->slot_pack) (void)hipFree(ctx->slot_pack);
+        if (ctx->slot_push) (void)hipFree(ctx->slot_push);
         if (ctx->arena_mem) (void)hipFree(ctx->arena_mem);
         delete ctx;
     });

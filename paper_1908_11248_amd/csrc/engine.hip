@@ -507,9 +507,16 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const uint64_t* pack = !leafc && k <= kSlotPackK && g.n < (1 << 24) && G.upb > 0
                                        ? ctx->slot_pack + slot_pack_offset(k, o.s - 1)
                                        : nullptr;
+            // push from the child's rows when its colour sets are the smaller
+            // side (C(k-1, s-2) < C(k-1, s-1)) and no count can wrap
+            const bool push = pack && 2 * in.s < k && below(o.s, 64) && in.a.R <= kSlotBlock;
             X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
-                launch_slot_edge(in.a, G, g, rq.colors, k, degF_u, degF_c, rank, unrank, slot_unrank_offset(o.s - 1),
-                                 pack, !leafc && below(in.s, 32), o.a, part, ovf, s);
+                if (push)
+                    launch_slot_edge_push(in.a, G, g, rq.colors, k, degF_u, ctx->slot_push + slot_push_offset(k, in.s - 1),
+                                          !below(o.s, 32), o.a, part, s);
+                else
+                    launch_slot_edge(in.a, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
+                                     slot_unrank_offset(o.s - 1), pack, !leafc && below(in.s, 32), o.a, part, ovf, s);
             });
             partials_done(i, G.blocks);
             tab[i + 1] = o;

@@ -508,6 +508,98 @@ k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ c
     count_entries(npres, nin, part, G.blocks);
 }
 
+// The same step pushed from the child's rows: a thread takes child slot r of
+// a neighbour entry (v, y) and, when colour(v) is not in the child's set C_y,
+// adds the child's count into v's output slot of C_y + colour(v), kept in
+// LDS.  With small child sets most child entries land in an output slot,
+// while most (output slot, neighbour) pairs of the gather find nothing.
+// Launched only when no count of this or any lower table can wrap (a degree
+// bound), so every child table is exact and a sum is present iff it is not
+// 0.  WIDE: 64-bit accumulators, else every output count is below 2^32.
+template <bool WIDE>
+__global__ void __launch_bounds__(kSlotBlock)
+k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
+                 const uint16_t* __restrict__ pmap, SlotArrays out, uint64_t* part) {
+    using Acc = typename std::conditional<WIDE, unsigned long long, uint32_t>::type;
+    // [upb M][R] accumulators, [upb M + 1] CSR offsets, [upb M] colours
+    extern __shared__ uint64_t s_dyn[];
+    __shared__ uint32_t s_y[kEdgeChunk];   // neighbour | colour << 24
+    __shared__ uint16_t s_lv[kEdgeChunk];  // its vertex within the block, 0xffff when masked
+    uint32_t b, v0, v1, jb, v, r;
+    bool lane_ok;
+    block_range(G, &b, &v0, &v1, &jb);
+    slot_of(G, v0, jb, &v, &r, &lane_ok);
+    const uint32_t nv = v1 - v0, cap = uint32_t(G.upb * G.m), R = uint32_t(G.R), R_in = uint32_t(in.R);
+    Acc* acc = reinterpret_cast<Acc*>(s_dyn);
+    uint32_t* s_off = reinterpret_cast<uint32_t*>(acc + cap * R);
+    uint8_t* s_cv = reinterpret_cast<uint8_t*>(s_off + cap + 1);
+    const uint64_t row0 = uint64_t(b) * uint32_t(g.n);
+    const uint8_t* cb = colors + row0;
+    const uint32_t* ilo = in.lo + row0 * R_in;
+    const uint32_t* ihi = in.hi + row0 * R_in;
+    const int64_t e_lo = nv ? g.rp[v0] : 0;
+    for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) acc[i] = 0;
+    for (uint32_t i = threadIdx.x; nv && i <= nv; i += kSlotBlock) s_off[i] = uint32_t(g.rp[v0 + i] - e_lo);
+    for (uint32_t i = threadIdx.x; i < nv; i += kSlotBlock) s_cv[i] = cb[v0 + i];
+    __syncthreads();
+    const uint32_t E = nv ? s_off[nv] : 0;
+    const uint32_t rows = kSlotBlock / R_in;  // neighbour entries per pass, R_in threads each
+    const uint32_t te = threadIdx.x / R_in, tr = threadIdx.x - te * R_in;
+    uint32_t nin = 0;
+    for (uint32_t c0 = 0; c0 < E; c0 += kEdgeChunk) {
+        const uint32_t cn = min(uint32_t(kEdgeChunk), E - c0);
+        for (uint32_t i0 = 0; i0 < cn; i0 += 4 * kSlotBlock) {
+            uint32_t y[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
+                y[j] = i < cn ? uint32_t(g.col[e_lo + c0 + i]) : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
+                const uint32_t c = cb[y[j]];
+                if (i < cn) s_y[i] = y[j] | (c << 24);
+            }
+        }
+        for (uint32_t lv = threadIdx.x; lv < nv; lv += kSlotBlock) {
+            const uint32_t a = max(s_off[lv], c0), z = min(s_off[lv + 1], c0 + cn);
+            const uint16_t mark = s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u) ? uint16_t(lv) : uint16_t(0xffff);
+            for (uint32_t e = a; e < z; e++) s_lv[e - c0] = mark;
+        }
+        __syncthreads();
+        if (te < rows) {
+            for (uint32_t e = te; e < cn; e += rows) {
+                const uint32_t ye = s_y[e], lv = s_lv[e];
+                const uint32_t y = ye & 0xffffffu, cy = ye >> 24;
+                const uint32_t idx = y * R_in + tr;  // < n R_in < 2^28
+                const uint32_t lo = ilo[idx];
+                const uint32_t hi = WIDE ? ihi[idx] : 0u;
+                if (lv == 0xffffu) continue;
+                const uint32_t slot = pmap[(cy * uint32_t(k) + s_cv[lv]) * R_in + tr];
+                const Acc val = WIDE ? (Acc(hi) << 32) | lo : Acc(lo);
+                if (slot == 0xffffu || val == 0) continue;
+                nin++;
+                atomicAdd(&acc[lv * R + slot], val);
+            }
+        }
+        __syncthreads();
+    }
+    uint32_t npres = 0, hi = 0;
+#pragma unroll 4
+    for (int i = 0; i < G.m; i++) {
+        const uint32_t vi = v + uint32_t(i * G.upb);
+        if (lane_ok && vi < v1) {
+            const uint64_t c = acc[(vi - v0) * R + r];
+            store_slot(out, (row0 + vi) * R + r, c, c != 0);
+            npres += c != 0;
+            hi |= uint32_t(c >> 32);
+        }
+    }
+    flag_wide(hi, &out.wide[b]);
+    count_entries(npres, nin, part, G.blocks);
+}
+
 // Join on a one-vertex bag (Sec. 3, join nodes): output slot (b, v, C) sums
 // y(C_y) * z(C_z) over the splits of C - colour(v) into disjoint parts of the
 // children's sizes.  The splits of slot r are the same for every vertex and
@@ -969,6 +1061,36 @@ std::vector<uint64_t> slot_pack_tables() {
     return t;
 }
 
+size_t slot_push_offset(int k, int p) {
+    size_t off = 0;
+    for (int kk = 2; kk <= kSlotPackK; kk++)
+        for (int pp = 0; pp < kk - 1; pp++) {
+            if (kk == k && pp == p) return off;
+            off += size_t(kk) * kk * binom_pq(kk - 1, pp);
+        }
+    return off;  // past the last: the total
+}
+
+std::vector<uint16_t> slot_push_tables() {
+    std::vector<uint16_t> rt = slot_rank_tables();
+    const int M = 1 << kSlotBits;
+    std::vector<uint16_t> t(slot_push_offset(kSlotPackK + 1, 0));
+    for (int k = 2; k <= kSlotPackK; k++)
+        for (int p = 0; p < k - 1; p++) {
+            const int R = binom_pq(k - 1, p);
+            const size_t off = slot_push_offset(k, p);
+            for (int cy = 0; cy < k; cy++)
+                for (int cv = 0; cv < k; cv++)
+                    for (int r = 0; r < R; r++) {
+                        // the child's set over k bits, its own colour included
+                        const uint32_t C = bit_open(rt[M + slot_unrank_offset(p) + r], uint32_t(cy)) | (1u << cy);
+                        t[off + (size_t(cy) * k + cv) * R + r] =
+                            (C >> cv) & 1u ? uint16_t(0xffff) : rt[bit_close(C, uint32_t(cv))];
+                    }
+        }
+    return t;
+}
+
 // vertices per thread with which a join block stages its children's rows and
 // split rows in kSlotJoinLds (0: none fit)
 int slot_join_m(int R_out, int R_y, int R_z, int nsplit) {
@@ -1019,6 +1141,19 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
     SLOT_BY_M(EDGE_M)
 #undef EDGE_M
 #undef EDGE_ARGS
+}
+
+void launch_slot_edge_push(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
+                           const uint16_t* push, bool wide, SlotArrays out, uint64_t* part, hipStream_t s) {
+    if (!G.blocks) return;
+    if (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0 || in.R > kSlotBlock)
+        throw std::runtime_error("launch_slot_edge_push: needs k <= 8, n < 2^24 and R <= 256");
+    const size_t cap = size_t(G.upb) * G.m;
+    const size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + cap;
+    if (wide)
+        k_slot_edge_push<true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, out, part);
+    else
+        k_slot_edge_push<false><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, out, part);
 }
 
 void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, bool nowrap,

@@ -5,7 +5,9 @@ over colourings) must be identical, bit for bit, on both paths.
 
 Batches of 9 colourings cover the XCD-interleaved block mapping with a
 ragged last group; k = 12 with 7-vertex trees gives 462 slots per vertex,
-more than one block's threads.
+more than one block's threads.  Trees with k <= 8 run the edge steps in
+both the gather and the push form, and a graph with a hub covers their
+64-bit variants.
 """
 import sys
 
@@ -69,6 +71,41 @@ def test_trees_dense_and_sparse_match_oracle(ctx, gname, make):
             assert np.array_equal(sd, ref_sizes), (gname, pat.name, k)
             assert np.array_equal(ss, ref_sizes), (gname, pat.name, k)
             C.close()
+
+
+def hub_graph(n=2500, m=3000, seed=5):
+    # vertex 0 adjacent to every other vertex, plus random edges: a degree
+    # bound of 2499^(s-1) puts 4-vertex subtrees past 2^32, so the push form
+    # of the edge step runs with 64-bit accumulators and the gather reads
+    # both count planes
+    rng = np.random.default_rng(seed)
+    a, b = rng.integers(1, n, m), rng.integers(1, n, m)
+    keep = a != b
+    src = np.concatenate([np.zeros(n - 1, dtype=np.int64), a[keep]])
+    dst = np.concatenate([np.arange(1, n), b[keep]])
+    return W.csr_from_edges(n, src, dst)
+
+
+@pytest.mark.parametrize("pat", [W.path(5), W.random_tree(6, 3), W.random_tree(7, 5)], ids=lambda p: p.name)
+def test_hub_graph_dense_and_sparse_match_oracle(ctx, pat):
+    g = hub_graph()
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    rng = np.random.default_rng(pat.n)
+    B, k = 5, 8
+    colors = rng.integers(0, k, size=(B, g.n)).astype(np.uint8)
+    say("hub", pat.name)
+    D = cc.build_decomposition(pat.n, pat.edges)
+    C = cc.color_explicit(ctx, G, k, colors)
+    cd, od, sd = run(ctx, G, C, D, 0)
+    cs, os_, ss = run(ctx, G, C, D, SPARSE)
+    ref_sizes = np.zeros(len(sd), dtype=np.int64)
+    for b in range(B):
+        ref = O.dp_count(g, pat, k, colors[b], td=D.export(), sizes=True)
+        assert int(cd[b]) == ref["count"] and bool(od[b]) == ref["overflow"], (pat.name, b)
+        ref_sizes += ref["sizes"]
+    assert np.array_equal(cd, cs) and np.array_equal(od, os_)
+    assert np.array_equal(sd, ref_sizes) and np.array_equal(ss, ref_sizes)
+    C.close()
 
 
 def test_overflow_on_both_paths(ctx):
