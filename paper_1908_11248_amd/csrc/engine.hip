@@ -433,14 +433,17 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     const uint16_t* rank = ctx->slot_tables;
     const uint16_t* unrank = ctx->slot_tables + (1 << kSlotBits);
     const double csr = double(B) * (9.0 * g.n + 4.0 * g.m2);
+    // a high plane only where counts can reach 2^32, presence bytes only
+    // where they can wrap
     auto make = [&](int set, size_t step) {
         SlotTab t;
         t.s = set;
         t.a.R = binom(k - 1, set - 1);
         t.a.wide = wide + step * B;
-        t.a.lo = X.alloc<uint32_t>(2 * units * t.a.R);
-        t.a.hi = t.a.lo + units * t.a.R;
-        t.a.flag = X.alloc<uint8_t>(units * t.a.R);
+        const uint64_t n = units * t.a.R;
+        t.a.lo = X.alloc<uint32_t>(below(set, 32) ? n : 2 * n);
+        t.a.hi = below(set, 32) ? nullptr : t.a.lo + n;
+        t.a.flag = below(set, 64) ? nullptr : X.alloc<uint8_t>(n);
         return t;
     };
     auto drop = [&](SlotTab& t) {
@@ -516,7 +519,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                                           !below(o.s, 32), o.a, part, s);
                 else
                     launch_slot_edge(in.a, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
-                                     slot_unrank_offset(o.s - 1), pack, !leafc && below(in.s, 32), o.a, part, ovf, s);
+                                     slot_unrank_offset(o.s - 1), pack, !leafc && below(in.s, 32),
+                                     !leafc && below(in.s, 64), o.a, part, ovf, s);
             });
             partials_done(i, G.blocks);
             tab[i + 1] = o;
@@ -555,7 +559,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             SlotGrid G = slot_grid(g.n, B, o.a.R, std::max(1, slot_join_m(o.a.R, y.a.R, z.a.R, nsplit)));
             X.timed("slot_join", double(units) * 9.0 * (y.a.R + z.a.R + o.a.R), [&] {
                 launch_slot_join(y.a, z.a, ctx->slot_splits + slot_split_offset(p, q), nsplit, binom(kSlotBits, p),
-                                 below(y.s, 32) && below(z.s, 32) && below(o.s, 64), G, o.a, part, ovf, s);
+                                 below(y.s, 32) && below(z.s, 32) && below(o.s, 64), below(y.s, 64) && below(z.s, 64),
+                                 G, o.a, part, ovf, s);
             });
             partials_done(i, G.blocks);
             tab[i] = o;

@@ -210,7 +210,10 @@ struct SlotGrid {
 SlotGrid slot_grid(int32_t n, int B, int R, int m_max);
 // A slot table on the device: counts mod 2^64 as two planes of 32-bit words
 // (low, high), presence bytes, each [B][n][R], and wide[b], set when some
-// count of colouring b is 2^32 or more (then the high plane matters).
+// count of colouring b is 2^32 or more (then the high plane matters).  A
+// table whose counts a bound keeps below 2^32 has no high plane (hi null),
+// and one whose counts cannot wrap has no presence bytes (flag null: an
+// entry is present iff its count is not 0).
 struct SlotArrays {
     uint32_t* lo = nullptr;
     uint32_t* hi = nullptr;
@@ -254,10 +257,10 @@ size_t slot_push_offset(int k, int p);
 // in.lo == nullptr: the child is a leaf (count 1 per vertex passing
 // degF_child).  pack: the entries of (k, p) above, or null (ranks from the
 // rank tables).  in_narrow: every count of the child is known to be below
-// 2^32.  out.wide must be cleared beforehand.
+// 2^32; in_exact: no count of the child can have wrapped.  out.wide must be cleared beforehand.
 void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
                       int degF_child, const uint16_t* rank, const uint16_t* unrank, int uoff, const uint64_t* pack,
-                      bool in_narrow, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
+                      bool in_narrow, bool in_exact, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
 // The same step pushed from the child's rows into LDS accumulators; only for
 // a step whose counts cannot wrap (then every table below is exact).  push:
 // the entries of (k, child size - 1) above; wide: 64-bit accumulators (else
@@ -270,9 +273,10 @@ constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage i
 std::vector<uint32_t> slot_split_tables();
 int slot_split_offset(int p, int q);
 // nowrap: both children's counts are known to be below 2^32 and the output's
-// below 2^64 (only honoured when the rows are staged)
+// below 2^64 (only honoured when the rows are staged); in_exact: no count of
+// either child can have wrapped
 void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, bool nowrap,
-                      const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
+                      bool in_exact, const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
 // rpart: slot_root_partials(n, B) words of scratch
 uint64_t slot_root_partials(int32_t n, int B);
 void launch_slot_root(SlotArrays in, int s_in, int32_t n, int B, const uint8_t* colors, const uint16_t* unrank,

@@ -164,7 +164,7 @@ __device__ __forceinline__ void stage_copy(T* dst, const T* __restrict__ src, ui
     if (ored) *ored |= acc;  // the OR of this thread's values
 }
 
-// dst[i] = lo[i] | hi[i] << 32 for i < n by the block
+// dst[i] = lo[i] | hi[i] << 32 for i < n by the block (no high plane: 0)
 __device__ __forceinline__ void stage_pair(uint64_t* dst, const uint32_t* __restrict__ lo,
                                            const uint32_t* __restrict__ hi, uint32_t n) {
     for (uint32_t i0 = 0; i0 < n; i0 += 2 * kSlotBlock) {
@@ -173,7 +173,7 @@ __device__ __forceinline__ void stage_pair(uint64_t* dst, const uint32_t* __rest
         for (int j = 0; j < 2; j++) {
             const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
             l[j] = i < n ? lo[i] : 0u;
-            h[j] = i < n ? hi[i] : 0u;
+            h[j] = i < n && hi ? hi[i] : 0u;
         }
 #pragma unroll
         for (int j = 0; j < 2; j++) {
@@ -183,12 +183,13 @@ __device__ __forceinline__ void stage_pair(uint64_t* dst, const uint32_t* __rest
     }
 }
 
-// stores a count into the two planes and its presence byte (streaming: the
-// output is not read again by the kernel that writes it)
+// stores a count into the planes and its presence byte, the high plane and
+// the bytes only where the table has them (streaming: the output is not read
+// again by the kernel that writes it)
 __device__ __forceinline__ void store_slot(const SlotArrays& o, uint64_t i, uint64_t c, bool present) {
     __builtin_nontemporal_store(uint32_t(c), &o.lo[i]);
-    __builtin_nontemporal_store(uint32_t(c >> 32), &o.hi[i]);
-    __builtin_nontemporal_store(uint8_t(present), &o.flag[i]);
+    if (o.hi) __builtin_nontemporal_store(uint32_t(c >> 32), &o.hi[i]);
+    if (o.flag) __builtin_nontemporal_store(uint8_t(present), &o.flag[i]);
 }
 
 // Four staged neighbours of one vertex with packed child slots: entry e =
@@ -371,7 +372,8 @@ template <int M, bool PACK>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
             const uint16_t* __restrict__ rank, const uint16_t* __restrict__ unrank, int uoff,
-            const uint64_t* __restrict__ pack, bool in_narrow, SlotArrays out, uint64_t* part, uint32_t* ovf) {
+            const uint64_t* __restrict__ pack, bool in_narrow, bool in_exact, SlotArrays out, uint64_t* part,
+            uint32_t* ovf) {
     extern __shared__ uint16_t s_rank[];  // rank of every mask over k - 1 bits
     // staged neighbours: PACK: y | 8 colour << 24; otherwise the neighbour's
     // row offset y R_in (< 2^28) | colour << 28.  Four entries of padding let
@@ -386,8 +388,8 @@ k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ c
     const uint64_t row0 = uint64_t(b) * n;
     // colouring b's part of the child table (n * R_in < 2^28 slots)
     const uint32_t* ilo = in.lo + row0 * R_in;
-    const uint32_t* ihi = in.hi + row0 * R_in;
-    const uint8_t* ifl = in.flag + row0 * R_in;
+    const uint32_t* ihi = in.hi ? in.hi + row0 * R_in : nullptr;
+    const uint8_t* ifl = in.flag ? in.flag + row0 * R_in : nullptr;
     if (!PACK) stage_rank(s_rank, rank, k);
     const uint8_t* cb = colors + row0;
     int64_t rb[M], re[M];
@@ -418,9 +420,10 @@ k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ c
         }
     }
     // the child table of colouring b is exact (no count wrapped while it was
-    // built) when b's overflow flag is still clear; then presence is count != 0
-    const bool exact = v1 > v0 && ovf[b] == 0;
-    const bool narrow = in_narrow || in.wide[b] == 0;
+    // built) when a bound says so or b's overflow flag is still clear; then
+    // presence is count != 0 (and the child has presence bytes otherwise)
+    const bool exact = in_exact || (v1 > v0 && ovf[b] == 0);
+    const bool narrow = in_narrow || !ihi || in.wide[b] == 0;
     const uint32_t rmask = (1u << (k - 1)) - 1u;  // keeps rank reads of masked-out lanes in the table
     const int64_t e_lo = v1 > v0 ? g.rp[v0] : 0, e_hi = v1 > v0 ? g.rp[v1] : 0;
     for (int64_t c0 = e_lo; c0 < e_hi; c0 += kEdgeChunk) {
@@ -536,7 +539,7 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     const uint64_t row0 = uint64_t(b) * uint32_t(g.n);
     const uint8_t* cb = colors + row0;
     const uint32_t* ilo = in.lo + row0 * R_in;
-    const uint32_t* ihi = in.hi + row0 * R_in;
+    const uint32_t* ihi = in.hi ? in.hi + row0 * R_in : nullptr;
     const int64_t e_lo = nv ? g.rp[v0] : 0;
     for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) acc[i] = 0;
     for (uint32_t i = threadIdx.x; nv && i <= nv; i += kSlotBlock) s_off[i] = uint32_t(g.rp[v0 + i] - e_lo);
@@ -574,7 +577,7 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
                 const uint32_t y = ye & 0xffffffu, cy = ye >> 24;
                 const uint32_t idx = y * R_in + tr;  // < n R_in < 2^28
                 const uint32_t lo = ilo[idx];
-                const uint32_t hi = WIDE ? ihi[idx] : 0u;
+                const uint32_t hi = WIDE && ihi ? ihi[idx] : 0u;
                 if (lv == 0xffffu) continue;
                 const uint32_t slot = pmap[(cy * uint32_t(k) + s_cv[lv]) * R_in + tr];
                 const Acc val = WIDE ? (Acc(hi) << 32) | lo : Acc(lo);
@@ -615,7 +618,7 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
 template <bool STAGE, int M>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int nsplit, int sstride, bool nowrap,
-            SlotGrid G, SlotArrays out, uint64_t* part, uint32_t* ovf) {
+            bool in_exact, SlotGrid G, SlotArrays out, uint64_t* part, uint32_t* ovf) {
     extern __shared__ uint64_t s_mem[];
     uint32_t b, v0, v1, jb, v, r;
     bool lane_ok;
@@ -623,7 +626,10 @@ k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int
     slot_of(G, v0, jb, &v, &r, &lane_ok);
     const uint32_t nu = v1 - v0;
     const uint64_t base = uint64_t(b) * uint32_t(G.n) + v0;  // first unit of the block
-    const bool exact = v1 > v0 && ovf[b] == 0;
+    // both children exact (by a bound, or no wrap yet in colouring b): an
+    // entry is present iff its count is not 0; otherwise a child without
+    // presence bytes is exact by its bound
+    const bool exact = in_exact || (v1 > v0 && ovf[b] == 0);
     const bool narrow = nowrap || (y.wide[b] == 0 && z.wide[b] == 0);
     const int R = G.R, R_y = y.R, R_z = z.R;
     // layout: [y counts][z counts][split rows][y flags][z flags]; narrow
@@ -642,17 +648,15 @@ k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int
             stage_copy(s_y32, y.lo + base * uint32_t(R_y), ny);
             stage_copy(s_z32, z.lo + base * uint32_t(R_z), nz);
         } else {
-            stage_pair(s_yc, y.lo + base * uint32_t(R_y), y.hi + base * uint32_t(R_y), ny);
-            stage_pair(s_zc, z.lo + base * uint32_t(R_z), z.hi + base * uint32_t(R_z), nz);
+            stage_pair(s_yc, y.lo + base * uint32_t(R_y), y.hi ? y.hi + base * uint32_t(R_y) : nullptr, ny);
+            stage_pair(s_zc, z.lo + base * uint32_t(R_z), z.hi ? z.hi + base * uint32_t(R_z) : nullptr, nz);
         }
         for (uint32_t i = threadIdx.x; i < uint32_t(nsplit * R); i += kSlotBlock) {
             const uint32_t t = i / uint32_t(R);
             s_sp[i] = splits[size_t(t) * sstride + (i - t * uint32_t(R))];
         }
-        if (!exact) {
-            stage_copy(s_yf, y.flag + base * uint32_t(R_y), ny);
-            stage_copy(s_zf, z.flag + base * uint32_t(R_z), nz);
-        }
+        if (!exact && y.flag) stage_copy(s_yf, y.flag + base * uint32_t(R_y), ny);
+        if (!exact && z.flag) stage_copy(s_zf, z.flag + base * uint32_t(R_z), nz);
         __syncthreads();
     }
     uint64_t sum[M];
@@ -756,11 +760,12 @@ k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int
                     a = narrow ? s_y32[iy] : s_yc[iy];
                     c = narrow ? s_z32[iz] : s_zc[iz];
                 } else {
-                    a = uint64_t(y.lo[iy]) | (uint64_t(y.hi[iy]) << 32);
-                    c = uint64_t(z.lo[iz]) | (uint64_t(z.hi[iz]) << 32);
+                    a = uint64_t(y.lo[iy]) | (y.hi ? uint64_t(y.hi[iy]) << 32 : 0);
+                    c = uint64_t(z.lo[iz]) | (z.hi ? uint64_t(z.hi[iz]) << 32 : 0);
                 }
-                const bool f = exact ? (a != 0 && c != 0)
-                                     : (STAGE ? (s_yf[iy] && s_zf[iz]) : (y.flag[iy] && z.flag[iz]));
+                const bool fy = exact || !y.flag ? a != 0 : (STAGE ? s_yf[iy] : y.flag[iy]) != 0;
+                const bool fz = exact || !z.flag ? c != 0 : (STAGE ? s_zf[iz] : z.flag[iz]) != 0;
+                const bool f = fy && fz;
                 if (!f) continue;
                 uint64_t pr;
                 if (((a | c) >> 32) == 0) {
@@ -814,15 +819,15 @@ k_slot_root(SlotArrays in, const uint8_t* __restrict__ colors, const uint16_t* _
         const uint64_t unit = uint64_t(b) * uint32_t(G.n) + vi;
         const int R_in = in.R;
         const uint32_t* pl = in.lo + unit * uint32_t(R_in);
-        const uint32_t* ph = in.hi + unit * uint32_t(R_in);
-        const uint8_t* f = in.flag + unit * uint32_t(R_in);
+        const uint32_t* ph = in.hi ? in.hi + unit * uint32_t(R_in) : nullptr;
+        const uint8_t* f = in.flag ? in.flag + unit * uint32_t(R_in) : nullptr;
         const uint32_t cv = colors[unit];
         uint64_t us = 0;
         for (int j = 0; j < R_in; j++) {
-            const uint64_t c = uint64_t(pl[j]) | (uint64_t(ph[j]) << 32);
+            const uint64_t c = uint64_t(pl[j]) | (ph ? uint64_t(ph[j]) << 32 : 0);
             us += c;
             over |= us < c;
-            if (f[j]) {
+            if (f ? f[j] != 0 : c != 0) {  // no presence bytes: exact by a bound
                 const uint32_t C = bit_open(unrank[uoff + j], cv) | (1u << cv);
                 atomicOr(&s_cs[C >> 5], 1u << (C & 31));
             }
@@ -1118,7 +1123,7 @@ void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, SlotArrays out, u
 
 void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
                       int degF_child, const uint16_t* rank, const uint16_t* unrank, int uoff, const uint64_t* pack,
-                      bool in_narrow, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
+                      bool in_narrow, bool in_exact, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
     if (!in.lo) {  // leaf child: output set size 2, R = k - 1
         if (G.R != k - 1 || G.upb == 0) throw std::runtime_error("launch_slot_edge: a leaf child needs R = k - 1");
@@ -1132,7 +1137,7 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
     if (pack && (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0))
         throw std::runtime_error("launch_slot_edge: packed slots need k <= 8, n < 2^24 and R <= 256");
     const size_t lds = pack ? 0 : size_t(2) << (k - 1);
-#define EDGE_ARGS in, G, g, colors, k, degF_u, rank, unrank, uoff, pack, in_narrow, out, part, ovf
+#define EDGE_ARGS in, G, g, colors, k, degF_u, rank, unrank, uoff, pack, in_narrow, in_exact, out, part, ovf
 #define EDGE_M(M)                                                                     \
     if (pack)                                                                         \
         k_slot_edge<M, true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(EDGE_ARGS); \
@@ -1157,17 +1162,17 @@ void launch_slot_edge_push(SlotArrays in, const SlotGrid& G, DevGraph g, const u
 }
 
 void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, bool nowrap,
-                      const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
+                      bool in_exact, const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
     const bool stage = G.upb > 0 && slot_join_m(G.R, y.R, z.R, nsplit) >= G.m;
     const size_t lds = stage ? size_t(G.upb) * G.m * size_t(y.R + z.R) * 9 + size_t(nsplit) * G.R * 4 : 0;
 #define JOIN_M(M)                                                                                                      \
     if (stage)                                                                                                         \
-        k_slot_join<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(y, z, splits, nsplit, sstride, nowrap, G,   \
-                                                                           out, part, ovf);                            \
+        k_slot_join<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(y, z, splits, nsplit, sstride, nowrap,      \
+                                                                           in_exact, G, out, part, ovf);               \
     else                                                                                                               \
-        k_slot_join<false, M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(y, z, splits, nsplit, sstride, false, G, out, \
-                                                                          part, ovf)
+        k_slot_join<false, M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(y, z, splits, nsplit, sstride, false,         \
+                                                                          in_exact, G, out, part, ovf)
     SLOT_BY_M(JOIN_M)
 #undef JOIN_M
 }
