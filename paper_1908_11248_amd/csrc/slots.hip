@@ -164,6 +164,28 @@ __device__ __forceinline__ void stage_copy(T* dst, const T* __restrict__ src, ui
     if (ored) *ored |= acc;  // the OR of this thread's values
 }
 
+// the two copies of stage_copy by the block at once: eight loads per
+// thread in flight, four from each source
+template <class T>
+__device__ __forceinline__ void stage_copy2(T* d0, const T* __restrict__ s0, uint32_t n0, T* d1,
+                                            const T* __restrict__ s1, uint32_t n1) {
+    for (uint32_t i0 = 0; i0 < max(n0, n1); i0 += 4 * kSlotBlock) {
+        T v0[4], v1[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
+            v0[j] = i < n0 ? s0[i] : T(0);
+            v1[j] = i < n1 ? s1[i] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
+            if (i < n0) d0[i] = v0[j];
+            if (i < n1) d1[i] = v1[j];
+        }
+    }
+}
+
 // dst[i] = lo[i] | hi[i] << 32 for i < n by the block (no high plane: 0)
 __device__ __forceinline__ void stage_pair(uint64_t* dst, const uint32_t* __restrict__ lo,
                                            const uint32_t* __restrict__ hi, uint32_t n) {
@@ -633,20 +655,20 @@ k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int
     const bool narrow = nowrap || (y.wide[b] == 0 && z.wide[b] == 0);
     const int R = G.R, R_y = y.R, R_z = z.R;
     // layout: [y counts][z counts][split rows][y flags][z flags]; narrow
-    // rows are 32-bit words at the start of the count regions
+    // rows are 32-bit words at the start of the count regions.  nowrap:
+    // [y words][z words][split rows] (exact, so no flags)
     const size_t cap = STAGE ? size_t(G.upb) * M : 0;
     uint64_t* s_yc = s_mem;
     uint64_t* s_zc = s_yc + cap * R_y;
     uint32_t* s_y32 = reinterpret_cast<uint32_t*>(s_yc);
-    uint32_t* s_z32 = reinterpret_cast<uint32_t*>(s_zc);
-    uint32_t* s_sp = reinterpret_cast<uint32_t*>(s_zc + cap * R_z);
+    uint32_t* s_z32 = nowrap ? s_y32 + cap * R_y : reinterpret_cast<uint32_t*>(s_zc);
+    uint32_t* s_sp = nowrap ? s_z32 + cap * R_z : reinterpret_cast<uint32_t*>(s_zc + cap * R_z);
     uint8_t* s_yf = reinterpret_cast<uint8_t*>(s_sp + (STAGE ? size_t(nsplit) * R : 0));
     uint8_t* s_zf = s_yf + cap * R_y;
     if (STAGE) {
         const uint32_t ny = nu * uint32_t(R_y), nz = nu * uint32_t(R_z);
         if (narrow) {
-            stage_copy(s_y32, y.lo + base * uint32_t(R_y), ny);
-            stage_copy(s_z32, z.lo + base * uint32_t(R_z), nz);
+            stage_copy2(s_y32, y.lo + base * uint32_t(R_y), ny, s_z32, z.lo + base * uint32_t(R_z), nz);
         } else {
             stage_pair(s_yc, y.lo + base * uint32_t(R_y), y.hi ? y.hi + base * uint32_t(R_y) : nullptr, ny);
             stage_pair(s_zc, z.lo + base * uint32_t(R_z), z.hi ? z.hi + base * uint32_t(R_z) : nullptr, nz);
@@ -1165,7 +1187,9 @@ void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int ns
                       bool in_exact, const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
     const bool stage = G.upb > 0 && slot_join_m(G.R, y.R, z.R, nsplit) >= G.m;
-    const size_t lds = stage ? size_t(G.upb) * G.m * size_t(y.R + z.R) * 9 + size_t(nsplit) * G.R * 4 : 0;
+    const size_t lds = !stage   ? 0
+                       : nowrap ? size_t(G.upb) * G.m * size_t(y.R + z.R) * 4 + size_t(nsplit) * G.R * 4
+                                : size_t(G.upb) * G.m * size_t(y.R + z.R) * 9 + size_t(nsplit) * G.R * 4;
 #define JOIN_M(M)                                                                                                      \
     if (stage)                                                                                                         \
         k_slot_join<true, M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(y, z, splits, nsplit, sstride, nowrap,      \
