@@ -546,7 +546,8 @@ __global__ void __launch_bounds__(kSlotBlock)
 k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
                  const uint16_t* __restrict__ pmap, SlotArrays out, uint64_t* part) {
     using Acc = typename std::conditional<WIDE, unsigned long long, uint32_t>::type;
-    // [upb M][R] accumulators, [upb M + 1] CSR offsets, [upb M] colours
+    // [upb M][R] accumulators, [upb M + 1] CSR offsets, the k k R_in output
+    // slots of pmap, [upb M] colours
     extern __shared__ uint64_t s_dyn[];
     __shared__ uint32_t s_y[kEdgeChunk];   // neighbour | colour << 24
     __shared__ uint16_t s_lv[kEdgeChunk];  // its vertex within the block, 0xffff when masked
@@ -557,7 +558,8 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     const uint32_t nv = v1 - v0, cap = uint32_t(G.upb * G.m), R = uint32_t(G.R), R_in = uint32_t(in.R);
     Acc* acc = reinterpret_cast<Acc*>(s_dyn);
     uint32_t* s_off = reinterpret_cast<uint32_t*>(acc + cap * R);
-    uint8_t* s_cv = reinterpret_cast<uint8_t*>(s_off + cap + 1);
+    uint16_t* s_pm = reinterpret_cast<uint16_t*>(s_off + cap + 1);
+    uint8_t* s_cv = reinterpret_cast<uint8_t*>(s_pm + k * k * R_in);
     const uint64_t row0 = uint64_t(b) * uint32_t(g.n);
     const uint8_t* cb = colors + row0;
     const uint32_t* ilo = in.lo + row0 * R_in;
@@ -566,6 +568,7 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) acc[i] = 0;
     for (uint32_t i = threadIdx.x; nv && i <= nv; i += kSlotBlock) s_off[i] = uint32_t(g.rp[v0 + i] - e_lo);
     for (uint32_t i = threadIdx.x; i < nv; i += kSlotBlock) s_cv[i] = cb[v0 + i];
+    for (uint32_t i = threadIdx.x; i < uint32_t(k * k) * R_in; i += kSlotBlock) s_pm[i] = pmap[i];
     __syncthreads();
     const uint32_t E = nv ? s_off[nv] : 0;
     const uint32_t rows = kSlotBlock / R_in;  // neighbour entries per pass, R_in threads each
@@ -594,18 +597,30 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
         }
         __syncthreads();
         if (te < rows) {
-            for (uint32_t e = te; e < cn; e += rows) {
-                const uint32_t ye = s_y[e], lv = s_lv[e];
-                const uint32_t y = ye & 0xffffffu, cy = ye >> 24;
-                const uint32_t idx = y * R_in + tr;  // < n R_in < 2^28
-                const uint32_t lo = ilo[idx];
-                const uint32_t hi = WIDE && ihi ? ihi[idx] : 0u;
-                if (lv == 0xffffu) continue;
-                const uint32_t slot = pmap[(cy * uint32_t(k) + s_cv[lv]) * R_in + tr];
-                const Acc val = WIDE ? (Acc(hi) << 32) | lo : Acc(lo);
-                if (slot == 0xffffu || val == 0) continue;
-                nin++;
-                atomicAdd(&acc[lv * R + slot], val);
+            // four neighbour entries per thread and round: their row loads are
+            // in flight together
+            for (uint32_t e0 = te; e0 < cn; e0 += 4 * rows) {
+                uint32_t lv[4], cy[4], lo[4], hi[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint32_t e = e0 + j * rows;
+                    const uint32_t ec = e < cn ? e : e0;  // past the chunk: a valid entry, masked
+                    const uint32_t ye = s_y[ec];
+                    lv[j] = e < cn ? s_lv[ec] : 0xffffu;
+                    cy[j] = ye >> 24;
+                    const uint32_t idx = (ye & 0xffffffu) * R_in + tr;  // < n R_in < 2^28
+                    lo[j] = ilo[idx];
+                    hi[j] = WIDE && ihi ? ihi[idx] : 0u;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (lv[j] == 0xffffu) continue;
+                    const uint32_t slot = s_pm[(cy[j] * uint32_t(k) + s_cv[lv[j]]) * R_in + tr];
+                    const Acc val = WIDE ? (Acc(hi[j]) << 32) | lo[j] : Acc(lo[j]);
+                    if (slot == 0xffffu || val == 0) continue;
+                    nin++;
+                    atomicAdd(&acc[lv[j] * R + slot], val);
+                }
             }
         }
         __syncthreads();
@@ -1176,7 +1191,7 @@ void launch_slot_edge_push(SlotArrays in, const SlotGrid& G, DevGraph g, const u
     if (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0 || in.R > kSlotBlock)
         throw std::runtime_error("launch_slot_edge_push: needs k <= 8, n < 2^24 and R <= 256");
     const size_t cap = size_t(G.upb) * G.m;
-    const size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + cap;
+    const size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 2 * size_t(k) * k * in.R + cap;
     if (wide)
         k_slot_edge_push<true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, out, part);
     else
