@@ -779,6 +779,8 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     uint64_t* gstart;
                     uint64_t G = X.groups(in, shift, &gstart);
                     uint32_t* wcount = X.alloc<uint32_t>(G);
+                    uint8_t* gsel = X.alloc<uint8_t>(G);
+                    ia.sel = gsel;
                     X.timed("push_work", 20.0 * G, [&] { launch_push_work(in, gstart, G, g, ia, wcount, s); });
                     uint64_t* woff;
                     uint64_t W = X.scan(wcount, G, &woff);
@@ -808,6 +810,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     X.release(toff);
                     X.release(soff);
                     X.release(woff);
+                    X.release(gsel);
                     X.release(gstart);
                     break;
                 }

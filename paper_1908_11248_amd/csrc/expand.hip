@@ -32,10 +32,13 @@ __global__ void k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t*
         uint64_t grp = upper_bound_u64(woff, 0, G + 1, s) - 1;
         uint64_t t = s - woff[grp];
         K k0 = keys[gstart[grp]];
-        uint32_t v = a.anchor >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, a.anchor)] + int64_t(t)]) : uint32_t(t);
+        const int src = a.anchor >= 0 && a.sel ? int(a.sel[grp]) : a.anchor;
+        uint32_t v = src >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, src)] + int64_t(t)]) : uint32_t(t);
         bool ok = gdeg(g, v) >= a.degF;
+        // the bag neighbours before pos other than the one the candidates came from
+        if (ok && src != a.anchor) ok = has_edge(g, kcol(k0, L, a.anchor), v);
         for (int c = 0; c < a.nchk && ok; c++)
-            if (a.chk[c] < a.pos) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
+            if (a.chk[c] < a.pos && a.chk[c] != src) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
         slen[s] = ok ? uint32_t(gstart[grp + 1] - gstart[grp]) : 0u;
     }
 }
@@ -78,7 +81,8 @@ __device__ __forceinline__ SegState seg_state(uint64_t s, uint64_t* grp, const K
         st.base = gstart[*grp];
         K k0 = keys[st.base];
         st.bid = kbid(k0, L);
-        st.v = a.anchor >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, a.anchor)] + int64_t(t)]) : uint32_t(t);
+        const int src = a.anchor >= 0 && a.sel ? int(a.sel[*grp]) : a.anchor;
+        st.v = src >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, src)] + int64_t(t)]) : uint32_t(t);
     }
     st.cb = 1u << colors[uint64_t(st.bid) * g.n + st.v];
     return st;

@@ -94,6 +94,11 @@ struct IntroArgs {
     int nchk;      // further child columns that must be adjacent
     int chk[4];
     int degF;
+    // push form, per prefix group: the column, among the anchor and the
+    // checked columns before pos, whose image has the fewest neighbours; its
+    // adjacency list gives the candidates (the others are checked).  Written
+    // by launch_push_work; null: the anchor.
+    uint8_t* sel = nullptr;
 };
 void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, DevGraph g,
                       const IntroArgs& a, uint32_t* wcount, hipStream_t s);

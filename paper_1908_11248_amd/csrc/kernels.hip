@@ -203,13 +203,26 @@ void launch_leaf_emit(DevGraph g, int B, int degF, const uint8_t* colors, const 
 
 template <class K>
 __global__ void k_push_work(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gstart, uint64_t G,
-                            DevGraph g, int anchor, uint32_t* wcount) {
+                            DevGraph g, IntroArgs a, uint32_t* wcount) {
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < G; i += uint64_t(gridDim.x) * blockDim.x) {
-        if (anchor < 0) {
+        if (a.anchor < 0) {
             wcount[i] = uint32_t(g.n);
         } else {
-            uint32_t a = kcol(keys[gstart[i]], L, anchor);
-            wcount[i] = uint32_t(gdeg(g, a));
+            // candidates: neighbours of the image with the fewest of them
+            // (Sec. 3.2: every bag neighbour's image must be adjacent)
+            const K k0 = keys[gstart[i]];
+            int best = a.anchor;
+            int64_t bd = gdeg(g, kcol(k0, L, a.anchor));
+            for (int c = 0; c < a.nchk; c++) {
+                if (a.chk[c] >= a.pos) continue;
+                const int64_t d = gdeg(g, kcol(k0, L, a.chk[c]));
+                if (d < bd) {
+                    bd = d;
+                    best = a.chk[c];
+                }
+            }
+            wcount[i] = uint32_t(bd);
+            if (a.sel) a.sel[i] = uint8_t(best);
         }
     }
 }
@@ -218,9 +231,9 @@ void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, De
                       uint32_t* wcount, hipStream_t s) {
     if (!G) return;
     if (in.lay.kw() == 1)
-        k_push_work<uint64_t><<<grid_for(G), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, gstart, G, g, a.anchor, wcount);
+        k_push_work<uint64_t><<<grid_for(G), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, gstart, G, g, a, wcount);
     else
-        k_push_work<u128><<<grid_for(G), kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, G, g, a.anchor, wcount);
+        k_push_work<u128><<<grid_for(G), kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, G, g, a, wcount);
 }
 
 // ---------------------------------------------------------------------------
