@@ -204,12 +204,17 @@ int cc_set_table_budget(cc_context *ctx, uint64_t max_entries);
  * estimated arena footprint fits the memory budget (the measured peak of an
  * earlier query with the same decomposition and colouring count, else an
  * equal share of the budget); admitted queries run concurrently on their own
- * streams.  A query that runs out of memory is re-queued to run alone.
- * Latency is measured from submission to completion. */
+ * streams.  With max_heavy > 0, at most that many queries whose
+ * decomposition has width >= 2 (the heavy, sorted-list path) are in flight
+ * at once: a later query waits behind a heavy one only if it is heavy too,
+ * so short queries overlap a long one instead of sharing the device with
+ * other long ones.  A query that runs out of memory is re-queued to run
+ * alone.  Latency is measured from submission to completion. */
 typedef struct {
     int32_t max_inflight;  /* worker lanes (concurrent queries), >= 1 */
     size_t mem_budget;     /* bytes of the arena the server may use (0: all) */
     uint64_t max_entries;  /* per-table budget of each query (0: none) */
+    int32_t max_heavy;     /* width >= 2 queries in flight at once (0: no limit) */
 } cc_server_opts;
 typedef struct {
     uint64_t submitted, completed, failed, requeued;

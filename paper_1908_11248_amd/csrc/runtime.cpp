@@ -162,7 +162,7 @@ struct cc_server {
     const cc_graph* g;
     cc_server_opts opts;
     size_t budget = 0, reserved = 0;
-    int running = 0, running_alone = 0;
+    int running = 0, running_alone = 0, running_heavy = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<uint64_t> queue;
@@ -192,10 +192,13 @@ struct cc_server {
                 if (i == 0) return 0;  // waits for the device to drain
                 continue;
             }
+            if (opts.max_heavy > 0 && heavy(r) && running_heavy >= opts.max_heavy) continue;
             if (reserved + r.est <= budget || running == 0) return queue[i];
         }
         return 0;
     }
+
+    static bool heavy(const Req& r) { return r.d->d.width >= 2; }
 
     void work(int lane_index) {
         (void)hipSetDevice(ctx->device);
@@ -212,6 +215,8 @@ struct cc_server {
             reserved += hold;
             running++;
             if (r.alone) running_alone++;
+            const bool hv = heavy(r);
+            if (hv) running_heavy++;
             const cc_decomp* d = r.d;
             int32_t k = r.k, B = r.B;
             uint64_t seed = r.seed;
@@ -239,6 +244,7 @@ struct cc_server {
             reserved -= hold;
             running--;
             if (r.alone) running_alone--;
+            if (hv) running_heavy--;
             Req& rr = reqs[id];
             if (rc == CC_ENOMEM && !rr.alone) {
                 rr.alone = true;  // run again when nothing else holds memory
