@@ -558,7 +558,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             SlotTab o = make(y.s + z.s - 1, i);
             const int p = o.s - 1, q = y.s - 1;
             const int nsplit = binom(p, q);
-            SlotGrid G = slot_grid(g.n, B, o.a.R, std::max(1, slot_join_m(o.a.R, y.a.R, z.a.R, nsplit)));
+            SlotGrid G = slot_grid(g.n, B, o.a.R, std::min(4, std::max(1, slot_join_m(o.a.R, y.a.R, z.a.R, nsplit))));
             X.timed("slot_join", double(units) * 9.0 * (y.a.R + z.a.R + o.a.R), [&] {
                 launch_slot_join(y.a, z.a, ctx->slot_splits + slot_split_offset(p, q), nsplit, binom(kSlotBits, p),
                                  below(y.s, 32) && below(z.s, 32) && below(o.s, 64), below(y.s, 64) && below(z.s, 64),
