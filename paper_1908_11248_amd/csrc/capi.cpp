@@ -99,7 +99,10 @@ int cc_context_destroy(cc_context* ctx) {
         {
             std::lock_guard<std::mutex> lk(ctx->color_pool->mu);
             ctx->color_pool->alive = false;
-            for (auto& b : ctx->color_pool->idle) (void)hipFree(b.second);
+            for (auto& b : ctx->color_pool->idle) {
+                (void)hipFree(b.buf);
+                if (b.ready) (void)hipEventDestroy(b.ready);
+            }
             ctx->color_pool->idle.clear();
         }
         if (ctx->slot_tables) (void)hipFree(ctx->slot_tables);
@@ -220,7 +223,8 @@ void cc_graph_free(cc_graph* g) {
 
 int32_t cc_graph_num_vertices(const cc_graph* g) { return g ? g->n : -1; }
 
-// a device buffer of `bytes` for a colouring: an idle one of that size, else new
+// a device buffer of `bytes` for a colouring and its ready event: an idle
+// pair of that size, else new ones
 static void color_buffer(cc_context* ctx, cc_coloring* c, size_t bytes) {
     c->pool = ctx->color_pool;
     c->bytes = bytes;
@@ -228,13 +232,26 @@ static void color_buffer(cc_context* ctx, cc_coloring* c, size_t bytes) {
         std::lock_guard<std::mutex> lk(c->pool->mu);
         auto& idle = c->pool->idle;
         for (size_t i = 0; i < idle.size(); i++)
-            if (idle[i].first == bytes) {
-                c->colors = idle[i].second;
+            if (idle[i].bytes == bytes) {
+                c->colors = idle[i].buf;
+                c->ready = idle[i].ready;
                 idle.erase(idle.begin() + i);
                 return;
             }
     }
     hip_check(hipMalloc(&c->colors, bytes), "hipMalloc colours");
+    hipError_t e = hipEventCreateWithFlags(&c->ready, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipFree(c->colors);
+        c->colors = nullptr;
+        c->ready = nullptr;
+        hip_check(e, "hipEventCreate");
+    }
+}
+
+// a stream that reads colouring c waits until its colours are written
+static void wait_colors(const cc_coloring* c, hipStream_t s) {
+    if (c->ready) hip_check(hipStreamWaitEvent(s, c->ready, 0), "hipStreamWaitEvent");
 }
 
 int cc_color(cc_context* ctx, const cc_graph* g, int32_t k, uint64_t seed, int32_t num_colorings,
@@ -256,7 +273,12 @@ int cc_color(cc_context* ctx, const cc_graph* g, int32_t k, uint64_t seed, int32
             throw;
         }
         launch_color_hash(c->colors, g->n, num_colorings, k, seed, ctx->main.stream);
-        hip_check(hipStreamSynchronize(ctx->main.stream), "colour kernel");
+        // no wait here: readers on other streams wait for this event
+        hipError_t e = hipEventRecord(c->ready, ctx->main.stream);
+        if (e != hipSuccess) {
+            cc_coloring_free(c);
+            hip_check(e, "hipEventRecord");
+        }
         *out = c;
     });
 }
@@ -296,6 +318,7 @@ int cc_coloring_download(const cc_coloring* c, int32_t b, uint8_t* colors_out) {
     return guarded([&] {
         need(c && colors_out && b >= 0 && b < c->B, CC_EINVAL, "bad arguments");
         hip_check(hipSetDevice(c->ctx->device), "hipSetDevice");
+        if (c->ready) hip_check(hipEventSynchronize(c->ready), "hipEventSynchronize");
         if (c->n)
             hip_check(hipMemcpy(colors_out, c->colors + size_t(b) * c->n, size_t(c->n), hipMemcpyDeviceToHost),
                       "hipMemcpy");
@@ -309,11 +332,14 @@ void cc_coloring_free(cc_coloring* c) {
         if (c->pool) {
             std::lock_guard<std::mutex> lk(c->pool->mu);
             if (c->pool->alive && c->pool->idle.size() < ColorPool::kMax) {
-                c->pool->idle.push_back({c->bytes, c->colors});
+                c->pool->idle.push_back({c->bytes, c->colors, c->ready});
                 kept = true;
             }
         }
-        if (!kept) (void)hipFree(c->colors);
+        if (!kept) {
+            (void)hipFree(c->colors);
+            if (c->ready) (void)hipEventDestroy(c->ready);
+        }
     }
     delete c;
 }
@@ -435,6 +461,7 @@ int cc_count(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_
         rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
         rq.max_entries = ctx->max_entries;
         RunResult r;
+        wait_colors(c, ctx->main.stream);
         run_dp_waves(ctx, ctx->main, rq, &r);
         std::copy(r.counts.begin(), r.counts.end(), counts);
         if (overflow) std::copy(r.overflow.begin(), r.overflow.end(), overflow);
@@ -462,6 +489,7 @@ int cc_count_by_vertex(cc_context* ctx, const cc_graph* g, const cc_coloring* c,
         rq.per_vertex = true;
         rq.max_entries = ctx->max_entries;
         RunResult r;
+        wait_colors(c, ctx->main.stream);
         run_dp(ctx, ctx->main, rq, &r);
         std::copy(r.per_vertex.begin(), r.per_vertex.end(), per_vertex);
         if (count) *count = r.counts[0];
@@ -547,6 +575,7 @@ int cc_enumerate(cc_context* ctx, const cc_graph* g, const cc_coloring* c, int32
         need(n_rows && total && (cap == 0 || rows), CC_EINVAL, "bad arguments");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         std::vector<int32_t> out;
+        wait_colors(c, ctx->main.stream);
         run_enumerate(ctx, ctx->main, g, c->colors + size_t(b) * g->n, c->k, d, cap, &out, n_rows, total);
         if (!out.empty()) std::memcpy(rows, out.data(), out.size() * sizeof(int32_t));
     });

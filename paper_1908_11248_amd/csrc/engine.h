@@ -109,7 +109,12 @@ struct Lane {
 struct ColorPool {
     std::mutex mu;
     bool alive = true;
-    std::vector<std::pair<size_t, uint8_t*>> idle;  // (bytes, buffer)
+    struct Idle {
+        size_t bytes;
+        uint8_t* buf;
+        hipEvent_t ready;
+    };
+    std::vector<Idle> idle;
     static constexpr size_t kMax = 8;
 };
 
@@ -152,6 +157,7 @@ struct cc_coloring {
     int32_t n = 0, k = 0, B = 0;
     uint8_t* colors = nullptr;  // [B][n] on the device
     size_t bytes = 0;           // of the buffer
+    hipEvent_t ready = nullptr;  // recorded once the colours are written
     std::shared_ptr<ColorPool> pool;
 };
 

@@ -90,7 +90,12 @@ int batch_run(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query* q,
             QueryRun qr{q[i].decomp, q[i].coloring->colors, q[i].coloring->B, q[i].coloring->k};
             RunResult r;
             std::string e;
-            int rc = run_one(ctx, lane, g, qr, flags, ctx->max_entries, &r, &e);
+            int rc = CC_OK;
+            if (q[i].coloring->ready && hipStreamWaitEvent(lane.stream, q[i].coloring->ready, 0) != hipSuccess) {
+                rc = CC_EDEVICE;
+                e = "hipStreamWaitEvent failed";
+            }
+            if (rc == CC_OK) rc = run_one(ctx, lane, g, qr, flags, ctx->max_entries, &r, &e);
             std::lock_guard<std::mutex> guard(mu);
             if (rc == CC_ENOMEM && lanes > 1) {
                 retry.push_back(i);  // memory was held by concurrent queries
@@ -116,6 +121,7 @@ int batch_run(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query* q,
         QueryRun qr{q[i].decomp, q[i].coloring->colors, q[i].coloring->B, q[i].coloring->k};
         RunResult r;
         std::string e;
+        if (q[i].coloring->ready) (void)hipStreamWaitEvent(ctx->main.stream, q[i].coloring->ready, 0);
         int rc = run_one(ctx, ctx->main, g, qr, flags, ctx->max_entries, &r, &e);
         if (rc != CC_OK) {
             first_rc = rc;
