@@ -73,9 +73,9 @@ int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_conte
             std::vector<uint64_t> pk = slot_pack_tables();
             hip_check(hipMalloc(&c->slot_pack, pk.size() * 8), "hipMalloc");
             hip_check(hipMemcpy(c->slot_pack, pk.data(), pk.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
-            std::vector<uint16_t> pu = slot_push_tables();
-            hip_check(hipMalloc(&c->slot_push, pu.size() * 2), "hipMalloc");
-            hip_check(hipMemcpy(c->slot_push, pu.data(), pu.size() * 2, hipMemcpyHostToDevice), "hipMemcpy");
+            std::vector<uint32_t> pu = slot_push_tables();
+            hip_check(hipMalloc(&c->slot_push, pu.size() * 4), "hipMalloc");
+            hip_check(hipMemcpy(c->slot_push, pu.data(), pu.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
         } catch (...) {
             if (c->slot_push) (void)hipFree(c->slot_push);
             if (c->slot_tables) (void)hipFree(c->slot_tables);

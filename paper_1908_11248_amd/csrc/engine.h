@@ -131,7 +131,7 @@ struct cc_context {
     uint16_t* slot_tables = nullptr;  // device: rank[2048] then unrank[2048] (slots.hip)
     uint32_t* slot_splits = nullptr;  // device: join split tables (slots.hip)
     uint64_t* slot_pack = nullptr;    // device: packed child slots of edge steps, k <= kSlotPackK
-    uint16_t* slot_push = nullptr;    // device: output slots of pushed edge steps, k <= kSlotPackK
+    uint32_t* slot_push = nullptr;    // device: (child slot, output slot) lists of pushed edge steps, k <= kSlotPackK
     ccg::Lane& worker(size_t i);
 };
 

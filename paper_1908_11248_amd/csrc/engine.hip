@@ -509,16 +509,16 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const uint64_t* pack = !leafc && k <= kSlotPackK && g.n < (1 << 24) && o.a.R <= kSlotBlock
                                        ? ctx->slot_pack + slot_pack_offset(k, o.s - 1)
                                        : nullptr;
-            // push from the child's rows when its colour sets are the smaller
-            // side (C(k-1, s-2) < C(k-1, s-1)) and no count can wrap
-            const bool push = pack && 2 * in.s < k && below(o.s, 64) && in.a.R <= kSlotBlock;
+            // push from the child's rows whenever no count can wrap: a
+            // (neighbour, child slot) pair of the push is always useful
+            const bool push = pack && below(o.s, 64) && in.a.R <= kSlotBlock;
             // vertices per thread (measured on workload 2): the gather's
             // latency wants more blocks, the push's LDS accumulators longer rows
             SlotGrid G = slot_grid(g.n, B, o.a.R, leafc ? 4 : push ? 8 : 2);
             X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 if (push)
-                    launch_slot_edge_push(in.a, G, g, rq.colors, k, degF_u, ctx->slot_push + slot_push_offset(k, in.s - 1),
-                                          !below(o.s, 32), o.a, part, s);
+                    launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, degF_u,
+                                          ctx->slot_push + slot_push_offset(k, in.s - 1), !below(o.s, 32), o.a, part, s);
                 else
                     launch_slot_edge(in.a, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
                                      slot_unrank_offset(o.s - 1), pack, !leafc && below(in.s, 32),

@@ -253,11 +253,11 @@ void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, SlotArrays out, u
 constexpr int kSlotPackK = 8;
 std::vector<uint64_t> slot_pack_tables();
 size_t slot_pack_offset(int k, int p);
-// Output slots of an edge step pushed from the child (k <= kSlotPackK): for
-// child colour-set size p + 1, child bag colour cy, output bag colour cv and
-// child slot r (index slot_push_offset(k, p) + (cy k + cv) C(k - 1, p) + r),
-// the output slot of the child's set plus cv, or 0xffff when cv is in it.
-std::vector<uint16_t> slot_push_tables();
+// Pushed edge steps (k <= kSlotPackK): for child colour-set size p + 1, child
+// bag colour cy and output bag colour cv != cy, entry (cy k + cv) W + w of
+// the block at slot_push_offset(k, p), W = C(k - 2, p), holds the w-th child
+// slot r whose set leaves cv out, | the output slot of that set plus cv << 16.
+std::vector<uint32_t> slot_push_tables();
 size_t slot_push_offset(int k, int p);
 // in.lo == nullptr: the child is a leaf (count 1 per vertex passing
 // degF_child).  pack: the entries of (k, p) above, or null (ranks from the
@@ -267,11 +267,12 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
                       int degF_child, const uint16_t* rank, const uint16_t* unrank, int uoff, const uint64_t* pack,
                       bool in_narrow, bool in_exact, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
 // The same step pushed from the child's rows into LDS accumulators; only for
-// a step whose counts cannot wrap (then every table below is exact).  push:
-// the entries of (k, child size - 1) above; wide: 64-bit accumulators (else
-// every output count is below 2^32).
-void launch_slot_edge_push(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
-                           const uint16_t* push, bool wide, SlotArrays out, uint64_t* part, hipStream_t s);
+// a step whose counts cannot wrap (then every table below is exact).  s_in:
+// the child's colour-set size; push: the entries of (k, s_in - 1) above;
+// wide: 64-bit accumulators (else every output count is below 2^32).
+void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
+                           int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
+                           hipStream_t s);
 constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
 // split table rows of (p, q) (see slots.hip) start at slot_split_offset(p, q);
 // row stride C(kSlotBits, p)

@@ -533,21 +533,24 @@ k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ c
     count_entries(npres, nin, part, G.blocks);
 }
 
-// The same step pushed from the child's rows: a thread takes child slot r of
-// a neighbour entry (v, y) and, when colour(v) is not in the child's set C_y,
-// adds the child's count into v's output slot of C_y + colour(v), kept in
-// LDS.  With small child sets most child entries land in an output slot,
-// while most (output slot, neighbour) pairs of the gather find nothing.
-// Launched only when no count of this or any lower table can wrap (a degree
-// bound), so every child table is exact and a sum is present iff it is not
-// 0.  WIDE: 64-bit accumulators, else every output count is below 2^32.
+// The same step pushed from the child's rows: for a neighbour entry (v, y)
+// with colour(y) != colour(v), the child slots of y whose set C_y leaves out
+// colour(v) are the same C(k-2, s_in-1) = W slots for every such pair of
+// colours (slot_push_tables lists them with the output slot of C_y +
+// colour(v)); W threads take one each and add the child's count into v's
+// output row, kept in LDS.  Every thread's work is useful, where the gather
+// spends most of its (output slot, neighbour) pairs on sets that do not
+// contain colour(y).  Launched only when no count of this or any lower table
+// can wrap (a degree bound), so every child table is exact and a sum is
+// present iff it is not 0.  WIDE: 64-bit accumulators, else every output
+// count is below 2^32.
 template <bool WIDE>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
-                 const uint16_t* __restrict__ pmap, SlotArrays out, uint64_t* part) {
+                 const uint32_t* __restrict__ cmap, int W, SlotArrays out, uint64_t* part) {
     using Acc = typename std::conditional<WIDE, unsigned long long, uint32_t>::type;
-    // [upb M][R] accumulators, [upb M + 1] CSR offsets, the k k R_in output
-    // slots of pmap, [upb M] colours
+    // [upb M][R] accumulators, [upb M + 1] CSR offsets, the k k W (child
+    // slot, output slot) pairs of cmap, [upb M] colours
     extern __shared__ uint64_t s_dyn[];
     __shared__ uint32_t s_y[kEdgeChunk];   // neighbour | colour << 24
     __shared__ uint16_t s_lv[kEdgeChunk];  // its vertex within the block, 0xffff when masked
@@ -558,8 +561,8 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     const uint32_t nv = v1 - v0, cap = uint32_t(G.upb * G.m), R = uint32_t(G.R), R_in = uint32_t(in.R);
     Acc* acc = reinterpret_cast<Acc*>(s_dyn);
     uint32_t* s_off = reinterpret_cast<uint32_t*>(acc + cap * R);
-    uint16_t* s_pm = reinterpret_cast<uint16_t*>(s_off + cap + 1);
-    uint8_t* s_cv = reinterpret_cast<uint8_t*>(s_pm + k * k * R_in);
+    uint32_t* s_cm = s_off + cap + 1;
+    uint8_t* s_cv = reinterpret_cast<uint8_t*>(s_cm + k * k * W);
     const uint64_t row0 = uint64_t(b) * uint32_t(g.n);
     const uint8_t* cb = colors + row0;
     const uint32_t* ilo = in.lo + row0 * R_in;
@@ -568,11 +571,11 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) acc[i] = 0;
     for (uint32_t i = threadIdx.x; nv && i <= nv; i += kSlotBlock) s_off[i] = uint32_t(g.rp[v0 + i] - e_lo);
     for (uint32_t i = threadIdx.x; i < nv; i += kSlotBlock) s_cv[i] = cb[v0 + i];
-    for (uint32_t i = threadIdx.x; i < uint32_t(k * k) * R_in; i += kSlotBlock) s_pm[i] = pmap[i];
+    for (uint32_t i = threadIdx.x; i < uint32_t(k * k * W); i += kSlotBlock) s_cm[i] = cmap[i];
     __syncthreads();
     const uint32_t E = nv ? s_off[nv] : 0;
-    const uint32_t rows = kSlotBlock / R_in;  // neighbour entries per pass, R_in threads each
-    const uint32_t te = threadIdx.x / R_in, tr = threadIdx.x - te * R_in;
+    const uint32_t rows = kSlotBlock / uint32_t(W);  // neighbour entries per pass, W threads each
+    const uint32_t te = threadIdx.x / uint32_t(W), tr = threadIdx.x - te * uint32_t(W);
     uint32_t nin = 0;
     for (uint32_t c0 = 0; c0 < E; c0 += kEdgeChunk) {
         const uint32_t cn = min(uint32_t(kEdgeChunk), E - c0);
@@ -600,26 +603,28 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
             // four neighbour entries per thread and round: their row loads are
             // in flight together
             for (uint32_t e0 = te; e0 < cn; e0 += 4 * rows) {
-                uint32_t lv[4], cy[4], lo[4], hi[4];
+                uint32_t lv[4], cm[4], lo[4], hi[4];
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     const uint32_t e = e0 + j * rows;
                     const uint32_t ec = e < cn ? e : e0;  // past the chunk: a valid entry, masked
                     const uint32_t ye = s_y[ec];
+                    const uint32_t cy = ye >> 24;
                     lv[j] = e < cn ? s_lv[ec] : 0xffffu;
-                    cy[j] = ye >> 24;
-                    const uint32_t idx = (ye & 0xffffffu) * R_in + tr;  // < n R_in < 2^28
+                    const uint32_t cv = lv[j] != 0xffffu ? s_cv[lv[j]] : cy;
+                    if (cv == cy) lv[j] = 0xffffu;  // same colour: no child set leaves colour(v) out
+                    cm[j] = lv[j] != 0xffffu ? s_cm[(cy * uint32_t(k) + cv) * uint32_t(W) + tr] : 0u;
+                    const uint32_t idx = (ye & 0xffffffu) * R_in + (cm[j] & 0xffffu);  // < n R_in < 2^28
                     lo[j] = ilo[idx];
                     hi[j] = WIDE && ihi ? ihi[idx] : 0u;
                 }
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     if (lv[j] == 0xffffu) continue;
-                    const uint32_t slot = s_pm[(cy[j] * uint32_t(k) + s_cv[lv[j]]) * R_in + tr];
                     const Acc val = WIDE ? (Acc(hi[j]) << 32) | lo[j] : Acc(lo[j]);
-                    if (slot == 0xffffu || val == 0) continue;
+                    if (val == 0) continue;
                     nin++;
-                    atomicAdd(&acc[lv[j] * R + slot], val);
+                    atomicAdd(&acc[lv[j] * R + (cm[j] >> 16)], val);
                 }
             }
         }
@@ -1103,32 +1108,38 @@ std::vector<uint64_t> slot_pack_tables() {
     return t;
 }
 
+// W(k, p) = C(k - 2, p): child slots of set size p + 1 that leave out a
+// given colour other than the child's own
 size_t slot_push_offset(int k, int p) {
     size_t off = 0;
     for (int kk = 2; kk <= kSlotPackK; kk++)
         for (int pp = 0; pp < kk - 1; pp++) {
             if (kk == k && pp == p) return off;
-            off += size_t(kk) * kk * binom_pq(kk - 1, pp);
+            off += size_t(kk) * kk * binom_pq(kk - 2, pp);
         }
     return off;  // past the last: the total
 }
 
-std::vector<uint16_t> slot_push_tables() {
+std::vector<uint32_t> slot_push_tables() {
     std::vector<uint16_t> rt = slot_rank_tables();
     const int M = 1 << kSlotBits;
-    std::vector<uint16_t> t(slot_push_offset(kSlotPackK + 1, 0));
+    std::vector<uint32_t> t(slot_push_offset(kSlotPackK + 1, 0), 0xffffffffu);
     for (int k = 2; k <= kSlotPackK; k++)
         for (int p = 0; p < k - 1; p++) {
-            const int R = binom_pq(k - 1, p);
+            const int R = binom_pq(k - 1, p), W = binom_pq(k - 2, p);
             const size_t off = slot_push_offset(k, p);
             for (int cy = 0; cy < k; cy++)
-                for (int cv = 0; cv < k; cv++)
+                for (int cv = 0; cv < k; cv++) {
+                    if (cv == cy) continue;  // no child set leaves its own colour out
+                    int w = 0;
                     for (int r = 0; r < R; r++) {
                         // the child's set over k bits, its own colour included
                         const uint32_t C = bit_open(rt[M + slot_unrank_offset(p) + r], uint32_t(cy)) | (1u << cy);
-                        t[off + (size_t(cy) * k + cv) * R + r] =
-                            (C >> cv) & 1u ? uint16_t(0xffff) : rt[bit_close(C, uint32_t(cv))];
+                        if ((C >> cv) & 1u) continue;
+                        t[off + (size_t(cy) * k + cv) * W + w] = uint32_t(r) | (uint32_t(rt[bit_close(C, uint32_t(cv))]) << 16);
+                        w++;
                     }
+                }
         }
     return t;
 }
@@ -1185,17 +1196,21 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
 #undef EDGE_ARGS
 }
 
-void launch_slot_edge_push(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
-                           const uint16_t* push, bool wide, SlotArrays out, uint64_t* part, hipStream_t s) {
+void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
+                           int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
+                           hipStream_t s) {
     if (!G.blocks) return;
-    if (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0 || in.R > kSlotBlock)
-        throw std::runtime_error("launch_slot_edge_push: needs k <= 8, n < 2^24 and R <= 256");
+    if (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0 || s_in < 1 || s_in > k - 1)
+        throw std::runtime_error("launch_slot_edge_push: needs k <= 8, n < 2^24, R <= 256 and a child set below k");
+    const int W = binom_pq(k - 2, s_in - 1);
     const size_t cap = size_t(G.upb) * G.m;
-    const size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 2 * size_t(k) * k * in.R + cap;
+    const size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 4 * size_t(k) * k * W + cap;
     if (wide)
-        k_slot_edge_push<true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, out, part);
+        k_slot_edge_push<true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, out,
+                                                                             part);
     else
-        k_slot_edge_push<false><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, out, part);
+        k_slot_edge_push<false><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, out,
+                                                                              part);
 }
 
 void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, bool nowrap,
