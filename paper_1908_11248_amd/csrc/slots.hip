@@ -31,6 +31,7 @@ namespace ccg {
 namespace {
 
 constexpr int kEdgeChunk = 2048;  // neighbours staged per round
+constexpr int kPushChunk = 1024;  // neighbour entries staged per round by the push form
 
 __host__ __device__ __forceinline__ uint32_t bit_open(uint32_t m, uint32_t c) {  // insert a 0 at bit c
     return ((m >> c) << (c + 1)) | (m & ((1u << c) - 1u));
@@ -552,8 +553,10 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     // [upb M][R] accumulators, [upb M + 1] CSR offsets, the k k W (child
     // slot, output slot) pairs of cmap, [upb M] colours
     extern __shared__ uint64_t s_dyn[];
-    __shared__ uint32_t s_y[kEdgeChunk];   // neighbour | colour << 24
-    __shared__ uint16_t s_lv[kEdgeChunk];  // its vertex within the block, 0xffff when masked
+    __shared__ uint32_t s_y[kPushChunk];   // neighbour | colour << 24
+    // its vertex within the block | (colour(y) k + colour(v)) << 16, or
+    // 0xffffffff when v is masked or the colours are equal
+    __shared__ uint32_t s_lv[kPushChunk];
     uint32_t b, v0, v1, jb, v, r;
     bool lane_ok;
     block_range(G, &b, &v0, &v1, &jb);
@@ -577,8 +580,8 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     const uint32_t rows = kSlotBlock / uint32_t(W);  // neighbour entries per pass, W threads each
     const uint32_t te = threadIdx.x / uint32_t(W), tr = threadIdx.x - te * uint32_t(W);
     uint32_t nin = 0;
-    for (uint32_t c0 = 0; c0 < E; c0 += kEdgeChunk) {
-        const uint32_t cn = min(uint32_t(kEdgeChunk), E - c0);
+    for (uint32_t c0 = 0; c0 < E; c0 += kPushChunk) {
+        const uint32_t cn = min(uint32_t(kPushChunk), E - c0);
         for (uint32_t i0 = 0; i0 < cn; i0 += 4 * kSlotBlock) {
             uint32_t y[4];
 #pragma unroll
@@ -593,33 +596,37 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
                 if (i < cn) s_y[i] = y[j] | (c << 24);
             }
         }
+        __syncthreads();
         for (uint32_t lv = threadIdx.x; lv < nv; lv += kSlotBlock) {
             const uint32_t a = max(s_off[lv], c0), z = min(s_off[lv + 1], c0 + cn);
-            const uint16_t mark = s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u) ? uint16_t(lv) : uint16_t(0xffff);
-            for (uint32_t e = a; e < z; e++) s_lv[e - c0] = mark;
+            const bool pass = s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u);
+            const uint32_t cv = s_cv[lv];
+            for (uint32_t e = a; e < z; e++) {
+                const uint32_t cy = s_y[e - c0] >> 24;
+                s_lv[e - c0] = pass && cy != cv ? lv | ((cy * uint32_t(k) + cv) << 16) : 0xffffffffu;
+            }
         }
         __syncthreads();
         if (te < rows) {
-            // four neighbour entries per thread and round: their row loads are
+            // eight neighbour entries per thread and round: their row loads are
             // in flight together
-            for (uint32_t e0 = te; e0 < cn; e0 += 4 * rows) {
-                uint32_t lv[4], cm[4], lo[4], hi[4];
+            constexpr int NE = 8;
+            for (uint32_t e0 = te; e0 < cn; e0 += NE * rows) {
+                uint32_t lv[NE], cm[NE], lo[NE], hi[NE];
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
+                for (int j = 0; j < NE; j++) {
                     const uint32_t e = e0 + j * rows;
                     const uint32_t ec = e < cn ? e : e0;  // past the chunk: a valid entry, masked
                     const uint32_t ye = s_y[ec];
-                    const uint32_t cy = ye >> 24;
-                    lv[j] = e < cn ? s_lv[ec] : 0xffffu;
-                    const uint32_t cv = lv[j] != 0xffffu ? s_cv[lv[j]] : cy;
-                    if (cv == cy) lv[j] = 0xffffu;  // same colour: no child set leaves colour(v) out
-                    cm[j] = lv[j] != 0xffffu ? s_cm[(cy * uint32_t(k) + cv) * uint32_t(W) + tr] : 0u;
+                    const uint32_t m = e < cn ? s_lv[ec] : 0xffffffffu;
+                    lv[j] = m == 0xffffffffu ? 0xffffu : m & 0xffffu;
+                    cm[j] = m == 0xffffffffu ? 0u : s_cm[(m >> 16) * uint32_t(W) + tr];
                     const uint32_t idx = (ye & 0xffffffu) * R_in + (cm[j] & 0xffffu);  // < n R_in < 2^28
                     lo[j] = ilo[idx];
                     hi[j] = WIDE && ihi ? ihi[idx] : 0u;
                 }
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
+                for (int j = 0; j < NE; j++) {
                     if (lv[j] == 0xffffu) continue;
                     const Acc val = WIDE ? (Acc(hi[j]) << 32) | lo[j] : Acc(lo[j]);
                     if (val == 0) continue;
