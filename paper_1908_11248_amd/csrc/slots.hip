@@ -47,12 +47,11 @@ __device__ __forceinline__ uint32_t block_index() { return blockIdx.y * gridDim.
 // the eight XCDs) take eight different colourings, so each XCD's L2 holds
 // the rows of the colouring it works on.  An empty range marks a block past
 // the end.
-__device__ __forceinline__ void block_range(const SlotGrid& G, uint32_t* b, uint32_t* v0, uint32_t* v1,
-                                            uint32_t* jb) {
+__device__ __forceinline__ void block_range_at(const SlotGrid& G, uint32_t L, uint32_t* b, uint32_t* v0,
+                                               uint32_t* v1, uint32_t* jb) {
     *b = 0;
     *v0 = *v1 = 0;
     *jb = 0;
-    const uint32_t L = block_index();
     if (L >= G.blocks) return;
     uint32_t bb, j;
     if (G.xcd) {
@@ -75,6 +74,11 @@ __device__ __forceinline__ void block_range(const SlotGrid& G, uint32_t* b, uint
     }
 }
 
+__device__ __forceinline__ void block_range(const SlotGrid& G, uint32_t* b, uint32_t* v0, uint32_t* v1,
+                                            uint32_t* jb) {
+    block_range_at(G, block_index(), b, v0, v1, jb);
+}
+
 // this thread's slot r and first vertex; its i-th vertex is v + i * upb
 __device__ __forceinline__ void slot_of(const SlotGrid& G, uint32_t v0, uint32_t jb, uint32_t* v, uint32_t* r,
                                         bool* lane_ok) {
@@ -93,7 +97,8 @@ __device__ __forceinline__ void slot_of(const SlotGrid& G, uint32_t v0, uint32_t
 // Entry counts of a block: (extra, present) summed over its threads and
 // stored at part[2L], part[2L + 1] (L = block index); k_slot_sum adds them
 // up.  Plain stores: no address is shared between blocks.
-__device__ __forceinline__ void count_entries(uint32_t present, uint64_t extra, uint64_t* part, uint64_t blocks) {
+__device__ __forceinline__ void count_entries_at(uint32_t present, uint64_t extra, uint64_t* part, uint64_t blocks,
+                                                 uint32_t L) {
     __shared__ uint64_t s_p[2][kSlotBlock / 64];
     const uint64_t pr = wave_sum(present);
     const uint64_t ex = wave_sum(extra);
@@ -102,12 +107,15 @@ __device__ __forceinline__ void count_entries(uint32_t present, uint64_t extra, 
         s_p[1][threadIdx.x >> 6] = pr;
     }
     __syncthreads();
-    const uint32_t L = block_index();
     if (threadIdx.x < 2 && L < blocks) {
         uint64_t t = 0;
         for (int i = 0; i < kSlotBlock / 64; i++) t += s_p[threadIdx.x][i];
         part[2 * uint64_t(L) + threadIdx.x] = t;
     }
+}
+
+__device__ __forceinline__ void count_entries(uint32_t present, uint64_t extra, uint64_t* part, uint64_t blocks) {
+    count_entries_at(present, extra, part, blocks, block_index());
 }
 
 // (sum, wrapped) over a block, sums mod 2^64: every lane of a butterfly sums
@@ -841,6 +849,97 @@ k_slot_join(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int
     count_entries(__popc(pres), 0, part, G.blocks);
 }
 
+// The no-wrap join (k_slot_join with STAGE and nowrap) as persistent blocks:
+// a block takes the virtual blocks L, L + stride, ... and loads the next
+// one's child words into registers while it computes the current one from
+// LDS, so the loads' latency overlaps the multiply-adds.  The split rows are
+// staged once.  stride is a multiple of 8 (or the whole grid), so every
+// virtual block of a block keeps the XCD of the one-shot mapping.
+constexpr int kPipeWords = 8;  // staged child words per thread and virtual block
+template <int M>
+__global__ void __launch_bounds__(kSlotBlock)
+k_slot_join_pipe(SlotArrays y, SlotArrays z, const uint32_t* __restrict__ splits, int nsplit, int sstride,
+                 SlotGrid G, uint32_t stride, SlotArrays out, uint64_t* part) {
+    extern __shared__ uint32_t s_w[];  // [upb M][R_y] y words, [upb M][R_z] z words, [nsplit][R] split rows
+    const int R = G.R, R_y = y.R, R_z = z.R;
+    const uint32_t cap = uint32_t(G.upb) * M;
+    uint32_t* s_y32 = s_w;
+    uint32_t* s_z32 = s_w + cap * R_y;
+    uint32_t* s_sp = s_z32 + cap * R_z;
+    for (uint32_t i = threadIdx.x; i < uint32_t(nsplit * R); i += kSlotBlock) {
+        const uint32_t t = i / uint32_t(R);
+        s_sp[i] = splits[size_t(t) * sstride + (i - t * uint32_t(R))];
+    }
+    uint32_t w[kPipeWords];
+    // the child words of virtual block L: y's rows, then z's
+    auto fetch = [&](uint32_t L) {
+        uint32_t b, v0, v1, jb;
+        block_range_at(G, L, &b, &v0, &v1, &jb);
+        const uint64_t base = uint64_t(b) * uint32_t(G.n) + v0;
+        const uint32_t ny = (v1 - v0) * uint32_t(R_y), nz = (v1 - v0) * uint32_t(R_z);
+        const uint32_t* ys = y.lo + base * uint32_t(R_y);
+        const uint32_t* zs = z.lo + base * uint32_t(R_z);
+#pragma unroll
+        for (int j = 0; j < kPipeWords; j++) {
+            const uint32_t i = threadIdx.x + j * kSlotBlock;
+            w[j] = i < ny ? ys[i] : i < ny + nz ? zs[i - ny] : 0u;
+        }
+    };
+    uint32_t L = block_index();
+    if (L < G.blocks) fetch(L);
+    for (; L < G.blocks; L += stride) {
+        uint32_t b, v0, v1, jb, v, r;
+        bool lane_ok;
+        block_range_at(G, L, &b, &v0, &v1, &jb);
+        slot_of(G, v0, jb, &v, &r, &lane_ok);
+        const uint32_t ny = (v1 - v0) * uint32_t(R_y), nz = (v1 - v0) * uint32_t(R_z);
+#pragma unroll
+        for (int j = 0; j < kPipeWords; j++) {
+            const uint32_t i = threadIdx.x + j * kSlotBlock;
+            if (i < ny)
+                s_y32[i] = w[j];
+            else if (i < ny + nz)
+                s_z32[i - ny] = w[j];
+        }
+        __syncthreads();
+        if (L + stride < G.blocks) fetch(L + stride);  // in flight during the sums below
+        uint64_t sum[M];
+        uint32_t by[M], bz[M];
+#pragma unroll
+        for (int i = 0; i < M; i++) {
+            sum[i] = 0;
+            const uint32_t u = (v - v0) + uint32_t(i * G.upb);
+            by[i] = u * uint32_t(R_y);
+            bz[i] = u * uint32_t(R_z);
+        }
+        if (lane_ok) {
+            for (int t = 0; t < nsplit; t++) {
+                const uint32_t e = s_sp[t * R + r];
+                const uint32_t ry = e & 0xffffu, rz = e >> 16;
+                uint32_t a[M], c[M];
+#pragma unroll
+                for (int i = 0; i < M; i++) {
+                    a[i] = s_y32[by[i] + ry];
+                    c[i] = s_z32[bz[i] + rz];
+                }
+#pragma unroll
+                for (int i = 0; i < M; i++) sum[i] += uint64_t(a[i]) * c[i];
+            }
+        }
+        uint32_t npres = 0, hi = 0;
+#pragma unroll
+        for (int i = 0; i < M; i++) {
+            const uint32_t vi = v + uint32_t(i * G.upb);
+            if (!(lane_ok && vi < v1)) continue;
+            store_slot(out, (uint64_t(b) * uint32_t(G.n) + vi) * uint32_t(R) + r, sum[i], sum[i] != 0);
+            npres += sum[i] != 0;
+            hi |= uint32_t(sum[i] >> 32);
+        }
+        flag_wide(hi, &out.wide[b]);
+        count_entries_at(npres, 0, part, G.blocks, L);  // its barrier also frees the staged rows
+    }
+}
+
 // Root (Sec. 3, the root's value): per colouring, the sum of every entry of
 // the one-column table below the root.  Each block stores its (sum, wrapped)
 // at rpart[2 (b nbx + j)] (j = the block's place within colouring b) and
@@ -1224,6 +1323,17 @@ void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int ns
                       bool in_exact, const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
     const bool stage = G.upb > 0 && slot_join_m(G.R, y.R, z.R, nsplit) >= G.m;
+    const size_t cap = size_t(G.upb) * G.m;
+    if (stage && nowrap && cap * (y.R + z.R) <= size_t(kPipeWords) * kSlotBlock && G.blocks < (uint64_t(1) << 32)) {
+        const uint64_t grid = std::min<uint64_t>(G.blocks, 2048);  // a multiple of 8 when smaller than the grid
+        const size_t lds = 4 * (cap * (y.R + z.R) + size_t(nsplit) * G.R);
+#define PIPE_M(M)                                                                                                   \
+    k_slot_join_pipe<M><<<unsigned(grid), kSlotBlock, lds, s>>>(y, z, splits, nsplit, sstride, G, uint32_t(grid), out, \
+                                                                 part)
+        SLOT_BY_M(PIPE_M)
+#undef PIPE_M
+        return;
+    }
     const size_t lds = !stage   ? 0
                        : nowrap ? size_t(G.upb) * G.m * size_t(y.R + z.R) * 4 + size_t(nsplit) * G.R * 4
                                 : size_t(G.upb) * G.m * size_t(y.R + z.R) * 9 + size_t(nsplit) * G.R * 4;
