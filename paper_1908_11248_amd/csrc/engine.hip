@@ -380,6 +380,22 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (st.in1 >= 0) uses[st.in1]++;
     }
     std::vector<SlotTab> tab(S);
+    // A join whose two inputs are introduce-over-a-leaf steps (at its bag
+    // vertex, used by nothing else) runs as one kernel from neighbourhood
+    // colour histograms; those inputs are deferred (never stored).
+    const bool one_sum_plan = S <= size_t(kSlotSumSteps);
+    std::vector<char> defer(S, 0), ljoin(S, 0);
+    auto leaf_edge = [&](int t) {
+        return t >= 1 && fuse[size_t(t - 1)] && virt[size_t(plan.steps[size_t(t - 1)].in0)] && uses[size_t(t)] == 1;
+    };
+    if (one_sum_plan && k >= 4 && k <= 12)
+        for (size_t i = 0; i < S; i++) {
+            const Step& st = plan.steps[i];
+            if (st.kind != S_JOIN || st.in0 == st.in1 || !leaf_edge(st.in0) || !leaf_edge(st.in1)) continue;
+            if (plan.steps[size_t(st.in0 - 1)].degF != plan.steps[size_t(st.in1 - 1)].degF) continue;
+            ljoin[i] = 1;
+            defer[size_t(st.in0)] = defer[size_t(st.in1)] = 1;
+        }
     // per step: introduce entries, output entries, added up from per-block
     // partials (one scratch buffer, reused step after step on the stream)
     // partials: one segment per step (summed by one launch at the end when
@@ -391,8 +407,10 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             part_words += w;
             seg_max = std::max(seg_max, w);
         }
-    const bool one_sum = S <= size_t(kSlotSumSteps);
+    const bool one_sum = one_sum_plan;
     if (!one_sum) part_words = seg_max;
+    for (size_t i = 0; i < S; i++)  // the two extra segments of a fused leaf join
+        if (ljoin[i]) part_words += 4 * slot_grid(g.n, B, binom(k - 1, 2), 1).blocks;
     const uint64_t root_off = part_words;
     part_words += slot_root_partials(g.n, B);
     // One block for everything the host reads back and every flag, cleared by
@@ -493,6 +511,13 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (fuse[i]) {
             const Step& f = plan.steps[i + 1];
             sig[i + 1] = "E(" + sig[st.in0] + "," + std::to_string(rq.degree_mask ? st.degF : 0) + ")";
+            if (defer[i + 1]) {  // computed with its join; its sizes come from that kernel
+                if (st.node >= 0) node_of.push_back({st.node, int(2 * i)});
+                if (f.node >= 0) node_of.push_back({f.node, int(2 * i + 1)});
+                budgeted.push_back(int(2 * i + 1));
+                i++;
+                continue;
+            }
             if (reuse(i + 1)) {
                 const size_t t = phys[i + 1];  // its fused pair is steps t - 1, t
                 if (st.node >= 0) node_of.push_back({st.node, int(2 * (t - 1))});
@@ -537,6 +562,32 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             sig[i] = "L" + std::to_string(rq.degree_mask ? st.degF : 0);
         else
             sig[i] = "J(" + std::min(sig[st.in0], sig[st.in1]) + "," + std::max(sig[st.in0], sig[st.in1]) + ")";
+        if (ljoin[i]) {
+            // the holder of its signature, computed here (no alias: the
+            // deferred inputs' sizes are produced by this kernel only)
+            seen[sig[i]] = i;
+            refs[i] += uses[i];
+            const Step& ia = plan.steps[size_t(st.in0 - 1)];
+            const Step& ic = plan.steps[size_t(st.in1 - 1)];
+            SlotTab o = make(3, i);
+            SlotGrid G = slot_grid(g.n, B, o.a.R, 8);  // histograms amortised over more vertices per block
+            uint64_t* pa = part;
+            partials_done(size_t(st.in0 - 1), G.blocks);
+            uint64_t* pc = part;
+            partials_done(size_t(st.in1 - 1), G.blocks);
+            uint64_t* pj = part;
+            partials_done(i, G.blocks);
+            X.timed("slot_join", double(units) * 9.0 * (2.0 * (k - 1) + o.a.R) + csr, [&] {
+                launch_slot_leaf_join(G, g, rq.colors, k, rq.degree_mask ? ia.degF : 0,
+                                      rq.degree_mask ? plan.steps[size_t(ia.in0)].degF : 0,
+                                      rq.degree_mask ? plan.steps[size_t(ic.in0)].degF : 0, unrank, o.a, pa, pc, pj,
+                                      s);
+            });
+            tab[i] = o;
+            if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
+            budgeted.push_back(int(2 * i + 1));
+            continue;
+        }
         if (reuse(i)) {
             if (st.node >= 0) node_of.push_back({st.node, int(2 * phys[i] + 1)});
             if (st.kind == S_JOIN) {

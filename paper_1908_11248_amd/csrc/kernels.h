@@ -266,6 +266,13 @@ size_t slot_push_offset(int k, int p);
 void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
                       int degF_child, const uint16_t* rank, const uint16_t* unrank, int uoff, const uint64_t* pack,
                       bool in_narrow, bool in_exact, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
+// Two introduce-over-a-leaf steps at one bag vertex and their join, with the
+// children's tables never stored: out gets the join's table (colour sets of
+// 3), part_a / part_c / part_j the per-block entry partials of the two
+// children (introduce and forget) and of the join.  k >= 4.
+void launch_slot_leaf_join(const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u, int degF_a,
+                           int degF_c, const uint16_t* unrank, SlotArrays out, uint64_t* part_a, uint64_t* part_c,
+                           uint64_t* part_j, hipStream_t s);
 // The same step pushed from the child's rows into LDS accumulators; only for
 // a step whose counts cannot wrap (then every table below is exact).  s_in:
 // the child's colour-set size; push: the entries of (k, s_in - 1) above;

@@ -389,6 +389,104 @@ k_slot_edge_leaf(SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int
     count_entries(npres, nin, part, G.blocks);
 }
 
+// Two introduce-over-a-leaf steps at the same bag vertex u and the join of
+// their tables (Sec. 3): the children's tables are the neighbourhood colour
+// histograms h_a, h_c of v (neighbours passing the two leaves' degree masks),
+// so output slot (b, v, {colour(v), c1, c2}) is h_a[c1] h_c[c2] + h_a[c2]
+// h_c[c1] (below 2^63: each factor is at most the largest degree, below
+// 2^31).  The children's tables are never stored; their entry counts (the
+// introduce and forget nodes of each) go to part_a and part_c, the join's to
+// part_j.  Needs R = C(k - 1, 2) >= k - 1 (k >= 4): the threads of slots
+// r < k - 1 also count the children's entries of colour r (skipping
+// colour(v)).
+template <int M>
+__global__ void __launch_bounds__(kSlotBlock)
+k_slot_leaf_join(SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u, int degF_a,
+                 int degF_c, const uint16_t* __restrict__ unrank, int uoff2, SlotArrays out, uint64_t* part_a,
+                 uint64_t* part_c, uint64_t* part_j) {
+    // [upb M + 1] CSR offsets relative to the block's first vertex, then the
+    // [upb M][k] histograms h_a and h_c
+    extern __shared__ uint32_t s_leaf[];
+    uint32_t b, v0, v1, jb, v, r;
+    bool lane_ok;
+    block_range(G, &b, &v0, &v1, &jb);
+    slot_of(G, v0, jb, &v, &r, &lane_ok);
+    const uint32_t nv = v1 - v0, cap = uint32_t(G.upb * M);
+    const uint8_t* cb = colors + uint64_t(b) * uint32_t(g.n);
+    uint32_t* s_off = s_leaf;
+    uint32_t* h_a = s_leaf + cap + 1;
+    uint32_t* h_c = h_a + cap * uint32_t(k);
+    const int64_t e_lo = nv ? g.rp[v0] : 0;
+    for (uint32_t i = threadIdx.x; nv && i <= nv; i += kSlotBlock) s_off[i] = uint32_t(g.rp[v0 + i] - e_lo);
+    for (uint32_t i = threadIdx.x; i < nv * uint32_t(k); i += kSlotBlock) h_a[i] = h_c[i] = 0;
+    __syncthreads();
+    const uint32_t E = nv ? s_off[nv] : 0;
+    const uint32_t per = (E + kSlotBlock - 1) / kSlotBlock;
+    uint32_t e = min(E, threadIdx.x * per);
+    const uint32_t e_end = min(E, e + per);
+    if (e < e_end) {
+        // the vertex whose range holds entry e: s_off[lo] <= e < s_off[hi]
+        uint32_t lo = 0, hi = nv;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= e)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        uint32_t lv = lo;
+        for (; e < e_end; e += 4) {
+            uint32_t y[4], c[4];
+            int64_t d[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) y[j] = e + j < e_end ? uint32_t(g.col[e_lo + e + j]) : 0u;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                c[j] = cb[y[j]];
+                d[j] = degF_a > 1 || degF_c > 1 ? g.rp[y[j] + 1] - g.rp[y[j]] : 1;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (e + j >= e_end) break;
+                while (e + j >= s_off[lv + 1]) lv++;
+                if (d[j] >= degF_a) atomicAdd(&h_a[lv * uint32_t(k) + c[j]], 1u);
+                if (d[j] >= degF_c) atomicAdd(&h_c[lv * uint32_t(k) + c[j]], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t pr_a = 0, pr_c = 0, pr_j = 0, hi = 0;
+    uint64_t in_a = 0, in_c = 0;
+    const uint32_t m = lane_ok ? unrank[uoff2 + r] : 3u;  // two of the k - 1 other colours
+    const uint32_t p1 = __ffs(m) - 1, p2 = 31 - __clz(m);
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        const uint32_t vi = v + uint32_t(i * G.upb);
+        if (!(lane_ok && vi < v1)) continue;
+        const uint32_t lv = vi - v0;
+        const uint32_t cv = cb[vi];
+        const bool pass = s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u);
+        const uint32_t* ha = h_a + lv * uint32_t(k);
+        const uint32_t* hc = h_c + lv * uint32_t(k);
+        const uint32_t c1 = p1 + (p1 >= cv), c2 = p2 + (p2 >= cv);
+        const uint64_t cnt = pass ? uint64_t(ha[c1]) * hc[c2] + uint64_t(ha[c2]) * hc[c1] : 0;
+        store_slot(out, (uint64_t(b) * uint32_t(g.n) + vi) * uint32_t(G.R) + r, cnt, cnt != 0);
+        pr_j += cnt != 0;
+        hi |= uint32_t(cnt >> 32);
+        if (pass && r < uint32_t(k - 1)) {  // colour slot r of the children's tables
+            const uint32_t c = r + (r >= cv);
+            in_a += ha[c];
+            pr_a += ha[c] != 0;
+            in_c += hc[c];
+            pr_c += hc[c] != 0;
+        }
+    }
+    flag_wide(hi, &out.wide[b]);
+    count_entries(pr_a, in_a, part_a, G.blocks);
+    count_entries(pr_c, in_c, part_c, G.blocks);
+    count_entries(pr_j, 0, part_j, G.blocks);
+}
+
 // Introduce u (image v, every neighbour y of v is a candidate for the child's
 // bag vertex) followed by the forget of the child's vertex: output slot
 // (b, v, C) sums the child entries (b, y, C - colour(v)) over neighbours y,
@@ -1273,6 +1371,21 @@ void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, SlotArrays out, u
 #define LEAF_M(M) k_slot_leaf<M><<<slot_dims(G.blocks), kSlotBlock, 0, s>>>(G, g, degF, out, part)
     SLOT_BY_M(LEAF_M)
 #undef LEAF_M
+}
+
+void launch_slot_leaf_join(const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u, int degF_a,
+                           int degF_c, const uint16_t* unrank, SlotArrays out, uint64_t* part_a, uint64_t* part_c,
+                           uint64_t* part_j, hipStream_t s) {
+    if (!G.blocks) return;
+    if (k < 4 || G.upb == 0 || G.R != (k - 1) * (k - 2) / 2)
+        throw std::runtime_error("launch_slot_leaf_join: needs k >= 4 and R = C(k - 1, 2)");
+    const size_t lds = 4 * (size_t(G.upb) * G.m * (2 * k + 1) + 1);
+#define LEAF_JOIN_M(M)                                                                                              \
+    k_slot_leaf_join<M><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(G, g, colors, k, degF_u, degF_a, degF_c, unrank, \
+                                                                      slot_unrank_offset(2), out, part_a, part_c,   \
+                                                                      part_j)
+    SLOT_BY_M(LEAF_JOIN_M)
+#undef LEAF_JOIN_M
 }
 
 void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u,
