@@ -95,9 +95,14 @@ struct Lane {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint64_t* pinned = nullptr;
+    // pinned host words a run reads its results back into (a copy to
+    // pageable memory would go through a staging buffer and wait for it)
+    uint64_t* results = nullptr;
+    size_t results_words = 0;
     Profiler prof;
     void create(hipStream_t given);
     void destroy();
+    uint64_t* result_words(size_t words);  // at least `words`, kept until destroy
 };
 
 }  // namespace ccg

@@ -183,9 +183,24 @@ void Lane::create(hipStream_t given) {
     hip_check(hipHostMalloc((void**)&pinned, 64, hipHostMallocDefault), "hipHostMalloc");
 }
 
+uint64_t* Lane::result_words(size_t words) {
+    if (words > results_words) {
+        if (results) (void)hipHostFree(results);
+        results = nullptr;
+        results_words = 0;
+        const size_t n = std::max<size_t>(words, 1024);
+        hip_check(hipHostMalloc((void**)&results, n * 8, hipHostMallocDefault), "hipHostMalloc");
+        results_words = n;
+    }
+    return results;
+}
+
 void Lane::destroy() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (pinned) (void)hipHostFree(pinned);
+    if (results) (void)hipHostFree(results);
+    results = nullptr;
+    results_words = 0;
     if (own_stream && stream) (void)hipStreamDestroy(stream);
     pinned = nullptr;
     stream = nullptr;
@@ -632,8 +647,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     X.timed("slot_root", double(units) * 9.0 * rc.a.R, [&] {
         launch_slot_root(rc.a, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv, csets, cwords, s);
     });
-    std::vector<uint64_t> host(res_words);
-    hip_check(hipMemcpyAsync(host.data(), res, 8 * res_words, hipMemcpyDeviceToHost, s), "copy results");
+    uint64_t* host = X.lane.result_words(res_words);
+    hip_check(hipMemcpyAsync(host, res, 8 * res_words, hipMemcpyDeviceToHost, s), "copy results");
     if (pv) {
         out->per_vertex.assign(units, 0);
         hip_check(hipMemcpyAsync(out->per_vertex.data(), pv, 8 * units, hipMemcpyDeviceToHost, s), "copy per-vertex");
@@ -641,9 +656,9 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     X.synced();
     X.lane.prof.resolve();
-    out->counts.assign(host.begin(), host.begin() + B);
-    const std::vector<uint64_t> sizes(host.begin() + B, host.begin() + B + nsz_words);
-    const uint32_t* of = reinterpret_cast<const uint32_t*>(host.data() + B + nsz_words);
+    out->counts.assign(host, host + B);
+    const std::vector<uint64_t> sizes(host + B, host + B + nsz_words);
+    const uint32_t* of = reinterpret_cast<const uint32_t*>(host + B + nsz_words);
     const uint32_t* cs = of + B;
     for (int j : budgeted)
         if (rq.max_entries && sizes[j] > rq.max_entries)
