@@ -108,6 +108,33 @@ def test_hub_graph_dense_and_sparse_match_oracle(ctx, pat):
     C.close()
 
 
+@pytest.mark.parametrize("pat", [W.star(4), W.path(4)], ids=lambda p: p.name)
+def test_degree_past_16_bits_matches_oracle(ctx, pat):
+    # a hub of degree 65 599: the leaf steps and the fused leaf join count
+    # neighbourhoods past 2^16, and the block holding the hub splits its
+    # neighbour list over all of its threads
+    n = 65600
+    rng = np.random.default_rng(9)
+    a, b = rng.integers(1, n, 2000), rng.integers(1, n, 2000)
+    keep = a != b
+    g = W.csr_from_edges(n, np.concatenate([np.zeros(n - 1, dtype=np.int64), a[keep]]),
+                         np.concatenate([np.arange(1, n), b[keep]]))
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    B, k = 2, 5
+    colors = rng.integers(0, k, size=(B, g.n)).astype(np.uint8)
+    say("hub 2^16", pat.name)
+    D = cc.build_decomposition(pat.n, pat.edges)
+    C = cc.color_explicit(ctx, G, k, colors)
+    cd, od, sd = run(ctx, G, C, D, 0)
+    ref_sizes = np.zeros(len(sd), dtype=np.int64)
+    for bb in range(B):
+        ref = O.dp_count(g, pat, k, colors[bb], td=D.export(), sizes=True)
+        assert int(cd[bb]) == ref["count"] and bool(od[bb]) == ref["overflow"], (pat.name, bb)
+        ref_sizes += ref["sizes"]
+    assert np.array_equal(sd, ref_sizes)
+    C.close()
+
+
 def test_overflow_on_both_paths(ctx):
     # a hub of degree 6000: the star S7 overflows 64 bits
     n = 6001
