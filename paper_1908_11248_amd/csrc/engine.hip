@@ -638,14 +638,15 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
         budgeted.push_back(int(2 * i + 1));
     }
-    if (one_sum) launch_slot_sums(part_base, sums, nsz, s);
     hip_check(hipGetLastError(), "kernel launch");
 
     const SlotTab& rc = tab[plan.root_child];
     uint64_t* pv = nullptr;
     if (rq.per_vertex) pv = X.alloc<uint64_t>(units);  // every entry is written
     X.timed("slot_root", double(units) * 9.0 * rc.a.R, [&] {
-        launch_slot_root(rc.a, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv, csets, cwords, s);
+        // with the steps' entry partials (one_sum) reduced in its last launch
+        launch_slot_root(rc.a, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv, csets, cwords,
+                         part_base, sums, nsz, s);
     });
     uint64_t* host = X.lane.result_words(res_words);
     hip_check(hipMemcpyAsync(host, res, 8 * res_words, hipMemcpyDeviceToHost, s), "copy results");

@@ -292,9 +292,11 @@ void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int ns
                       bool in_exact, const SlotGrid& G, SlotArrays out, uint64_t* part, uint32_t* ovf, hipStream_t s);
 // rpart: slot_root_partials(n, B) words of scratch
 uint64_t slot_root_partials(int32_t n, int B);
+// Also reduces the steps' entry partials listed in sums (as launch_slot_sums)
+// in the same final launch.
 void launch_slot_root(SlotArrays in, int s_in, int32_t n, int B, const uint8_t* colors, const uint16_t* unrank,
                       uint64_t* rpart, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, uint32_t* csets,
-                      int cwords, hipStream_t s);
+                      int cwords, const uint64_t* part, const SlotSums& sums, uint64_t* nsz, hipStream_t s);
 
 // root: per colouring the sum of the entries (counts), a sticky overflow flag,
 // optionally the per-image sums of the bag vertex, and a bitmap of the colour

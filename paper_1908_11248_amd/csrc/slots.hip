@@ -1093,9 +1093,43 @@ k_slot_root(SlotArrays in, const uint8_t* __restrict__ colors, const uint16_t* _
     }
 }
 
-// counts[b] = the sum of colouring b's block partials; ovf[b] set if any wrapped
+// the partials of several steps: block x of step st adds every 16th
+// segment of its partials into nsz[2 step], nsz[2 step + 1]
+__device__ __forceinline__ void slot_sums_block(const uint64_t* __restrict__ part, const SlotSums& S, uint64_t* nsz,
+                                                int st, uint32_t x) {
+    const uint64_t* p = part + S.off[st];
+    const uint64_t blocks = S.blocks[st];
+    __shared__ uint64_t s_p[2][kSlotBlock / 64];
+    uint64_t a = 0, c = 0;
+    for (uint64_t i = uint64_t(x) * kSlotBlock + threadIdx.x; i < blocks; i += 16 * kSlotBlock) {
+        a += p[2 * i];
+        c += p[2 * i + 1];
+    }
+    a = wave_sum(a);
+    c = wave_sum(c);
+    if (__lane_id() == 0) {
+        s_p[0][threadIdx.x >> 6] = a;
+        s_p[1][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        uint64_t t = 0;
+        for (int i = 0; i < kSlotBlock / 64; i++) t += s_p[threadIdx.x][i];
+        if (t) atomicAdd((unsigned long long*)&nsz[2 * S.step[st] + threadIdx.x], (unsigned long long)t);
+    }
+}
+
+// counts[b] = the sum of colouring b's block partials; ovf[b] set if any
+// wrapped.  Blocks B and above reduce the steps' entry partials (as
+// k_slot_sums, 16 blocks per step), so both final reductions take one launch.
 __global__ void __launch_bounds__(kSlotBlock)
-k_slot_root_sum(const uint64_t* __restrict__ rpart, uint32_t nbx, uint64_t* counts, uint32_t* ovf) {
+k_slot_root_sum(const uint64_t* __restrict__ rpart, uint32_t nbx, int B, uint64_t* counts, uint32_t* ovf,
+                const uint64_t* __restrict__ part, SlotSums S, uint64_t* nsz) {
+    if (int(blockIdx.x) >= B) {
+        const uint32_t j = blockIdx.x - uint32_t(B);
+        slot_sums_block(part, S, nsz, int(j / 16), j % 16);
+        return;
+    }
     const uint32_t b = blockIdx.x;
     uint64_t sum = 0;
     bool over = false;
@@ -1135,27 +1169,7 @@ __global__ void __launch_bounds__(kSlotBlock) k_slot_sum(const uint64_t* __restr
 
 // the partials of several steps in one launch: blockIdx.y = step
 __global__ void __launch_bounds__(kSlotBlock) k_slot_sums(const uint64_t* __restrict__ part, SlotSums S, uint64_t* nsz) {
-    const int st = blockIdx.y;
-    const uint64_t* p = part + S.off[st];
-    const uint64_t blocks = S.blocks[st];
-    __shared__ uint64_t s_p[2][kSlotBlock / 64];
-    uint64_t a = 0, c = 0;
-    for (uint64_t i = uint64_t(blockIdx.x) * kSlotBlock + threadIdx.x; i < blocks; i += uint64_t(gridDim.x) * kSlotBlock) {
-        a += p[2 * i];
-        c += p[2 * i + 1];
-    }
-    a = wave_sum(a);
-    c = wave_sum(c);
-    if (__lane_id() == 0) {
-        s_p[0][threadIdx.x >> 6] = a;
-        s_p[1][threadIdx.x >> 6] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        uint64_t t = 0;
-        for (int i = 0; i < kSlotBlock / 64; i++) t += s_p[threadIdx.x][i];
-        if (t) atomicAdd((unsigned long long*)&nsz[2 * S.step[st] + threadIdx.x], (unsigned long long)t);
-    }
+    slot_sums_block(part, S, nsz, int(blockIdx.y), blockIdx.x);
 }
 
 void launch_slot_sums(const uint64_t* part, const SlotSums& S, uint64_t* nsz, hipStream_t s) {
@@ -1463,10 +1477,11 @@ void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int ns
 
 void launch_slot_root(SlotArrays in, int s_in, int32_t n, int B, const uint8_t* colors, const uint16_t* unrank,
                       uint64_t* rpart, uint64_t* counts, uint32_t* ovf, uint64_t* per_vertex, uint32_t* csets,
-                      int cwords, hipStream_t s) {
+                      int cwords, const uint64_t* part, const SlotSums& sums, uint64_t* nsz, hipStream_t s) {
     SlotGrid G = slot_grid(n, B, 1, 8);
     if (!G.blocks) {
         launch_fill_u64(counts, 0, uint64_t(B), s);
+        launch_slot_sums(part, sums, nsz, s);
         return;
     }
 #define ROOT_M(M)                                                                                                 \
@@ -1474,7 +1489,7 @@ void launch_slot_root(SlotArrays in, int s_in, int32_t n, int B, const uint8_t* 
         in, colors, unrank, slot_unrank_offset(s_in - 1), G, rpart, per_vertex, csets, cwords)
     SLOT_BY_M(ROOT_M)
 #undef ROOT_M
-    k_slot_root_sum<<<unsigned(B), kSlotBlock, 0, s>>>(rpart, G.nbx, counts, ovf);
+    k_slot_root_sum<<<unsigned(B) + 16u * sums.n, kSlotBlock, 0, s>>>(rpart, G.nbx, B, counts, ovf, part, sums, nsz);
 }
 
 uint64_t slot_root_partials(int32_t n, int B) { return 2 * uint64_t(slot_grid(n, B, 1, 8).nbx) * uint64_t(B); }
