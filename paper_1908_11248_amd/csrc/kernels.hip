@@ -659,54 +659,99 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const K* __restrict__ key
     hist[uint64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// stable scatter: items are ranked in (round, wave, lane) order, which is
-// their order in the input
+// Stable scatter of one tile: items are ranked in (round, wave, lane) order,
+// which is their order in the input, and placed in LDS in digit order; the
+// tile then leaves in that order, so the writes of one digit's run are
+// contiguous (keys first, then values, through the same LDS buffer).
 template <class K>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const K* __restrict__ keys, const uint64_t* __restrict__ vals,
-                                                          uint64_t n, int shift, const uint64_t* __restrict__ offs,
-                                                          uint64_t nblk, K* okeys, uint64_t* ovals) {
-    __shared__ uint64_t run[256];
+                                                          uint64_t n, int shift, const uint32_t* __restrict__ hist,
+                                                          const uint64_t* __restrict__ offs, uint64_t nblk, K* okeys,
+                                                          uint64_t* ovals) {
+    __shared__ K s_key[kRadixTile];                 // keys, then (as 64-bit words) values, in digit order
+    __shared__ uint8_t s_dig[kRadixTile];           // digit of every position
+    __shared__ uint32_t s_start[256];               // tile-local start of every digit
+    __shared__ uint64_t s_goff[256];                // where that digit's run goes
+    __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kBlock / 64][256];
+    __shared__ uint32_t s_wtot[kBlock / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    run[threadIdx.x] = offs[uint64_t(threadIdx.x) * nblk + blockIdx.x];
+    const uint64_t base = uint64_t(blockIdx.x) * kRadixTile;
+    const uint32_t cnt = uint32_t(n - base < uint64_t(kRadixTile) ? n - base : uint64_t(kRadixTile));
+    // exclusive scan of the tile's digit counts, one digit per thread
+    const uint32_t hd = hist[uint64_t(threadIdx.x) * nblk + blockIdx.x];
+    uint32_t x = hd;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wtot[w] = x;
     for (int i = lane; i < 256; i += 64) wcnt[w][i] = 0;
     __syncthreads();
-    uint64_t base = uint64_t(blockIdx.x) * kRadixTile;
+    uint32_t excl = x - hd;
+    for (int q = 0; q < w; q++) excl += s_wtot[q];
+    s_start[threadIdx.x] = excl;
+    run[threadIdx.x] = excl;
+    s_goff[threadIdx.x] = offs[uint64_t(threadIdx.x) * nblk + blockIdx.x];
+    // every item of the thread in flight at once
+    K k[kRadixItems];
+    uint64_t v[kRadixItems];
+#pragma unroll
     for (int r = 0; r < kRadixItems; r++) {
-        uint64_t i = base + uint64_t(r) * kBlock + threadIdx.x;
-        bool valid = i < n;
-        K k = valid ? keys[i] : K(0);
-        uint32_t d = valid ? (uint32_t(k >> shift) & 255u) : 0u;
+        const uint32_t i = uint32_t(r) * kBlock + threadIdx.x;
+        k[r] = i < cnt ? keys[base + i] : K(0);
+        v[r] = i < cnt ? vals[base + i] : 0;
+    }
+    __syncthreads();
+    uint32_t pos[kRadixItems];
+#pragma unroll
+    for (int r = 0; r < kRadixItems; r++) {
+        const bool valid = uint32_t(r) * kBlock + threadIdx.x < cnt;
+        const uint32_t d = valid ? (uint32_t(k[r] >> shift) & 255u) : 0u;
         uint64_t same = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; bit++) {
-            bool on = (d >> bit) & 1u;
-            uint64_t m = __ballot(on);
+            const bool on = (d >> bit) & 1u;
+            const uint64_t m = __ballot(on);
             same &= on ? m : ~m;
         }
-        uint32_t rank_in_wave = __popcll(same & lanemask_lt());
-        bool leader = valid && rank_in_wave == 0;
-        if (leader) wcnt[w][d] = __popcll(same);
+        const uint32_t rank_in_wave = __popcll(same & lanemask_lt());
+        if (valid && rank_in_wave == 0) wcnt[w][d] = __popcll(same);
         __syncthreads();
-        uint64_t dest = 0;
-        if (valid) {
-            dest = run[d] + rank_in_wave;
-            for (int q = 0; q < w; q++) dest += wcnt[q][d];
-        }
+        pos[r] = run[d] + rank_in_wave;
+        for (int q = 0; q < w; q++) pos[r] += wcnt[q][d];
+        if (!valid) pos[r] = ~0u;
         __syncthreads();
         {
             uint32_t t = 0;
             for (int q = 0; q < kBlock / 64; q++) {
                 t += wcnt[q][threadIdx.x];
+                wcnt[q][threadIdx.x] = 0;
             }
             run[threadIdx.x] += t;
-            for (int q = 0; q < kBlock / 64; q++) wcnt[q][threadIdx.x] = 0;
         }
-        __syncthreads();
-        if (valid) {
-            okeys[dest] = k;
-            ovals[dest] = vals[i];
+        __syncthreads();  // the counters are cleared before the next round's leaders write them
+    }
+#pragma unroll
+    for (int r = 0; r < kRadixItems; r++)
+        if (pos[r] != ~0u) {
+            s_key[pos[r]] = k[r];
+            s_dig[pos[r]] = uint8_t(uint32_t(k[r] >> shift) & 255u);
         }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+        const uint32_t d = s_dig[j];
+        okeys[s_goff[d] + (j - s_start[d])] = s_key[j];
+    }
+    __syncthreads();
+    uint64_t* s_val = reinterpret_cast<uint64_t*>(s_key);
+#pragma unroll
+    for (int r = 0; r < kRadixItems; r++)
+        if (pos[r] != ~0u) s_val[pos[r]] = v[r];
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+        const uint32_t d = s_dig[j];
+        ovals[s_goff[d] + (j - s_start[d])] = s_val[j];
     }
 }
 
@@ -738,11 +783,11 @@ void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, 
         }
         launch_scan_u32(hist, offs, h, stmp, s);
         if (kw == 1)
-            k_radix_scatter<uint64_t><<<unsigned(nblk), kBlock, 0, s>>>((const uint64_t*)src_k, src_v, n, shift, offs, nblk,
-                                                                        (uint64_t*)dst_k, dst_v);
+            k_radix_scatter<uint64_t><<<unsigned(nblk), kBlock, 0, s>>>((const uint64_t*)src_k, src_v, n, shift, hist,
+                                                                        offs, nblk, (uint64_t*)dst_k, dst_v);
         else
-            k_radix_scatter<u128><<<unsigned(nblk), kBlock, 0, s>>>((const u128*)src_k, src_v, n, shift, offs, nblk,
-                                                                    (u128*)dst_k, dst_v);
+            k_radix_scatter<u128><<<unsigned(nblk), kBlock, 0, s>>>((const u128*)src_k, src_v, n, shift, hist, offs,
+                                                                    nblk, (u128*)dst_k, dst_v);
         void* tk = src_k;
         src_k = dst_k;
         dst_k = tk;
