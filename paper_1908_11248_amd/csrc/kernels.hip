@@ -275,32 +275,39 @@ k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
          uint64_t G, uint32_t* gcount, const uint64_t* __restrict__ goff, KO* okeys, uint64_t* ocnt, uint32_t* ovf) {
     Acc acc = acc_bind(L.kb, EMIT);
     const int sh = L.kb + L.vb;  // drop the colour set and the last column
-    for (uint64_t grp = blockIdx.x; grp < G; grp += gridDim.x) {
-        uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
-        if (e1 - e0 <= kForgetSmall) continue;  // k_forget_small's
-        acc_clear(acc, EMIT);
-        __syncthreads();
-        bool over = false;
-        for (uint64_t e = e0 + threadIdx.x; e < e1; e += 64) {
-            uint32_t C = kset(keys[e], L);
-            atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
-            if (EMIT) {
-                uint64_t c = cnt[e];
-                uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)c);
-                over |= (old + c < old);
+    // 64 groups per visit: each lane reads one group's length, the block then
+    // takes the longer ones in turn (the others are k_forget_small's)
+    for (uint64_t g0 = uint64_t(blockIdx.x) * 64; g0 < G; g0 += uint64_t(gridDim.x) * 64) {
+        const uint64_t gl = g0 + threadIdx.x;
+        uint64_t todo = __ballot(gl < G && gstart[gl + 1] - gstart[gl] > uint64_t(kForgetSmall));
+        while (todo) {
+            const uint64_t grp = g0 + uint64_t(__ffsll((unsigned long long)todo) - 1);
+            todo &= todo - 1;
+            uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
+            acc_clear(acc, EMIT);
+            __syncthreads();
+            bool over = false;
+            for (uint64_t e = e0 + threadIdx.x; e < e1; e += 64) {
+                uint32_t C = kset(keys[e], L);
+                atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
+                if (EMIT) {
+                    uint64_t c = cnt[e];
+                    uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)c);
+                    over |= (old + c < old);
+                }
             }
+            __syncthreads();
+            if (EMIT) {
+                KI k0 = keys[e0];
+                if (__ballot(over) && threadIdx.x == 0) atomicOr(&ovf[kbid(k0, L)], 1u);
+                KO prefix = KO(shr(k0, sh)) << L.kb;
+                acc_emit<KO>(acc, prefix, goff[grp], okeys, ocnt);
+            } else {
+                uint32_t c = acc_count(acc);
+                if (threadIdx.x == 0) gcount[grp] = c;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (EMIT) {
-            KI k0 = keys[e0];
-            if (__ballot(over) && threadIdx.x == 0) atomicOr(&ovf[kbid(k0, L)], 1u);
-            KO prefix = KO(shr(k0, sh)) << L.kb;
-            acc_emit<KO>(acc, prefix, goff[grp], okeys, ocnt);
-        } else {
-            uint32_t c = acc_count(acc);
-            if (threadIdx.x == 0) gcount[grp] = c;
-        }
-        __syncthreads();
     }
 }
 
@@ -373,7 +380,8 @@ static void forget_dispatch(const DevTable& in, const uint64_t* gstart, uint64_t
                             const uint64_t* goff, DevTable* out, uint32_t* ovf, hipStream_t s) {
     if (!G) return;
     Lay LO{in.lay.b - 1, in.lay.vb, in.lay.kb, in.lay.bb};
-    unsigned grid = unsigned(G < (1u << 20) ? G : (1u << 20));
+    const uint64_t visits = (G + 63) / 64;
+    unsigned grid = unsigned(visits < (1u << 16) ? visits : (1u << 16));
     size_t lds = acc_bytes(in.lay.kb, EMIT);
     int ki = in.lay.kw(), ko = LO.kw();
     void* okk = out ? out->keys : nullptr;
