@@ -395,6 +395,12 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (st.in1 >= 0) uses[st.in1]++;
     }
     std::vector<SlotTab> tab(S);
+    // Every count of a table whose pattern subtree has s vertices is at most
+    // dmax^(s - 1): an embedding maps the subtree's vertices other than the
+    // bag vertex, parent before child, to neighbours of their parents'
+    // images.  log2 of that bound decides which arithmetic is exact.
+    const double ldmax = rq.g->sorted_deg.empty() ? 0.0 : std::log2(double(std::max<int64_t>(1, rq.g->sorted_deg.back())));
+    auto below = [&](int set, int bits) { return double(set - 1) * ldmax < double(bits) - 1e-9; };
     // A join whose two inputs are introduce-over-a-leaf steps (at its bag
     // vertex, used by nothing else) runs as one kernel from neighbourhood
     // colour histograms; those inputs are deferred (never stored).
@@ -411,6 +417,36 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             ljoin[i] = 1;
             defer[size_t(st.in0)] = defer[size_t(st.in1)] = 1;
         }
+    // A join of such a fused leaf join with an edge step in the push form (at
+    // the same bag vertex, both read by nothing else) runs in the edge step's
+    // kernel (PushJoin) when nothing can wrap, the leaves have no neighbour
+    // degree mask and 2 dmax^2 < 2^32: neither child table is stored.
+    // pskip: steps computed by such a kernel, at the join's place.
+    std::vector<int> pedge(S, -1);  // join -> its edge step (the forget)
+    std::vector<char> pskip(S, 0);
+    auto leaf_mask = [&](int t) {  // the neighbour degree mask of leaf edge t
+        return rq.degree_mask ? plan.steps[size_t(plan.steps[size_t(t - 1)].in0)].degF : 0;
+    };
+    if (k <= kSlotPackK && g.n < (1 << 24) && 1.0 + 2.0 * ldmax < 32.0 - 1e-9)
+        for (size_t i = 0; i < S; i++) {
+            const Step& st = plan.steps[i];
+            if (st.kind != S_JOIN || st.in0 == st.in1 || !below(sz[i], 64)) continue;
+            for (int side = 0; side < 2; side++) {
+                const int l = side ? st.in1 : st.in0, e = side ? st.in0 : st.in1;
+                if (!ljoin[size_t(l)] || uses[size_t(l)] != 1 || e < 1 || !fuse[size_t(e - 1)] || uses[size_t(e)] != 1)
+                    continue;
+                const Step& ie = plan.steps[size_t(e - 1)];
+                if (virt[size_t(ie.in0)] || defer[size_t(e)] || !below(sz[size_t(e)], 64) ||
+                    binom(k - 1, sz[size_t(e)] - 1) > kSlotBlock || binom(k - 1, sz[size_t(ie.in0)] - 1) > kSlotBlock)
+                    continue;
+                const Step& L = plan.steps[size_t(l)];
+                if (leaf_mask(L.in0) > 1 || leaf_mask(L.in1) > 1 || plan.steps[size_t(L.in0 - 1)].degF != ie.degF)
+                    continue;
+                pedge[i] = e;
+                pskip[size_t(e)] = pskip[size_t(l)] = 1;
+                break;
+            }
+        }
     // per step: introduce entries, output entries, added up from per-block
     // partials (one scratch buffer, reused step after step on the stream)
     // partials: one segment per step (summed by one launch at the end when
@@ -424,8 +460,11 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         }
     const bool one_sum = one_sum_plan;
     if (!one_sum) part_words = seg_max;
-    for (size_t i = 0; i < S; i++)  // the two extra segments of a fused leaf join
+    for (size_t i = 0; i < S; i++) {  // the two extra segments of a fused leaf join
         if (ljoin[i]) part_words += 4 * slot_grid(g.n, B, binom(k - 1, 2), 1).blocks;
+        // and the five of a join in a push kernel, on that kernel's grid
+        if (pedge[i] >= 0) part_words += 10 * slot_grid(g.n, B, binom(k - 1, sz[size_t(pedge[i])] - 1), 8).blocks;
+    }
     const uint64_t root_off = part_words;
     part_words += slot_root_partials(g.n, B);
     // One block for everything the host reads back and every flag, cleared by
@@ -457,12 +496,6 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             launch_slot_sum(part, blocks, nsz + 2 * i, s);
         }
     };
-    // Every count of a table whose pattern subtree has s vertices is at most
-    // dmax^(s - 1): an embedding maps the subtree's vertices other than the
-    // bag vertex, parent before child, to neighbours of their parents'
-    // images.  log2 of that bound decides which arithmetic is exact.
-    const double ldmax = rq.g->sorted_deg.empty() ? 0.0 : std::log2(double(std::max<int64_t>(1, rq.g->sorted_deg.back())));
-    auto below = [&](int set, int bits) { return double(set - 1) * ldmax < double(bits) - 1e-9; };
     const uint16_t* rank = ctx->slot_tables;
     const uint16_t* unrank = ctx->slot_tables + (1 << kSlotBits);
     const double csr = double(B) * (9.0 * g.n + 4.0 * g.m2);
@@ -526,7 +559,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (fuse[i]) {
             const Step& f = plan.steps[i + 1];
             sig[i + 1] = "E(" + sig[st.in0] + "," + std::to_string(rq.degree_mask ? st.degF : 0) + ")";
-            if (defer[i + 1]) {  // computed with its join; its sizes come from that kernel
+            if (defer[i + 1] || pskip[i + 1]) {  // computed with its join; its sizes come from that kernel
                 if (st.node >= 0) node_of.push_back({st.node, int(2 * i)});
                 if (f.node >= 0) node_of.push_back({f.node, int(2 * i + 1)});
                 budgeted.push_back(int(2 * i + 1));
@@ -558,7 +591,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 if (push)
                     launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, degF_u,
-                                          ctx->slot_push + slot_push_offset(k, in.s - 1), !below(o.s, 32), o.a, part, s);
+                                          ctx->slot_push + slot_push_offset(k, in.s - 1), !below(o.s, 32), o.a, part, nullptr, s);
                 else
                     launch_slot_edge(in.a, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
                                      slot_unrank_offset(o.s - 1), pack, !leafc && below(in.s, 32),
@@ -577,6 +610,50 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             sig[i] = "L" + std::to_string(rq.degree_mask ? st.degF : 0);
         else
             sig[i] = "J(" + std::min(sig[st.in0], sig[st.in1]) + "," + std::max(sig[st.in0], sig[st.in1]) + ")";
+        if (pskip[i]) {  // a leaf join computed in its reader's push kernel
+            if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
+            budgeted.push_back(int(2 * i + 1));
+            continue;
+        }
+        if (pedge[i] >= 0) {
+            seen[sig[i]] = i;  // the holder of its signature, computed here
+            refs[i] += uses[i];
+            const int e = pedge[i], l = st.in0 == e ? st.in1 : st.in0;
+            const Step& ie = plan.steps[size_t(e - 1)];
+            const Step& L = plan.steps[size_t(l)];
+            const SlotTab in = tab[ie.in0];
+            const int s_e = sz[size_t(e)];
+            SlotTab o = make(sz[i], i);
+            const int p = o.s - 1, q = (st.in0 == l ? 3 : s_e) - 1;
+            SlotGrid G = slot_grid(g.n, B, binom(k - 1, s_e - 1), 8);
+            PushJoin pj;
+            pj.splits = ctx->slot_splits + slot_split_offset(p, q);
+            pj.nsplit = binom(p, q);
+            pj.sstride = binom(kSlotBits, p);
+            pj.lj_is_y = st.in0 == l;
+            pj.unrank = unrank + slot_unrank_offset(2);
+            pj.out = o.a;
+            pj.part_e = part;
+            partials_done(size_t(e - 1), G.blocks);
+            pj.part_a = part;
+            partials_done(size_t(L.in0 - 1), G.blocks);
+            pj.part_c = part;
+            partials_done(size_t(L.in1 - 1), G.blocks);
+            pj.part_lj = part;
+            partials_done(size_t(l), G.blocks);
+            pj.part_j = part;
+            partials_done(i, G.blocks);
+            X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
+                launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, rq.degree_mask ? ie.degF : 0,
+                                      ctx->slot_push + slot_push_offset(k, in.s - 1), !below(s_e, 32), SlotArrays(),
+                                      nullptr, &pj, s);
+            });
+            tab[i] = o;
+            if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
+            budgeted.push_back(int(2 * i + 1));
+            done_with(ie.in0);
+            continue;
+        }
         if (ljoin[i]) {
             // the holder of its signature, computed here (no alias: the
             // deferred inputs' sizes are produced by this kernel only)

@@ -273,13 +273,32 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
 void launch_slot_leaf_join(const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u, int degF_a,
                            int degF_c, const uint16_t* unrank, SlotArrays out, uint64_t* part_a, uint64_t* part_c,
                            uint64_t* part_j, hipStream_t s);
+// A join computed in the epilogue of the push form of an edge step (its
+// child E): the other child is the fused join of two leaves at the same bag
+// vertex, neither with a neighbour degree mask, whose counts 2 h1 h2 stay
+// below 2^32; no count of the join can wrap.  E's table is not stored.
+struct PushJoin {
+    const uint32_t* splits = nullptr;  // the join's split table (slot_split_tables)
+    int nsplit = 0, sstride = 0;
+    int lj_is_y = 0;                   // the leaf join is the join's first child
+    const uint16_t* unrank = nullptr;  // colour pairs: unrank tables at slot_unrank_offset(2)
+    SlotArrays out;                    // the join's table
+    // per-block entry partials of E, the two leaves, the leaf join, the join
+    uint64_t* part_e = nullptr;
+    uint64_t* part_a = nullptr;
+    uint64_t* part_c = nullptr;
+    uint64_t* part_lj = nullptr;
+    uint64_t* part_j = nullptr;
+};
 // The same step pushed from the child's rows into LDS accumulators; only for
 // a step whose counts cannot wrap (then every table below is exact).  s_in:
 // the child's colour-set size; push: the entries of (k, s_in - 1) above;
-// wide: 64-bit accumulators (else every output count is below 2^32).
+// wide: 64-bit accumulators (else every output count is below 2^32).  pj
+// (optional): the step's only reader is that join, computed instead of
+// storing out (then out and part are unused).
 void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
                            int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
-                           hipStream_t s);
+                           const PushJoin* pj, hipStream_t s);
 constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
 // split table rows of (p, q) (see slots.hip) start at slot_split_offset(p, q);
 // row stride C(kSlotBits, p)

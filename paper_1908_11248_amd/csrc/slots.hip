@@ -640,6 +640,102 @@ k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ c
     count_entries(npres, nin, part, G.blocks);
 }
 
+// The join rows of push_join_epilogue: thread (slot r, first vertex) sums
+// four vertices' splits at a time; Y, Z are the join's children (the leaf
+// join rows in LDS as 32-bit words, E's accumulators).
+template <class TY, class TZ>
+__device__ __forceinline__ void push_join_rows(const TY* ys, uint32_t Ry, const TZ* zs, uint32_t Rz,
+                                               const uint32_t* s_sp, int nsplit, uint32_t nv, SlotArrays out,
+                                               uint64_t u0, uint32_t* pr, uint32_t* hi) {
+    const uint32_t R_j = uint32_t(out.R), up = kSlotBlock / R_j;
+    const uint32_t r = threadIdx.x % R_j, first = threadIdx.x / R_j;
+    if (first >= up) return;
+    for (uint32_t lv0 = first; lv0 < nv; lv0 += 4 * up) {
+        uint64_t sum[4] = {0, 0, 0, 0};
+        uint32_t by[4], bz[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t lv = min(lv0 + uint32_t(j) * up, nv - 1);  // rows past nv are read, then dropped
+            by[j] = lv * Ry;
+            bz[j] = lv * Rz;
+        }
+        for (int t = 0; t < nsplit; t++) {
+            const uint32_t sp = s_sp[uint32_t(t) * R_j + r];
+            const uint32_t ry = sp & 0xffffu, rz = sp >> 16;
+#pragma unroll
+            for (int j = 0; j < 4; j++) sum[j] += uint64_t(ys[by[j] + ry]) * uint64_t(zs[bz[j] + rz]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t lv = lv0 + uint32_t(j) * up;
+            if (lv >= nv) break;
+            store_slot(out, (u0 + lv) * R_j + r, sum[j], sum[j] != 0);
+            *pr += sum[j] != 0;
+            *hi |= uint32_t(sum[j] >> 32);
+        }
+    }
+}
+
+// Epilogue of k_slot_edge_push<.., true>: after the push, with E's rows in
+// acc and every vertex's neighbour counts by colour in s_h (vertices
+// 0 .. nv - 1 of the block, first unit u0), the leaf join rows, the join
+// and the entry partials of E, the two leaves, the leaf join and the join.
+template <class Acc>
+__device__ void push_join_epilogue(const Acc* acc, const uint32_t* s_off, const uint8_t* s_cv, const uint32_t* s_h,
+                                   uint32_t* s_lj, uint32_t* s_sp, uint32_t nv, uint32_t R, int k, int degF_u,
+                                   uint64_t u0, uint32_t b, uint32_t nin, const PushJoin& pj, uint64_t blocks) {
+    const uint32_t R_lj = uint32_t((k - 1) * (k - 2) / 2), R_j = uint32_t(pj.out.R);
+    // E: present slots (exact: present iff not 0)
+    uint32_t pr_e = 0;
+    for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) pr_e += acc[i] != 0;
+    // the leaf join, slot q = a pair {c1, c2} of the other colours: 2 h[c1]
+    // h[c2]; the threads of slots q < k - 1 also count the leaves' colour
+    // slot q (colour q, skipping colour(v)), h[colour], for both leaves
+    uint32_t pr_l = 0, pr_lj = 0;
+    uint64_t in_l = 0;
+    {
+        const uint32_t up = kSlotBlock / R_lj, q = threadIdx.x % R_lj, first = threadIdx.x / R_lj;
+        if (first < up) {
+            const uint32_t m = pj.unrank[q];
+            const uint32_t p1 = __ffs(m) - 1, p2 = 31 - __clz(m);
+            for (uint32_t lv = first; lv < nv; lv += up) {
+                const uint32_t cv = s_cv[lv];
+                const uint32_t* h = s_h + lv * uint32_t(k);
+                uint32_t x = 0;
+                if (s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u)) {
+                    x = 2u * h[p1 + (p1 >= cv)] * h[p2 + (p2 >= cv)];
+                    if (q < uint32_t(k - 1)) {
+                        const uint32_t hq = h[q + (q >= cv)];
+                        pr_l += hq != 0;
+                        in_l += hq;
+                    }
+                }
+                s_lj[lv * R_lj + q] = x;
+                pr_lj += x != 0;
+            }
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < uint32_t(pj.nsplit) * R_j; i += kSlotBlock) {
+        const uint32_t t = i / R_j;
+        s_sp[i] = pj.splits[size_t(t) * pj.sstride + (i - t * R_j)];
+    }
+    __syncthreads();
+    // the join: exact sums of exact products (no count of it can wrap)
+    uint32_t pr_j = 0, hi = 0;
+    if (nv) {
+        if (pj.lj_is_y)
+            push_join_rows(s_lj, R_lj, acc, R, s_sp, pj.nsplit, nv, pj.out, u0, &pr_j, &hi);
+        else
+            push_join_rows(acc, R, s_lj, R_lj, s_sp, pj.nsplit, nv, pj.out, u0, &pr_j, &hi);
+    }
+    flag_wide(hi, &pj.out.wide[b]);
+    count_entries(pr_e, nin, pj.part_e, blocks);
+    count_entries(pr_l, in_l, pj.part_a, blocks);
+    count_entries(pr_l, in_l, pj.part_c, blocks);
+    count_entries(pr_lj, 0, pj.part_lj, blocks);
+    count_entries(pr_j, 0, pj.part_j, blocks);
+}
+
 // The same step pushed from the child's rows: for a neighbour entry (v, y)
 // with colour(y) != colour(v), the child slots of y whose set C_y leaves out
 // colour(v) are the same C(k-2, s_in-1) = W slots for every such pair of
@@ -651,13 +747,24 @@ k_slot_edge(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ c
 // can wrap (a degree bound), so every child table is exact and a sum is
 // present iff it is not 0.  WIDE: 64-bit accumulators, else every output
 // count is below 2^32.
-template <bool WIDE>
+//
+// EPI: the step's table E is not stored.  Its only reader, a join at the
+// same bag vertex with the fused leaf join of two leaves hanging off that
+// vertex (Sec. 3, join nodes; leaves without a neighbour degree mask), is
+// computed here instead (PushJoin): the block counts its vertices'
+// neighbours by colour while it stages them, which gives the leaf tables
+// h[c] and the leaf join 2 h[c1] h[c2] (below 2^32 by a bound), and the join
+// output follows from the split table with E's rows still in LDS.  The
+// partials of all five tables are written.
+template <bool WIDE, bool EPI>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
-                 const uint32_t* __restrict__ cmap, int W, SlotArrays out, uint64_t* part) {
+                 const uint32_t* __restrict__ cmap, int W, SlotArrays out, uint64_t* part, PushJoin pj) {
     using Acc = typename std::conditional<WIDE, unsigned long long, uint32_t>::type;
     // [upb M][R] accumulators, [upb M + 1] CSR offsets, the k k W (child
-    // slot, output slot) pairs of cmap, [upb M] colours
+    // slot, output slot) pairs of cmap, [upb M] colours; EPI: then (4-byte
+    // aligned) [upb M][k] neighbour counts by colour, [upb M][R_lj] leaf join
+    // rows, the join's split rows
     extern __shared__ uint64_t s_dyn[];
     __shared__ uint32_t s_y[kPushChunk];   // neighbour | colour << 24
     // its vertex within the block | (colour(y) k + colour(v)) << 16, or
@@ -672,12 +779,18 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     uint32_t* s_off = reinterpret_cast<uint32_t*>(acc + cap * R);
     uint32_t* s_cm = s_off + cap + 1;
     uint8_t* s_cv = reinterpret_cast<uint8_t*>(s_cm + k * k * W);
+    uint32_t* s_h = reinterpret_cast<uint32_t*>(s_cm + k * k * W + (cap + 3) / 4);
+    const uint32_t R_lj = uint32_t((k - 1) * (k - 2) / 2);
+    uint32_t* s_lj = s_h + cap * uint32_t(k);
+    uint32_t* s_sp = s_lj + cap * R_lj;
     const uint64_t row0 = uint64_t(b) * uint32_t(g.n);
     const uint8_t* cb = colors + row0;
     const uint32_t* ilo = in.lo + row0 * R_in;
     const uint32_t* ihi = in.hi ? in.hi + row0 * R_in : nullptr;
     const int64_t e_lo = nv ? g.rp[v0] : 0;
     for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) acc[i] = 0;
+    if (EPI)
+        for (uint32_t i = threadIdx.x; i < nv * uint32_t(k); i += kSlotBlock) s_h[i] = 0;
     for (uint32_t i = threadIdx.x; nv && i <= nv; i += kSlotBlock) s_off[i] = uint32_t(g.rp[v0 + i] - e_lo);
     for (uint32_t i = threadIdx.x; i < nv; i += kSlotBlock) s_cv[i] = cb[v0 + i];
     for (uint32_t i = threadIdx.x; i < uint32_t(k * k * W); i += kSlotBlock) s_cm[i] = cmap[i];
@@ -710,6 +823,7 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
             for (uint32_t e = a; e < z; e++) {
                 const uint32_t cy = s_y[e - c0] >> 24;
                 s_lv[e - c0] = pass && cy != cv ? lv | ((cy * uint32_t(k) + cv) << 16) : 0xffffffffu;
+                if (EPI) s_h[lv * uint32_t(k) + cy]++;  // row lv is this thread's alone
             }
         }
         __syncthreads();
@@ -742,6 +856,10 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
             }
         }
         __syncthreads();
+    }
+    if (EPI) {
+        push_join_epilogue<Acc>(acc, s_off, s_cv, s_h, s_lj, s_sp, nv, R, k, degF_u, row0 + v0, b, nin, pj, G.blocks);
+        return;
     }
     uint32_t npres = 0, hi = 0;
 #pragma unroll 4
@@ -1431,19 +1549,33 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
 
 void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
                            int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
-                           hipStream_t s) {
+                           const PushJoin* pj, hipStream_t s) {
     if (!G.blocks) return;
     if (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0 || s_in < 1 || s_in > k - 1)
         throw std::runtime_error("launch_slot_edge_push: needs k <= 8, n < 2^24, R <= 256 and a child set below k");
     const int W = binom_pq(k - 2, s_in - 1);
     const size_t cap = size_t(G.upb) * G.m;
-    const size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 4 * size_t(k) * k * W + cap;
-    if (wide)
-        k_slot_edge_push<true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, out,
-                                                                             part);
-    else
-        k_slot_edge_push<false><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, out,
-                                                                              part);
+    size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 4 * size_t(k) * k * W + 4 * ((cap + 3) / 4);
+    PushJoin none{};
+    if (pj) {
+        if (k < 4) throw std::runtime_error("launch_slot_edge_push: a fused join needs k >= 4");
+        lds += 4 * (cap * size_t(k) + cap * size_t((k - 1) * (k - 2) / 2) + size_t(pj->nsplit) * pj->out.R);
+    }
+#define PUSH_LAUNCH(WIDE, EPI)                                                                                     \
+    k_slot_edge_push<WIDE, EPI><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, \
+                                                                              out, part, pj ? *pj : none)
+    if (pj) {
+        if (wide)
+            PUSH_LAUNCH(true, true);
+        else
+            PUSH_LAUNCH(false, true);
+    } else {
+        if (wide)
+            PUSH_LAUNCH(true, false);
+        else
+            PUSH_LAUNCH(false, false);
+    }
+#undef PUSH_LAUNCH
 }
 
 void launch_slot_join(SlotArrays y, SlotArrays z, const uint32_t* splits, int nsplit, int sstride, bool nowrap,

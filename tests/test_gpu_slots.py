@@ -135,6 +135,39 @@ def test_degree_past_16_bits_matches_oracle(ctx, pat):
     C.close()
 
 
+# a vertex with two leaf children and one deeper child: the join of the
+# leaves' fused join with the deeper child's edge step runs in that step's
+# push kernel (k <= 8, no count can wrap); vertex orders vary which child the
+# plan joins first
+PUSH_JOIN = [W.Pattern(5, [(0, 1), (0, 2), (0, 3), (3, 4)], "LJ+P2"),
+             W.Pattern(6, [(0, 3), (3, 4), (4, 5), (0, 1), (0, 2)], "LJ+P3"),
+             W.Pattern(7, [(0, 1), (1, 2), (1, 3), (1, 4), (4, 5), (0, 6)], "LJ+P2+up"),
+             W.workload_pattern(2)]
+
+
+@pytest.mark.parametrize("gname", ["er40", "rgg300", "ba400", "hub"])
+def test_push_join_matches_oracle(ctx, gname):
+    g = hub_graph() if gname == "hub" else dict(GRAPHS)[gname]()
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    rng = np.random.default_rng(len(gname) + 7)
+    for pat in PUSH_JOIN:
+        for k in sorted({pat.n, min(pat.n + 2, 8)}):
+            B = 9 if gname != "hub" else 3
+            colors = rng.integers(0, k, size=(B, g.n)).astype(np.uint8)
+            say("push join", gname, pat.name, "k", k)
+            D = cc.build_decomposition(pat.n, pat.edges)
+            td = D.export()
+            C = cc.color_explicit(ctx, G, k, colors)
+            cd, od, sd = run(ctx, G, C, D, 0)
+            ref_sizes = np.zeros(len(sd), dtype=np.int64)
+            for b in range(B):
+                ref = O.dp_count(g, pat, k, colors[b], td=td, sizes=True)
+                assert int(cd[b]) == ref["count"] and bool(od[b]) == ref["overflow"], (gname, pat.name, k, b)
+                ref_sizes += ref["sizes"]
+            assert np.array_equal(sd, ref_sizes), (gname, pat.name, k)
+            C.close()
+
+
 def test_overflow_on_both_paths(ctx):
     # a hub of degree 6000: the star S7 overflows 64 bits
     n = 6001
