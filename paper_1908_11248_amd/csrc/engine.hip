@@ -447,6 +447,60 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                 break;
             }
         }
+    // Likewise an edge step in the push form joined with one leaf edge at its
+    // bag vertex, and that join (read by nothing else) with a second one:
+    // chain[i] = (edge step, first leaf, second leaf or -1, first join or -1)
+    // at the join that launches it.
+    struct Chain {
+        int e = -1, lx = -1, ly = -1, mid = -1;
+    };
+    std::vector<Chain> chain(S);
+    std::vector<int> reader(S, -1);
+    for (size_t i = 0; i < S; i++)
+        for (int in : {plan.steps[i].in0, plan.steps[i].in1})
+            if (in >= 0) reader[size_t(in)] = int(i);
+    auto push_edge = [&](int e) {  // an edge step this fusion can take
+        if (e < 1 || !fuse[size_t(e - 1)] || uses[size_t(e)] != 1 || defer[size_t(e)] || pskip[size_t(e)]) return false;
+        const Step& ie = plan.steps[size_t(e - 1)];
+        return !virt[size_t(ie.in0)] && below(sz[size_t(e)], 64) && binom(k - 1, sz[size_t(e)] - 1) <= kSlotBlock &&
+               binom(k - 1, sz[size_t(ie.in0)] - 1) <= kSlotBlock;
+    };
+    auto push_leaf = [&](int t, int e) {  // a leaf edge at e's bag vertex without a neighbour mask
+        return leaf_edge(t) && !defer[size_t(t)] && !pskip[size_t(t)] && leaf_mask(t) <= 1 &&
+               plan.steps[size_t(t - 1)].degF == plan.steps[size_t(e - 1)].degF;
+    };
+    if (one_sum_plan && k <= kSlotPackK && g.n < (1 << 24))
+        for (size_t i = 0; i < S; i++) {
+            const Step& st = plan.steps[i];
+            if (st.kind != S_JOIN || st.in0 == st.in1 || pedge[i] >= 0 || pskip[i] || !below(sz[i], 64)) continue;
+            int e = -1, lx = -1;
+            if (push_edge(st.in0) && push_leaf(st.in1, st.in0)) {
+                e = st.in0;
+                lx = st.in1;
+            } else if (push_edge(st.in1) && push_leaf(st.in0, st.in1)) {
+                e = st.in1;
+                lx = st.in0;
+            } else {
+                continue;
+            }
+            Chain c;
+            c.e = e;
+            c.lx = lx;
+            size_t at = i;
+            const int i2 = reader[i];
+            if (uses[i] == 1 && i2 >= 0 && plan.steps[size_t(i2)].kind == S_JOIN && below(sz[size_t(i2)], 64)) {
+                const Step& s2 = plan.steps[size_t(i2)];
+                const int ly = s2.in0 == int(i) ? s2.in1 : s2.in0;
+                if (ly != int(i) && ly != lx && push_leaf(ly, e)) {
+                    c.ly = ly;
+                    c.mid = int(i);
+                    at = size_t(i2);
+                    pskip[i] = pskip[size_t(ly)] = 1;
+                }
+            }
+            chain[at] = c;
+            pskip[size_t(e)] = pskip[size_t(lx)] = 1;
+        }
     // per step: introduce entries, output entries, added up from per-block
     // partials (one scratch buffer, reused step after step on the stream)
     // partials: one segment per step (summed by one launch at the end when
@@ -464,6 +518,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (ljoin[i]) part_words += 4 * slot_grid(g.n, B, binom(k - 1, 2), 1).blocks;
         // and the five of a join in a push kernel, on that kernel's grid
         if (pedge[i] >= 0) part_words += 10 * slot_grid(g.n, B, binom(k - 1, sz[size_t(pedge[i])] - 1), 8).blocks;
+        if (chain[i].e >= 0) part_words += 10 * slot_grid(g.n, B, binom(k - 1, sz[size_t(chain[i].e)] - 1), 8).blocks;
     }
     const uint64_t root_off = part_words;
     part_words += slot_root_partials(g.n, B);
@@ -643,6 +698,58 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             partials_done(size_t(l), G.blocks);
             pj.part_j = part;
             partials_done(i, G.blocks);
+            X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
+                launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, rq.degree_mask ? ie.degF : 0,
+                                      ctx->slot_push + slot_push_offset(k, in.s - 1), !below(s_e, 32), SlotArrays(),
+                                      nullptr, &pj, s);
+            });
+            tab[i] = o;
+            if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
+            budgeted.push_back(int(2 * i + 1));
+            done_with(ie.in0);
+            continue;
+        }
+        if (chain[i].e >= 0) {
+            seen[sig[i]] = i;  // the holder of its signature, computed here
+            refs[i] += uses[i];
+            const Chain& c = chain[i];
+            const Step& ie = plan.steps[size_t(c.e - 1)];
+            const SlotTab in = tab[ie.in0];
+            const int s_e = sz[size_t(c.e)];
+            SlotTab o = make(sz[i], i);
+            SlotGrid G = slot_grid(g.n, B, binom(k - 1, s_e - 1), 8);
+            const size_t j1 = c.mid >= 0 ? size_t(c.mid) : i;  // the join of E with the first leaf
+            const int p1 = sz[j1] - 1, q1 = (plan.steps[j1].in0 == c.e ? s_e : 2) - 1;
+            PushJoin pj;
+            pj.chain = c.mid >= 0 ? 2 : 1;
+            pj.splits1 = ctx->slot_splits + slot_split_offset(p1, q1);
+            pj.nsplit1 = binom(p1, q1);
+            pj.sstride1 = binom(kSlotBits, p1);
+            pj.r1 = binom(k - 1, sz[j1] - 1);
+            pj.e_is_y1 = plan.steps[j1].in0 == c.e;
+            if (c.mid >= 0) {
+                const int p = o.s - 1, q = (st.in0 == c.mid ? sz[size_t(c.mid)] : 2) - 1;
+                pj.splits = ctx->slot_splits + slot_split_offset(p, q);
+                pj.nsplit = binom(p, q);
+                pj.sstride = binom(kSlotBits, p);
+                pj.e_is_y2 = st.in0 == c.mid;
+            }
+            pj.out = o.a;
+            pj.part_e = part;
+            partials_done(size_t(c.e - 1), G.blocks);
+            pj.part_a = part;
+            partials_done(size_t(c.lx - 1), G.blocks);
+            pj.part_c = pj.part_a;
+            if (c.ly >= 0) {
+                pj.part_c = part;
+                partials_done(size_t(c.ly - 1), G.blocks);
+            }
+            pj.part_lj = part;
+            partials_done(j1, G.blocks);
+            if (c.mid >= 0) {
+                pj.part_j = part;
+                partials_done(i, G.blocks);
+            }
             X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, rq.degree_mask ? ie.degF : 0,
                                       ctx->slot_push + slot_push_offset(k, in.s - 1), !below(s_e, 32), SlotArrays(),

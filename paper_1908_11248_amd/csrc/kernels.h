@@ -273,17 +273,29 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
 void launch_slot_leaf_join(const SlotGrid& G, DevGraph g, const uint8_t* colors, int k, int degF_u, int degF_a,
                            int degF_c, const uint16_t* unrank, SlotArrays out, uint64_t* part_a, uint64_t* part_c,
                            uint64_t* part_j, hipStream_t s);
-// A join computed in the epilogue of the push form of an edge step (its
-// child E): the other child is the fused join of two leaves at the same bag
-// vertex, neither with a neighbour degree mask, whose counts 2 h1 h2 stay
-// below 2^32; no count of the join can wrap.  E's table is not stored.
+// Joins computed in the epilogue of the push form of an edge step (its
+// child E), at the same bag vertex, with leaves hanging off that vertex (no
+// neighbour degree mask; no count of the joins can wrap).  E's table is not
+// stored.  chain = 0: one join of E with the fused join of two leaves (its
+// counts 2 h1 h2 below 2^32).  chain = 1: E joined with one leaf; chain =
+// 2: that result (not stored) joined with a second leaf.
 struct PushJoin {
-    const uint32_t* splits = nullptr;  // the join's split table (slot_split_tables)
+    int chain = 0;
+    const uint32_t* splits = nullptr;  // the (last) join's split table (slot_split_tables)
     int nsplit = 0, sstride = 0;
-    int lj_is_y = 0;                   // the leaf join is the join's first child
-    const uint16_t* unrank = nullptr;  // colour pairs: unrank tables at slot_unrank_offset(2)
-    SlotArrays out;                    // the join's table
-    // per-block entry partials of E, the two leaves, the leaf join, the join
+    int lj_is_y = 0;                   // chain 0: the leaf join is the join's first child
+    const uint16_t* unrank = nullptr;  // chain 0: colour pairs, unrank tables at slot_unrank_offset(2)
+    // chain >= 1: the first join (E with a leaf): split table, slots of its
+    // output, E (chain 2: that output) as the first child of each join
+    const uint32_t* splits1 = nullptr;
+    int nsplit1 = 0, sstride1 = 0, r1 = 0;
+    int e_is_y1 = 0, e_is_y2 = 0;
+    // set by the launcher: the epilogue's rows, its split rows, fit the
+    // push kernel's chunk arrays
+    int rows_static = 0, spl_static = 0;
+    SlotArrays out;                    // the last join's table
+    // per-block entry partials of E, the two leaves (chain 1: both the one
+    // leaf), the leaf join (chain >= 1: the first join), the last join
     uint64_t* part_e = nullptr;
     uint64_t* part_a = nullptr;
     uint64_t* part_c = nullptr;

@@ -676,6 +676,47 @@ __device__ __forceinline__ void push_join_rows(const TY* ys, uint32_t Ry, const 
     }
 }
 
+// A join of LDS rows X (stride Rx) with a leaf's table at the same vertex
+// (slot q of vertex lv: h[colour q, skipping colour(v)]), thread (slot r,
+// first vertex) summing four vertices at a time; the rows go to LDS (to,
+// stride R_o) or, when to is null, to out.
+template <class TX>
+__device__ __forceinline__ void push_leaf_rows(const TX* xs, uint32_t Rx, bool x_is_y, const uint32_t* s_h,
+                                               const uint8_t* s_cv, int k, const uint32_t* s_sp, int nsplit,
+                                               uint32_t nv, uint32_t R_o, uint64_t* to, SlotArrays out, uint64_t u0,
+                                               uint32_t* pr, uint32_t* hi) {
+    const uint32_t up = kSlotBlock / R_o;
+    const uint32_t r = threadIdx.x % R_o, first = threadIdx.x / R_o;
+    if (first >= up) return;
+    for (uint32_t lv0 = first; lv0 < nv; lv0 += 4 * up) {
+        uint64_t sum[4] = {0, 0, 0, 0};
+        uint32_t lvs[4], cv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            lvs[j] = min(lv0 + uint32_t(j) * up, nv - 1);  // rows past nv are read, then dropped
+            cv[j] = s_cv[lvs[j]];
+        }
+        for (int t = 0; t < nsplit; t++) {
+            const uint32_t sp = s_sp[uint32_t(t) * R_o + r];
+            const uint32_t rx = x_is_y ? sp & 0xffffu : sp >> 16, rl = x_is_y ? sp >> 16 : sp & 0xffffu;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                sum[j] += uint64_t(xs[lvs[j] * Rx + rx]) * s_h[lvs[j] * uint32_t(k) + rl + (rl >= cv[j])];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t lv = lv0 + uint32_t(j) * up;
+            if (lv >= nv) break;
+            if (to)
+                to[lv * R_o + r] = sum[j];
+            else
+                store_slot(out, (u0 + lv) * R_o + r, sum[j], sum[j] != 0);
+            *pr += sum[j] != 0;
+            *hi |= uint32_t(sum[j] >> 32);
+        }
+    }
+}
+
 // Epilogue of k_slot_edge_push<.., true>: after the push, with E's rows in
 // acc and every vertex's neighbour counts by colour in s_h (vertices
 // 0 .. nv - 1 of the block, first unit u0), the leaf join rows, the join
@@ -688,6 +729,58 @@ __device__ void push_join_epilogue(const Acc* acc, const uint32_t* s_off, const 
     // E: present slots (exact: present iff not 0)
     uint32_t pr_e = 0;
     for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) pr_e += acc[i] != 0;
+    if (pj.chain) {
+        // E joined with one leaf (then the result with a second one): the
+        // leaves' tables, and the first join's rows in LDS (s_lj, as 64-bit
+        // words) when there are two
+        uint32_t pr_l = 0;
+        uint64_t in_l = 0;
+        for (uint32_t i = threadIdx.x; i < nv * uint32_t(k - 1); i += kSlotBlock) {
+            const uint32_t lv = i / uint32_t(k - 1), q = i - lv * uint32_t(k - 1);
+            if (s_off[lv + 1] - s_off[lv] < uint32_t(degF_u)) continue;
+            const uint32_t hq = s_h[lv * uint32_t(k) + q + (q >= s_cv[lv])];
+            pr_l += hq != 0;
+            in_l += hq;
+        }
+        const uint32_t R_1 = uint32_t(pj.r1);
+        uint32_t* sp1 = s_sp;
+        uint32_t* sp2 = s_sp + pj.nsplit1 * R_1;
+        for (uint32_t i = threadIdx.x; i < uint32_t(pj.nsplit1) * R_1; i += kSlotBlock) {
+            const uint32_t t = i / R_1;
+            sp1[i] = pj.splits1[size_t(t) * pj.sstride1 + (i - t * R_1)];
+        }
+        if (pj.chain == 2)
+            for (uint32_t i = threadIdx.x; i < uint32_t(pj.nsplit) * R_j; i += kSlotBlock) {
+                const uint32_t t = i / R_j;
+                sp2[i] = pj.splits[size_t(t) * pj.sstride + (i - t * R_j)];
+            }
+        __syncthreads();
+        uint32_t pr_1 = 0, pr_j = 0, hi = 0;
+        uint64_t* s_t1 = reinterpret_cast<uint64_t*>(s_lj);
+        if (nv) {
+            if (pj.chain == 2) {
+                uint32_t hi1 = 0;
+                push_leaf_rows(acc, R, pj.e_is_y1, s_h, s_cv, k, sp1, pj.nsplit1, nv, R_1, s_t1, pj.out, u0, &pr_1,
+                               &hi1);
+            } else {
+                push_leaf_rows(acc, R, pj.e_is_y1, s_h, s_cv, k, sp1, pj.nsplit1, nv, R_1, nullptr, pj.out, u0, &pr_j,
+                               &hi);
+            }
+        }
+        if (pj.chain == 2) {
+            __syncthreads();
+            if (nv)
+                push_leaf_rows(s_t1, R_1, pj.e_is_y2, s_h, s_cv, k, sp2, pj.nsplit, nv, R_j, nullptr, pj.out, u0, &pr_j,
+                               &hi);
+        }
+        flag_wide(hi, &pj.out.wide[b]);
+        count_entries(pr_e, nin, pj.part_e, blocks);
+        count_entries(pr_l, in_l, pj.part_a, blocks);
+        count_entries(pr_l, in_l, pj.part_c, blocks);
+        count_entries(pj.chain == 2 ? pr_1 : pr_j, 0, pj.part_lj, blocks);
+        if (pj.chain == 2) count_entries(pr_j, 0, pj.part_j, blocks);
+        return;
+    }
     // the leaf join, slot q = a pair {c1, c2} of the other colours: 2 h[c1]
     // h[c2]; the threads of slots q < k - 1 also count the leaves' colour
     // slot q (colour q, skipping colour(v)), h[colour], for both leaves
@@ -763,13 +856,16 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     using Acc = typename std::conditional<WIDE, unsigned long long, uint32_t>::type;
     // [upb M][R] accumulators, [upb M + 1] CSR offsets, the k k W (child
     // slot, output slot) pairs of cmap, [upb M] colours; EPI: then (4-byte
-    // aligned) [upb M][k] neighbour counts by colour, [upb M][R_lj] leaf join
-    // rows, the join's split rows
+    // aligned) [upb M][k] neighbour counts by colour, then the epilogue's
+    // rows and split rows (PushJoin) unless they fit s_stat
     extern __shared__ uint64_t s_dyn[];
-    __shared__ uint32_t s_y[kPushChunk];   // neighbour | colour << 24
-    // its vertex within the block | (colour(y) k + colour(v)) << 16, or
-    // 0xffffffff when v is masked or the colours are equal
-    __shared__ uint32_t s_lv[kPushChunk];
+    // the staged neighbour entries of a chunk, free again after the push:
+    // s_y: neighbour | colour << 24; s_lv: its vertex within the block |
+    // (colour(y) k + colour(v)) << 16, or 0xffffffff when v is masked or the
+    // colours are equal
+    __shared__ uint64_t s_stat[kPushChunk];
+    uint32_t* s_y = reinterpret_cast<uint32_t*>(s_stat);
+    uint32_t* s_lv = s_y + kPushChunk;
     uint32_t b, v0, v1, jb, v, r;
     bool lane_ok;
     block_range(G, &b, &v0, &v1, &jb);
@@ -781,8 +877,15 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     uint8_t* s_cv = reinterpret_cast<uint8_t*>(s_cm + k * k * W);
     uint32_t* s_h = reinterpret_cast<uint32_t*>(s_cm + k * k * W + (cap + 3) / 4);
     const uint32_t R_lj = uint32_t((k - 1) * (k - 2) / 2);
-    uint32_t* s_lj = s_h + cap * uint32_t(k);
-    uint32_t* s_sp = s_lj + cap * R_lj;
+    // the epilogue's rows (8-byte aligned: a chain keeps 64-bit rows), then
+    // its split rows, each in the chunk arrays when the launcher found room
+    const uint32_t epi_rows = pj.chain == 2 ? 2u * cap * uint32_t(pj.r1) : pj.chain ? 0u : cap * R_lj;
+    uint32_t* s_next = s_h + cap * uint32_t(k);
+    s_next += (reinterpret_cast<uintptr_t>(s_next) >> 2) & 1u;
+    uint32_t* s_st = reinterpret_cast<uint32_t*>(s_stat);
+    uint32_t* s_lj = pj.rows_static ? s_st : s_next;
+    if (!pj.rows_static) s_next += epi_rows;
+    uint32_t* s_sp = pj.spl_static ? s_st + (pj.rows_static ? epi_rows : 0u) : s_next;
     const uint64_t row0 = uint64_t(b) * uint32_t(g.n);
     const uint8_t* cb = colors + row0;
     const uint32_t* ilo = in.lo + row0 * R_in;
@@ -1557,13 +1660,24 @@ void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph 
     const size_t cap = size_t(G.upb) * G.m;
     size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 4 * size_t(k) * k * W + 4 * ((cap + 3) / 4);
     PushJoin none{};
+    PushJoin pjl;
     if (pj) {
-        if (k < 4) throw std::runtime_error("launch_slot_edge_push: a fused join needs k >= 4");
-        lds += 4 * (cap * size_t(k) + cap * size_t((k - 1) * (k - 2) / 2) + size_t(pj->nsplit) * pj->out.R);
+        if (!pj->chain && k < 4) throw std::runtime_error("launch_slot_edge_push: a fused leaf join needs k >= 4");
+        pjl = *pj;
+        // the epilogue's rows and split rows (32-bit words), in the chunk
+        // arrays (kPushChunk 64-bit words) when they fit
+        const size_t rows = pj->chain == 2 ? 2 * cap * size_t(pj->r1)
+                            : pj->chain    ? 0
+                                           : cap * size_t((k - 1) * (k - 2) / 2);
+        const size_t spl = pj->chain ? size_t(pj->nsplit1) * pj->r1 + (pj->chain == 2 ? size_t(pj->nsplit) * pj->out.R : 0)
+                                     : size_t(pj->nsplit) * pj->out.R;
+        pjl.rows_static = rows <= 2 * size_t(kPushChunk);
+        pjl.spl_static = (pjl.rows_static ? rows : 0) + spl <= 2 * size_t(kPushChunk);
+        lds += 4 * cap * size_t(k) + 4 + 4 * ((pjl.rows_static ? 0 : rows) + (pjl.spl_static ? 0 : spl));
     }
 #define PUSH_LAUNCH(WIDE, EPI)                                                                                     \
     k_slot_edge_push<WIDE, EPI><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, \
-                                                                              out, part, pj ? *pj : none)
+                                                                              out, part, pj ? pjl : none)
     if (pj) {
         if (wide)
             PUSH_LAUNCH(true, true);

@@ -135,13 +135,16 @@ def test_degree_past_16_bits_matches_oracle(ctx, pat):
     C.close()
 
 
-# a vertex with two leaf children and one deeper child: the join of the
-# leaves' fused join with the deeper child's edge step runs in that step's
-# push kernel (k <= 8, no count can wrap); vertex orders vary which child the
-# plan joins first
+# joins at a vertex computed in the push kernel of its deeper child's edge
+# step (k <= 8, no count can wrap): with the fused join of two leaf children
+# ("LJ+"), or with one leaf and then another ("chain"); vertex orders decide
+# which children the plan joins first.  On the hub graph the chain of a
+# 4-vertex child runs with 64-bit accumulators.
 PUSH_JOIN = [W.Pattern(5, [(0, 1), (0, 2), (0, 3), (3, 4)], "LJ+P2"),
              W.Pattern(6, [(0, 3), (3, 4), (4, 5), (0, 1), (0, 2)], "LJ+P3"),
-             W.Pattern(7, [(0, 1), (1, 2), (1, 3), (1, 4), (4, 5), (0, 6)], "LJ+P2+up"),
+             W.Pattern(7, [(0, 1), (1, 2), (1, 3), (1, 4), (4, 5), (0, 6)], "LJ+P2+chain1"),
+             W.Pattern(5, [(0, 1), (1, 2), (0, 3), (0, 4)], "chain2-P3"),
+             W.Pattern(6, [(0, 1), (1, 2), (2, 3), (0, 4), (0, 5)], "chain2-P4"),
              W.workload_pattern(2)]
 
 
