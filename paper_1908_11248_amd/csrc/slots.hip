@@ -96,7 +96,8 @@ __device__ __forceinline__ void slot_of(const SlotGrid& G, uint32_t v0, uint32_t
 
 // Entry counts of a block: (extra, present) summed over its threads and
 // stored at part[2L], part[2L + 1] (L = block index); k_slot_sum adds them
-// up.  Plain stores: no address is shared between blocks.
+// up.  Plain stores: no address is shared between blocks.  Ends with a
+// barrier, so the next call may reuse the per-wave slots.
 __device__ __forceinline__ void count_entries_at(uint32_t present, uint64_t extra, uint64_t* part, uint64_t blocks,
                                                  uint32_t L) {
     __shared__ uint64_t s_p[2][kSlotBlock / 64];
@@ -112,6 +113,32 @@ __device__ __forceinline__ void count_entries_at(uint32_t present, uint64_t extr
         for (int i = 0; i < kSlotBlock / 64; i++) t += s_p[threadIdx.x][i];
         part[2 * uint64_t(L) + threadIdx.x] = t;
     }
+    __syncthreads();
+}
+
+// count_entries for N tables at once (one barrier pair): part[j] gets
+// (extra[j], present[j]).
+template <int N>
+__device__ __forceinline__ void count_entries_n(const uint32_t (&present)[N], const uint64_t (&extra)[N],
+                                                uint64_t* const (&part)[N], uint64_t blocks) {
+    __shared__ uint64_t s_q[2 * N][kSlotBlock / 64];
+    const uint32_t L = block_index();
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        const uint64_t ex = wave_sum(extra[j]);
+        const uint64_t pr = wave_sum(present[j]);
+        if (__lane_id() == 0) {
+            s_q[2 * j][threadIdx.x >> 6] = ex;
+            s_q[2 * j + 1][threadIdx.x >> 6] = pr;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * N && L < blocks) {
+        uint64_t t = 0;
+        for (int i = 0; i < kSlotBlock / 64; i++) t += s_q[threadIdx.x][i];
+        part[threadIdx.x / 2][2 * uint64_t(L) + (threadIdx.x & 1)] = t;
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ void count_entries(uint32_t present, uint64_t extra, uint64_t* part, uint64_t blocks) {
@@ -774,11 +801,17 @@ __device__ void push_join_epilogue(const Acc* acc, const uint32_t* s_off, const 
                                &hi);
         }
         flag_wide(hi, &pj.out.wide[b]);
-        count_entries(pr_e, nin, pj.part_e, blocks);
-        count_entries(pr_l, in_l, pj.part_a, blocks);
-        count_entries(pr_l, in_l, pj.part_c, blocks);
-        count_entries(pj.chain == 2 ? pr_1 : pr_j, 0, pj.part_lj, blocks);
-        if (pj.chain == 2) count_entries(pr_j, 0, pj.part_j, blocks);
+        if (pj.chain == 2) {
+            const uint32_t prs[5] = {pr_e, pr_l, pr_l, pr_1, pr_j};
+            const uint64_t exs[5] = {nin, in_l, in_l, 0, 0};
+            uint64_t* const parts[5] = {pj.part_e, pj.part_a, pj.part_c, pj.part_lj, pj.part_j};
+            count_entries_n<5>(prs, exs, parts, blocks);
+        } else {  // one leaf: part_c is part_a
+            const uint32_t prs[3] = {pr_e, pr_l, pr_j};
+            const uint64_t exs[3] = {nin, in_l, 0};
+            uint64_t* const parts[3] = {pj.part_e, pj.part_a, pj.part_lj};
+            count_entries_n<3>(prs, exs, parts, blocks);
+        }
         return;
     }
     // the leaf join, slot q = a pair {c1, c2} of the other colours: 2 h[c1]
@@ -822,11 +855,10 @@ __device__ void push_join_epilogue(const Acc* acc, const uint32_t* s_off, const 
             push_join_rows(acc, R, s_lj, R_lj, s_sp, pj.nsplit, nv, pj.out, u0, &pr_j, &hi);
     }
     flag_wide(hi, &pj.out.wide[b]);
-    count_entries(pr_e, nin, pj.part_e, blocks);
-    count_entries(pr_l, in_l, pj.part_a, blocks);
-    count_entries(pr_l, in_l, pj.part_c, blocks);
-    count_entries(pr_lj, 0, pj.part_lj, blocks);
-    count_entries(pr_j, 0, pj.part_j, blocks);
+    const uint32_t prs[5] = {pr_e, pr_l, pr_l, pr_lj, pr_j};
+    const uint64_t exs[5] = {nin, in_l, in_l, 0, 0};
+    uint64_t* const parts[5] = {pj.part_e, pj.part_a, pj.part_c, pj.part_lj, pj.part_j};
+    count_entries_n<5>(prs, exs, parts, blocks);
 }
 
 // The same step pushed from the child's rows: for a neighbour entry (v, y)
