@@ -1039,7 +1039,10 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     uint64_t W = X.scan(wcount, G, &woff);
                     X.release(wcount);
                     uint32_t* slen = X.alloc<uint32_t>(W);
-                    X.timed("push_seglen", 24.0 * W, [&] { launch_push_seglen(in, gstart, woff, G, W, g, ia, slen, s); });
+                    // each segment's candidate and its colour, for the expand passes
+                    ia.segv = g.n <= (1 << 27) ? X.alloc<uint32_t>(W) : nullptr;
+                    X.timed("push_seglen", 28.0 * W,
+                            [&] { launch_push_seglen(in, gstart, woff, G, W, g, rq.colors, ia, slen, s); });
                     uint64_t* soff;
                     uint64_t T = X.scan(slen, W, &soff);
                     X.release(slen);
@@ -1063,6 +1066,8 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     X.release(toff);
                     X.release(soff);
                     X.release(woff);
+                    X.release(ia.segv);
+                    ia.segv = nullptr;
                     X.release(gsel);
                     X.release(gstart);
                     break;

@@ -26,8 +26,8 @@ constexpr int kExpTile = kBlock * kExpItems;
 
 template <class K>
 __global__ void k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gstart,
-                              const uint64_t* __restrict__ woff, uint64_t G, uint64_t W, DevGraph g, IntroArgs a,
-                              uint32_t* slen) {
+                              const uint64_t* __restrict__ woff, uint64_t G, uint64_t W, DevGraph g,
+                              const uint8_t* __restrict__ colors, IntroArgs a, uint32_t* slen) {
     for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < W; s += uint64_t(gridDim.x) * blockDim.x) {
         uint64_t grp = upper_bound_u64(woff, 0, G + 1, s) - 1;
         uint64_t t = s - woff[grp];
@@ -40,6 +40,7 @@ __global__ void k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t*
         for (int c = 0; c < a.nchk && ok; c++)
             if (a.chk[c] < a.pos && a.chk[c] != src) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
         slen[s] = ok ? uint32_t(gstart[grp + 1] - gstart[grp]) : 0u;
+        if (a.segv) a.segv[s] = v | uint32_t(colors[uint64_t(kbid(k0, L)) * uint32_t(g.n) + v]) << 27;
     }
 }
 
@@ -77,8 +78,15 @@ __device__ __forceinline__ SegState seg_state(uint64_t s, uint64_t* grp, const K
         st.base = rstart[uint64_t(st.bid) * uint64_t(g.n) + uint32_t(g.col[e])];
     } else {
         while (woff[*grp + 1] <= s) (*grp)++;
-        uint64_t t = s - woff[*grp];
         st.base = gstart[*grp];
+        if (a.segv) {  // v and its colour from the seglen pass
+            const uint32_t sv = a.segv[s];
+            st.v = sv & ((1u << 27) - 1u);
+            st.cb = 1u << (sv >> 27);
+            st.bid = 0;  // not needed: an item's colouring is in its own key
+            return st;
+        }
+        uint64_t t = s - woff[*grp];
         K k0 = keys[st.base];
         st.bid = kbid(k0, L);
         const int src = a.anchor >= 0 && a.sel ? int(a.sel[*grp]) : a.anchor;
@@ -199,13 +207,12 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
         uint32_t rest = pass;
         while (rest) {
             uint64_t idx[4];
-            uint32_t vv[4], bid4[4], cb4[4];
+            uint32_t vv[4], cb4[4];
             int nb = 0;
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 idx[j] = st.base;
                 vv[j] = st.v;
-                bid4[j] = st.bid;
                 cb4[j] = st.cb;
                 if (rest) {
                     const uint64_t t = t0 + uint64_t(__ffs(rest) - 1);
@@ -217,7 +224,6 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
                     }
                     idx[j] = st.base + (t - soff[seg]);
                     vv[j] = st.v;
-                    bid4[j] = st.bid;
                     cb4[j] = st.cb;
                     nb = j + 1;
                 }
@@ -239,7 +245,7 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
                 } else {
                     for (int c = 0, s2 = 0; c < LO.b; c++) cols[c] = (c == a.pos) ? vv[j] : kcol(kk[j], L, s2++);
                 }
-                okeys[o] = kpack<KO>(bid4[j], cols, LO.b, kset(kk[j], L) | cb4[j], LO);
+                okeys[o] = kpack<KO>(kbid(kk[j], L), cols, LO.b, kset(kk[j], L) | cb4[j], LO);
                 ocnt[o] = cv[j];
                 if (osrc) osrc[o] = idx[j];
                 o++;
@@ -251,13 +257,15 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
 // ---- launchers -------------------------------------------------------------
 
 void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
-                        DevGraph g, const IntroArgs& a, uint32_t* slen, hipStream_t s) {
+                        DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* slen, hipStream_t s) {
     if (!W) return;
+    if (a.segv && g.n > (1 << 27)) throw std::runtime_error("launch_push_seglen: packed segment vertices need n <= 2^27");
     if (in.lay.kw() == 1)
-        k_push_seglen<uint64_t><<<grid_for(W), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, gstart, woff, G, W, g, a,
-                                                               slen);
+        k_push_seglen<uint64_t><<<grid_for(W), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, gstart, woff, G, W, g,
+                                                               colors, a, slen);
     else
-        k_push_seglen<u128><<<grid_for(W), kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, woff, G, W, g, a, slen);
+        k_push_seglen<u128><<<grid_for(W), kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, woff, G, W, g, colors,
+                                                           a, slen);
 }
 
 void launch_pull_seglen(const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g, int degF, uint32_t* slen,

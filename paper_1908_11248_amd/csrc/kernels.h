@@ -99,13 +99,17 @@ struct IntroArgs {
     // adjacency list gives the candidates (the others are checked).  Written
     // by launch_push_work; null: the anchor.
     uint8_t* sel = nullptr;
+    // push form, per segment (optional, n < 2^27): its candidate vertex v |
+    // colour(v) << 27, written by launch_push_seglen and read by the expand
+    // instead of walking group -> first key -> adjacency list -> colour again
+    uint32_t* segv = nullptr;
 };
 void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, DevGraph g,
                       const IntroArgs& a, uint32_t* wcount, hipStream_t s);
 // load-balanced expand of introduce candidates (expand.hip): segment
 // lengths, then count and emit over tiles of expand_tiles(T) items
 void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
-                        DevGraph g, const IntroArgs& a, uint32_t* slen, hipStream_t s);
+                        DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* slen, hipStream_t s);
 void launch_pull_seglen(const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g, int degF, uint32_t* slen,
                         hipStream_t s);
 uint64_t expand_tiles(uint64_t T);
