@@ -427,6 +427,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     auto leaf_mask = [&](int t) {  // the neighbour degree mask of leaf edge t
         return rq.degree_mask ? plan.steps[size_t(plan.steps[size_t(t - 1)].in0)].degF : 0;
     };
+    // (joins in the push kernel: k <= 8, where their LDS rows always fit)
     if (k <= kSlotPackK && g.n < (1 << 24) && 1.0 + 2.0 * ldmax < 32.0 - 1e-9)
         for (size_t i = 0; i < S; i++) {
             const Step& st = plan.steps[i];
@@ -639,7 +640,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                                        : nullptr;
             // push from the child's rows whenever no count can wrap: a
             // (neighbour, child slot) pair of the push is always useful
-            const bool push = pack && below(o.s, 64) && in.a.R <= kSlotBlock;
+            const bool push = !leafc && k <= kSlotPushK && g.n < (1 << 24) && o.a.R <= kSlotBlock &&
+                              below(o.s, 64) && in.a.R <= kSlotBlock;
             // vertices per thread (measured on workload 2): the gather's
             // latency wants more blocks, the push's LDS accumulators longer rows
             SlotGrid G = slot_grid(g.n, B, o.a.R, leafc ? 4 : push ? 8 : 2);

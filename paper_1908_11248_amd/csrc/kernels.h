@@ -257,10 +257,13 @@ void launch_slot_leaf(const SlotGrid& G, DevGraph g, int degF, SlotArrays out, u
 constexpr int kSlotPackK = 8;
 std::vector<uint64_t> slot_pack_tables();
 size_t slot_pack_offset(int k, int p);
-// Pushed edge steps (k <= kSlotPackK): for child colour-set size p + 1, child
+// Pushed edge steps (k <= kSlotPushK; the list of one colour pair, at most
+// C(8, 4) = 70 slots, and all k^2 lists fit a block's LDS): for child
+// colour-set size p + 1, child
 // bag colour cy and output bag colour cv != cy, entry (cy k + cv) W + w of
 // the block at slot_push_offset(k, p), W = C(k - 2, p), holds the w-th child
 // slot r whose set leaves cv out, | the output slot of that set plus cv << 16.
+constexpr int kSlotPushK = 10;
 std::vector<uint32_t> slot_push_tables();
 size_t slot_push_offset(int k, int p);
 // in.lo == nullptr: the child is a leaf (count 1 per vertex passing

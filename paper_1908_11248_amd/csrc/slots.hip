@@ -1583,7 +1583,7 @@ std::vector<uint64_t> slot_pack_tables() {
 // given colour other than the child's own
 size_t slot_push_offset(int k, int p) {
     size_t off = 0;
-    for (int kk = 2; kk <= kSlotPackK; kk++)
+    for (int kk = 2; kk <= kSlotPushK; kk++)
         for (int pp = 0; pp < kk - 1; pp++) {
             if (kk == k && pp == p) return off;
             off += size_t(kk) * kk * binom_pq(kk - 2, pp);
@@ -1594,8 +1594,8 @@ size_t slot_push_offset(int k, int p) {
 std::vector<uint32_t> slot_push_tables() {
     std::vector<uint16_t> rt = slot_rank_tables();
     const int M = 1 << kSlotBits;
-    std::vector<uint32_t> t(slot_push_offset(kSlotPackK + 1, 0), 0xffffffffu);
-    for (int k = 2; k <= kSlotPackK; k++)
+    std::vector<uint32_t> t(slot_push_offset(kSlotPushK + 1, 0), 0xffffffffu);
+    for (int k = 2; k <= kSlotPushK; k++)
         for (int p = 0; p < k - 1; p++) {
             const int R = binom_pq(k - 1, p), W = binom_pq(k - 2, p);
             const size_t off = slot_push_offset(k, p);
@@ -1686,8 +1686,8 @@ void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph 
                            int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
                            const PushJoin* pj, hipStream_t s) {
     if (!G.blocks) return;
-    if (k > kSlotPackK || g.n >= (1 << 24) || G.upb == 0 || s_in < 1 || s_in > k - 1)
-        throw std::runtime_error("launch_slot_edge_push: needs k <= 8, n < 2^24, R <= 256 and a child set below k");
+    if (k > kSlotPushK || g.n >= (1 << 24) || G.upb == 0 || s_in < 1 || s_in > k - 1)
+        throw std::runtime_error("launch_slot_edge_push: needs k <= 10, n < 2^24, R <= 256 and a child set below k");
     const int W = binom_pq(k - 2, s_in - 1);
     const size_t cap = size_t(G.upb) * G.m;
     size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 4 * size_t(k) * k * W + 4 * ((cap + 3) / 4);
@@ -1707,6 +1707,7 @@ void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph 
         pjl.spl_static = (pjl.rows_static ? rows : 0) + spl <= 2 * size_t(kPushChunk);
         lds += 4 * cap * size_t(k) + 4 + 4 * ((pjl.rows_static ? 0 : rows) + (pjl.spl_static ? 0 : spl));
     }
+    if (lds > 64 * 1024) throw std::runtime_error("launch_slot_edge_push: LDS beyond 64 KiB");
 #define PUSH_LAUNCH(WIDE, EPI)                                                                                     \
     k_slot_edge_push<WIDE, EPI><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, \
                                                                               out, part, pj ? pjl : none)

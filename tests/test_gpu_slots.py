@@ -5,9 +5,9 @@ over colourings) must be identical, bit for bit, on both paths.
 
 Batches of 9 colourings cover the XCD-interleaved block mapping with a
 ragged last group; k = 12 with 7-vertex trees gives 462 slots per vertex,
-more than one block's threads.  Trees with k <= 8 run the edge steps in
-both the gather and the push form, and a graph with a hub covers their
-64-bit variants.
+more than one block's threads.  Trees with k <= 10 run the edge steps in
+the push form where no count can wrap and in the gather form otherwise;
+a graph with a hub covers their 64-bit variants.
 """
 import sys
 
@@ -86,14 +86,15 @@ def hub_graph(n=2500, m=3000, seed=5):
     return W.csr_from_edges(n, src, dst)
 
 
+@pytest.mark.parametrize("k", [8, 10])
 @pytest.mark.parametrize("pat", [W.path(5), W.random_tree(6, 3), W.random_tree(7, 5)], ids=lambda p: p.name)
-def test_hub_graph_dense_and_sparse_match_oracle(ctx, pat):
+def test_hub_graph_dense_and_sparse_match_oracle(ctx, pat, k):
     g = hub_graph()
     G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
-    rng = np.random.default_rng(pat.n)
-    B, k = 5, 8
+    rng = np.random.default_rng(pat.n + k)
+    B = 5
     colors = rng.integers(0, k, size=(B, g.n)).astype(np.uint8)
-    say("hub", pat.name)
+    say("hub", pat.name, "k", k)
     D = cc.build_decomposition(pat.n, pat.edges)
     C = cc.color_explicit(ctx, G, k, colors)
     cd, od, sd = run(ctx, G, C, D, 0)
