@@ -427,8 +427,13 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     auto leaf_mask = [&](int t) {  // the neighbour degree mask of leaf edge t
         return rq.degree_mask ? plan.steps[size_t(plan.steps[size_t(t - 1)].in0)].degF : 0;
     };
-    // (joins in the push kernel: k <= 8, where their LDS rows always fit)
-    if (k <= kSlotPackK && g.n < (1 << 24) && 1.0 + 2.0 * ldmax < 32.0 - 1e-9)
+    // an edge step's push kernel (child set s_in, output s_e) fits a block's
+    // LDS with the epilogue pj (null: none)
+    auto push_fits = [&](int s_in, int s_e, const PushJoin* pj) {
+        const SlotGrid G = slot_grid(g.n, B, binom(k - 1, s_e - 1), 8);
+        return slot_push_lds(k, s_in, G, !below(s_e, 32), pj) <= kPushLdsMax;
+    };
+    if (k <= kSlotPushK && g.n < (1 << 24) && 1.0 + 2.0 * ldmax < 32.0 - 1e-9)
         for (size_t i = 0; i < S; i++) {
             const Step& st = plan.steps[i];
             if (st.kind != S_JOIN || st.in0 == st.in1 || !below(sz[i], 64)) continue;
@@ -443,6 +448,10 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                 const Step& L = plan.steps[size_t(l)];
                 if (leaf_mask(L.in0) > 1 || leaf_mask(L.in1) > 1 || plan.steps[size_t(L.in0 - 1)].degF != ie.degF)
                     continue;
+                PushJoin shape;
+                shape.nsplit = binom(sz[i] - 1, (st.in0 == l ? 3 : sz[size_t(e)]) - 1);
+                shape.out.R = binom(k - 1, sz[i] - 1);
+                if (!push_fits(sz[size_t(ie.in0)], sz[size_t(e)], &shape)) continue;
                 pedge[i] = e;
                 pskip[size_t(e)] = pskip[size_t(l)] = 1;
                 break;
@@ -470,7 +479,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         return leaf_edge(t) && !defer[size_t(t)] && !pskip[size_t(t)] && leaf_mask(t) <= 1 &&
                plan.steps[size_t(t - 1)].degF == plan.steps[size_t(e - 1)].degF;
     };
-    if (one_sum_plan && k <= kSlotPackK && g.n < (1 << 24))
+    if (one_sum_plan && k <= kSlotPushK && g.n < (1 << 24))
         for (size_t i = 0; i < S; i++) {
             const Step& st = plan.steps[i];
             if (st.kind != S_JOIN || st.in0 == st.in1 || pedge[i] >= 0 || pskip[i] || !below(sz[i], 64)) continue;
@@ -488,17 +497,28 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             c.e = e;
             c.lx = lx;
             size_t at = i;
+            const int s_in = sz[size_t(plan.steps[size_t(e - 1)].in0)];
+            PushJoin shape;  // the first join's sizes (the launch uses the same)
+            shape.chain = 1;
+            shape.r1 = binom(k - 1, sz[i] - 1);
+            shape.nsplit1 = binom(sz[i] - 1, (st.in0 == e ? sz[size_t(e)] : 2) - 1);
+            shape.out.R = shape.r1;
             const int i2 = reader[i];
             if (uses[i] == 1 && i2 >= 0 && plan.steps[size_t(i2)].kind == S_JOIN && below(sz[size_t(i2)], 64)) {
                 const Step& s2 = plan.steps[size_t(i2)];
                 const int ly = s2.in0 == int(i) ? s2.in1 : s2.in0;
-                if (ly != int(i) && ly != lx && push_leaf(ly, e)) {
+                PushJoin two = shape;
+                two.chain = 2;
+                two.nsplit = binom(sz[size_t(i2)] - 1, (s2.in0 == int(i) ? sz[i] : 2) - 1);
+                two.out.R = binom(k - 1, sz[size_t(i2)] - 1);
+                if (ly != int(i) && ly != lx && push_leaf(ly, e) && push_fits(s_in, sz[size_t(e)], &two)) {
                     c.ly = ly;
                     c.mid = int(i);
                     at = size_t(i2);
                     pskip[i] = pskip[size_t(ly)] = 1;
                 }
             }
+            if (c.mid < 0 && !push_fits(s_in, sz[size_t(e)], &shape)) continue;
             chain[at] = c;
             pskip[size_t(e)] = pskip[size_t(lx)] = 1;
         }
@@ -641,7 +661,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             // push from the child's rows whenever no count can wrap: a
             // (neighbour, child slot) pair of the push is always useful
             const bool push = !leafc && k <= kSlotPushK && g.n < (1 << 24) && o.a.R <= kSlotBlock &&
-                              below(o.s, 64) && in.a.R <= kSlotBlock;
+                              below(o.s, 64) && in.a.R <= kSlotBlock && push_fits(in.s, o.s, nullptr);
             // vertices per thread (measured on workload 2): the gather's
             // latency wants more blocks, the push's LDS accumulators longer rows
             SlotGrid G = slot_grid(g.n, B, o.a.R, leafc ? 4 : push ? 8 : 2);

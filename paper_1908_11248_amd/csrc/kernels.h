@@ -318,6 +318,11 @@ struct PushJoin {
 void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
                            int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
                            const PushJoin* pj, hipStream_t s);
+// Dynamic LDS bytes of that launch (pj: its sizes chain, r1, nsplit1, nsplit
+// and out.R are used); a launch needs at most kPushLdsMax (64 KiB per block
+// less the kernel's static arrays).
+size_t slot_push_lds(int k, int s_in, const SlotGrid& G, bool wide, const PushJoin* pj);
+constexpr size_t kPushLdsMax = 54 * 1024;
 constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
 // split table rows of (p, q) (see slots.hip) start at slot_split_offset(p, q);
 // row stride C(kSlotBits, p)

@@ -1682,20 +1682,13 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
 #undef EDGE_ARGS
 }
 
-void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
-                           int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
-                           const PushJoin* pj, hipStream_t s) {
-    if (!G.blocks) return;
-    if (k > kSlotPushK || g.n >= (1 << 24) || G.upb == 0 || s_in < 1 || s_in > k - 1)
-        throw std::runtime_error("launch_slot_edge_push: needs k <= 10, n < 2^24, R <= 256 and a child set below k");
+// Dynamic LDS of k_slot_edge_push for grid G, child set size s_in and the
+// epilogue pj (null: none); sets pj's rows_static and spl_static.
+static size_t push_lds(int k, int s_in, const SlotGrid& G, bool wide, PushJoin* pj) {
     const int W = binom_pq(k - 2, s_in - 1);
     const size_t cap = size_t(G.upb) * G.m;
     size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 4 * size_t(k) * k * W + 4 * ((cap + 3) / 4);
-    PushJoin none{};
-    PushJoin pjl;
     if (pj) {
-        if (!pj->chain && k < 4) throw std::runtime_error("launch_slot_edge_push: a fused leaf join needs k >= 4");
-        pjl = *pj;
         // the epilogue's rows and split rows (32-bit words), in the chunk
         // arrays (kPushChunk 64-bit words) when they fit
         const size_t rows = pj->chain == 2 ? 2 * cap * size_t(pj->r1)
@@ -1703,11 +1696,30 @@ void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph 
                                            : cap * size_t((k - 1) * (k - 2) / 2);
         const size_t spl = pj->chain ? size_t(pj->nsplit1) * pj->r1 + (pj->chain == 2 ? size_t(pj->nsplit) * pj->out.R : 0)
                                      : size_t(pj->nsplit) * pj->out.R;
-        pjl.rows_static = rows <= 2 * size_t(kPushChunk);
-        pjl.spl_static = (pjl.rows_static ? rows : 0) + spl <= 2 * size_t(kPushChunk);
-        lds += 4 * cap * size_t(k) + 4 + 4 * ((pjl.rows_static ? 0 : rows) + (pjl.spl_static ? 0 : spl));
+        pj->rows_static = rows <= 2 * size_t(kPushChunk);
+        pj->spl_static = (pj->rows_static ? rows : 0) + spl <= 2 * size_t(kPushChunk);
+        lds += 4 * cap * size_t(k) + 4 + 4 * ((pj->rows_static ? 0 : rows) + (pj->spl_static ? 0 : spl));
     }
-    if (lds > 64 * 1024) throw std::runtime_error("launch_slot_edge_push: LDS beyond 64 KiB");
+    return lds;
+}
+
+size_t slot_push_lds(int k, int s_in, const SlotGrid& G, bool wide, const PushJoin* pj) {
+    PushJoin p = pj ? *pj : PushJoin();
+    return push_lds(k, s_in, G, wide, pj ? &p : nullptr);
+}
+
+void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
+                           int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
+                           const PushJoin* pj, hipStream_t s) {
+    if (!G.blocks) return;
+    if (k > kSlotPushK || g.n >= (1 << 24) || G.upb == 0 || s_in < 1 || s_in > k - 1)
+        throw std::runtime_error("launch_slot_edge_push: needs k <= 10, n < 2^24, R <= 256 and a child set below k");
+    if (pj && !pj->chain && k < 4) throw std::runtime_error("launch_slot_edge_push: a fused leaf join needs k >= 4");
+    const int W = binom_pq(k - 2, s_in - 1);
+    PushJoin none{};
+    PushJoin pjl = pj ? *pj : none;
+    const size_t lds = push_lds(k, s_in, G, wide, pj ? &pjl : nullptr);
+    if (lds > kPushLdsMax) throw std::runtime_error("launch_slot_edge_push: dynamic LDS beyond kPushLdsMax");
 #define PUSH_LAUNCH(WIDE, EPI)                                                                                     \
     k_slot_edge_push<WIDE, EPI><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, \
                                                                               out, part, pj ? pjl : none)

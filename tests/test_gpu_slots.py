@@ -137,7 +137,7 @@ def test_degree_past_16_bits_matches_oracle(ctx, pat):
 
 
 # joins at a vertex computed in the push kernel of its deeper child's edge
-# step (k <= 8, no count can wrap): with the fused join of two leaf children
+# step (k <= 10, no count can wrap, the kernel's LDS fits): with the fused join of two leaf children
 # ("LJ+"), or with one leaf and then another ("chain"); vertex orders decide
 # which children the plan joins first.  On the hub graph the chain of a
 # 4-vertex child runs with 64-bit accumulators.
@@ -155,7 +155,7 @@ def test_push_join_matches_oracle(ctx, gname):
     G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
     rng = np.random.default_rng(len(gname) + 7)
     for pat in PUSH_JOIN:
-        for k in sorted({pat.n, min(pat.n + 2, 8)}):
+        for k in sorted({pat.n, min(pat.n + 2, 10)}):
             B = 9 if gname != "hub" else 3
             colors = rng.integers(0, k, size=(B, g.n)).astype(np.uint8)
             say("push join", gname, pat.name, "k", k)
