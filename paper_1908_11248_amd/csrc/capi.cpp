@@ -163,9 +163,11 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
         std::vector<int32_t> src(m2);
         for (int32_t v = 0; v < n; v++)
             for (int64_t e = rp[v]; e < rp[v + 1]; e++) src[e] = v;
-        // edge set for adjacency tests: 4m cells or more, a power of two
+        // edge set for adjacency tests: 8m cells or more, a power of two (a
+        // load of at most 1/8 keeps the linear-probing chains, which every
+        // lane of a wave waits for, short)
         uint64_t cells = 16;
-        while (cells < uint64_t(std::max<int64_t>(m2, 1)) * 2) cells <<= 1;
+        while (cells < uint64_t(std::max<int64_t>(m2, 1)) * 4) cells <<= 1;
         std::vector<uint64_t> eh(cells, kEdgeEmpty);
         for (int32_t v = 0; v < n; v++)
             for (int64_t e = rp[v]; e < rp[v + 1]; e++) {

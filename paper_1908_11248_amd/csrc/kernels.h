@@ -39,7 +39,7 @@ struct DevGraph {
     const int32_t* heavy; // vertices of degree > kHeavyDegree, ascending
     int32_t nheavy;
     const uint64_t* eh;   // edge set: open addressing, linear probing, kEdgeEmpty in free cells
-    uint64_t ehmask;      // cells - 1 (a power of two at least four times m)
+    uint64_t ehmask;      // cells - 1 (a power of two at least eight times m)
 };
 
 // edge-set key of {a, b} (a != b): smaller id in the high half
