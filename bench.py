@@ -124,8 +124,8 @@ def main():
                     help="first run one plain device copy of MIB mebibytes (reference kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X; "
-              "--gpus %d is not supported (multi-GPU sharding is described in DESIGN.md)" % args.gpus,
+        print("bench.py measures one GPU (one MI355X); --gpus %d is not supported: colourings and "
+              "queries are independent, so more GPUs would each take their own share" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
