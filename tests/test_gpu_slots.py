@@ -173,6 +173,42 @@ def test_push_join_matches_oracle(ctx, gname):
             C.close()
 
 
+def test_random_tree_sweep_matches_oracle(ctx):
+    # 40 seeded random trees of 3-9 vertices at k from n_F to 10 on a graph
+    # mixing a dense core with sparse periphery: many plan shapes, so the
+    # push form, its joins (leaf joins, chains of one or two leaves) and
+    # their fallbacks all meet the oracle's counts and node sizes, and the
+    # sorted-list path agrees
+    rng = np.random.default_rng(2024)
+    n = 700
+    a, b = rng.integers(0, n, 2600), rng.integers(0, n, 2600)
+    core = rng.integers(0, 60, (2, 900))
+    keep = a != b
+    ck = core[0] != core[1]
+    g = W.csr_from_edges(n, np.concatenate([a[keep], core[0][ck]]), np.concatenate([b[keep], core[1][ck]]))
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    for t in range(40):
+        nf = int(rng.integers(3, 10))
+        pat = W.random_tree(nf, 1000 + t)
+        k = int(rng.integers(nf, 11))
+        B = 3
+        colors = rng.integers(0, k, size=(B, g.n)).astype(np.uint8)
+        say("sweep", t, pat.name, pat.edges, "k", k)
+        D = cc.build_decomposition(pat.n, pat.edges)
+        td = D.export()
+        C = cc.color_explicit(ctx, G, k, colors)
+        cd, od, sd = run(ctx, G, C, D, 0)
+        cs, os_, ss = run(ctx, G, C, D, SPARSE)
+        ref_sizes = np.zeros(len(sd), dtype=np.int64)
+        for bb in range(B):
+            ref = O.dp_count(g, pat, k, colors[bb], td=td, sizes=True)
+            assert int(cd[bb]) == ref["count"] and bool(od[bb]) == ref["overflow"], (t, pat.edges, k, bb)
+            ref_sizes += ref["sizes"]
+        assert np.array_equal(sd, ref_sizes), (t, pat.edges, k)
+        assert np.array_equal(cd, cs) and np.array_equal(od, os_) and np.array_equal(ss, ref_sizes), (t, k)
+        C.close()
+
+
 def test_overflow_on_both_paths(ctx):
     # a hub of degree 6000: the star S7 overflows 64 bits
     n = 6001
