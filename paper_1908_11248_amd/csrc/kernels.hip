@@ -311,65 +311,116 @@ k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
     }
 }
 
-// Runs of at most kForgetSmall entries, four per wave (16 lanes each, one
-// entry per lane): equal colour sets are found by comparing all pairs with
-// lane shuffles, and a set's place in the output is the number of distinct
-// smaller sets, so the output stays sorted without an accumulator.
-template <class KI, class KO, bool EMIT, int LN>
+// Runs of at most kForgetSmall entries, one per 16-lane row of a wave (one
+// entry per lane): equal colour sets are found by comparing all pairs, each
+// lane's values reaching the rest of its row by a DPP row broadcast, and a
+// set's place in the output is the number of distinct smaller sets, so the
+// output stays sorted without an accumulator.
+static_assert(kForgetSmall == 16, "one run per 16-lane DPP row");
+
+// lane I of every 16-lane row, to all lanes of that row (DPP row_newbcast);
+// every lane of the wave must be active
+template <int I>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t x) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x150 + I, 0xF, 0xF, false));
+}
+
+// lane I's entry against this lane's: equal sets add, and a lane is the first
+// of its set when no lower lane holds it.  NW: counts are 64-bit (else every
+// count of the wave is below 2^28, so sixteen of them add in 32 bits)
+template <int I, bool EMIT, bool NW>
+__device__ __forceinline__ void small_pairs(uint32_t mm, int sl, bool valid, uint32_t C, uint64_t c, bool& first,
+                                            uint64_t& sum, bool& over) {
+    if (uint32_t(I) >= mm) return;
+    const uint32_t Ci = row_bcast<I>(C);
+    const bool eq = valid && Ci == C;
+    first = first && !(eq && I < sl);
+    if (EMIT && NW) {
+        const uint64_t ci = uint64_t(row_bcast<I>(uint32_t(c))) | (uint64_t(row_bcast<I>(uint32_t(c >> 32))) << 32);
+        const uint64_t add = eq ? ci : 0;
+        sum += add;
+        over |= sum < add;
+    } else if (EMIT) {
+        const uint32_t ci = row_bcast<I>(uint32_t(c));
+        sum = uint32_t(sum) + (eq ? ci : 0u);
+    }
+    if constexpr (I + 1 < kForgetSmall) small_pairs<I + 1, EMIT, NW>(mm, sl, valid, C, c, first, sum, over);
+}
+
+// number of first lanes (distinct sets) below C; F is C on first lanes and
+// all ones elsewhere
+template <int I>
+__device__ __forceinline__ void small_rank(uint32_t mm, uint32_t F, uint32_t C, uint32_t& rank) {
+    if (uint32_t(I) >= mm) return;
+    rank += row_bcast<I>(F) < C ? 1u : 0u;
+    if constexpr (I + 1 < kForgetSmall) small_rank<I + 1>(mm, F, C, rank);
+}
+
+// Each 16-lane row takes kForgetSmallU runs per pass and issues all their
+// loads before it compares, which keeps more bytes in flight per wave.
+constexpr int kForgetSmallU = 4;
+template <class KI, class KO, bool EMIT>
 __global__ void __launch_bounds__(kBlock)
 k_forget_small(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L,
                const uint64_t* __restrict__ gstart, uint64_t G, uint32_t* gcount, const uint64_t* __restrict__ goff,
                KO* okeys, uint64_t* ocnt, uint32_t* ovf) {
-    // runs of m <= LN entries, 64 / LN per wave
-    const uint64_t m_lo = 1;
+    constexpr int LN = kForgetSmall, U = kForgetSmallU;
     const int sh = L.kb + L.vb;  // drop the colour set and the last column
     const int sl = threadIdx.x % LN;
-    const uint64_t units_per_block = kBlock / LN;
-    for (uint64_t grp0 = uint64_t(blockIdx.x) * units_per_block; grp0 < G; grp0 += uint64_t(gridDim.x) * units_per_block) {
-        const uint64_t grp = grp0 + threadIdx.x / LN;
-        uint64_t e0 = 0, m = 0;
-        if (grp < G) {
-            e0 = gstart[grp];
-            m = gstart[grp + 1] - e0;
-            if (m > uint64_t(LN) || m < m_lo) m = 0;  // another kernel's run
-        }
-        const bool valid = uint64_t(sl) < m;
-        KI k = valid ? keys[e0 + sl] : KI(0);
-        const uint32_t C = valid ? kset(k, L) : ~0u;
-        const uint64_t c = (valid && EMIT) ? cnt[e0 + sl] : 0;
-        // the wave runs the longest of its runs
-        uint32_t mm = uint32_t(m);
-        for (int d = 32; d >= 1; d >>= 1) mm = max(mm, (uint32_t)__shfl_xor(mm, d, 64));
-        bool first = valid, over = false;
-        uint64_t sum = 0;
-        for (uint32_t i = 0; i < mm; i++) {
-            const uint32_t Ci = __shfl(C, int(i), LN);
-            const uint64_t ci = EMIT ? __shfl(c, int(i), LN) : 0;
-            if (valid && Ci == C) {
-                if (i < uint32_t(sl)) first = false;
-                sum += ci;
-                over |= sum < ci;
+    const uint64_t rows = kBlock / LN;  // runs per block and pass
+    // the loop bound is uniform over the block, so every lane reaches the
+    // row broadcasts
+    for (uint64_t base = uint64_t(blockIdx.x) * rows * U; base < G; base += uint64_t(gridDim.x) * rows * U) {
+        uint64_t e0[U], m[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t grp = base + u * rows + threadIdx.x / LN;
+            e0[u] = 0;
+            m[u] = 0;
+            if (grp < G) {
+                e0[u] = gstart[grp];
+                m[u] = gstart[grp + 1] - e0[u];
+                if (m[u] > uint64_t(LN)) m[u] = 0;  // k_forget's run
             }
         }
-        uint32_t rank = 0;
-        for (uint32_t i = 0; i < mm; i++) {
-            const uint32_t Ci = __shfl(C, int(i), LN);
-            const int fi = __shfl(int(first), int(i), LN);
-            rank += (fi && Ci < C) ? 1u : 0u;
+        KI k[U];
+        uint64_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const bool valid = uint64_t(sl) < m[u];
+            k[u] = valid ? keys[e0[u] + sl] : KI(0);
+            c[u] = (valid && EMIT) ? cnt[e0[u] + sl] : 0;
         }
-        if (EMIT) {
-            if (first) {
-                const uint64_t o = goff[grp] + rank;
-                okeys[o] = (KO(shr(k, sh)) << L.kb) | KO(C);
-                ocnt[o] = sum;
-            }
-            if (over) atomicOr(&ovf[kbid(k, L)], 1u);
-        } else {
-            const uint64_t fb = __ballot(first);
-            if (sl == 0 && grp < G && m > 0) {
-                const int base = int(threadIdx.x % 64) / LN * LN;
-                const uint64_t lanes = LN == 64 ? ~0ull : ((1ull << LN) - 1ull);
-                gcount[grp] = uint32_t(__popcll((fb >> base) & lanes));
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t grp = base + u * rows + threadIdx.x / LN;
+            const bool valid = uint64_t(sl) < m[u];
+            const uint32_t C = valid ? kset(k[u], L) : ~0u;
+            // the wave runs the longest of its four runs (m is equal on a row)
+            const uint32_t m32 = uint32_t(m[u]);
+            const uint32_t mm = max(max(__builtin_amdgcn_readlane(m32, 0), __builtin_amdgcn_readlane(m32, 16)),
+                                    max(__builtin_amdgcn_readlane(m32, 32), __builtin_amdgcn_readlane(m32, 48)));
+            bool first = valid, over = false;
+            uint64_t sum = 0;
+            if (!EMIT || __ballot(c[u] >> 28) == 0)
+                small_pairs<0, EMIT, false>(mm, sl, valid, C, c[u], first, sum, over);
+            else
+                small_pairs<0, EMIT, true>(mm, sl, valid, C, c[u], first, sum, over);
+            if (EMIT) {
+                uint32_t rank = 0;
+                small_rank<0>(mm, first ? C : ~0u, C, rank);
+                if (first) {
+                    const uint64_t o = goff[grp] + rank;
+                    okeys[o] = (KO(shr(k[u], sh)) << L.kb) | KO(C);
+                    ocnt[o] = sum;
+                }
+                if (over) atomicOr(&ovf[kbid(k[u], L)], 1u);
+            } else {
+                const uint64_t fb = __ballot(first);
+                if (sl == 0 && grp < G && m[u] > 0) {
+                    const int base_l = int(threadIdx.x % 64) / LN * LN;
+                    gcount[grp] = uint32_t(__popcll((fb >> base_l) & ((1ull << LN) - 1ull)));
+                }
             }
         }
     }
@@ -386,12 +437,13 @@ static void forget_dispatch(const DevTable& in, const uint64_t* gstart, uint64_t
     int ki = in.lay.kw(), ko = LO.kw();
     void* okk = out ? out->keys : nullptr;
     uint64_t* oc = out ? out->cnt : nullptr;
-    // runs of 1-16 entries four per wave, longer ones k_forget
+    // runs of 1-16 entries one per 16-lane row, longer ones k_forget
     {
-        const uint64_t sblocks = (G + kBlock / kForgetSmall - 1) / (kBlock / kForgetSmall);
+        const uint64_t per = uint64_t(kBlock / kForgetSmall) * kForgetSmallU;
+        const uint64_t sblocks = (G + per - 1) / per;
         const unsigned sgrid = unsigned(sblocks < (1u << 20) ? sblocks : (1u << 20));
 #define FORGET_SMALL(KIT, KOT)                                                                                       \
-    k_forget_small<KIT, KOT, EMIT, kForgetSmall><<<sgrid, kBlock, 0, s>>>((const KIT*)in.keys, in.cnt, in.lay, gstart, \
+    k_forget_small<KIT, KOT, EMIT><<<sgrid, kBlock, 0, s>>>((const KIT*)in.keys, in.cnt, in.lay, gstart, \
                                                                         G, gcount, goff, (KOT*)okk, oc, ovf)
         if (ki == 1) {
             FORGET_SMALL(uint64_t, uint64_t);

@@ -107,6 +107,26 @@ def test_overflow_flag_and_wraparound(ctx):
     assert int(counts[0]) == ref["count"] and bool(ovf[0]) and ref["overflow"]
 
 
+def test_short_forget_runs_with_large_counts(ctx):
+    # A hub joined to D vertices that are paired by edges: every pair closes a
+    # triangle with the hub.  Pattern: triangle (0, 1, 2) with four leaves on
+    # vertex 2.  Forgetting vertex 2 with 0 and 1 on a pair leaves runs of a
+    # few colour sets whose counts, (D/7)^4 * 4! or so embeddings of the
+    # leaves at the hub, exceed 2^28: the short-run forget must add them in
+    # 64 bits.
+    pat = W.Pattern(7, [(0, 1), (1, 2), (0, 2), (2, 3), (2, 4), (2, 5), (2, 6)], "triangle+4")
+    for D in (600, 6000):
+        src = np.concatenate([np.zeros(D, np.int64), np.arange(1, D, 2)])
+        dst = np.concatenate([np.arange(1, D + 1), np.arange(2, D + 1, 2)])
+        g = W.csr_from_edges(D + 1, src, dst)
+        colors = np.random.default_rng(D).integers(0, 7, size=(3, g.n)).astype(np.uint8)
+        counts, ovf, Dd = run_gpu(ctx, g, pat, 7, colors)
+        for b in range(3):
+            ref = O.dp_count(g, pat, 7, colors[b], td=Dd.export())
+            assert ref["count"] > 1 << 32
+            assert int(counts[b]) == ref["count"] and bool(ovf[b]) == ref["overflow"], (D, b)
+
+
 def test_edge_cases(ctx):
     # graph without edges, pattern with edges: zero
     g = W.csr_from_edges(50, np.zeros(0, np.int64), np.zeros(0, np.int64))
