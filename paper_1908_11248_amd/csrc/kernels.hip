@@ -269,25 +269,82 @@ void launch_pull_index(const DevTable& in, int32_t n, uint64_t* rstart, uint64_t
 // Runs longer than kForgetSmall go through a dense LDS accumulator, one run
 // per 64-lane workgroup; shorter ones through k_forget_small.
 constexpr int kForgetSmall = 16;
+
+// lane 0's value of x, word by word
+template <class T>
+__device__ __forceinline__ T from_lane0(T x) {
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); i++) w[i] = __builtin_amdgcn_readlane(w[i], 0);
+    __builtin_memcpy(&x, w, sizeof(T));
+    return x;
+}
+
 template <class KI, class KO, bool EMIT>
 __global__ void __launch_bounds__(64)
 k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ gstart,
          uint64_t G, uint32_t* gcount, const uint64_t* __restrict__ goff, KO* okeys, uint64_t* ocnt, uint32_t* ovf) {
     Acc acc = acc_bind(L.kb, EMIT);
     const int sh = L.kb + L.vb;  // drop the colour set and the last column
-    // 64 groups per visit: each lane reads one group's length, the block then
-    // takes the longer ones in turn (the others are k_forget_small's)
+    const int lane = threadIdx.x;
+    // 64 groups per visit: each lane reads one group's bounds, the block then
+    // takes the longer ones in turn (the others are k_forget_small's), with
+    // the first 64 entries of the next one loading while it works on one
     for (uint64_t g0 = uint64_t(blockIdx.x) * 64; g0 < G; g0 += uint64_t(gridDim.x) * 64) {
-        const uint64_t gl = g0 + threadIdx.x;
-        uint64_t todo = __ballot(gl < G && gstart[gl + 1] - gstart[gl] > uint64_t(kForgetSmall));
+        const uint64_t gl = g0 + lane;
+        uint64_t s0 = 0, s1 = 0;
+        if (gl < G) {
+            s0 = gstart[gl];
+            s1 = gstart[gl + 1];
+        }
+        uint64_t todo = __ballot(s1 - s0 > uint64_t(kForgetSmall));
+        // bounds of group g0 + j, from lane j
+        auto bounds = [&](int j, uint64_t& e0, uint64_t& e1) {
+            e0 = uint64_t(__builtin_amdgcn_readlane(uint32_t(s0), j)) |
+                 (uint64_t(__builtin_amdgcn_readlane(uint32_t(s0 >> 32), j)) << 32);
+            e1 = uint64_t(__builtin_amdgcn_readlane(uint32_t(s1), j)) |
+                 (uint64_t(__builtin_amdgcn_readlane(uint32_t(s1 >> 32), j)) << 32);
+        };
+        int nj = 0;
+        uint64_t n0 = 0, n1 = 0;
+        KI nk = KI(0);
+        uint64_t nc = 0;
+        if (todo) {
+            nj = __ffsll((unsigned long long)todo) - 1;
+            bounds(nj, n0, n1);
+            if (n0 + lane < n1) {
+                nk = keys[n0 + lane];
+                if (EMIT) nc = cnt[n0 + lane];
+            }
+        }
         while (todo) {
-            const uint64_t grp = g0 + uint64_t(__ffsll((unsigned long long)todo) - 1);
+            const uint64_t grp = g0 + uint64_t(nj);
+            const uint64_t e0 = n0, e1 = n1;
+            const KI k0 = nk;
+            const uint64_t c0 = nc;
             todo &= todo - 1;
-            uint64_t e0 = gstart[grp], e1 = gstart[grp + 1];
+            if (todo) {
+                nj = __ffsll((unsigned long long)todo) - 1;
+                bounds(nj, n0, n1);
+                if (n0 + lane < n1) {
+                    nk = keys[n0 + lane];
+                    if (EMIT) nc = cnt[n0 + lane];
+                }
+            }
             acc_clear(acc, EMIT);
             __syncthreads();
             bool over = false;
-            for (uint64_t e = e0 + threadIdx.x; e < e1; e += 64) {
+            // every group here has more than 16 entries, so lane 0's is one
+            if (e0 + lane < e1) {
+                const uint32_t C = kset(k0, L);
+                atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
+                if (EMIT) {
+                    uint64_t old = atomicAdd((unsigned long long*)&acc.val[C], (unsigned long long)c0);
+                    over |= (old + c0 < old);
+                }
+            }
+            for (uint64_t e = e0 + 64 + lane; e < e1; e += 64) {
                 uint32_t C = kset(keys[e], L);
                 atomicOr(&acc.bits[C >> 5], 1u << (C & 31));
                 if (EMIT) {
@@ -298,13 +355,13 @@ k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
             }
             __syncthreads();
             if (EMIT) {
-                KI k0 = keys[e0];
-                if (__ballot(over) && threadIdx.x == 0) atomicOr(&ovf[kbid(k0, L)], 1u);
-                KO prefix = KO(shr(k0, sh)) << L.kb;
+                const KI kf = from_lane0(k0);
+                if (__ballot(over) && lane == 0) atomicOr(&ovf[kbid(kf, L)], 1u);
+                KO prefix = KO(shr(kf, sh)) << L.kb;
                 acc_emit<KO>(acc, prefix, goff[grp], okeys, ocnt);
             } else {
                 uint32_t c = acc_count(acc);
-                if (threadIdx.x == 0) gcount[grp] = c;
+                if (lane == 0) gcount[grp] = c;
             }
             __syncthreads();
         }
