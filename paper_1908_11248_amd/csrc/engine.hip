@@ -291,14 +291,25 @@ struct Exec {
 
     // runs of equal key >> shift; returns G and starts[G + 1]
     uint64_t groups(const DevTable& t, int shift, uint64_t** starts) {
-        uint32_t* flags = alloc<uint32_t>(t.n);
-        timed("heads", double(t.n) * (t.lay.key_bytes() + 4), [&] { launch_heads(t.keys, t.lay.kw(), t.n, shift, flags, s); });
-        uint64_t* offs;
-        uint64_t G = scan(flags, t.n, &offs);
+        if (!t.n) {
+            *starts = alloc<uint64_t>(1);
+            launch_fill_u64(*starts, 0, 1, s);
+            return 0;
+        }
+        const uint64_t nt = head_tiles(t.n);
+        uint64_t* tsum = alloc<uint64_t>(nt);
+        timed("heads", double(t.n) * t.lay.key_bytes() + 8.0 * nt,
+              [&] { launch_head_count(t.keys, t.lay.kw(), t.n, shift, tsum, s); });
+        uint64_t* toff = alloc<uint64_t>(nt + 1);
+        uint64_t* tmp = (uint64_t*)raw(scan_tmp_bytes(nt));
+        timed("scan", 16.0 * nt + 8.0, [&] { launch_scan_u64(tsum, toff, nt, tmp, s); });
+        release(tmp);
+        const uint64_t G = read(toff + nt);
         *starts = alloc<uint64_t>(G + 1);
-        timed("group_starts", 12.0 * t.n + 8.0 * G, [&] { launch_group_starts(flags, offs, t.n, *starts, s); });
-        release(flags);
-        release(offs);
+        timed("group_starts", double(t.n) * t.lay.key_bytes() + 8.0 * (nt + G + 1),
+              [&] { launch_head_starts(t.keys, t.lay.kw(), t.n, shift, toff, *starts, s); });
+        release(tsum);
+        release(toff);
         return G;
     }
 };

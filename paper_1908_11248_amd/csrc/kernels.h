@@ -76,11 +76,13 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 
 void launch_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed, hipStream_t s);
 
-// group heads over key >> shift: flags[i] = 1 at the first key of every run
-void launch_heads(const void* keys, int kw, uint64_t n, int shift, uint32_t* flags, hipStream_t s);
-// starts[offs[i]] = i where flags[i]; starts[G] = n
-void launch_group_starts(const uint32_t* flags, const uint64_t* offs, uint64_t n, uint64_t* starts,
-                         hipStream_t s);
+// runs of equal key >> shift in a sorted table: head_tiles(n) tiles; tsum[t]
+// = number of runs starting in tile t; with toff = exclusive scan of tsum
+// (toff[tiles] = G), starts[j] = first index of run j and starts[G] = n
+uint64_t head_tiles(uint64_t n);
+void launch_head_count(const void* keys, int kw, uint64_t n, int shift, uint64_t* tsum, hipStream_t s);
+void launch_head_starts(const void* keys, int kw, uint64_t n, int shift, const uint64_t* toff, uint64_t* starts,
+                        hipStream_t s);
 
 // leaf
 void launch_leaf_count(DevGraph g, int B, int degF, uint32_t* flags, hipStream_t s);

@@ -125,34 +125,81 @@ void launch_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_
 }
 
 // ---------------------------------------------------------------------------
-// run heads and run starts
+// run heads and run starts: runs of equal key >> shift in a sorted table, in
+// two passes over the keys (per-tile head counts, then, after a scan of those,
+// every run's first index written at its rank)
+
+constexpr int kHeadItems = 16;
+constexpr uint64_t kHeadTile = uint64_t(kBlock) * kHeadItems;
+
+uint64_t head_tiles(uint64_t n) { return (n + kHeadTile - 1) / kHeadTile; }
+
+// bit r: item base + r * kBlock + threadIdx.x starts a run
+template <class K>
+__device__ __forceinline__ uint32_t head_bits(const K* __restrict__ keys, uint64_t n, int shift, uint64_t base) {
+    uint32_t hb = 0;
+#pragma unroll
+    for (int r = 0; r < kHeadItems; r++) {
+        const uint64_t i = base + uint64_t(r) * kBlock + threadIdx.x;
+        if (i < n && (i == 0 || shr(keys[i], shift) != shr(keys[i - 1], shift))) hb |= 1u << r;
+    }
+    return hb;
+}
 
 template <class K>
-__global__ void k_heads(const K* __restrict__ keys, uint64_t n, int shift, uint32_t* flags) {
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
-        uint32_t f = 1;
-        if (i > 0) f = shr(keys[i], shift) != shr(keys[i - 1], shift);
-        flags[i] = f;
+__global__ void __launch_bounds__(kBlock) k_head_count(const K* __restrict__ keys, uint64_t n, int shift,
+                                                       uint64_t* tsum) {
+    const uint32_t hb = head_bits(keys, n, shift, uint64_t(blockIdx.x) * kHeadTile);
+    uint64_t tot;
+    block_excl_scan(uint64_t(__popc(hb)), &tot);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+template <class K>
+__global__ void __launch_bounds__(kBlock) k_head_starts(const K* __restrict__ keys, uint64_t n, int shift,
+                                                        const uint64_t* __restrict__ toff, uint64_t* starts) {
+    __shared__ uint32_t s_w[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t base = uint64_t(blockIdx.x) * kHeadTile;
+    const uint32_t hb = head_bits(keys, n, shift, base);
+    uint64_t at = toff[blockIdx.x];
+    // round r: heads in (wave, lane) order, which is index order
+    for (int r = 0; r < kHeadItems; r++) {
+        const bool h = (hb >> r) & 1u;
+        const uint64_t m = __ballot(h);
+        if (lane == 0) s_w[w] = uint32_t(__popcll(m));
+        __syncthreads();
+        uint64_t before = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / 64; q++) {
+            const uint32_t c = s_w[q];
+            if (q < w) before += c;
+            tot += c;
+        }
+        if (h) starts[at + before + __popcll(m & lanemask_lt())] = base + uint64_t(r) * kBlock + threadIdx.x;
+        at += tot;
+        __syncthreads();
     }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) starts[toff[gridDim.x]] = n;
 }
 
-void launch_heads(const void* keys, int kw, uint64_t n, int shift, uint32_t* flags, hipStream_t s) {
-    if (!n) return;
+void launch_head_count(const void* keys, int kw, uint64_t n, int shift, uint64_t* tsum, hipStream_t s) {
+    const uint64_t nb = head_tiles(n);
+    if (!nb) return;
     if (kw == 1)
-        k_heads<uint64_t><<<grid_for(n), kBlock, 0, s>>>((const uint64_t*)keys, n, shift, flags);
+        k_head_count<uint64_t><<<unsigned(nb), kBlock, 0, s>>>((const uint64_t*)keys, n, shift, tsum);
     else
-        k_heads<u128><<<grid_for(n), kBlock, 0, s>>>((const u128*)keys, n, shift, flags);
+        k_head_count<u128><<<unsigned(nb), kBlock, 0, s>>>((const u128*)keys, n, shift, tsum);
 }
 
-__global__ void k_group_starts(const uint32_t* flags, const uint64_t* offs, uint64_t n, uint64_t* starts) {
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
-        if (flags[i]) starts[offs[i]] = i;
-    if (blockIdx.x == 0 && threadIdx.x == 0) starts[offs[n]] = n;
-}
-
-void launch_group_starts(const uint32_t* flags, const uint64_t* offs, uint64_t n, uint64_t* starts,
-                         hipStream_t s) {
-    k_group_starts<<<grid_for(n), kBlock, 0, s>>>(flags, offs, n, starts);
+void launch_head_starts(const void* keys, int kw, uint64_t n, int shift, const uint64_t* toff, uint64_t* starts,
+                        hipStream_t s) {
+    const uint64_t nb = head_tiles(n);
+    if (!nb) return;
+    if (kw == 1)
+        k_head_starts<uint64_t><<<unsigned(nb), kBlock, 0, s>>>((const uint64_t*)keys, n, shift, toff, starts);
+    else
+        k_head_starts<u128><<<unsigned(nb), kBlock, 0, s>>>((const u128*)keys, n, shift, toff, starts);
 }
 
 // ---------------------------------------------------------------------------
