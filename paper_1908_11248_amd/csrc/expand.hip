@@ -24,23 +24,64 @@ constexpr int kExpTile = kBlock * kExpItems;
 
 // ---- segment lengths -------------------------------------------------------
 
+// Tiles of kSegTile consecutive segments, kSegItems per thread: the block
+// finds the tile's group range once, each thread searches only that range for
+// its first segment's group and walks on from there, so consecutive segments
+// of one group share its first key and anchor row.
+constexpr int kSegItems = 4;
+constexpr uint64_t kSegTile = uint64_t(kBlock) * kSegItems;
+
 template <class K>
-__global__ void k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gstart,
-                              const uint64_t* __restrict__ woff, uint64_t G, uint64_t W, DevGraph g,
-                              const uint8_t* __restrict__ colors, IntroArgs a, uint32_t* slen) {
-    for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < W; s += uint64_t(gridDim.x) * blockDim.x) {
-        uint64_t grp = upper_bound_u64(woff, 0, G + 1, s) - 1;
-        uint64_t t = s - woff[grp];
-        K k0 = keys[gstart[grp]];
-        const int src = a.anchor >= 0 && a.sel ? int(a.sel[grp]) : a.anchor;
-        uint32_t v = src >= 0 ? uint32_t(g.col[g.rp[kcol(k0, L, src)] + int64_t(t)]) : uint32_t(t);
-        bool ok = gdeg(g, v) >= a.degF;
-        // the bag neighbours before pos other than the one the candidates came from
-        if (ok && src != a.anchor) ok = has_edge(g, kcol(k0, L, a.anchor), v);
-        for (int c = 0; c < a.nchk && ok; c++)
-            if (a.chk[c] < a.pos && a.chk[c] != src) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
-        slen[s] = ok ? uint32_t(gstart[grp + 1] - gstart[grp]) : 0u;
-        if (a.segv) a.segv[s] = v | uint32_t(colors[uint64_t(kbid(k0, L)) * uint32_t(g.n) + v]) << 27;
+__global__ void __launch_bounds__(kBlock)
+k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gstart,
+              const uint64_t* __restrict__ woff, uint64_t G, uint64_t W, DevGraph g,
+              const uint8_t* __restrict__ colors, IntroArgs a, uint32_t* slen) {
+    __shared__ uint64_t gb[2];
+    const uint64_t tiles = (W + kSegTile - 1) / kSegTile;
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint64_t s_lo = tile * kSegTile;
+        const uint64_t s_hi = s_lo + kSegTile < W ? s_lo + kSegTile : W;
+        if (threadIdx.x == 0) {
+            gb[0] = upper_bound_u64(woff, 0, G + 1, s_lo) - 1;              // group of the first segment
+            gb[1] = upper_bound_u64(woff, gb[0], G + 1, s_hi - 1);          // one past the last one's
+        }
+        __syncthreads();
+        const uint64_t g_lo = gb[0], g_end = gb[1];
+        __syncthreads();
+        const uint64_t s0 = s_lo + uint64_t(threadIdx.x) * kSegItems;
+        if (s0 >= s_hi) continue;
+        uint64_t grp = upper_bound_u64(woff, g_lo, g_end + 1, s0) - 1;
+        // the group's state: first key, candidate source column and its row
+        K k0;
+        int src;
+        int64_t row;
+        uint32_t glen;
+        auto load_group = [&]() {
+            const uint64_t e0 = gstart[grp];
+            k0 = keys[e0];
+            src = a.anchor >= 0 && a.sel ? int(a.sel[grp]) : a.anchor;
+            row = src >= 0 ? g.rp[kcol(k0, L, src)] : 0;
+            glen = uint32_t(gstart[grp + 1] - e0);
+        };
+        load_group();
+        for (int j = 0; j < kSegItems; j++) {
+            const uint64_t s = s0 + uint64_t(j);
+            if (s >= s_hi) break;
+            if (woff[grp + 1] <= s) {
+                do grp++;
+                while (woff[grp + 1] <= s);
+                load_group();
+            }
+            const uint64_t t = s - woff[grp];
+            const uint32_t v = src >= 0 ? uint32_t(g.col[row + int64_t(t)]) : uint32_t(t);
+            bool ok = gdeg(g, v) >= a.degF;
+            // the bag neighbours before pos other than the one the candidates came from
+            if (ok && src != a.anchor) ok = has_edge(g, kcol(k0, L, a.anchor), v);
+            for (int c = 0; c < a.nchk && ok; c++)
+                if (a.chk[c] < a.pos && a.chk[c] != src) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
+            slen[s] = ok ? glen : 0u;
+            if (a.segv) a.segv[s] = v | uint32_t(colors[uint64_t(kbid(k0, L)) * uint32_t(g.n) + v]) << 27;
+        }
     }
 }
 
@@ -260,12 +301,14 @@ void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64
                         DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* slen, hipStream_t s) {
     if (!W) return;
     if (a.segv && g.n > (1 << 27)) throw std::runtime_error("launch_push_seglen: packed segment vertices need n <= 2^27");
+    const uint64_t tiles = (W + kSegTile - 1) / kSegTile;
+    const unsigned grid = unsigned(tiles < (1u << 20) ? tiles : (1u << 20));
     if (in.lay.kw() == 1)
-        k_push_seglen<uint64_t><<<grid_for(W), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, gstart, woff, G, W, g,
-                                                               colors, a, slen);
+        k_push_seglen<uint64_t><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, gstart, woff, G, W, g, colors,
+                                                        a, slen);
     else
-        k_push_seglen<u128><<<grid_for(W), kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, woff, G, W, g, colors,
-                                                           a, slen);
+        k_push_seglen<u128><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.lay, gstart, woff, G, W, g, colors, a,
+                                                    slen);
 }
 
 void launch_pull_seglen(const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g, int degF, uint32_t* slen,
