@@ -137,6 +137,29 @@ __device__ __forceinline__ SegState seg_state(uint64_t s, uint64_t* grp, const K
     return st;
 }
 
+// per tile: the first segment, one past the last, and (push form) the same
+// for prefix groups; one tile per thread, so the searches run side by side
+__global__ void k_expand_bounds(const uint64_t* __restrict__ soff, uint64_t S, const uint64_t* __restrict__ woff,
+                                uint64_t G, uint64_t T, bool pull, uint64_t* tb) {
+    const uint64_t tiles = (T + kExpTile - 1) / kExpTile;
+    for (uint64_t tile = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; tile < tiles;
+         tile += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t tile0 = tile * kExpTile;
+        const uint64_t tile1 = tile0 + kExpTile < T ? tile0 + kExpTile : T;
+        const uint64_t s_lo = upper_bound_u64(soff, 0, S + 1, tile0) - 1;
+        const uint64_t s_hi = upper_bound_u64(soff, s_lo, S + 1, tile1 - 1);
+        uint64_t g_lo = 0, g_hi = 0;
+        if (!pull) {
+            g_lo = upper_bound_u64(woff, 0, G + 1, s_lo) - 1;
+            g_hi = upper_bound_u64(woff, g_lo, G + 1, s_hi - 1);
+        }
+        tb[4 * tile] = s_lo;
+        tb[4 * tile + 1] = s_hi;
+        tb[4 * tile + 2] = g_lo;
+        tb[4 * tile + 3] = g_hi;
+    }
+}
+
 template <class KI, class KO, bool EMIT, bool PULL>
 __global__ void __launch_bounds__(kBlock)
 k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint64_t* __restrict__ gstart,
@@ -144,26 +167,15 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
          const uint64_t* __restrict__ soff, uint64_t S, uint64_t T, DevGraph g, const uint8_t* __restrict__ colors,
          IntroArgs a, uint32_t* tcount, const uint64_t* __restrict__ toff, KO* okeys, uint64_t* ocnt, Lay LO,
          uint64_t* osrc, uint16_t* pbits) {
-    // pbits: the count pass stores every thread's survivor bits, the emit pass reads them
-    __shared__ uint64_t bounds[4];  // segment and group ranges of the tile
+    // pbits: the count pass stores every thread's survivor bits, the emit pass
+    // reads them; after them, k_expand_bounds's four words per tile
     const uint64_t tiles = (T + kExpTile - 1) / kExpTile;
+    const uint64_t* tbounds = reinterpret_cast<const uint64_t*>(pbits + tiles * kBlock);
     for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const uint64_t tile0 = tile * kExpTile;
         const uint64_t tile1 = tile0 + kExpTile < T ? tile0 + kExpTile : T;
-        if (threadIdx.x == 0) {
-            uint64_t s_lo = upper_bound_u64(soff, 0, S + 1, tile0) - 1;
-            uint64_t s_hi = upper_bound_u64(soff, s_lo, S + 1, tile1 - 1);  // one past the last segment
-            bounds[0] = s_lo;
-            bounds[1] = s_hi;
-            if (!PULL) {
-                bounds[2] = upper_bound_u64(woff, 0, G + 1, s_lo) - 1;
-                bounds[3] = upper_bound_u64(woff, bounds[2], G + 1, s_hi - 1);
-            }
-        }
-        __syncthreads();
-        const uint64_t s_lo = bounds[0], s_hi = bounds[1];
-        const uint64_t g_lo = PULL ? 0 : bounds[2], g_hi = PULL ? 0 : bounds[3];
-        __syncthreads();
+        const uint64_t s_lo = tbounds[4 * tile], s_hi = tbounds[4 * tile + 1];
+        const uint64_t g_lo = PULL ? 0 : tbounds[4 * tile + 2], g_hi = PULL ? 0 : tbounds[4 * tile + 3];
         const uint64_t t0 = tile0 + uint64_t(threadIdx.x) * kExpItems;
         const uint64_t t1 = t0 + kExpItems < tile1 ? t0 + kExpItems : tile1;
         uint32_t pass = 0;  // bit j: item t0 + j survives
@@ -345,11 +357,17 @@ static void expand_dispatch(const DevTable& in, const uint64_t* gstart, const ui
                                                                   (u128*)ok, oc, LO, osrc, pbits);
 }
 
-uint64_t expand_pass_words(uint64_t T) { return expand_tiles(T) * kBlock; }
+// survivor bits (one 16-bit word per thread and tile), then four 64-bit tile
+// bounds per tile
+uint64_t expand_pass_words(uint64_t T) { return expand_tiles(T) * (kBlock + 16); }
 
 void launch_expand_count(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
                          const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
                          const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, uint16_t* pbits, hipStream_t s) {
+    const uint64_t tiles = expand_tiles(T);
+    if (!tiles) return;
+    k_expand_bounds<<<grid_for(tiles), kBlock, 0, s>>>(soff, S, woff, G, T, pull,
+                                                      reinterpret_cast<uint64_t*>(pbits + tiles * kBlock));
     if (pull)
         expand_dispatch<false, true>(in, gstart, woff, G, rstart, soff, S, T, g, colors, a, tcount, nullptr, nullptr,
                                      nullptr, pbits, s);

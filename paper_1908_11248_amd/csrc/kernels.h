@@ -115,7 +115,9 @@ void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64
 void launch_pull_seglen(const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g, int degF, uint32_t* slen,
                         hipStream_t s);
 uint64_t expand_tiles(uint64_t T);
-// survivor bits of the count pass, read back by the emit pass: expand_pass_words(T) words
+// survivor bits of the count pass and the tiles' segment and group bounds,
+// both written by launch_expand_count and read back by the emit pass:
+// expand_pass_words(T) words
 uint64_t expand_pass_words(uint64_t T);
 void launch_expand_count(bool pull, const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G,
                          const uint64_t* rstart, const uint64_t* soff, uint64_t S, uint64_t T, DevGraph g,
