@@ -1281,7 +1281,10 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         void* kb2 = X.raw(in.n * lo.key_bytes());
                         uint64_t* vb2 = X.alloc<uint64_t>(in.n);
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
-                        radix_sort(o.keys, idx, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s);
+                        if (radix_sort(o.keys, idx, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s, false)) {
+                            std::swap(o.keys, kb2);  // the sorted data is in the second buffers: keep those
+                            std::swap(idx, vb2);
+                        }
                         X.release(tmp);
                         X.release(vb2);
                         X.release(kb2);
@@ -1293,8 +1296,14 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         void* kb2 = X.raw(in.n * lo.key_bytes());
                         uint64_t* vb2 = X.alloc<uint64_t>(in.n);
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
-                        X.timed("radix_sort", double(in.n) * (lo.key_bytes() + 8) * 2,
-                                [&] { radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s); });
+                        bool in_b = false;
+                        X.timed("radix_sort", double(in.n) * (lo.key_bytes() + 8) * 2, [&] {
+                            in_b = radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s, false);
+                        });
+                        if (in_b) {  // the sorted data is in the second buffers: keep those
+                            std::swap(o.keys, kb2);
+                            std::swap(o.cnt, vb2);
+                        }
                         X.release(tmp);
                         X.release(vb2);
                         X.release(kb2);

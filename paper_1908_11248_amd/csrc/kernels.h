@@ -150,10 +150,13 @@ void launch_join_emit(const DevTable& y, const DevTable& z, const uint64_t* gsta
 // column permutation (out column j <- in column perm[j]) into tmp, then sort
 // index_values: the values become the input positions instead of the counts
 void launch_permute(const DevTable& in, const int* perm, DevTable& out, bool index_values, hipStream_t s);
-// stable LSD radix sort of (keys, vals) on key bits [lo, bits); result in the a-buffers
+// stable LSD radix sort of (keys, vals) on key bits [lo, bits), ping-ponging
+// between the a- and b-buffers. Returns true when the result is in the
+// b-buffers, which happens only with copy_back false; with copy_back true an
+// odd number of passes ends with a copy back into the a-buffers.
 size_t radix_tmp_bytes(uint64_t n);
-void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, int lo,
-                void* tmp, hipStream_t s);
+bool radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, int lo,
+                void* tmp, hipStream_t s, bool copy_back = true);
 
 // fused introduce (pull, one-column child) + forget of the child's column
 // (fused.hip); in == nullptr means the child is a leaf synthesised from the

@@ -925,9 +925,9 @@ size_t radix_tmp_bytes(uint64_t n) {
     return h * 4 + (h + 1) * 8 + scan_tmp_bytes(h) + 256;
 }
 
-void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, int lo,
-                void* tmp, hipStream_t s) {
-    if (n <= 1 || bits <= lo) return;
+bool radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, int lo,
+                void* tmp, hipStream_t s, bool copy_back) {
+    if (n <= 1 || bits <= lo) return false;
     uint64_t nblk = (n + kRadixTile - 1) / kRadixTile;
     uint64_t h = 256 * nblk;
     uint32_t* hist = (uint32_t*)tmp;
@@ -959,10 +959,11 @@ void radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, 
         src_v = dst_v;
         dst_v = tv;
     }
-    if (src_k != keys_a) {
-        (void)hipMemcpyAsync(keys_a, src_k, n * (kw == 1 ? 8 : 16), hipMemcpyDeviceToDevice, s);
-        (void)hipMemcpyAsync(vals_a, src_v, n * 8, hipMemcpyDeviceToDevice, s);
-    }
+    if (src_k == keys_a) return false;
+    if (!copy_back) return true;
+    (void)hipMemcpyAsync(keys_a, src_k, n * (kw == 1 ? 8 : 16), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(vals_a, src_v, n * 8, hipMemcpyDeviceToDevice, s);
+    return false;
 }
 
 // ---------------------------------------------------------------------------
