@@ -1291,14 +1291,20 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         launch_gather_u64(in.cnt, idx, in.n, o.cnt, s);
                         lk[i].src = idx;
                     } else if (in.n) {
-                        X.timed("permute", double(in.n) * (in.lay.key_bytes() + lo.key_bytes() + 16),
-                                [&] { launch_permute(in, st.perm, o, false, s); });
+                        // same key width: the sort's first pass reads the input and
+                        // reorders its columns on the way
+                        const bool fold = in.lay.kw() == lo.kw();
+                        if (!fold)
+                            X.timed("permute", double(in.n) * (in.lay.key_bytes() + lo.key_bytes() + 16),
+                                    [&] { launch_permute(in, st.perm, o, false, s); });
                         void* kb2 = X.raw(in.n * lo.key_bytes());
                         uint64_t* vb2 = X.alloc<uint64_t>(in.n);
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
+                        RadixSource from{in.keys, in.cnt, in.lay, lo, {st.perm[0], st.perm[1], st.perm[2], st.perm[3]}};
                         bool in_b = false;
                         X.timed("radix_sort", double(in.n) * (lo.key_bytes() + 8) * 2, [&] {
-                            in_b = radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s, false);
+                            in_b = radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s, false,
+                                              fold ? &from : nullptr);
                         });
                         if (in_b) {  // the sorted data is in the second buffers: keep those
                             std::swap(o.keys, kb2);

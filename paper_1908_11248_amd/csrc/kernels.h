@@ -154,9 +154,19 @@ void launch_permute(const DevTable& in, const int* perm, DevTable& out, bool ind
 // between the a- and b-buffers. Returns true when the result is in the
 // b-buffers, which happens only with copy_back false; with copy_back true an
 // odd number of passes ends with a copy back into the a-buffers.
+// With `from`, the first pass reads from->keys / from->vals (a table of n
+// entries in layout from->lay, keys of the same width) with its columns
+// reordered as by launch_permute into from->lay_out, and writes the a-buffers;
+// with no bits to sort it only reorders into the a-buffers.
+struct RadixSource {
+    const void* keys;
+    const uint64_t* vals;
+    Lay lay, lay_out;
+    int perm[4];
+};
 size_t radix_tmp_bytes(uint64_t n);
 bool radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, int lo,
-                void* tmp, hipStream_t s, bool copy_back = true);
+                void* tmp, hipStream_t s, bool copy_back = true, const RadixSource* from = nullptr);
 
 // fused introduce (pull, one-column child) + forget of the child's column
 // (fused.hip); in == nullptr means the child is a leaf synthesised from the

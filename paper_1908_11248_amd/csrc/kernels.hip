@@ -774,14 +774,19 @@ struct Perm {
     int p[4];
 };
 
+// k with its columns reordered: column j of the result is column pm.p[j] of k
+template <class KI, class KO>
+__device__ __forceinline__ KO permute_key(KI k, const Lay& L, const Perm& pm, const Lay& LO) {
+    uint32_t cols[4];
+    for (int j = 0; j < LO.b; j++) cols[j] = kcol(k, L, pm.p[j]);
+    return kpack<KO>(kbid(k, L), cols, LO.b, kset(k, L), LO);
+}
+
 template <class KI, class KO>
 __global__ void k_permute(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, uint64_t N, Lay L, Perm pm,
                           Lay LO, KO* okeys, uint64_t* ocnt, bool index_values) {
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += uint64_t(gridDim.x) * blockDim.x) {
-        KI k = keys[i];
-        uint32_t cols[4];
-        for (int j = 0; j < LO.b; j++) cols[j] = kcol(k, L, pm.p[j]);
-        okeys[i] = kpack<KO>(kbid(k, L), cols, LO.b, kset(k, L), LO);
+        okeys[i] = permute_key<KI, KO>(keys[i], L, pm, LO);
         ocnt[i] = index_values ? i : cnt[i];
     }
 }
@@ -808,16 +813,22 @@ void launch_permute(const DevTable& in, const int* perm, DevTable& out, bool ind
 constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kBlock * kRadixItems;
 
-template <class K>
+// PERM: the keys are those of the table before its columns are reordered
+// (L -> LO by pm), and the pass works on the reordered keys
+template <class K, bool PERM>
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const K* __restrict__ keys, uint64_t n, int shift, uint32_t* hist,
-                                                       uint64_t nblk) {
+                                                       uint64_t nblk, Lay L, Perm pm, Lay LO) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
     uint64_t base = uint64_t(blockIdx.x) * kRadixTile;
     for (int r = 0; r < kRadixItems; r++) {
         uint64_t i = base + uint64_t(r) * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[uint32_t(keys[i] >> shift) & 255u], 1u);
+        if (i < n) {
+            K k = keys[i];
+            if (PERM) k = permute_key<K, K>(k, L, pm, LO);
+            atomicAdd(&h[uint32_t(k >> shift) & 255u], 1u);
+        }
     }
     __syncthreads();
     hist[uint64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
@@ -827,11 +838,11 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const K* __restrict__ key
 // which is their order in the input, and placed in LDS in digit order; the
 // tile then leaves in that order, so the writes of one digit's run are
 // contiguous (keys first, then values, through the same LDS buffer).
-template <class K>
+template <class K, bool PERM>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const K* __restrict__ keys, const uint64_t* __restrict__ vals,
                                                           uint64_t n, int shift, const uint32_t* __restrict__ hist,
                                                           const uint64_t* __restrict__ offs, uint64_t nblk, K* okeys,
-                                                          uint64_t* ovals) {
+                                                          uint64_t* ovals, Lay L, Perm pm, Lay LO) {
     __shared__ K s_key[kRadixTile];                 // keys, then (as 64-bit words) values, in digit order
     __shared__ uint8_t s_dig[kRadixTile];           // digit of every position
     __shared__ uint32_t s_start[256];               // tile-local start of every digit
@@ -865,6 +876,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const K* __restrict__ 
         const uint32_t i = uint32_t(r) * kBlock + threadIdx.x;
         k[r] = i < cnt ? keys[base + i] : K(0);
         v[r] = i < cnt ? vals[base + i] : 0;
+        if (PERM && i < cnt) k[r] = permute_key<K, K>(k[r], L, pm, LO);
     }
     __syncthreads();
     uint32_t pos[kRadixItems];
@@ -925,39 +937,62 @@ size_t radix_tmp_bytes(uint64_t n) {
     return h * 4 + (h + 1) * 8 + scan_tmp_bytes(h) + 256;
 }
 
+template <class K>
+static void radix_pass(bool perm, const void* src_k, const uint64_t* src_v, void* dst_k, uint64_t* dst_v, uint64_t n,
+                       int shift, uint32_t* hist, uint64_t* offs, uint64_t* stmp, const Lay& L, const Perm& pm,
+                       const Lay& LO, hipStream_t s) {
+    const uint64_t nblk = (n + kRadixTile - 1) / kRadixTile;
+    const K* sk = (const K*)src_k;
+    if (perm)
+        k_radix_hist<K, true><<<unsigned(nblk), kBlock, 0, s>>>(sk, n, shift, hist, nblk, L, pm, LO);
+    else
+        k_radix_hist<K, false><<<unsigned(nblk), kBlock, 0, s>>>(sk, n, shift, hist, nblk, L, pm, LO);
+    launch_scan_u32(hist, offs, 256 * nblk, stmp, s);
+    if (perm)
+        k_radix_scatter<K, true><<<unsigned(nblk), kBlock, 0, s>>>(sk, src_v, n, shift, hist, offs, nblk, (K*)dst_k, dst_v,
+                                                                   L, pm, LO);
+    else
+        k_radix_scatter<K, false><<<unsigned(nblk), kBlock, 0, s>>>(sk, src_v, n, shift, hist, offs, nblk, (K*)dst_k,
+                                                                    dst_v, L, pm, LO);
+}
+
 bool radix_sort(void* keys_a, uint64_t* vals_a, void* keys_b, uint64_t* vals_b, uint64_t n, int kw, int bits, int lo,
-                void* tmp, hipStream_t s, bool copy_back) {
-    if (n <= 1 || bits <= lo) return false;
+                void* tmp, hipStream_t s, bool copy_back, const RadixSource* from) {
+    const int passes = (n <= 1 || bits <= lo) ? 0 : (bits - lo + 7) / 8;
+    if (from && passes == 0) {  // nothing to sort: only the reordering
+        DevTable in{const_cast<void*>(from->keys), const_cast<uint64_t*>(from->vals), n, from->lay};
+        DevTable out{keys_a, vals_a, n, from->lay_out};
+        launch_permute(in, from->perm, out, false, s);
+        return false;
+    }
+    if (passes == 0) return false;
     uint64_t nblk = (n + kRadixTile - 1) / kRadixTile;
     uint64_t h = 256 * nblk;
     uint32_t* hist = (uint32_t*)tmp;
     uint64_t* offs = (uint64_t*)((char*)tmp + ((h * 4 + 255) / 256) * 256);
     uint64_t* stmp = offs + h + 1;
-    int passes = (bits - lo + 7) / 8;
-    void* src_k = keys_a;
-    uint64_t* src_v = vals_a;
-    void* dst_k = keys_b;
-    uint64_t* dst_v = vals_b;
+    const Lay L = from ? from->lay : Lay{};
+    const Lay LO = from ? from->lay_out : Lay{};
+    const Perm pm = from ? Perm{{from->perm[0], from->perm[1], from->perm[2], from->perm[3]}} : Perm{{0, 1, 2, 3}};
+    // without a source table the passes go a -> b -> a ...; with one, the
+    // first reads it and writes a
+    const void* src_k = from ? from->keys : keys_a;
+    const uint64_t* src_v = from ? from->vals : vals_a;
+    void* dst_k = from ? keys_a : keys_b;
+    uint64_t* dst_v = from ? vals_a : vals_b;
     for (int p = 0; p < passes; p++) {
-        int shift = lo + 8 * p;
-        if (kw == 1) {
-            k_radix_hist<uint64_t><<<unsigned(nblk), kBlock, 0, s>>>((const uint64_t*)src_k, n, shift, hist, nblk);
-        } else {
-            k_radix_hist<u128><<<unsigned(nblk), kBlock, 0, s>>>((const u128*)src_k, n, shift, hist, nblk);
-        }
-        launch_scan_u32(hist, offs, h, stmp, s);
+        const int shift = lo + 8 * p;
+        const bool perm = from && p == 0;
         if (kw == 1)
-            k_radix_scatter<uint64_t><<<unsigned(nblk), kBlock, 0, s>>>((const uint64_t*)src_k, src_v, n, shift, hist,
-                                                                        offs, nblk, (uint64_t*)dst_k, dst_v);
+            radix_pass<uint64_t>(perm, src_k, src_v, dst_k, dst_v, n, shift, hist, offs, stmp, L, pm, LO, s);
         else
-            k_radix_scatter<u128><<<unsigned(nblk), kBlock, 0, s>>>((const u128*)src_k, src_v, n, shift, hist, offs,
-                                                                    nblk, (u128*)dst_k, dst_v);
-        void* tk = src_k;
+            radix_pass<u128>(perm, src_k, src_v, dst_k, dst_v, n, shift, hist, offs, stmp, L, pm, LO, s);
+        // the next pass reads what this one wrote and writes the other buffer
+        const bool wrote_a = dst_k == keys_a;
         src_k = dst_k;
-        dst_k = tk;
-        uint64_t* tv = src_v;
         src_v = dst_v;
-        dst_v = tv;
+        dst_k = wrote_a ? keys_b : keys_a;
+        dst_v = wrote_a ? vals_b : vals_a;
     }
     if (src_k == keys_a) return false;
     if (!copy_back) return true;
