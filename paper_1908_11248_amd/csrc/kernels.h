@@ -152,8 +152,9 @@ void launch_join_emit(const DevTable& y, const DevTable& z, const uint64_t* gsta
 void launch_permute(const DevTable& in, const int* perm, DevTable& out, bool index_values, hipStream_t s);
 // stable LSD radix sort of (keys, vals) on key bits [lo, bits), ping-ponging
 // between the a- and b-buffers. Returns true when the result is in the
-// b-buffers, which happens only with copy_back false; with copy_back true an
-// odd number of passes ends with a copy back into the a-buffers.
+// b-buffers, which happens only with copy_back false; with copy_back true a
+// result that the last pass wrote to the b-buffers is copied back into the
+// a-buffers.
 // With `from`, the first pass reads from->keys / from->vals (a table of n
 // entries in layout from->lay, keys of the same width) with its columns
 // reordered as by launch_permute into from->lay_out, and writes the a-buffers;

@@ -340,10 +340,11 @@ k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
     // the first 64 entries of the next one loading while it works on one
     for (uint64_t g0 = uint64_t(blockIdx.x) * 64; g0 < G; g0 += uint64_t(gridDim.x) * 64) {
         const uint64_t gl = g0 + lane;
-        uint64_t s0 = 0, s1 = 0;
+        uint64_t s0 = 0, s1 = 0, so = 0;
         if (gl < G) {
             s0 = gstart[gl];
             s1 = gstart[gl + 1];
+            if (EMIT) so = goff[gl];
         }
         uint64_t todo = __ballot(s1 - s0 > uint64_t(kForgetSmall));
         // bounds of group g0 + j, from lane j
@@ -405,7 +406,10 @@ k_forget(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
                 const KI kf = from_lane0(k0);
                 if (__ballot(over) && lane == 0) atomicOr(&ovf[kbid(kf, L)], 1u);
                 KO prefix = KO(shr(kf, sh)) << L.kb;
-                acc_emit<KO>(acc, prefix, goff[grp], okeys, ocnt);
+                const int j = int(grp - g0);  // the group's output offset, from lane j
+                const uint64_t ob = uint64_t(__builtin_amdgcn_readlane(uint32_t(so), j)) |
+                                    (uint64_t(__builtin_amdgcn_readlane(uint32_t(so >> 32), j)) << 32);
+                acc_emit<KO>(acc, prefix, ob, okeys, ocnt);
             } else {
                 uint32_t c = acc_count(acc);
                 if (lane == 0) gcount[grp] = c;
@@ -475,15 +479,17 @@ k_forget_small(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
     // the loop bound is uniform over the block, so every lane reaches the
     // row broadcasts
     for (uint64_t base = uint64_t(blockIdx.x) * rows * U; base < G; base += uint64_t(gridDim.x) * rows * U) {
-        uint64_t e0[U], m[U];
+        uint64_t e0[U], m[U], o0[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const uint64_t grp = base + u * rows + threadIdx.x / LN;
             e0[u] = 0;
             m[u] = 0;
+            o0[u] = 0;
             if (grp < G) {
                 e0[u] = gstart[grp];
                 m[u] = gstart[grp + 1] - e0[u];
+                if (EMIT) o0[u] = goff[grp];
                 if (m[u] > uint64_t(LN)) m[u] = 0;  // k_forget's run
             }
         }
@@ -514,7 +520,7 @@ k_forget_small(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
                 uint32_t rank = 0;
                 small_rank<0>(mm, first ? C : ~0u, C, rank);
                 if (first) {
-                    const uint64_t o = goff[grp] + rank;
+                    const uint64_t o = o0[u] + rank;
                     okeys[o] = (KO(shr(k[u], sh)) << L.kb) | KO(C);
                     ocnt[o] = sum;
                 }
