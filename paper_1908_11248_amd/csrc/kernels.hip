@@ -828,12 +828,19 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const K* __restrict__ key
     h[threadIdx.x] = 0;
     __syncthreads();
     uint64_t base = uint64_t(blockIdx.x) * kRadixTile;
+    // all loads first, then the digits
+    K k[kRadixItems];
+#pragma unroll
     for (int r = 0; r < kRadixItems; r++) {
-        uint64_t i = base + uint64_t(r) * kBlock + threadIdx.x;
+        const uint64_t i = base + uint64_t(r) * kBlock + threadIdx.x;
+        k[r] = i < n ? keys[i] : K(0);
+    }
+#pragma unroll
+    for (int r = 0; r < kRadixItems; r++) {
+        const uint64_t i = base + uint64_t(r) * kBlock + threadIdx.x;
         if (i < n) {
-            K k = keys[i];
-            if (PERM) k = permute_key<K, K>(k, L, pm, LO);
-            atomicAdd(&h[uint32_t(k >> shift) & 255u], 1u);
+            const K kr = PERM ? permute_key<K, K>(k[r], L, pm, LO) : k[r];
+            atomicAdd(&h[uint32_t(kr >> shift) & 255u], 1u);
         }
     }
     __syncthreads();
@@ -882,7 +889,11 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const K* __restrict__ 
         const uint32_t i = uint32_t(r) * kBlock + threadIdx.x;
         k[r] = i < cnt ? keys[base + i] : K(0);
         v[r] = i < cnt ? vals[base + i] : 0;
-        if (PERM && i < cnt) k[r] = permute_key<K, K>(k[r], L, pm, LO);
+    }
+    if (PERM) {  // after all loads are issued
+#pragma unroll
+        for (int r = 0; r < kRadixItems; r++)
+            if (uint32_t(r) * kBlock + threadIdx.x < cnt) k[r] = permute_key<K, K>(k[r], L, pm, LO);
     }
     __syncthreads();
     uint32_t pos[kRadixItems];
