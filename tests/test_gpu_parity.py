@@ -127,6 +127,29 @@ def test_short_forget_runs_with_large_counts(ctx):
             assert int(counts[b]) == ref["count"] and bool(ovf[b]) == ref["overflow"], (D, b)
 
 
+def test_two_word_keys_match_oracle(ctx):
+    # An ER(300) graph whose vertex ids are spread over 2^20 + 7 vertices: an
+    # image takes 21 bits, so a bag of three or four columns, its colour set
+    # and the colouring index need 128-bit keys, and every sorted-list kernel
+    # runs its two-word form.
+    g0 = W.er_pairs(300, 0.05, 21)
+    n = (1 << 20) + 7
+    ids = (np.arange(300, dtype=np.int64) * 3491 + 17) % n
+    src = np.repeat(np.arange(300), np.diff(g0.row_ptr))
+    m = src < g0.col
+    g = W.csr_from_edges(n, ids[src[m]], ids[g0.col[m]])
+    rng = np.random.default_rng(99)
+    for pat in (W.cycle(5), W.ladder(3), W.partial_3tree(7, 2)):
+        for k in (pat.n, pat.n + 1):
+            colors = rng.integers(0, k, size=(3, g.n)).astype(np.uint8)
+            say("two-word keys", pat.name, "k", k)
+            counts, ovf, D = run_gpu(ctx, g, pat, k, colors)
+            for b in range(3):
+                ref = O.dp_count(g, pat, k, colors[b], td=D.export())
+                assert int(counts[b]) == ref["count"] and bool(ovf[b]) == ref["overflow"], (pat.name, k, b)
+            assert counts.any(), pat.name
+
+
 def test_edge_cases(ctx):
     # graph without edges, pattern with edges: zero
     g = W.csr_from_edges(50, np.zeros(0, np.int64), np.zeros(0, np.int64))
