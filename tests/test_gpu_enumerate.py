@@ -95,3 +95,30 @@ def test_workload3_capped_enumeration(ctx, b):
     assert np.array_equal(rows, ref)
     counts, _ = cc.count(ctx, G, C, D)
     assert total == int(counts[b])
+
+
+def test_enumeration_with_two_word_keys(ctx):
+    """An ER(300) graph with its vertex ids spread over 2^20 + 7 vertices: the
+    tables of a bag of three columns need 128-bit keys, and the rows still
+    equal brute force's, capped or not."""
+    g0 = W.er_pairs(300, 0.05, 21)
+    n = (1 << 20) + 7
+    ids = (np.arange(300, dtype=np.int64) * 3491 + 17) % n
+    src = np.repeat(np.arange(300), np.diff(g0.row_ptr))
+    m = src < g0.col
+    g = W.csr_from_edges(n, ids[src[m]], ids[g0.col[m]])
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    rng = np.random.default_rng(7)
+    for pat in (W.cycle(5), W.ladder(3)):
+        colors = rng.integers(0, pat.n, size=(1, g.n)).astype(np.uint8)
+        C = cc.color_explicit(ctx, G, pat.n, colors)
+        D = cc.build_decomposition(pat.n, pat.edges)
+        say("enum two-word keys", pat.name)
+        ref = O.brute_enum(g, pat, colors[0], 10**7)
+        assert len(ref) > 0
+        rows, total = cc.enumerate(ctx, G, C, 0, D, 10**7)
+        assert total == len(ref) and np.array_equal(rows, ref)
+        cap = len(ref) // 3
+        rows2, total2 = cc.enumerate(ctx, G, C, 0, D, cap)
+        assert total2 == len(ref) and np.array_equal(rows2, ref[:cap])
+        C.close()
