@@ -7,7 +7,7 @@ its binding) never loads it.
 It wraps ``oracle.c`` (plain C, written from the paper of Malik, Suchy and
 Valla, arXiv 1908.11248) through ctypes:
 
-* ``color_array``      -- splitmix64 random colouring (Sec. 2.1)
+* ``color_of``, ``color_array`` -- splitmix64 random colouring (Sec. 2.1)
 * ``brute_count``      -- count of colourful mappings by backtracking (the
                           definition: Sec. 1 problem statement, colourful copy)
 * ``brute_enum``       -- lexicographically first mappings (same definition)
@@ -91,6 +91,10 @@ def _pattern(pat):
 
 def splitmix64(x: int) -> int:
     return int(_load().orc_splitmix64(ctypes.c_uint64(x & (2**64 - 1))))
+
+
+def color_of(seed: int, b: int, v: int, k: int) -> int:
+    return int(_load().orc_color_of(seed & (2**64 - 1), b, v, k))
 
 
 def color_array(seed: int, b: int, n: int, k: int) -> np.ndarray:

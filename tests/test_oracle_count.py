@@ -277,3 +277,76 @@ def test_per_root_vertex_split():
         assert int(prv.sum()) == r["count"]
         for v in rng.choice(g.n, 6, replace=False):
             assert int(prv[v]) == O.brute_count(g, pat, col, fix0=int(v))
+
+
+def _td_nodes(td):
+    N = int(td[0])
+    return [(int(td[1 + 5 * i]), int(td[2 + 5 * i]), int(td[3 + 5 * i]), int(td[4 + 5 * i]),
+             int(td[5 + 5 * i]) & 0xFFFFFFFF) for i in range(N)]
+
+
+def _definition_table_sizes(g, pat, k, col, td, degmask=True):
+    """|D_x| of every node straight from the definition of D(x, phi, C)
+    (Sec. 3.1): the number of distinct pairs (phi, C) such that some mapping
+    Phi of V_x (the vertices of the bags below x) preserves the edges of F
+    among V_x, gives V_x pairwise distinct colours, restricts to phi on the
+    bag and has colour set C; with the degree mask (Sec. 3.2) every image
+    also has deg_G >= deg_F.  Plain backtracking over all such Phi."""
+    adj = B.adjacency(g)
+    fadj = {u: set() for u in range(pat.n)}
+    for a, b in pat.edges:
+        fadj[a].add(b)
+        fadj[b].add(a)
+    nodes = _td_nodes(td)
+    below = []
+    for t, u, c0, c1, bag in nodes:
+        s = bag
+        for c in (c0, c1):
+            if c >= 0:
+                s |= below[c]
+        below.append(s)
+    sizes = []
+    for i, (t, u, c0, c1, bag) in enumerate(nodes):
+        vx = [w for w in range(pat.n) if below[i] >> w & 1]
+        bagv = [w for w in range(pat.n) if bag >> w & 1]
+        seen = set()
+        phi = {}
+
+        def rec(j, used):
+            if j == len(vx):
+                seen.add((tuple(phi[w] for w in bagv), used))
+                return
+            w = vx[j]
+            for v in range(g.n):
+                c = int(col[v])
+                if used >> c & 1:
+                    continue
+                if degmask and len(adj[v]) < len(fadj[w]):
+                    continue
+                if any(x in phi and phi[x] not in adj[v] for x in fadj[w]):
+                    continue
+                phi[w] = v
+                rec(j + 1, used | (1 << c))
+                del phi[w]
+
+        rec(0, 0)
+        sizes.append(len(seen))
+    return sizes
+
+
+@pytest.mark.parametrize("pat", [W.path(4), W.cycle(4), W.cycle(5), W.star(4), W.grid(2, 2),
+                                 W.Pattern(4, [(0, 1), (2, 3)], "2K2"),
+                                 W.Pattern(5, [(0, 1), (1, 2), (0, 2), (2, 3), (3, 4)], "tri+tail")],
+                         ids=lambda p: p.name)
+def test_node_table_sizes_vs_definition(pat):
+    """The oracle's per-node |D_x| (dp_count sizes=True) equals the number of
+    (phi, C) pairs the definition of D(x, phi, C) admits, node by node, with
+    and without the degree mask, with k = n_F and k = n_F + 1."""
+    rng = np.random.default_rng(77)
+    td, _ = O.build_td(pat)
+    for g in zoo_graphs()[:4]:
+        for k in (pat.n, pat.n + 1):
+            col = colours(rng, g.n, k)
+            for dm in (True, False):
+                got = O.dp_count(g, pat, k, col, td=td, degmask=dm, sizes=True)["sizes"]
+                assert list(got) == _definition_table_sizes(g, pat, k, col, td, degmask=dm)

@@ -1,6 +1,8 @@
 """Pins of the oracle's tree-decomposition side (Sec. 1.2 definitions, Sec. 3).
 
 * splitmix64 against its published outputs (golden file).
+* the colour map against colours derived by hand from those outputs (golden
+  file).
 * exact treewidth against the families' known values and Table `prop`
   (golden file), and against brute force over all elimination orderings.
 * the nice-TD validator accepts the oracle's TDs and rejects planted mistakes.
@@ -27,6 +29,22 @@ def test_splitmix64_published_vectors():
         assert O.splitmix64((seed + (i - 1) * gamma) % 2**64) == out
         n += 1
     assert n == 6
+
+
+def test_colour_map_hand_derived_vectors():
+    """Colours derived by hand from the published splitmix64 outputs
+    (golden/colour_vectors.txt): pins the seed mixing, the high word and the
+    multiply-shift, for b = 0 and b > 0 and vertex ids up to 2^31 - 1."""
+    n = 0
+    for line in open(os.path.join(GOLDEN, "colour_vectors.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        seed, b, v, k, colour = (int(x) for x in line.split("|")[0].split())
+        assert O.color_of(seed, b, v, k) == colour, line
+        if v < 200000:
+            assert int(O.color_array(seed, b, v + 1, k)[v]) == colour, line
+        n += 1
+    assert n == 18
 
 
 def test_colouring_range_and_uniformity():
