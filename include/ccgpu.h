@@ -30,10 +30,12 @@
  *   - A context is used by one host thread at a time.  Calls that produce
  *     results synchronise the context's stream before they return.
  *   - Colours are 0-based: colour c of a k-colouring is c in [0, k).
- *   - Limits: 1 <= n_F <= 16, n_F <= k <= 16 (colour sets are k-bit masks;
- *     the paper uses 32-bit masks for n_F <= 32, Sec. 3.2), n_G < 2^31, and
- *     the packed table key (colouring index, bag images, colour set) must fit
- *     128 bits; otherwise CC_ERANGE.
+ *   - Limits (CC_ERANGE when exceeded): a decomposition takes
+ *     1 <= n_F <= 16 pattern vertices; a colouring takes 1 <= k <= 12 colours
+ *     and at most 2^20 colourings; counting and enumeration need
+ *     n_F <= k (colour sets are k-bit masks; the paper uses 32-bit masks for
+ *     n_F <= 32, Sec. 3.2); n_G < 2^31; the packed table key (colouring
+ *     index, bag images, colour set) must fit 128 bits.
  */
 #ifndef CCGPU_H
 #define CCGPU_H
@@ -62,12 +64,20 @@ typedef struct cc_decomp cc_decomp;
 const char *cc_last_error(void);
 
 /* Creates a context on HIP device `device`.
- *   arena_bytes  size of the device arena that holds every DP table; the
- *                library allocates it (0: a default of 3/4 of free memory).
- *   hip_stream   hipStream_t to launch on (NULL: the library creates one;
- *                the caller keeps ownership of a stream it passes).
- * Errors: CC_EDEVICE (no such device), CC_ENOMEM. */
-int cc_context_create(int device, size_t arena_bytes, void *hip_stream, cc_context **out);
+ *   arena_dev    device memory of `device` that holds every DP table and the
+ *                per-run scratch (e.g. a torch uint8 tensor's data pointer),
+ *                256-byte aligned; the caller owns it and must keep it alive
+ *                until cc_context_destroy returns.  NULL: the library
+ *                allocates the arena itself.
+ *   arena_bytes  size of the arena (>= 4096 with arena_dev; with NULL,
+ *                0 means 3/4 of the device's free memory).
+ *   hip_stream   hipStream_t to launch the single-query calls on (e.g. torch's
+ *                current stream; NULL: the library creates one).  The caller
+ *                keeps ownership of a stream it passes.
+ * Errors: CC_EINVAL (misaligned or foreign arena), CC_EDEVICE (no such
+ * device), CC_ENOMEM. */
+int cc_context_create(int device, void *arena_dev, size_t arena_bytes, void *hip_stream,
+                      cc_context **out);
 int cc_context_destroy(cc_context *ctx);
 
 /* Uploads host graph G (Sec. 1.2: simple and undirected) in CSR form:
@@ -228,6 +238,8 @@ int cc_server_start(cc_context *ctx, const cc_graph *g, const cc_server_opts *op
  * cc_color(k, seed); the decomposition must outlive the request. */
 int cc_server_submit(cc_server *srv, const cc_decomp *d, int32_t k, uint64_t seed, int32_t num_colorings,
                      uint64_t *ticket);
+/* (errors: CC_EINVAL for NULL arguments, CC_ERANGE when k or num_colorings
+ * is outside the limits above, CC_ECANCELLED once the server is stopping) */
 /* *state: 0 queued or running, 1 done (counts[num_colorings] and overflow
  * written), or a negative CC_E* code of a failed query. */
 int cc_server_poll(cc_server *srv, uint64_t ticket, uint64_t *counts, uint8_t *overflow, int32_t *state);

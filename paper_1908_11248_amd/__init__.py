@@ -57,12 +57,21 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise LibraryMissing("libccgpu.so is not built: run python -m paper_1908_11248_amd.build")
+        # One HIP runtime per process: torch ships its own libamdhip64 (same
+        # soname), which it loads by file name.  Loaded first, it also serves
+        # this library; loaded second, a second runtime would start that sees
+        # no devices.  So torch, when installed, is imported before the
+        # library is opened.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, I32, U32, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
         PP = ctypes.POINTER(ctypes.c_void_p)
         sig = {
             "cc_last_error": (ctypes.c_char_p, []),
-            "cc_context_create": (ctypes.c_int, [ctypes.c_int, SZ, P, PP]),
+            "cc_context_create": (ctypes.c_int, [ctypes.c_int, P, SZ, P, PP]),
             "cc_context_destroy": (ctypes.c_int, [P]),
             "cc_load_graph": (ctypes.c_int, [P, I32, P, P, U32, PP]),
             "cc_graph_free": (None, [P]),
@@ -187,18 +196,39 @@ class KernelStat(ctypes.Structure):
                 ("algo_bytes", ctypes.c_double)]
 
 
+def _stream_handle(stream):
+    """A raw hipStream_t from None, an int, or an object with .cuda_stream
+    (torch.cuda.Stream)."""
+    if stream is None:
+        return None
+    return int(getattr(stream, "cuda_stream", stream)) or None
+
+
 class Context(_Handle):
+    """A library context on one device.
+
+    ``arena`` optionally supplies the DP arena as caller-owned device memory:
+    any object with ``data_ptr()`` and ``numel()`` (a contiguous torch uint8
+    tensor on the context's device, say) -- the context keeps a reference to
+    it.  ``stream`` is a raw hipStream_t or a torch.cuda.Stream."""
     _free = None
 
-    def __init__(self, device: int = 0, arena_bytes: int = 0, stream: Optional[int] = None):
+    def __init__(self, device: int = 0, arena_bytes: int = 0, stream=None, arena=None):
         out = ctypes.c_void_p()
-        _check(lib().cc_context_create(device, arena_bytes, stream, ctypes.byref(out)))
+        ptr = None
+        if arena is not None:
+            ptr = int(arena.data_ptr())
+            arena_bytes = int(arena.numel()) * int(getattr(arena, "element_size", lambda: 1)())
+        self._arena = arena
+        self._stream = stream
+        _check(lib().cc_context_create(device, ptr, arena_bytes, _stream_handle(stream), ctypes.byref(out)))
         super().__init__(out.value)
 
     def close(self):
         if self.ptr:
             lib().cc_context_destroy(self.ptr)
             self.ptr = None
+        self._arena = None
 
     def __enter__(self):
         return self

@@ -33,7 +33,7 @@ int guarded(F&& f) {
     }
 }
 
-void need(bool ok, int code, const char* msg) {
+void need(bool ok, int code, const std::string& msg) {
     if (!ok) fail(code, msg);
 }
 }  // namespace
@@ -46,9 +46,11 @@ extern "C" {
 
 const char* cc_last_error(void) { return g_last_error.c_str(); }
 
-int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_context** out) {
+int cc_context_create(int device, void* arena_dev, size_t arena_bytes, void* hip_stream, cc_context** out) {
     return guarded([&] {
         need(out != nullptr, CC_EINVAL, "out is NULL");
+        need(!arena_dev || arena_bytes >= 4096, CC_EINVAL, "a caller arena needs arena_bytes >= 4096");
+        need((uintptr_t(arena_dev) & 255) == 0, CC_EINVAL, "a caller arena must be 256-byte aligned");
         int ndev = 0;
         hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
         need(device >= 0 && device < ndev, CC_EDEVICE, "no such HIP device");
@@ -57,13 +59,22 @@ int cc_context_create(int device, size_t arena_bytes, void* hip_stream, cc_conte
         c->device = device;
         try {
             c->main.create((hipStream_t)hip_stream);
-            if (arena_bytes == 0) {
-                size_t freeb = 0, total = 0;
-                hip_check(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
-                arena_bytes = freeb / 4 * 3;
+            if (arena_dev) {
+                // caller-owned device memory (a torch tensor, say): used, never freed
+                hipPointerAttribute_t at;
+                hip_check(hipPointerGetAttributes(&at, arena_dev), "arena pointer attributes");
+                need(at.type == hipMemoryTypeDevice && at.device == device, CC_EINVAL,
+                     "the caller arena is not device memory of this device");
+                c->arena.init((char*)arena_dev, arena_bytes);
+            } else {
+                if (arena_bytes == 0) {
+                    size_t freeb = 0, total = 0;
+                    hip_check(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
+                    arena_bytes = freeb / 4 * 3;
+                }
+                hip_check(hipMalloc(&c->arena_mem, arena_bytes), "arena hipMalloc");
+                c->arena.init((char*)c->arena_mem, arena_bytes);
             }
-            hip_check(hipMalloc(&c->arena_mem, arena_bytes), "arena hipMalloc");
-            c->arena.init((char*)c->arena_mem, arena_bytes);
             std::vector<uint16_t> st = slot_rank_tables();
             hip_check(hipMalloc(&c->slot_tables, st.size() * 2), "hipMalloc");
             hip_check(hipMemcpy(c->slot_tables, st.data(), st.size() * 2, hipMemcpyHostToDevice), "hipMemcpy");
@@ -171,7 +182,7 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
         std::vector<uint64_t> eh(cells, kEdgeEmpty);
         for (int32_t v = 0; v < n; v++)
             for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
-                const uint32_t w = uint32_t(col[e]);
+                const uint32_t w = uint32_t(cl[e]);
                 if (w <= uint32_t(v)) continue;  // each edge once
                 const uint64_t key = edge_key(uint32_t(v), w);
                 uint64_t h = edge_cell(key, cells - 1);
@@ -260,7 +271,7 @@ int cc_color(cc_context* ctx, const cc_graph* g, int32_t k, uint64_t seed, int32
              cc_coloring** out) {
     return guarded([&] {
         need(ctx && g && out, CC_EINVAL, "bad arguments");
-        need(k >= 1 && k <= 32, CC_ERANGE, "k must be in [1, 32]");
+        need(k >= 1 && k <= kMaxColours, CC_ERANGE, "k must be in [1, " + std::to_string(kMaxColours) + "]");
         need(num_colorings >= 1 && num_colorings <= (1 << 20), CC_ERANGE, "num_colorings out of range");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         auto* c = new cc_coloring();
@@ -289,7 +300,7 @@ int cc_color_explicit(cc_context* ctx, const cc_graph* g, int32_t k, int32_t num
                       cc_coloring** out) {
     return guarded([&] {
         need(ctx && g && out && colors, CC_EINVAL, "bad arguments");
-        need(k >= 1 && k <= 32, CC_ERANGE, "k must be in [1, 32]");
+        need(k >= 1 && k <= kMaxColours, CC_ERANGE, "k must be in [1, " + std::to_string(kMaxColours) + "]");
         need(num_colorings >= 1 && num_colorings <= (1 << 20), CC_ERANGE, "num_colorings out of range");
         size_t total = size_t(g->n) * num_colorings;
         for (size_t i = 0; i < total; i++) need(colors[i] < k, CC_EINVAL, "colour out of range");

@@ -920,7 +920,8 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     const Decomp& dec = rq.dec->d;
     const DevGraph g = rq.g->dev();
     const int B = rq.B, k = rq.k;
-    if (k < dec.n || k > 12) fail(CC_ERANGE, "colours k must satisfy n_F <= k <= 12");
+    if (k < dec.n || k > kMaxColours)
+        fail(CC_ERANGE, "colours k must satisfy n_F <= k <= " + std::to_string(kMaxColours));
     if (B < 1) fail(CC_EINVAL, "no colourings");
     for (int b = 1; b <= plan.max_bag; b++)
         if (table_layout(b, g.n, B, k).bits() > 128)

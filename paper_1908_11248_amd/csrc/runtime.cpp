@@ -298,10 +298,13 @@ int cc_count_batch(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_quer
         return CC_EINVAL;
     }
     for (int32_t i = 0; i < nq; i++) {
-        if (!q[i].decomp || !q[i].coloring || q[i].coloring->ctx != ctx || q[i].coloring->n != g->n ||
-            q[i].coloring->k < q[i].decomp->d.n) {
+        if (!q[i].decomp || !q[i].coloring || q[i].coloring->ctx != ctx || q[i].coloring->n != g->n) {
             set_error("query " + std::to_string(i) + ": bad decomposition or colouring");
             return CC_EINVAL;
+        }
+        if (q[i].coloring->k < q[i].decomp->d.n) {
+            set_error("query " + std::to_string(i) + ": fewer colours than pattern vertices");
+            return CC_ERANGE;
         }
     }
     if (hipSetDevice(ctx->device) != hipSuccess) {
@@ -369,9 +372,14 @@ int cc_server_start(cc_context* ctx, const cc_graph* g, const cc_server_opts* op
 
 int cc_server_submit(cc_server* srv, const cc_decomp* d, int32_t k, uint64_t seed, int32_t num_colorings,
                      uint64_t* ticket) {
-    if (!srv || !d || !ticket || num_colorings < 1 || k < d->d.n || k > 12) {
+    if (!srv || !d || !ticket || num_colorings < 1) {
         set_error("bad arguments");
         return CC_EINVAL;
+    }
+    if (k < d->d.n || k > kMaxColours || num_colorings > (1 << 20)) {
+        set_error("colours k must satisfy n_F <= k <= " + std::to_string(kMaxColours) +
+                  " and num_colorings <= 2^20");
+        return CC_ERANGE;
     }
     std::lock_guard<std::mutex> guard(srv->mu);
     if (srv->stopping) {

@@ -315,7 +315,7 @@ __device__ __forceinline__ void flag_wide(uint32_t hi, uint32_t* flag) {
 
 }  // namespace
 
-// Leaf (Sec. 3, leaf nodes; degree mask of Sec. 4): one slot per (b, v).
+// Leaf (Sec. 3.1, leaf nodes; degree mask of Sec. 3.2): one slot per (b, v).
 template <int M>
 __global__ void __launch_bounds__(kSlotBlock) k_slot_leaf(SlotGrid G, DevGraph g, int degF, SlotArrays out,
                                                           uint64_t* part) {
