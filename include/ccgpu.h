@@ -142,6 +142,23 @@ void cc_decomp_free(cc_decomp *d);
 int cc_count(cc_context *ctx, const cc_graph *g, const cc_coloring *c, const cc_decomp *d,
              uint32_t flags, uint64_t *counts, uint8_t *overflow);
 
+/* cc_count for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments, results and flags as cc_count, but the run makes no device or
+ * pinned-host allocation (no hipMalloc, hipFree or allocating library call).
+ * Its DP tables and scratch live in a fixed 64 MiB device array inside the
+ * library (one per device, held until the process ends; its address is
+ * taken when a context is created on the device); the results are read back
+ * through a pinned buffer the context allocated at creation.  Inputs that
+ * cannot fit (colourings x vertices x 16 bytes above 64 MiB, or tables that
+ * outgrow the array during the run) fail with CC_ERANGE and a message
+ * naming the limit.  All calls on one device share that array: calls that
+ * overlap in time on the same device (from several threads or contexts)
+ * race and must be serialised by the caller.  The per-table budget of
+ * cc_set_table_budget does not apply. */
+int cc_count_noalloc(cc_context *ctx, const cc_graph *g, const cc_coloring *c, const cc_decomp *d,
+                     uint32_t flags, uint64_t *counts, uint8_t *overflow);
+
 /* Same DP for one colouring index b; per_vertex[v] (n entries) receives the
  * number of colourful mappings with Phi(0) = v (the entries of the node
  * below the root, whose bag is {0}). */

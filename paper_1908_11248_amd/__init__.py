@@ -36,6 +36,7 @@ EXPORTS = [
     "cc_profile_enable", "cc_profile_filter", "cc_profile_read", "cc_decomp_describe",
     "cc_set_batch_lanes", "cc_tune_batch", "cc_set_table_budget",
     "cc_server_start", "cc_server_submit", "cc_server_poll", "cc_server_wait", "cc_server_stop",
+    "cc_count_noalloc",
 ]
 
 
@@ -86,6 +87,7 @@ def lib():
             "cc_decomp_width": (I32, [P]),
             "cc_decomp_free": (None, [P]),
             "cc_count": (ctypes.c_int, [P, P, P, P, U32, P, P]),
+            "cc_count_noalloc": (ctypes.c_int, [P, P, P, P, U32, P, P]),
             "cc_count_by_vertex": (ctypes.c_int, [P, P, P, I32, P, U32, P, P, P]),
             "cc_enumerate": (ctypes.c_int, [P, P, P, I32, P, U64, P, P, P]),
             "cc_last_table_sizes": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
@@ -318,6 +320,15 @@ def count(ctx: Context, g: Graph, c: Coloring, d: Decomp, flags: int = 0):
     counts = np.zeros(c.num, dtype=np.uint64)
     ovf = np.zeros(c.num, dtype=np.uint8)
     _check(lib().cc_count(ctx.ptr, g.ptr, c.ptr, d.ptr, flags, _p(counts), _p(ovf)))
+    return counts, ovf.astype(bool)
+
+
+def count_noalloc(ctx: Context, g: Graph, c: Coloring, d: Decomp, flags: int = 0):
+    """count() through cc_count_noalloc (the library's fixed device scratch;
+    no device allocation).  (counts, overflow)"""
+    counts = np.zeros(c.num, dtype=np.uint64)
+    ovf = np.zeros(c.num, dtype=np.uint8)
+    _check(lib().cc_count_noalloc(ctx.ptr, g.ptr, c.ptr, d.ptr, flags, _p(counts), _p(ovf)))
     return counts, ovf.astype(bool)
 
 

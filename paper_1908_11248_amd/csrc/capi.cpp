@@ -12,7 +12,35 @@
 
 using namespace ccg;
 
+// Device scratch of cc_count_noalloc: a fixed array in the code object, so
+// that call allocates nothing.  Every device the library runs on holds its
+// own copy until the process ends.  In host code `scratch` is only a
+// stand-in for the symbol: kernels get the device address that
+// hipGetSymbolAddress returned for the current device (g_scratch_ptr).
+#define CC_NOALLOC_SCRATCH_BYTES (size_t(64) << 20)
+static __device__ __align__(256) char scratch[CC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+constexpr int kMaxDevices = 64;
+constexpr size_t kResultWordsAtInit = size_t(1) << 15;  // pinned read-back words of the main lane
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // per device, set while that device is current
+hipError_t g_scratch_err[kMaxDevices] = {};
+ccg::Arena g_scratch_arena[kMaxDevices];
+
+// Looks up this device's scratch address once (the device must be current).
+// A failure is kept and reported by cc_count_noalloc; the other entry points
+// do not use the array.
+void lookup_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    if (e != hipSuccess) (void)hipGetLastError();  // not sticky for the other calls
+}
+
 thread_local std::string g_last_error;
 
 template <class F>
@@ -53,12 +81,14 @@ int cc_context_create(int device, void* arena_dev, size_t arena_bytes, void* hip
         need((uintptr_t(arena_dev) & 255) == 0, CC_EINVAL, "a caller arena must be 256-byte aligned");
         int ndev = 0;
         hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
-        need(device >= 0 && device < ndev, CC_EDEVICE, "no such HIP device");
+        need(device >= 0 && device < ndev && device < kMaxDevices, CC_EDEVICE, "no such HIP device");
         hip_check(hipSetDevice(device), "hipSetDevice");
+        lookup_scratch(device);  // once per device, with that device current
         auto* c = new cc_context();
         c->device = device;
         try {
             c->main.create((hipStream_t)hip_stream);
+            (void)c->main.result_words(kResultWordsAtInit);
             if (arena_dev) {
                 // caller-owned device memory (a torch tensor, say): used, never freed
                 hipPointerAttribute_t at;
@@ -476,6 +506,54 @@ int cc_count(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_
         RunResult r;
         wait_colors(c, ctx->main.stream);
         run_dp_waves(ctx, ctx->main, rq, &r);
+        std::copy(r.counts.begin(), r.counts.end(), counts);
+        if (overflow) std::copy(r.overflow.begin(), r.overflow.end(), overflow);
+        ctx->last_sizes = r.node_sizes;
+    });
+}
+
+int cc_count_noalloc(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_decomp* d, uint32_t flags,
+                     uint64_t* counts, uint8_t* overflow) {
+    return guarded([&] {
+        check_run_args(ctx, g, c, d);
+        need(counts != nullptr, CC_EINVAL, "counts is NULL");
+        // every run holds at least its first leaf table: B x n entries of 16 bytes
+        const uint64_t least = uint64_t(c->B) * uint64_t(std::max(g->n, 1)) * 16u;
+        need(least <= CC_NOALLOC_SCRATCH_BYTES, CC_ERANGE,
+             "colourings x vertices = " + std::to_string(uint64_t(c->B) * uint64_t(g->n)) +
+                 " is too large for the " + std::to_string(CC_NOALLOC_SCRATCH_BYTES >> 20) +
+                 " MiB static scratch of cc_count_noalloc");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        void* base = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_scratch_mu);
+            base = g_scratch_ptr[ctx->device];  // looked up when the context was created
+            if (!base)
+                fail(CC_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                     hipGetErrorString(g_scratch_err[ctx->device]));
+        }
+        Arena& A = g_scratch_arena[ctx->device];
+        A.init((char*)base, CC_NOALLOC_SCRATCH_BYTES);  // the last call's contents are dead
+        RunRequest rq;
+        rq.g = g;
+        rq.colors = c->colors;
+        rq.B = c->B;
+        rq.k = c->k;
+        rq.dec = d;
+        rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
+        rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
+        rq.arena = &A;
+        rq.no_alloc = true;
+        RunResult r;
+        wait_colors(c, ctx->main.stream);
+        try {
+            run_dp(ctx, ctx->main, rq, &r);
+        } catch (const CcError& e) {
+            if (e.code == CC_ENOMEM)
+                fail(CC_ERANGE, "the DP tables exceed the " + std::to_string(CC_NOALLOC_SCRATCH_BYTES >> 20) +
+                                    " MiB static scratch of cc_count_noalloc (" + e.msg + ")");
+            throw;
+        }
         std::copy(r.counts.begin(), r.counts.end(), counts);
         if (overflow) std::copy(r.overflow.begin(), r.overflow.end(), overflow);
         ctx->last_sizes = r.node_sizes;

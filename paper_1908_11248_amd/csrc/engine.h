@@ -184,6 +184,8 @@ struct RunRequest {
     bool keep_tables = false;
     bool links = false;  // record the contributor index the row decoder needs (implies keep_tables)
     uint64_t max_entries = 0;  // fail with CC_ERANGE when a table would exceed this (0: no limit)
+    Arena* arena = nullptr;    // device memory of the run's tables and scratch (nullptr: the context's)
+    bool no_alloc = false;     // make no device or pinned-host allocation (fail with CC_ERANGE instead)
 };
 
 // contributor index of one step's table (enumeration)

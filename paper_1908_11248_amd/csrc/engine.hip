@@ -865,6 +865,10 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         launch_slot_root(rc.a, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv, csets, cwords,
                          part_base, sums, nsz, s);
     });
+    if (rq.no_alloc && res_words > X.lane.results_words)
+        fail(CC_ERANGE, "the run's results (" + std::to_string(res_words) +
+                            " words) exceed the preallocated read-back buffer of " +
+                            std::to_string(X.lane.results_words) + " words");
     uint64_t* host = X.lane.result_words(res_words);
     hip_check(hipMemcpyAsync(host, res, 8 * res_words, hipMemcpyDeviceToHost, s), "copy results");
     if (pv) {
@@ -927,7 +931,8 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         if (table_layout(b, g.n, B, k).bits() > 128)
             fail(CC_ERANGE, "packed key (colouring, bag images, colour set) exceeds 128 bits");
 
-    Exec X{lane, lane.stream, ctx->arena, rq.max_entries};
+    Arena& arena = rq.arena ? *rq.arena : ctx->arena;
+    Exec X{lane, lane.stream, arena, rq.max_entries};
     hipStream_t s = lane.stream;
     const size_t S = plan.steps.size();
     std::vector<DevTable> tab(S);
@@ -962,7 +967,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     std::vector<int> sz;
     if (!keep && !rq.sparse_only && slot_plan(plan, fuse, &sz)) {
         const uint64_t units = uint64_t(B) * uint64_t(g.n);
-        bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= ctx->arena.size() / 4;
+        bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= arena.size() / 4;
         // 32-bit block indices; slot offsets within one colouring's table below
         // 2^28 (they share a staged word with a colour)
         for (size_t i = 0; i < S && fits; i++)
