@@ -1,26 +1,39 @@
 """Benchmark of the colour-coding DP on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload serve|2|3|4|5]
 
-A step is one pass of the hot path over one batch: a fresh batch of random
-colourings of the resident host graph (computed on the device) and the DP
-over the pattern's nice tree decomposition for all of them (leaf,
-introduce, forget and join nodes, root counts copied to the host).  The
-graph upload and the decomposition are done once, before timing.
+Default (`serve`): the served stream of the largest configuration, Chung-Lu
+n = 10^6 (exponent 2.5, mean degree 10) resident on the device, pattern
+queries of 5-10 vertices (random trees and partial 3-trees, as admitted by the
+workload's rule), 32 colourings each.  A step is one batch of --per-step
+queries (each query is one pass of the whole hot path over its 32
+colourings: colouring, leaf / introduce / forget / join kernels, root
+counts back on the host).  W warm-up steps are served first; then the K
+timed steps are submitted at once to the server (continuous batching over
+concurrent lanes, admission by estimated table memory) and `value` is the
+served queries/s over that timed region.  Beside it, on the same queries:
+  plain      one query at a time on one stream (the paper's single runs);
+  poisson    Poisson arrivals at --load x the plain rate, served with
+             --inflight lanes and with one lane: queries/s, p50/p99 latency;
+  batched_w4 the 256-query batch of BA(200000, 5) (16 colourings per query):
+             plain vs cc_count_batch, DP table entries/s (--no-w4 skips it).
+Served, Poisson and batched counts are checked bit-equal to the plain ones.
 
-Prints one JSON line.  `value` is DP table entries per second: the sum over
-all tree-decomposition nodes and colourings of |D_x| (the paper's nonzero
-configurations) divided by the wall time of the steps.  The `roofline`
-object is measured live with HIP events on the library's stream; the
-`cpu_baseline` object times the CPU oracle on a bounded sample of the same
-workload on this host's cores.
+The `roofline` object names the kernel with the largest total time in the
+timed region and divides its algorithmic bytes per launch (table entries read
+and written x the per-entry size of the roofline model, plus graph bytes) by
+its average launch time, from HIP event pairs on the streams it ran on.  The
+`cpu_baseline` object times the CPU oracle on the same stream's colourings,
+on this host's cores, for a bounded time.
+
+--workload 2/3/4/5 run one standard workload alone (2 and 3: one pattern, a
+step is one batch of all its colourings).
 """
 import argparse
-import concurrent.futures as cf
-import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -46,10 +59,11 @@ def kernel_source_hash():
     return h()
 
 
-def traffic_for(kernel, workload, launches_algo_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; otherwise None."""
-    path = os.path.join(ROOT, "profiles", "traffic_w%d.json" % workload)
+def traffic_for(kernel, tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    profiles/traffic_<tag>.json, if it was taken on the current kernel
+    sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % tag)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -76,63 +90,311 @@ def copy_calibration(mib):
     del src, dst
 
 
-def cpu_baseline(workload, g, pat, k, budget_s=15.0):
-    """The oracle DP (single-threaded C) on a sample of colourings, one
-    colouring per host thread."""
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, share
+
+
+def roofline_from(prof, tag):
+    if not prof:
+        raise SystemExit("no kernel timings were recorded")
+    name, (launches, ms, byts) = max(prof.items(), key=lambda kv: kv[1][1])
+    achieved = (byts / launches) / ((ms / launches) * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(name, tag),
+            "avg_launch_ms": round(ms / launches, 4), "algo_bytes_per_launch": round(byts / launches),
+            "launches_timed": launches, "share_of_timed_kernel_ms": round(ms / max(1e-9, sum(v[1] for v in prof.values())), 3)}
+
+
+def kernel_table(prof):
+    return {k: {"launches": v[0], "ms": round(v[1], 3),
+                "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] else None}
+            for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]}
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle in worker processes, stopped after a time budget
+
+def cpu_baseline(jobs, unit_per_job, unit, what, budget_s=20.0, workers=8):
+    """Runs oracle jobs (workload index, pattern, k, colouring seed, b) in a
+    child process pool for about budget_s seconds; the child prints one line
+    per finished job and is killed when the budget runs out (a job of the
+    oracle cannot be interrupted, and the GPU side must not wait for it)."""
+    model, ncpu, share = host_cpu()
+    workers = max(1, min(workers, share))
+    spec = json.dumps({"jobs": jobs, "workers": workers})
+    t0 = time.perf_counter()
+    p = subprocess.Popen([sys.executable, "-u", os.path.abspath(__file__), "--oracle-worker"],
+                         stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                         text=True, start_new_session=True)
+    p.stdin.write(spec)
+    p.stdin.close()
+    done, entries = 0, 0
+    import selectors
+
+    sel = selectors.DefaultSelector()
+    sel.register(p.stdout, selectors.EVENT_READ)
+    last = t0
+    while time.perf_counter() - t0 < budget_s:
+        if not sel.select(timeout=max(0.05, budget_s - (time.perf_counter() - t0))):
+            continue
+        line = p.stdout.readline()
+        if not line:
+            break
+        done += 1
+        entries += int(line.split()[0])
+        last = time.perf_counter()
+    try:
+        os.killpg(p.pid, 9)
+    except OSError:
+        pass
+    p.wait()
+    dt = max(last - t0, 1e-9) if done else time.perf_counter() - t0
+    return {"value": (done * unit_per_job) / dt, "unit": unit, "cores": workers, "kind": "oracle",
+            "sample": "%s: %d oracle runs (one colouring each) finished in %.1f s on %d worker processes "
+                      "(host: %s, %d CPUs, %d in this process's share)" % (what, done, dt, workers, model, ncpu, share),
+            "entries_per_s": round(entries / dt, 1)}
+
+
+def oracle_worker():
+    """Child process of cpu_baseline."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    spec = json.loads(sys.stdin.read())
+    graphs = {}
+    for j in spec["jobs"]:
+        if j[0] not in graphs:
+            graphs[j[0]] = W.workload_graph(j[0])
+
+    def init():
+        pass
+
+    ctx = mp.get_context("fork")
+    global _GRAPHS
+    _GRAPHS = graphs
+    with cf.ProcessPoolExecutor(max_workers=spec["workers"], mp_context=ctx) as ex:
+        for fut in cf.as_completed([ex.submit(_oracle_job, j) for j in spec["jobs"]]):
+            print(fut.result(), flush=True)
+
+
+_GRAPHS = {}
+
+
+def _oracle_job(j):
     import oracle as O
 
-    w = W.workload(workload)
-    cores = min(os.cpu_count() or 1, 16)
-    td = None
-    done = 0
+    index, n_f, edges, k, seed, b = j
+    g = _GRAPHS[index]
+    pat = W.Pattern(n_f, [tuple(e) for e in edges])
+    r = O.dp_count(g, pat, k, O.color_array(seed, b, g.n, k), sizes=True)
+    return "%d" % int(r["sizes"].sum())
+
+
+# ---------------------------------------------------------------------------
+# the served stream (default)
+
+def bench_serve(args):
+    w = W.workload(5)
+    B = w.colorings
+    nq_w, nq_t = args.warmup * args.per_step, args.steps * args.per_step
+    log("workload 5", w.name, "warm-up queries", nq_w, "timed queries", nq_t)
+    t0 = time.perf_counter()
+    g = W.workload_graph(5)
+    log("graph n %d m %d (%.1f s)" % (g.n, g.m, time.perf_counter() - t0))
+    ctx = cc.Context(0)
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    sel, redraws = W.select_queries(5, nq_w + nq_t)
+    decs = [cc.build_decomposition(p.n, p.edges) for p, _ in sel]
+    warm, timed = list(range(nq_w)), list(range(nq_w, nq_w + nq_t))
+
+    def plain_one(q):
+        p, s = sel[q]
+        C = cc.color(ctx, G, p.n, W.colouring_seed(s), B)
+        c, o = cc.count(ctx, G, C, decs[q])
+        ent = int(ctx.last_table_sizes().sum())
+        C.close()
+        return c, o, ent
+
+    # plain: one query at a time on one stream
+    for q in warm[: max(2, args.per_step)]:
+        plain_one(q)
+    plain = {}
+    lat_plain = []
     entries = 0
     t0 = time.perf_counter()
-    nb = w.colorings
+    for i, q in enumerate(timed):
+        tq = time.perf_counter()
+        c, o, e = plain_one(q)
+        plain[q] = (c, o)
+        entries += e
+        lat_plain.append(time.perf_counter() - tq)
+        if i % 10 == 9:
+            log("plain", i + 1, "of", len(timed), "%.1f s" % (time.perf_counter() - t0))
+    t_plain = time.perf_counter() - t0
+    plain_qps = len(timed) / t_plain
+    log("plain %.2f q/s (%.1f s)" % (plain_qps, t_plain))
 
-    def one(b):
-        col = O.color_array(w.color_seed, b, g.n, k)
-        r = O.dp_count(g, pat, k, col, td=td, sizes=True)
-        return int(r["sizes"].sum())
+    def serve(queries, inflight, gaps=None, profile=False):
+        srv = cc.Server(ctx, G, max_inflight=inflight, max_heavy=0)
+        tickets = []
+        t_start = time.perf_counter()
+        due = t_start
+        for i, q in enumerate(queries):
+            if gaps is not None:
+                due += gaps[i]
+                while time.perf_counter() < due:
+                    time.sleep(min(0.0005, max(0.0, due - time.perf_counter())))
+            p, s = sel[q]
+            tickets.append((q, srv.submit(decs[q], p.n, W.colouring_seed(s), B)))
+        res = {}
+        for i, (q, t) in enumerate(tickets):
+            res[q] = srv.wait(t)
+            if i % 20 == 19:
+                log("served", i + 1, "of", len(tickets))
+        wall = time.perf_counter() - t_start
+        st = srv.stop()
+        return st, res, wall
 
-    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
-        b = 0
-        while b < nb and time.perf_counter() - t0 < budget_s:
-            batch = list(range(b, min(nb, b + cores)))
-            for e in ex.map(one, batch):
-                entries += e
-            done += len(batch)
-            b += len(batch)
+    def same(res):
+        return all(r[0] == 1 and np.array_equal(r[1], plain[q][0]) and np.array_equal(r[2], plain[q][1])
+                   for q, r in res.items())
+
+    # warm-up steps through the server, every kernel timed: the dominant
+    # kernel is named here and the timed steps record only it
+    ctx.profile_enable(True)
+    serve(warm, args.inflight)
+    prof_w = ctx.profile_read()
+    dom = max(prof_w.items(), key=lambda kv: kv[1][1])[0] if prof_w else None
+    ctx.profile_enable(True)
+    if dom:
+        ctx.profile_filter(dom, 1)
+    # timed: the K steps submitted at once (saturation)
+    st_sat, res_sat, wall_sat = serve(timed, args.inflight)
+    prof = ctx.profile_read()
+    ctx.profile_filter(None)
+    ctx.profile_enable(False)
+    if not same(res_sat):
+        raise SystemExit("served counts differ from plain counts")
+    served_qps = len(timed) / wall_sat
+    log("served at saturation %.2f q/s (%.1f s), plain %.2f q/s" % (served_qps, wall_sat, plain_qps))
+
+    # Poisson arrivals at a fraction of the plain rate: many lanes vs one
+    lam = args.load * plain_qps
+    rng = np.random.Generator(np.random.PCG64(w.seed ^ 0xA5))
+    gaps = rng.exponential(1.0 / lam, size=len(timed))
+    st_p, res_p, _ = serve(timed, args.inflight, gaps)
+    st_1, res_1, _ = serve(timed, 1, gaps)
+    if not (same(res_p) and same(res_1)):
+        raise SystemExit("served counts differ from plain counts")
+
+    def lat(st):
+        return {k: round(st[k], 2) for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms")} | {"qps": round(st["qps"], 3)}
+
+    fam = {}
+    for q in timed:
+        p = sel[q][0]
+        key = "%s%d" % (p.family, p.n)
+        fam[key] = fam.get(key, 0) + 1
+    out = {
+        "metric": METRIC, "value": served_qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall_sat / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": w.name, "queries_per_step": args.per_step, "timed_queries": len(timed),
+                   "warmup_queries": len(warm), "colorings_per_query": B, "n_G": g.n, "m_G": g.m,
+                   "families": fam, "redraws": {"%s%d" % k: v for k, v in sorted(redraws.items())},
+                   "admission": "longest induced cycle of F <= %d" % W.MAX_INDUCED_CYCLE[5]},
+        "served_saturation": {"qps": round(served_qps, 3), "p50_ms": round(st_sat["p50_ms"], 2),
+                              "p99_ms": round(st_sat["p99_ms"], 2), "inflight": args.inflight},
+        "plain": {"qps": round(plain_qps, 3), "p50_ms": round(1e3 * float(np.percentile(lat_plain, 50)), 2),
+                  "p99_ms": round(1e3 * float(np.percentile(lat_plain, 99)), 2),
+                  "entries_per_s": round(entries / t_plain, 1)},
+        "served_vs_plain": round(served_qps / plain_qps, 3),
+        "poisson": {"offered_qps": round(lam, 3), "load": args.load, "served": lat(st_p), "one_lane": lat(st_1),
+                    "p99_vs_one_lane": round(st_p["p99_ms"] / st_1["p99_ms"], 3) if st_1["p99_ms"] else None},
+        "entries_per_s_served": round(entries / wall_sat, 1),
+        "bit_identical_served_vs_plain": True,
+        "roofline": roofline_from(prof, "w5"),
+        "kernels_warmup": kernel_table(prof_w),
+    }
+    ctx.close()
+    if not args.no_w4:
+        out["batched_w4"] = bench_batched_w4(args, timed_steps=1)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        jobs = [[5, sel[q][0].n, sel[q][0].edges, sel[q][0].n, W.colouring_seed(sel[q][1]), b]
+                for q in timed for b in range(B)]
+        out["cpu_baseline"] = cpu_baseline(jobs, 1.0 / B, "queries/s", "the timed stream's colourings in order",
+                                           budget_s=args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# the batched uneven queries of workload 4
+
+def bench_batched_w4(args, timed_steps=None):
+    w = W.workload(4)
+    B = w.colorings
+    nq = args.queries or 256
+    g = W.workload_graph(4)
+    log("workload 4", w.name, "queries", nq)
+    ctx = cc.Context(0)
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    sel, redraws = W.select_queries(4, nq)
+    decs = [cc.build_decomposition(p.n, p.edges) for p, _ in sel]
+    cols = [cc.color(ctx, G, p.n, W.colouring_seed(s), B) for p, s in sel]
+    queries = list(zip(decs, cols))
+    cc.count(ctx, G, cols[0], decs[0])
+    t0 = time.perf_counter()
+    plain = []
+    for qi, (D, C) in enumerate(queries):
+        plain.append(cc.count(ctx, G, C, D))
+        if qi % 64 == 63:
+            log("plain query", qi + 1, "at %.1f s" % (time.perf_counter() - t0))
+    t_plain = time.perf_counter() - t0
+    ctx.set_batch_lanes(args.lanes)
+    steps = timed_steps or args.steps
+    ctx.profile_enable(True)
+    entries = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = cc.count_batch(ctx, G, queries)
+        entries += int(ctx.last_table_sizes().sum())
     dt = time.perf_counter() - t0
-    return {"value": entries / dt, "unit": "entries/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of %d colourings of workload %d (%s), one colouring per thread, %.1f s"
-                      % (done, nb, workload, w.name, dt)}
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    same = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(out, plain))
+    if not same:
+        raise SystemExit("batched counts differ from plain counts")
+    fam = {}
+    for p, _ in sel:
+        fam["%s%d" % (p.family, p.n)] = fam.get("%s%d" % (p.family, p.n), 0) + 1
+    res = {"workload": w.name, "queries": len(sel), "colorings_per_query": B,
+           "families": fam, "redraws": {"%s%d" % k: v for k, v in sorted(redraws.items())},
+           "entries_per_s": round(entries / dt, 1), "entries_per_pass": entries // steps,
+           "batched_queries_per_s": round(len(sel) * steps / dt, 3), "plain_queries_per_s": round(len(sel) / t_plain, 3),
+           "batched_vs_plain": round(t_plain * steps / dt, 3), "bit_identical_batched_vs_plain": True,
+           "lanes": args.lanes, "roofline": roofline_from(prof, "w4"), "kernels": kernel_table(prof)}
+    ctx.close()
+    log("workload 4: batched %.2f q/s, plain %.2f q/s" % (res["batched_queries_per_s"], res["plain_queries_per_s"]))
+    return res
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
-    ap.add_argument("--queries", type=int, default=0, help="queries of workloads 4/5 (0: 256 / 120)")
-    ap.add_argument("--budget", type=float, default=3e7, help="DP entries per table and colouring (workloads 4/5)")
-    ap.add_argument("--load", type=float, default=0.7, help="arrival rate / plain throughput (workload 5)")
-    ap.add_argument("--inflight", type=int, default=4, help="concurrent queries while serving (workload 5)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--plain", type=int, default=4, help="colourings timed one at a time for the plain rate")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="first run one plain device copy of MIB mebibytes (reference kernel for counter scaling)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU (one MI355X); --gpus %d is not supported: colourings and "
-              "queries are independent, so more GPUs would each take their own share" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
+# ---------------------------------------------------------------------------
+# one pattern, all colourings per step (workloads 2 and 3)
 
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-    if args.workload in (4, 5):
-        return bench_queries(args)
+def bench_single(args):
     w = W.workload(args.workload)
     log("workload", w.index, w.name)
     g = W.workload_graph(args.workload)
@@ -147,19 +409,11 @@ def main():
         C.close()
         return counts
 
-    # warm-up with every kernel timed: it names the dominant kernel and gives
-    # the per-kernel table; the timed steps record events around that kernel
-    # only, so the other launches run without event overhead
     ctx.profile_enable(True)
-    for i in range(max(args.warmup, 1)):  # at least one step names the dominant kernel
+    for i in range(max(args.warmup, 1)):
         step(i)
-        log("warmup", i, "done")
     prof_all = ctx.profile_read()
-    if not prof_all:
-        raise SystemExit("no kernel timings were recorded")
     dom_name = max(prof_all.items(), key=lambda kv: kv[1][1])[0]
-    # one launch in `every`, with `every` coprime to the launches per step so
-    # that the sample visits every launch site of the step
     per_step = max(1, prof_all[dom_name][0] // max(args.warmup, 1))
     every = 4
     while math.gcd(every, per_step) != 1:
@@ -175,210 +429,83 @@ def main():
     prof = ctx.profile_read()
     ctx.profile_filter(None)
     ctx.profile_enable(False)
-    log("timed", args.steps, "steps in %.3f s" % dt)
-
-    # plain path: the same colourings one at a time (the paper's single run)
+    # plain: the same colourings one at a time (the paper's single run),
+    # checked equal to one batched launch of them
     plain_rate = None
     if args.plain > 0:
-        cols = [cc.color(ctx, G, w.k, w.color_seed + 7 + b, 1) for b in range(args.plain)]
+        Cb = cc.color(ctx, G, w.k, w.color_seed, args.plain)
+        batched, _ = cc.count(ctx, G, Cb, D)
+        cols = [cc.color_explicit(ctx, G, w.k, Cb.download(b, g.n)) for b in range(args.plain)]
         cc.count(ctx, G, cols[0], D)
         t1 = time.perf_counter()
-        for C in cols:
-            cc.count(ctx, G, C, D)
+        singles = [int(cc.count(ctx, G, C, D)[0][0]) for C in cols]
         plain_rate = args.plain / (time.perf_counter() - t1)
-
-    if not prof:
-        raise SystemExit("no kernel timings were recorded")
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
-    name, (launches, ms, byts) = dom
-    achieved = (byts / launches) / ((ms / launches) * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for(name, args.workload, byts / launches),
-                "avg_launch_ms": round(ms / launches, 4), "algo_bytes_per_launch": round(byts / launches)}
-    kernels = {k: {"launches": v[0], "ms": round(v[1], 3), "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] else None}
-               for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1][1])}
-    ms_per_step = dt / args.steps * 1e3
+        if singles != [int(x) for x in batched]:
+            raise SystemExit("plain counts differ from batched counts")
     out = {
-        "metric": METRIC,
-        "value": entries / dt,
-        "unit": "entries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
+        "metric": METRIC, "value": entries / dt, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": w.name, "colorings_per_step": w.colorings, "k": w.k, "n_G": g.n, "m_G": g.m,
                    "pattern": pat.name, "pattern_edges": pat.edges, "width": D.width},
         "colorings_per_s": round(w.colorings * args.steps / dt, 2),
         "plain_colorings_per_s": round(plain_rate, 2) if plain_rate else None,
         "entries_per_step": entries // args.steps,
-        "roofline": roofline,
-        "kernels_warmup": kernels,
+        "roofline": roofline_from(prof, "w%d" % args.workload),
+        "kernels_warmup": kernel_table(prof_all),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.workload, g, pat, w.k)
+        jobs = [[args.workload, pat.n, pat.edges, w.k, w.color_seed, b] for b in range(w.colorings)]
+        r = cpu_baseline(jobs, 1.0, "colourings/s", "workload %d colourings" % args.workload, budget_s=args.cpu_budget)
+        r["value"] = r.pop("entries_per_s")
+        r["unit"] = "entries/s"
+        out["cpu_baseline"] = r
     print(json.dumps(out), flush=True)
     ctx.close()
 
 
-def bench_queries(args):
-    """Workloads 4 and 5: streams of uneven pattern queries over a resident
-    host graph.  Queries over the per-colouring table budget are redrawn
-    (workloads.select_queries); the redraws are reported."""
-    w = W.workload(args.workload)
-    nq = args.queries or (256 if args.workload == 4 else 120)
-    log("workload", w.index, w.name, "queries", nq)
-    g = W.workload_graph(args.workload)
-    log("graph", g.n, g.m)
-    ctx = cc.Context(0, arena_bytes=0)
-    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
-    B = w.colorings
-    budget1 = int(args.budget)
-
-    def fits(p, s):
-        log("select", p.name, hex(s))
-        D = cc.build_decomposition(p.n, p.edges)
-        C = cc.color(ctx, G, p.n, W.colouring_seed(s), 1)
-        ctx.set_table_budget(budget1)
-        try:
-            cc.count(ctx, G, C, D)
-            return True
-        except cc.CcError as e:
-            if e.code != cc.CC_ERANGE:
-                raise
-            return False
-        finally:
-            ctx.set_table_budget(0)
-            C.close()
-
-    t0 = time.perf_counter()
-    sel, redraws = W.select_queries(args.workload, nq, fits)
-    t_sel = time.perf_counter() - t0
-    log("selected %d queries in %.1f s, %d redraws" % (len(sel), t_sel, sum(redraws.values())))
-    ctx.set_table_budget(budget1 * B)
-    decs = [cc.build_decomposition(p.n, p.edges) for p, _ in sel]
-    fam = {}
-    for p, _ in sel:
-        fam["%s%d" % (p.family, p.n)] = fam.get("%s%d" % (p.family, p.n), 0) + 1
-
-    if args.workload == 4:
-        cols = [cc.color(ctx, G, p.n, W.colouring_seed(s), B) for p, s in sel]
-        queries = list(zip(decs, cols))
-        # plain: one query at a time on one stream (the paper's sequential runs)
-        t0 = time.perf_counter()
-        plain = []
-        for qi, (D, C) in enumerate(queries):
-            plain.append(cc.count(ctx, G, C, D))
-            if qi % 16 == 15:
-                log("plain query", qi + 1, "at %.1f s" % (time.perf_counter() - t0))
-        t_plain = time.perf_counter() - t0
-        log("plain %.2f s" % t_plain)
-        lanes = cc.tune_batch(ctx, G, queries[: min(32, len(queries))])
-        log("tuned lanes", lanes)
-        for i in range(args.warmup):
-            cc.count_batch(ctx, G, queries)
-        ctx.profile_enable(True)
-        t0 = time.perf_counter()
-        entries = 0
-        for i in range(args.steps):
-            out = cc.count_batch(ctx, G, queries)
-            entries += int(ctx.last_table_sizes().sum())
-        dt = time.perf_counter() - t0
-        prof = ctx.profile_read()
-        ctx.profile_enable(False)
-        same = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(out, plain))
-        if not same:
-            raise SystemExit("batched counts differ from plain counts")
-        extra = {"plain_queries_per_s": round(len(sel) / t_plain, 3),
-                 "batched_queries_per_s": round(len(sel) * args.steps / dt, 3),
-                 "batched_vs_plain": round((len(sel) * args.steps / dt) / (len(sel) / t_plain), 3),
-                 "bit_identical_batched_vs_plain": same, "lanes": lanes}
-        value = entries / dt
-        ms_per_step = dt / args.steps * 1e3
-    else:
-        # plain rate first (one at a time), then Poisson arrivals at a fixed
-        # fraction of it, served with `inflight` lanes and with one lane
-        t0 = time.perf_counter()
-        plain_counts = []
-        for qi, ((p, s), D) in enumerate(zip(sel, decs)):
-            C = cc.color(ctx, G, p.n, W.colouring_seed(s), B)
-            tq = time.perf_counter()
-            plain_counts.append(cc.count(ctx, G, C, D)[0])
-            log("plain query", qi, p.name, "%.3f s" % (time.perf_counter() - tq))
-            C.close()
-        t_plain = time.perf_counter() - t0
-        plain_qps = len(sel) / t_plain
-        lam = args.load * plain_qps
-        rng = np.random.Generator(np.random.PCG64(w.seed ^ 0xA5))
-        gaps = rng.exponential(1.0 / lam, size=len(sel))
-        log("plain %.2f q/s; arrivals at %.2f q/s" % (plain_qps, lam))
-
-        def serve(inflight):
-            srv = cc.Server(ctx, G, max_inflight=inflight, max_entries=budget1 * B, max_heavy=1)
-            tickets = []
-            t_start = time.perf_counter()
-            due = t_start
-            for i, ((p, s), D) in enumerate(zip(sel, decs)):
-                due += gaps[i]
-                while time.perf_counter() < due:
-                    time.sleep(min(0.0005, max(0.0, due - time.perf_counter())))
-                tickets.append(srv.submit(D, p.n, W.colouring_seed(s), B))
-            log("submitted", len(tickets), "queries with", inflight, "lanes")
-            res = []
-            for i, t in enumerate(tickets):
-                res.append(srv.wait(t))
-                if i % 10 == 9:
-                    log("served", i + 1)
-            st = srv.stop()
-            ok = all(r[0] == 1 for r in res) and all(np.array_equal(r[1], c) for r, c in zip(res, plain_counts))
-            return st, ok
-
-        ctx.profile_enable(True)
-        st_b, ok_b = serve(args.inflight)
-        prof = ctx.profile_read()
-        ctx.profile_enable(False)
-        log("served", st_b)
-        st_p, ok_p = serve(1)
-        log("one lane", st_p)
-        if not (ok_b and ok_p):
-            raise SystemExit("served counts differ from plain counts")
-        extra = {"plain_queries_per_s": round(plain_qps, 3), "arrival_rate_qps": round(lam, 3),
-                 "served": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st_b.items()},
-                 "served_one_lane": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st_p.items()},
-                 "p50_ms": round(st_b["p50_ms"], 2), "p99_ms": round(st_b["p99_ms"], 2),
-                 "p99_vs_one_lane": round(st_b["p99_ms"] / st_p["p99_ms"], 3) if st_p["p99_ms"] else None,
-                 "bit_identical_served_vs_plain": True, "inflight": args.inflight, "max_heavy": 1}
-        value = st_b["qps"]
-        dt = st_b["wall_s"]
-        ms_per_step = dt * 1e3
-    if not prof:
-        raise SystemExit("no kernel timings were recorded")
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
-    name, (launches, ms, byts) = dom
-    achieved = (byts / launches) / ((ms / launches) * 1e-3) / 1e9
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "entries/s" if args.workload == 4 else "queries/s",
-        "n_gpus": 1, "steps": args.steps if args.workload == 4 else 1, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": w.name, "queries": len(sel), "colorings_per_query": B, "n_G": g.n, "m_G": g.m,
-                   "budget_entries_per_table_per_coloring": budget1, "families": fam,
-                   "redraws": {"%s%d" % k: v for k, v in sorted(redraws.items())}, "selection_s": round(t_sel, 1)},
-        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_launch_ms": round(ms / launches, 4), "algo_bytes_per_launch": round(byts / launches)},
-    }
-    out.update(extra)
-    print(json.dumps(out), flush=True)
-    ctx.close()
+def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--oracle-worker":
+        return oracle_worker()
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="serve", choices=["serve", "2", "3", "4", "5"])
+    ap.add_argument("--per-step", type=int, default=4, help="served queries per step")
+    ap.add_argument("--queries", type=int, default=0, help="queries of workload 4 (0: 256)")
+    ap.add_argument("--load", type=float, default=0.7, help="Poisson arrival rate / plain throughput")
+    ap.add_argument("--inflight", type=int, default=4, help="concurrent queries while serving")
+    ap.add_argument("--lanes", type=int, default=4, help="concurrent streams of the workload-4 batch")
+    ap.add_argument("--no-w4", action="store_true", help="skip the workload-4 batch in the default run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    ap.add_argument("--plain", type=int, default=4, help="colourings timed one at a time (workloads 2 and 3)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB mebibytes (reference kernel for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU (one MI355X); --gpus %d is not supported: colourings and "
+              "queries are independent, so more GPUs would each take their own share" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+    if args.workload in ("serve", "5"):
+        if args.workload == "5":
+            args.no_w4 = True
+        return bench_serve(args)
+    if args.workload == "4":
+        res = bench_batched_w4(args)
+        out = {"metric": METRIC, "value": res["entries_per_s"], "unit": "entries/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "u64", "data": "synthetic", "config": {"workload": res["workload"]}, "batched_w4": res,
+               "roofline": res["roofline"]}
+        print(json.dumps(out), flush=True)
+        return
+    args.workload = int(args.workload)
+    return bench_single(args)
 
 
 if __name__ == "__main__":

@@ -142,6 +142,37 @@ void cc_decomp_free(cc_decomp *d);
 int cc_count(cc_context *ctx, const cc_graph *g, const cc_coloring *c, const cc_decomp *d,
              uint32_t flags, uint64_t *counts, uint8_t *overflow);
 
+/* cc_count restricted to the mappings with Phi(0) in [lo, hi) (0 <= lo <=
+ * hi <= n_G).  Counts over disjoint ranges add up (mod 2^64) to cc_count's:
+ * this is the unit of the anchor-range chunking below and of a split of one
+ * colouring across devices.  Table sizes of nodes whose bag holds pattern
+ * vertex 0 cover the range only; other nodes' tables are whole. */
+int cc_count_range(cc_context *ctx, const cc_graph *g, const cc_coloring *c, const cc_decomp *d,
+                   uint32_t flags, int32_t lo, int32_t hi, uint64_t *counts, uint8_t *overflow);
+
+/* Anchor-range chunking.  When a table of cc_count / cc_count_range /
+ * cc_count_batch / the server exceeds the per-table budget or the arena
+ * (arenas of 256 MiB or more), the run is repeated in waves of half the
+ * colourings, and a single colouring in two halves of the image range of
+ * pattern vertex 0 (pattern vertex 0 stays in every bag above its
+ * introduction, so each table of those nodes splits into disjoint parts),
+ * recursively, at most 64 ranges per colouring.  Counts and flags equal the
+ * unsplit run's (a carry in the final sum sets the flag).  This returns the
+ * number of (colouring-wave, range) runs of the last single-query count on
+ * ctx (1: not split). */
+int32_t cc_last_chunk_count(const cc_context *ctx);
+
+/* Estimated device memory of a count of pattern d with k colours and
+ * num_colorings colourings on graph g: *peak_bytes the peak arena footprint,
+ * *entries (optional) the sum of |D_x| over nodes and colourings.  A model
+ * from the plan and g's degree statistics (mean neighbour degree, sampled
+ * transitivity): introduce multiplies by the candidates of a bag neighbour's
+ * adjacency list, the chance that the new colour is unused and that further
+ * bag neighbours are adjacent; forget and join are capped by the number of
+ * keys the bag can hold.  The serving loop admits queries by it.  Host only. */
+int cc_estimate_memory(const cc_graph *g, const cc_decomp *d, int32_t k, int32_t num_colorings,
+                       double *peak_bytes, double *entries);
+
 /* cc_count for callers that cannot allocate memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): same
  * arguments, results and flags as cc_count, but the run makes no device or
@@ -226,17 +257,21 @@ int cc_tune_batch(cc_context *ctx, const cc_graph *g, int32_t nq, const cc_query
 int cc_set_table_budget(cc_context *ctx, uint64_t max_entries);
 
 /* ---------------------------------------------------------------------- */
-/* Serving: a request loop over a resident graph.  Submitted queries wait
- * in FIFO order and are admitted while a worker lane is free and their
- * estimated arena footprint fits the memory budget (the measured peak of an
- * earlier query with the same decomposition and colouring count, else an
- * equal share of the budget); admitted queries run concurrently on their own
- * streams.  With max_heavy > 0, at most that many queries whose
- * decomposition has width >= 2 (the heavy, sorted-list path) are in flight
- * at once: a later query waits behind a heavy one only if it is heavy too,
- * so short queries overlap a long one instead of sharing the device with
- * other long ones.  A query that runs out of memory is re-queued to run
- * alone.  Latency is measured from submission to completion. */
+/* Serving: a request loop over a resident graph (continuous batching).
+ * Submitted queries wait in FIFO order and are admitted while a worker lane
+ * is free and their estimated arena footprint fits the free part of the
+ * memory budget.  The estimate is cc_estimate_memory's model of the query's
+ * plan on the resident graph, scaled by a running correction (the geometric
+ * mean of measured peak / model over completed queries, within [0.5, 4]);
+ * a decomposition and colouring count seen before uses its measured peak
+ * (+1/8) instead.  Admitted queries run concurrently on their own streams,
+ * so their kernels overlap on the device; a query whose estimate exceeds the
+ * budget still runs (alone when nothing else fits) and splits itself into
+ * waves and anchor ranges when its tables do not fit.  With max_heavy > 0,
+ * at most that many queries whose decomposition has width >= 2 are in
+ * flight at once (0: no such limit).  A query that runs out of memory while
+ * others hold it is re-queued to run alone.  Latency is measured from
+ * submission to completion. */
 typedef struct {
     int32_t max_inflight;  /* worker lanes (concurrent queries), >= 1 */
     size_t mem_budget;     /* bytes of the arena the server may use (0: all) */

@@ -15,6 +15,7 @@ Valla, arXiv 1908.11248) through ctypes:
 * ``treewidth``        -- exact treewidth (Sec. 3)
 * ``validate_td``      -- nice tree decomposition checker (Sec. 1.2)
 * ``dp_count``         -- the DP over the nice TD with counts (Sec. 3.1)
+* ``dp_count_range``   -- the same, for mappings with Phi(0) in a range
 * ``dp_enumerate``     -- reconstruction R(x, M) (Sec. 4)
 
 Every function here is pinned by tests in ``tests/test_oracle_*.py`` against
@@ -55,6 +56,8 @@ def _load():
         lib.orc_validate_td.argtypes = [i32, i32, P, P, i32]
         lib.orc_count.restype = ctypes.c_int
         lib.orc_count.argtypes = [i32, P, P, i32, i32, P, i32, P, P, i32, i32, P, P, P, P]
+        lib.orc_count_range.restype = ctypes.c_int
+        lib.orc_count_range.argtypes = [i32, P, P, i32, i32, P, i32, P, P, i32, i32, i32, i32, P, P, P]
         lib.orc_enumerate.restype = ctypes.c_int
         lib.orc_enumerate.argtypes = [i32, P, P, i32, i32, P, i32, P, P, i32, i32, u64, P, P, P]
         _lib = lib
@@ -170,6 +173,27 @@ def dp_count(g, pat, k, colors, td=None, degmask=True, per_root_vertex=False, si
     out = {"count": int(cnt[0]), "overflow": bool(ovf[0])}
     if prv is not None:
         out["per_root_vertex"] = prv[:n]
+    if sz is not None:
+        out["sizes"] = sz
+    return out
+
+
+def dp_count_range(g, pat, k, colors, lo, hi, td=None, degmask=True, sizes=False):
+    """dp_count restricted to the mappings with Phi(0) in [lo, hi)."""
+    n, rp, col = _graph(g)
+    nF, mF, e = _pattern(pat)
+    if td is None:
+        td, _ = build_td(pat)
+    td = np.ascontiguousarray(td, dtype=np.int32)
+    colors = np.ascontiguousarray(colors, dtype=np.uint8)
+    cnt = np.zeros(1, dtype=np.uint64)
+    ovf = np.zeros(1, dtype=np.uint8)
+    sz = np.zeros(int(td[0]), dtype=np.int64) if sizes else None
+    rc = _load().orc_count_range(n, _p(rp), _p(col), nF, mF, _p(e), k, _p(colors), _p(td), int(td.size),
+                                 1 if degmask else 0, int(lo), int(hi), _p(cnt), _p(ovf),
+                                 _p(sz) if sz is not None else None)
+    _check(rc, "dp_count_range")
+    out = {"count": int(cnt[0]), "overflow": bool(ovf[0])}
     if sz is not None:
         out["sizes"] = sz
     return out

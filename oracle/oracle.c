@@ -646,10 +646,15 @@ typedef struct {
     const uint8_t *col;
     int degmask;
     int ovf;
+    int32_t lo0, hi0; /* images allowed for pattern vertex 0: [lo0, hi0) */
 } dpctx_t;
 
-/* deg_G(v) >= deg_F(u) (Sec. 3.2 "Masking Unprofitable Mappings") */
+/* deg_G(v) >= deg_F(u) (Sec. 3.2 "Masking Unprofitable Mappings"), and for
+ * pattern vertex 0 an image inside the requested range.  Restricting the
+ * image of one pattern vertex keeps exactly the mappings with Phi(0) in the
+ * range, so counts over disjoint ranges add up to the full count. */
 static int deg_ok(const dpctx_t *c, int u, int32_t v) {
+    if (u == 0 && (v < c->lo0 || v >= c->hi0)) return 0;
     return !c->degmask || gdeg(c->g, v) >= popc(c->F->adj[u]);
 }
 
@@ -796,10 +801,35 @@ static int check_inputs(int32_t n, int32_t nF, int32_t k, const uint8_t *colors)
  * per_root_vertex (optional, length n): for the node just below the root
  * (bag {r0}), the sum of its entries grouped by the image of r0.
  * sizes (optional, length N): |D_x| per node. */
+static int count_in_range(int32_t n, const int64_t *rp, const int32_t *colidx, int32_t nF,
+                          int32_t mF, const int32_t *edges, int32_t k, const uint8_t *colors,
+                          const int32_t *td, int32_t td_len, int32_t degmask, int32_t lo0,
+                          int32_t hi0, uint64_t *count, uint8_t *overflow,
+                          uint64_t *per_root_vertex, int64_t *sizes);
+
 int orc_count(int32_t n, const int64_t *rp, const int32_t *colidx, int32_t nF, int32_t mF,
               const int32_t *edges, int32_t k, const uint8_t *colors, const int32_t *td,
               int32_t td_len, int32_t degmask, uint64_t *count, uint8_t *overflow,
               uint64_t *per_root_vertex, int64_t *sizes) {
+    return count_in_range(n, rp, colidx, nF, mF, edges, k, colors, td, td_len, degmask, 0, n,
+                          count, overflow, per_root_vertex, sizes);
+}
+
+/* The same count restricted to the mappings with Phi(0) in [lo0, hi0). */
+int orc_count_range(int32_t n, const int64_t *rp, const int32_t *colidx, int32_t nF, int32_t mF,
+                    const int32_t *edges, int32_t k, const uint8_t *colors, const int32_t *td,
+                    int32_t td_len, int32_t degmask, int32_t lo0, int32_t hi0, uint64_t *count,
+                    uint8_t *overflow, int64_t *sizes) {
+    if (lo0 < 0 || hi0 < lo0 || hi0 > n) return ORC_EINVAL;
+    return count_in_range(n, rp, colidx, nF, mF, edges, k, colors, td, td_len, degmask, lo0, hi0,
+                          count, overflow, NULL, sizes);
+}
+
+static int count_in_range(int32_t n, const int64_t *rp, const int32_t *colidx, int32_t nF,
+                          int32_t mF, const int32_t *edges, int32_t k, const uint8_t *colors,
+                          const int32_t *td, int32_t td_len, int32_t degmask, int32_t lo0,
+                          int32_t hi0, uint64_t *count, uint8_t *overflow,
+                          uint64_t *per_root_vertex, int64_t *sizes) {
     int rc = check_inputs(n, nF, k, colors);
     if (rc) return rc;
     graph_t g = {n, rp, colidx};
@@ -809,7 +839,7 @@ int orc_count(int32_t n, const int64_t *rp, const int32_t *colidx, int32_t nF, i
     int N = td[0];
     table_t *tabs = calloc(N, sizeof(table_t));
     if (!tabs) return ORC_ENOMEM;
-    dpctx_t c = {&g, &F, colors, degmask, 0};
+    dpctx_t c = {&g, &F, colors, degmask, 0, lo0, hi0};
     /* keep the root's child when the per-vertex split is wanted */
     rc = dp_run(&c, td, tabs, per_root_vertex != NULL, sizes);
     if (rc == ORC_OK) {
@@ -1167,7 +1197,7 @@ int orc_enumerate(int32_t n, const int64_t *rp, const int32_t *colidx, int32_t n
     int N = td[0];
     table_t *tabs = calloc(N, sizeof(table_t));
     if (!tabs) return ORC_ENOMEM;
-    dpctx_t c = {&g, &F, colors, degmask, 0};
+    dpctx_t c = {&g, &F, colors, degmask, 0, 0, n};
     rc = dp_run(&c, td, tabs, 1, NULL);
     mset_t M = {0};
     llist_t L = {0};

@@ -36,7 +36,7 @@ EXPORTS = [
     "cc_profile_enable", "cc_profile_filter", "cc_profile_read", "cc_decomp_describe",
     "cc_set_batch_lanes", "cc_tune_batch", "cc_set_table_budget",
     "cc_server_start", "cc_server_submit", "cc_server_poll", "cc_server_wait", "cc_server_stop",
-    "cc_count_noalloc",
+    "cc_count_noalloc", "cc_count_range", "cc_last_chunk_count", "cc_estimate_memory",
 ]
 
 
@@ -88,6 +88,9 @@ def lib():
             "cc_decomp_free": (None, [P]),
             "cc_count": (ctypes.c_int, [P, P, P, P, U32, P, P]),
             "cc_count_noalloc": (ctypes.c_int, [P, P, P, P, U32, P, P]),
+            "cc_count_range": (ctypes.c_int, [P, P, P, P, U32, I32, I32, P, P]),
+            "cc_last_chunk_count": (I32, [P]),
+            "cc_estimate_memory": (ctypes.c_int, [P, P, I32, I32, P, P]),
             "cc_count_by_vertex": (ctypes.c_int, [P, P, P, I32, P, U32, P, P, P]),
             "cc_enumerate": (ctypes.c_int, [P, P, P, I32, P, U64, P, P, P]),
             "cc_last_table_sizes": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
@@ -262,6 +265,9 @@ class Context(_Handle):
     def set_table_budget(self, max_entries: int):
         _check(lib().cc_set_table_budget(self.ptr, max_entries))
 
+    def last_chunk_count(self) -> int:
+        return int(lib().cc_last_chunk_count(self.ptr))
+
     def last_table_sizes(self) -> np.ndarray:
         n = ctypes.c_size_t(0)
         buf = np.zeros(4096, dtype=np.int64)
@@ -320,6 +326,22 @@ def count(ctx: Context, g: Graph, c: Coloring, d: Decomp, flags: int = 0):
     counts = np.zeros(c.num, dtype=np.uint64)
     ovf = np.zeros(c.num, dtype=np.uint8)
     _check(lib().cc_count(ctx.ptr, g.ptr, c.ptr, d.ptr, flags, _p(counts), _p(ovf)))
+    return counts, ovf.astype(bool)
+
+
+def estimate_memory(g: Graph, d: Decomp, k: int, num_colorings: int):
+    """(estimated peak arena bytes, estimated sum of |D_x|) of a count."""
+    pk = ctypes.c_double(0)
+    en = ctypes.c_double(0)
+    _check(lib().cc_estimate_memory(g.ptr, d.ptr, k, num_colorings, ctypes.byref(pk), ctypes.byref(en)))
+    return pk.value, en.value
+
+
+def count_range(ctx: Context, g: Graph, c: Coloring, d: Decomp, lo: int, hi: int, flags: int = 0):
+    """Counts of the mappings with Phi(0) in [lo, hi): (counts, overflow)."""
+    counts = np.zeros(c.num, dtype=np.uint64)
+    ovf = np.zeros(c.num, dtype=np.uint8)
+    _check(lib().cc_count_range(ctx.ptr, g.ptr, c.ptr, d.ptr, flags, int(lo), int(hi), _p(counts), _p(ovf)))
     return counts, ovf.astype(bool)
 
 

@@ -227,9 +227,11 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
         g->ctx = ctx;
         g->n = n;
         g->m2 = m2;
+        g->host_rp = rp;
         g->sorted_deg.resize(n);
         for (int32_t v = 0; v < n; v++) g->sorted_deg[v] = rp[v + 1] - rp[v];
         std::sort(g->sorted_deg.begin(), g->sorted_deg.end());
+        graph_statistics(g, rp, cl);
         try {
             hip_check(hipMalloc(&g->rp, 8 * size_t(n + 1)), "hipMalloc");
             hip_check(hipMalloc(&g->col, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
@@ -509,6 +511,48 @@ int cc_count(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_
         std::copy(r.counts.begin(), r.counts.end(), counts);
         if (overflow) std::copy(r.overflow.begin(), r.overflow.end(), overflow);
         ctx->last_sizes = r.node_sizes;
+        ctx->last_chunks = r.chunks;
+    });
+}
+
+int cc_count_range(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_decomp* d, uint32_t flags,
+                   int32_t lo, int32_t hi, uint64_t* counts, uint8_t* overflow) {
+    return guarded([&] {
+        check_run_args(ctx, g, c, d);
+        need(counts != nullptr, CC_EINVAL, "counts is NULL");
+        need(lo >= 0 && lo <= hi && hi <= g->n, CC_EINVAL, "need 0 <= lo <= hi <= n_G");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        RunRequest rq;
+        rq.g = g;
+        rq.colors = c->colors;
+        rq.B = c->B;
+        rq.k = c->k;
+        rq.dec = d;
+        rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
+        rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
+        rq.max_entries = ctx->max_entries;
+        rq.anchor_lo = lo;
+        rq.anchor_hi = hi;
+        RunResult r;
+        wait_colors(c, ctx->main.stream);
+        run_dp_waves(ctx, ctx->main, rq, &r);
+        std::copy(r.counts.begin(), r.counts.end(), counts);
+        if (overflow) std::copy(r.overflow.begin(), r.overflow.end(), overflow);
+        ctx->last_sizes = r.node_sizes;
+        ctx->last_chunks = r.chunks;
+    });
+}
+
+int32_t cc_last_chunk_count(const cc_context* ctx) { return ctx ? ctx->last_chunks : -1; }
+
+int cc_estimate_memory(const cc_graph* g, const cc_decomp* d, int32_t k, int32_t num_colorings, double* peak_bytes,
+                       double* entries) {
+    return guarded([&] {
+        need(g && d && peak_bytes && num_colorings >= 1, CC_EINVAL, "bad arguments");
+        need(k >= d->d.n && k <= kMaxColours, CC_ERANGE, "colours k must satisfy n_F <= k <= " + std::to_string(kMaxColours));
+        MemEstimate e = estimate_memory(g, d, k, num_colorings);
+        *peak_bytes = e.peak_bytes;
+        if (entries) *entries = e.total_entries;
     });
 }
 

@@ -47,6 +47,11 @@ __device__ __forceinline__ K shr(K key, int sh) {
 }
 
 __device__ __forceinline__ int64_t gdeg(const DevGraph& g, uint32_t v) { return g.rp[v + 1] - g.rp[v]; }
+// v passes the degree mask of the introduced vertex (deg_G(v) >= deg_F(u),
+// Sec. 3.2) and lies in the step's image range
+__device__ __forceinline__ bool intro_ok(const DevGraph& g, uint32_t v, int degF) {
+    return gdeg(g, v) >= degF && int32_t(v) >= g.vlo && int32_t(v) < g.vhi;
+}
 
 // {a, b} in E(G): a probe of the edge set (usually one cell)
 __device__ __forceinline__ bool has_edge(const DevGraph& g, uint32_t a, uint32_t b) {

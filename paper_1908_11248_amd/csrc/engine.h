@@ -69,7 +69,10 @@ class Profiler {
     uint32_t every = 1;   // of those, one launch in `every`
     uint32_t seen_ = 0;
     void reset();
-    void begin(hipStream_t s, const char* name, double bytes);
+    // returns a handle of the recorded launch (-1: not recorded) whose bytes
+    // set_bytes may still change before resolve()
+    int begin(hipStream_t s, const char* name, double bytes);
+    void set_bytes(int handle, double bytes);
     void end(hipStream_t s);
     void resolve();  // call after the stream has synchronised
     const std::vector<KernelStat>& stats() const { return stats_; }
@@ -131,6 +134,7 @@ struct cc_context {
     ccg::Lane main;  // the lane of the single-query calls
     std::vector<std::unique_ptr<ccg::Lane>> workers;  // lanes of batched and served queries
     std::vector<int64_t> last_sizes;
+    int32_t last_chunks = 1;  // anchor-range chunks of the last single-query count
     uint64_t max_entries = 0;  // per-table budget (0: none)
     int batch_lanes = 0;       // lanes for cc_count_batch (0: tuned on first use)
     uint16_t* slot_tables = nullptr;  // device: rank[2048] then unrank[2048] (slots.hip)
@@ -152,8 +156,14 @@ struct cc_graph {
     uint64_t* ehash = nullptr;  // edge set (kernels.h edge_key / edge_cell)
     uint64_t ehmask = 0;
     std::vector<int64_t> sorted_deg;  // host copy, ascending
+    std::vector<int64_t> host_rp;     // host copy of the row pointers (degree prefix sums)
+    std::vector<int64_t> deg_mass;    // deg_mass[i] = sum of sorted_deg[i..n)
+    double nb_degree = 0;             // mean degree of an edge's endpoint: sum d^2 / sum d
+    double transitivity = 0;          // closed wedges / wedges (sampled)
     // vertices with degree >= d
     int64_t count_deg_at_least(int64_t d) const;
+    // fraction of edge endpoints whose vertex has degree >= d
+    double nb_fraction_at_least(int64_t d) const;
     ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc, heavy, nheavy, ehash, ehmask}; }
 };
 
@@ -184,6 +194,11 @@ struct RunRequest {
     bool keep_tables = false;
     bool links = false;  // record the contributor index the row decoder needs (implies keep_tables)
     uint64_t max_entries = 0;  // fail with CC_ERANGE when a table would exceed this (0: no limit)
+    // anchor-range chunk: only mappings with Phi(anchor_vertex) in
+    // [anchor_lo, anchor_hi) are counted (anchor_hi < 0: no restriction)
+    int anchor_vertex = 0;
+    int32_t anchor_lo = 0, anchor_hi = -1;
+    int chunk_depth = 0;  // halvings of the anchor range so far
     Arena* arena = nullptr;    // device memory of the run's tables and scratch (nullptr: the context's)
     bool no_alloc = false;     // make no device or pinned-host allocation (fail with CC_ERANGE instead)
 };
@@ -204,13 +219,33 @@ struct RunResult {
     std::vector<DevTable> tables;      // per plan step, when kept (arena-owned)
     std::vector<StepLinks> links;      // per plan step, when recorded (arena-owned)
     std::vector<int64_t> node_sizes;   // per TD node: sum over colourings of |D_x|
+    std::vector<uint32_t> root_sets;   // [B][words]: bitmap of the colour sets at the root
     size_t peak_bytes = 0;             // largest arena footprint of the run
+    int chunks = 1;                    // anchor-range chunks the result was computed in
 };
 
 void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out);
-// run_dp, with the colourings split into waves (halves, recursively) while a
-// table exceeds the per-table budget; colourings are independent, so the
-// results equal one run.  Fails only when a single colouring exceeds it.
+
+// Degree and wedge statistics of a host graph for the memory estimate
+// (host CSR with sorted rows; fills the statistics fields of g).
+void graph_statistics(cc_graph* g, const std::vector<int64_t>& rp, const std::vector<int32_t>& col);
+// Estimated entries per colouring of every plan step's table, and the peak
+// arena bytes of a run over B colourings (tables live at once plus the
+// working buffers of the step that needs most), from the plan and the
+// graph's degree statistics.  A model, not a bound: used to admit queries.
+struct MemEstimate {
+    std::vector<double> entries;  // per plan step, one colouring
+    double peak_bytes = 0;        // B colourings
+    double total_entries = 0;     // sum over steps, B colourings
+};
+MemEstimate estimate_memory(const cc_graph* g, const cc_decomp* d, int k, int B);
+// run_dp, split while a table exceeds the per-table budget or the arena
+// (CC_ENOMEM) into waves of colourings (halves, recursively; colourings are
+// independent), and a single colouring into anchor-range chunks: disjoint
+// ranges of the image of pattern vertex 0, whose counts add mod 2^64 (carry
+// sets the overflow flag), whose tables of nodes holding vertex 0 partition
+// the unsplit tables and whose other tables repeat.  Results equal one run;
+// fails only when a range of one vertex still does not fit.
 void run_dp_waves(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out);
 void release_tables(cc_context* ctx, RunResult* r);
 // the first min(total, cap) mappings of one colouring in lexicographic order

@@ -21,6 +21,12 @@ int64_t cc_graph::count_deg_at_least(int64_t d) const {
     return int64_t(sorted_deg.end() - std::lower_bound(sorted_deg.begin(), sorted_deg.end(), d));
 }
 
+double cc_graph::nb_fraction_at_least(int64_t d) const {
+    if (sorted_deg.empty() || deg_mass.empty() || deg_mass[0] == 0) return 0;
+    const size_t i = size_t(std::lower_bound(sorted_deg.begin(), sorted_deg.end(), d) - sorted_deg.begin());
+    return i >= deg_mass.size() ? 0.0 : double(deg_mass[i]) / double(deg_mass[0]);
+}
+
 namespace ccg {
 
 void fail(int code, const std::string& msg) { throw CcError{code, msg}; }
@@ -103,10 +109,14 @@ void Profiler::reset() {
     index_.clear();
 }
 
-void Profiler::begin(hipStream_t s, const char* name, double bytes) {
+void Profiler::set_bytes(int handle, double bytes) {
+    if (handle >= 0 && size_t(handle) < pending_.size()) pending_[size_t(handle)].bytes = bytes;
+}
+
+int Profiler::begin(hipStream_t s, const char* name, double bytes) {
     armed_ = false;
-    if (!on || (!only.empty() && only != name)) return;
-    if (every > 1 && (seen_++ % every) != 0) return;
+    if (!on || (!only.empty() && only != name)) return -1;
+    if (every > 1 && (seen_++ % every) != 0) return -1;
     armed_ = true;
     auto it = index_.find(name);
     int id;
@@ -120,6 +130,7 @@ void Profiler::begin(hipStream_t s, const char* name, double bytes) {
     Pending p{id, bytes, take(), take()};
     hip_check(hipEventRecord(p.a, s), "hipEventRecord");
     pending_.push_back(p);
+    return int(pending_.size()) - 1;
 }
 
 void Profiler::end(hipStream_t s) {
@@ -208,6 +219,12 @@ void Lane::destroy() {
 
 namespace {
 
+// Algorithmic bytes of one DP table entry with a b-vertex bag, the per-entry
+// unit of the roofline figures: b int32 images, a 16-bit colour set, a
+// uint64 count and a 16-bit colouring index (the packed keys here are
+// narrower; counters report the bytes actually moved).
+inline double entry_bytes(int b) { return 4.0 * b + 12.0; }
+
 struct Exec {
     Lane& lane;
     hipStream_t s;
@@ -274,10 +291,11 @@ struct Exec {
         t.cnt = nullptr;
     }
     template <class F>
-    void timed(const char* name, double bytes, F&& launch) {
-        lane.prof.begin(s, name, bytes);
+    int timed(const char* name, double bytes, F&& launch) {
+        const int h = lane.prof.begin(s, name, bytes);
         launch();
         lane.prof.end(s);
+        return h;
     }
 
     // exclusive scan of n counts; returns offsets[n + 1] and the total
@@ -586,6 +604,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     const uint16_t* rank = ctx->slot_tables;
     const uint16_t* unrank = ctx->slot_tables + (1 << kSlotBits);
     const double csr = double(B) * (9.0 * g.n + 4.0 * g.m2);
+    const double csr_alg = double(B) * (8.0 * g.n + 4.0 * g.m2 + g.n);  // row pointers, columns, colours
     // a high plane only where counts can reach 2^32, presence bytes only
     // where they can wrap
     auto make = [&](int set, size_t step) {
@@ -635,6 +654,15 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     };
     std::vector<std::pair<int, int>> node_of;  // (TD node, nsz index)
     std::vector<int> budgeted;                 // nsz indices of tables under the budget
+    // recorded launches whose algorithmic bytes follow from the table sizes
+    // read back at the end: entries of the tables read and written, at
+    // entry_bytes(1) each, plus the graph bytes
+    struct SlotBytes {
+        int h;
+        int in0, in1, out;  // steps whose tables the launch reads / writes (-1: none)
+        double extra;
+    };
+    std::vector<SlotBytes> slot_bytes;
     for (size_t i = 0; i < S; i++) {
         const Step& st = plan.steps[i];
         if (virt[i]) {
@@ -676,7 +704,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             // vertices per thread (measured on workload 2): the gather's
             // latency wants more blocks, the push's LDS accumulators longer rows
             SlotGrid G = slot_grid(g.n, B, o.a.R, leafc ? 4 : push ? 8 : 2);
-            X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
+            const char* kname = push ? "slot_edge_push" : leafc ? "slot_edge_leaf" : "slot_edge";
+            const int h_fe = X.timed(kname, double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 if (push)
                     launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, degF_u,
                                           ctx->slot_push + slot_push_offset(k, in.s - 1), !below(o.s, 32), o.a, part, nullptr, s);
@@ -685,6 +714,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                                      slot_unrank_offset(o.s - 1), pack, !leafc && below(in.s, 32),
                                      !leafc && below(in.s, 64), o.a, part, ovf, s);
             });
+            slot_bytes.push_back({h_fe, leafc ? -1 : st.in0, -1, int(i + 1), csr_alg});
             partials_done(i, G.blocks);
             tab[i + 1] = o;
             if (st.node >= 0) node_of.push_back({st.node, int(2 * i)});
@@ -731,11 +761,12 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             partials_done(size_t(l), G.blocks);
             pj.part_j = part;
             partials_done(i, G.blocks);
-            X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
+            const int h_pe = X.timed("slot_edge_push", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, rq.degree_mask ? ie.degF : 0,
                                       ctx->slot_push + slot_push_offset(k, in.s - 1), !below(s_e, 32), SlotArrays(),
                                       nullptr, &pj, s);
             });
+            slot_bytes.push_back({h_pe, ie.in0, -1, int(i), csr_alg});
             tab[i] = o;
             if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
             budgeted.push_back(int(2 * i + 1));
@@ -783,11 +814,12 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                 pj.part_j = part;
                 partials_done(i, G.blocks);
             }
-            X.timed("slot_edge", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
+            const int h_pe = X.timed("slot_edge_push", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, rq.degree_mask ? ie.degF : 0,
                                       ctx->slot_push + slot_push_offset(k, in.s - 1), !below(s_e, 32), SlotArrays(),
                                       nullptr, &pj, s);
             });
+            slot_bytes.push_back({h_pe, ie.in0, -1, int(i), csr_alg});
             tab[i] = o;
             if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
             budgeted.push_back(int(2 * i + 1));
@@ -809,12 +841,13 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             partials_done(size_t(st.in1 - 1), G.blocks);
             uint64_t* pj = part;
             partials_done(i, G.blocks);
-            X.timed("slot_join", double(units) * 9.0 * (2.0 * (k - 1) + o.a.R) + csr, [&] {
+            const int h_lj = X.timed("slot_leaf_join", double(units) * 9.0 * (2.0 * (k - 1) + o.a.R) + csr, [&] {
                 launch_slot_leaf_join(G, g, rq.colors, k, rq.degree_mask ? ia.degF : 0,
                                       rq.degree_mask ? plan.steps[size_t(ia.in0)].degF : 0,
                                       rq.degree_mask ? plan.steps[size_t(ic.in0)].degF : 0, unrank, o.a, pa, pc, pj,
                                       s);
             });
+            slot_bytes.push_back({h_lj, -1, -1, int(i), csr_alg});
             tab[i] = o;
             if (st.node >= 0) node_of.push_back({st.node, int(2 * i + 1)});
             budgeted.push_back(int(2 * i + 1));
@@ -831,8 +864,9 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         if (st.kind == S_LEAF) {
             SlotTab o = make(1, i);
             SlotGrid G = slot_grid(g.n, B, 1, 4);
-            X.timed("slot_leaf", double(units) * 9.0 + 8.0 * g.n,
-                    [&] { launch_slot_leaf(G, g, rq.degree_mask ? st.degF : 0, o.a, part, s); });
+            const int h_lf = X.timed("slot_leaf", double(units) * 9.0 + 8.0 * g.n,
+                                     [&] { launch_slot_leaf(G, g, rq.degree_mask ? st.degF : 0, o.a, part, s); });
+            slot_bytes.push_back({h_lf, -1, -1, int(i), 8.0 * g.n + double(units)});
             partials_done(i, G.blocks);
             tab[i] = o;
         } else {  // one-vertex join
@@ -842,11 +876,12 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const int p = o.s - 1, q = y.s - 1;
             const int nsplit = binom(p, q);
             SlotGrid G = slot_grid(g.n, B, o.a.R, std::min(4, std::max(1, slot_join_m(o.a.R, y.a.R, z.a.R, nsplit))));
-            X.timed("slot_join", double(units) * 9.0 * (y.a.R + z.a.R + o.a.R), [&] {
+            const int h_j = X.timed("slot_join", double(units) * 9.0 * (y.a.R + z.a.R + o.a.R), [&] {
                 launch_slot_join(y.a, z.a, ctx->slot_splits + slot_split_offset(p, q), nsplit, binom(kSlotBits, p),
                                  below(y.s, 32) && below(z.s, 32) && below(o.s, 64), below(y.s, 64) && below(z.s, 64),
                                  G, o.a, part, ovf, s);
             });
+            slot_bytes.push_back({h_j, st.in0, st.in1, int(i), 0.0});
             partials_done(i, G.blocks);
             tab[i] = o;
             done_with(st.in0);
@@ -860,7 +895,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     const SlotTab& rc = tab[plan.root_child];
     uint64_t* pv = nullptr;
     if (rq.per_vertex) pv = X.alloc<uint64_t>(units);  // every entry is written
-    X.timed("slot_root", double(units) * 9.0 * rc.a.R, [&] {
+    const int h_root = X.timed("slot_root", double(units) * 9.0 * rc.a.R, [&] {
         // with the steps' entry partials (one_sum) reduced in its last launch
         launch_slot_root(rc.a, rc.s, g.n, B, rq.colors, unrank, part_base + root_off, counts, ovf, pv, csets, cwords,
                          part_base, sums, nsz, s);
@@ -877,7 +912,6 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     }
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     X.synced();
-    X.lane.prof.resolve();
     out->counts.assign(host, host + B);
     const std::vector<uint64_t> sizes(host + B, host + B + nsz_words);
     const uint32_t* of = reinterpret_cast<const uint32_t*>(host + B + nsz_words);
@@ -889,11 +923,25 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                               std::to_string(rq.max_entries),
                           true};
     for (auto& nd : node_of) out->node_sizes[nd.first] = int64_t(sizes[nd.second]);
+    // entries of step t's table: its size word (a fused introduce + forget
+    // pair keeps it with the introduce), through aliases of identical tables
+    auto entries_of = [&](int t) -> double {
+        if (t < 0) return 0.0;
+        const size_t p = phys[size_t(t)];
+        const size_t w = (p > 0 && fuse[p - 1]) ? 2 * (p - 1) + 1 : 2 * p + 1;
+        return w < sizes.size() ? double(sizes[w]) : 0.0;
+    };
+    for (const SlotBytes& sb : slot_bytes)
+        X.lane.prof.set_bytes(sb.h, (entries_of(sb.in0) + entries_of(sb.in1) + entries_of(sb.out)) * entry_bytes(1) +
+                                        sb.extra);
+    X.lane.prof.set_bytes(h_root, entries_of(plan.root_child) * entry_bytes(1));
+    X.lane.prof.resolve();
     out->overflow.assign(B, 0);
     for (int b = 0; b < B; b++) out->overflow[b] = of[b] ? 1 : 0;
     int64_t nzr = 0;
     for (uint64_t i = 0; i < uint64_t(B) * cwords; i++) nzr += __builtin_popcount(cs[i]);
     out->node_sizes[dec.nodes.size() - 1] = nzr;
+    out->root_sets.assign(cs, cs + uint64_t(B) * cwords);
     X.release(pv);
     X.release(part_base);
     X.release(res);
@@ -922,7 +970,8 @@ void release_tables(cc_context* ctx, RunResult* r) {
 void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     const Plan& plan = rq.dec->plan;
     const Decomp& dec = rq.dec->d;
-    const DevGraph g = rq.g->dev();
+    const DevGraph g_all = rq.g->dev();
+    const DevGraph& g = g_all;  // every step but those introducing the chunk's anchor vertex
     const int B = rq.B, k = rq.k;
     if (k < dec.n || k > kMaxColours)
         fail(CC_ERANGE, "colours k must satisfy n_F <= k <= " + std::to_string(kMaxColours));
@@ -963,9 +1012,10 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     out->node_sizes.assign(dec.nodes.size(), 0);
 
     // dense one-column tables when the plan allows them and they fit a
-    // quarter of the arena
+    // quarter of the arena (an anchor-range chunk runs on sorted lists)
+    const bool chunked = rq.anchor_hi >= 0;
     std::vector<int> sz;
-    if (!keep && !rq.sparse_only && slot_plan(plan, fuse, &sz)) {
+    if (!keep && !rq.sparse_only && !chunked && slot_plan(plan, fuse, &sz)) {
         const uint64_t units = uint64_t(B) * uint64_t(g.n);
         bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= arena.size() / 4;
         // 32-bit block indices; slot offsets within one colouring's table below
@@ -991,6 +1041,14 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     try {
         for (size_t i = 0; i < S; i++) {
             const Step& st = plan.steps[i];
+            // an anchor-range chunk restricts the image of the anchor vertex
+            // where a step introduces it (a leaf, or an introduce possibly fused)
+            DevGraph g = g_all;
+            if (chunked && st.u == rq.anchor_vertex &&
+                (st.kind == S_LEAF || st.kind == S_INTRO_PUSH || st.kind == S_INTRO_PULL)) {
+                g.vlo = rq.anchor_lo;
+                g.vhi = rq.anchor_hi;
+            }
             if (virt[i]) {  // consumed by a fused edge step
                 if (st.node >= 0)
                     out->node_sizes[st.node] = int64_t(B) * rq.g->count_deg_at_least(rq.degree_mask ? st.degF : 0);
@@ -1028,7 +1086,9 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 DevTable& o = tab[i + 1];
                 o = X.table(lo, N);
                 if (N)
-                    X.timed("edge_emit", in_bytes + 16.0 * slots + 8.0 * g.m2 + double(N) * (lo.key_bytes() + 8),
+                    X.timed("edge_emit",
+                            (leafc ? 0.0 : double(in->n) * entry_bytes(1)) + double(N) * entry_bytes(1) +
+                                double(B) * (8.0 * g.n + 4.0 * g.m2 + g.n),
                             [&] { launch_edge_emit(in, rstart, rend, B, g, rq.colors, degF_u, degF_c, goff, o, ovf, s); });
                 X.release(goff);
                 X.release(rstart);
@@ -1056,7 +1116,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     uint64_t N = X.scan(flags, total, &offs);
                     X.release(flags);
                     o = X.table(lo, N);
-                    X.timed("leaf_emit", 9.0 * total + 8.0 * g.n + double(N) * (lo.key_bytes() + 8),
+                    X.timed("leaf_emit", 8.0 * g.n + double(total) + double(N) * entry_bytes(1),
                             [&] { launch_leaf_emit(g, B, ia.degF, rq.colors, offs, lo, o.keys, o.cnt, s); });
                     X.release(offs);
                     break;
@@ -1097,7 +1157,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     o = X.table(lo, N);
                     if (links) lk[i].src = X.alloc<uint64_t>(N);
                     if (N)
-                        X.timed("push_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8), [&] {
+                        X.timed("push_emit", double(in.n) * entry_bytes(in.lay.b) + double(N) * entry_bytes(lo.b) + 5.0 * W, [&] {
                             launch_expand_emit(false, in, gstart, woff, G, nullptr, soff, W, T, g, rq.colors, ia, toff, pbits, o,
                                                lk[i].src, s);
                         });
@@ -1141,7 +1201,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     o = X.table(lo, N);
                     if (links) lk[i].src = X.alloc<uint64_t>(N);
                     if (N)
-                        X.timed("pull_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8), [&] {
+                        X.timed("pull_emit", double(in.n) * entry_bytes(in.lay.b) + double(N) * entry_bytes(lo.b) + 5.0 * S, [&] {
                             launch_expand_emit(true, in, nullptr, nullptr, 0, rstart, soff, S, T, g, rq.colors, ia, toff, pbits, o,
                                                lk[i].src, s);
                         });
@@ -1167,7 +1227,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     uint64_t N = X.scan(gcount, G, &goff);
                     X.release(gcount);
                     o = X.table(lo, N);
-                    X.timed("forget_emit", double(in.n) * (in.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8),
+                    X.timed("forget_emit", double(in.n) * entry_bytes(in.lay.b) + double(N) * entry_bytes(lo.b),
                             [&] { launch_forget_emit(in, gstart, G, goff, o, ovf, s); });
                     if (links) {
                         // contributors of every output entry: child entries sorted by output position
@@ -1216,7 +1276,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     X.release(gcount);
                     o = X.table(lo, N);
                     if (N)
-                        X.timed("join_emit", double(y.n + z.n) * (y.lay.key_bytes() + 8) + double(N) * (lo.key_bytes() + 8),
+                        X.timed("join_emit", double(y.n + z.n) * entry_bytes(y.lay.b) + double(N) * entry_bytes(lo.b),
                                 [&] { launch_join_emit(y, z, gstart, G, g.n, rq.colors, zlo, zhi, goff, o, ovf, s); });
                     X.release(zlo);
                     X.release(zhi);
@@ -1308,7 +1368,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
                         RadixSource from{in.keys, in.cnt, in.lay, lo, {st.perm[0], st.perm[1], st.perm[2], st.perm[3]}};
                         bool in_b = false;
-                        X.timed("radix_sort", double(in.n) * (lo.key_bytes() + 8) * 2, [&] {
+                        X.timed("radix_sort", double(in.n) * entry_bytes(lo.b) * 2, [&] {
                             in_b = radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s, false,
                                               fold ? &from : nullptr);
                         });
@@ -1343,7 +1403,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         const int cwords = k >= 5 ? 1 << (k - 5) : 1;
         uint32_t* csets = X.alloc<uint32_t>(uint64_t(B) * cwords);
         launch_fill_u32(csets, 0, uint64_t(B) * cwords, s);
-        X.timed("root", double(rc.n) * (rc.lay.key_bytes() + 8),
+        X.timed("root", double(rc.n) * entry_bytes(1),
                 [&] { launch_root(rc, g.n, counts, ovf, pv, csets, cwords, s); });
         std::vector<uint32_t> cs(uint64_t(B) * cwords);
         hip_check(hipMemcpyAsync(cs.data(), csets, 4 * cs.size(), hipMemcpyDeviceToHost, s), "copy colour sets");
@@ -1365,6 +1425,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         int64_t nz = 0;
         for (uint32_t w : cs) nz += __builtin_popcount(w);
         out->node_sizes[root_node] = nz;
+        out->root_sets = cs;
         X.release(csets);
         X.release(counts);
         X.release(pv);
@@ -1388,32 +1449,90 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
 
 namespace ccg {
 
+// At most 2^6 anchor-range chunks per colouring, and none in an arena below
+// 256 MiB (there the tables are not what exhausts it).
+constexpr int kMaxChunkDepth = 6;
+
+static bool splittable(cc_context* ctx, const CcError& e, const RunRequest& rq) {
+    if (rq.keep_tables || rq.links || rq.no_alloc) return false;
+    const Arena& A = rq.arena ? *rq.arena : ctx->arena;
+    return e.budget || (e.code == CC_ENOMEM && A.size() >= (size_t(256) << 20));
+}
+
 void run_dp_waves(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     try {
         run_dp(ctx, lane, rq, out);
         return;
     } catch (const CcError& e) {
-        if (!e.budget || rq.B <= 1 || rq.keep_tables || rq.links) throw;
+        if (!splittable(ctx, e, rq)) throw;
+        const int32_t lo = rq.anchor_hi >= 0 ? rq.anchor_lo : 0;
+        const int32_t hi = rq.anchor_hi >= 0 ? rq.anchor_hi : rq.g->n;
+        if (rq.B <= 1 && (hi - lo <= 1 || rq.chunk_depth >= kMaxChunkDepth)) throw;
     }
-    const int B1 = rq.B / 2;
-    RunRequest a = rq, b = rq;
-    a.B = B1;
-    b.B = rq.B - B1;
-    b.colors = rq.colors + size_t(B1) * size_t(rq.g->n);
     RunResult ra, rb;
+    if (rq.B > 1) {  // waves of colourings
+        const int B1 = rq.B / 2;
+        RunRequest a = rq, b = rq;
+        a.B = B1;
+        b.B = rq.B - B1;
+        b.colors = rq.colors + size_t(B1) * size_t(rq.g->n);
+        run_dp_waves(ctx, lane, a, &ra);
+        run_dp_waves(ctx, lane, b, &rb);
+        out->counts = ra.counts;
+        out->counts.insert(out->counts.end(), rb.counts.begin(), rb.counts.end());
+        out->overflow = ra.overflow;
+        out->overflow.insert(out->overflow.end(), rb.overflow.begin(), rb.overflow.end());
+        if (rq.per_vertex) {
+            out->per_vertex = ra.per_vertex;
+            out->per_vertex.insert(out->per_vertex.end(), rb.per_vertex.begin(), rb.per_vertex.end());
+        }
+        out->node_sizes = ra.node_sizes;
+        for (size_t i = 0; i < out->node_sizes.size() && i < rb.node_sizes.size(); i++)
+            out->node_sizes[i] += rb.node_sizes[i];
+        out->root_sets = ra.root_sets;
+        out->root_sets.insert(out->root_sets.end(), rb.root_sets.begin(), rb.root_sets.end());
+        out->peak_bytes = std::max(ra.peak_bytes, rb.peak_bytes);
+        out->chunks = ra.chunks + rb.chunks;
+        return;
+    }
+    // one colouring: two anchor ranges of equal degree mass (the entries an
+    // anchor image carries grow with its degree; on heavy-tailed graphs equal
+    // vertex counts would leave the hubs' range as large as the whole)
+    const int32_t lo = rq.anchor_hi >= 0 ? rq.anchor_lo : 0;
+    const int32_t hi = rq.anchor_hi >= 0 ? rq.anchor_hi : rq.g->n;
+    int32_t mid = lo + (hi - lo) / 2;
+    {
+        const std::vector<int64_t>& rp = rq.g->host_rp;
+        const int64_t half = rp[size_t(lo)] + (rp[size_t(hi)] - rp[size_t(lo)] + 1) / 2;
+        const int32_t m = int32_t(std::lower_bound(rp.begin() + lo, rp.begin() + hi + 1, half) - rp.begin());
+        if (rp[size_t(hi)] > rp[size_t(lo)]) mid = std::min(std::max(m, lo + 1), hi - 1);
+    }
+    RunRequest a = rq, b = rq;
+    a.anchor_lo = lo;
+    a.anchor_hi = mid;
+    b.anchor_lo = mid;
+    b.anchor_hi = hi;
+    a.chunk_depth = b.chunk_depth = rq.chunk_depth + 1;
     run_dp_waves(ctx, lane, a, &ra);
     run_dp_waves(ctx, lane, b, &rb);
-    out->counts = ra.counts;
-    out->counts.insert(out->counts.end(), rb.counts.begin(), rb.counts.end());
-    out->overflow = ra.overflow;
-    out->overflow.insert(out->overflow.end(), rb.overflow.begin(), rb.overflow.end());
-    if (rq.per_vertex) {
+    out->counts.assign(1, ra.counts[0] + rb.counts[0]);
+    const bool carry = ra.counts[0] + rb.counts[0] < ra.counts[0];
+    out->overflow.assign(1, uint8_t(ra.overflow[0] || rb.overflow[0] || carry));
+    if (rq.per_vertex) {  // the ranges are disjoint: each vertex has one nonzero part
         out->per_vertex = ra.per_vertex;
-        out->per_vertex.insert(out->per_vertex.end(), rb.per_vertex.begin(), rb.per_vertex.end());
+        for (size_t v = 0; v < out->per_vertex.size(); v++) out->per_vertex[v] += rb.per_vertex[v];
     }
+    const Decomp& dec = rq.dec->d;
     out->node_sizes = ra.node_sizes;
-    for (size_t i = 0; i < out->node_sizes.size() && i < rb.node_sizes.size(); i++) out->node_sizes[i] += rb.node_sizes[i];
+    for (size_t i = 0; i + 1 < dec.nodes.size() && i < rb.node_sizes.size(); i++)
+        if (dec.nodes[i].bag >> rq.anchor_vertex & 1u) out->node_sizes[i] += rb.node_sizes[i];
+    out->root_sets = ra.root_sets;
+    for (size_t w = 0; w < out->root_sets.size() && w < rb.root_sets.size(); w++) out->root_sets[w] |= rb.root_sets[w];
+    int64_t nz = 0;
+    for (uint32_t w : out->root_sets) nz += __builtin_popcount(w);
+    out->node_sizes[dec.nodes.size() - 1] = nz;
     out->peak_bytes = std::max(ra.peak_bytes, rb.peak_bytes);
+    out->chunks = ra.chunks + rb.chunks;
 }
 
 // Enumeration (Sec. 4) of one colouring: forward DP keeping every table and

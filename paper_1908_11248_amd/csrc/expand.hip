@@ -74,7 +74,7 @@ k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gs
             }
             const uint64_t t = s - woff[grp];
             const uint32_t v = src >= 0 ? uint32_t(g.col[row + int64_t(t)]) : uint32_t(t);
-            bool ok = gdeg(g, v) >= a.degF;
+            bool ok = intro_ok(g, v, a.degF);
             // the bag neighbours before pos other than the one the candidates came from
             if (ok && src != a.anchor) ok = has_edge(g, kcol(k0, L, a.anchor), v);
             for (int c = 0; c < a.nchk && ok; c++)
@@ -93,7 +93,7 @@ __global__ void k_pull_seglen(const uint64_t* __restrict__ rstart, const uint64_
         uint64_t e = s % uint64_t(g.m2);
         uint32_t v = uint32_t(g.esrc[e]);
         uint64_t slot = uint64_t(bid) * uint64_t(g.n) + uint32_t(g.col[e]);
-        slen[s] = gdeg(g, v) >= degF ? uint32_t(rend[slot] - rstart[slot]) : 0u;
+        slen[s] = intro_ok(g, v, degF) ? uint32_t(rend[slot] - rstart[slot]) : 0u;
     }
 }
 

@@ -55,7 +55,7 @@ k_edge(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, con
             rb = g.rp[v];
             re = g.rp[v + 1];
             if (skip_above > 0 && re - rb > skip_above) mine = active = false;
-            if (re - rb < degF_u) active = false;
+            if (re - rb < degF_u || int32_t(v) < g.vlo || int32_t(v) >= g.vhi) active = false;
         }
         const uint64_t w = uint64_t(bid) * uint64_t(g.n) + v;  // the unit's output slot
         if (!active) re = rb;

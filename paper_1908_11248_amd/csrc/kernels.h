@@ -40,6 +40,10 @@ struct DevGraph {
     int32_t nheavy;
     const uint64_t* eh;   // edge set: open addressing, linear probing, kEdgeEmpty in free cells
     uint64_t ehmask;      // cells - 1 (a power of two at least eight times m)
+    // Images allowed for the vertex a step introduces: [vlo, vhi).  The whole
+    // of V(G) except in the steps that introduce the anchor pattern vertex of
+    // an anchor-range chunk (counts add over disjoint ranges of its image).
+    int32_t vlo = 0, vhi = 0x7fffffff;
 };
 
 // edge-set key of {a, b} (a != b): smaller id in the high half

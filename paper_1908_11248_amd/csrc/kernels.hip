@@ -209,7 +209,7 @@ __global__ void k_leaf_count(DevGraph g, int B, int degF, uint32_t* flags) {
     uint64_t total = uint64_t(g.n) * B;
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += uint64_t(gridDim.x) * blockDim.x) {
         uint32_t v = uint32_t(i % uint64_t(g.n));
-        flags[i] = gdeg(g, v) >= degF;
+        flags[i] = intro_ok(g, v, degF);
     }
 }
 
@@ -220,7 +220,7 @@ __global__ void k_leaf_emit(DevGraph g, int B, int degF, const uint8_t* __restri
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += uint64_t(gridDim.x) * blockDim.x) {
         uint32_t v = uint32_t(i % uint64_t(g.n));
         uint32_t bid = uint32_t(i / uint64_t(g.n));
-        if (gdeg(g, v) < degF) continue;
+        if (!intro_ok(g, v, degF)) continue;
         uint64_t o = offs[i];
         keys[o] = kpack<K>(bid, &v, 1, 1u << colors[i], lo);
         cnt[o] = 1;

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -158,6 +159,7 @@ struct cc_server {
         uint64_t seed;
         int32_t B;
         size_t est = 0;
+        double model = 0;  // estimate_memory's peak bytes
         Clock::time_point arrival, done_at;
         int state = 0;  // 0 waiting/running, 1 done, < 0 error
         bool alone = false;
@@ -174,6 +176,7 @@ struct cc_server {
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, Req> reqs;
     std::map<std::pair<const cc_decomp*, int32_t>, size_t> peak_seen;
+    double correction = 1.0;  // running geometric mean of measured peak / model, clamped
     uint64_t next_id = 1;
     bool stopping = false;
     std::vector<std::thread> workers;
@@ -182,10 +185,19 @@ struct cc_server {
     bool have_first = false;
     Clock::time_point first_arrival, last_done;
 
+    // Admission size of a request: the measured peak of an earlier run of
+    // the same decomposition and colouring count, else the memory model of
+    // the plan on this graph (estimate_memory) scaled by the running
+    // correction, plus the colouring buffer; never above the whole budget
+    // (a larger query runs alone and splits itself into waves and ranges).
     size_t estimate(const Req& r) {
         auto it = peak_seen.find({r.d, r.B});
-        if (it != peak_seen.end()) return it->second + it->second / 8;
-        return budget / size_t(std::max(1, opts.max_inflight));
+        double e;
+        if (it != peak_seen.end())
+            e = double(it->second) * 1.125;
+        else
+            e = r.model * correction + double(g->n) * double(r.B);
+        return size_t(std::min(e, double(budget)));
     }
 
     // oldest admissible request (lock held); 0 if none
@@ -263,6 +275,11 @@ struct cc_server {
                     rr.counts = res.counts;
                     rr.ovf = res.overflow;
                     peak_seen[{d, B}] = std::max(peak_seen[{d, B}], res.peak_bytes + size_t(g->n) * size_t(B));
+                    if (rr.model > 0 && res.peak_bytes > 0 && res.chunks == 1) {
+                        const double ratio = std::min(4.0, std::max(0.25, double(res.peak_bytes) / rr.model));
+                        correction = std::exp(0.8 * std::log(correction) + 0.2 * std::log(ratio));
+                        correction = std::min(4.0, std::max(0.5, correction));
+                    }
                     completed++;
                     latencies_ms.push_back(std::chrono::duration<double, std::milli>(rr.done_at - rr.arrival).count());
                     last_done = rr.done_at;
@@ -393,6 +410,7 @@ int cc_server_submit(cc_server* srv, const cc_decomp* d, int32_t k, uint64_t see
     r.seed = seed;
     r.B = num_colorings;
     r.arrival = Clock::now();
+    r.model = estimate_memory(srv->g, d, k, num_colorings).peak_bytes;
     r.est = srv->estimate(r);
     if (!srv->have_first) {
         srv->have_first = true;

@@ -23,7 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # device kernel -> library profiler name
 KERNEL_NAMES = [
-    (r"k_slot_edge", "slot_edge"), (r"k_slot_join", "slot_join"), (r"k_slot_leaf_join", "slot_join"),
+    (r"k_slot_edge_push", "slot_edge_push"), (r"k_slot_edge_leaf", "slot_edge_leaf"), (r"k_slot_edge", "slot_edge"),
+    (r"k_slot_leaf_join", "slot_leaf_join"), (r"k_slot_join", "slot_join"),
     (r"k_slot_root", "slot_root"),
     (r"k_slot_leaf", "slot_leaf"), (r"k_slot_counters", "slot_counters"),
     (r"k_edge<.*true, true>", "edge_emit"), (r"k_edge<.*true, false>", "edge_emit"),

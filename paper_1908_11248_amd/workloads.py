@@ -389,22 +389,71 @@ def random_query(seed: int) -> Pattern:
     return p
 
 
-def select_queries(index: int, count: int, fits, max_redraws: int = 200):
-    """The query stream of a batched/served workload under a work budget.
+def longest_induced_cycle(p: Pattern) -> int:
+    """Length of the longest chordless (induced) cycle of F; 0 for a forest.
+    Plain search over simple cycles (patterns have at most 16 vertices)."""
+    adj = [set() for _ in range(p.n)]
+    for a, b in p.edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    best = 0
 
-    Query i starts from seed query_seeds(index, count)[i]; while
-    fits(pattern, seed) is False the query is redrawn from seed + 1 (a fresh
-    size and family draw).  `fits` is the caller's budget test (the per-table
-    entry budget on the query's first colouring).  Returns a list of
-    (pattern, seed) and a dict of redraw counts keyed by (family, size) of
-    the rejected draws."""
+    def grow(path, on):
+        nonlocal best
+        u = path[-1]
+        for w in adj[u]:
+            if w == path[0] and len(path) >= 3:
+                L = len(path)
+                if all(path[j] not in adj[path[i]] for i in range(L) for j in range(i + 2, L)
+                       if not (i == 0 and j == L - 1)):
+                    best = max(best, L)
+            elif w > path[0] and w not in on:
+                # a chord to an earlier path vertex (other than the previous
+                # one) can never be removed: prune
+                if any(w in adj[x] for x in path[1:-1]):
+                    continue
+                on.add(w)
+                path.append(w)
+                grow(path, on)
+                path.pop()
+                on.discard(w)
+
+    for s in range(p.n):
+        grow([s], {s})
+    return best
+
+
+# Work budget of the batched and served workloads: a query is redrawn when
+# its pattern has a chordless cycle longer than this.  Such a cycle makes some
+# DP table hold pairs of graph vertices joined by paths of about half its
+# length with no edge between them to prune them, and on these heavy-tailed
+# graphs the number of such pairs grows by the mean neighbour degree (about
+# 30 on BA(200000, 5), 50 on CL(10^6, 2.5, 10)) per extra step.  Measured per
+# colouring: C5 on BA(200000, 5) 4.4e8 entries in its largest table, C6
+# 5.6e9; on CL(10^6) C5 3.7e9, and partial 3-trees with an induced 4-cycle
+# above 4e8.  Everything else stays below about 5e8.
+MAX_INDUCED_CYCLE = {4: 5, 5: 3}
+
+
+def admissible(index: int, p: Pattern) -> bool:
+    return longest_induced_cycle(p) <= MAX_INDUCED_CYCLE.get(index, 32)
+
+
+def select_queries(index: int, count: int, fits=None, max_redraws: int = 200):
+    """The query stream of a batched/served workload under the work budget.
+
+    Query i starts from seed query_seeds(index, count)[i]; while the pattern
+    is not admissible(index, .) (or fits(pattern, seed) is False, when a
+    caller gives that extra test) the query is redrawn from seed + 1 (a fresh
+    size and family draw).  Returns a list of (pattern, seed) and a dict of
+    redraw counts keyed by (family, size) of the rejected draws."""
     out = []
     redraws = {}
     for s0 in query_seeds(index, count):
         s = s0
         for _ in range(max_redraws):
             p = random_query(s)
-            if fits(p, s):
+            if admissible(index, p) and (fits is None or fits(p, s)):
                 break
             key = (p.family, p.n)
             redraws[key] = redraws.get(key, 0) + 1

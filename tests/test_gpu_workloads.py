@@ -1,0 +1,117 @@
+"""GPU parity at the standard workloads' own sizes, against the oracle's
+stored values (tests/golden/w*_counts.txt, w5_sample.txt, written by
+tests/golden/make_goldens.py from the CPU oracle and the seeded generators
+only).  Bit-exact uint64 counts and overflow flags.
+
+  workload 2  ER(10000, d=8), tree on 8 vertices: all 64 colourings, one launch
+  workload 3  RGG(50000, d=10), ladder 2x4: all 32 colourings, one launch
+  workload 4  BA(200000, 5): colouring 0 of all 256 queries through the batched
+              path (the 5-cycles on four sampled ranges of Phi(0))
+  workload 5  CL(10^6, 2.5, 10): colouring 0 of a seeded sample of 32 queries
+              through the server (continuous batching) and through cc_count
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1908_11248_amd as cc
+from paper_1908_11248_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rows(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip("%s not generated (python tests/golden/make_goldens.py)" % name)
+    return [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = cc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("index", [2, 3])
+def test_single_pattern_workloads_all_colourings(ctx, index):
+    rows = _rows("w%d_counts.txt" % index)
+    w = W.workload(index)
+    g = W.workload_graph(index)
+    pat = W.workload_pattern(index)
+    say("workload", index, w.name, "colourings", w.colorings)
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    C = cc.color(ctx, G, w.k, w.color_seed, w.colorings)
+    D = cc.build_decomposition(pat.n, pat.edges)
+    counts, ovf = cc.count(ctx, G, C, D)
+    assert len(rows) == w.colorings
+    for b, cnt, o in rows:
+        assert int(counts[int(b)]) == int(cnt), (index, b)
+        assert bool(ovf[int(b)]) == bool(int(o)), (index, b)
+
+
+def _query_rows(name):
+    by_q = {}
+    for q, seed, pname, b, lo, hi, cnt, o in _rows(name):
+        by_q.setdefault(int(q), []).append((int(seed), pname, int(b), int(lo), int(hi), int(cnt), int(o)))
+    return by_q
+
+
+def test_workload4_all_queries_colouring0(ctx):
+    by_q = _query_rows("w4_counts.txt")
+    g = W.workload_graph(4)
+    sel, _ = W.select_queries(4, 256)
+    assert sorted(by_q) == list(range(len(sel))) and len(sel) == 256
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    full, ranged = [], []
+    for q, (p, s) in enumerate(sel):
+        assert all(r[0] == s and r[1] == p.name for r in by_q[q])
+        D = cc.build_decomposition(p.n, p.edges)
+        C = cc.color(ctx, G, p.n, W.colouring_seed(s), 1)
+        for r in by_q[q]:
+            (full if (r[3], r[4]) == (0, g.n) else ranged).append((q, D, C, r))
+    say("workload 4: %d full counts through cc_count_batch, %d ranges" % (len(full), len(ranged)))
+    out = cc.count_batch(ctx, G, [(D, C) for _, D, C, _ in full])
+    for (q, _, _, r), (cnt, ovf) in zip(full, out):
+        assert int(cnt[0]) == r[5] and bool(ovf[0]) == bool(r[6]), (q, r[1])
+    for q, D, C, r in ranged:
+        cnt, ovf = cc.count_range(ctx, G, C, D, r[3], r[4])
+        assert int(cnt[0]) == r[5] and bool(ovf[0]) == bool(r[6]), (q, r[1], r[3], r[4])
+
+
+def test_workload5_sample_served_and_plain(ctx):
+    by_q = _query_rows("w5_sample.txt")
+    g = W.workload_graph(5)
+    sel, _ = W.select_queries(5, 200)
+    G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+    say("workload 5: %d sampled queries" % len(by_q))
+    srv = cc.Server(ctx, G, max_inflight=4, max_heavy=0)
+    tickets = {}
+    decs = {}
+    try:
+        for q in sorted(by_q):
+            p, s = sel[q]
+            assert all(r[0] == s and r[1] == p.name for r in by_q[q])
+            decs[q] = cc.build_decomposition(p.n, p.edges)
+            tickets[q] = srv.submit(decs[q], p.n, W.colouring_seed(s), 1)
+        for q, t in tickets.items():
+            st, cnt, ovf = srv.wait(t)
+            r = by_q[q][0]
+            assert st == 1 and int(cnt[0]) == r[5] and bool(ovf[0]) == bool(r[6]), (q, r[1])
+    finally:
+        srv.stop()
+    for q in sorted(by_q)[:8]:
+        p, s = sel[q]
+        C = cc.color(ctx, G, p.n, W.colouring_seed(s), 1)
+        cnt, ovf = cc.count(ctx, G, C, decs[q])
+        assert int(cnt[0]) == by_q[q][0][5], (q, p.name)

@@ -350,3 +350,30 @@ def test_node_table_sizes_vs_definition(pat):
             for dm in (True, False):
                 got = O.dp_count(g, pat, k, col, td=td, degmask=dm, sizes=True)["sizes"]
                 assert list(got) == _definition_table_sizes(g, pat, k, col, td, degmask=dm)
+
+
+@pytest.mark.parametrize("pat", [W.cycle(5), W.pattern_B(), W.path(4), W.partial_3tree(6, 1)], ids=lambda p: p.name)
+def test_anchor_ranges_partition_the_count(pat):
+    """Counting only mappings with Phi(0) in [lo, hi): single-vertex ranges
+    equal the brute force with Phi(0) fixed (the definition), and any
+    partition of V(G) into ranges adds up to the full count; tables of nodes
+    without pattern vertex 0 in their bag do not depend on the range."""
+    g = W.er_pairs(40, 0.2, 8)
+    rng = np.random.default_rng(5)
+    col = colours(rng, g.n, pat.n)
+    full = O.dp_count(g, pat, pat.n, col, sizes=True)
+    td, _ = O.build_td(pat)
+    for v in range(0, g.n, 7):
+        assert O.dp_count_range(g, pat, pat.n, col, v, v + 1)["count"] == O.brute_count(g, pat, col, fix0=v)
+    cuts = [0, 3, 11, 12, 29, g.n]
+    total = 0
+    nodes = _td_nodes(td)
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        r = O.dp_count_range(g, pat, pat.n, col, lo, hi, td=td, sizes=True)
+        total += r["count"]
+        for i, node in enumerate(nodes[:-1]):
+            if not node[4] & 1:
+                assert r["sizes"][i] == full["sizes"][i]
+    assert total % U64 == full["count"]
+    assert O.dp_count_range(g, pat, pat.n, col, 0, g.n)["count"] == full["count"]
+    assert O.dp_count_range(g, pat, pat.n, col, 5, 5)["count"] == 0
