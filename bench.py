@@ -15,8 +15,9 @@ served queries/s over that timed region.  Beside it, on the same queries:
   plain      one query at a time on one stream (the paper's single runs);
   poisson    Poisson arrivals at --load x the plain rate, served with
              --inflight lanes and with one lane: queries/s, p50/p99 latency;
-  batched_w4 the 256-query batch of BA(200000, 5) (16 colourings per query):
-             plain vs cc_count_batch, DP table entries/s (--no-w4 skips it).
+  batched_w4 the first 64 of the 256 queries of BA(200000, 5) (16 colourings
+             each; all 256 with --workload 4): plain vs cc_count_batch, DP
+             table entries/s (--no-w4 skips it).
 Served, Poisson and batched counts are checked bit-equal to the plain ones.
 
 The `roofline` object names the kernel with the largest total time in the
@@ -134,7 +135,6 @@ def cpu_baseline(jobs, unit_per_job, unit, what, budget_s=20.0, workers=8):
     model, ncpu, share = host_cpu()
     workers = max(1, min(workers, share))
     spec = json.dumps({"jobs": jobs, "workers": workers})
-    t0 = time.perf_counter()
     p = subprocess.Popen([sys.executable, "-u", os.path.abspath(__file__), "--oracle-worker"],
                          stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
                          text=True, start_new_session=True)
@@ -145,6 +145,13 @@ def cpu_baseline(jobs, unit_per_job, unit, what, budget_s=20.0, workers=8):
 
     sel = selectors.DefaultSelector()
     sel.register(p.stdout, selectors.EVENT_READ)
+    # the clock starts once the child has generated the graph
+    t_ready = time.perf_counter()
+    while time.perf_counter() - t_ready < 120:
+        if sel.select(timeout=1.0):
+            if p.stdout.readline().strip() == "ready":
+                break
+    t0 = time.perf_counter()
     last = t0
     while time.perf_counter() - t0 < budget_s:
         if not sel.select(timeout=max(0.05, budget_s - (time.perf_counter() - t0))):
@@ -178,12 +185,10 @@ def oracle_worker():
         if j[0] not in graphs:
             graphs[j[0]] = W.workload_graph(j[0])
 
-    def init():
-        pass
-
     ctx = mp.get_context("fork")
     global _GRAPHS
     _GRAPHS = graphs
+    print("ready", flush=True)
     with cf.ProcessPoolExecutor(max_workers=spec["workers"], mp_context=ctx) as ex:
         for fut in cf.as_completed([ex.submit(_oracle_job, j) for j in spec["jobs"]]):
             print(fut.result(), flush=True)
@@ -233,6 +238,7 @@ def bench_serve(args):
     plain = {}
     lat_plain = []
     entries = 0
+    ctx.profile_enable(True)  # one stream: the kernels' own durations
     t0 = time.perf_counter()
     for i, q in enumerate(timed):
         tq = time.perf_counter()
@@ -243,6 +249,8 @@ def bench_serve(args):
         if i % 10 == 9:
             log("plain", i + 1, "of", len(timed), "%.1f s" % (time.perf_counter() - t0))
     t_plain = time.perf_counter() - t0
+    prof_plain = ctx.profile_read()
+    ctx.profile_enable(False)
     plain_qps = len(timed) / t_plain
     log("plain %.2f q/s (%.1f s)" % (plain_qps, t_plain))
 
@@ -326,27 +334,38 @@ def bench_serve(args):
         "entries_per_s_served": round(entries / wall_sat, 1),
         "bit_identical_served_vs_plain": True,
         "roofline": roofline_from(prof, "w5"),
-        "kernels_warmup": kernel_table(prof_w),
+        # the same kernel in the plain pass, where no other query's kernels
+        # share the device while it runs
+        "roofline_plain_pass": roofline_from({k: v for k, v in prof_plain.items() if k == (dom or "")} or prof_plain, "w5"),
+        "kernels_plain_pass": kernel_table(prof_plain),
     }
     ctx.close()
     if not args.no_w4:
-        out["batched_w4"] = bench_batched_w4(args, timed_steps=1)
+        out["batched_w4"] = bench_batched_w4(args, timed_steps=1, nq=args.queries or 64)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
+        # the oracle needs tens of seconds per colouring of the larger queries
+        # on this graph: the sample is the colourings of the timed stream's
+        # queries of at most six vertices, smallest first
+        small = sorted((q for q in timed if sel[q][0].n <= 6), key=lambda q: (sel[q][0].n, q))
         jobs = [[5, sel[q][0].n, sel[q][0].edges, sel[q][0].n, W.colouring_seed(sel[q][1]), b]
-                for q in timed for b in range(B)]
-        out["cpu_baseline"] = cpu_baseline(jobs, 1.0 / B, "queries/s", "the timed stream's colourings in order",
-                                           budget_s=args.cpu_budget)
+                for q in small for b in range(B)]
+        out["cpu_baseline"] = cpu_baseline(jobs, 1.0 / B, "queries/s",
+                                           "colourings of the %d timed queries with at most 6 vertices" % len(small),
+                                           budget_s=args.cpu_budget, workers=16)
+        # the GPU's plain rate on the same queries, for comparison
+        small_s = sum(lat_plain[timed.index(q)] for q in small)
+        out["cpu_baseline"]["gpu_plain_same_sample_qps"] = round(len(small) / small_s, 3) if small_s else None
     print(json.dumps(out), flush=True)
 
 
 # ---------------------------------------------------------------------------
 # the batched uneven queries of workload 4
 
-def bench_batched_w4(args, timed_steps=None):
+def bench_batched_w4(args, timed_steps=None, nq=None):
     w = W.workload(4)
     B = w.colorings
-    nq = args.queries or 256
+    nq = nq or args.queries or 256
     g = W.workload_graph(4)
     log("workload 4", w.name, "queries", nq)
     ctx = cc.Context(0)
@@ -473,14 +492,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="serve", choices=["serve", "2", "3", "4", "5"])
-    ap.add_argument("--per-step", type=int, default=4, help="served queries per step")
-    ap.add_argument("--queries", type=int, default=0, help="queries of workload 4 (0: 256)")
+    ap.add_argument("--per-step", type=int, default=2, help="served queries per step")
+    ap.add_argument("--queries", type=int, default=0,
+                    help="queries of workload 4 (0: all 256 with --workload 4, the first 64 in the default run)")
     ap.add_argument("--load", type=float, default=0.7, help="Poisson arrival rate / plain throughput")
     ap.add_argument("--inflight", type=int, default=4, help="concurrent queries while serving")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams of the workload-4 batch")
     ap.add_argument("--no-w4", action="store_true", help="skip the workload-4 batch in the default run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of oracle work")
     ap.add_argument("--plain", type=int, default=4, help="colourings timed one at a time (workloads 2 and 3)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB mebibytes (reference kernel for counter scaling)")

@@ -139,6 +139,11 @@ void cc_decomp_free(cc_decomp *d);
  * overflow flags). */
 #define CC_NO_DEGREE_MASK 1u
 #define CC_SPARSE_TABLES 2u
+/* Introduce nodes whose new vertex u has two or more neighbours in the bag
+ * normally draw each entry's candidates from the adjacency list of the bag
+ * neighbour whose image has the fewest neighbours (then re-sort); with
+ * CC_CLASSIC_EXPAND they always use one fixed column's list (same counts). */
+#define CC_CLASSIC_EXPAND 4u
 int cc_count(cc_context *ctx, const cc_graph *g, const cc_coloring *c, const cc_decomp *d,
              uint32_t flags, uint64_t *counts, uint8_t *overflow);
 

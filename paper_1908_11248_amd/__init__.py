@@ -26,6 +26,7 @@ CC_ECANCELLED = -5
 CC_GRAPH_CANONICALIZE = 1
 CC_NO_DEGREE_MASK = 1
 CC_SPARSE_TABLES = 2
+CC_CLASSIC_EXPAND = 4
 
 # every symbol the header declares (checked by the CPU tests)
 EXPORTS = [

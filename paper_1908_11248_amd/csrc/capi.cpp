@@ -504,6 +504,7 @@ int cc_count(cc_context* ctx, const cc_graph* g, const cc_coloring* c, const cc_
         rq.dec = d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
         rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
+        rq.classic_expand = (flags & CC_CLASSIC_EXPAND) != 0;
         rq.max_entries = ctx->max_entries;
         RunResult r;
         wait_colors(c, ctx->main.stream);
@@ -530,6 +531,7 @@ int cc_count_range(cc_context* ctx, const cc_graph* g, const cc_coloring* c, con
         rq.dec = d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
         rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
+        rq.classic_expand = (flags & CC_CLASSIC_EXPAND) != 0;
         rq.max_entries = ctx->max_entries;
         rq.anchor_lo = lo;
         rq.anchor_hi = hi;
@@ -586,6 +588,7 @@ int cc_count_noalloc(cc_context* ctx, const cc_graph* g, const cc_coloring* c, c
         rq.dec = d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
         rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
+        rq.classic_expand = (flags & CC_CLASSIC_EXPAND) != 0;
         rq.arena = &A;
         rq.no_alloc = true;
         RunResult r;
@@ -621,6 +624,7 @@ int cc_count_by_vertex(cc_context* ctx, const cc_graph* g, const cc_coloring* c,
         rq.dec = d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
         rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
+        rq.classic_expand = (flags & CC_CLASSIC_EXPAND) != 0;
         rq.per_vertex = true;
         rq.max_entries = ctx->max_entries;
         RunResult r;

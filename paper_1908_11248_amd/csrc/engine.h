@@ -201,6 +201,7 @@ struct RunRequest {
     int chunk_depth = 0;  // halvings of the anchor range so far
     Arena* arena = nullptr;    // device memory of the run's tables and scratch (nullptr: the context's)
     bool no_alloc = false;     // make no device or pinned-host allocation (fail with CC_ERANGE instead)
+    bool classic_expand = false;  // never the entry-wise introduce (tests compare both)
 };
 
 // contributor index of one step's table (enumeration)

@@ -1020,10 +1020,18 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= arena.size() / 4;
         // 32-bit block indices; slot offsets within one colouring's table below
         // 2^28 (they share a staged word with a colour)
-        for (size_t i = 0; i < S && fits; i++)
+        bool shape_ok = true;
+        for (size_t i = 0; i < S && shape_ok; i++)
             if (sz[i] > 0 && (slot_grid(g.n, B, binom(k - 1, sz[i] - 1), 1).blocks >= (uint64_t(1) << 32) ||
                               uint64_t(g.n) * binom(k - 1, sz[i] - 1) >= (uint64_t(1) << 28)))
-                fits = false;
+                shape_ok = false;
+        // too many colourings for dense tables, but one fits: waves of
+        // colourings on dense tables beat one launch on sorted lists
+        if (shape_ok && !fits && B > 1 && !rq.no_alloc &&
+            slot_peak_bytes(plan, fuse, virt, sz, uint64_t(g.n), k) <= arena.size() / 4)
+            throw CcError{CC_ERANGE, "dense tables of " + std::to_string(B) + " colourings exceed a quarter of the arena",
+                          true};
+        fits = fits && shape_ok;
         if (fits) {
             try {
                 run_slots(ctx, X, rq, fuse, virt, sz, out);
@@ -1107,6 +1115,95 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
             for (int j = 0; j < 4; j++) ia.chk[j] = st.chk[j];
             ia.degF = rq.degree_mask ? st.degF : 0;
             DevTable& o = tab[i];
+            // Introduce by entries: candidates from the bag neighbour of u
+            // whose image has the fewest neighbours, per child entry; used
+            // when u has a further bag neighbour that the push or pull form
+            // would test per item anyway (so those forms cannot prune by it
+            // before walking a possibly huge row); the output is re-sorted
+            // on (colouring, columns 0..pos).
+            // It walks fewer candidates, but each one costs more (its own
+            // degree, colour and edge tests instead of per-group ones): it is
+            // taken when it walks under a third of the anchor column's rows.
+            const bool entry_eligible =
+                !links && !rq.classic_expand && tab[st.in0].n > 0 &&
+                ((st.kind == S_INTRO_PULL && st.nchk >= 1) ||
+                 (st.kind == S_INTRO_PUSH && std::any_of(st.chk, st.chk + st.nchk, [&](int c) { return c >= st.pos; })));
+            bool entry_form = false;
+            uint32_t* e_slen = nullptr;
+            uint8_t* e_src = nullptr;
+            uint64_t* e_soff = nullptr;
+            uint64_t e_T = 0;
+            IntroArgs ea = ia;
+            if (entry_eligible) {
+                const DevTable& in = tab[st.in0];
+                ea.sel = nullptr;
+                ea.segv = nullptr;
+                e_slen = X.alloc<uint32_t>(in.n);
+                e_src = X.alloc<uint8_t>(in.n);
+                uint64_t* anchor_items = X.alloc<uint64_t>(1);
+                launch_fill_u64(anchor_items, 0, 1, s);
+                X.timed("entry_seglen", double(in.n) * entry_bytes(in.lay.b) + 8.0 * in.n,
+                        [&] { launch_entry_seglen(in, g, ea, e_slen, e_src, anchor_items, s); });
+                e_T = X.scan(e_slen, in.n, &e_soff);  // synchronises: anchor_items is final
+                const uint64_t classic = read_u64(X.lane, anchor_items);
+                X.release(anchor_items);
+                X.release(e_slen);
+                entry_form = 3 * e_T < classic;
+                if (!entry_form) {
+                    X.release(e_soff);
+                    X.release(e_src);
+                }
+            }
+            if (entry_form) {
+                const DevTable& in = tab[st.in0];
+                {
+                    uint8_t* src = e_src;
+                    uint64_t* soff = e_soff;
+                    const uint64_t T = e_T;
+                    const uint64_t tiles = expand_tiles(T);
+                    uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                    uint16_t* pbits = X.alloc<uint16_t>(expand_pass_words(T));
+                    X.timed("entry_count", double(in.n) * entry_bytes(in.lay.b) + 5.0 * T,
+                            [&] { launch_entry_count(in, src, soff, T, g, rq.colors, ea, tcount, pbits, s); });
+                    uint64_t* toff;
+                    const uint64_t N = X.scan(tcount, tiles, &toff);
+                    X.release(tcount);
+                    o = X.table(lo, N);
+                    if (N) {
+                        X.timed("entry_emit", double(in.n) * entry_bytes(in.lay.b) + double(N) * entry_bytes(lo.b), [&] {
+                            launch_entry_emit(in, src, soff, T, g, rq.colors, ea, toff, pbits, o, s);
+                        });
+                    }
+                    X.release(pbits);
+                    X.release(toff);
+                    X.release(soff);
+                    X.release(src);
+                    if (N > 1) {
+                        // stable sort on (colouring, columns 0..pos)
+                        const int sort_lo = lo.kb + (lo.b - 1 - st.pos) * lo.vb;
+                        void* kb2 = X.raw(N * lo.key_bytes());
+                        uint64_t* vb2 = X.alloc<uint64_t>(N);
+                        void* tmp = X.raw(radix_tmp_bytes(N));
+                        bool in_b = false;
+                        X.timed("radix_sort", double(N) * entry_bytes(lo.b) * 2, [&] {
+                            in_b = radix_sort(o.keys, o.cnt, kb2, vb2, N, lo.kw(), lo.bits(), sort_lo, tmp, s, false);
+                        });
+                        if (in_b) {
+                            std::swap(o.keys, kb2);
+                            std::swap(o.cnt, vb2);
+                        }
+                        X.release(tmp);
+                        X.release(vb2);
+                        X.release(kb2);
+                    }
+                }
+                if (st.node >= 0) out->node_sizes[st.node] = int64_t(o.n);
+                if (!keep) {
+                    for (int in2 : {st.in0, st.in1})
+                        if (in2 >= 0 && --uses[in2] == 0) X.drop(tab[in2]);
+                }
+                continue;
+            }
             switch (st.kind) {
                 case S_LEAF: {
                     uint64_t total = uint64_t(g.n) * B;

@@ -144,17 +144,39 @@ MemEstimate estimate_memory(const cc_graph* g, const cc_decomp* d, int k, int B)
         const double key = bits > 64 ? 16 : 8;
         return est.entries[i] * B * (key + 8);
     };
+    // an introduce by pull over a one-column child followed by the forget of
+    // that column runs as one gather: its own table is never stored
+    std::vector<char> fused(S, 0);
+    for (size_t i = 0; i + 1 < S; i++) {
+        const Step& a = plan.steps[i];
+        const Step& f = plan.steps[i + 1];
+        if (a.kind == S_INTRO_PULL && a.b_in == 1 && a.nchk == 0 && f.kind == S_FORGET_LAST && f.in0 == int(i) &&
+            uses[i] == 1)
+            fused[i] = 1;
+    }
     double live = 0, peak = 0;
     for (size_t i = 0; i < S; i++) {
         const Step& st = plan.steps[i];
+        if (fused[i]) continue;  // no table; its forget reads the child directly
         const double out = bytes(i);
         double work = out;  // counts, offsets, survivor bits
         if (st.kind == S_RESORT) work = 2 * out;
-        if (st.kind == S_FORGET_LAST || st.kind == S_JOIN) work = st.in0 >= 0 ? bytes(size_t(st.in0)) : 0;
+        if (st.kind == S_FORGET_LAST || st.kind == S_JOIN) {
+            int in = st.in0;
+            if (in >= 0 && fused[size_t(in)]) in = plan.steps[size_t(in)].in0;  // the gather reads the child
+            work = in >= 0 ? bytes(size_t(in)) : 0;
+        }
         live += out;
         peak = std::max(peak, live + work);
-        for (int in : {st.in0, st.in1})
-            if (in >= 0 && --uses[size_t(in)] == 0) live -= bytes(size_t(in));
+        for (int in : {st.in0, st.in1}) {
+            if (in < 0) continue;
+            if (fused[size_t(in)]) {  // the fused introduce's child is this step's real input
+                const int c = plan.steps[size_t(in)].in0;
+                if (c >= 0 && --uses[size_t(c)] == 0) live -= bytes(size_t(c));
+                continue;
+            }
+            if (--uses[size_t(in)] == 0) live -= bytes(size_t(in));
+        }
     }
     // plans of one-vertex bags (trees) may run on dense tables instead:
     // n_G x B x C(k-1, s-1) slots of at most 9 bytes per table

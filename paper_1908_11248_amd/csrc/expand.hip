@@ -307,7 +307,227 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
     }
 }
 
+// ---- entry-wise expand -----------------------------------------------------
+//
+// A segment is one child entry; its candidates for the new vertex are the
+// adjacency list of the image of whichever bag neighbour of u has the fewest
+// neighbours for that entry, and each other bag neighbour is an edge test.
+// The push and pull forms above draw candidates from one fixed column, which
+// on heavy-tailed graphs walks a hub's whole row for every entry holding the
+// hub even when another bag neighbour of u maps to a vertex of degree 5.
+// Items come out in (entry, candidate) order with v at column pos; the
+// caller restores key order with a stable sort on (colouring, columns
+// 0..pos): entries are in key order and within one entry the candidates
+// ascend, so equal (colouring, columns 0..pos) keep (later columns, colour
+// set) order.
+
+// also adds up, into *anchor_items, the candidates the fixed-column forms
+// would walk (the anchor's degree per entry), so the caller can pick a form
+template <class K>
+__global__ void __launch_bounds__(kBlock)
+k_entry_seglen(const K* __restrict__ keys, Lay L, uint64_t N, DevGraph g, IntroArgs a, uint32_t* slen, uint8_t* src,
+               unsigned long long* anchor_items) {
+    uint64_t mine = 0;
+    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < N; e += uint64_t(gridDim.x) * blockDim.x) {
+        const K k = keys[e];
+        int best = a.anchor;
+        int64_t bd = gdeg(g, kcol(k, L, a.anchor));
+        mine += uint64_t(bd);
+        for (int c = 0; c < a.nchk; c++) {
+            const int64_t d = gdeg(g, kcol(k, L, a.chk[c]));
+            if (d < bd) {
+                bd = d;
+                best = a.chk[c];
+            }
+        }
+        slen[e] = uint32_t(bd);
+        src[e] = uint8_t(best);
+    }
+    uint64_t total;
+    (void)block_excl_scan(mine, &total);
+    if (threadIdx.x == 0 && total) atomicAdd(anchor_items, (unsigned long long)total);
+}
+
+template <class KI, class KO, bool EMIT>
+__global__ void __launch_bounds__(kBlock)
+k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, const uint8_t* __restrict__ src,
+               const uint64_t* __restrict__ soff, uint64_t S, uint64_t T, DevGraph g,
+               const uint8_t* __restrict__ colors, IntroArgs a, uint32_t* tcount, const uint64_t* __restrict__ toff,
+               KO* okeys, uint64_t* ocnt, Lay LO, uint16_t* pbits) {
+    const uint64_t tiles = (T + kExpTile - 1) / kExpTile;
+    const uint64_t* tbounds = reinterpret_cast<const uint64_t*>(pbits + tiles * kBlock);
+    // the bag neighbours of u (child columns): the anchor, then the checks
+    int nb[5];
+    int nnb = 0;
+    nb[nnb++] = a.anchor;
+    for (int c = 0; c < a.nchk; c++) nb[nnb++] = a.chk[c];
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint64_t tile0 = tile * kExpTile;
+        const uint64_t tile1 = tile0 + kExpTile < T ? tile0 + kExpTile : T;
+        const uint64_t s_lo = tbounds[4 * tile], s_hi = tbounds[4 * tile + 1];
+        const uint64_t t0 = tile0 + uint64_t(threadIdx.x) * kExpItems;
+        const uint64_t t1 = t0 + kExpItems < tile1 ? t0 + kExpItems : tile1;
+        uint32_t pass = 0;
+        uint32_t n_pass = 0;
+        uint64_t seg0 = 0;
+        if (t0 < tile1) seg0 = upper_bound_u64(soff, s_lo, s_hi + 1, t0) - 1;
+        // the segment's entry: key, candidate row, colouring, colour set
+        uint64_t seg = seg0;
+        KI key{};
+        int64_t row = 0;
+        uint32_t sc = 0;
+        auto load_seg = [&]() {
+            key = keys[seg];
+            sc = src[seg];
+            row = g.rp[kcol(key, L, int(sc))];
+        };
+        if (t0 < tile1) load_seg();
+        if (EMIT) {
+            if (t0 < tile1) {
+                pass = pbits[tile * kBlock + threadIdx.x];
+                n_pass = __popc(pass);
+            }
+        } else if (t0 < tile1) {
+            for (uint64_t tb = t0; tb < t1; tb += 4) {
+                uint32_t vv[4], scj[4], ok = 0;
+                KI kk[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint64_t t = tb + j;
+                    vv[j] = 0;
+                    kk[j] = key;
+                    scj[j] = sc;
+                    if (t < t1) {
+                        if (soff[seg + 1] <= t) {
+                            do seg++;
+                            while (soff[seg + 1] <= t);
+                            load_seg();
+                        }
+                        vv[j] = uint32_t(g.col[row + int64_t(t - soff[seg])]);
+                        kk[j] = key;
+                        scj[j] = sc;
+                        ok |= 1u << j;
+                    }
+                }
+                // the colour of v not yet used, the degree mask and the image range
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (!((ok >> j) & 1u)) continue;
+                    const uint32_t cb = 1u << colors[uint64_t(kbid(kk[j], L)) * uint32_t(g.n) + vv[j]];
+                    if ((kset(kk[j], L) & cb) || !intro_ok(g, vv[j], a.degF)) ok &= ~(1u << j);
+                }
+                // every bag neighbour other than the candidates' source is
+                // adjacent (the source is, by construction)
+                for (int c = 0; c < nnb; c++) {
+                    uint64_t ek[4], h[4], xw[4];
+                    uint32_t probe = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const uint32_t w = kcol(kk[j], L, nb[c]);
+                        ek[j] = edge_key(w, vv[j]);
+                        h[j] = edge_cell(ek[j], g.ehmask);
+                        if (w == vv[j]) ok &= ~(1u << j);
+                        if (((ok >> j) & 1u) && uint32_t(nb[c]) != scj[j]) probe |= 1u << j;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; j++) xw[j] = ((probe >> j) & 1u) ? g.eh[h[j]] : ek[j];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if (!((probe >> j) & 1u)) continue;
+                        while (xw[j] != ek[j] && xw[j] != kEdgeEmpty) {
+                            h[j] = (h[j] + 1) & g.ehmask;
+                            xw[j] = g.eh[h[j]];
+                        }
+                        if (xw[j] != ek[j]) ok &= ~(1u << j);
+                    }
+                }
+                pass |= ok << (tb - t0);
+                n_pass += __popc(ok);
+            }
+            pbits[tile * kBlock + threadIdx.x] = uint16_t(pass);
+        }
+        uint64_t total;
+        uint64_t my = block_excl_scan(n_pass, &total);
+        if (!EMIT) {
+            if (threadIdx.x == 0) tcount[tile] = uint32_t(total);
+            continue;
+        }
+        if (!pass) continue;
+        uint64_t o = toff[tile] + my;
+        seg = seg0;
+        load_seg();
+        uint32_t rest = pass;
+        while (rest) {
+            const uint64_t t = t0 + uint64_t(__ffs(rest) - 1);
+            rest &= rest - 1u;
+            if (soff[seg + 1] <= t) {
+                do seg++;
+                while (soff[seg + 1] <= t);
+                load_seg();
+            }
+            const uint32_t v = uint32_t(g.col[row + int64_t(t - soff[seg])]);
+            const uint32_t bid = kbid(key, L);
+            uint32_t cols[5];
+            for (int c = 0, s2 = 0; c < LO.b; c++) cols[c] = (c == a.pos) ? v : kcol(key, L, s2++);
+            okeys[o] = kpack<KO>(bid, cols, LO.b, kset(key, L) | (1u << colors[uint64_t(bid) * uint32_t(g.n) + v]), LO);
+            ocnt[o] = cnt[seg];
+            o++;
+        }
+    }
+}
+
 // ---- launchers -------------------------------------------------------------
+
+void launch_entry_seglen(const DevTable& in, DevGraph g, const IntroArgs& a, uint32_t* slen, uint8_t* src,
+                         uint64_t* anchor_items, hipStream_t s) {
+    if (!in.n) return;
+    auto* ai = reinterpret_cast<unsigned long long*>(anchor_items);
+    if (in.lay.kw() == 1)
+        k_entry_seglen<uint64_t><<<grid_for(in.n), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, in.n, g, a, slen,
+                                                                   src, ai);
+    else
+        k_entry_seglen<u128><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.lay, in.n, g, a, slen, src, ai);
+}
+
+template <bool EMIT>
+static void entry_dispatch(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,
+                           const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, const uint64_t* toff,
+                           DevTable* out, uint16_t* pbits, hipStream_t s) {
+    const uint64_t tiles = expand_tiles(T);
+    if (!tiles) return;
+    const unsigned grid = unsigned(tiles < (1u << 20) ? tiles : (1u << 20));
+    Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
+    void* ok = out ? out->keys : nullptr;
+    uint64_t* oc = out ? out->cnt : nullptr;
+    const int ki = in.lay.kw(), ko = LO.kw();
+    if (ki == 1 && ko == 1)
+        k_expand_entry<uint64_t, uint64_t, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, src,
+                                                                         soff, in.n, T, g, colors, a, tcount, toff,
+                                                                         (uint64_t*)ok, oc, LO, pbits);
+    else if (ki == 1)
+        k_expand_entry<uint64_t, u128, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, src, soff,
+                                                                     in.n, T, g, colors, a, tcount, toff, (u128*)ok, oc,
+                                                                     LO, pbits);
+    else
+        k_expand_entry<u128, u128, EMIT><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, src, soff, in.n,
+                                                                 T, g, colors, a, tcount, toff, (u128*)ok, oc, LO,
+                                                                 pbits);
+}
+
+void launch_entry_count(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,
+                        const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, uint16_t* pbits, hipStream_t s) {
+    const uint64_t tiles = expand_tiles(T);
+    if (!tiles) return;
+    k_expand_bounds<<<grid_for(tiles), kBlock, 0, s>>>(soff, in.n, nullptr, 0, T, true,
+                                                      reinterpret_cast<uint64_t*>(pbits + tiles * kBlock));
+    entry_dispatch<false>(in, src, soff, T, g, colors, a, tcount, nullptr, nullptr, pbits, s);
+}
+
+void launch_entry_emit(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,
+                       const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, const uint16_t* pbits,
+                       DevTable& out, hipStream_t s) {
+    entry_dispatch<true>(in, src, soff, T, g, colors, a, nullptr, toff, &out, const_cast<uint16_t*>(pbits), s);
+}
 
 void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64_t* woff, uint64_t G, uint64_t W,
                         DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* slen, hipStream_t s) {

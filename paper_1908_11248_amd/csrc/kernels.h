@@ -119,6 +119,17 @@ void launch_push_seglen(const DevTable& in, const uint64_t* gstart, const uint64
 void launch_pull_seglen(const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g, int degF, uint32_t* slen,
                         hipStream_t s);
 uint64_t expand_tiles(uint64_t T);
+// entry-wise form: one segment per child entry, candidates from the bag
+// neighbour of u whose image has the fewest neighbours (src[e], a child
+// column), every other bag neighbour an edge test; output in (entry,
+// candidate) order with v at column pos (to be re-sorted on columns 0..pos)
+void launch_entry_seglen(const DevTable& in, DevGraph g, const IntroArgs& a, uint32_t* slen, uint8_t* src,
+                         uint64_t* anchor_items, hipStream_t s);
+void launch_entry_count(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,
+                        const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, uint16_t* pbits, hipStream_t s);
+void launch_entry_emit(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,
+                       const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, const uint16_t* pbits,
+                       DevTable& out, hipStream_t s);
 // survivor bits of the count pass and the tiles' segment and group bounds,
 // both written by launch_expand_count and read back by the emit pass:
 // expand_pass_words(T) words

@@ -44,6 +44,7 @@ int run_one(cc_context* ctx, Lane& lane, const cc_graph* g, const QueryRun& q, u
         rq.dec = q.d;
         rq.degree_mask = !(flags & CC_NO_DEGREE_MASK);
         rq.sparse_only = (flags & CC_SPARSE_TABLES) != 0;
+        rq.classic_expand = (flags & CC_CLASSIC_EXPAND) != 0;
         rq.max_entries = max_entries;
         run_dp_waves(ctx, lane, rq, r);
         return CC_OK;

@@ -240,3 +240,30 @@ def test_workload3_sampled_vertices(ctx):
     rng = np.random.default_rng(0)
     for v in rng.choice(g.n, 40, replace=False):
         assert int(pv[v]) == O.brute_count(g, pat, col, fix0=int(v)), v
+
+
+@pytest.mark.parametrize("gname,make", [("ba600", lambda: W.barabasi_albert(600, 3, 12)),
+                                        ("rgg800", lambda: W.rgg(800, 8, 13)),
+                                        ("cl1500", lambda: W.chung_lu(1500, 2.5, 6.0, 14))],
+                         ids=["ba600", "rgg800", "cl1500"])
+def test_entry_and_classic_introduce_match_oracle(ctx, gname, make):
+    """Introduce nodes whose vertex has two or more bag neighbours: the
+    entry-wise form (candidates from the lowest-degree neighbour's row, then
+    a re-sort) and the fixed-column form give the oracle's counts, flags and
+    per-node table sizes on heavy-tailed and clustered hosts."""
+    g = make()
+    pats = [W.complete(4), W.pattern_B(), W.ladder(4), W.cycle(6), W.partial_3tree(8, 5),
+            W.partial_3tree(9, 21), W.partial_3tree(10, 8)]
+    G = gpu_graph(ctx, g)
+    for pat in pats:
+        D = cc.build_decomposition(pat.n, pat.edges)
+        td = D.export()
+        C = cc.color(ctx, G, pat.n, 31, 2)
+        ref = [O.dp_count(g, pat, pat.n, O.color_array(31, b, g.n, pat.n), td=td, sizes=True) for b in range(2)]
+        for flags in (0, cc.CC_CLASSIC_EXPAND):
+            say("introduce forms", gname, pat.name, "flags", flags)
+            counts, ovf = cc.count(ctx, G, C, D, flags)
+            sizes = ctx.last_table_sizes()
+            for b in range(2):
+                assert int(counts[b]) == ref[b]["count"] and bool(ovf[b]) == ref[b]["overflow"], (gname, pat.name, flags, b)
+            assert np.array_equal(sizes, ref[0]["sizes"] + ref[1]["sizes"]), (gname, pat.name, flags)
