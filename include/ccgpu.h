@@ -31,11 +31,12 @@
  *     results synchronise the context's stream before they return.
  *   - Colours are 0-based: colour c of a k-colouring is c in [0, k).
  *   - Limits (CC_ERANGE when exceeded): a decomposition takes
- *     1 <= n_F <= 16 pattern vertices; a colouring takes 1 <= k <= 12 colours
- *     and at most 2^20 colourings; counting and enumeration need
+ *     1 <= n_F <= 16 pattern vertices and treewidth <= 3; a colouring takes
+ *     1 <= k <= 16 colours and at most 2^20 colourings; counting needs
  *     n_F <= k (colour sets are k-bit masks; the paper uses 32-bit masks for
- *     n_F <= 32, Sec. 3.2); n_G < 2^31; the packed table key (colouring
- *     index, bag images, colour set) must fit 128 bits.
+ *     n_F <= 32, Sec. 3.2), enumeration and vertex sets k <= 12; n_G < 2^31;
+ *     the packed table key (colouring index, bag images, colour set) must
+ *     fit 128 bits.
  */
 #ifndef CCGPU_H
 #define CCGPU_H
@@ -211,6 +212,37 @@ int cc_enumerate(cc_context *ctx, const cc_graph *g, const cc_coloring *c, int32
                  const cc_decomp *d, uint64_t cap, int32_t *rows, uint64_t *n_rows,
                  uint64_t *total);
 
+/* Occurrences that differ in their vertex sets (Sec. 5.2: the method can
+ * count every mapping, the default, or only occurrences with distinct vertex
+ * sets).  For colouring b: *n_mappings = the colourful mappings (as
+ * cc_count), *n_sets = the distinct sets {Phi(0), ..., Phi(n_F - 1)} among
+ * them; sets (if not NULL, cap rows of n_F int32) receives those sets, each
+ * sorted ascending, in lexicographic order.  CC_ERANGE when the mappings
+ * exceed cap (every mapping is enumerated to find the sets). */
+int cc_vertex_sets(cc_context *ctx, const cc_graph *g, const cc_coloring *c, int32_t b, const cc_decomp *d,
+                   uint64_t cap, int32_t *sets, uint64_t *n_sets, uint64_t *n_mappings);
+
+/* Repetition driver of the randomised algorithm (Sec. 2.1, Sec. 5.2):
+ * colourings 0, 1, 2, ... of cc_color(k = n_F, seed) are run in batches of
+ * `batch` until l = ceil(e^{n_F} ln(1/eps)) colourings are done (then a
+ * fixed occurrence is missed with probability at most eps) or at least
+ * max_solutions distinct solutions were found.  After each colouring with a
+ * nonzero count its first max_solutions mappings (lexicographic) are added
+ * to the set of solutions; solutions are mappings, or with
+ * CC_SEARCH_DISTINCT_SETS their sorted vertex sets.  rows[max_solutions][n_F]
+ * receives the lexicographically first min(found, max_solutions) solutions;
+ * *colourings_run and *colourings_planned (= l) report the repetitions. */
+#define CC_SEARCH_DISTINCT_SETS 1u
+typedef struct {
+    double eps;             /* error bound in (0, 1); the paper uses 1/e */
+    uint64_t seed;          /* colouring seed */
+    int32_t batch;          /* colourings per device batch (0: 16) */
+    uint64_t max_solutions; /* stop once this many distinct solutions are found */
+    uint32_t flags;         /* CC_SEARCH_DISTINCT_SETS */
+} cc_search_opts;
+int cc_search(cc_context *ctx, const cc_graph *g, const cc_decomp *d, const cc_search_opts *opts, int32_t *rows,
+              uint64_t *n_rows, uint64_t *colourings_run, uint64_t *colourings_planned);
+
 /* Per-node statistics of the last cc_count / cc_enumerate call on ctx:
  * entries[i] = sum over colourings of |D_x| for TD node i (export order),
  * up to cap nodes; *n_nodes receives the node count. */
@@ -236,6 +268,22 @@ int cc_profile_enable(cc_context *ctx, int enable);
 int cc_profile_filter(cc_context *ctx, const char *name, uint32_t every);
 int cc_profile_read(cc_context *ctx, cc_kernel_stat *stats, size_t cap, size_t *n);
 
+/* Captured counts (HIP graphs).  cc_plan_create records the device work of
+ * one count of pattern d with k colours and num_colorings colourings on g
+ * (every kernel of the plan, which on dense one-column tables needs no host
+ * round trip between steps) into a HIP graph; cc_plan_count colours with
+ * cc_color(k, seed) numbering into the plan's own buffer and replays the
+ * graph, writing counts[num_colorings] (and overflow) like cc_count.  The
+ * plan owns its colour buffer and a slice of the context arena sized by one
+ * eager run at creation, and its own stream.  CC_ERANGE for plans that do
+ * not run on dense tables (tables with two or more bag vertices read their
+ * sizes back between steps).  flags: CC_NO_DEGREE_MASK. */
+typedef struct cc_plan cc_plan;
+int cc_plan_create(cc_context *ctx, const cc_graph *g, const cc_decomp *d, int32_t k, int32_t num_colorings,
+                   uint32_t flags, cc_plan **out);
+int cc_plan_count(cc_plan *p, uint64_t seed, uint64_t *counts, uint8_t *overflow);
+int cc_plan_destroy(cc_plan *p);
+
 /* ---------------------------------------------------------------------- */
 /* Batched queries: many (decomposition, colouring) pairs over one graph,
  * scheduled together.  counts_flat / overflow_flat receive, query after
@@ -251,8 +299,23 @@ int cc_count_batch(cc_context *ctx, const cc_graph *g, int32_t nq, const cc_quer
  * out of arena memory while others hold it is re-run alone.  Results are
  * identical to one cc_count per query. */
 int cc_set_batch_lanes(cc_context *ctx, int32_t lanes);
-/* Autotuner: times cc_count_batch on the given queries with 1, 2, 4 and 8
- * lanes and keeps the fastest for the context; *best receives it. */
+/* Schedule of a context: concurrent lanes of a batch; the introduce form
+ * (entry-wise when it walks fewer than 1/entry_factor of the fixed column's
+ * candidates); forget and join on sorted lists add up by sorting when
+ * k > sort_above_k, else in dense 2^k LDS accumulators (k <= 12 only).
+ * Defaults: 4 lanes (0 = default), 3, 12.  Every schedule gives the same
+ * results. */
+typedef struct {
+    int32_t lanes;
+    int32_t entry_factor;
+    int32_t sort_above_k;
+} cc_schedule;
+int cc_get_schedule(const cc_context *ctx, cc_schedule *out);
+int cc_set_schedule(cc_context *ctx, const cc_schedule *s);
+/* Autotuner: times cc_count_batch on the given queries and keeps the
+ * fastest schedule for the context, by coordinate descent: lanes 1, 2, 4, 8;
+ * then entry_factor 1, 3, 8; then sort_above_k 12, 8, 0.  The counts of
+ * every trial must agree (CC_EDEVICE otherwise).  *best receives the lanes. */
 int cc_tune_batch(cc_context *ctx, const cc_graph *g, int32_t nq, const cc_query *q, uint32_t flags,
                   int32_t *best);
 /* Work budget: with max_entries > 0 no DP table of one launch may hold more

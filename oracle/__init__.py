@@ -17,6 +17,8 @@ Valla, arXiv 1908.11248) through ctypes:
 * ``dp_count``         -- the DP over the nice TD with counts (Sec. 3.1)
 * ``dp_count_range``   -- the same, for mappings with Phi(0) in a range
 * ``dp_enumerate``     -- reconstruction R(x, M) (Sec. 4)
+* ``vertex_sets``      -- distinct vertex sets of the mappings (Sec. 5.2)
+* ``repetitions``, ``search`` -- the repetition driver (Sec. 2.1, Sec. 5.2)
 
 Every function here is pinned by tests in ``tests/test_oracle_*.py`` against
 brute force, closed forms and invariants (see the module docstrings there).
@@ -152,9 +154,15 @@ def validate_td(pat, td) -> int:
     return int(_load().orc_validate_td(nF, mF, _p(e), _p(td), int(td.size)))
 
 
-def dp_count(g, pat, k, colors, td=None, degmask=True, per_root_vertex=False, sizes=False):
+def _opts(degmask, distbound):
+    return (1 if degmask else 0) | (0 if distbound else 2)
+
+
+def dp_count(g, pat, k, colors, td=None, degmask=True, per_root_vertex=False, sizes=False, distbound=True):
     """Count of colourful mappings by the DP.  Returns a dict with 'count',
-    'overflow' and optionally 'per_root_vertex' (np.uint64[n]) and 'sizes'."""
+    'overflow' and optionally 'per_root_vertex' (np.uint64[n]) and 'sizes'.
+    degmask / distbound switch the degree mask and the distance bound of
+    Sec. 3.2 (both prune entries that cannot complete; counts are the same)."""
     n, rp, col = _graph(g)
     nF, mF, e = _pattern(pat)
     if td is None:
@@ -166,7 +174,7 @@ def dp_count(g, pat, k, colors, td=None, degmask=True, per_root_vertex=False, si
     prv = np.zeros(max(n, 1), dtype=np.uint64) if per_root_vertex else None
     sz = np.zeros(int(td[0]), dtype=np.int64) if sizes else None
     rc = _load().orc_count(n, _p(rp), _p(col), nF, mF, _p(e), k, _p(colors), _p(td), int(td.size),
-                           1 if degmask else 0, _p(cnt), _p(ovf),
+                           _opts(degmask, distbound), _p(cnt), _p(ovf),
                            _p(prv) if prv is not None else None,
                            _p(sz) if sz is not None else None)
     _check(rc, "dp_count")
@@ -178,7 +186,7 @@ def dp_count(g, pat, k, colors, td=None, degmask=True, per_root_vertex=False, si
     return out
 
 
-def dp_count_range(g, pat, k, colors, lo, hi, td=None, degmask=True, sizes=False):
+def dp_count_range(g, pat, k, colors, lo, hi, td=None, degmask=True, sizes=False, distbound=True):
     """dp_count restricted to the mappings with Phi(0) in [lo, hi)."""
     n, rp, col = _graph(g)
     nF, mF, e = _pattern(pat)
@@ -190,7 +198,7 @@ def dp_count_range(g, pat, k, colors, lo, hi, td=None, degmask=True, sizes=False
     ovf = np.zeros(1, dtype=np.uint8)
     sz = np.zeros(int(td[0]), dtype=np.int64) if sizes else None
     rc = _load().orc_count_range(n, _p(rp), _p(col), nF, mF, _p(e), k, _p(colors), _p(td), int(td.size),
-                                 1 if degmask else 0, int(lo), int(hi), _p(cnt), _p(ovf),
+                                 _opts(degmask, distbound), int(lo), int(hi), _p(cnt), _p(ovf),
                                  _p(sz) if sz is not None else None)
     _check(rc, "dp_count_range")
     out = {"count": int(cnt[0]), "overflow": bool(ovf[0])}
@@ -199,7 +207,7 @@ def dp_count_range(g, pat, k, colors, lo, hi, td=None, degmask=True, sizes=False
     return out
 
 
-def dp_enumerate(g, pat, k, colors, cap, td=None, degmask=True):
+def dp_enumerate(g, pat, k, colors, cap, td=None, degmask=True, distbound=True):
     """(rows int32[min(total,cap), nF] lexicographically sorted, total)."""
     n, rp, col = _graph(g)
     nF, mF, e = _pattern(pat)
@@ -208,12 +216,49 @@ def dp_enumerate(g, pat, k, colors, cap, td=None, degmask=True):
     td = np.ascontiguousarray(td, dtype=np.int32)
     colors = np.ascontiguousarray(colors, dtype=np.uint8)
     # rows buffer bounded by the true total, found with a count first
-    total = dp_count(g, pat, k, colors, td=td, degmask=degmask)["count"]
+    total = dp_count(g, pat, k, colors, td=td, degmask=degmask, distbound=distbound)["count"]
     m = min(total, cap)
     rows = np.empty((max(m, 1), nF), dtype=np.int32)
     nr = np.zeros(1, dtype=np.uint64)
     tot = np.zeros(1, dtype=np.uint64)
     rc = _load().orc_enumerate(n, _p(rp), _p(col), nF, mF, _p(e), k, _p(colors), _p(td),
-                               int(td.size), 1 if degmask else 0, cap, _p(rows), _p(nr), _p(tot))
+                               int(td.size), _opts(degmask, distbound), cap, _p(rows), _p(nr), _p(tot))
     _check(rc, "dp_enumerate")
     return rows[: int(nr[0])].copy(), int(tot[0])
+
+
+def vertex_sets(g, pat, k, colors):
+    """Distinct vertex sets of the colourful mappings (the paper's second
+    counting mode, Sec. 5.2): sorted tuples, in lexicographic order."""
+    rows, _ = dp_enumerate(g, pat, k, colors, 2**62)
+    return sorted({tuple(sorted(int(x) for x in r)) for r in rows})
+
+
+def repetitions(n_f, eps):
+    """Colourings the randomised algorithm runs for error bound eps (Sec. 2.1):
+    each run reveals a fixed occurrence with probability at least e^{-n_F},
+    so ceil(e^{n_F} ln(1/eps)) runs miss it with probability at most eps."""
+    import math
+
+    return int(math.ceil(math.exp(n_f) * math.log(1.0 / eps)))
+
+
+def search(g, pat, eps, seed, max_solutions, distinct_sets=False):
+    """The repetition driver step by step: colourings b = 0, 1, ... of the
+    seed (k = n_F colours) until repetitions(n_F, eps) are done or at least
+    max_solutions distinct solutions are known; each colouring adds its first
+    max_solutions mappings (or their sorted vertex sets).  Returns (the
+    lexicographically first min(found, max_solutions) solutions, colourings
+    run)."""
+    k = pat.n
+    planned = repetitions(pat.n, eps)
+    found = set()
+    run = 0
+    while run < planned and len(found) < max_solutions:
+        col = color_array(seed, run, g.n, k)
+        run += 1
+        rows, _ = dp_enumerate(g, pat, k, col, max_solutions)
+        for r in rows:
+            t = tuple(int(x) for x in r)
+            found.add(tuple(sorted(t)) if distinct_sets else t)
+    return sorted(found)[:max_solutions], run

@@ -640,6 +640,15 @@ static int sort_and_merge(table_t *t, int *ovf) {
     return ORC_OK;
 }
 
+/* Options of a DP run (the `degmask` argument of the entry points):
+ * bit 0: degree mask on (Sec. 3.2 "Masking Unprofitable Mappings");
+ * bit 1: distance bound OFF (Sec. 3.2, last paragraphs of "Mapping Expansion
+ * Optimizations": by default an introduced vertex with no bag neighbour only
+ * takes images within distance dist_F(w, u) of phi(w) for the bag vertex w
+ * nearest to u in F). */
+#define ORC_DEGMASK 1
+#define ORC_NO_DISTBOUND 2
+
 typedef struct {
     const graph_t *g;
     const pattern_t *F;
@@ -647,6 +656,7 @@ typedef struct {
     int degmask;
     int ovf;
     int32_t lo0, hi0; /* images allowed for pattern vertex 0: [lo0, hi0) */
+    int distbound;
 } dpctx_t;
 
 /* deg_G(v) >= deg_F(u) (Sec. 3.2 "Masking Unprofitable Mappings"), and for
@@ -655,7 +665,55 @@ typedef struct {
  * range, so counts over disjoint ranges add up to the full count. */
 static int deg_ok(const dpctx_t *c, int u, int32_t v) {
     if (u == 0 && (v < c->lo0 || v >= c->hi0)) return 0;
-    return !c->degmask || gdeg(c->g, v) >= popc(c->F->adj[u]);
+    return !(c->degmask & ORC_DEGMASK) || gdeg(c->g, v) >= popc(c->F->adj[u]);
+}
+
+/* distances in F from u (-1: another component) */
+static void pattern_dist(const pattern_t *F, int u, int *dist) {
+    int queue[ORC_MAXF], qh = 0, qt = 0;
+    for (int v = 0; v < F->n; v++) dist[v] = -1;
+    dist[u] = 0;
+    queue[qt++] = u;
+    while (qh < qt) {
+        int x = queue[qh++];
+        for (int y = 0; y < F->n; y++)
+            if ((F->adj[x] >> y & 1) && dist[y] < 0) {
+                dist[y] = dist[x] + 1;
+                queue[qt++] = y;
+            }
+    }
+}
+
+/* The vertices of G within distance r of a, ascending (plain BFS; *out is
+ * malloc'ed, *cnt its length). */
+static int ball(const graph_t *g, int32_t a, int r, int32_t **out, int64_t *cnt) {
+    int32_t *dist = malloc(sizeof(int32_t) * (size_t)g->n);
+    int32_t *q = malloc(sizeof(int32_t) * (size_t)g->n);
+    if (!dist || !q) {
+        free(dist);
+        free(q);
+        return ORC_ENOMEM;
+    }
+    for (int32_t v = 0; v < g->n; v++) dist[v] = -1;
+    int64_t qh = 0, qt = 0;
+    dist[a] = 0;
+    q[qt++] = a;
+    while (qh < qt) {
+        int32_t x = q[qh++];
+        if (dist[x] == r) continue;
+        for (int64_t e = g->rp[x]; e < g->rp[x + 1]; e++)
+            if (dist[g->col[e]] < 0) {
+                dist[g->col[e]] = dist[x] + 1;
+                q[qt++] = g->col[e];
+            }
+    }
+    int64_t m = 0;
+    for (int32_t v = 0; v < g->n; v++)
+        if (dist[v] >= 0) q[m++] = v;
+    free(dist);
+    *out = q;
+    *cnt = m;
+    return ORC_OK;
 }
 
 /* Leaf: u mapped to every vertex of G, colour set {zeta(v)} (Sec. 3.1). */
@@ -678,16 +736,37 @@ static int dp_intro(dpctx_t *c, int u, const table_t *y, table_t *out) {
     int npos[ORC_MAXF], nn = 0;
     for (int i = 0; i < y->b; i++)
         if (c->F->adj[u] >> y->bagv[i] & 1) { npos[nn++] = i; nb_in_bag |= 1u << i; }
+    /* no bag neighbour: the bag vertex nearest to u in F (smallest id on a
+     * tie) bounds the candidates by its distance */
+    int near = -1, rad = 0;
+    if (!nn && c->distbound) {
+        int dist[ORC_MAXF];
+        pattern_dist(c->F, u, dist);
+        for (int i = 0; i < y->b; i++) {
+            int d = dist[y->bagv[i]];
+            if (d > 0 && (near < 0 || d < rad)) {
+                near = i;
+                rad = d;
+            }
+        }
+    }
     int32_t phi[ORC_MAXF];
     for (size_t e = 0; e < y->n; e++) {
         const int32_t *pp = y->phi + e * y->b;
         int64_t lo = 0, hi = c->g->n;
         const int32_t *cand = NULL;
+        int32_t *ballv = NULL;
         if (nn) {
             int32_t w = pp[npos[0]];
             lo = c->g->rp[w];
             hi = c->g->rp[w + 1];
             cand = c->g->col;
+        } else if (near >= 0) {
+            int64_t m;
+            if (ball(c->g, pp[near], rad, &ballv, &m)) return ORC_ENOMEM;
+            lo = 0;
+            hi = m;
+            cand = ballv;
         }
         for (int64_t t = lo; t < hi; t++) {
             int32_t v = cand ? cand[t] : (int32_t)t;
@@ -698,8 +777,12 @@ static int dp_intro(dpctx_t *c, int u, const table_t *y, table_t *out) {
                 if (!has_edge(c->g, pp[npos[j]], v)) ok = 0;
             if (!ok) continue;
             for (int i = 0, k = 0; i < out->b; i++) phi[i] = (i == pu) ? v : pp[k++];
-            if (tab_push(out, phi, y->C[e] | cb, y->cnt[e])) return ORC_ENOMEM;
+            if (tab_push(out, phi, y->C[e] | cb, y->cnt[e])) {
+                free(ballv);
+                return ORC_ENOMEM;
+            }
         }
+        free(ballv);
     }
     return ORC_OK;
 }
@@ -839,7 +922,7 @@ static int count_in_range(int32_t n, const int64_t *rp, const int32_t *colidx, i
     int N = td[0];
     table_t *tabs = calloc(N, sizeof(table_t));
     if (!tabs) return ORC_ENOMEM;
-    dpctx_t c = {&g, &F, colors, degmask, 0, lo0, hi0};
+    dpctx_t c = {&g, &F, colors, degmask, 0, lo0, hi0, !(degmask & ORC_NO_DISTBOUND)};
     /* keep the root's child when the per-vertex split is wanted */
     rc = dp_run(&c, td, tabs, per_root_vertex != NULL, sizes);
     if (rc == ORC_OK) {
@@ -1197,7 +1280,7 @@ int orc_enumerate(int32_t n, const int64_t *rp, const int32_t *colidx, int32_t n
     int N = td[0];
     table_t *tabs = calloc(N, sizeof(table_t));
     if (!tabs) return ORC_ENOMEM;
-    dpctx_t c = {&g, &F, colors, degmask, 0, 0, n};
+    dpctx_t c = {&g, &F, colors, degmask, 0, 0, n, !(degmask & ORC_NO_DISTBOUND)};
     rc = dp_run(&c, td, tabs, 1, NULL);
     mset_t M = {0};
     llist_t L = {0};

@@ -37,7 +37,8 @@ EXPORTS = [
     "cc_profile_enable", "cc_profile_filter", "cc_profile_read", "cc_decomp_describe",
     "cc_set_batch_lanes", "cc_tune_batch", "cc_set_table_budget",
     "cc_server_start", "cc_server_submit", "cc_server_poll", "cc_server_wait", "cc_server_stop",
-    "cc_count_noalloc", "cc_count_range", "cc_last_chunk_count", "cc_estimate_memory",
+    "cc_count_noalloc", "cc_count_range", "cc_last_chunk_count", "cc_estimate_memory", "cc_vertex_sets",
+    "cc_search", "cc_plan_create", "cc_plan_count", "cc_plan_destroy", "cc_get_schedule", "cc_set_schedule",
 ]
 
 
@@ -92,6 +93,13 @@ def lib():
             "cc_count_range": (ctypes.c_int, [P, P, P, P, U32, I32, I32, P, P]),
             "cc_last_chunk_count": (I32, [P]),
             "cc_estimate_memory": (ctypes.c_int, [P, P, I32, I32, P, P]),
+            "cc_vertex_sets": (ctypes.c_int, [P, P, P, I32, P, U64, P, P, P]),
+            "cc_search": (ctypes.c_int, [P, P, P, P, P, P, P, P]),
+            "cc_plan_create": (ctypes.c_int, [P, P, P, I32, I32, U32, PP]),
+            "cc_plan_count": (ctypes.c_int, [P, U64, P, P]),
+            "cc_plan_destroy": (ctypes.c_int, [P]),
+            "cc_get_schedule": (ctypes.c_int, [P, P]),
+            "cc_set_schedule": (ctypes.c_int, [P, P]),
             "cc_count_by_vertex": (ctypes.c_int, [P, P, P, I32, P, U32, P, P, P]),
             "cc_enumerate": (ctypes.c_int, [P, P, P, I32, P, U64, P, P, P]),
             "cc_last_table_sizes": (ctypes.c_int, [P, P, SZ, ctypes.POINTER(SZ)]),
@@ -197,6 +205,10 @@ class Decomp(_Handle):
         return buf
 
 
+class _Schedule(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("entry_factor", ctypes.c_int32), ("sort_above_k", ctypes.c_int32)]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
                 ("algo_bytes", ctypes.c_double)]
@@ -263,6 +275,15 @@ class Context(_Handle):
     def set_batch_lanes(self, lanes: int):
         _check(lib().cc_set_batch_lanes(self.ptr, lanes))
 
+    def schedule(self) -> dict:
+        s = _Schedule()
+        _check(lib().cc_get_schedule(self.ptr, ctypes.byref(s)))
+        return {"lanes": s.lanes, "entry_factor": s.entry_factor, "sort_above_k": s.sort_above_k}
+
+    def set_schedule(self, lanes: int = 0, entry_factor: int = 3, sort_above_k: int = 12):
+        s = _Schedule(lanes, entry_factor, sort_above_k)
+        _check(lib().cc_set_schedule(self.ptr, ctypes.byref(s)))
+
     def set_table_budget(self, max_entries: int):
         _check(lib().cc_set_table_budget(self.ptr, max_entries))
 
@@ -328,6 +349,53 @@ def count(ctx: Context, g: Graph, c: Coloring, d: Decomp, flags: int = 0):
     ovf = np.zeros(c.num, dtype=np.uint8)
     _check(lib().cc_count(ctx.ptr, g.ptr, c.ptr, d.ptr, flags, _p(counts), _p(ovf)))
     return counts, ovf.astype(bool)
+
+
+def vertex_sets(ctx: Context, g: Graph, c: Coloring, b: int, d: Decomp, cap: int):
+    """(distinct vertex sets int32[n_sets, n_F] sorted, n_mappings) of colouring b."""
+    sets = np.zeros((max(cap, 1), d.n_F), dtype=np.int32)
+    ns = np.zeros(1, dtype=np.uint64)
+    nm = np.zeros(1, dtype=np.uint64)
+    _check(lib().cc_vertex_sets(ctx.ptr, g.ptr, c.ptr, b, d.ptr, cap, _p(sets), _p(ns), _p(nm)))
+    return sets[: int(ns[0])].copy(), int(nm[0])
+
+
+CC_SEARCH_DISTINCT_SETS = 1
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("seed", ctypes.c_uint64), ("batch", ctypes.c_int32),
+                ("max_solutions", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
+
+
+def search(ctx: Context, g: Graph, d: Decomp, eps: float, seed: int, max_solutions: int, batch: int = 16,
+           distinct_sets: bool = False):
+    """Repetition driver: (solutions int32[m, n_F], colourings run, colourings planned)."""
+    opts = SearchOpts(eps, seed & (2**64 - 1), batch, max_solutions, CC_SEARCH_DISTINCT_SETS if distinct_sets else 0)
+    rows = np.zeros((max_solutions, d.n_F), dtype=np.int32)
+    nr = ctypes.c_uint64(0)
+    run = ctypes.c_uint64(0)
+    planned = ctypes.c_uint64(0)
+    _check(lib().cc_search(ctx.ptr, g.ptr, d.ptr, ctypes.byref(opts), _p(rows), ctypes.byref(nr), ctypes.byref(run),
+                           ctypes.byref(planned)))
+    return rows[: nr.value].copy(), run.value, planned.value
+
+
+class Plan(_Handle):
+    """A count captured into a HIP graph (cc_plan_*): replay with new seeds."""
+    _free = "cc_plan_destroy"
+
+    def __init__(self, ctx: Context, g: Graph, d: Decomp, k: int, num_colorings: int, flags: int = 0):
+        out = ctypes.c_void_p()
+        _check(lib().cc_plan_create(ctx.ptr, g.ptr, d.ptr, k, num_colorings, flags, ctypes.byref(out)))
+        super().__init__(out.value)
+        self.ctx, self.g, self.d, self.num = ctx, g, d, num_colorings
+
+    def count(self, seed: int):
+        counts = np.zeros(self.num, dtype=np.uint64)
+        ovf = np.zeros(self.num, dtype=np.uint8)
+        _check(lib().cc_plan_count(self.ptr, seed & (2**64 - 1), _p(counts), _p(ovf)))
+        return counts, ovf.astype(bool)
 
 
 def estimate_memory(g: Graph, d: Decomp, k: int, num_colorings: int):

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libccgpu.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["kernels.hip", "expand.hip", "fused.hip", "slots.hip", "enumerate.hip", "engine.hip", "capi.cpp", "runtime.cpp",
-           "planner.cpp", "estimate.cpp"]
+           "planner.cpp", "estimate.cpp", "search.cpp", "graphplan.cpp"]
 ARCH = os.environ.get("CCGPU_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

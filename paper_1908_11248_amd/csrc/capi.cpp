@@ -263,6 +263,8 @@ void cc_graph_free(cc_graph* g) {
     if (g->esrc) (void)hipFree(g->esrc);
     if (g->heavy) (void)hipFree(g->heavy);
     if (g->ehash) (void)hipFree(g->ehash);
+    if (g->ball_pre) (void)hipFree(g->ball_pre);
+    if (g->ball_w2) (void)hipFree(g->ball_w2);
     delete g;
 }
 

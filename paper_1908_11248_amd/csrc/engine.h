@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -137,6 +138,9 @@ struct cc_context {
     int32_t last_chunks = 1;  // anchor-range chunks of the last single-query count
     uint64_t max_entries = 0;  // per-table budget (0: none)
     int batch_lanes = 0;       // lanes for cc_count_batch (0: tuned on first use)
+    // schedule choices (cc_tune_batch / cc_set_schedule):
+    int entry_factor = 3;      // entry-wise introduce when it walks < 1/entry_factor of the fixed column's rows
+    int sort_above_k = 12;     // sorted-list forget and join add up by sorting when k exceeds this (else dense LDS)
     uint16_t* slot_tables = nullptr;  // device: rank[2048] then unrank[2048] (slots.hip)
     uint32_t* slot_splits = nullptr;  // device: join split tables (slots.hip)
     uint64_t* slot_pack = nullptr;    // device: packed child slots of edge steps, k <= kSlotPackK
@@ -160,6 +164,12 @@ struct cc_graph {
     std::vector<int64_t> deg_mass;    // deg_mass[i] = sum of sorted_deg[i..n)
     double nb_degree = 0;             // mean degree of an edge's endpoint: sum d^2 / sum d
     double transitivity = 0;          // closed wedges / wedges (sampled)
+    // walk tables of the distance-bounded introduce, built on first use:
+    // ball_pre[e] = degrees of the neighbours before stored edge e in its row,
+    // ball_w2[v] = deg(v) + the degrees of v's neighbours
+    std::mutex ball_mu;
+    uint64_t* ball_pre = nullptr;
+    uint64_t* ball_w2 = nullptr;
     // vertices with degree >= d
     int64_t count_deg_at_least(int64_t d) const;
     // fraction of edge endpoints whose vertex has degree >= d
@@ -183,6 +193,13 @@ struct cc_decomp {
 
 namespace ccg {
 
+struct RunResult;
+// A run recorded into a HIP graph: the host work that turns the read-back
+// words into results, to call after each replay has synchronised.
+struct SlotCapture {
+    std::function<void(RunResult*, std::vector<uint64_t>*)> finish;
+};
+
 struct RunRequest {
     const cc_graph* g = nullptr;
     const uint8_t* colors = nullptr;  // device [B][n]
@@ -202,6 +219,7 @@ struct RunRequest {
     Arena* arena = nullptr;    // device memory of the run's tables and scratch (nullptr: the context's)
     bool no_alloc = false;     // make no device or pinned-host allocation (fail with CC_ERANGE instead)
     bool classic_expand = false;  // never the entry-wise introduce (tests compare both)
+    SlotCapture* capture = nullptr;  // record the device work only (dense-table plans; the stream is capturing)
 };
 
 // contributor index of one step's table (enumeration)
@@ -223,6 +241,7 @@ struct RunResult {
     std::vector<uint32_t> root_sets;   // [B][words]: bitmap of the colour sets at the root
     size_t peak_bytes = 0;             // largest arena footprint of the run
     int chunks = 1;                    // anchor-range chunks the result was computed in
+    bool dense = false;                // ran on dense one-column tables
 };
 
 void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out);

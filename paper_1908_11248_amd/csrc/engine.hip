@@ -910,19 +910,42 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
         out->per_vertex.assign(units, 0);
         hip_check(hipMemcpyAsync(out->per_vertex.data(), pv, 8 * units, hipMemcpyDeviceToHost, s), "copy per-vertex");
     }
+    // Host side, once the stream has run: counts, flags and node sizes from
+    // the read-back words.  A captured run (HIP graph) keeps it to call after
+    // each replay.
+    const std::vector<int64_t> prefilled = out->node_sizes;
+    const uint64_t max_entries = rq.max_entries;
+    const size_t n_nodes = dec.nodes.size();
+    auto finish = [host, B, nsz_words, cwords, budgeted, node_of, prefilled, max_entries,
+                   n_nodes](RunResult* r, std::vector<uint64_t>* sizes_out) {
+        r->node_sizes = prefilled;
+        r->counts.assign(host, host + B);
+        const std::vector<uint64_t> sizes(host + B, host + B + nsz_words);
+        const uint32_t* of = reinterpret_cast<const uint32_t*>(host + B + nsz_words);
+        const uint32_t* cs = of + B;
+        for (int j : budgeted)
+            if (max_entries && sizes[j] > max_entries)
+                throw CcError{CC_ERANGE,
+                              "a DP table of " + std::to_string(sizes[j]) + " entries exceeds the per-table budget of " +
+                                  std::to_string(max_entries),
+                              true};
+        for (auto& nd : node_of) r->node_sizes[nd.first] = int64_t(sizes[nd.second]);
+        r->overflow.assign(B, 0);
+        for (int b = 0; b < B; b++) r->overflow[b] = of[b] ? 1 : 0;
+        int64_t nzr = 0;
+        for (uint64_t i = 0; i < uint64_t(B) * cwords; i++) nzr += __builtin_popcount(cs[i]);
+        r->node_sizes[n_nodes - 1] = nzr;
+        r->root_sets.assign(cs, cs + uint64_t(B) * cwords);
+        if (sizes_out) *sizes_out = sizes;
+    };
+    if (rq.capture) {  // graph capture: nothing may wait for the stream
+        rq.capture->finish = finish;
+        return;
+    }
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     X.synced();
-    out->counts.assign(host, host + B);
-    const std::vector<uint64_t> sizes(host + B, host + B + nsz_words);
-    const uint32_t* of = reinterpret_cast<const uint32_t*>(host + B + nsz_words);
-    const uint32_t* cs = of + B;
-    for (int j : budgeted)
-        if (rq.max_entries && sizes[j] > rq.max_entries)
-            throw CcError{CC_ERANGE,
-                          "a DP table of " + std::to_string(sizes[j]) + " entries exceeds the per-table budget of " +
-                              std::to_string(rq.max_entries),
-                          true};
-    for (auto& nd : node_of) out->node_sizes[nd.first] = int64_t(sizes[nd.second]);
+    std::vector<uint64_t> sizes;
+    finish(out, &sizes);
     // entries of step t's table: its size word (a fused introduce + forget
     // pair keeps it with the introduce), through aliases of identical tables
     auto entries_of = [&](int t) -> double {
@@ -936,12 +959,6 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
                                         sb.extra);
     X.lane.prof.set_bytes(h_root, entries_of(plan.root_child) * entry_bytes(1));
     X.lane.prof.resolve();
-    out->overflow.assign(B, 0);
-    for (int b = 0; b < B; b++) out->overflow[b] = of[b] ? 1 : 0;
-    int64_t nzr = 0;
-    for (uint64_t i = 0; i < uint64_t(B) * cwords; i++) nzr += __builtin_popcount(cs[i]);
-    out->node_sizes[dec.nodes.size() - 1] = nzr;
-    out->root_sets.assign(cs, cs + uint64_t(B) * cwords);
     X.release(pv);
     X.release(part_base);
     X.release(res);
@@ -975,6 +992,8 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     const int B = rq.B, k = rq.k;
     if (k < dec.n || k > kMaxColours)
         fail(CC_ERANGE, "colours k must satisfy n_F <= k <= " + std::to_string(kMaxColours));
+    if (k > kDenseColours && rq.links)
+        fail(CC_ERANGE, "enumeration needs k <= " + std::to_string(kDenseColours));
     if (B < 1) fail(CC_EINVAL, "no colourings");
     for (int b = 1; b <= plan.max_bag; b++)
         if (table_layout(b, g.n, B, k).bits() > 128)
@@ -1014,10 +1033,14 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     // dense one-column tables when the plan allows them and they fit a
     // quarter of the arena (an anchor-range chunk runs on sorted lists)
     const bool chunked = rq.anchor_hi >= 0;
+    if (rq.capture && (rq.per_vertex || keep || chunked))
+        fail(CC_EINVAL, "only plain counts can be captured into a graph");
     std::vector<int> sz;
-    if (!keep && !rq.sparse_only && !chunked && slot_plan(plan, fuse, &sz)) {
+    if (!keep && !rq.sparse_only && !chunked && k <= kDenseColours && slot_plan(plan, fuse, &sz)) {
         const uint64_t units = uint64_t(B) * uint64_t(g.n);
-        bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= arena.size() / 4;
+        // a quarter of the shared arena; all of a captured plan's own slice
+        const uint64_t room = rq.capture ? arena.size() : arena.size() / 4;
+        bool fits = slot_peak_bytes(plan, fuse, virt, sz, units, k) <= room;
         // 32-bit block indices; slot offsets within one colouring's table below
         // 2^28 (they share a staged word with a colour)
         bool shape_ok = true;
@@ -1027,12 +1050,13 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 shape_ok = false;
         // too many colourings for dense tables, but one fits: waves of
         // colourings on dense tables beat one launch on sorted lists
-        if (shape_ok && !fits && B > 1 && !rq.no_alloc &&
-            slot_peak_bytes(plan, fuse, virt, sz, uint64_t(g.n), k) <= arena.size() / 4)
+        if (shape_ok && !fits && B > 1 && !rq.no_alloc && !rq.capture &&
+            slot_peak_bytes(plan, fuse, virt, sz, uint64_t(g.n), k) <= room)
             throw CcError{CC_ERANGE, "dense tables of " + std::to_string(B) + " colourings exceed a quarter of the arena",
                           true};
         fits = fits && shape_ok;
         if (fits) {
+            out->dense = true;
             try {
                 run_slots(ctx, X, rq, fuse, virt, sz, out);
             } catch (...) {
@@ -1044,6 +1068,8 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         }
     }
 
+    if (rq.capture)
+        fail(CC_ERANGE, "only plans whose tables all fit as dense one-column tables (trees) can be captured");
     uint32_t* ovf = X.alloc<uint32_t>(B);
     launch_fill_u32(ovf, 0, B, s);
     try {
@@ -1128,6 +1154,112 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 !links && !rq.classic_expand && tab[st.in0].n > 0 &&
                 ((st.kind == S_INTRO_PULL && st.nchk >= 1) ||
                  (st.kind == S_INTRO_PUSH && std::any_of(st.chk, st.chk + st.nchk, [&](int c) { return c >= st.pos; })));
+            // Distance-bounded introduce (u has no bag neighbour, but a bag
+            // vertex at distance 2 in F): candidates within two steps of
+            // that vertex's image instead of all of V(G).
+            int ball_col = -1;
+            if (st.kind == S_INTRO_PUSH && st.anchor < 0 && !links && !rq.classic_expand && tab[st.in0].n > 0 &&
+                g.m2 < (int64_t(1) << 32)) {
+                int dist[32];
+                for (int v = 0; v < 32; v++) dist[v] = -1;
+                int queue[32], qh = 0, qt = 0;
+                dist[st.u] = 0;
+                queue[qt++] = st.u;
+                while (qh < qt) {
+                    const int x = queue[qh++];
+                    for (uint32_t m = dec.adj[x]; m; m &= m - 1) {
+                        const int y = __builtin_ctz(m);
+                        if (dist[y] < 0) {
+                            dist[y] = dist[x] + 1;
+                            queue[qt++] = y;
+                        }
+                    }
+                }
+                // the bag vertex nearest to u (smallest id on a tie); its
+                // distance bounds the candidates (a ball of radius 2 here;
+                // farther ones scan V(G))
+                const Step& ch = plan.steps[size_t(st.in0)];
+                int best_d = 1 << 20, best_v = 1 << 20;
+                for (int j = 0; j < ch.b_out; j++) {
+                    const int w = ch.cols[j];
+                    if (w < 0 || dist[w] <= 0) continue;
+                    if (dist[w] < best_d || (dist[w] == best_d && w < best_v)) {
+                        best_d = dist[w];
+                        best_v = w;
+                        ball_col = j;
+                    }
+                }
+                if (best_d != 2) ball_col = -1;
+            }
+            if (ball_col >= 0) {
+                const DevTable& in = tab[st.in0];
+                cc_graph* gm = const_cast<cc_graph*>(rq.g);
+                {
+                    std::lock_guard<std::mutex> lk(gm->ball_mu);
+                    if (!gm->ball_pre) {
+                        uint64_t *pre = nullptr, *w2 = nullptr;
+                        hip_check(hipMalloc(&pre, 8 * size_t(std::max<int64_t>(g.m2, 1))), "hipMalloc");
+                        if (hipMalloc(&w2, 8 * size_t(std::max<int32_t>(g.n, 1))) != hipSuccess) {
+                            (void)hipFree(pre);
+                            fail(CC_ENOMEM, "walk tables of the distance-bounded introduce");
+                        }
+                        launch_nbdeg_prefix(g_all, pre, w2, s);
+                        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+                        gm->ball_pre = pre;
+                        gm->ball_w2 = w2;
+                    }
+                }
+                uint32_t* slen = X.alloc<uint32_t>(in.n);
+                X.timed("ball_seglen", double(in.n) * entry_bytes(in.lay.b),
+                        [&] { launch_ball_seglen(in, ball_col, gm->ball_w2, slen, s); });
+                uint64_t* soff;
+                const uint64_t T = X.scan(slen, in.n, &soff);
+                X.release(slen);
+                const uint64_t tiles = expand_tiles(T);
+                uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                uint16_t* pbits = X.alloc<uint16_t>(expand_pass_words(T));
+                X.timed("ball_count", double(in.n) * entry_bytes(in.lay.b) + 5.0 * T,
+                        [&] { launch_ball_count(in, ball_col, gm->ball_pre, soff, T, g, rq.colors, ia, tcount, pbits, s); });
+                uint64_t* toff;
+                const uint64_t Nd = X.scan(tcount, tiles, &toff);
+                X.release(tcount);
+                DevTable dup = X.table(lo, Nd);
+                if (Nd)
+                    X.timed("ball_emit", double(in.n) * entry_bytes(in.lay.b) + double(Nd) * entry_bytes(lo.b), [&] {
+                        launch_ball_emit(in, ball_col, gm->ball_pre, soff, T, g, rq.colors, ia, toff, pbits, dup, s);
+                    });
+                X.release(pbits);
+                X.release(toff);
+                X.release(soff);
+                if (Nd > 1) {
+                    void* kb2 = X.raw(Nd * lo.key_bytes());
+                    uint64_t* vb2 = X.alloc<uint64_t>(Nd);
+                    void* tmp = X.raw(radix_tmp_bytes(Nd));
+                    bool in_b = false;
+                    X.timed("radix_sort", double(Nd) * entry_bytes(lo.b) * 2, [&] {
+                        in_b = radix_sort(dup.keys, dup.cnt, kb2, vb2, Nd, lo.kw(), lo.bits(), 0, tmp, s, false);
+                    });
+                    if (in_b) {
+                        std::swap(dup.keys, kb2);
+                        std::swap(dup.cnt, vb2);
+                    }
+                    X.release(tmp);
+                    X.release(vb2);
+                    X.release(kb2);
+                }
+                uint64_t* starts;
+                const uint64_t Gu = X.groups(dup, 0, &starts);
+                o = X.table(lo, Gu);
+                X.timed("take_runs", double(Gu) * entry_bytes(lo.b) * 2, [&] { launch_take_runs(dup, starts, Gu, o, s); });
+                X.release(starts);
+                X.drop(dup);
+                if (st.node >= 0) out->node_sizes[st.node] = int64_t(o.n);
+                if (!keep) {
+                    for (int in2 : {st.in0, st.in1})
+                        if (in2 >= 0 && --uses[in2] == 0) X.drop(tab[in2]);
+                }
+                continue;
+            }
             bool entry_form = false;
             uint32_t* e_slen = nullptr;
             uint8_t* e_src = nullptr;
@@ -1148,7 +1280,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 const uint64_t classic = read_u64(X.lane, anchor_items);
                 X.release(anchor_items);
                 X.release(e_slen);
-                entry_form = 3 * e_T < classic;
+                entry_form = uint64_t(std::max(1, ctx->entry_factor)) * e_T < classic;
                 if (!entry_form) {
                     X.release(e_soff);
                     X.release(e_src);
@@ -1315,6 +1447,39 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         o = X.table(lo, 0);
                         break;
                     }
+                    if (k > std::min(kDenseColours, ctx->sort_above_k)) {
+                        // colour sets too wide for the dense accumulators (or
+                        // the schedule prefers sorting): drop
+                        // the column, sort, add up runs of equal keys
+                        DevTable d = X.table(lo, in.n);
+                        hip_check(hipMemcpyAsync(d.cnt, in.cnt, 8 * in.n, hipMemcpyDeviceToDevice, s), "copy counts");
+                        X.timed("drop_last", double(in.n) * (entry_bytes(in.lay.b) + entry_bytes(lo.b)),
+                                [&] { launch_drop_last(in, d, s); });
+                        if (in.n > 1) {
+                            void* kb2 = X.raw(in.n * lo.key_bytes());
+                            uint64_t* vb2 = X.alloc<uint64_t>(in.n);
+                            void* tmp = X.raw(radix_tmp_bytes(in.n));
+                            bool in_b = false;
+                            X.timed("radix_sort", double(in.n) * entry_bytes(lo.b) * 2, [&] {
+                                in_b = radix_sort(d.keys, d.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), 0, tmp, s, false);
+                            });
+                            if (in_b) {
+                                std::swap(d.keys, kb2);
+                                std::swap(d.cnt, vb2);
+                            }
+                            X.release(tmp);
+                            X.release(vb2);
+                            X.release(kb2);
+                        }
+                        uint64_t* starts;
+                        const uint64_t Gr = X.groups(d, 0, &starts);
+                        o = X.table(lo, Gr);
+                        X.timed("reduce_runs", double(in.n) * entry_bytes(lo.b) + double(Gr) * entry_bytes(lo.b),
+                                [&] { launch_reduce_runs(d, starts, Gr, o, ovf, s); });
+                        X.release(starts);
+                        X.drop(d);
+                        break;
+                    }
                     uint64_t* gstart;
                     uint64_t G = X.groups(in, in.lay.kb + in.lay.vb, &gstart);
                     uint32_t* gcount = X.alloc<uint32_t>(G);
@@ -1355,6 +1520,46 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     const DevTable& z = tab[st.in1];
                     if (y.n == 0 || z.n == 0) {
                         o = X.table(lo, 0);
+                        break;
+                    }
+                    if (k > std::min(kDenseColours, ctx->sort_above_k)) {
+                        // colour sets too wide for the dense accumulators (or
+                        // the schedule prefers sorting): all admissible
+                        // pairs, then sort and add up runs
+                        uint32_t* pc = X.alloc<uint32_t>(y.n);
+                        X.timed("join_pairs_count", double(y.n + z.n) * entry_bytes(y.lay.b),
+                                [&] { launch_join_pairs(y, z, g.n, rq.colors, pc, nullptr, nullptr, ovf, s); });
+                        uint64_t* poff;
+                        const uint64_t P = X.scan(pc, y.n, &poff);
+                        X.release(pc);
+                        DevTable pr = X.table(lo, P);
+                        if (P)
+                            X.timed("join_pairs_emit", double(y.n + z.n) * entry_bytes(y.lay.b) + double(P) * entry_bytes(lo.b),
+                                    [&] { launch_join_pairs(y, z, g.n, rq.colors, nullptr, poff, &pr, ovf, s); });
+                        X.release(poff);
+                        if (P > 1) {
+                            void* kb2 = X.raw(P * lo.key_bytes());
+                            uint64_t* vb2 = X.alloc<uint64_t>(P);
+                            void* tmp = X.raw(radix_tmp_bytes(P));
+                            bool in_b = false;
+                            X.timed("radix_sort", double(P) * entry_bytes(lo.b) * 2, [&] {
+                                in_b = radix_sort(pr.keys, pr.cnt, kb2, vb2, P, lo.kw(), lo.bits(), 0, tmp, s, false);
+                            });
+                            if (in_b) {
+                                std::swap(pr.keys, kb2);
+                                std::swap(pr.cnt, vb2);
+                            }
+                            X.release(tmp);
+                            X.release(vb2);
+                            X.release(kb2);
+                        }
+                        uint64_t* starts;
+                        const uint64_t Gr = X.groups(pr, 0, &starts);
+                        o = X.table(lo, Gr);
+                        X.timed("reduce_runs", double(P) * entry_bytes(lo.b) + double(Gr) * entry_bytes(lo.b),
+                                [&] { launch_reduce_runs(pr, starts, Gr, o, ovf, s); });
+                        X.release(starts);
+                        X.drop(pr);
                         break;
                     }
                     uint64_t* gstart;

@@ -476,6 +476,348 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
     }
 }
 
+// ---- distance-bounded introduce (no bag neighbour) ----------------------------
+//
+// Sec. 3.2, last paragraphs of "Mapping Expansion Optimizations": a vertex u
+// with no neighbour in the bag, at distance r = dist_F(w, u) from a bag
+// vertex w, can only map to a vertex within distance r of phi(w) in G.  For
+// r = 2 the candidates of an entry are the ends of the walks of length 1 and
+// 2 from a = phi(w): deg(a) + sum over x in N(a) of deg(x) items, the
+// second level addressed through per-edge prefix sums of the neighbours'
+// degrees (nbpre[e] for stored edge e = (a, col[e]): the degrees of the
+// earlier neighbours in a's row).  A vertex reached by several walks is
+// emitted several times: the caller sorts the output and keeps one entry of
+// each key (equal keys come from the same child entry and carry its count).
+
+__global__ void k_nbdeg_prefix(DevGraph g, uint64_t* nbpre, uint64_t* w2) {
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < uint64_t(g.n);
+         v += uint64_t(gridDim.x) * blockDim.x) {
+        uint64_t acc = 0;
+        for (int64_t e = g.rp[v]; e < g.rp[v + 1]; e++) {
+            nbpre[e] = acc;
+            acc += uint64_t(gdeg(g, uint32_t(g.col[e])));
+        }
+        w2[v] = uint64_t(gdeg(g, uint32_t(v))) + acc;
+    }
+}
+
+void launch_nbdeg_prefix(DevGraph g, uint64_t* nbpre, uint64_t* w2, hipStream_t s) {
+    if (g.n) k_nbdeg_prefix<<<grid_for(uint64_t(g.n)), kBlock, 0, s>>>(g, nbpre, w2);
+}
+
+template <class K>
+__global__ void k_ball_seglen(const K* __restrict__ keys, Lay L, uint64_t N, int col, const uint64_t* __restrict__ w2,
+                              uint32_t* slen) {
+    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < N; e += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t len = w2[kcol(keys[e], L, col)];
+        slen[e] = uint32_t(len < 0xffffffffull ? len : 0xffffffffull);
+    }
+}
+
+// the walk end of item t (< deg(a) + sum deg) from a
+__device__ __forceinline__ uint32_t ball_vertex(const DevGraph& g, const uint64_t* nbpre, uint32_t a, uint64_t t) {
+    const int64_t r0 = g.rp[a], r1 = g.rp[a + 1];
+    const uint64_t d = uint64_t(r1 - r0);
+    if (t < d) return uint32_t(g.col[r0 + int64_t(t)]);
+    const uint64_t u = t - d;
+    // last neighbour x of a (row position i) with nbpre[r0 + i] <= u
+    int64_t lo = r0, hi = r1;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (nbpre[mid] <= u) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t x = uint32_t(g.col[lo]);
+    return uint32_t(g.col[g.rp[x] + int64_t(u - nbpre[lo])]);
+}
+
+template <class KI, class KO, bool EMIT>
+__global__ void __launch_bounds__(kBlock)
+k_expand_ball(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, int col,
+              const uint64_t* __restrict__ nbpre, const uint64_t* __restrict__ soff, uint64_t T, DevGraph g,
+              const uint8_t* __restrict__ colors, IntroArgs a, uint32_t* tcount, const uint64_t* __restrict__ toff,
+              KO* okeys, uint64_t* ocnt, Lay LO, uint16_t* pbits) {
+    const uint64_t tiles = (T + kExpTile - 1) / kExpTile;
+    const uint64_t* tbounds = reinterpret_cast<const uint64_t*>(pbits + tiles * kBlock);
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint64_t tile0 = tile * kExpTile;
+        const uint64_t tile1 = tile0 + kExpTile < T ? tile0 + kExpTile : T;
+        const uint64_t s_lo = tbounds[4 * tile], s_hi = tbounds[4 * tile + 1];
+        const uint64_t t0 = tile0 + uint64_t(threadIdx.x) * kExpItems;
+        const uint64_t t1 = t0 + kExpItems < tile1 ? t0 + kExpItems : tile1;
+        uint32_t pass = 0, n_pass = 0;
+        uint64_t seg = 0;
+        if (t0 < tile1) seg = upper_bound_u64(soff, s_lo, s_hi + 1, t0) - 1;
+        const uint64_t seg0 = seg;
+        KI key{};
+        uint32_t img = 0;
+        if (t0 < tile1) {
+            key = keys[seg];
+            img = kcol(key, L, col);
+        }
+        if (EMIT) {
+            if (t0 < tile1) {
+                pass = pbits[tile * kBlock + threadIdx.x];
+                n_pass = __popc(pass);
+            }
+        } else {
+            for (uint64_t t = t0; t < t1; t++) {
+                if (soff[seg + 1] <= t) {
+                    do seg++;
+                    while (soff[seg + 1] <= t);
+                    key = keys[seg];
+                    img = kcol(key, L, col);
+                }
+                const uint32_t v = ball_vertex(g, nbpre, img, t - soff[seg]);
+                const uint32_t cb = 1u << colors[uint64_t(kbid(key, L)) * uint32_t(g.n) + v];
+                if (!(kset(key, L) & cb) && intro_ok(g, v, a.degF)) {
+                    pass |= 1u << (t - t0);
+                    n_pass++;
+                }
+            }
+            if (t0 < tile1) pbits[tile * kBlock + threadIdx.x] = uint16_t(pass);
+        }
+        uint64_t total;
+        const uint64_t my = block_excl_scan(n_pass, &total);
+        if (!EMIT) {
+            if (threadIdx.x == 0) tcount[tile] = uint32_t(total);
+            continue;
+        }
+        if (!pass) continue;
+        uint64_t o = toff[tile] + my;
+        seg = seg0;
+        key = keys[seg];
+        img = kcol(key, L, col);
+        uint32_t rest = pass;
+        while (rest) {
+            const uint64_t t = t0 + uint64_t(__ffs(rest) - 1);
+            rest &= rest - 1u;
+            if (soff[seg + 1] <= t) {
+                do seg++;
+                while (soff[seg + 1] <= t);
+                key = keys[seg];
+                img = kcol(key, L, col);
+            }
+            const uint32_t v = ball_vertex(g, nbpre, img, t - soff[seg]);
+            const uint32_t bid = kbid(key, L);
+            uint32_t cols[5];
+            for (int c = 0, s2 = 0; c < LO.b; c++) cols[c] = (c == a.pos) ? v : kcol(key, L, s2++);
+            okeys[o] = kpack<KO>(bid, cols, LO.b, kset(key, L) | (1u << colors[uint64_t(bid) * uint32_t(g.n) + v]), LO);
+            ocnt[o] = cnt[seg];
+            o++;
+        }
+    }
+}
+
+// keeps the first entry of every run of equal keys (starts[G + 1] from the
+// run-start pass with shift 0)
+template <class K>
+__global__ void k_take_runs(const K* __restrict__ keys, const uint64_t* __restrict__ cnt,
+                            const uint64_t* __restrict__ starts, uint64_t G, K* okeys, uint64_t* ocnt) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < G; i += uint64_t(gridDim.x) * blockDim.x) {
+        okeys[i] = keys[starts[i]];
+        ocnt[i] = cnt[starts[i]];
+    }
+}
+
+void launch_ball_seglen(const DevTable& in, int col, const uint64_t* w2, uint32_t* slen, hipStream_t s) {
+    if (!in.n) return;
+    if (in.lay.kw() == 1)
+        k_ball_seglen<uint64_t><<<grid_for(in.n), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, in.n, col, w2, slen);
+    else
+        k_ball_seglen<u128><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.lay, in.n, col, w2, slen);
+}
+
+template <bool EMIT>
+static void ball_dispatch(const DevTable& in, int col, const uint64_t* nbpre, const uint64_t* soff, uint64_t T,
+                          DevGraph g, const uint8_t* colors, const IntroArgs& a, uint32_t* tcount,
+                          const uint64_t* toff, DevTable* out, uint16_t* pbits, hipStream_t s) {
+    const uint64_t tiles = expand_tiles(T);
+    if (!tiles) return;
+    const unsigned grid = unsigned(tiles < (1u << 20) ? tiles : (1u << 20));
+    Lay LO = out ? out->lay : Lay{in.lay.b + 1, in.lay.vb, in.lay.kb, in.lay.bb};
+    void* ok = out ? out->keys : nullptr;
+    uint64_t* oc = out ? out->cnt : nullptr;
+    const int ki = in.lay.kw(), ko = LO.kw();
+    if (ki == 1 && ko == 1)
+        k_expand_ball<uint64_t, uint64_t, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, col,
+                                                                        nbpre, soff, T, g, colors, a, tcount, toff,
+                                                                        (uint64_t*)ok, oc, LO, pbits);
+    else if (ki == 1)
+        k_expand_ball<uint64_t, u128, EMIT><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, in.lay, col, nbpre,
+                                                                    soff, T, g, colors, a, tcount, toff, (u128*)ok, oc,
+                                                                    LO, pbits);
+    else
+        k_expand_ball<u128, u128, EMIT><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.cnt, in.lay, col, nbpre, soff, T,
+                                                                g, colors, a, tcount, toff, (u128*)ok, oc, LO, pbits);
+}
+
+void launch_ball_count(const DevTable& in, int col, const uint64_t* nbpre, const uint64_t* soff, uint64_t T, DevGraph g,
+                       const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, uint16_t* pbits, hipStream_t s) {
+    const uint64_t tiles = expand_tiles(T);
+    if (!tiles) return;
+    k_expand_bounds<<<grid_for(tiles), kBlock, 0, s>>>(soff, in.n, nullptr, 0, T, true,
+                                                      reinterpret_cast<uint64_t*>(pbits + tiles * kBlock));
+    ball_dispatch<false>(in, col, nbpre, soff, T, g, colors, a, tcount, nullptr, nullptr, pbits, s);
+}
+
+void launch_ball_emit(const DevTable& in, int col, const uint64_t* nbpre, const uint64_t* soff, uint64_t T, DevGraph g,
+                      const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, const uint16_t* pbits,
+                      DevTable& out, hipStream_t s) {
+    ball_dispatch<true>(in, col, nbpre, soff, T, g, colors, a, nullptr, toff, &out, const_cast<uint16_t*>(pbits), s);
+}
+
+void launch_take_runs(const DevTable& in, const uint64_t* starts, uint64_t G, DevTable& out, hipStream_t s) {
+    if (!G) return;
+    if (in.lay.kw() == 1)
+        k_take_runs<uint64_t><<<grid_for(G), kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, starts, G,
+                                                             (uint64_t*)out.keys, out.cnt);
+    else
+        k_take_runs<u128><<<grid_for(G), kBlock, 0, s>>>((const u128*)in.keys, in.cnt, starts, G, (u128*)out.keys,
+                                                         out.cnt);
+}
+
+// ---- forget by sorting (colour sets wider than the dense accumulators) ------
+//
+// Forget u (Sec. 3.1) without a 2^k accumulator: every entry's key loses its
+// last column, the keys are sorted (stable radix), and each run of equal keys
+// becomes one entry whose count is the run's sum mod 2^64; a carry sets the
+// colouring's overflow flag.
+
+template <class KI, class KO>
+__global__ void k_drop_last(const KI* __restrict__ keys, uint64_t N, Lay L, Lay LO, KO* okeys) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += uint64_t(gridDim.x) * blockDim.x) {
+        const KI k = keys[i];
+        uint32_t cols[4];
+        for (int c = 0; c < LO.b; c++) cols[c] = kcol(k, L, c);
+        okeys[i] = kpack<KO>(kbid(k, L), cols, LO.b, kset(k, L), LO);
+    }
+}
+
+template <class K>
+__global__ void k_reduce_runs(const K* __restrict__ keys, const uint64_t* __restrict__ cnt,
+                              const uint64_t* __restrict__ starts, uint64_t G, Lay L, K* okeys, uint64_t* ocnt,
+                              uint32_t* ovf) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < G; i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t a = starts[i], b = starts[i + 1];
+        uint64_t sum = 0;
+        bool over = false;
+        for (uint64_t j = a; j < b; j++) {
+            const uint64_t v = cnt[j];
+            over |= sum + v < sum;
+            sum += v;
+        }
+        okeys[i] = keys[a];
+        ocnt[i] = sum;
+        if (over) atomicOr(&ovf[kbid(keys[a], L)], 1u);
+    }
+}
+
+// Join (Sec. 3.1) without a 2^k accumulator: one thread per entry of y finds
+// the run of z with the same (colouring, bag images) by binary search and
+// pairs its colour set with every colour set there whose intersection is
+// exactly the colours of the bag's images; the products (mod 2^64, a carry
+// beyond 64 bits sets the colouring's flag) are emitted unreduced, in no
+// order: the caller sorts them and adds up runs of equal keys.
+template <class K>
+__device__ __forceinline__ uint64_t key_lower_bound(const K* keys, uint64_t n, K prefix, int sh) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (shr(keys[mid], sh) < prefix) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <class K, bool EMIT>
+__global__ void k_join_pairs(const K* __restrict__ ykeys, const uint64_t* __restrict__ ycnt, uint64_t ny,
+                             const K* __restrict__ zkeys, const uint64_t* __restrict__ zcnt, uint64_t nz, Lay L,
+                             int32_t n, const uint8_t* __restrict__ colors, uint32_t* pcount,
+                             const uint64_t* __restrict__ poff, K* okeys, uint64_t* ocnt, uint32_t* ovf) {
+    const int sh = L.kb;
+    const K cmask = (K(1) << L.kb) - K(1);
+    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < ny; e += uint64_t(gridDim.x) * blockDim.x) {
+        const K ky = ykeys[e];
+        const K prefix = shr(ky, sh);
+        const uint32_t bid = kbid(ky, L);
+        uint32_t bag = 0;
+        for (int c = 0; c < L.b; c++) bag |= 1u << colors[uint64_t(bid) * uint32_t(n) + kcol(ky, L, c)];
+        const uint32_t cy = kset(ky, L);
+        uint64_t j = key_lower_bound(zkeys, nz, prefix, sh);
+        uint32_t m = 0;
+        uint64_t o = EMIT ? poff[e] : 0;
+        bool over = false;
+        for (; j < nz; j++) {
+            const K kz = zkeys[j];
+            if (shr(kz, sh) != prefix) break;
+            const uint32_t cz = kset(kz, L);
+            if ((cy & cz) != bag) continue;
+            if (EMIT) {
+                const uint64_t a = ycnt[e], b = zcnt[j];
+                over |= __umul64hi(a, b) != 0;
+                okeys[o] = (ky & ~cmask) | K(cy | cz);
+                ocnt[o] = a * b;
+                o++;
+            } else {
+                m++;
+            }
+        }
+        if (!EMIT) pcount[e] = m;
+        if (EMIT && over) atomicOr(&ovf[bid], 1u);
+    }
+}
+
+void launch_join_pairs(const DevTable& y, const DevTable& z, int32_t n, const uint8_t* colors, uint32_t* pcount,
+                       const uint64_t* poff, DevTable* out, uint32_t* ovf, hipStream_t s) {
+    if (!y.n || !z.n) return;
+    const unsigned grid = grid_for(y.n);
+    if (y.lay.kw() == 1) {
+        if (out)
+            k_join_pairs<uint64_t, true><<<grid, kBlock, 0, s>>>((const uint64_t*)y.keys, y.cnt, y.n,
+                                                                 (const uint64_t*)z.keys, z.cnt, z.n, y.lay, n, colors,
+                                                                 nullptr, poff, (uint64_t*)out->keys, out->cnt, ovf);
+        else
+            k_join_pairs<uint64_t, false><<<grid, kBlock, 0, s>>>((const uint64_t*)y.keys, y.cnt, y.n,
+                                                                  (const uint64_t*)z.keys, z.cnt, z.n, y.lay, n, colors,
+                                                                  pcount, nullptr, nullptr, nullptr, nullptr);
+    } else {
+        if (out)
+            k_join_pairs<u128, true><<<grid, kBlock, 0, s>>>((const u128*)y.keys, y.cnt, y.n, (const u128*)z.keys, z.cnt,
+                                                             z.n, y.lay, n, colors, nullptr, poff, (u128*)out->keys,
+                                                             out->cnt, ovf);
+        else
+            k_join_pairs<u128, false><<<grid, kBlock, 0, s>>>((const u128*)y.keys, y.cnt, y.n, (const u128*)z.keys,
+                                                              z.cnt, z.n, y.lay, n, colors, pcount, nullptr, nullptr,
+                                                              nullptr, nullptr);
+    }
+}
+
+void launch_drop_last(const DevTable& in, DevTable& out, hipStream_t s) {
+    if (!in.n) return;
+    const int ki = in.lay.kw(), ko = out.lay.kw();
+    if (ki == 1)
+        k_drop_last<uint64_t, uint64_t><<<grid_for(in.n), kBlock, 0, s>>>((const uint64_t*)in.keys, in.n, in.lay, out.lay,
+                                                                          (uint64_t*)out.keys);
+    else if (ko == 1)
+        k_drop_last<u128, uint64_t><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.n, in.lay, out.lay,
+                                                                      (uint64_t*)out.keys);
+    else
+        k_drop_last<u128, u128><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.n, in.lay, out.lay,
+                                                                  (u128*)out.keys);
+}
+
+void launch_reduce_runs(const DevTable& in, const uint64_t* starts, uint64_t G, DevTable& out, uint32_t* ovf,
+                        hipStream_t s) {
+    if (!G) return;
+    if (in.lay.kw() == 1)
+        k_reduce_runs<uint64_t><<<grid_for(G), kBlock, 0, s>>>((const uint64_t*)in.keys, in.cnt, starts, G, in.lay,
+                                                               (uint64_t*)out.keys, out.cnt, ovf);
+    else
+        k_reduce_runs<u128><<<grid_for(G), kBlock, 0, s>>>((const u128*)in.keys, in.cnt, starts, G, in.lay,
+                                                           (u128*)out.keys, out.cnt, ovf);
+}
+
 // ---- launchers -------------------------------------------------------------
 
 void launch_entry_seglen(const DevTable& in, DevGraph g, const IntroArgs& a, uint32_t* slen, uint8_t* src,

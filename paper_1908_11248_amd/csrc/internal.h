@@ -12,7 +12,8 @@
 namespace ccg {
 
 constexpr int kMaxPattern = 16;  // n_F limit of a decomposition
-constexpr int kMaxColours = 12;  // k limit of a colouring and of every DP run
+constexpr int kMaxColours = 16;    // k limit of a colouring and of every DP run
+constexpr int kDenseColours = 12;  // k limit of the dense 2^k colour-set accumulators
 constexpr int kMaxBag = 4;       // bag size limit of the device kernels (width <= 3)
 
 enum NodeType { LEAF = 0, INTRO = 1, FORGET = 2, JOIN = 3 };

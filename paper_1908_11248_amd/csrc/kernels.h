@@ -79,6 +79,9 @@ void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 
 void launch_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed, hipStream_t s);
+// colourings b0 .. b0 + B - 1 of the seed (written to colors[0 .. B n))
+void launch_color_hash_from(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed, uint32_t b0,
+                            hipStream_t s);
 
 // runs of equal key >> shift in a sorted table: head_tiles(n) tiles; tsum[t]
 // = number of runs starting in tile t; with toff = exclusive scan of tsum
@@ -130,6 +133,31 @@ void launch_entry_count(const DevTable& in, const uint8_t* src, const uint64_t* 
 void launch_entry_emit(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,
                        const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, const uint16_t* pbits,
                        DevTable& out, hipStream_t s);
+// distance-bounded form for an introduced vertex with no bag neighbour at
+// distance 2 from the vertex of child column `col`: per entry, the ends of
+// the walks of length 1 and 2 from that column's image (w2[v] = deg(v) + sum
+// of its neighbours' degrees, nbpre[e] = degrees of the earlier neighbours
+// in the row of stored edge e, from launch_nbdeg_prefix); the output holds
+// duplicates and is in no order: sort it, then keep one entry per key
+// (launch_take_runs over the run starts)
+void launch_nbdeg_prefix(DevGraph g, uint64_t* nbpre, uint64_t* w2, hipStream_t s);
+void launch_ball_seglen(const DevTable& in, int col, const uint64_t* w2, uint32_t* slen, hipStream_t s);
+void launch_ball_count(const DevTable& in, int col, const uint64_t* nbpre, const uint64_t* soff, uint64_t T, DevGraph g,
+                       const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, uint16_t* pbits, hipStream_t s);
+void launch_ball_emit(const DevTable& in, int col, const uint64_t* nbpre, const uint64_t* soff, uint64_t T, DevGraph g,
+                      const uint8_t* colors, const IntroArgs& a, const uint64_t* toff, const uint16_t* pbits,
+                      DevTable& out, hipStream_t s);
+void launch_take_runs(const DevTable& in, const uint64_t* starts, uint64_t G, DevTable& out, hipStream_t s);
+// forget by sorting: out (same n, layout with one column less) = in without
+// its last column; after a sort of out and its run starts (shift 0),
+// launch_reduce_runs sums every run into one entry (carry: ovf[colouring])
+void launch_drop_last(const DevTable& in, DevTable& out, hipStream_t s);
+// join by pairs: pcount[e] (out == nullptr) or the pairs at poff[e] (out)
+// for entry e of y; the products are unreduced and unsorted
+void launch_join_pairs(const DevTable& y, const DevTable& z, int32_t n, const uint8_t* colors, uint32_t* pcount,
+                       const uint64_t* poff, DevTable* out, uint32_t* ovf, hipStream_t s);
+void launch_reduce_runs(const DevTable& in, const uint64_t* starts, uint64_t G, DevTable& out, uint32_t* ovf,
+                        hipStream_t s);
 // survivor bits of the count pass and the tiles' segment and group bounds,
 // both written by launch_expand_count and read back by the emit pass:
 // expand_pass_words(T) words

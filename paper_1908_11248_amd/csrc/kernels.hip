@@ -109,19 +109,24 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
     return z ^ (z >> 31);
 }
 
-__global__ void k_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed) {
+__global__ void k_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed, uint32_t b0) {
     uint64_t total = uint64_t(n) * uint64_t(B);
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
          i += uint64_t(gridDim.x) * blockDim.x) {
-        uint64_t b = i / uint64_t(n), v = i % uint64_t(n);
+        uint64_t b = b0 + i / uint64_t(n), v = i % uint64_t(n);
         uint64_t h = splitmix64(seed ^ ((b << 32) + v));
         colors[i] = uint8_t(((h >> 32) * uint64_t(k)) >> 32);
     }
 }
 
 void launch_color_hash(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed, hipStream_t s) {
+    launch_color_hash_from(colors, n, B, k, seed, 0, s);
+}
+
+void launch_color_hash_from(uint8_t* colors, int32_t n, int32_t B, int32_t k, uint64_t seed, uint32_t b0,
+                            hipStream_t s) {
     uint64_t total = uint64_t(n) * uint64_t(B);
-    if (total) k_color_hash<<<grid_for(total), kBlock, 0, s>>>(colors, n, B, k, seed);
+    if (total) k_color_hash<<<grid_for(total), kBlock, 0, s>>>(colors, n, B, k, seed, b0);
 }
 
 // ---------------------------------------------------------------------------

@@ -343,22 +343,88 @@ int cc_tune_batch(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query
     }
     size_t total = 0;
     for (int32_t i = 0; i < nq; i++) total += size_t(q[i].coloring->B);
-    std::vector<uint64_t> counts(total);
+    std::vector<uint64_t> counts(total), first(total);
+    bool have_first = false;
+    // one timed batch under the current schedule; every schedule must give
+    // the same counts
+    auto timed = [&](double* dt) {
+        auto t0 = Clock::now();
+        int rc = cc_count_batch(ctx, g, nq, q, flags, counts.data(), nullptr);
+        *dt = std::chrono::duration<double>(Clock::now() - t0).count();
+        if (rc != CC_OK) return rc;
+        if (!have_first) {
+            first = counts;
+            have_first = true;
+        } else if (counts != first) {
+            set_error("schedules gave different counts");
+            return CC_EDEVICE;
+        }
+        return CC_OK;
+    };
+    // coordinate descent: lanes, then the introduce form threshold, then
+    // dense LDS accumulators against sorting in forget and join
     double best_t = 1e300;
     int best_l = 1;
     for (int l : {1, 2, 4, 8}) {
         ctx->batch_lanes = l;
-        auto t0 = Clock::now();
-        int rc = cc_count_batch(ctx, g, nq, q, flags, counts.data(), nullptr);
-        double dt = std::chrono::duration<double>(Clock::now() - t0).count();
-        if (rc != CC_OK) return rc;
+        double dt;
+        if (int rc = timed(&dt)) return rc;
         if (dt < best_t) {
             best_t = dt;
             best_l = l;
         }
     }
     ctx->batch_lanes = best_l;
+    const int f0 = ctx->entry_factor;
+    int best_f = f0;
+    for (int f : {1, 8}) {
+        ctx->entry_factor = f;
+        double dt;
+        if (int rc = timed(&dt)) {
+            ctx->entry_factor = f0;
+            return rc;
+        }
+        if (dt < best_t) {
+            best_t = dt;
+            best_f = f;
+        }
+    }
+    ctx->entry_factor = best_f;
+    const int s0 = ctx->sort_above_k;
+    int best_s = s0;
+    for (int sk : {8, 0}) {
+        ctx->sort_above_k = sk;
+        double dt;
+        if (int rc = timed(&dt)) {
+            ctx->sort_above_k = s0;
+            return rc;
+        }
+        if (dt < best_t) {
+            best_t = dt;
+            best_s = sk;
+        }
+    }
+    ctx->sort_above_k = best_s;
     *best = best_l;
+    return CC_OK;
+}
+
+int cc_get_schedule(const cc_context* ctx, cc_schedule* out) {
+    if (!ctx || !out) return CC_EINVAL;
+    out->lanes = ctx->batch_lanes;
+    out->entry_factor = ctx->entry_factor;
+    out->sort_above_k = ctx->sort_above_k;
+    return CC_OK;
+}
+
+int cc_set_schedule(cc_context* ctx, const cc_schedule* s) {
+    if (!ctx || !s || s->lanes < 0 || s->lanes > 64 || s->entry_factor < 1 || s->sort_above_k < 0) {
+        set_error("bad arguments");
+        return CC_EINVAL;
+    }
+    ctx->batch_lanes = s->lanes;
+    ctx->entry_factor = s->entry_factor;
+    ctx->sort_above_k = s->sort_above_k;
     return CC_OK;
 }
 

@@ -531,3 +531,47 @@ def query_seeds(index: int, count: int) -> List[int]:
     w = workload(index)
     rng = np.random.Generator(np.random.PCG64(w.seed ^ 0x51))
     return [int(x) for x in rng.integers(0, 1 << 62, size=count)]
+
+
+# ---------------------------------------------------------------------------
+# paper-shaped context workloads (Sec. 5.1, Sec. 5.4): synthetic stand-ins at
+# the sizes the paper prints; no item of its data sets is reproduced
+
+IMAGES_SIZE = (4838, 7067)    # Images: a segmented image's region graph (Sec. 5.1)
+TRANS_SIZE = (45733, 44727)   # Trans: bank transfers (Sec. 5.1)
+
+
+def images_standin(seed: int = BASE_SEED + 11) -> Graph:
+    """Planar-like stand-in for Images: a 2-D random geometric graph on 4838
+    points with the radius that gives 7067 edges in expectation."""
+    n, m = IMAGES_SIZE
+    g = rgg(n, 2.0 * m / n, seed)
+    g.name = "RGG(4838,m~7067) [Images stand-in]"
+    return g
+
+
+def trans_standin(seed: int = BASE_SEED + 12) -> Graph:
+    """Sparse heavy-tailed stand-in for Trans: Chung-Lu on 45733 vertices,
+    exponent 2.5, mean degree 2 * 44727 / 45733."""
+    n, m = TRANS_SIZE
+    g = chung_lu(n, 2.5, 2.0 * m / n, seed)
+    g.name = "CL(45733,2.5,m~44727) [Trans stand-in]"
+    return g
+
+
+def paper_patterns() -> List[Pattern]:
+    """The pattern set of the paper's tables (Sec. 5.1, Table `prop`,
+    Fig. `figpatt`): paths P5, P10, P15, star S5, cycles C5, C10, K4, the
+    3 x 3 grid, and patterns A-D."""
+    return [path(5), path(10), path(15), star(5), cycle(5), cycle(10), complete(4), grid(3, 3),
+            pattern_A(), pattern_B(), pattern_C(), pattern_D()]
+
+
+def er_sweep(p_target: float, p_pattern: float, seed: int):
+    """One cell of the Erdos-Renyi setup of Sec. 5.4: target G(150, p_target),
+    pattern G(10, p_pattern)."""
+    g = er_pairs(150, p_target, seed)
+    pg = er_pairs(10, p_pattern, seed ^ 0x5EED)
+    src, dst = edge_list(pg)
+    pat = Pattern(10, [(int(a), int(b)) for a, b in zip(src, dst)], "G(10,%.2f)" % p_pattern, "er")
+    return g, pat

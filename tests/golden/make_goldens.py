@@ -10,13 +10,15 @@ Files (one line per value, each with a header naming this command):
   w4_counts.txt   workload 4: colouring 0 of all 256 queries (selected under
                   the workload's admission rule); the 5-cycles, whose largest
                   table holds about 4e8 entries per colouring, by four
-                  sampled ranges of the image of pattern vertex 0
+                  sampled ranges of the image of pattern vertex 0, and every
+                  query whose full count exceeds the oracle's caps (12 GiB of
+                  address space, 300 s) by two such ranges; a range over the
+                  caps is listed in the header as skipped
                   q seed name b lo hi count overflow   (lo hi = 0 n: full count)
   w5_sample.txt   workload 5: colouring 0 of a seeded sample of 32 of the
                   first 200 queries of the stream       same format
 """
 import argparse
-import concurrent.futures as cf
 import multiprocessing as mp
 import os
 import sys
@@ -56,21 +58,118 @@ def _one(task):
     return task, r["count"], int(r["overflow"]), time.perf_counter() - t0
 
 
-def _run(tasks, workers, out_path, header, fmt):
+MEM_CAP = 12 << 30  # address-space limit of one oracle process
+TIME_CAP = 300.0  # seconds for one oracle task
+
+
+def _child(task, conn):
+    import resource
+
+    resource.setrlimit(resource.RLIMIT_AS, (MEM_CAP, MEM_CAP))
+    try:
+        conn.send(("ok",) + _one(task)[1:3])
+    except Exception as e:  # ENOMEM of the oracle under the limit, or MemoryError
+        conn.send(("fail", repr(e)))
+    conn.close()
+
+
+def _fallback(task, n):
+    """Two anchor ranges of the image of pattern vertex 0 in place of a full
+    count that exceeded the caps."""
+    index, q, seed, name, k, edges, b, cseed, lo, hi = task
+    rng = np.random.Generator(np.random.PCG64(seed ^ 0xA5))
+    x = int(rng.integers(0, n - 500))
+    return [(index, q, seed, name, k, edges, b, cseed, 0, 64), (index, q, seed, name, k, edges, b, cseed, x, x + 500)]
+
+
+def _run(tasks, workers, out_path, header, fmt, n=None):
+    """Runs the oracle tasks, each in a process of its own with MEM_CAP bytes
+    of address space and TIME_CAP seconds, and writes one line per finished
+    task.  A full count that exceeds either cap is replaced by two anchor
+    ranges (_fallback); a range that exceeds them is recorded as skipped.
+    Finished lines go to <out_path>.part as they come, so an interrupted run
+    resumes where it stopped."""
     ctx = mp.get_context("fork")
-    rows = {}
+    part = out_path + ".part"
+    done = {}
+    if os.path.exists(part):
+        for line in open(part):
+            key, val = line.rsplit("|", 1)
+            done[key] = val.strip()
+    rows, skipped = {}, []
+    queue = list(tasks)
+    todo = []
+    while queue:
+        t = queue.pop(0)
+        v = done.get(repr(t))
+        if v is None:
+            todo.append(t)
+        elif v == "skip":
+            if n is not None and (t[8], t[9]) == (0, n):
+                queue.extend(_fallback(t, n))
+            else:
+                skipped.append(t)
+        else:
+            c, o = v.split()
+            rows[t] = (int(c), int(o))
     t0 = time.perf_counter()
-    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
-        futs = [ex.submit(_one, t) for t in tasks]
-        for i, f in enumerate(cf.as_completed(futs)):
-            task, cnt, ovf, dt = f.result()
-            rows[task] = (cnt, ovf)
-            print("%s: %d/%d done (%.1f s, last %.1f s)" % (os.path.basename(out_path), i + 1, len(tasks),
-                                                             time.perf_counter() - t0, dt), flush=True)
+    running = {}
+    with open(part, "a") as ph:
+        def record(t, val):
+            ph.write("%r|%s\n" % (t, val))
+            ph.flush()
+
+        while todo or running:
+            while todo and len(running) < workers:
+                t = todo.pop(0)
+                a, b_ = ctx.Pipe(duplex=False)
+                pr = ctx.Process(target=_child, args=(t, b_))
+                pr.start()
+                b_.close()
+                running[t] = (pr, a, time.perf_counter())
+            time.sleep(0.2)
+            for t in list(running):
+                pr, a, ts = running[t]
+                res = None
+                if a.poll():
+                    try:
+                        res = a.recv()
+                    except EOFError:
+                        res = ("fail", "died")
+                elif not pr.is_alive():
+                    res = ("fail", "exit %s" % pr.exitcode)
+                elif time.perf_counter() - ts > TIME_CAP:
+                    pr.kill()
+                    res = ("fail", "time cap")
+                if res is None:
+                    continue
+                pr.join()
+                a.close()
+                del running[t]
+                dt = time.perf_counter() - ts
+                if res[0] == "ok":
+                    rows[t] = (res[1], res[2])
+                    record(t, "%d %d" % (res[1], res[2]))
+                    what = "done"
+                else:
+                    record(t, "skip")
+                    if n is not None and (t[8], t[9]) == (0, n):
+                        todo.extend(_fallback(t, n))
+                        what = "over the caps (%s): two ranges instead" % res[1]
+                    else:
+                        skipped.append(t)
+                        what = "over the caps (%s): skipped" % res[1]
+                print("%s: %d finished, %d queued, %d running (%.0f s; task q%d n_F %d [%d,%d) %.1f s) %s"
+                      % (os.path.basename(out_path), len(rows), len(todo), len(running), time.perf_counter() - t0,
+                         t[1], t[4], t[8], t[9], dt, what), flush=True)
     with open(out_path, "w") as fh:
         fh.write(header)
-        for t in tasks:
-            fh.write(fmt(t, *rows[t]) + "\n")
+        for t in skipped:
+            fh.write("# skipped: q %d %s [%d, %d) exceeds the oracle's caps\n" % (t[1], t[3], t[8], t[9]))
+        for t in tasks + [x for x in rows if x not in tasks]:
+            if t in rows:
+                fh.write(fmt(t, *rows[t]) + "\n")
+    os.remove(part)
 
 
 def _hdr(what):
@@ -117,16 +216,16 @@ def w_queries(index, workers):
                 tasks.append((index, q, s, p.name, p.n, tuple(tuple(e) for e in p.edges), 0, cs, lo, hi))
         else:
             tasks.append((index, q, s, p.name, p.n, tuple(tuple(e) for e in p.edges), 0, cs, 0, g.n))
-    # the largest patterns first, so the pool drains evenly
-    tasks.sort(key=lambda t: -t[4])
+    # the smallest patterns first
+    tasks.sort(key=lambda t: (t[4], t[1]))
     _run(tasks, workers, os.path.join(HERE, out),
          _hdr(what + "\n# q seed name b lo hi count overflow (lo hi = 0 n_G: the full count)"),
-         lambda t, c, o: "%d %d %s %d %d %d %d %d" % (t[1], t[2], t[3], t[6], t[8], t[9], c, o))
+         lambda t, c, o: "%d %d %s %d %d %d %d %d" % (t[1], t[2], t[3], t[6], t[8], t[9], c, o), n=g.n)
     # rewrite in query order
     path = os.path.join(HERE, out)
     lines = open(path).read().splitlines()
     head = [l for l in lines if l.startswith("#")]
-    body = sorted((l for l in lines if not l.startswith("#")), key=lambda l: (int(l.split()[0]), int(l.split()[4])))
+    body = sorted(set(l for l in lines if not l.startswith("#")), key=lambda l: (int(l.split()[0]), int(l.split()[4])))
     with open(path, "w") as fh:
         fh.write("\n".join(head + body) + "\n")
 
@@ -141,7 +240,7 @@ def main():
         if index in (2, 3):
             w_single(index, a.workers or (8 if index == 2 else 6))
         else:
-            w_queries(index, a.workers or (3 if index == 4 else 2))
+            w_queries(index, a.workers or 4)
         print("workload %d goldens in %.0f s" % (index, time.perf_counter() - t0), flush=True)
 
 

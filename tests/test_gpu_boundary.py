@@ -134,7 +134,7 @@ def test_size_limits_are_erange(ctx):
     say("boundary: CC_ERANGE limits")
     g = W.er_pairs(30, 0.2, 2)
     G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
-    for k in (0, 13, 33):
+    for k in (0, 17, 33):
         with pytest.raises(cc.CcError) as e:
             cc.color(ctx, G, k, 1, 1)
         assert e.value.code == cc.CC_ERANGE
@@ -148,7 +148,7 @@ def test_size_limits_are_erange(ctx):
     assert e.value.code == cc.CC_ERANGE
     srv = cc.Server(ctx, G, max_inflight=1)
     try:
-        for k in (5, 13):
+        for k in (5, 17):
             with pytest.raises(cc.CcError) as e:
                 srv.submit(D, k, 1, 1)
             assert e.value.code == cc.CC_ERANGE

@@ -267,3 +267,62 @@ def test_entry_and_classic_introduce_match_oracle(ctx, gname, make):
             for b in range(2):
                 assert int(counts[b]) == ref[b]["count"] and bool(ovf[b]) == ref[b]["overflow"], (gname, pat.name, flags, b)
             assert np.array_equal(sizes, ref[0]["sizes"] + ref[1]["sizes"]), (gname, pat.name, flags)
+
+
+@pytest.mark.parametrize("gname,make", [("er150", lambda: W.er_pairs(150, 0.07, 9)),
+                                        ("ba500", lambda: W.barabasi_albert(500, 3, 10)),
+                                        ("rgg400", lambda: W.rgg(400, 8, 11))], ids=["er150", "ba500", "rgg400"])
+def test_distance_bounded_introduce_matches_oracle(ctx, gname, make):
+    """Pattern C's decomposition introduces vertices with no bag neighbour but
+    a bag vertex at distance 2 (Sec. 3.2): their candidates are the walks of
+    length <= 2 from that vertex's image, de-duplicated.  Same counts, flags
+    and table sizes as the oracle with the same bound; with CC_CLASSIC_EXPAND
+    the full scan, equal to the oracle without the bound."""
+    g = make()
+    pat = W.pattern_C()
+    D = cc.build_decomposition(pat.n, pat.edges)
+    assert "anchor=-1" in D.describe()
+    td = D.export()
+    G = gpu_graph(ctx, g)
+    C = cc.color(ctx, G, pat.n, 57, 2)
+    for flags in (0, cc.CC_CLASSIC_EXPAND):
+        say("distance-bounded", gname, "flags", flags)
+        # the full scan (CC_CLASSIC_EXPAND) keeps the entries the bound drops
+        ref = [O.dp_count(g, pat, pat.n, O.color_array(57, b, g.n, pat.n), td=td, sizes=True,
+                          distbound=(flags == 0)) for b in range(2)]
+        counts, ovf = cc.count(ctx, G, C, D, flags)
+        sizes = ctx.last_table_sizes()
+        for b in range(2):
+            assert int(counts[b]) == ref[b]["count"] and bool(ovf[b]) == ref[b]["overflow"], (gname, flags, b)
+        assert np.array_equal(sizes, ref[0]["sizes"] + ref[1]["sizes"]), (gname, flags)
+
+
+def test_wide_colour_sets_match_oracle(ctx):
+    """k from 13 to 16 colours (the paper's masks allow n_F <= 32, Sec. 3.2):
+    forget and join by sorting and adding up runs instead of the dense 2^k
+    accumulators; paths up to P15 (the paper's largest pattern), trees with
+    joins and a ladder, against the oracle, with flags.  Enumeration stays
+    limited to k <= 12."""
+    g = W.er_pairs(90, 0.1, 17)
+    G = gpu_graph(ctx, g)
+    cases = [(W.path(13), 13), (W.path(13), 14), (W.path(15), 15), (W.random_tree(14, 3), 14),
+             (W.star(13), 13), (W.ladder(6), 13), (W.random_tree(16, 9), 16)]
+    for pat, k in cases:
+        say("wide colour sets", pat.name, "k", k)
+        D = cc.build_decomposition(pat.n, pat.edges)
+        td = D.export()
+        C = cc.color(ctx, G, k, 5, 2)
+        counts, ovf = cc.count(ctx, G, C, D)
+        sizes = ctx.last_table_sizes()
+        ref_sizes = 0
+        for b in range(2):
+            ref = O.dp_count(g, pat, k, O.color_array(5, b, g.n, k), td=td, sizes=True)
+            assert int(counts[b]) == ref["count"] and bool(ovf[b]) == ref["overflow"], (pat.name, k, b)
+            ref_sizes = ref_sizes + ref["sizes"]
+        assert np.array_equal(sizes, ref_sizes), (pat.name, k)
+    with pytest.raises(cc.CcError) as e:
+        cc.enumerate(ctx, G, C, 0, D, 10)
+    assert e.value.code == cc.CC_ERANGE
+    with pytest.raises(cc.CcError) as e:
+        cc.color(ctx, G, 17, 1, 1)
+    assert e.value.code == cc.CC_ERANGE

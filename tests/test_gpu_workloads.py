@@ -60,6 +60,11 @@ def test_single_pattern_workloads_all_colourings(ctx, index):
         assert bool(ovf[int(b)]) == bool(int(o)), (index, b)
 
 
+def _skipped(name):
+    path = os.path.join(GOLDEN, name)
+    return {int(l.split()[3]) for l in open(path) if l.startswith("# skipped: q ")}
+
+
 def _query_rows(name):
     by_q = {}
     for q, seed, pname, b, lo, hi, cnt, o in _rows(name):
@@ -69,9 +74,13 @@ def _query_rows(name):
 
 def test_workload4_all_queries_colouring0(ctx):
     by_q = _query_rows("w4_counts.txt")
+    skipped = _skipped("w4_counts.txt")
     g = W.workload_graph(4)
     sel, _ = W.select_queries(4, 256)
-    assert sorted(by_q) == list(range(len(sel))) and len(sel) == 256
+    # every query has a full count or anchor ranges, unless each of its ranges
+    # exceeded the oracle's caps (listed in the file's header)
+    assert len(sel) == 256 and set(by_q) | skipped == set(range(len(sel)))
+    assert len(by_q) >= 200
     G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
     full, ranged = [], []
     for q, (p, s) in enumerate(sel):
@@ -103,15 +112,26 @@ def test_workload5_sample_served_and_plain(ctx):
             p, s = sel[q]
             assert all(r[0] == s and r[1] == p.name for r in by_q[q])
             decs[q] = cc.build_decomposition(p.n, p.edges)
-            tickets[q] = srv.submit(decs[q], p.n, W.colouring_seed(s), 1)
+            if (by_q[q][0][3], by_q[q][0][4]) == (0, g.n):
+                tickets[q] = srv.submit(decs[q], p.n, W.colouring_seed(s), 1)
         for q, t in tickets.items():
             st, cnt, ovf = srv.wait(t)
             r = by_q[q][0]
             assert st == 1 and int(cnt[0]) == r[5] and bool(ovf[0]) == bool(r[6]), (q, r[1])
     finally:
         srv.stop()
-    for q in sorted(by_q)[:8]:
+    say("workload 5: %d served full counts" % len(tickets))
+    assert len(tickets) >= 16
+    n_plain = 0
+    for q in sorted(by_q):
         p, s = sel[q]
         C = cc.color(ctx, G, p.n, W.colouring_seed(s), 1)
-        cnt, ovf = cc.count(ctx, G, C, decs[q])
-        assert int(cnt[0]) == by_q[q][0][5], (q, p.name)
+        for r in by_q[q]:
+            if (r[3], r[4]) == (0, g.n):
+                if n_plain < 8:
+                    cnt, ovf = cc.count(ctx, G, C, decs[q])
+                    assert int(cnt[0]) == r[5] and bool(ovf[0]) == bool(r[6]), (q, p.name)
+                    n_plain += 1
+            else:
+                cnt, ovf = cc.count_range(ctx, G, C, decs[q], r[3], r[4])
+                assert int(cnt[0]) == r[5] and bool(ovf[0]) == bool(r[6]), (q, p.name, r[3], r[4])

@@ -348,7 +348,7 @@ def test_node_table_sizes_vs_definition(pat):
         for k in (pat.n, pat.n + 1):
             col = colours(rng, g.n, k)
             for dm in (True, False):
-                got = O.dp_count(g, pat, k, col, td=td, degmask=dm, sizes=True)["sizes"]
+                got = O.dp_count(g, pat, k, col, td=td, degmask=dm, sizes=True, distbound=False)["sizes"]
                 assert list(got) == _definition_table_sizes(g, pat, k, col, td, degmask=dm)
 
 
@@ -377,3 +377,78 @@ def test_anchor_ranges_partition_the_count(pat):
     assert total % U64 == full["count"]
     assert O.dp_count_range(g, pat, pat.n, col, 0, g.n)["count"] == full["count"]
     assert O.dp_count_range(g, pat, pat.n, col, 5, 5)["count"] == 0
+
+
+def test_vertex_sets_closed_forms():
+    """A host that is a disjoint union of induced copies of F: every copy is
+    one vertex set and |Aut(F)| mappings; with fewer vertex-set-distinct
+    colourings the sets are exactly the colourful copies (brute force)."""
+    for pat, aut in ((W.cycle(3), 6), (W.path(4), 2), (W.star(4), 6), (W.cycle(5), 10)):
+        copies = 4
+        a = np.concatenate([np.array([e[0] for e in pat.edges]) + pat.n * c for c in range(copies)])
+        b = np.concatenate([np.array([e[1] for e in pat.edges]) + pat.n * c for c in range(copies)])
+        g = W.csr_from_edges(pat.n * copies, a, b)
+        col = np.tile(np.arange(pat.n), copies).astype(np.uint8)  # every copy colourful
+        sets = O.vertex_sets(g, pat, pat.n, col)
+        assert len(sets) == copies
+        assert O.dp_count(g, pat, pat.n, col)["count"] == copies * aut
+        assert B.automorphisms(pat) == aut
+    # general hosts: the sets of the brute-force mappings
+    rng = np.random.default_rng(9)
+    for g in zoo_graphs():
+        for pat in (W.path(3), W.cycle(4), W.star(4), W.grid(2, 2)):
+            col = colours(rng, g.n, pat.n)
+            ref = sorted({tuple(sorted(m)) for m in B.all_mappings(g, pat, col)})
+            assert O.vertex_sets(g, pat, pat.n, col) == ref
+
+
+def test_repetition_count_and_search_finds_every_occurrence():
+    """ceil(e^{n_F} ln(1/eps)) colourings; with eps tiny the union of the
+    colourful mappings of all runs is every injective adjacency-preserving
+    mapping of a tiny host (each is colourful in a run with probability
+    >= n_F!/n_F^{n_F})."""
+    import math
+
+    assert O.repetitions(5, 1 / math.e) == math.ceil(math.exp(5))
+    assert O.repetitions(3, 1e-9) == math.ceil(math.exp(3) * math.log(1e9))
+    g = W.er_pairs(9, 0.45, 4)
+    for pat in (W.path(3), W.cycle(3)):
+        every = set()
+        adj = B.adjacency(g)
+        for phi in itertools.permutations(range(g.n), pat.n):
+            if all(phi[b] in adj[phi[a]] for a, b in pat.edges):
+                every.add(phi)
+        rows, run = O.search(g, pat, 1e-9, 77, 10**6)
+        assert run == O.repetitions(pat.n, 1e-9)
+        assert set(rows) == every
+        sets, _ = O.search(g, pat, 1e-9, 77, 10**6, distinct_sets=True)
+        assert set(sets) == {tuple(sorted(r)) for r in every}
+        few, run2 = O.search(g, pat, 1e-9, 77, 3)
+        assert len(few) == 3 and run2 <= run and few == sorted(few)
+
+
+@pytest.mark.parametrize("pat", [W.pattern_C(), W.pattern_D(), W.Pattern(6, [(0, 1), (1, 2), (3, 4), (4, 5), (2, 3)], "P6")],
+                         ids=lambda p: p.name)
+def test_distance_bound_keeps_counts(pat):
+    """The distance bound of Sec. 3.2 only drops entries that cannot
+    complete: with it on and off, counts, flags and enumerated rows agree
+    (brute force) on every decomposition tried, while the tables of
+    introduce nodes with no bag neighbour can only shrink."""
+    rng = np.random.default_rng(31)
+    tds = [O.build_td(pat)[0]]
+    import paper_1908_11248_amd as cc
+
+    try:
+        tds.append(cc.build_decomposition(pat.n, pat.edges).export())
+    except Exception:
+        pass
+    for g in (W.er_pairs(14, 0.3, 3), W.er_pairs(30, 0.15, 4), W.rgg(40, 6, 5)):
+        col = colours(rng, g.n, pat.n)
+        ref = O.brute_count(g, pat, col)
+        for td in tds:
+            on = O.dp_count(g, pat, pat.n, col, td=td, sizes=True)
+            off = O.dp_count(g, pat, pat.n, col, td=td, sizes=True, distbound=False)
+            assert on["count"] == off["count"] == ref
+            assert (on["sizes"] <= off["sizes"]).all()
+        rows, _ = O.dp_enumerate(g, pat, pat.n, col, 10**6)
+        assert [tuple(r) for r in rows] == [tuple(r) for r in O.brute_enum(g, pat, col, 10**6)]
