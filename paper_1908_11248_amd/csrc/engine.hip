@@ -1447,7 +1447,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         o = X.table(lo, 0);
                         break;
                     }
-                    if (k > std::min(kDenseColours, ctx->sort_above_k)) {
+                    if (k > kDenseColours || (!links && k > ctx->sort_above_k)) {
                         // colour sets too wide for the dense accumulators (or
                         // the schedule prefers sorting): drop
                         // the column, sort, add up runs of equal keys
@@ -1522,7 +1522,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         o = X.table(lo, 0);
                         break;
                     }
-                    if (k > std::min(kDenseColours, ctx->sort_above_k)) {
+                    if (k > kDenseColours || (!links && k > ctx->sort_above_k)) {
                         // colour sets too wide for the dense accumulators (or
                         // the schedule prefers sorting): all admissible
                         // pairs, then sort and add up runs

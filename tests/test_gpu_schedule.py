@@ -43,3 +43,19 @@ def test_schedules_agree_with_oracle_and_tuner_picks_one():
         out = cc.count_batch(ctx, G, list(zip(decs, cols)))
         for i, (c, _) in enumerate(out):
             assert [int(x) for x in c] == ref[i], pats[i].name
+
+
+def test_enumeration_under_a_sorting_schedule():
+    # enumeration records contributors, which only the dense forget and join
+    # produce: a schedule that sorts elsewhere leaves it unchanged
+    g = W.er_pairs(80, 0.12, 5)
+    pat = W.cycle(5)
+    with cc.Context(0, arena_bytes=1 << 30) as ctx:
+        ctx.set_schedule(lanes=1, entry_factor=3, sort_above_k=0)
+        G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
+        D = cc.build_decomposition(pat.n, pat.edges)
+        C = cc.color(ctx, G, pat.n, 3, 1)
+        sets, nmap = cc.vertex_sets(ctx, G, C, 0, D, 10**6)
+        col = O.color_array(3, 0, g.n, pat.n)
+        assert nmap == O.dp_count(g, pat, pat.n, col)["count"]
+        assert [tuple(r) for r in sets] == O.vertex_sets(g, pat, pat.n, col)
