@@ -12,6 +12,9 @@
 
 using namespace ccg;
 
+// edge-set cells per stored (directed) edge, rounded up to a power of two
+static constexpr uint64_t kEdgeCellFactor = 2;
+
 // Device scratch of cc_count_noalloc: a fixed array in the code object, so
 // that call allocates nothing.  Every device the library runs on holds its
 // own copy until the process ends.  In host code `scratch` is only a
@@ -204,11 +207,13 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
         std::vector<int32_t> src(m2);
         for (int32_t v = 0; v < n; v++)
             for (int64_t e = rp[v]; e < rp[v + 1]; e++) src[e] = v;
-        // edge set for adjacency tests: 8m cells or more, a power of two (a
-        // load of at most 1/8 keeps the linear-probing chains, which every
-        // lane of a wave waits for, short)
+        // edge set for adjacency tests: 2m cells or more, a power of two (a
+        // load of at most one half; the kernels read a chain a 64-byte group
+        // of eight cells at a time, and at this load it rarely leaves its home
+        // group, while the table stays small enough for the last-level cache
+        // on graphs of 10^7 edges)
         uint64_t cells = 16;
-        while (cells < uint64_t(std::max<int64_t>(m2, 1)) * 4) cells <<= 1;
+        while (cells < uint64_t(std::max<int64_t>(m2, 1)) * kEdgeCellFactor) cells <<= 1;
         std::vector<uint64_t> eh(cells, kEdgeEmpty);
         for (int32_t v = 0; v < n; v++)
             for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
@@ -237,6 +242,12 @@ int cc_load_graph(cc_context* ctx, int32_t n, const int64_t* row_ptr, const int3
             hip_check(hipMalloc(&g->col, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
             hip_check(hipMalloc(&g->esrc, 4 * size_t(std::max<int64_t>(m2, 1))), "hipMalloc");
             hip_check(hipMalloc(&g->ehash, 8 * cells), "hipMalloc");
+            {
+                std::vector<uint8_t> d8(std::max<int32_t>(n, 1), 0);
+                for (int32_t v = 0; v < n; v++) d8[v] = uint8_t(std::min<int64_t>(rp[v + 1] - rp[v], 255));
+                hip_check(hipMalloc(&g->deg8, d8.size()), "hipMalloc");
+                hip_check(hipMemcpy(g->deg8, d8.data(), d8.size(), hipMemcpyHostToDevice), "hipMemcpy");
+            }
             hip_check(hipMemcpy(g->ehash, eh.data(), 8 * cells, hipMemcpyHostToDevice), "hipMemcpy");
             g->ehmask = cells - 1;
             hip_check(hipMalloc(&g->heavy, 4 * std::max<size_t>(heavy.size(), 1)), "hipMalloc");
@@ -263,6 +274,7 @@ void cc_graph_free(cc_graph* g) {
     if (g->esrc) (void)hipFree(g->esrc);
     if (g->heavy) (void)hipFree(g->heavy);
     if (g->ehash) (void)hipFree(g->ehash);
+    if (g->deg8) (void)hipFree(g->deg8);
     if (g->ball_pre) (void)hipFree(g->ball_pre);
     if (g->ball_w2) (void)hipFree(g->ball_w2);
     delete g;

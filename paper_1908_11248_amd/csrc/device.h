@@ -49,21 +49,80 @@ __device__ __forceinline__ K shr(K key, int sh) {
 __device__ __forceinline__ int64_t gdeg(const DevGraph& g, uint32_t v) { return g.rp[v + 1] - g.rp[v]; }
 // v passes the degree mask of the introduced vertex (deg_G(v) >= deg_F(u),
 // Sec. 3.2) and lies in the step's image range
+// (deg_F(u) <= 15 < 255, so the clamped byte decides it)
 __device__ __forceinline__ bool intro_ok(const DevGraph& g, uint32_t v, int degF) {
-    return gdeg(g, v) >= degF && int32_t(v) >= g.vlo && int32_t(v) < g.vhi;
+    return int(g.deg8[v]) >= degF && int32_t(v) >= g.vlo && int32_t(v) < g.vhi;
 }
 
-// {a, b} in E(G): a probe of the edge set (usually one cell)
+// The edge set is probed a group of kEdgeGroup cells at a time (aligned, one
+// vector load per two cells; the table is a power of two of at least 16
+// cells, so groups never wrap).  A key sits at or after its home cell, before
+// the first empty cell from there on: in the home group, cells before the
+// home cell can hold the key (a hit all the same) but their empty cells do
+// not end the search.  Returns 1: present, 0: absent, -1: look on in the
+// next group.
+constexpr int kEdgeGroup = 2;
+__device__ __forceinline__ int edge_group(const uint64_t* __restrict__ eh, uint64_t grp, int first, uint64_t key) {
+    uint64_t c[kEdgeGroup];
+    if (kEdgeGroup == 1) {
+        c[0] = eh[grp];
+    } else {
+        const ulonglong2* p = reinterpret_cast<const ulonglong2*>(eh + grp);
+#pragma unroll
+        for (int j = 0; j < kEdgeGroup / 2; j++) {
+            const ulonglong2 x = p[j];
+            c[2 * j] = x.x;
+            c[2 * j + 1] = x.y;
+        }
+    }
+    bool hit = false, empty = false;
+#pragma unroll
+    for (int j = 0; j < kEdgeGroup; j++) {
+        hit |= c[j] == key;
+        empty |= j >= first && c[j] == kEdgeEmpty;
+    }
+    return hit ? 1 : (empty ? 0 : -1);
+}
+
+// presence of an edge-set key: the home group, then the following ones
+__device__ __forceinline__ bool edge_present(const DevGraph& g, uint64_t key) {
+    const uint64_t h = edge_cell(key, g.ehmask);
+    uint64_t grp = h & ~uint64_t(kEdgeGroup - 1);
+    int r = edge_group(g.eh, grp, int(h & (kEdgeGroup - 1)), key);
+    while (r < 0) {
+        grp = (grp + kEdgeGroup) & g.ehmask;
+        r = edge_group(g.eh, grp, 0, key);
+    }
+    return r > 0;
+}
+
+// {a, b} in E(G)
 __device__ __forceinline__ bool has_edge(const DevGraph& g, uint32_t a, uint32_t b) {
     if (a == b) return false;
-    const uint64_t key = edge_key(a, b);
-    uint64_t h = edge_cell(key, g.ehmask);
-    for (;;) {
-        const uint64_t x = g.eh[h];
-        if (x == key) return true;
-        if (x == kEdgeEmpty) return false;
-        h = (h + 1) & g.ehmask;
+    return edge_present(g, edge_key(a, b));
+}
+
+// four keys at once: the home groups' loads are in flight together
+// (bit j of want: probe key j; returns the bits of the present ones)
+__device__ __forceinline__ uint32_t edges_present4(const DevGraph& g, const uint64_t key[4], uint32_t want) {
+    int r[4];
+    uint64_t grp[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint64_t h = edge_cell(key[j], g.ehmask);
+        grp[j] = h & ~uint64_t(kEdgeGroup - 1);
+        r[j] = ((want >> j) & 1u) ? edge_group(g.eh, grp[j], int(h & (kEdgeGroup - 1)), key[j]) : 0;
     }
+    uint32_t out = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        while (r[j] < 0) {  // rare: the chain runs past the home group
+            grp[j] = (grp[j] + kEdgeGroup) & g.ehmask;
+            r[j] = edge_group(g.eh, grp[j], 0, key[j]);
+        }
+        out |= uint32_t(r[j] > 0) << j;
+    }
+    return out;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {

@@ -158,6 +158,7 @@ struct cc_graph {
     int32_t* heavy = nullptr;
     int32_t nheavy = 0;
     uint64_t* ehash = nullptr;  // edge set (kernels.h edge_key / edge_cell)
+    uint8_t* deg8 = nullptr;    // [n] min(degree, 255)
     uint64_t ehmask = 0;
     std::vector<int64_t> sorted_deg;  // host copy, ascending
     std::vector<int64_t> host_rp;     // host copy of the row pointers (degree prefix sums)
@@ -174,7 +175,7 @@ struct cc_graph {
     int64_t count_deg_at_least(int64_t d) const;
     // fraction of edge endpoints whose vertex has degree >= d
     double nb_fraction_at_least(int64_t d) const;
-    ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc, heavy, nheavy, ehash, ehmask}; }
+    ccg::DevGraph dev() const { return ccg::DevGraph{n, m2, rp, col, esrc, heavy, nheavy, ehash, ehmask, deg8}; }
 };
 
 struct cc_coloring {

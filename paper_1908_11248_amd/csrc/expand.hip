@@ -221,25 +221,14 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
                 for (int j = 0; j < 4; j++) ok |= uint32_t(!(kset(kk[j], L) & cb4[j])) << j;
                 for (int c = 0; c < a.nchk; c++) {
                     if (!(PULL || a.chk[c] >= a.pos)) continue;
-                    uint64_t key[4], h[4], x[4];
+                    uint64_t key[4];
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const uint32_t u = kcol(kk[j], L, a.chk[c]);
                         key[j] = edge_key(u, vv[j]);
-                        h[j] = edge_cell(key[j], g.ehmask);
                         if (u == vv[j]) ok &= ~(1u << j);
                     }
-#pragma unroll
-                    for (int j = 0; j < 4; j++) x[j] = ((ok >> j) & 1u) ? g.eh[h[j]] : key[j];
-#pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        if (!((ok >> j) & 1u)) continue;
-                        while (x[j] != key[j] && x[j] != kEdgeEmpty) {  // rare: probe on
-                            h[j] = (h[j] + 1) & g.ehmask;
-                            x[j] = g.eh[h[j]];
-                        }
-                        if (x[j] != key[j]) ok &= ~(1u << j);
-                    }
+                    ok &= edges_present4(g, key, ok);
                 }
                 pass |= ok << (tb - t0);
                 n_pass += __popc(ok);
@@ -419,27 +408,16 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
                 // every bag neighbour other than the candidates' source is
                 // adjacent (the source is, by construction)
                 for (int c = 0; c < nnb; c++) {
-                    uint64_t ek[4], h[4], xw[4];
+                    uint64_t ek[4];
                     uint32_t probe = 0;
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const uint32_t w = kcol(kk[j], L, nb[c]);
                         ek[j] = edge_key(w, vv[j]);
-                        h[j] = edge_cell(ek[j], g.ehmask);
                         if (w == vv[j]) ok &= ~(1u << j);
                         if (((ok >> j) & 1u) && uint32_t(nb[c]) != scj[j]) probe |= 1u << j;
                     }
-#pragma unroll
-                    for (int j = 0; j < 4; j++) xw[j] = ((probe >> j) & 1u) ? g.eh[h[j]] : ek[j];
-#pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        if (!((probe >> j) & 1u)) continue;
-                        while (xw[j] != ek[j] && xw[j] != kEdgeEmpty) {
-                            h[j] = (h[j] + 1) & g.ehmask;
-                            xw[j] = g.eh[h[j]];
-                        }
-                        if (xw[j] != ek[j]) ok &= ~(1u << j);
-                    }
+                    ok &= ~probe | edges_present4(g, ek, probe);
                 }
                 pass |= ok << (tb - t0);
                 n_pass += __popc(ok);

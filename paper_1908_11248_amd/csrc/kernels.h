@@ -39,7 +39,8 @@ struct DevGraph {
     const int32_t* heavy; // vertices of degree > kHeavyDegree, ascending
     int32_t nheavy;
     const uint64_t* eh;   // edge set: open addressing, linear probing, kEdgeEmpty in free cells
-    uint64_t ehmask;      // cells - 1 (a power of two at least eight times m)
+    uint64_t ehmask;      // cells - 1 (a power of two, at least 2 m: a load of at most one half)
+    const uint8_t* deg8;  // [n] min(deg(v), 255): the degree masks read one byte
     // Images allowed for the vertex a step introduces: [vlo, vhi).  The whole
     // of V(G) except in the steps that introduce the anchor pattern vertex of
     // an anchor-range chunk (counts add over disjoint ranges of its image).

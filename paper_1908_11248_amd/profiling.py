@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
-    python -m paper_1908_11248_amd.profiling stats  <kernel_stats.csv> <out.md> <command...>
+    python -m paper_1908_11248_amd.profiling stats  <kernel_stats.csv | results.db> <out.md> <command...>
     python -m paper_1908_11248_amd.profiling traffic <fetch_dir> <write_dir> <copy_mib> <out.json> <command...>
 
 `stats` turns a --kernel-trace --stats CSV into a short table.  `traffic`
@@ -31,6 +31,11 @@ KERNEL_NAMES = [
     (r"k_edge<.*false, true>", "edge_count"), (r"k_edge<.*false, false>", "edge_count"),
     (r"k_join<.*true>", "join_emit"), (r"k_join<.*false>", "join_count"),
     (r"k_forget<.*true>", "forget_emit"), (r"k_forget<.*false>", "forget_count"),
+    (r"k_expand_entry<.*true>", "entry_emit"), (r"k_expand_entry<.*false>", "entry_count"),
+    (r"k_entry_seglen", "entry_seglen"), (r"k_push_seglen", "push_seglen"), (r"k_pull_seglen", "pull_seglen"),
+    (r"k_expand_ball<.*true>", "ball_emit"), (r"k_expand_ball<.*false>", "ball_count"), (r"k_ball_seglen", "ball_seglen"),
+    (r"k_join_pairs", "join_pairs"), (r"k_drop_last", "drop_last"), (r"k_reduce_runs", "reduce_runs"),
+    (r"k_take_runs", "take_runs"), (r"k_expand_bounds", "expand_bounds"),
     (r"k_expand<.*true, true>", "pull_emit"), (r"k_expand<.*false, true>", "pull_count"),
     (r"k_expand<.*true, false>", "push_emit"), (r"k_expand<.*false, false>", "push_count"),
     (r"k_pull_index", "pull_index"), (r"k_root", "root"), (r"k_heads", "heads"),
@@ -55,17 +60,31 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def _db_stats(db_path):
+    """kernel_stats rows from a rocprofv3 database (its default output)."""
+    import sqlite3
+
+    db = sqlite3.connect(db_path)
+    rows = db.execute("SELECT name, COUNT(*), SUM(end - start), AVG(end - start) FROM kernels "
+                      "GROUP BY name ORDER BY SUM(end - start) DESC").fetchall()
+    total = sum(r[2] for r in rows) or 1
+    return [{"Name": r[0], "Calls": r[1], "TotalDurationNs": r[2], "AverageNs": r[3], "Percentage": 100.0 * r[2] / total}
+            for r in rows]
+
+
 def stats(csv_path, out_md, command):
-    rows = list(csv.DictReader(open(csv_path)))
+    rows = _db_stats(csv_path) if csv_path.endswith(".db") else list(csv.DictReader(open(csv_path)))
     lines = ["# rocprofv3 kernel statistics", "", "Command:", "", "    " + command, "",
-             "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+             "Durations are of the kernels alone (concurrent kernels overlap in time).", "",
+             "| kernel | short name | calls | total ms | avg us | % |", "|---|---|---|---|---|---|"]
     for r in rows[:25]:
         name = r.get("Name") or r.get("KernelName") or r.get("Kernel_Name")
         calls = int(r.get("Calls") or r.get("TotalCalls") or 0)
         tot = float(r.get("TotalDurationNs") or r.get("TotalDuration") or 0)
         avg = float(r.get("AverageNs") or r.get("Average") or 0)
         pct = float(r.get("Percentage") or 0)
-        lines.append("| %s | %d | %.3f | %.1f | %.1f |" % (name.split("(")[0][:110], calls, tot / 1e6, avg / 1e3, pct))
+        lines.append("| %s | %s | %d | %.3f | %.1f | %.1f |" % (name.split("(")[0][:110], short_name(name) or "-", calls,
+                                                               tot / 1e6, avg / 1e3, pct))
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
