@@ -301,20 +301,24 @@ int cc_count_batch(cc_context *ctx, const cc_graph *g, int32_t nq, const cc_quer
 int cc_set_batch_lanes(cc_context *ctx, int32_t lanes);
 /* Schedule of a context: concurrent lanes of a batch; the introduce form
  * (entry-wise when it walks fewer than 1/entry_factor of the fixed column's
- * candidates); forget and join on sorted lists add up by sorting when
- * k > sort_above_k, else in dense 2^k LDS accumulators (k <= 12 only).
- * Defaults: 4 lanes (0 = default), 3, 12.  Every schedule gives the same
- * results. */
+ * candidates); entry-wise introduces test adjacency once per group of
+ * entries with equal bag images when the child has at least group_min
+ * entries per such group (0: never); forget and join on sorted lists add up
+ * by sorting when k > sort_above_k, else in dense 2^k LDS accumulators
+ * (k <= 12 only).  Defaults: 4 lanes (0 = default), 3, 12, 2.  Every
+ * schedule gives the same results. */
 typedef struct {
     int32_t lanes;
     int32_t entry_factor;
     int32_t sort_above_k;
+    int32_t group_min;
 } cc_schedule;
 int cc_get_schedule(const cc_context *ctx, cc_schedule *out);
 int cc_set_schedule(cc_context *ctx, const cc_schedule *s);
 /* Autotuner: times cc_count_batch on the given queries and keeps the
  * fastest schedule for the context, by coordinate descent: lanes 1, 2, 4, 8;
- * then entry_factor 1, 3, 8; then sort_above_k 12, 8, 0.  The counts of
+ * then entry_factor 1, 3, 8; then sort_above_k 12, 8, 0; then group_min 2,
+ * 0, 4.  The counts of
  * every trial must agree (CC_EDEVICE otherwise).  *best receives the lanes. */
 int cc_tune_batch(cc_context *ctx, const cc_graph *g, int32_t nq, const cc_query *q, uint32_t flags,
                   int32_t *best);

@@ -206,7 +206,8 @@ class Decomp(_Handle):
 
 
 class _Schedule(ctypes.Structure):
-    _fields_ = [("lanes", ctypes.c_int32), ("entry_factor", ctypes.c_int32), ("sort_above_k", ctypes.c_int32)]
+    _fields_ = [("lanes", ctypes.c_int32), ("entry_factor", ctypes.c_int32), ("sort_above_k", ctypes.c_int32),
+                ("group_min", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -278,10 +279,11 @@ class Context(_Handle):
     def schedule(self) -> dict:
         s = _Schedule()
         _check(lib().cc_get_schedule(self.ptr, ctypes.byref(s)))
-        return {"lanes": s.lanes, "entry_factor": s.entry_factor, "sort_above_k": s.sort_above_k}
+        return {"lanes": s.lanes, "entry_factor": s.entry_factor, "sort_above_k": s.sort_above_k,
+                "group_min": s.group_min}
 
-    def set_schedule(self, lanes: int = 0, entry_factor: int = 3, sort_above_k: int = 12):
-        s = _Schedule(lanes, entry_factor, sort_above_k)
+    def set_schedule(self, lanes: int = 0, entry_factor: int = 3, sort_above_k: int = 12, group_min: int = 2):
+        s = _Schedule(lanes, entry_factor, sort_above_k, group_min)
         _check(lib().cc_set_schedule(self.ptr, ctypes.byref(s)))
 
     def set_table_budget(self, max_entries: int):

@@ -277,6 +277,8 @@ void cc_graph_free(cc_graph* g) {
     if (g->deg8) (void)hipFree(g->deg8);
     if (g->ball_pre) (void)hipFree(g->ball_pre);
     if (g->ball_w2) (void)hipFree(g->ball_w2);
+    if (g->cn_off) (void)hipFree(g->cn_off);
+    if (g->cn_col) (void)hipFree(g->cn_col);
     delete g;
 }
 

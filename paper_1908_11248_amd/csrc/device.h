@@ -96,6 +96,28 @@ __device__ __forceinline__ bool edge_present(const DevGraph& g, uint64_t key) {
     return r > 0;
 }
 
+// index in col of the stored edge between x and y (x != y), searched in the
+// shorter of the two rows; -1 when they are not adjacent
+__device__ __forceinline__ int64_t edge_index(const DevGraph& g, uint32_t x, uint32_t y) {
+    int64_t lo = g.rp[x], end = g.rp[x + 1];
+    const int64_t lo_y = g.rp[y], end_y = g.rp[y + 1];
+    uint32_t key = y;
+    if (end_y - lo_y < end - lo) {
+        lo = lo_y;
+        end = end_y;
+        key = x;
+    }
+    int64_t hi = end;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (uint32_t(g.col[mid]) < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < end && uint32_t(g.col[lo]) == key) ? lo : -1;
+}
+
 // {a, b} in E(G)
 __device__ __forceinline__ bool has_edge(const DevGraph& g, uint32_t a, uint32_t b) {
     if (a == b) return false;

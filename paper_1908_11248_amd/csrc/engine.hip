@@ -1002,6 +1002,35 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     Arena& arena = rq.arena ? *rq.arena : ctx->arena;
     Exec X{lane, lane.stream, arena, rq.max_entries};
     hipStream_t s = lane.stream;
+    // the graph's common-neighbour index, built the first time an introduce
+    // can use it (not in calls that may not allocate)
+    auto cn_ready = [&]() -> bool {
+        cc_graph* gm = const_cast<cc_graph*>(rq.g);
+        std::lock_guard<std::mutex> lk(gm->ball_mu);
+        if (!gm->cn_off && !rq.no_alloc && g_all.m2 > 0) {
+            const uint64_t m2 = uint64_t(g_all.m2);
+            uint32_t* cnt = X.alloc<uint32_t>(m2);
+            X.timed("cn_count", 12.0 * double(m2), [&] { launch_cn_count(g_all, cnt, s); });
+            uint64_t* offs;
+            const uint64_t total = X.scan(cnt, m2, &offs);
+            X.release(cnt);
+            uint64_t* off = nullptr;
+            int32_t* lists = nullptr;
+            hip_check(hipMalloc(&off, 8 * (size_t(m2) + 1)), "hipMalloc");
+            if (hipMalloc(&lists, 4 * std::max<size_t>(total, 1)) != hipSuccess) {
+                (void)hipFree(off);
+                X.release(offs);
+                fail(CC_ENOMEM, "common-neighbour index");
+            }
+            hip_check(hipMemcpyAsync(off, offs, 8 * (size_t(m2) + 1), hipMemcpyDeviceToDevice, s), "copy");
+            X.timed("cn_emit", 12.0 * double(m2) + 4.0 * double(total), [&] { launch_cn_emit(g_all, off, lists, s); });
+            hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            X.release(offs);
+            gm->cn_off = off;
+            gm->cn_col = lists;
+        }
+        return gm->cn_off != nullptr;
+    };
     const size_t S = plan.steps.size();
     std::vector<DevTable> tab(S);
     std::vector<StepLinks> lk(S);
@@ -1270,6 +1299,29 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 const DevTable& in = tab[st.in0];
                 ea.sel = nullptr;
                 ea.segv = nullptr;
+                // two bag neighbours of u adjacent to each other in F: the
+                // candidates are the common neighbours of their images
+                {
+                    const Step& ch = plan.steps[size_t(st.in0)];
+                    int cand[5], nc = 0;
+                    cand[nc++] = st.anchor;
+                    for (int j = 0; j < st.nchk; j++) cand[nc++] = st.chk[j];
+                    for (int p = 0; p < nc && ea.cn0 < 0; p++)
+                        for (int q = p + 1; q < nc && ea.cn0 < 0; q++)
+                            if ((dec.adj[ch.cols[cand[p]]] >> ch.cols[cand[q]]) & 1u) {
+                                ea.cn0 = cand[p];
+                                ea.cn1 = cand[q];
+                            }
+                }
+                if (ea.cn0 >= 0) {
+                    if (cn_ready()) {
+                        ea.cn_off = rq.g->cn_off;
+                        ea.cn_col = rq.g->cn_col;
+                        ea.erow = X.alloc<int64_t>(in.n);
+                    } else {
+                        ea.cn0 = ea.cn1 = -1;
+                    }
+                }
                 e_slen = X.alloc<uint32_t>(in.n);
                 e_src = X.alloc<uint8_t>(in.n);
                 uint64_t* anchor_items = X.alloc<uint64_t>(1);
@@ -1284,11 +1336,83 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 if (!entry_form) {
                     X.release(e_soff);
                     X.release(e_src);
+                    if (ea.erow) X.release(ea.erow);
                 }
             }
             if (entry_form) {
                 const DevTable& in = tab[st.in0];
-                {
+                // Entries that differ only in their colour sets share every
+                // adjacency test: when they come at least two to a group, the
+                // tests run once per (group, candidate) with the push-form
+                // kernels over groups of whole bags, and the expand then only
+                // tests colours.  Output order (group, candidate, colour set)
+                // is key order when u is the last column; else the same
+                // re-sort follows.
+                uint64_t* fgs = nullptr;
+                const uint64_t Gf = X.groups(in, in.lay.kb, &fgs);
+                if (ea.cn0 < 0 && g.n <= (1 << 27) && ctx->group_min > 0 && uint64_t(ctx->group_min) * Gf <= in.n) {
+                    X.release(e_soff);
+                    X.release(e_src);
+                    IntroArgs ga = ea;
+                    ga.grouped = true;
+                    uint32_t* wcount = X.alloc<uint32_t>(Gf);
+                    uint8_t* gsel = X.alloc<uint8_t>(Gf);
+                    ga.sel = gsel;
+                    X.timed("group_work", double(Gf) * (in.lay.key_bytes() + 13.0),
+                            [&] { launch_push_work(in, fgs, Gf, g, ga, wcount, s); });
+                    uint64_t* woff;
+                    const uint64_t W = X.scan(wcount, Gf, &woff);
+                    X.release(wcount);
+                    uint32_t* slen = X.alloc<uint32_t>(W);
+                    ga.segv = X.alloc<uint32_t>(W);
+                    X.timed("group_seglen", 28.0 * W,
+                            [&] { launch_push_seglen(in, fgs, woff, Gf, W, g, rq.colors, ga, slen, s); });
+                    uint64_t* soff;
+                    const uint64_t T = X.scan(slen, W, &soff);
+                    X.release(slen);
+                    const uint64_t tiles = expand_tiles(T);
+                    uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                    uint16_t* pbits = X.alloc<uint16_t>(expand_pass_words(T));
+                    X.timed("group_count", double(T) * in.lay.key_bytes(), [&] {
+                        launch_expand_count(false, in, fgs, woff, Gf, nullptr, soff, W, T, g, rq.colors, ga, tcount, pbits,
+                                            s);
+                    });
+                    uint64_t* toff;
+                    const uint64_t N = X.scan(tcount, tiles, &toff);
+                    X.release(tcount);
+                    o = X.table(lo, N);
+                    if (N)
+                        X.timed("group_emit", double(in.n) * entry_bytes(in.lay.b) + double(N) * entry_bytes(lo.b), [&] {
+                            launch_expand_emit(false, in, fgs, woff, Gf, nullptr, soff, W, T, g, rq.colors, ga, toff, pbits,
+                                               o, nullptr, s);
+                        });
+                    X.release(pbits);
+                    X.release(toff);
+                    X.release(soff);
+                    X.release(ga.segv);
+                    X.release(woff);
+                    X.release(gsel);
+                    X.release(fgs);
+                    if (N > 1 && st.pos != lo.b - 1) {
+                        // stable sort on (colouring, columns 0..pos)
+                        const int sort_lo = lo.kb + (lo.b - 1 - st.pos) * lo.vb;
+                        void* kb2 = X.raw(N * lo.key_bytes());
+                        uint64_t* vb2 = X.alloc<uint64_t>(N);
+                        void* tmp = X.raw(radix_tmp_bytes(N));
+                        bool in_b = false;
+                        X.timed("radix_sort", double(N) * entry_bytes(lo.b) * 2, [&] {
+                            in_b = radix_sort(o.keys, o.cnt, kb2, vb2, N, lo.kw(), lo.bits(), sort_lo, tmp, s, false);
+                        });
+                        if (in_b) {
+                            std::swap(o.keys, kb2);
+                            std::swap(o.cnt, vb2);
+                        }
+                        X.release(tmp);
+                        X.release(vb2);
+                        X.release(kb2);
+                    }
+                } else {
+                    X.release(fgs);
                     uint8_t* src = e_src;
                     uint64_t* soff = e_soff;
                     const uint64_t T = e_T;
@@ -1310,6 +1434,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     X.release(toff);
                     X.release(soff);
                     X.release(src);
+                    if (ea.erow) X.release(ea.erow);
                     if (N > 1) {
                         // stable sort on (colouring, columns 0..pos)
                         const int sort_lo = lo.kb + (lo.b - 1 - st.pos) * lo.vb;
@@ -1362,6 +1487,29 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     uint32_t* wcount = X.alloc<uint32_t>(G);
                     uint8_t* gsel = X.alloc<uint8_t>(G);
                     ia.sel = gsel;
+                    // two bag neighbours of u before pos adjacent to each other
+                    // in F: a group's candidates are the common neighbours of
+                    // their images
+                    if (st.anchor >= 0 && !links && g.n <= (1 << 27)) {
+                        const Step& ch = plan.steps[size_t(st.in0)];
+                        int cand[5], nc = 0;
+                        cand[nc++] = st.anchor;
+                        for (int j = 0; j < st.nchk; j++)
+                            if (st.chk[j] < st.pos) cand[nc++] = st.chk[j];
+                        for (int p = 0; p < nc && ia.cn0 < 0; p++)
+                            for (int q = p + 1; q < nc && ia.cn0 < 0; q++)
+                                if ((dec.adj[ch.cols[cand[p]]] >> ch.cols[cand[q]]) & 1u) {
+                                    ia.cn0 = cand[p];
+                                    ia.cn1 = cand[q];
+                                }
+                        if (ia.cn0 >= 0 && cn_ready()) {
+                            ia.cn_off = rq.g->cn_off;
+                            ia.cn_col = rq.g->cn_col;
+                            ia.erow = X.alloc<int64_t>(G);
+                        } else {
+                            ia.cn0 = ia.cn1 = -1;
+                        }
+                    }
                     X.timed("push_work", 20.0 * G, [&] { launch_push_work(in, gstart, G, g, ia, wcount, s); });
                     uint64_t* woff;
                     uint64_t W = X.scan(wcount, G, &woff);
@@ -1396,6 +1544,9 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     X.release(woff);
                     X.release(ia.segv);
                     ia.segv = nullptr;
+                    if (ia.erow) X.release(ia.erow);
+                    ia.erow = nullptr;
+                    ia.cn0 = ia.cn1 = -1;
                     X.release(gsel);
                     X.release(gstart);
                     break;

@@ -51,18 +51,28 @@ k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gs
         const uint64_t s0 = s_lo + uint64_t(threadIdx.x) * kSegItems;
         if (s0 >= s_hi) continue;
         uint64_t grp = upper_bound_u64(woff, g_lo, g_end + 1, s0) - 1;
-        // the group's state: first key, candidate source column and its row
+        // the group's state: first key, candidate source column (-2: the
+        // common neighbours of columns cn0 and cn1) and its list
         K k0;
         int src;
         int64_t row;
+        const int32_t* cand = g.col;
         uint32_t glen;
         auto load_group = [&]() {
             const uint64_t e0 = gstart[grp];
             k0 = keys[e0];
-            src = a.anchor >= 0 && a.sel ? int(a.sel[grp]) : a.anchor;
-            row = src >= 0 ? g.rp[kcol(k0, L, src)] : 0;
+            if (a.cn0 >= 0) {
+                src = -2;
+                row = a.erow[grp];
+                cand = a.cn_col;
+            } else {
+                src = a.anchor >= 0 && a.sel ? int(a.sel[grp]) : a.anchor;
+                row = src >= 0 ? g.rp[kcol(k0, L, src)] : 0;
+                cand = g.col;
+            }
             glen = uint32_t(gstart[grp + 1] - e0);
         };
+        auto tested = [&](int c) { return c != src && c != a.cn0 && c != a.cn1; };
         load_group();
         for (int j = 0; j < kSegItems; j++) {
             const uint64_t s = s0 + uint64_t(j);
@@ -73,12 +83,12 @@ k_push_seglen(const K* __restrict__ keys, Lay L, const uint64_t* __restrict__ gs
                 load_group();
             }
             const uint64_t t = s - woff[grp];
-            const uint32_t v = src >= 0 ? uint32_t(g.col[row + int64_t(t)]) : uint32_t(t);
+            const uint32_t v = src != -1 ? uint32_t(cand[row + int64_t(t)]) : uint32_t(t);
             bool ok = intro_ok(g, v, a.degF);
-            // the bag neighbours before pos other than the one the candidates came from
-            if (ok && src != a.anchor) ok = has_edge(g, kcol(k0, L, a.anchor), v);
+            // the bag neighbours before pos other than those the candidates came from
+            if (ok && tested(a.anchor)) ok = has_edge(g, kcol(k0, L, a.anchor), v);
             for (int c = 0; c < a.nchk && ok; c++)
-                if (a.chk[c] < a.pos && a.chk[c] != src) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
+                if ((a.grouped || a.chk[c] < a.pos) && tested(a.chk[c])) ok = has_edge(g, kcol(k0, L, a.chk[c]), v);
             slen[s] = ok ? glen : 0u;
             if (a.segv) a.segv[s] = v | uint32_t(colors[uint64_t(kbid(k0, L)) * uint32_t(g.n) + v]) << 27;
         }
@@ -220,7 +230,7 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
 #pragma unroll
                 for (int j = 0; j < 4; j++) ok |= uint32_t(!(kset(kk[j], L) & cb4[j])) << j;
                 for (int c = 0; c < a.nchk; c++) {
-                    if (!(PULL || a.chk[c] >= a.pos)) continue;
+                    if (!(PULL || (!a.grouped && a.chk[c] >= a.pos))) continue;
                     uint64_t key[4];
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
@@ -322,6 +332,14 @@ k_entry_seglen(const K* __restrict__ keys, Lay L, uint64_t N, DevGraph g, IntroA
         int best = a.anchor;
         int64_t bd = gdeg(g, kcol(k, L, a.anchor));
         mine += uint64_t(bd);
+        if (a.cn0 >= 0) {  // the common neighbours of two adjacent bag images
+            const int64_t ei = edge_index(g, kcol(k, L, a.cn0), kcol(k, L, a.cn1));
+            const uint64_t c0 = ei >= 0 ? a.cn_off[ei] : 0, c1 = ei >= 0 ? a.cn_off[ei + 1] : 0;
+            slen[e] = uint32_t(c1 - c0);
+            src[e] = uint8_t(0x80 | (a.cn0 << 3) | a.cn1);
+            a.erow[e] = int64_t(c0);
+            continue;
+        }
         for (int c = 0; c < a.nchk; c++) {
             const int64_t d = gdeg(g, kcol(k, L, a.chk[c]));
             if (d < bd) {
@@ -360,15 +378,29 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
         uint32_t n_pass = 0;
         uint64_t seg0 = 0;
         if (t0 < tile1) seg0 = upper_bound_u64(soff, s_lo, s_hi + 1, t0) - 1;
-        // the segment's entry: key, candidate row, colouring, colour set
+        // the segment's entry: key, candidate list, colouring, colour set;
+        // source byte sc: the column whose adjacency list gives the
+        // candidates, or 0x80 | c0 << 3 | c1 for the common neighbours of
+        // columns c0 and c1
         uint64_t seg = seg0;
         KI key{};
         int64_t row = 0;
+        const int32_t* cand = g.col;
         uint32_t sc = 0;
         auto load_seg = [&]() {
             key = keys[seg];
             sc = src[seg];
-            row = g.rp[kcol(key, L, int(sc))];
+            if (sc & 0x80u) {
+                row = a.erow[seg];
+                cand = a.cn_col;
+            } else {
+                row = g.rp[kcol(key, L, int(sc))];
+                cand = g.col;
+            }
+        };
+        // bag neighbour column nb needs no edge test: it gave the candidates
+        auto is_source = [](uint32_t s_, int nbc) {
+            return (s_ & 0x80u) ? (uint32_t(nbc) == ((s_ >> 3) & 7u) || uint32_t(nbc) == (s_ & 7u)) : uint32_t(nbc) == s_;
         };
         if (t0 < tile1) load_seg();
         if (EMIT) {
@@ -392,7 +424,7 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
                             while (soff[seg + 1] <= t);
                             load_seg();
                         }
-                        vv[j] = uint32_t(g.col[row + int64_t(t - soff[seg])]);
+                        vv[j] = uint32_t(cand[row + int64_t(t - soff[seg])]);
                         kk[j] = key;
                         scj[j] = sc;
                         ok |= 1u << j;
@@ -415,7 +447,7 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
                         const uint32_t w = kcol(kk[j], L, nb[c]);
                         ek[j] = edge_key(w, vv[j]);
                         if (w == vv[j]) ok &= ~(1u << j);
-                        if (((ok >> j) & 1u) && uint32_t(nb[c]) != scj[j]) probe |= 1u << j;
+                        if (((ok >> j) & 1u) && !is_source(scj[j], nb[c])) probe |= 1u << j;
                     }
                     ok &= ~probe | edges_present4(g, ek, probe);
                 }
@@ -443,7 +475,7 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
                 while (soff[seg + 1] <= t);
                 load_seg();
             }
-            const uint32_t v = uint32_t(g.col[row + int64_t(t - soff[seg])]);
+            const uint32_t v = uint32_t(cand[row + int64_t(t - soff[seg])]);
             const uint32_t bid = kbid(key, L);
             uint32_t cols[5];
             for (int c = 0, s2 = 0; c < LO.b; c++) cols[c] = (c == a.pos) ? v : kcol(key, L, s2++);
@@ -452,6 +484,59 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
             o++;
         }
     }
+}
+
+// ---- common-neighbour index ---------------------------------------------------
+//
+// For every stored edge e = (a, b): the common neighbours of a and b in
+// increasing order, found by walking the shorter row and searching each of
+// its vertices in the longer one from the last position found (both rows
+// ascend).  An introduced vertex adjacent in F to two bag vertices that are
+// adjacent to each other has exactly these candidates (Sec. 3.2: every bag
+// neighbour's image must be adjacent to the candidate).
+
+template <bool EMIT>
+__global__ void k_cn(DevGraph g, uint32_t* cnt, const uint64_t* __restrict__ off, int32_t* out) {
+    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < uint64_t(g.m2);
+         e += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t a = uint32_t(g.esrc[e]), b = uint32_t(g.col[e]);
+        int64_t ia = g.rp[a], ea = g.rp[a + 1], ib = g.rp[b], eb = g.rp[b + 1];
+        if (ea - ia > eb - ib) {
+            const int64_t t0 = ia, t1 = ea;
+            ia = ib;
+            ea = eb;
+            ib = t0;
+            eb = t1;
+        }
+        uint32_t c = 0;
+        const uint64_t o = EMIT ? off[e] : 0;
+        int64_t p = ib;
+        for (int64_t i = ia; i < ea && p < eb; i++) {
+            const uint32_t x = uint32_t(g.col[i]);
+            int64_t hi = eb;
+            while (p < hi) {
+                const int64_t mid = (p + hi) >> 1;
+                if (uint32_t(g.col[mid]) < x)
+                    p = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (p < eb && uint32_t(g.col[p]) == x) {
+                if (EMIT) out[o + c] = int32_t(x);
+                c++;
+                p++;
+            }
+        }
+        if (!EMIT) cnt[e] = c;
+    }
+}
+
+void launch_cn_count(DevGraph g, uint32_t* cnt, hipStream_t s) {
+    if (g.m2) k_cn<false><<<grid_for(uint64_t(g.m2)), kBlock, 0, s>>>(g, cnt, nullptr, nullptr);
+}
+
+void launch_cn_emit(DevGraph g, const uint64_t* off, int32_t* out, hipStream_t s) {
+    if (g.m2) k_cn<true><<<grid_for(uint64_t(g.m2)), kBlock, 0, s>>>(g, nullptr, off, out);
 }
 
 // ---- distance-bounded introduce (no bag neighbour) ----------------------------

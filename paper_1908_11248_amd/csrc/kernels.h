@@ -113,6 +113,20 @@ struct IntroArgs {
     // colour(v) << 27, written by launch_push_seglen and read by the expand
     // instead of walking group -> first key -> adjacency list -> colour again
     uint32_t* segv = nullptr;
+    // entry-grouped form: the groups hold every child column (entries that
+    // differ only in their colour sets), so every adjacency check is a
+    // per-group one (push_work and push_seglen) and the expand only tests
+    // colours
+    bool grouped = false;
+    // entry-wise form: two child columns whose pattern vertices are adjacent
+    // in F (cn0 < 0: none).  Their images are adjacent in G, so the
+    // candidates of an entry are the common neighbours of those images: the
+    // list of that edge in the graph's common-neighbour index (cn_off /
+    // cn_col, per stored edge); erow[e] keeps the list's start for entry e.
+    int cn0 = -1, cn1 = -1;
+    const uint64_t* cn_off = nullptr;
+    const int32_t* cn_col = nullptr;
+    int64_t* erow = nullptr;
 };
 void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, DevGraph g,
                       const IntroArgs& a, uint32_t* wcount, hipStream_t s);
@@ -127,6 +141,10 @@ uint64_t expand_tiles(uint64_t T);
 // neighbour of u whose image has the fewest neighbours (src[e], a child
 // column), every other bag neighbour an edge test; output in (entry,
 // candidate) order with v at column pos (to be re-sorted on columns 0..pos)
+// common-neighbour index of the stored edges: counts, then (off = their
+// exclusive prefix sums) the lists
+void launch_cn_count(DevGraph g, uint32_t* cnt, hipStream_t s);
+void launch_cn_emit(DevGraph g, const uint64_t* off, int32_t* out, hipStream_t s);
 void launch_entry_seglen(const DevTable& in, DevGraph g, const IntroArgs& a, uint32_t* slen, uint8_t* src,
                          uint64_t* anchor_items, hipStream_t s);
 void launch_entry_count(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,

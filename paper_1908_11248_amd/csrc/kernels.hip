@@ -259,6 +259,12 @@ __global__ void k_push_work(const K* __restrict__ keys, Lay L, const uint64_t* _
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < G; i += uint64_t(gridDim.x) * blockDim.x) {
         if (a.anchor < 0) {
             wcount[i] = uint32_t(g.n);
+        } else if (a.cn0 >= 0) {  // the common neighbours of two adjacent bag images
+            const K k0 = keys[gstart[i]];
+            const int64_t ei = edge_index(g, kcol(k0, L, a.cn0), kcol(k0, L, a.cn1));
+            const uint64_t c0 = ei >= 0 ? a.cn_off[ei] : 0, c1 = ei >= 0 ? a.cn_off[ei + 1] : 0;
+            wcount[i] = uint32_t(c1 - c0);
+            a.erow[i] = int64_t(c0);
         } else {
             // candidates: neighbours of the image with the fewest of them
             // (Sec. 3.2: every bag neighbour's image must be adjacent)
@@ -266,7 +272,7 @@ __global__ void k_push_work(const K* __restrict__ keys, Lay L, const uint64_t* _
             int best = a.anchor;
             int64_t bd = gdeg(g, kcol(k0, L, a.anchor));
             for (int c = 0; c < a.nchk; c++) {
-                if (a.chk[c] >= a.pos) continue;
+                if (!a.grouped && a.chk[c] >= a.pos) continue;
                 const int64_t d = gdeg(g, kcol(k0, L, a.chk[c]));
                 if (d < bd) {
                     bd = d;

@@ -405,6 +405,21 @@ int cc_tune_batch(cc_context* ctx, const cc_graph* g, int32_t nq, const cc_query
         }
     }
     ctx->sort_above_k = best_s;
+    const int m0 = ctx->group_min;
+    int best_m = m0;
+    for (int gm : {0, 4}) {
+        ctx->group_min = gm;
+        double dt;
+        if (int rc = timed(&dt)) {
+            ctx->group_min = m0;
+            return rc;
+        }
+        if (dt < best_t) {
+            best_t = dt;
+            best_m = gm;
+        }
+    }
+    ctx->group_min = best_m;
     *best = best_l;
     return CC_OK;
 }
@@ -414,17 +429,19 @@ int cc_get_schedule(const cc_context* ctx, cc_schedule* out) {
     out->lanes = ctx->batch_lanes;
     out->entry_factor = ctx->entry_factor;
     out->sort_above_k = ctx->sort_above_k;
+    out->group_min = ctx->group_min;
     return CC_OK;
 }
 
 int cc_set_schedule(cc_context* ctx, const cc_schedule* s) {
-    if (!ctx || !s || s->lanes < 0 || s->lanes > 64 || s->entry_factor < 1 || s->sort_above_k < 0) {
+    if (!ctx || !s || s->lanes < 0 || s->lanes > 64 || s->entry_factor < 1 || s->sort_above_k < 0 || s->group_min < 0) {
         set_error("bad arguments");
         return CC_EINVAL;
     }
     ctx->batch_lanes = s->lanes;
     ctx->entry_factor = s->entry_factor;
     ctx->sort_above_k = s->sort_above_k;
+    ctx->group_min = s->group_min;
     return CC_OK;
 }
 

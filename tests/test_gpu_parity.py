@@ -249,8 +249,9 @@ def test_workload3_sampled_vertices(ctx):
 def test_entry_and_classic_introduce_match_oracle(ctx, gname, make):
     """Introduce nodes whose vertex has two or more bag neighbours: the
     entry-wise form (candidates from the lowest-degree neighbour's row, then
-    a re-sort) and the fixed-column form give the oracle's counts, flags and
-    per-node table sizes on heavy-tailed and clustered hosts."""
+    a re-sort), per entry or per group of entries with equal bag images, and
+    the fixed-column form give the oracle's counts, flags and per-node table
+    sizes on heavy-tailed and clustered hosts."""
     g = make()
     pats = [W.complete(4), W.pattern_B(), W.ladder(4), W.cycle(6), W.partial_3tree(8, 5),
             W.partial_3tree(9, 21), W.partial_3tree(10, 8)]
@@ -260,13 +261,20 @@ def test_entry_and_classic_introduce_match_oracle(ctx, gname, make):
         td = D.export()
         C = cc.color(ctx, G, pat.n, 31, 2)
         ref = [O.dp_count(g, pat, pat.n, O.color_array(31, b, g.n, pat.n), td=td, sizes=True) for b in range(2)]
-        for flags in (0, cc.CC_CLASSIC_EXPAND):
-            say("introduce forms", gname, pat.name, "flags", flags)
-            counts, ovf = cc.count(ctx, G, C, D, flags)
+        # (flags, entry_factor, group_min): default; entry-wise whenever it
+        # walks fewer candidates, always grouped; the same, never grouped;
+        # the fixed-column forms only
+        for flags, ef, gm in ((0, 3, 2), (0, 1, 1), (0, 1, 0), (cc.CC_CLASSIC_EXPAND, 3, 2)):
+            say("introduce forms", gname, pat.name, "flags", flags, "entry_factor", ef, "group_min", gm)
+            ctx.set_schedule(entry_factor=ef, group_min=gm)
+            try:
+                counts, ovf = cc.count(ctx, G, C, D, flags)
+            finally:
+                ctx.set_schedule()
             sizes = ctx.last_table_sizes()
             for b in range(2):
-                assert int(counts[b]) == ref[b]["count"] and bool(ovf[b]) == ref[b]["overflow"], (gname, pat.name, flags, b)
-            assert np.array_equal(sizes, ref[0]["sizes"] + ref[1]["sizes"]), (gname, pat.name, flags)
+                assert int(counts[b]) == ref[b]["count"] and bool(ovf[b]) == ref[b]["overflow"], (gname, pat.name, flags, gm, b)
+            assert np.array_equal(sizes, ref[0]["sizes"] + ref[1]["sizes"]), (gname, pat.name, flags, gm)
 
 
 @pytest.mark.parametrize("gname,make", [("er150", lambda: W.er_pairs(150, 0.07, 9)),

@@ -27,8 +27,9 @@ def test_schedules_agree_with_oracle_and_tuner_picks_one():
         cols = [cc.color(ctx, G, p.n, 40 + i, 2) for i, p in enumerate(pats)]
         ref = [[O.dp_count(g, p, p.n, O.color_array(40 + i, b, g.n, p.n))["count"] for b in range(2)]
                for i, p in enumerate(pats)]
-        for sched in ({"lanes": 1, "entry_factor": 1, "sort_above_k": 12}, {"lanes": 4, "entry_factor": 8, "sort_above_k": 0},
-                      {"lanes": 2, "entry_factor": 3, "sort_above_k": 6}):
+        for sched in ({"lanes": 1, "entry_factor": 1, "sort_above_k": 12, "group_min": 1},
+                      {"lanes": 4, "entry_factor": 8, "sort_above_k": 0, "group_min": 0},
+                      {"lanes": 2, "entry_factor": 3, "sort_above_k": 6, "group_min": 2}):
             say("schedule", sched)
             ctx.set_schedule(**sched)
             assert ctx.schedule() == sched
@@ -39,7 +40,7 @@ def test_schedules_agree_with_oracle_and_tuner_picks_one():
         best = cc.tune_batch(ctx, G, list(zip(decs, cols)))
         s = ctx.schedule()
         assert best == s["lanes"] and s["lanes"] in (1, 2, 4, 8)
-        assert s["entry_factor"] in (1, 3, 8) and s["sort_above_k"] in (12, 8, 0)
+        assert s["entry_factor"] in (1, 3, 8) and s["sort_above_k"] in (12, 8, 0) and s["group_min"] in (2, 0, 4)
         out = cc.count_batch(ctx, G, list(zip(decs, cols)))
         for i, (c, _) in enumerate(out):
             assert [int(x) for x in c] == ref[i], pats[i].name
