@@ -227,6 +227,10 @@ struct RunRequest {
     bool no_alloc = false;     // make no device or pinned-host allocation (fail with CC_ERANGE instead)
     bool classic_expand = false;  // never the entry-wise introduce (tests compare both)
     SlotCapture* capture = nullptr;  // record the device work only (dense-table plans; the stream is capturing)
+    // dense plans: log2 bounds of the counts by colour-set size, from an
+    // earlier run of the same plan on the same graph (a captured run cannot
+    // compute them: that needs a read-back)
+    const std::vector<double>* slot_lb_in = nullptr;
 };
 
 // contributor index of one step's table (enumeration)
@@ -249,6 +253,7 @@ struct RunResult {
     size_t peak_bytes = 0;             // largest arena footprint of the run
     int chunks = 1;                    // anchor-range chunks the result was computed in
     bool dense = false;                // ran on dense one-column tables
+    std::vector<double> slot_lb;       // dense runs: log2 bounds of the counts by colour-set size
 };
 
 void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out);

@@ -429,7 +429,62 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     // bag vertex, parent before child, to neighbours of their parents'
     // images.  log2 of that bound decides which arithmetic is exact.
     const double ldmax = rq.g->sorted_deg.empty() ? 0.0 : std::log2(double(std::max<int64_t>(1, rq.g->sorted_deg.back())));
-    auto below = [&](int set, int bits) { return double(set - 1) * ldmax < double(bits) - 1e-9; };
+    // lb[s]: log2 of a bound on every count of a table of colour-set size s:
+    // the smaller of that degree bound and the largest homomorphism count of
+    // the plan's subtrees of at most s vertices (slots.hip, count bounds),
+    // which needs one read-back (so a captured run takes an earlier run's)
+    std::vector<double> lb(size_t(k) + 2);
+    for (size_t s2 = 0; s2 < lb.size(); s2++) lb[s2] = double(std::max(int(s2) - 1, 0)) * ldmax;
+    if (rq.slot_lb_in && rq.slot_lb_in->size() == lb.size()) {
+        lb = *rq.slot_lb_in;
+    } else if (!rq.capture && !rq.no_alloc && g.n > 0) {
+        std::vector<double*> h(S, nullptr);
+        uint64_t* hmax = nullptr;
+        try {
+            hmax = X.alloc<uint64_t>(S);
+            launch_fill_u64(hmax, 0, S, s);
+            for (size_t i = 0; i < S; i++) {
+                const Step& st = plan.steps[i];
+                size_t o = i;
+                if (st.kind == S_LEAF) {
+                    h[i] = X.alloc<double>(uint64_t(g.n));
+                    launch_fill_u64(reinterpret_cast<uint64_t*>(h[i]), 0x3FF0000000000000ull, uint64_t(g.n), s);  // 1.0
+                } else if (fuse[i]) {
+                    o = i + 1;
+                    h[o] = X.alloc<double>(uint64_t(g.n));
+                    launch_hom_spmv(g, h[size_t(st.in0)], h[o], s);
+                    i++;
+                } else if (st.kind == S_JOIN) {
+                    h[i] = X.alloc<double>(uint64_t(g.n));
+                    launch_hom_mul(h[size_t(st.in0)], h[size_t(st.in1)], h[i], uint64_t(g.n), s);
+                }
+                if (h[o]) launch_hom_max(h[o], uint64_t(g.n), hmax + o, s);
+            }
+            uint64_t* hb = X.lane.result_words(S);
+            hip_check(hipMemcpyAsync(hb, hmax, 8 * S, hipMemcpyDeviceToHost, s), "copy bounds");
+            hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            std::vector<double> by_size(lb.size(), 0.0);
+            for (size_t i = 0; i < S; i++) {
+                if (!h[i]) continue;
+                double m;
+                std::memcpy(&m, &hb[i], 8);
+                const double l = m > 1.0 ? std::log2(m) + 1e-6 : 0.0;  // margin for rounding
+                by_size[size_t(sz[i])] = std::max(by_size[size_t(sz[i])], l);
+            }
+            double pm = 0.0;
+            for (size_t s2 = 0; s2 < lb.size(); s2++) {
+                pm = std::max(pm, by_size[s2]);
+                lb[s2] = std::min(lb[s2], pm);
+            }
+        } catch (const CcError& e) {
+            if (e.code != CC_ENOMEM) throw;  // no room: the degree bound stands
+        }
+        for (double* x : h)
+            if (x) X.release(x);
+        if (hmax) X.release(hmax);
+    }
+    out->slot_lb = lb;
+    auto below = [&](int set, int bits) { return lb[size_t(set)] < double(bits) - 1e-9; };
     // A join whose two inputs are introduce-over-a-leaf steps (at its bag
     // vertex, used by nothing else) runs as one kernel from neighbourhood
     // colour histograms; those inputs are deferred (never stored).

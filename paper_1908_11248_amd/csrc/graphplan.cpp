@@ -95,6 +95,7 @@ int cc_plan_create(cc_context* ctx, const cc_graph* g, const cc_decomp* d, int32
             p->arena.init((char*)p->arena_mem, bytes);
             rq.arena = &p->arena;
             rq.capture = &p->cap;
+            rq.slot_lb_in = &sizing.slot_lb;
             hip_check(hipStreamBeginCapture(p->lane.stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
             RunResult rec;
             try {

@@ -144,6 +144,11 @@ uint64_t expand_tiles(uint64_t T);
 // common-neighbour index of the stored edges: counts, then (off = their
 // exclusive prefix sums) the lists
 void launch_cn_count(DevGraph g, uint32_t* cnt, hipStream_t s);
+// count bounds of tree plans (slots.hip): hout[v] = sum of hin over N(v);
+// out = a * b elementwise; *out = max(*out, max of h) (h >= 0, as bits)
+void launch_hom_spmv(DevGraph g, const double* hin, double* hout, hipStream_t s);
+void launch_hom_mul(const double* a, const double* b, double* out, uint64_t n, hipStream_t s);
+void launch_hom_max(const double* h, uint64_t n, uint64_t* out, hipStream_t s);
 void launch_cn_emit(DevGraph g, const uint64_t* off, int32_t* out, hipStream_t s);
 void launch_entry_seglen(const DevTable& in, DevGraph g, const IntroArgs& a, uint32_t* slen, uint8_t* src,
                          uint64_t* anchor_items, hipStream_t s);

@@ -1785,4 +1785,62 @@ void launch_slot_root(SlotArrays in, int s_in, int32_t n, int B, const uint8_t* 
 
 uint64_t slot_root_partials(int32_t n, int B) { return 2 * uint64_t(slot_grid(n, B, 1, 8).nbx) * uint64_t(B); }
 
+// ---- count bounds of tree plans ---------------------------------------------
+//
+// Every count of a dense table (colouring b, image v, colour set C) is at most
+// the number of homomorphisms of the table's pattern subtree into G that map
+// its bag vertex to v: a leaf gives 1, an edge step sums its child's bound
+// over N(v), a join multiplies its children's bounds.  These are real
+// numbers here (doubles; only their maximum over v is used, with a margin),
+// and the executor keeps a table narrow (no high plane) or exact (no presence
+// bytes) when the maximum is below 2^32 or 2^64.  The bound is far below
+// deg_max^(s - 1) on heavy-tailed graphs, where a few hubs set deg_max.
+
+__global__ void k_hom_spmv(DevGraph g, const double* __restrict__ hin, double* __restrict__ hout) {
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < uint64_t(g.n);
+         v += uint64_t(gridDim.x) * blockDim.x) {
+        double acc = 0.0;
+        for (int64_t e = g.rp[v]; e < g.rp[v + 1]; e++) acc += hin[g.col[e]];
+        hout[v] = acc;
+    }
+}
+
+__global__ void k_hom_mul(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out,
+                          uint64_t n) {
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n; v += uint64_t(gridDim.x) * blockDim.x)
+        out[v] = a[v] * b[v];
+}
+
+// maximum of non-negative doubles: their bit patterns order like the values
+__global__ void k_hom_max(const double* __restrict__ h, uint64_t n, unsigned long long* out) {
+    __shared__ unsigned long long w[kBlock / 64];
+    unsigned long long m = 0;
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n; v += uint64_t(gridDim.x) * blockDim.x) {
+        const unsigned long long x = static_cast<unsigned long long>(__double_as_longlong(h[v]));
+        m = x > m ? x : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(m, o, 64);
+        m = y > m ? y : m;
+    }
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; i++) m = w[i] > m ? w[i] : m;
+        atomicMax(out, m);
+    }
+}
+
+void launch_hom_spmv(DevGraph g, const double* hin, double* hout, hipStream_t s) {
+    if (g.n) k_hom_spmv<<<grid_for(uint64_t(g.n)), kBlock, 0, s>>>(g, hin, hout);
+}
+
+void launch_hom_mul(const double* a, const double* b, double* out, uint64_t n, hipStream_t s) {
+    if (n) k_hom_mul<<<grid_for(n), kBlock, 0, s>>>(a, b, out, n);
+}
+
+void launch_hom_max(const double* h, uint64_t n, uint64_t* out, hipStream_t s) {
+    if (n) k_hom_max<<<grid_for(n), kBlock, 0, s>>>(h, n, reinterpret_cast<unsigned long long*>(out));
+}
+
 }  // namespace ccg
