@@ -14,7 +14,8 @@ concurrent lanes, admission by estimated table memory) and `value` is the
 served queries/s over that timed region.  Beside it, on the same queries:
   plain      one query at a time on one stream (the paper's single runs);
   poisson    Poisson arrivals at --load x the plain rate, served with
-             --inflight lanes and with one lane: queries/s, p50/p99 latency;
+             --inflight lanes (with and without tail protection, --tail)
+             and with one lane: queries/s, p50/p99 latency;
   batched_w4 the first 64 of the 256 queries of BA(200000, 5) (16 colourings
              each; all 256 with --workload 4): plain vs cc_count_batch, DP
              table entries/s (--no-w4 skips it).
@@ -23,9 +24,11 @@ Served, Poisson and batched counts are checked bit-equal to the plain ones.
 The `roofline` object names the kernel with the largest total time in the
 timed region and divides its algorithmic bytes per launch (table entries read
 and written x the per-entry size of the roofline model, plus graph bytes) by
-its average launch time, from HIP event pairs on the streams it ran on.  The
-`cpu_baseline` object times the CPU oracle on the same stream's colourings,
-on this host's cores, for a bounded time.
+its average launch time, from HIP event pairs on the streams it ran on
+(`roofline_plain_pass`: the same kernel while no other query shares the
+device).  The `cpu_baseline` object times the CPU oracle on the host's cores
+for a bounded time on the stream's small queries over CL(50000) of the same
+law, and converts its DP-entry rate to queries/s of the full-size stream.
 
 --workload 2/3/4/5 run one standard workload alone (2 and 3: one pattern, a
 step is one batch of all its colourings).
@@ -257,8 +260,8 @@ def bench_serve(args):
     plain_qps = len(timed) / t_plain
     log("plain %.2f q/s (%.1f s)" % (plain_qps, t_plain))
 
-    def serve(queries, inflight, gaps=None, profile=False):
-        srv = cc.Server(ctx, G, max_inflight=inflight, max_heavy=0)
+    def serve(queries, inflight, gaps=None, tail=0.0):
+        srv = cc.Server(ctx, G, max_inflight=inflight, max_heavy=0, tail_factor=tail)
         tickets = []
         t_start = time.perf_counter()
         due = t_start
@@ -305,9 +308,10 @@ def bench_serve(args):
     lam = args.load * plain_qps
     rng = np.random.Generator(np.random.PCG64(w.seed ^ 0xA5))
     gaps = rng.exponential(1.0 / lam, size=len(timed))
-    st_p, res_p, _ = serve(timed, args.inflight, gaps)
+    st_p, res_p, _ = serve(timed, args.inflight, gaps, tail=args.tail)
+    st_n, res_n, _ = serve(timed, args.inflight, gaps)
     st_1, res_1, _ = serve(timed, 1, gaps)
-    if not (same(res_p) and same(res_1)):
+    if not (same(res_p) and same(res_n) and same(res_1)):
         raise SystemExit("served counts differ from plain counts")
 
     def lat(st):
@@ -332,7 +336,8 @@ def bench_serve(args):
                   "p99_ms": round(1e3 * float(np.percentile(lat_plain, 99)), 2),
                   "entries_per_s": round(entries / t_plain, 1)},
         "served_vs_plain": round(served_qps / plain_qps, 3),
-        "poisson": {"offered_qps": round(lam, 3), "load": args.load, "served": lat(st_p), "one_lane": lat(st_1),
+        "poisson": {"offered_qps": round(lam, 3), "load": args.load, "tail_factor": args.tail, "served": lat(st_p),
+                    "served_no_tail_protection": lat(st_n), "one_lane": lat(st_1),
                     "p99_vs_one_lane": round(st_p["p99_ms"] / st_1["p99_ms"], 3) if st_1["p99_ms"] else None},
         "entries_per_s_served": round(entries / wall_sat, 1),
         "bit_identical_served_vs_plain": True,
@@ -566,6 +571,9 @@ def main():
                     help="queries of workload 4 (0: all 256 with --workload 4, the first 64 in the default run)")
     ap.add_argument("--load", type=float, default=0.7, help="Poisson arrival rate / plain throughput")
     ap.add_argument("--inflight", type=int, default=4, help="concurrent queries while serving")
+    ap.add_argument("--tail", type=float, default=2.5,
+                    help="tail protection of the Poisson-served run: no admission while a query has run this many "
+                         "times the mean service time (0: off)")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams of the workload-4 batch")
     ap.add_argument("--no-w4", action="store_true", help="skip the workload-4 batch in the default run")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -342,13 +342,18 @@ int cc_set_table_budget(cc_context *ctx, uint64_t max_entries);
  * waves and anchor ranges when its tables do not fit.  With max_heavy > 0,
  * at most that many queries whose decomposition has width >= 2 are in
  * flight at once (0: no such limit).  A query that runs out of memory while
- * others hold it is re-queued to run alone.  Latency is measured from
- * submission to completion. */
+ * others hold it is re-queued to run alone.  Tail protection (tail_factor >
+ * 0): while some running query has run longer than tail_factor times the
+ * mean service time of the queries completed so far, no further query is
+ * admitted, so a long query does not share the device with a stream of
+ * newcomers (it then finishes about as fast as alone, which bounds the
+ * latency tail).  Latency is measured from submission to completion. */
 typedef struct {
     int32_t max_inflight;  /* worker lanes (concurrent queries), >= 1 */
     size_t mem_budget;     /* bytes of the arena the server may use (0: all) */
     uint64_t max_entries;  /* per-table budget of each query (0: none) */
     int32_t max_heavy;     /* width >= 2 queries in flight at once (0: no limit) */
+    double tail_factor;    /* tail protection threshold (0: off) */
 } cc_server_opts;
 typedef struct {
     uint64_t submitted, completed, failed, requeued;

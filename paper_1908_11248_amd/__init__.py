@@ -488,7 +488,7 @@ def count_batch(ctx: Context, g: Graph, queries: Sequence[Tuple[Decomp, Coloring
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("max_entries", ctypes.c_uint64),
-                ("max_heavy", ctypes.c_int32)]
+                ("max_heavy", ctypes.c_int32), ("tail_factor", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
@@ -502,9 +502,9 @@ class Server:
     """Request loop over a resident graph (cc_server_*)."""
 
     def __init__(self, ctx: Context, g: Graph, max_inflight: int = 4, mem_budget: int = 0, max_entries: int = 0,
-                 max_heavy: int = 1):
+                 max_heavy: int = 1, tail_factor: float = 0.0):
         self.ctx, self.g = ctx, g
-        opts = ServerOpts(max_inflight, mem_budget, max_entries, max_heavy)
+        opts = ServerOpts(max_inflight, mem_budget, max_entries, max_heavy, tail_factor)
         out = ctypes.c_void_p()
         _check(lib().cc_server_start(ctx.ptr, g.ptr, ctypes.byref(opts), ctypes.byref(out)))
         self.ptr = out.value

@@ -14,6 +14,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -161,7 +162,7 @@ struct cc_server {
         int32_t B;
         size_t est = 0;
         double model = 0;  // estimate_memory's peak bytes
-        Clock::time_point arrival, done_at;
+        Clock::time_point arrival, started, done_at;
         int state = 0;  // 0 waiting/running, 1 done, < 0 error
         bool alone = false;
         std::vector<uint64_t> counts;
@@ -183,6 +184,8 @@ struct cc_server {
     std::vector<std::thread> workers;
     uint64_t submitted = 0, completed = 0, failed = 0, requeued = 0;
     std::vector<double> latencies_ms;
+    double service_sum_ms = 0;  // of the completed queries (tail protection)
+    std::set<uint64_t> in_flight;
     bool have_first = false;
     Clock::time_point first_arrival, last_done;
 
@@ -201,9 +204,19 @@ struct cc_server {
         return size_t(std::min(e, double(budget)));
     }
 
+    // a running query is far past the mean service time: admit nothing new
+    bool tail_hold() {
+        if (opts.tail_factor <= 0 || completed < 4 || in_flight.empty()) return false;
+        const double limit = opts.tail_factor * service_sum_ms / double(completed);
+        const Clock::time_point now = Clock::now();
+        for (uint64_t id : in_flight)
+            if (std::chrono::duration<double, std::milli>(now - reqs[id].started).count() > limit) return true;
+        return false;
+    }
+
     // oldest admissible request (lock held); 0 if none
     uint64_t pick() {
-        if (running_alone) return 0;
+        if (running_alone || tail_hold()) return 0;
         for (size_t i = 0; i < queue.size(); i++) {
             Req& r = reqs[queue[i]];
             if (r.alone) {
@@ -229,6 +242,8 @@ struct cc_server {
             if (id == 0) return;
             queue.erase(std::find(queue.begin(), queue.end(), id));
             Req& r = reqs[id];
+            r.started = Clock::now();
+            in_flight.insert(id);
             r.est = estimate(r);
             size_t hold = r.alone ? budget : r.est;
             reserved += hold;
@@ -260,6 +275,7 @@ struct cc_server {
             if (colors) ctx->arena.release(colors);
 
             lk.lock();
+            in_flight.erase(id);
             reserved -= hold;
             running--;
             if (r.alone) running_alone--;
@@ -282,6 +298,7 @@ struct cc_server {
                         correction = std::min(4.0, std::max(0.5, correction));
                     }
                     completed++;
+                    service_sum_ms += std::chrono::duration<double, std::milli>(rr.done_at - rr.started).count();
                     latencies_ms.push_back(std::chrono::duration<double, std::milli>(rr.done_at - rr.arrival).count());
                     last_done = rr.done_at;
                 } else {

@@ -16,7 +16,10 @@ Files (one line per value, each with a header naming this command):
                   caps is listed in the header as skipped
                   q seed name b lo hi count overflow   (lo hi = 0 n: full count)
   w5_sample.txt   workload 5: colouring 0 of a seeded sample of 32 of the
-                  first 200 queries of the stream       same format
+                  first 200 queries of the stream, under caps of 12 GiB and
+                  900 s per oracle run (one colouring of a 5-vertex partial
+                  3-tree takes the oracle about 500 s on CL(10^6))
+                                                        same format
 """
 import argparse
 import multiprocessing as mp
@@ -59,7 +62,7 @@ def _one(task):
 
 
 MEM_CAP = 12 << 30  # address-space limit of one oracle process
-TIME_CAP = 300.0  # seconds for one oracle task
+TIME_CAP = 300.0  # seconds for one oracle task (--time-cap)
 
 
 def _child(task, conn):
@@ -234,13 +237,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", nargs="*", type=int, default=[2, 3, 4, 5])
     ap.add_argument("--workers", type=int, default=0)
+    ap.add_argument("--time-cap", type=float, default=0.0, help="seconds per oracle task (default 300; 900 for workload 5)")
     a = ap.parse_args()
+    global TIME_CAP
     for index in a.which:
         t0 = time.perf_counter()
         if index in (2, 3):
             w_single(index, a.workers or (8 if index == 2 else 6))
         else:
-            w_queries(index, a.workers or 4)
+            TIME_CAP = a.time_cap or (900.0 if index == 5 else 300.0)
+            w_queries(index, a.workers or (3 if index == 5 else 4))
         print("workload %d goldens in %.0f s" % (index, time.perf_counter() - t0), flush=True)
 
 

@@ -124,6 +124,22 @@ def test_server_alone_vs_mix(env):
     assert 0 < stats["p50_ms"] <= stats["p99_ms"] <= stats["max_ms"]
 
 
+@pytest.mark.parametrize("tail", [0.5, 2.5])
+def test_server_tail_protection(env, tail):
+    """With tail protection the server holds admissions while a query runs
+    long; every query still completes with the counts of its own run."""
+    ctx, g, G = env
+    qs = make_queries(ctx, G, 16, 4, seed0=90)
+    alone = [cc.count(ctx, G, C, D)[0] for _, D, C, _ in qs]
+    srv = cc.Server(ctx, G, max_inflight=4, tail_factor=tail)
+    tickets = [srv.submit(D, p.n, W.colouring_seed(s), 4) for p, D, _, s in qs]
+    for t, ref in zip(tickets, alone):
+        st, c, _ = srv.wait(t)
+        assert st == 1 and np.array_equal(c, ref)
+    stats = srv.stop()
+    assert stats["completed"] == 16 and stats["failed"] == 0
+
+
 def test_server_under_memory_pressure():
     """A small arena: concurrent queries run out of memory, are re-queued to
     run alone, and still give the counts of the sequential runs."""
