@@ -224,6 +224,13 @@ namespace {
 // uint64 count and a 16-bit colouring index (the packed keys here are
 // narrower; counters report the bytes actually moved).
 inline double entry_bytes(int b) { return 4.0 * b + 12.0; }
+// algorithmic bytes of an LSD radix sort of n entries of layout L on the key
+// bits from lo up: every 8-bit pass reads and writes each key and count once
+// (the cost the roofline model charges a sort: 2 passes (key + payload))
+inline double sort_bytes(uint64_t n, const Lay& L, int lo) {
+    const int passes = (L.bits() - lo + 7) / 8;
+    return 2.0 * double(std::max(passes, 0)) * double(n) * (double(L.key_bytes()) + 8.0);
+}
 
 struct Exec {
     Lane& lane;
@@ -1320,7 +1327,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     uint64_t* vb2 = X.alloc<uint64_t>(Nd);
                     void* tmp = X.raw(radix_tmp_bytes(Nd));
                     bool in_b = false;
-                    X.timed("radix_sort", double(Nd) * entry_bytes(lo.b) * 2, [&] {
+                    X.timed("radix_sort", sort_bytes(Nd, lo, 0), [&] {
                         in_b = radix_sort(dup.keys, dup.cnt, kb2, vb2, Nd, lo.kw(), lo.bits(), 0, tmp, s, false);
                     });
                     if (in_b) {
@@ -1455,7 +1462,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         uint64_t* vb2 = X.alloc<uint64_t>(N);
                         void* tmp = X.raw(radix_tmp_bytes(N));
                         bool in_b = false;
-                        X.timed("radix_sort", double(N) * entry_bytes(lo.b) * 2, [&] {
+                        X.timed("radix_sort", sort_bytes(N, lo, sort_lo), [&] {
                             in_b = radix_sort(o.keys, o.cnt, kb2, vb2, N, lo.kw(), lo.bits(), sort_lo, tmp, s, false);
                         });
                         if (in_b) {
@@ -1497,7 +1504,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         uint64_t* vb2 = X.alloc<uint64_t>(N);
                         void* tmp = X.raw(radix_tmp_bytes(N));
                         bool in_b = false;
-                        X.timed("radix_sort", double(N) * entry_bytes(lo.b) * 2, [&] {
+                        X.timed("radix_sort", sort_bytes(N, lo, sort_lo), [&] {
                             in_b = radix_sort(o.keys, o.cnt, kb2, vb2, N, lo.kw(), lo.bits(), sort_lo, tmp, s, false);
                         });
                         if (in_b) {
@@ -1666,7 +1673,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                             uint64_t* vb2 = X.alloc<uint64_t>(in.n);
                             void* tmp = X.raw(radix_tmp_bytes(in.n));
                             bool in_b = false;
-                            X.timed("radix_sort", double(in.n) * entry_bytes(lo.b) * 2, [&] {
+                            X.timed("radix_sort", sort_bytes(in.n, lo, 0), [&] {
                                 in_b = radix_sort(d.keys, d.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), 0, tmp, s, false);
                             });
                             if (in_b) {
@@ -1748,7 +1755,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                             uint64_t* vb2 = X.alloc<uint64_t>(P);
                             void* tmp = X.raw(radix_tmp_bytes(P));
                             bool in_b = false;
-                            X.timed("radix_sort", double(P) * entry_bytes(lo.b) * 2, [&] {
+                            X.timed("radix_sort", sort_bytes(P, lo, 0), [&] {
                                 in_b = radix_sort(pr.keys, pr.cnt, kb2, vb2, P, lo.kw(), lo.bits(), 0, tmp, s, false);
                             });
                             if (in_b) {
@@ -1876,7 +1883,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                         void* tmp = X.raw(radix_tmp_bytes(in.n));
                         RadixSource from{in.keys, in.cnt, in.lay, lo, {st.perm[0], st.perm[1], st.perm[2], st.perm[3]}};
                         bool in_b = false;
-                        X.timed("radix_sort", double(in.n) * entry_bytes(lo.b) * 2, [&] {
+                        X.timed("radix_sort", sort_bytes(in.n, lo, sort_lo), [&] {
                             in_b = radix_sort(o.keys, o.cnt, kb2, vb2, in.n, lo.kw(), lo.bits(), sort_lo, tmp, s, false,
                                               fold ? &from : nullptr);
                         });
