@@ -1379,27 +1379,45 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     if (cn_ready()) {
                         ea.cn_off = rq.g->cn_off;
                         ea.cn_col = rq.g->cn_col;
-                        ea.erow = X.alloc<int64_t>(in.n);
                     } else {
                         ea.cn0 = ea.cn1 = -1;
                     }
                 }
-                e_slen = X.alloc<uint32_t>(in.n);
-                e_src = X.alloc<uint8_t>(in.n);
-                uint64_t* anchor_items = X.alloc<uint64_t>(1);
-                launch_fill_u64(anchor_items, 0, 1, s);
-                X.timed("entry_seglen", double(in.n) * entry_bytes(in.lay.b) + 8.0 * in.n,
-                        [&] { launch_entry_seglen(in, g, ea, e_slen, e_src, anchor_items, s); });
-                e_T = X.scan(e_slen, in.n, &e_soff);  // synchronises: anchor_items is final
-                const uint64_t classic = read_u64(X.lane, anchor_items);
-                X.release(anchor_items);
-                X.release(e_slen);
-                entry_form = uint64_t(std::max(1, ctx->entry_factor)) * e_T < classic;
-                if (!entry_form) {
-                    X.release(e_soff);
-                    X.release(e_src);
-                    if (ea.erow) X.release(ea.erow);
+                // sums[0]: candidates of the fixed-column forms (the anchor's
+                // degree per entry), sums[1]: of the entry-wise form; a large
+                // table decides on a sample of about 2^16 entries first,
+                // unless the candidates are common neighbours (then the
+                // entry-wise form nearly always walks far fewer)
+                uint64_t* sums = X.alloc<uint64_t>(2);
+                launch_fill_u64(sums, 0, 2, s);
+                const uint64_t factor = uint64_t(std::max(1, ctx->entry_factor));
+                const uint64_t stride = ea.cn0 < 0 && in.n >= (uint64_t(1) << 20) ? in.n >> 16 : 1;
+                bool decided = false;
+                if (stride > 1) {
+                    X.timed("entry_sample", double(in.n / stride) * (entry_bytes(in.lay.b) + 8.0),
+                            [&] { launch_entry_seglen(in, g, ea, nullptr, nullptr, sums, stride, s); });
+                    const uint64_t cls = read_u64(X.lane, sums), ent = read_u64(X.lane, sums + 1);
+                    entry_form = factor * ent < cls;
+                    decided = true;
                 }
+                if (!decided || entry_form) {
+                    if (ea.cn0 >= 0) ea.erow = X.alloc<int64_t>(in.n);
+                    e_slen = X.alloc<uint32_t>(in.n);
+                    e_src = X.alloc<uint8_t>(in.n);
+                    launch_fill_u64(sums, 0, 2, s);
+                    X.timed("entry_seglen", double(in.n) * entry_bytes(in.lay.b) + 8.0 * in.n,
+                            [&] { launch_entry_seglen(in, g, ea, e_slen, e_src, sums, 1, s); });
+                    e_T = X.scan(e_slen, in.n, &e_soff);  // synchronises: the sums are final
+                    X.release(e_slen);
+                    if (!decided) entry_form = factor * e_T < read_u64(X.lane, sums);
+                    if (!entry_form) {
+                        X.release(e_soff);
+                        X.release(e_src);
+                        if (ea.erow) X.release(ea.erow);
+                        ea.erow = nullptr;
+                    }
+                }
+                X.release(sums);
             }
             if (entry_form) {
                 const DevTable& in = tab[st.in0];

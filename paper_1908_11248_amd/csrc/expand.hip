@@ -324,10 +324,13 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
 // would walk (the anchor's degree per entry), so the caller can pick a form
 template <class K>
 __global__ void __launch_bounds__(kBlock)
-k_entry_seglen(const K* __restrict__ keys, Lay L, uint64_t N, DevGraph g, IntroArgs a, uint32_t* slen, uint8_t* src,
-               unsigned long long* anchor_items) {
-    uint64_t mine = 0;
-    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < N; e += uint64_t(gridDim.x) * blockDim.x) {
+k_entry_seglen(const K* __restrict__ keys, Lay L, uint64_t N, uint64_t stride, DevGraph g, IntroArgs a, uint32_t* slen,
+               uint8_t* src, unsigned long long* sums) {
+    // stride > 1: a sample (every stride-th entry), sums only
+    uint64_t mine = 0, items = 0;
+    const uint64_t M = (N + stride - 1) / stride;
+    for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < M; j += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t e = j * stride;
         const K k = keys[e];
         int best = a.anchor;
         int64_t bd = gdeg(g, kcol(k, L, a.anchor));
@@ -335,9 +338,12 @@ k_entry_seglen(const K* __restrict__ keys, Lay L, uint64_t N, DevGraph g, IntroA
         if (a.cn0 >= 0) {  // the common neighbours of two adjacent bag images
             const int64_t ei = edge_index(g, kcol(k, L, a.cn0), kcol(k, L, a.cn1));
             const uint64_t c0 = ei >= 0 ? a.cn_off[ei] : 0, c1 = ei >= 0 ? a.cn_off[ei + 1] : 0;
-            slen[e] = uint32_t(c1 - c0);
-            src[e] = uint8_t(0x80 | (a.cn0 << 3) | a.cn1);
-            a.erow[e] = int64_t(c0);
+            items += c1 - c0;
+            if (stride == 1) {
+                slen[e] = uint32_t(c1 - c0);
+                src[e] = uint8_t(0x80 | (a.cn0 << 3) | a.cn1);
+                a.erow[e] = int64_t(c0);
+            }
             continue;
         }
         for (int c = 0; c < a.nchk; c++) {
@@ -347,12 +353,17 @@ k_entry_seglen(const K* __restrict__ keys, Lay L, uint64_t N, DevGraph g, IntroA
                 best = a.chk[c];
             }
         }
-        slen[e] = uint32_t(bd);
-        src[e] = uint8_t(best);
+        items += uint64_t(bd);
+        if (stride == 1) {
+            slen[e] = uint32_t(bd);
+            src[e] = uint8_t(best);
+        }
     }
     uint64_t total;
     (void)block_excl_scan(mine, &total);
-    if (threadIdx.x == 0 && total) atomicAdd(anchor_items, (unsigned long long)total);
+    if (threadIdx.x == 0 && total) atomicAdd(&sums[0], (unsigned long long)total);
+    (void)block_excl_scan(items, &total);
+    if (threadIdx.x == 0 && total) atomicAdd(&sums[1], (unsigned long long)total);
 }
 
 template <class KI, class KO, bool EMIT>
@@ -884,14 +895,17 @@ void launch_reduce_runs(const DevTable& in, const uint64_t* starts, uint64_t G, 
 // ---- launchers -------------------------------------------------------------
 
 void launch_entry_seglen(const DevTable& in, DevGraph g, const IntroArgs& a, uint32_t* slen, uint8_t* src,
-                         uint64_t* anchor_items, hipStream_t s) {
+                         uint64_t* sums, uint64_t stride, hipStream_t s) {
     if (!in.n) return;
-    auto* ai = reinterpret_cast<unsigned long long*>(anchor_items);
+    auto* ai = reinterpret_cast<unsigned long long*>(sums);
+    const uint64_t M = (in.n + stride - 1) / stride;
+    // a bounded grid: each block adds its sums with two atomics
+    const unsigned grid = grid_for(M, kBlock, 4096);
     if (in.lay.kw() == 1)
-        k_entry_seglen<uint64_t><<<grid_for(in.n), kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, in.n, g, a, slen,
-                                                                   src, ai);
+        k_entry_seglen<uint64_t><<<grid, kBlock, 0, s>>>((const uint64_t*)in.keys, in.lay, in.n, stride, g, a, slen, src,
+                                                         ai);
     else
-        k_entry_seglen<u128><<<grid_for(in.n), kBlock, 0, s>>>((const u128*)in.keys, in.lay, in.n, g, a, slen, src, ai);
+        k_entry_seglen<u128><<<grid, kBlock, 0, s>>>((const u128*)in.keys, in.lay, in.n, stride, g, a, slen, src, ai);
 }
 
 template <bool EMIT>

@@ -150,8 +150,10 @@ void launch_hom_spmv(DevGraph g, const double* hin, double* hout, hipStream_t s)
 void launch_hom_mul(const double* a, const double* b, double* out, uint64_t n, hipStream_t s);
 void launch_hom_max(const double* h, uint64_t n, uint64_t* out, hipStream_t s);
 void launch_cn_emit(DevGraph g, const uint64_t* off, int32_t* out, hipStream_t s);
+// sums[0] += the anchor column's candidates, sums[1] += the entry-wise form's;
+// stride > 1: over every stride-th entry only, writing no lengths
 void launch_entry_seglen(const DevTable& in, DevGraph g, const IntroArgs& a, uint32_t* slen, uint8_t* src,
-                         uint64_t* anchor_items, hipStream_t s);
+                         uint64_t* sums, uint64_t stride, hipStream_t s);
 void launch_entry_count(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,
                         const uint8_t* colors, const IntroArgs& a, uint32_t* tcount, uint16_t* pbits, hipStream_t s);
 void launch_entry_emit(const DevTable& in, const uint8_t* src, const uint64_t* soff, uint64_t T, DevGraph g,

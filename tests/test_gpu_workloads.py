@@ -84,6 +84,8 @@ def test_workload4_all_queries_colouring0(ctx):
     G = cc.load_graph(ctx, g.n, g.row_ptr, g.col)
     full, ranged = [], []
     for q, (p, s) in enumerate(sel):
+        if q not in by_q:
+            continue  # every range of it exceeded the oracle's caps
         assert all(r[0] == s and r[1] == p.name for r in by_q[q])
         D = cc.build_decomposition(p.n, p.edges)
         C = cc.color(ctx, G, p.n, W.colouring_seed(s), 1)
