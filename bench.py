@@ -570,7 +570,7 @@ def main():
     ap.add_argument("--queries", type=int, default=0,
                     help="queries of workload 4 (0: all 256 with --workload 4, the first 64 in the default run)")
     ap.add_argument("--load", type=float, default=0.7, help="Poisson arrival rate / plain throughput")
-    ap.add_argument("--inflight", type=int, default=4, help="concurrent queries while serving")
+    ap.add_argument("--inflight", type=int, default=6, help="concurrent queries while serving")
     ap.add_argument("--tail", type=float, default=2.5,
                     help="tail protection of the Poisson-served run: no admission while a query has run this many "
                          "times the mean service time (0: off)")
