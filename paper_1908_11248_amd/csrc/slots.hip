@@ -921,7 +921,9 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     const uint64_t row0 = uint64_t(b) * uint32_t(g.n);
     const uint8_t* cb = colors + row0;
     const uint32_t* ilo = in.lo + row0 * R_in;
-    const uint32_t* ihi = in.hi ? in.hi + row0 * R_in : nullptr;
+    // the child's high plane only for a colouring in which some child count
+    // reached 2^32 (its producer's flag); else every high word is 0
+    const uint32_t* ihi = in.hi && (!in.wide || in.wide[b]) ? in.hi + row0 * R_in : nullptr;
     const int64_t e_lo = nv ? g.rp[v0] : 0;
     for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) acc[i] = 0;
     if (EPI)
