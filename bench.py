@@ -590,7 +590,11 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
     if args.workload == "paper":
-        return bench_paper(args)
+        # bench_paper stays unused until the cause is found
+        print("bench.py --workload paper is switched off: one run of it ended in a device memory fault whose "
+              "input was not identified (the failing process's output was lost); the parity tests of these "
+              "workloads (tests/test_gpu_paper_workloads.py) cover the cases that are known to run", file=sys.stderr)
+        sys.exit(2)
     if args.workload in ("serve", "5"):
         if args.workload == "5":
             args.no_w4 = True
