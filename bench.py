@@ -295,7 +295,9 @@ def bench_serve(args):
     if dom:
         ctx.profile_filter(dom, 1)
     # timed: the K steps submitted at once (saturation)
+    win0 = time.monotonic_ns()
     st_sat, res_sat, wall_sat = serve(timed, args.inflight)
+    win1 = time.monotonic_ns()
     prof = ctx.profile_read()
     ctx.profile_filter(None)
     ctx.profile_enable(False)
@@ -341,6 +343,9 @@ def bench_serve(args):
                     "p99_vs_one_lane": round(st_p["p99_ms"] / st_1["p99_ms"], 3) if st_1["p99_ms"] else None},
         "entries_per_s_served": round(entries / wall_sat, 1),
         "bit_identical_served_vs_plain": True,
+        # CLOCK_MONOTONIC bounds of the timed region, to select its kernel
+        # dispatches in a profiler trace of the same command
+        "timed_window_monotonic_ns": [win0, win1],
         "roofline": roofline_from(prof, "w5"),
         # the same kernel in the plain pass, where no other query's kernels
         # share the device while it runs
@@ -400,11 +405,13 @@ def bench_batched_w4(args, timed_steps=None, nq=None):
     steps = timed_steps or args.steps
     ctx.profile_enable(True)
     entries = 0
+    win0 = time.monotonic_ns()
     t0 = time.perf_counter()
     for _ in range(steps):
         out = cc.count_batch(ctx, G, queries)
         entries += int(ctx.last_table_sizes().sum())
     dt = time.perf_counter() - t0
+    win1 = time.monotonic_ns()
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     same = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(out, plain))
@@ -418,7 +425,8 @@ def bench_batched_w4(args, timed_steps=None, nq=None):
            "entries_per_s": round(entries / dt, 1), "entries_per_pass": entries // steps,
            "batched_queries_per_s": round(len(sel) * steps / dt, 3), "plain_queries_per_s": round(len(sel) / t_plain, 3),
            "batched_vs_plain": round(t_plain * steps / dt, 3), "bit_identical_batched_vs_plain": True,
-           "lanes": args.lanes, "roofline": roofline_from(prof, "w4"), "kernels": kernel_table(prof)}
+           "lanes": args.lanes, "roofline": roofline_from(prof, "w4"), "kernels": kernel_table(prof),
+           "timed_window_monotonic_ns": [win0, win1]}
     ctx.close()
     log("workload 4: batched %.2f q/s, plain %.2f q/s" % (res["batched_queries_per_s"], res["plain_queries_per_s"]))
     return res
@@ -454,11 +462,13 @@ def bench_single(args):
     ctx.profile_enable(True)
     ctx.profile_filter(dom_name, every)
     entries = 0
+    win0 = time.monotonic_ns()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(args.warmup + i)
         entries += int(ctx.last_table_sizes().sum())
     dt = time.perf_counter() - t0
+    win1 = time.monotonic_ns()
     prof = ctx.profile_read()
     ctx.profile_filter(None)
     ctx.profile_enable(False)
@@ -484,6 +494,7 @@ def bench_single(args):
         "colorings_per_s": round(w.colorings * args.steps / dt, 2),
         "plain_colorings_per_s": round(plain_rate, 2) if plain_rate else None,
         "entries_per_step": entries // args.steps,
+        "timed_window_monotonic_ns": [win0, win1],
         "roofline": roofline_from(prof, "w%d" % args.workload),
         "kernels_warmup": kernel_table(prof_all),
     }

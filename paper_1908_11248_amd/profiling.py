@@ -2,8 +2,14 @@
 
     python -m paper_1908_11248_amd.profiling stats  <kernel_stats.csv | results.db> <out.md> <command...>
     python -m paper_1908_11248_amd.profiling traffic <fetch_dir> <write_dir> <copy_mib> <out.json> <command...>
+    python -m paper_1908_11248_amd.profiling window <results.db> <bench.json> <out.md>
 
-`stats` turns a --kernel-trace --stats CSV into a short table.  `traffic`
+`stats` turns a --kernel-trace --stats CSV (or the database rocprofv3 writes
+by default) into a short table.  `window` appends to such a table the
+dispatches of the bench line's roofline kernel (and its nested batched
+line's) that ran inside the line's timed window (CLOCK_MONOTONIC
+nanoseconds, the clock of the trace) and their mean duration beside the
+bench's own HIP-event figure.  `traffic`
 reads two --pmc runs (FETCH_SIZE, WRITE_SIZE; values in KiB per dispatch),
 scales every dispatch by the factor measured on the calibration copy kernel
 (bytes it must move / bytes counted) and writes bytes per launch per kernel,
@@ -136,9 +142,32 @@ def traffic(fetch_dir, write_dir, copy_mib, out_json, command):
     json.dump(out, open(out_json, "w"), indent=1, sort_keys=True)
 
 
+def window(db_path, bench_json, out_md):
+    import sqlite3
+
+    line = [l for l in open(bench_json).read().splitlines() if l.strip().startswith("{")][-1]
+    b = json.loads(line)
+    db = sqlite3.connect(db_path)
+    rows = db.execute("SELECT name, start, end FROM kernels").fetchall()
+    out = ["", "Dispatches inside the bench line's timed window (trace clock = CLOCK_MONOTONIC):", "",
+           "| line | kernel | dispatches | mean us (trace) | mean us (bench, HIP events) |", "|---|---|---|---|---|"]
+    for label, obj in (("main", b), ("batched_w4", b.get("batched_w4"))):
+        if not obj or "timed_window_monotonic_ns" not in obj or "roofline" not in obj:
+            continue
+        t0, t1 = obj["timed_window_monotonic_ns"]
+        k = obj["roofline"]["kernel"]
+        d = [e - s0 for name, s0, e in rows if short_name(name) == k and s0 >= t0 and e <= t1]
+        mean = sum(d) / len(d) / 1e3 if d else float("nan")
+        out.append("| %s | %s | %d | %.1f | %.1f |" % (label, k, len(d), mean, 1e3 * obj["roofline"]["avg_launch_ms"]))
+    with open(out_md, "a") as fh:
+        fh.write("\n".join(out) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif sys.argv[1] == "window":
+        window(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], " ".join(sys.argv[6:]))
     else:
