@@ -495,7 +495,7 @@ def bench_single(args):
         "plain_colorings_per_s": round(plain_rate, 2) if plain_rate else None,
         "entries_per_step": entries // args.steps,
         "timed_window_monotonic_ns": [win0, win1],
-        "roofline": roofline_from(prof, "w%d" % args.workload),
+        "roofline": roofline_from(prof, "w%d" % args.workload) | {"launches_in_window": per_step * args.steps},
         "kernels_warmup": kernel_table(prof_all),
     }
     if not args.no_cpu_baseline:
