@@ -116,26 +116,52 @@ def traffic(fetch_dir, write_dir, copy_mib, out_json, command):
     f = _per_dispatch(_counter_rows(fetch_dir))
     w = _per_dispatch(_counter_rows(write_dir))
     copy_bytes = float(copy_mib) * (1 << 20)
-    # the calibration copy: the largest dispatch of a kernel outside the library
+    # the calibration copy: the largest dispatch before the library's first
+    # kernel (the bench runs it first; later runtime copies belong to the
+    # library's own work)
     def calib(acc):
-        cands = [(v, k) for k, v in acc.items() if short_name(k[0]) is None]
+        lib_ids = [int(d) for (name, d) in acc if "ccg::" in name]
+        first = min(lib_ids) if lib_ids else None
+        cands = [(v, k) for k, v in acc.items() if "ccg::" not in k[0] and (first is None or int(k[1]) < first)]
         return max(cands)[0] if cands else None
     fc, wc = calib(f), calib(w)
     sf = copy_bytes / fc if fc else 1.0
     sw = copy_bytes / wc if wc else 1.0
-    per = defaultdict(lambda: [0.0, 0.0, 0])
-    for (name, disp), v in f.items():
-        s = short_name(name)
-        if s:
-            per[s][0] += v * sf
-            per[s][2] += 1
-    for (name, disp), v in w.items():
-        s = short_name(name)
-        if s:
-            per[s][1] += v * sw
+    # A radix sort is one library launch of several dispatches (a histogram,
+    # scans and a scatter per 8-bit pass): the dispatches from one radix
+    # kernel up to the next kernel that is neither a radix nor a scan kernel
+    # form one launch, scans included, as the library's profiler times it.
+    # Each counter's run is grouped on its own (dispatch ids differ between
+    # runs when lanes run concurrently).
+    def grouped(acc, scale):
+        names = {int(d): name for (name, d) in acc}
+        vals = defaultdict(float)
+        for (name, d), v in acc.items():
+            vals[int(d)] += v
+        total, launches = defaultdict(float), defaultdict(int)
+        in_sort = False
+        for d in sorted(names):
+            sn = short_name(names[d])
+            if sn == "radix_sort":
+                if not in_sort:
+                    launches[sn] += 1
+                in_sort = True
+                total[sn] += vals[d] * scale
+            elif sn == "scan" and in_sort:
+                total["radix_sort"] += vals[d] * scale
+            else:
+                in_sort = False
+                if sn:
+                    launches[sn] += 1
+                    total[sn] += vals[d] * scale
+        return total, launches
+
+    ft, fl = grouped(f, sf)
+    wt, wl = grouped(w, sw)
+    per = {k: [ft[k], wt.get(k, 0.0), fl[k], wl.get(k, 0)] for k in ft}
     kernels = {k: {"fetch_bytes_per_launch": round(v[0] / max(v[2], 1)),
-                   "write_bytes_per_launch": round(v[1] / max(v[2], 1)),
-                   "bytes_per_launch": round((v[0] + v[1]) / max(v[2], 1)), "launches": v[2]}
+                   "write_bytes_per_launch": round(v[1] / max(v[3], 1)),
+                   "bytes_per_launch": round(v[0] / max(v[2], 1) + v[1] / max(v[3], 1)), "launches": v[2]}
                for k, v in per.items()}
     out = {"command": command, "source_hash": kernel_source_hash(), "copy_calibration_bytes": copy_bytes,
            "fetch_scale": sf, "write_scale": sw, "kernels": kernels}
