@@ -177,6 +177,9 @@ struct cc_graph {
     // endpoints of stored edge e, ascending
     uint64_t* cn_off = nullptr;
     int32_t* cn_col = nullptr;
+    // log2 of the largest homomorphism count of a tree plan's subtrees by
+    // their size (prefix maxima), keyed by the plan's step structure
+    std::map<std::string, std::vector<double>> hom_bounds;
     // vertices with degree >= d
     int64_t count_deg_at_least(int64_t d) const;
     // fraction of edge endpoints whose vertex has degree >= d

@@ -445,50 +445,71 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     if (rq.slot_lb_in && rq.slot_lb_in->size() == lb.size()) {
         lb = *rq.slot_lb_in;
     } else if (!rq.capture && !rq.no_alloc && g.n > 0) {
-        std::vector<double*> h(S, nullptr);
-        uint64_t* hmax = nullptr;
-        try {
-            hmax = X.alloc<uint64_t>(S);
-            launch_fill_u64(hmax, 0, S, s);
-            for (size_t i = 0; i < S; i++) {
-                const Step& st = plan.steps[i];
-                size_t o = i;
-                if (st.kind == S_LEAF) {
-                    h[i] = X.alloc<double>(uint64_t(g.n));
-                    launch_fill_u64(reinterpret_cast<uint64_t*>(h[i]), 0x3FF0000000000000ull, uint64_t(g.n), s);  // 1.0
-                } else if (fuse[i]) {
-                    o = i + 1;
-                    h[o] = X.alloc<double>(uint64_t(g.n));
-                    launch_hom_spmv(g, h[size_t(st.in0)], h[o], s);
-                    i++;
-                } else if (st.kind == S_JOIN) {
-                    h[i] = X.alloc<double>(uint64_t(g.n));
-                    launch_hom_mul(h[size_t(st.in0)], h[size_t(st.in1)], h[i], uint64_t(g.n), s);
-                }
-                if (h[o]) launch_hom_max(h[o], uint64_t(g.n), hmax + o, s);
-            }
-            uint64_t* hb = X.lane.result_words(S);
-            hip_check(hipMemcpyAsync(hb, hmax, 8 * S, hipMemcpyDeviceToHost, s), "copy bounds");
-            hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-            std::vector<double> by_size(lb.size(), 0.0);
-            for (size_t i = 0; i < S; i++) {
-                if (!h[i]) continue;
-                double m;
-                std::memcpy(&m, &hb[i], 8);
-                const double l = m > 1.0 ? std::log2(m) + 1e-6 : 0.0;  // margin for rounding
-                by_size[size_t(sz[i])] = std::max(by_size[size_t(sz[i])], l);
-            }
-            double pm = 0.0;
-            for (size_t s2 = 0; s2 < lb.size(); s2++) {
-                pm = std::max(pm, by_size[s2]);
-                lb[s2] = std::min(lb[s2], pm);
-            }
-        } catch (const CcError& e) {
-            if (e.code != CC_ENOMEM) throw;  // no room: the degree bound stands
+        // the bounds depend on the graph and the plan's step structure only:
+        // computed once per (graph, structure)
+        std::string key;
+        for (size_t i = 0; i < S; i++) {
+            const Step& st = plan.steps[i];
+            key += std::to_string(int(st.kind)) + ":" + std::to_string(st.in0) + ":" + std::to_string(st.in1) + ":" +
+                   std::to_string(int(fuse[i])) + ":" + std::to_string(sz[i]) + ";";
         }
-        for (double* x : h)
-            if (x) X.release(x);
-        if (hmax) X.release(hmax);
+        cc_graph* gm = const_cast<cc_graph*>(rq.g);
+        std::vector<double> pm_size;
+        {
+            std::lock_guard<std::mutex> lk(gm->ball_mu);
+            auto it = gm->hom_bounds.find(key);
+            if (it != gm->hom_bounds.end()) pm_size = it->second;
+        }
+        if (pm_size.empty()) {
+            std::vector<double*> h(S, nullptr);
+            uint64_t* hmax = nullptr;
+            try {
+                hmax = X.alloc<uint64_t>(S);
+                launch_fill_u64(hmax, 0, S, s);
+                for (size_t i = 0; i < S; i++) {
+                    const Step& st = plan.steps[i];
+                    size_t o = i;
+                    if (st.kind == S_LEAF) {
+                        h[i] = X.alloc<double>(uint64_t(g.n));
+                        launch_fill_u64(reinterpret_cast<uint64_t*>(h[i]), 0x3FF0000000000000ull, uint64_t(g.n), s);  // 1.0
+                    } else if (fuse[i]) {
+                        o = i + 1;
+                        h[o] = X.alloc<double>(uint64_t(g.n));
+                        launch_hom_spmv(g, h[size_t(st.in0)], h[o], s);
+                        i++;
+                    } else if (st.kind == S_JOIN) {
+                        h[i] = X.alloc<double>(uint64_t(g.n));
+                        launch_hom_mul(h[size_t(st.in0)], h[size_t(st.in1)], h[i], uint64_t(g.n), s);
+                    }
+                    if (h[o]) launch_hom_max(h[o], uint64_t(g.n), hmax + o, s);
+                }
+                uint64_t* hb = X.lane.result_words(S);
+                hip_check(hipMemcpyAsync(hb, hmax, 8 * S, hipMemcpyDeviceToHost, s), "copy bounds");
+                hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+                std::vector<double> by_size(lb.size(), 0.0);
+                for (size_t i = 0; i < S; i++) {
+                    if (!h[i]) continue;
+                    double m;
+                    std::memcpy(&m, &hb[i], 8);
+                    const double l = m > 1.0 ? std::log2(m) + 1e-6 : 0.0;  // margin for rounding
+                    by_size[size_t(sz[i])] = std::max(by_size[size_t(sz[i])], l);
+                }
+                double pm = 0.0;
+                for (size_t s2 = 0; s2 < by_size.size(); s2++) {
+                    pm = std::max(pm, by_size[s2]);
+                    by_size[s2] = pm;
+                }
+                pm_size = by_size;
+                std::lock_guard<std::mutex> lk(gm->ball_mu);
+                gm->hom_bounds[key] = pm_size;
+            } catch (const CcError& e) {
+                if (e.code != CC_ENOMEM) throw;  // no room: the degree bound stands
+            }
+            for (double* x : h)
+                if (x) X.release(x);
+            if (hmax) X.release(hmax);
+        }
+        for (size_t s2 = 0; s2 < lb.size() && s2 < pm_size.size(); s2++) lb[s2] = std::min(lb[s2], pm_size[s2]);
     }
     out->slot_lb = lb;
     auto below = [&](int set, int bits) { return lb[size_t(set)] < double(bits) - 1e-9; };
