@@ -140,8 +140,8 @@ struct cc_context {
     int batch_lanes = 0;       // lanes for cc_count_batch (0: tuned on first use)
     // schedule choices (cc_tune_batch / cc_set_schedule):
     int entry_factor = 3;      // entry-wise introduce when it walks < 1/entry_factor of the fixed column's rows
-    int sort_above_k = 12;
-    int group_min = 2;         // entry-wise introduces group entries with equal bag images at this many per group     // sorted-list forget and join add up by sorting when k exceeds this (else dense LDS)
+    int sort_above_k = 12;     // sorted-list forget and join add up by sorting when k exceeds this (else dense LDS)
+    int group_min = 2;         // entry-wise introduces group entries with equal bag images at this many per group
     uint16_t* slot_tables = nullptr;  // device: rank[2048] then unrank[2048] (slots.hip)
     uint32_t* slot_splits = nullptr;  // device: join split tables (slots.hip)
     uint64_t* slot_pack = nullptr;    // device: packed child slots of edge steps, k <= kSlotPackK
