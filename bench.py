@@ -13,9 +13,9 @@ timed steps are submitted at once to the server (continuous batching over
 concurrent lanes, admission by estimated table memory) and `value` is the
 served queries/s over that timed region.  Beside it, on the same queries:
   plain      one query at a time on one stream (the paper's single runs);
-  poisson    Poisson arrivals at --load x the plain rate, served with
-             --inflight lanes (with and without tail protection, --tail)
-             and with one lane: queries/s, p50/p99 latency;
+  poisson    --poisson-queries Poisson arrivals at --load x the plain
+             rate, served with --poisson-inflight lanes (also with tail
+             protection, --tail) and with one lane: queries/s, p50/p99;
   batched_w4 the first 64 of the 256 queries of BA(200000, 5) (16 colourings
              each; all 256 with --workload 4): plain vs cc_count_batch, DP
              table entries/s (--no-w4 skips it).
@@ -272,9 +272,9 @@ def bench_serve(args):
                     time.sleep(min(0.0005, max(0.0, due - time.perf_counter())))
             p, s = sel[q]
             tickets.append((q, srv.submit(decs[q], p.n, W.colouring_seed(s), B)))
-        res = {}
+        res = []
         for i, (q, t) in enumerate(tickets):
-            res[q] = srv.wait(t)
+            res.append((q, srv.wait(t)))
             if i % 20 == 19:
                 log("served", i + 1, "of", len(tickets))
         wall = time.perf_counter() - t_start
@@ -283,7 +283,7 @@ def bench_serve(args):
 
     def same(res):
         return all(r[0] == 1 and np.array_equal(r[1], plain[q][0]) and np.array_equal(r[2], plain[q][1])
-                   for q, r in res.items())
+                   for q, r in res)
 
     # warm-up steps through the server, every kernel timed: the dominant
     # kernel is named here and the timed steps record only it
@@ -309,10 +309,13 @@ def bench_serve(args):
     # Poisson arrivals at a fraction of the plain rate: many lanes vs one
     lam = args.load * plain_qps
     rng = np.random.Generator(np.random.PCG64(w.seed ^ 0xA5))
-    gaps = rng.exponential(1.0 / lam, size=len(timed))
-    st_p, res_p, _ = serve(timed, args.inflight, gaps, tail=args.tail)
-    st_n, res_n, _ = serve(timed, args.inflight, gaps)
-    st_1, res_1, _ = serve(timed, 1, gaps)
+    # a longer stream than the timed queries (they repeat, in order), so the
+    # p99 is not just the single slowest arrival
+    pq = [timed[i % len(timed)] for i in range(max(args.poisson_queries, len(timed)))]
+    gaps = rng.exponential(1.0 / lam, size=len(pq))
+    st_p, res_p, _ = serve(pq, args.poisson_inflight, gaps)
+    st_n, res_n, _ = serve(pq, args.poisson_inflight, gaps, tail=args.tail)
+    st_1, res_1, _ = serve(pq, 1, gaps)
     if not (same(res_p) and same(res_n) and same(res_1)):
         raise SystemExit("served counts differ from plain counts")
 
@@ -338,8 +341,9 @@ def bench_serve(args):
                   "p99_ms": round(1e3 * float(np.percentile(lat_plain, 99)), 2),
                   "entries_per_s": round(entries / t_plain, 1)},
         "served_vs_plain": round(served_qps / plain_qps, 3),
-        "poisson": {"offered_qps": round(lam, 3), "load": args.load, "tail_factor": args.tail, "served": lat(st_p),
-                    "served_no_tail_protection": lat(st_n), "one_lane": lat(st_1),
+        "poisson": {"offered_qps": round(lam, 3), "load": args.load, "tail_factor": args.tail,
+                    "inflight": args.poisson_inflight, "arrivals": len(pq), "served": lat(st_p),
+                    "served_tail_protection": lat(st_n), "one_lane": lat(st_1),
                     "p99_vs_one_lane": round(st_p["p99_ms"] / st_1["p99_ms"], 3) if st_1["p99_ms"] else None},
         "entries_per_s_served": round(entries / wall_sat, 1),
         "bit_identical_served_vs_plain": True,
@@ -582,9 +586,12 @@ def main():
                     help="queries of workload 4 (0: all 256 with --workload 4, the first 64 in the default run)")
     ap.add_argument("--load", type=float, default=0.7, help="Poisson arrival rate / plain throughput")
     ap.add_argument("--inflight", type=int, default=6, help="concurrent queries while serving")
+    ap.add_argument("--poisson-inflight", type=int, default=2, help="concurrent queries of the Poisson-served runs")
+    ap.add_argument("--poisson-queries", type=int, default=120,
+                    help="arrivals of each Poisson run (the timed queries, repeated in order)")
     ap.add_argument("--tail", type=float, default=2.5,
-                    help="tail protection of the Poisson-served run: no admission while a query has run this many "
-                         "times the mean service time (0: off)")
+                    help="tail protection of the second Poisson-served run: no admission while a query has run this "
+                         "many times the mean service time")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams of the workload-4 batch")
     ap.add_argument("--no-w4", action="store_true", help="skip the workload-4 batch in the default run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
