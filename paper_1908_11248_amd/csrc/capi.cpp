@@ -279,6 +279,10 @@ void cc_graph_free(cc_graph* g) {
     if (g->ball_w2) (void)hipFree(g->ball_w2);
     if (g->cn_off) (void)hipFree(g->cn_off);
     if (g->cn_col) (void)hipFree(g->cn_col);
+    if (g->wd_hk) (void)hipFree(g->wd_hk);
+    if (g->wd_hv) (void)hipFree(g->wd_hv);
+    if (g->wd_start) (void)hipFree(g->wd_start);
+    if (g->wd_mid) (void)hipFree(g->wd_mid);
     delete g;
 }
 

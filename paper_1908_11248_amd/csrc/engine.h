@@ -177,6 +177,17 @@ struct cc_graph {
     // endpoints of stored edge e, ascending
     uint64_t* cn_off = nullptr;
     int32_t* cn_col = nullptr;
+    // wedge index (built when an introduce first needs it and the graph has
+    // at most 2^28 neighbour pairs): a hash of the vertex pairs x < y with a
+    // common neighbour (keys x << wd_vb | y in wd_hk, their run in wd_hv) over
+    // the runs wd_start[r] .. wd_start[r + 1] of common neighbours in wd_mid
+    uint64_t* wd_hk = nullptr;
+    uint32_t* wd_hv = nullptr;
+    uint64_t wd_mask = 0;
+    uint64_t* wd_start = nullptr;
+    int32_t* wd_mid = nullptr;
+    int wd_vb = 0;
+    bool wd_tried = false;
     // log2 of the largest homomorphism count of a tree plan's subtrees by
     // their size (prefix maxima), keyed by the plan's step structure
     std::map<std::string, std::vector<double>> hom_bounds;

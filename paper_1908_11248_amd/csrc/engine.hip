@@ -1114,6 +1114,94 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
         }
         return gm->cn_off != nullptr;
     };
+    // the graph's wedge index, built the first time an introduce can use it
+    // (not in calls that may not allocate, nor past 2^28 neighbour pairs;
+    // without room in the arena the introduce walks adjacency rows instead)
+    auto wedge_ready = [&]() -> bool {
+        cc_graph* gm = const_cast<cc_graph*>(rq.g);
+        std::lock_guard<std::mutex> lk(gm->ball_mu);
+        if (gm->wd_start) return true;
+        if (gm->wd_tried || rq.no_alloc || g_all.m2 == 0) return false;
+        double pairs = 0;
+        for (int32_t v = 0; v < gm->n; v++) {
+            const double d = double(gm->host_rp[size_t(v) + 1] - gm->host_rp[size_t(v)]);
+            pairs += d * (d - 1) / 2;
+        }
+        if (pairs > double(uint64_t(1) << 28)) {
+            gm->wd_tried = true;
+            return false;
+        }
+        const int vb = std::max(1, bits_for(uint64_t(gm->n)));
+        const uint64_t m2 = uint64_t(g_all.m2);
+        std::vector<void*> temps;
+        uint64_t* hk = nullptr;
+        uint32_t* hv = nullptr;
+        uint64_t* wstart = nullptr;
+        int32_t* mid = nullptr;
+        try {
+            uint32_t* cnt = X.alloc<uint32_t>(m2);
+            temps.push_back(cnt);
+            X.timed("wedge_count", 12.0 * double(m2), [&] { launch_wedge_count(g_all, cnt, s); });
+            uint64_t* off;
+            const uint64_t R = X.scan(cnt, m2, &off);
+            temps.push_back(off);
+            uint64_t* keys = X.alloc<uint64_t>(std::max<uint64_t>(R, 1));
+            uint64_t* vals = X.alloc<uint64_t>(std::max<uint64_t>(R, 1));
+            temps.push_back(keys);
+            temps.push_back(vals);
+            X.timed("wedge_emit", 16.0 * double(R), [&] { launch_wedge_emit(g_all, vb, off, keys, vals, s); });
+            if (R > 1) {
+                void* kb2 = X.raw(R * 8);
+                uint64_t* vb2 = X.alloc<uint64_t>(R);
+                void* tmp = X.raw(radix_tmp_bytes(R));
+                temps.push_back(kb2);
+                temps.push_back(vb2);
+                temps.push_back(tmp);
+                bool in_b = false;
+                X.timed("radix_sort", 2.0 * double((2 * vb + 7) / 8) * double(R) * 16.0,
+                        [&] { in_b = radix_sort(keys, vals, kb2, vb2, R, 1, 2 * vb, 0, tmp, s, false); });
+                if (in_b) {
+                    keys = static_cast<uint64_t*>(kb2);
+                    vals = vb2;
+                }
+            }
+            DevTable t;
+            t.keys = keys;
+            t.cnt = vals;
+            t.n = R;
+            t.lay = Lay{2, vb, 0, 0};
+            uint64_t* starts;
+            const uint64_t G = X.groups(t, 0, &starts);
+            temps.push_back(starts);
+            uint64_t cells = 16;
+            while (cells < 2 * std::max<uint64_t>(G, 1)) cells <<= 1;
+            if (hipMalloc(&hk, 8 * cells) != hipSuccess || hipMalloc(&hv, 4 * cells) != hipSuccess ||
+                hipMalloc(&wstart, 8 * (G + 1)) != hipSuccess ||
+                hipMalloc(&mid, 4 * std::max<uint64_t>(R, 1)) != hipSuccess)
+                fail(CC_ENOMEM, "wedge index");
+            launch_fill_u64(hk, kEdgeEmpty, cells, s);
+            X.timed("wedge_hash", 28.0 * double(G), [&] { launch_wedge_hash(keys, starts, G, hk, hv, cells - 1, s); });
+            hip_check(hipMemcpyAsync(wstart, starts, 8 * (G + 1), hipMemcpyDeviceToDevice, s), "copy");
+            launch_u64_to_i32(vals, mid, R, s);
+            hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            for (void* p : temps) X.release(p);
+            gm->wd_hk = hk;
+            gm->wd_hv = hv;
+            gm->wd_mask = cells - 1;
+            gm->wd_start = wstart;
+            gm->wd_mid = mid;
+            gm->wd_vb = vb;
+            return true;
+        } catch (const CcError& e) {
+            (void)hipStreamSynchronize(s);
+            for (void* p : temps) X.release(p);
+            for (void* p : {(void*)hk, (void*)hv, (void*)wstart, (void*)mid})
+                if (p) (void)hipFree(p);
+            gm->wd_tried = true;
+            if (e.code != CC_ENOMEM) throw;
+            return false;
+        }
+    };
     const size_t S = plan.steps.size();
     std::vector<DevTable> tab(S);
     std::vector<StepLinks> lk(S);
@@ -1403,6 +1491,17 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     } else {
                         ea.cn0 = ea.cn1 = -1;
                     }
+                } else if (st.nchk >= 1 && wedge_ready()) {
+                    // two bag neighbours not adjacent in F: the common
+                    // neighbours of their images, from the wedge index
+                    ea.wd0 = st.anchor;
+                    ea.wd1 = st.chk[0];
+                    ea.wd_vb = rq.g->wd_vb;
+                    ea.wd_hk = rq.g->wd_hk;
+                    ea.wd_hv = rq.g->wd_hv;
+                    ea.wd_mask = rq.g->wd_mask;
+                    ea.wd_start = rq.g->wd_start;
+                    ea.wd_mid = rq.g->wd_mid;
                 }
                 // sums[0]: candidates of the fixed-column forms (the anchor's
                 // degree per entry), sums[1]: of the entry-wise form; a large
@@ -1412,7 +1511,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 uint64_t* sums = X.alloc<uint64_t>(2);
                 launch_fill_u64(sums, 0, 2, s);
                 const uint64_t factor = uint64_t(std::max(1, ctx->entry_factor));
-                const uint64_t stride = ea.cn0 < 0 && in.n >= (uint64_t(1) << 20) ? in.n >> 16 : 1;
+                const uint64_t stride = ea.cn0 < 0 && ea.wd0 < 0 && in.n >= (uint64_t(1) << 20) ? in.n >> 16 : 1;
                 bool decided = false;
                 if (stride > 1) {
                     X.timed("entry_sample", double(in.n / stride) * (entry_bytes(in.lay.b) + 8.0),
@@ -1422,7 +1521,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     decided = true;
                 }
                 if (!decided || entry_form) {
-                    if (ea.cn0 >= 0) ea.erow = X.alloc<int64_t>(in.n);
+                    if (ea.cn0 >= 0 || ea.wd0 >= 0) ea.erow = X.alloc<int64_t>(in.n);
                     e_slen = X.alloc<uint32_t>(in.n);
                     e_src = X.alloc<uint8_t>(in.n);
                     launch_fill_u64(sums, 0, 2, s);
@@ -1451,7 +1550,8 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 // re-sort follows.
                 uint64_t* fgs = nullptr;
                 const uint64_t Gf = X.groups(in, in.lay.kb, &fgs);
-                if (ea.cn0 < 0 && g.n <= (1 << 27) && ctx->group_min > 0 && uint64_t(ctx->group_min) * Gf <= in.n) {
+                if (ea.cn0 < 0 && ea.wd0 < 0 && g.n <= (1 << 27) && ctx->group_min > 0 &&
+                    uint64_t(ctx->group_min) * Gf <= in.n) {
                     X.release(e_soff);
                     X.release(e_src);
                     IntroArgs ga = ea;

@@ -306,6 +306,18 @@ k_expand(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, c
     }
 }
 
+// the run of the pair (x, y), x < y, in the wedge index; -1: no common neighbour
+__device__ __forceinline__ int64_t wedge_run(const IntroArgs& a, uint32_t x, uint32_t y) {
+    const uint64_t key = (uint64_t(x) << a.wd_vb) | uint64_t(y);
+    uint64_t h = edge_cell(key, a.wd_mask);
+    for (;;) {
+        const uint64_t k = a.wd_hk[h];
+        if (k == key) return int64_t(a.wd_hv[h]);
+        if (k == kEdgeEmpty) return -1;
+        h = (h + 1) & a.wd_mask;
+    }
+}
+
 // ---- entry-wise expand -----------------------------------------------------
 //
 // A segment is one child entry; its candidates for the new vertex are the
@@ -342,6 +354,23 @@ k_entry_seglen(const K* __restrict__ keys, Lay L, uint64_t N, uint64_t stride, D
             if (stride == 1) {
                 slen[e] = uint32_t(c1 - c0);
                 src[e] = uint8_t(0x80 | (a.cn0 << 3) | a.cn1);
+                a.erow[e] = int64_t(c0);
+            }
+            continue;
+        }
+        if (a.wd0 >= 0) {  // the common neighbours of two non-adjacent bag images
+            uint32_t x = kcol(k, L, a.wd0), y = kcol(k, L, a.wd1);
+            if (x > y) {
+                const uint32_t t = x;
+                x = y;
+                y = t;
+            }
+            const int64_t r = wedge_run(a, x, y);
+            const uint64_t c0 = r >= 0 ? a.wd_start[r] : 0, c1 = r >= 0 ? a.wd_start[r + 1] : 0;
+            items += c1 - c0;
+            if (stride == 1) {
+                slen[e] = uint32_t(c1 - c0);
+                src[e] = uint8_t(0xC0 | (a.wd0 << 3) | a.wd1);
                 a.erow[e] = int64_t(c0);
             }
             continue;
@@ -392,7 +421,8 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
         // the segment's entry: key, candidate list, colouring, colour set;
         // source byte sc: the column whose adjacency list gives the
         // candidates, or 0x80 | c0 << 3 | c1 for the common neighbours of
-        // columns c0 and c1
+        // columns c0 and c1 (with 0x40: from the wedge index, the columns'
+        // vertices not adjacent in F)
         uint64_t seg = seg0;
         KI key{};
         int64_t row = 0;
@@ -403,7 +433,7 @@ k_expand_entry(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, La
             sc = src[seg];
             if (sc & 0x80u) {
                 row = a.erow[seg];
-                cand = a.cn_col;
+                cand = (sc & 0x40u) ? a.wd_mid : a.cn_col;
             } else {
                 row = g.rp[kcol(key, L, int(sc))];
                 cand = g.col;
@@ -540,6 +570,81 @@ __global__ void k_cn(DevGraph g, uint32_t* cnt, const uint64_t* __restrict__ off
         }
         if (!EMIT) cnt[e] = c;
     }
+}
+
+// ---- wedge index ---------------------------------------------------------------
+//
+// Two bag neighbours a, b of an introduced vertex u that are not adjacent in
+// F: u's candidates are the common neighbours of phi(a) and phi(b), vertices
+// at distance 2 or less of each other in G.  For every vertex w and every
+// pair x < y of its neighbours (rows ascend, so a stored edge (w, x) at row
+// position i pairs with the positions after i) a record (x << vb | y, w);
+// sorted, one pair's records are its common neighbours; an open-addressing
+// hash of the pairs gives a pair's run.
+
+__global__ void k_wedge_count(DevGraph g, uint32_t* cnt) {
+    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < uint64_t(g.m2);
+         e += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t w = uint32_t(g.esrc[e]);
+        const int64_t r0 = g.rp[w], d = g.rp[w + 1] - r0, i = int64_t(e) - r0;
+        cnt[e] = uint32_t(d - 1 - i);
+    }
+}
+
+__global__ void k_wedge_emit(DevGraph g, int vb, const uint64_t* __restrict__ off, uint64_t* keys, uint64_t* vals) {
+    for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < uint64_t(g.m2);
+         e += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t w = uint32_t(g.esrc[e]);
+        const int64_t r1 = g.rp[w + 1];
+        const uint64_t x = uint64_t(uint32_t(g.col[e]));
+        uint64_t o = off[e];
+        for (int64_t j = int64_t(e) + 1; j < r1; j++, o++) {
+            keys[o] = (x << vb) | uint64_t(uint32_t(g.col[j]));
+            vals[o] = w;
+        }
+    }
+}
+
+__global__ void k_wedge_hash(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ starts, uint64_t G,
+                             unsigned long long* hk, uint32_t* hv, uint64_t mask) {
+    for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < G; r += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t key = keys[starts[r]];
+        uint64_t h = edge_cell(key, mask);
+        // the keys are distinct and the table has at least twice as many
+        // cells: every insertion finds a free cell
+        for (;;) {
+            const unsigned long long old = atomicCAS(&hk[h], (unsigned long long)kEdgeEmpty, (unsigned long long)key);
+            if (old == (unsigned long long)kEdgeEmpty) {
+                hv[h] = uint32_t(r);
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+}
+
+__global__ void k_u64_to_i32(const uint64_t* __restrict__ in, int32_t* out, uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        out[i] = int32_t(in[i]);
+}
+
+void launch_wedge_count(DevGraph g, uint32_t* cnt, hipStream_t s) {
+    if (g.m2) k_wedge_count<<<grid_for(uint64_t(g.m2)), kBlock, 0, s>>>(g, cnt);
+}
+
+void launch_wedge_emit(DevGraph g, int vb, const uint64_t* off, uint64_t* keys, uint64_t* vals, hipStream_t s) {
+    if (g.m2) k_wedge_emit<<<grid_for(uint64_t(g.m2)), kBlock, 0, s>>>(g, vb, off, keys, vals);
+}
+
+void launch_wedge_hash(const uint64_t* keys, const uint64_t* starts, uint64_t G, uint64_t* hk, uint32_t* hv,
+                       uint64_t mask, hipStream_t s) {
+    if (G)
+        k_wedge_hash<<<grid_for(G), kBlock, 0, s>>>(keys, starts, G, reinterpret_cast<unsigned long long*>(hk), hv,
+                                                     mask);
+}
+
+void launch_u64_to_i32(const uint64_t* in, int32_t* out, uint64_t n, hipStream_t s) {
+    if (n) k_u64_to_i32<<<grid_for(n), kBlock, 0, s>>>(in, out, n);
 }
 
 void launch_cn_count(DevGraph g, uint32_t* cnt, hipStream_t s) {

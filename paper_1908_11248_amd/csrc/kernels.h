@@ -127,6 +127,17 @@ struct IntroArgs {
     const uint64_t* cn_off = nullptr;
     const int32_t* cn_col = nullptr;
     int64_t* erow = nullptr;
+    // entry-wise form: two child columns whose pattern vertices are not
+    // adjacent (wd0 < 0: none); the candidates are the common neighbours of
+    // their images, found in the graph's wedge index: a hash of vertex pairs
+    // (wd_hk keys x << wd_vb | y, x < y; wd_hv their run) over the runs
+    // wd_start[r] .. wd_start[r + 1] of middle vertices in wd_mid
+    int wd0 = -1, wd1 = -1, wd_vb = 0;
+    const uint64_t* wd_hk = nullptr;
+    const uint32_t* wd_hv = nullptr;
+    uint64_t wd_mask = 0;
+    const uint64_t* wd_start = nullptr;
+    const int32_t* wd_mid = nullptr;
 };
 void launch_push_work(const DevTable& in, const uint64_t* gstart, uint64_t G, DevGraph g,
                       const IntroArgs& a, uint32_t* wcount, hipStream_t s);
@@ -144,6 +155,14 @@ uint64_t expand_tiles(uint64_t T);
 // common-neighbour index of the stored edges: counts, then (off = their
 // exclusive prefix sums) the lists
 void launch_cn_count(DevGraph g, uint32_t* cnt, hipStream_t s);
+// wedge index: per stored edge (w, x) at row position i, the d(w) - 1 - i
+// pairs (x, y) of later neighbours y of w: counts, records (key x << vb | y,
+// value w), then the hash of the sorted records' runs, and the values as int32
+void launch_wedge_count(DevGraph g, uint32_t* cnt, hipStream_t s);
+void launch_wedge_emit(DevGraph g, int vb, const uint64_t* off, uint64_t* keys, uint64_t* vals, hipStream_t s);
+void launch_wedge_hash(const uint64_t* keys, const uint64_t* starts, uint64_t G, uint64_t* hk, uint32_t* hv,
+                       uint64_t mask, hipStream_t s);
+void launch_u64_to_i32(const uint64_t* in, int32_t* out, uint64_t n, hipStream_t s);
 // count bounds of tree plans (slots.hip): hout[v] = sum of hin over N(v);
 // out = a * b elementwise; *out = max(*out, max of h) (h >= 0, as bits)
 void launch_hom_spmv(DevGraph g, const double* hin, double* hout, hipStream_t s);
