@@ -935,9 +935,16 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     const uint32_t E = nv ? s_off[nv] : 0;
     const uint32_t rows = kSlotBlock / uint32_t(W);  // neighbour entries per pass, W threads each
     const uint32_t te = threadIdx.x / uint32_t(W), tr = threadIdx.x - te * uint32_t(W);
+    // largest power of two below nv: the first step of the search for an
+    // entry's vertex
+    const uint32_t top = nv > 1 ? 1u << (31 - __clz(nv - 1)) : 0u;
     uint32_t nin = 0;
     for (uint32_t c0 = 0; c0 < E; c0 += kPushChunk) {
         const uint32_t cn = min(uint32_t(kPushChunk), E - c0);
+        // one thread per staged entry: its neighbour, the neighbour's colour
+        // and its vertex within the block (the last lv whose row starts at
+        // or before it; a search over the block's offsets, so a vertex with
+        // many entries costs no more than one with few)
         for (uint32_t i0 = 0; i0 < cn; i0 += 4 * kSlotBlock) {
             uint32_t y[4];
 #pragma unroll
@@ -949,18 +956,17 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
             for (int j = 0; j < 4; j++) {
                 const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
                 const uint32_t c = cb[y[j]];
-                if (i < cn) s_y[i] = y[j] | (c << 24);
-            }
-        }
-        __syncthreads();
-        for (uint32_t lv = threadIdx.x; lv < nv; lv += kSlotBlock) {
-            const uint32_t a = max(s_off[lv], c0), z = min(s_off[lv + 1], c0 + cn);
-            const bool pass = s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u);
-            const uint32_t cv = s_cv[lv];
-            for (uint32_t e = a; e < z; e++) {
-                const uint32_t cy = s_y[e - c0] >> 24;
-                s_lv[e - c0] = pass && cy != cv ? lv | ((cy * uint32_t(k) + cv) << 16) : 0xffffffffu;
-                if (EPI) s_h[lv * uint32_t(k) + cy]++;  // row lv is this thread's alone
+                if (i < cn) {
+                    const uint32_t e = c0 + i;
+                    uint32_t lv = 0;
+                    for (uint32_t st = top; st; st >>= 1)
+                        if (lv + st < nv && s_off[lv + st] <= e) lv += st;
+                    const bool pass = s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u);
+                    const uint32_t cv = s_cv[lv];
+                    s_y[i] = y[j] | (c << 24);
+                    s_lv[i] = pass && c != cv ? lv | ((c * uint32_t(k) + cv) << 16) : 0xffffffffu;
+                    if (EPI) atomicAdd(&s_h[lv * uint32_t(k) + c], 1u);
+                }
             }
         }
         __syncthreads();
