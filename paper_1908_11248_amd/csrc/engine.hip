@@ -541,9 +541,9 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
     };
     // an edge step's push kernel (child set s_in, output s_e) fits a block's
     // LDS with the epilogue pj (null: none)
-    auto push_fits = [&](int s_in, int s_e, const PushJoin* pj) {
+    auto push_fits = [&](int s_in, int s_e, const PushJoin* pj, bool wrap = false) {
         const SlotGrid G = slot_grid(g.n, B, binom(k - 1, s_e - 1), 8);
-        return slot_push_lds(k, s_in, G, !below(s_e, 32), pj) <= kPushLdsMax;
+        return slot_push_lds(k, s_in, G, !below(s_e, 32), pj, wrap) <= kPushLdsMax;
     };
     if (k <= kSlotPushK && g.n < (1 << 24) && 1.0 + 2.0 * ldmax < 32.0 - 1e-9)
         for (size_t i = 0; i < S; i++) {
@@ -780,10 +780,12 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const uint64_t* pack = !leafc && k <= kSlotPackK && g.n < (1 << 24) && o.a.R <= kSlotBlock
                                        ? ctx->slot_pack + slot_pack_offset(k, o.s - 1)
                                        : nullptr;
-            // push from the child's rows whenever no count can wrap: a
-            // (neighbour, child slot) pair of the push is always useful
+            // push from the child's rows (a wrapping push when the step's
+            // counts may reach 2^64): a (neighbour, child slot) pair of the
+            // push is always useful
+            const bool wrap = !below(o.s, 64);
             const bool push = !leafc && k <= kSlotPushK && g.n < (1 << 24) && o.a.R <= kSlotBlock &&
-                              below(o.s, 64) && in.a.R <= kSlotBlock && push_fits(in.s, o.s, nullptr);
+                              in.a.R <= kSlotBlock && push_fits(in.s, o.s, nullptr, wrap);
             // vertices per thread (measured on workload 2): the gather's
             // latency wants more blocks, the push's LDS accumulators longer rows
             SlotGrid G = slot_grid(g.n, B, o.a.R, leafc ? 4 : push ? 8 : 2);
@@ -791,7 +793,8 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const int h_fe = X.timed(kname, double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 if (push)
                     launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, degF_u,
-                                          ctx->slot_push + slot_push_offset(k, in.s - 1), !below(o.s, 32), o.a, part, nullptr, s);
+                                          ctx->slot_push + slot_push_offset(k, in.s - 1), !below(o.s, 32), o.a, part, nullptr,
+                                          wrap, ovf, s);
                 else
                     launch_slot_edge(in.a, G, g, rq.colors, k, degF_u, degF_c, rank, unrank,
                                      slot_unrank_offset(o.s - 1), pack, !leafc && below(in.s, 32),
@@ -847,7 +850,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const int h_pe = X.timed("slot_edge_push", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, rq.degree_mask ? ie.degF : 0,
                                       ctx->slot_push + slot_push_offset(k, in.s - 1), !below(s_e, 32), SlotArrays(),
-                                      nullptr, &pj, s);
+                                      nullptr, &pj, false, nullptr, s);
             });
             slot_bytes.push_back({h_pe, ie.in0, -1, int(i), csr_alg});
             tab[i] = o;
@@ -900,7 +903,7 @@ void run_slots(cc_context* ctx, Exec& X, const RunRequest& rq, const std::vector
             const int h_pe = X.timed("slot_edge_push", double(units) * 9.0 * (in.a.R + o.a.R) + csr, [&] {
                 launch_slot_edge_push(in.a, in.s, G, g, rq.colors, k, rq.degree_mask ? ie.degF : 0,
                                       ctx->slot_push + slot_push_offset(k, in.s - 1), !below(s_e, 32), SlotArrays(),
-                                      nullptr, &pj, s);
+                                      nullptr, &pj, false, nullptr, s);
             });
             slot_bytes.push_back({h_pe, ie.in0, -1, int(i), csr_alg});
             tab[i] = o;

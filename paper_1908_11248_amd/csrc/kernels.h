@@ -415,19 +415,21 @@ struct PushJoin {
     uint64_t* part_lj = nullptr;
     uint64_t* part_j = nullptr;
 };
-// The same step pushed from the child's rows into LDS accumulators; only for
-// a step whose counts cannot wrap (then every table below is exact).  s_in:
+// The same step pushed from the child's rows into LDS accumulators.  s_in:
 // the child's colour-set size; push: the entries of (k, s_in - 1) above;
 // wide: 64-bit accumulators (else every output count is below 2^32).  pj
-// (optional): the step's only reader is that join, computed instead of
-// storing out (then out and part are unused).
+// (optional, only where no count can wrap): the step's only reader is that
+// join, computed instead of storing out (then out and part are unused).
+// wrap: the step's counts may wrap (needs wide, no pj, out's presence bytes
+// and the overflow flags ovf, which a wrapped sum raises); else no count of
+// this or any table below can wrap (then every child table is exact).
 void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
                            int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
-                           const PushJoin* pj, hipStream_t s);
+                           const PushJoin* pj, bool wrap, uint32_t* ovf, hipStream_t s);
 // Dynamic LDS bytes of that launch (pj: its sizes chain, r1, nsplit1, nsplit
 // and out.R are used); a launch needs at most kPushLdsMax (64 KiB per block
 // less the kernel's static arrays).
-size_t slot_push_lds(int k, int s_in, const SlotGrid& G, bool wide, const PushJoin* pj);
+size_t slot_push_lds(int k, int s_in, const SlotGrid& G, bool wide, const PushJoin* pj, bool wrap = false);
 constexpr size_t kPushLdsMax = 54 * 1024;
 constexpr size_t kSlotJoinLds = 48 << 10;  // LDS bytes a join block may stage its children's rows in
 // split table rows of (p, q) (see slots.hip) start at slot_split_offset(p, q);

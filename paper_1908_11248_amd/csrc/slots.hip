@@ -873,6 +873,14 @@ __device__ void push_join_epilogue(const Acc* acc, const uint32_t* s_off, const 
 // present iff it is not 0.  WIDE: 64-bit accumulators, else every output
 // count is below 2^32.
 //
+// WRAP (with WIDE, not EPI): the bound allows counts of 2^64 or more, so sums
+// wrap mod 2^64 and the output has presence bytes.  The child is exact when
+// it has no presence bytes or colouring b's overflow flag is clear (its
+// producers raise it before this launch), and then an entry is present iff
+// its count is not 0; else its presence byte says.  An output slot is present
+// iff its sum is not 0 or it took a present 0 or its sum wrapped (a bit per
+// slot in LDS, set in those rare cases); a wrapped sum raises ovf[b].
+//
 // EPI: the step's table E is not stored.  Its only reader, a join at the
 // same bag vertex with the fused leaf join of two leaves hanging off that
 // vertex (Sec. 3, join nodes; leaves without a neighbour degree mask), is
@@ -881,15 +889,18 @@ __device__ void push_join_epilogue(const Acc* acc, const uint32_t* s_off, const 
 // h[c] and the leaf join 2 h[c1] h[c2] (below 2^32 by a bound), and the join
 // output follows from the split table with E's rows still in LDS.  The
 // partials of all five tables are written.
-template <bool WIDE, bool EPI>
+template <bool WIDE, bool EPI, bool WRAP>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
-                 const uint32_t* __restrict__ cmap, int W, SlotArrays out, uint64_t* part, PushJoin pj) {
+                 const uint32_t* __restrict__ cmap, int W, SlotArrays out, uint64_t* part, PushJoin pj,
+                 uint32_t* ovf) {
+    static_assert(!WRAP || (WIDE && !EPI), "a wrapping push has 64-bit sums and no epilogue");
     using Acc = typename std::conditional<WIDE, unsigned long long, uint32_t>::type;
     // [upb M][R] accumulators, [upb M + 1] CSR offsets, the k k W (child
     // slot, output slot) pairs of cmap, [upb M] colours; EPI: then (4-byte
     // aligned) [upb M][k] neighbour counts by colour, then the epilogue's
-    // rows and split rows (PushJoin) unless they fit s_stat
+    // rows and split rows (PushJoin) unless they fit s_stat; WRAP: then the
+    // [upb M][R] bits of the slots whose presence is not their sum's
     extern __shared__ uint64_t s_dyn[];
     // the staged neighbour entries of a chunk, free again after the push:
     // s_y: neighbour | colour << 24; s_lv: its vertex within the block |
@@ -924,8 +935,13 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     // the child's high plane only for a colouring in which some child count
     // reached 2^32 (its producer's flag); else every high word is 0
     const uint32_t* ihi = in.hi && (!in.wide || in.wide[b]) ? in.hi + row0 * R_in : nullptr;
+    const uint8_t* ifl = WRAP && in.flag && ovf[b] != 0 ? in.flag + row0 * R_in : nullptr;
+    uint32_t* s_cb = s_h;
+    uint32_t carry = 0;
     const int64_t e_lo = nv ? g.rp[v0] : 0;
     for (uint32_t i = threadIdx.x; i < nv * R; i += kSlotBlock) acc[i] = 0;
+    if (WRAP)
+        for (uint32_t i = threadIdx.x; i < (nv * R + 31) / 32; i += kSlotBlock) s_cb[i] = 0;
     if (EPI)
         for (uint32_t i = threadIdx.x; i < nv * uint32_t(k); i += kSlotBlock) s_h[i] = 0;
     for (uint32_t i = threadIdx.x; nv && i <= nv; i += kSlotBlock) s_off[i] = uint32_t(g.rp[v0 + i] - e_lo);
@@ -976,6 +992,7 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
             constexpr int NE = 8;
             for (uint32_t e0 = te; e0 < cn; e0 += NE * rows) {
                 uint32_t lv[NE], cm[NE], lo[NE], hi[NE];
+                uint8_t fl[NE];
 #pragma unroll
                 for (int j = 0; j < NE; j++) {
                     const uint32_t e = e0 + j * rows;
@@ -987,14 +1004,28 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
                     const uint32_t idx = (ye & 0xffffffu) * R_in + (cm[j] & 0xffffu);  // < n R_in < 2^28
                     lo[j] = ilo[idx];
                     hi[j] = WIDE && ihi ? ihi[idx] : 0u;
+                    fl[j] = WRAP && ifl ? ifl[idx] : uint8_t(1);
                 }
 #pragma unroll
                 for (int j = 0; j < NE; j++) {
                     if (lv[j] == 0xffffu) continue;
                     const Acc val = WIDE ? (Acc(hi[j]) << 32) | lo[j] : Acc(lo[j]);
+                    const uint32_t slot = lv[j] * R + (cm[j] >> 16);
+                    if (WRAP) {
+                        if (ifl ? fl[j] == 0 : val == 0) continue;  // absent
+                        nin++;
+                        bool mark = val == 0;
+                        if (!mark) {
+                            const Acc old = atomicAdd(&acc[slot], val);
+                            mark = old + val < old;
+                            carry |= uint32_t(mark);
+                        }
+                        if (mark) atomicOr(&s_cb[slot >> 5], 1u << (slot & 31u));
+                        continue;
+                    }
                     if (val == 0) continue;
                     nin++;
-                    atomicAdd(&acc[lv[j] * R + (cm[j] >> 16)], val);
+                    atomicAdd(&acc[slot], val);
                 }
             }
         }
@@ -1009,13 +1040,16 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     for (int i = 0; i < G.m; i++) {
         const uint32_t vi = v + uint32_t(i * G.upb);
         if (lane_ok && vi < v1) {
-            const uint64_t c = acc[(vi - v0) * R + r];
-            store_slot(out, (row0 + vi) * R + r, c, c != 0);
-            npres += c != 0;
+            const uint32_t slot = (vi - v0) * R + r;
+            const uint64_t c = acc[slot];
+            const bool p = c != 0 || (WRAP && ((s_cb[slot >> 5] >> (slot & 31u)) & 1u));
+            store_slot(out, (row0 + vi) * R + r, c, p);
+            npres += p;
             hi |= uint32_t(c >> 32);
         }
     }
     flag_wide(hi, &out.wide[b]);
+    if (WRAP && __ballot(carry != 0) != 0 && __lane_id() == 0) atomicOr(&ovf[b], 1u);
     count_entries(npres, nin, part, G.blocks);
 }
 
@@ -1692,10 +1726,11 @@ void launch_slot_edge(SlotArrays in, const SlotGrid& G, DevGraph g, const uint8_
 
 // Dynamic LDS of k_slot_edge_push for grid G, child set size s_in and the
 // epilogue pj (null: none); sets pj's rows_static and spl_static.
-static size_t push_lds(int k, int s_in, const SlotGrid& G, bool wide, PushJoin* pj) {
+static size_t push_lds(int k, int s_in, const SlotGrid& G, bool wide, PushJoin* pj, bool wrap) {
     const int W = binom_pq(k - 2, s_in - 1);
     const size_t cap = size_t(G.upb) * G.m;
     size_t lds = cap * G.R * (wide ? 8 : 4) + 4 * (cap + 1) + 4 * size_t(k) * k * W + 4 * ((cap + 3) / 4);
+    if (wrap) lds += 4 * ((cap * G.R + 31) / 32);
     if (pj) {
         // the epilogue's rows and split rows (32-bit words), in the chunk
         // arrays (kPushChunk 64-bit words) when they fit
@@ -1711,36 +1746,42 @@ static size_t push_lds(int k, int s_in, const SlotGrid& G, bool wide, PushJoin* 
     return lds;
 }
 
-size_t slot_push_lds(int k, int s_in, const SlotGrid& G, bool wide, const PushJoin* pj) {
+size_t slot_push_lds(int k, int s_in, const SlotGrid& G, bool wide, const PushJoin* pj, bool wrap) {
     PushJoin p = pj ? *pj : PushJoin();
-    return push_lds(k, s_in, G, wide, pj ? &p : nullptr);
+    return push_lds(k, s_in, G, wide, pj ? &p : nullptr, wrap);
 }
 
 void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph g, const uint8_t* colors, int k,
                            int degF_u, const uint32_t* push, bool wide, SlotArrays out, uint64_t* part,
-                           const PushJoin* pj, hipStream_t s) {
+                           const PushJoin* pj, bool wrap, uint32_t* ovf, hipStream_t s) {
     if (!G.blocks) return;
+    if (wrap && (pj || !wide || !ovf || !out.flag))
+        throw std::runtime_error("launch_slot_edge_push: a wrapping push needs 64-bit sums, presence bytes and the "
+                                 "overflow flags, and no epilogue");
     if (k > kSlotPushK || g.n >= (1 << 24) || G.upb == 0 || s_in < 1 || s_in > k - 1)
         throw std::runtime_error("launch_slot_edge_push: needs k <= 10, n < 2^24, R <= 256 and a child set below k");
     if (pj && !pj->chain && k < 4) throw std::runtime_error("launch_slot_edge_push: a fused leaf join needs k >= 4");
     const int W = binom_pq(k - 2, s_in - 1);
     PushJoin none{};
     PushJoin pjl = pj ? *pj : none;
-    const size_t lds = push_lds(k, s_in, G, wide, pj ? &pjl : nullptr);
+    const size_t lds = push_lds(k, s_in, G, wide, pj ? &pjl : nullptr, wrap);
     if (lds > kPushLdsMax) throw std::runtime_error("launch_slot_edge_push: dynamic LDS beyond kPushLdsMax");
-#define PUSH_LAUNCH(WIDE, EPI)                                                                                     \
-    k_slot_edge_push<WIDE, EPI><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, push, W, \
-                                                                              out, part, pj ? pjl : none)
+#define PUSH_LAUNCH(WIDE, EPI, WRAP)                                                                       \
+    k_slot_edge_push<WIDE, EPI, WRAP><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, \
+                                                                                    push, W, out, part,         \
+                                                                                    pj ? pjl : none, ovf)
     if (pj) {
         if (wide)
-            PUSH_LAUNCH(true, true);
+            PUSH_LAUNCH(true, true, false);
         else
-            PUSH_LAUNCH(false, true);
+            PUSH_LAUNCH(false, true, false);
+    } else if (wrap) {
+        PUSH_LAUNCH(true, false, true);
     } else {
         if (wide)
-            PUSH_LAUNCH(true, false);
+            PUSH_LAUNCH(true, false, false);
         else
-            PUSH_LAUNCH(false, false);
+            PUSH_LAUNCH(false, false, false);
     }
 #undef PUSH_LAUNCH
 }
