@@ -1218,8 +1218,9 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
     // Fusions (not when the contributor index is recorded): an introduce in
     // pull form over a one-column child followed by the forget of that column
     // runs as one gather (fused.hip); a leaf consumed only by such a step is
-    // never materialised.
-    std::vector<char> fuse(S, 0), virt(S, 0);
+    // never materialised.  Nor is a leaf whose only reader is an introduce in
+    // pull form with no edge test (lpull: its entries come from the edges).
+    std::vector<char> fuse(S, 0), virt(S, 0), lpull(S, 0);
     if (!keep) {
         for (size_t i = 0; i + 1 < S; i++) {
             const Step& a = plan.steps[i];
@@ -1229,6 +1230,18 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                 fuse[i] = 1;
                 if (plan.steps[a.in0].kind == S_LEAF && uses[a.in0] == 1) virt[a.in0] = 1;
             }
+        }
+        for (size_t i = 0; i < S; i++) {
+            const Step& a = plan.steps[i];
+            if (fuse[i] || (i > 0 && fuse[i - 1]) || a.kind != S_INTRO_PULL || a.b_in != 1 || a.nchk != 0 ||
+                rq.classic_expand || a.in0 < 0)
+                continue;
+            const Step& l = plan.steps[size_t(a.in0)];
+            // (an anchor-range chunk restricting the leaf's image keeps the table)
+            if (l.kind != S_LEAF || uses[size_t(a.in0)] != 1 || (rq.anchor_hi >= 0 && l.u == rq.anchor_vertex))
+                continue;
+            lpull[i] = 1;
+            virt[size_t(a.in0)] = 1;
         }
     }
     out->node_sizes.assign(dec.nodes.size(), 0);
@@ -1756,6 +1769,29 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
                     break;
                 }
                 case S_INTRO_PULL: {
+                    if (lpull[i]) {
+                        const int degF_l = rq.degree_mask ? plan.steps[size_t(st.in0)].degF : 0;
+                        const uint64_t tiles = leaf_pull_tiles(g, B);
+                        if (!tiles) {  // no edges
+                            o = X.table(lo, 0);
+                            break;
+                        }
+                        uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                        const double edges = double(B) * double(g.m2);
+                        X.timed("leaf_pull_count", 8.0 * double(g.m2) + 2.0 * edges + 4.0 * double(tiles), [&] {
+                            launch_leaf_pull_count(g, B, ia.degF, degF_l, rq.colors, lo, tcount, s);
+                        });
+                        uint64_t* toff;
+                        const uint64_t N = X.scan(tcount, tiles, &toff);
+                        X.release(tcount);
+                        o = X.table(lo, N);
+                        if (N)
+                            X.timed("leaf_pull_emit", 8.0 * double(g.m2) + 2.0 * edges + double(N) * entry_bytes(lo.b), [&] {
+                                launch_leaf_pull_emit(g, B, ia.degF, degF_l, rq.colors, toff, o, s);
+                            });
+                        X.release(toff);
+                        break;
+                    }
                     const DevTable& in = tab[st.in0];
                     if (in.n == 0) {
                         o = X.table(lo, 0);

@@ -264,4 +264,109 @@ void launch_edge_emit(const DevTable* in, const uint64_t* rstart, const uint64_t
                                 &out, out.lay, ovf, s);
 }
 
+
+// Introduce u in pull form over a leaf (Sec. 3.1 leaf and introduce rules;
+// degree masks of Sec. 3.2).  The leaf's table holds ((b, y), {zeta(y)}, 1)
+// for every y passing its mask, so the introduce's entries are the adjacent
+// pairs (v, y) with v passing u's mask and range, y the leaf's mask, and
+// zeta(v) != zeta(y): key (b, v, y, {zeta(v), zeta(y)}), count 1.  Neither
+// table is read: the items are the (colouring, directed edge) pairs, in
+// colouring-major CSR order, which is key order, so the output is sorted.
+// A tile is kLeafPullItems rounds of kBlock consecutive edges of one
+// colouring; the count pass stores a tile's survivors, the emit pass ranks
+// each round's survivors across the block (a ballot per wave), so a round's
+// outputs are one contiguous run.
+constexpr int kLeafPullItems = 16;
+constexpr uint64_t kLeafPullTile = uint64_t(kBlock) * kLeafPullItems;
+
+uint64_t leaf_pull_tiles(const DevGraph& g, int B) {
+    return uint64_t(B) * ((uint64_t(g.m2) + kLeafPullTile - 1) / kLeafPullTile);
+}
+
+template <class KO, bool EMIT>
+__global__ void __launch_bounds__(kBlock)
+k_leaf_pull(DevGraph g, int B, int degF_u, int degF_leaf, const uint8_t* __restrict__ colors, uint64_t tpb,
+            uint32_t* tcount, const uint64_t* __restrict__ toff, Lay LO, KO* okeys, uint64_t* ocnt) {
+    __shared__ uint32_t s_w[kBlock / 64];
+    const uint64_t tiles = tpb * uint64_t(B), m2 = uint64_t(g.m2);
+    const uint32_t wv = threadIdx.x >> 6, ln = threadIdx.x & 63u;
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint32_t b = uint32_t(tile / tpb);
+        const uint64_t e0 = (tile - uint64_t(b) * tpb) * kLeafPullTile;
+        const uint8_t* cb = colors + uint64_t(b) * uint32_t(g.n);
+        uint64_t o = EMIT ? toff[tile] : 0;
+        uint32_t mine = 0;
+        for (int j = 0; j < kLeafPullItems; j++) {
+            const uint64_t e = e0 + uint64_t(j) * kBlock + threadIdx.x;
+            bool ok = false;
+            uint32_t v = 0, y = 0, cv = 0, cy = 0;
+            if (e < m2) {
+                v = uint32_t(g.esrc[e]);
+                y = uint32_t(g.col[e]);
+                cv = cb[v];
+                cy = cb[y];
+                ok = cv != cy && intro_ok(g, v, degF_u) && int(g.deg8[y]) >= degF_leaf;
+            }
+            if (!EMIT) {
+                mine += ok;
+                continue;
+            }
+            const uint64_t bal = __ballot(ok);
+            if (ln == 0) s_w[wv] = uint32_t(__popcll(bal));
+            __syncthreads();
+            uint32_t before = 0, round = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; w++) {
+                const uint32_t c = s_w[w];
+                before += w < int(wv) ? c : 0u;
+                round += c;
+            }
+            __syncthreads();
+            if (ok) {
+                const uint64_t p = o + before + uint32_t(__popcll(bal & ((1ull << ln) - 1ull)));
+                const uint32_t cols[2] = {v, y};
+                okeys[p] = kpack<KO>(b, cols, 2, (1u << cv) | (1u << cy), LO);
+                ocnt[p] = 1;
+            }
+            o += round;
+        }
+        if (!EMIT) {
+            const uint32_t w = uint32_t(wave_sum(mine));
+            if (ln == 0) s_w[wv] = w;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t t = 0;
+                for (int i = 0; i < kBlock / 64; i++) t += s_w[i];
+                tcount[tile] = t;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <bool EMIT>
+static void leaf_pull_launch(DevGraph g, int B, int degF_u, int degF_leaf, const uint8_t* colors, uint32_t* tcount,
+                             const uint64_t* toff, Lay LO, void* okeys, uint64_t* ocnt, hipStream_t s) {
+    const uint64_t tiles = leaf_pull_tiles(g, B);
+    if (!tiles) return;
+    const uint64_t tpb = tiles / uint64_t(B);
+    const unsigned grid = unsigned(std::min<uint64_t>(tiles, 1u << 16));
+    if (LO.kw() == 1)
+        k_leaf_pull<uint64_t, EMIT><<<grid, kBlock, 0, s>>>(g, B, degF_u, degF_leaf, colors, tpb, tcount, toff, LO,
+                                                            (uint64_t*)okeys, ocnt);
+    else
+        k_leaf_pull<u128, EMIT><<<grid, kBlock, 0, s>>>(g, B, degF_u, degF_leaf, colors, tpb, tcount, toff, LO,
+                                                        (u128*)okeys, ocnt);
+}
+
+void launch_leaf_pull_count(DevGraph g, int B, int degF_u, int degF_leaf, const uint8_t* colors, Lay LO,
+                            uint32_t* tcount, hipStream_t s) {
+    leaf_pull_launch<false>(g, B, degF_u, degF_leaf, colors, tcount, nullptr, LO, nullptr, nullptr, s);
+}
+
+void launch_leaf_pull_emit(DevGraph g, int B, int degF_u, int degF_leaf, const uint8_t* colors,
+                           const uint64_t* toff, DevTable& out, hipStream_t s) {
+    leaf_pull_launch<true>(g, B, degF_u, degF_leaf, colors, nullptr, toff, out.lay, out.keys, out.cnt, s);
+}
+
 }  // namespace ccg

@@ -266,6 +266,15 @@ void launch_edge_count(const DevTable* in, const uint64_t* rstart, const uint64_
 void launch_edge_emit(const DevTable* in, const uint64_t* rstart, const uint64_t* rend, int B, DevGraph g,
                       const uint8_t* colors, int degF_u, int degF_child, const uint64_t* goff, DevTable& out,
                       uint32_t* ovf, hipStream_t s);
+// Introduce u in pull form over a leaf child, neither table read (the leaf
+// with mask degF_leaf is never stored): tiles of (colouring, directed edge)
+// items; the count pass writes survivors per tile (leaf_pull_tiles of them),
+// the emit pass the sorted output from the tiles' exclusive offsets.
+uint64_t leaf_pull_tiles(const DevGraph& g, int B);
+void launch_leaf_pull_count(DevGraph g, int B, int degF_u, int degF_leaf, const uint8_t* colors, Lay LO,
+                            uint32_t* tcount, hipStream_t s);
+void launch_leaf_pull_emit(DevGraph g, int B, int degF_u, int degF_leaf, const uint8_t* colors,
+                           const uint64_t* toff, DevTable& out, hipStream_t s);
 
 // enumeration support (enumerate.hip)
 // forget: dst[e] = output position of child entry e
