@@ -130,7 +130,7 @@ def kernel_table(prof):
 # ---------------------------------------------------------------------------
 # CPU baseline: the oracle in worker processes, stopped after a time budget
 
-def cpu_baseline(jobs, unit_per_job, unit, what, budget_s=20.0, workers=8):
+def cpu_baseline(jobs, unit_per_job, unit, what, budget_s=20.0, workers=16):
     """Runs oracle jobs (workload index, pattern, k, colouring seed, b) in a
     child process pool for about budget_s seconds; the child prints one line
     per finished job and is killed when the budget runs out (a job of the
@@ -411,9 +411,10 @@ def bench_batched_w4(args, timed_steps=None, nq=None):
     entries = 0
     win0 = time.monotonic_ns()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         out = cc.count_batch(ctx, G, queries)
         entries += int(ctx.last_table_sizes().sum())
+        log("batched step", i + 1, "of", steps, "at %.1f s" % (time.perf_counter() - t0))
     dt = time.perf_counter() - t0
     win1 = time.monotonic_ns()
     prof = ctx.profile_read()
@@ -578,7 +579,8 @@ def main():
         return oracle_worker()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 1 with --workload 4, where a step is the whole 256-query batch)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="serve", choices=["serve", "2", "3", "4", "5", "paper"])
     ap.add_argument("--per-step", type=int, default=2, help="served queries per step")
@@ -600,6 +602,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB mebibytes (reference kernel for counter scaling)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 1 if args.workload == "4" else 20
     if args.gpus != 1:
         print("bench.py measures one GPU (one MI355X); --gpus %d is not supported: colourings and "
               "queries are independent, so more GPUs would each take their own share" % args.gpus,
