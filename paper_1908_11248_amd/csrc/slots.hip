@@ -889,7 +889,7 @@ __device__ void push_join_epilogue(const Acc* acc, const uint32_t* s_off, const 
 // h[c] and the leaf join 2 h[c1] h[c2] (below 2^32 by a bound), and the join
 // output follows from the split table with E's rows still in LDS.  The
 // partials of all five tables are written.
-template <bool WIDE, bool EPI, bool WRAP>
+template <bool WIDE, bool EPI, bool WRAP, bool SEARCH>
 __global__ void __launch_bounds__(kSlotBlock)
 k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restrict__ colors, int k, int degF_u,
                  const uint32_t* __restrict__ cmap, int W, SlotArrays out, uint64_t* part, PushJoin pj,
@@ -954,13 +954,16 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
     // largest power of two below nv: the first step of the search for an
     // entry's vertex
     const uint32_t top = nv > 1 ? 1u << (31 - __clz(nv - 1)) : 0u;
+    // SEARCH (a graph with vertices of degree > kHeavyDegree): each staged
+    // entry finds its vertex by a search, since a hub would keep one walking
+    // thread busy for whole chunks; otherwise one thread per vertex walks its
+    // few entries, which costs fewer LDS reads
     uint32_t nin = 0;
     for (uint32_t c0 = 0; c0 < E; c0 += kPushChunk) {
         const uint32_t cn = min(uint32_t(kPushChunk), E - c0);
         // one thread per staged entry: its neighbour, the neighbour's colour
-        // and its vertex within the block (the last lv whose row starts at
-        // or before it; a search over the block's offsets, so a vertex with
-        // many entries costs no more than one with few)
+        // and (search) its vertex within the block, the last lv whose row
+        // starts at or before it
         for (uint32_t i0 = 0; i0 < cn; i0 += 4 * kSlotBlock) {
             uint32_t y[4];
 #pragma unroll
@@ -972,7 +975,7 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
             for (int j = 0; j < 4; j++) {
                 const uint32_t i = i0 + j * kSlotBlock + threadIdx.x;
                 const uint32_t c = cb[y[j]];
-                if (i < cn) {
+                if (i < cn && SEARCH) {
                     const uint32_t e = c0 + i;
                     uint32_t lv = 0;
                     for (uint32_t st = top; st; st >>= 1)
@@ -982,10 +985,25 @@ k_slot_edge_push(SlotArrays in, SlotGrid G, DevGraph g, const uint8_t* __restric
                     s_y[i] = y[j] | (c << 24);
                     s_lv[i] = pass && c != cv ? lv | ((c * uint32_t(k) + cv) << 16) : 0xffffffffu;
                     if (EPI) atomicAdd(&s_h[lv * uint32_t(k) + c], 1u);
+                } else if (i < cn) {
+                    s_y[i] = y[j] | (c << 24);
                 }
             }
         }
         __syncthreads();
+        if (!SEARCH) {
+            for (uint32_t lv = threadIdx.x; lv < nv; lv += kSlotBlock) {
+                const uint32_t a = max(s_off[lv], c0), z = min(s_off[lv + 1], c0 + cn);
+                const bool pass = s_off[lv + 1] - s_off[lv] >= uint32_t(degF_u);
+                const uint32_t cv = s_cv[lv];
+                for (uint32_t e = a; e < z; e++) {
+                    const uint32_t cy = s_y[e - c0] >> 24;
+                    s_lv[e - c0] = pass && cy != cv ? lv | ((cy * uint32_t(k) + cv) << 16) : 0xffffffffu;
+                    if (EPI) s_h[lv * uint32_t(k) + cy]++;  // row lv is this thread's alone
+                }
+            }
+            __syncthreads();
+        }
         if (te < rows) {
             // eight neighbour entries per thread and round: their row loads are
             // in flight together
@@ -1766,10 +1784,15 @@ void launch_slot_edge_push(SlotArrays in, int s_in, const SlotGrid& G, DevGraph 
     PushJoin pjl = pj ? *pj : none;
     const size_t lds = push_lds(k, s_in, G, wide, pj ? &pjl : nullptr, wrap);
     if (lds > kPushLdsMax) throw std::runtime_error("launch_slot_edge_push: dynamic LDS beyond kPushLdsMax");
-#define PUSH_LAUNCH(WIDE, EPI, WRAP)                                                                       \
-    k_slot_edge_push<WIDE, EPI, WRAP><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(in, G, g, colors, k, degF_u, \
-                                                                                    push, W, out, part,         \
-                                                                                    pj ? pjl : none, ovf)
+#define PUSH_LAUNCH(WIDE, EPI, WRAP)                                                                                \
+    do {                                                                                                             \
+        if (g.nheavy > 0)                                                                                            \
+            k_slot_edge_push<WIDE, EPI, WRAP, true><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(                    \
+                in, G, g, colors, k, degF_u, push, W, out, part, pj ? pjl : none, ovf);                              \
+        else                                                                                                         \
+            k_slot_edge_push<WIDE, EPI, WRAP, false><<<slot_dims(G.blocks), kSlotBlock, lds, s>>>(                   \
+                in, G, g, colors, k, degF_u, push, W, out, part, pj ? pjl : none, ovf);                              \
+    } while (0)
     if (pj) {
         if (wide)
             PUSH_LAUNCH(true, true, false);
