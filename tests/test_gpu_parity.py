@@ -107,6 +107,32 @@ def test_overflow_flag_and_wraparound(ctx):
     assert int(counts[0]) == ref["count"] and bool(ovf[0]) and ref["overflow"]
 
 
+def test_wrapping_push_matches_oracle(ctx):
+    # Paths of 10 vertices on K(200, 200) and on K(400): the count bound of
+    # the late edge steps of the dense plan passes 2^64, so they run the push
+    # form that tracks wraps (no gather launch).  On K(400) single slots pass
+    # 2^64 as well (about (400/10)^9 9! colourful paths leave a vertex with a
+    # given colour set), so sums wrap inside the push.
+    pat = W.path(10)
+    a = 200
+    bip = W.csr_from_edges(2 * a, np.repeat(np.arange(a), a).astype(np.int64),
+                           (a + np.tile(np.arange(a), a)).astype(np.int64))
+    iu = np.triu_indices(400, 1)
+    kn = W.csr_from_edges(400, iu[0].astype(np.int64), iu[1].astype(np.int64))
+    for name, g in (("K200,200", bip), ("K400", kn)):
+        col = np.random.default_rng(g.n).integers(0, 10, size=(1, g.n)).astype(np.uint8)
+        ctx.profile_enable(True)
+        counts, ovf, D = run_gpu(ctx, g, pat, 10, col)
+        sizes = ctx.last_table_sizes()
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        assert "slot_edge_push" in prof and "slot_edge" not in prof, (name, sorted(prof))
+        ref = O.dp_count(g, pat, 10, col[0], td=D.export(), sizes=True)
+        assert int(counts[0]) == ref["count"] and bool(ovf[0]) == ref["overflow"], name
+        assert ref["overflow"], name
+        assert np.array_equal(sizes, ref["sizes"]), name
+
+
 def test_short_forget_runs_with_large_counts(ctx):
     # A hub joined to D vertices that are paired by edges: every pair closes a
     # triangle with the hub.  Pattern: triangle (0, 1, 2) with four leaves on
