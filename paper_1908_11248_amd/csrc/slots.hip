@@ -868,10 +868,10 @@ __device__ void push_join_epilogue(const Acc* acc, const uint32_t* s_off, const 
 // colour(v)); W threads take one each and add the child's count into v's
 // output row, kept in LDS.  Every thread's work is useful, where the gather
 // spends most of its (output slot, neighbour) pairs on sets that do not
-// contain colour(y).  Launched only when no count of this or any lower table
-// can wrap (a degree bound), so every child table is exact and a sum is
-// present iff it is not 0.  WIDE: 64-bit accumulators, else every output
-// count is below 2^32.
+// contain colour(y).  Without WRAP no count of this or any lower table can
+// wrap (a count bound), so every child table is exact and a sum is present
+// iff it is not 0.  WIDE: 64-bit accumulators, else every output count is
+// below 2^32.
 //
 // WRAP (with WIDE, not EPI): the bound allows counts of 2^64 or more, so sums
 // wrap mod 2^64 and the output has presence bytes.  The child is exact when

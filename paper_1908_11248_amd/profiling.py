@@ -58,12 +58,44 @@ def short_name(full):
     return None
 
 
-def kernel_source_hash():
+def code_only(text):
+    """C++/HIP source text without its comments, whitespace runs collapsed to
+    one space (string and character literals kept as written), so that an
+    edit of comments or layout leaves the code's hash unchanged."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def kernel_source_hash(sources=None):
+    """Hash of the library's sources (file name and code without comments);
+    sources: {file name: text}, default the files of csrc/."""
+    if sources is None:
+        d = os.path.join(HERE, "csrc")
+        sources = {}
+        for f in os.listdir(d):
+            with open(os.path.join(d, f), encoding="utf-8") as fh:
+                sources[f] = fh.read()
     h = hashlib.sha256()
-    d = os.path.join(HERE, "csrc")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+    for f in sorted(sources):
+        h.update(f.encode() + b"\0" + code_only(sources[f]).encode() + b"\0")
     return h.hexdigest()[:16]
 
 

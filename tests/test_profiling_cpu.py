@@ -76,3 +76,15 @@ def test_window_matches_dispatches(tmp_path):
 def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_source_hash_ignores_comments_not_code():
+    from paper_1908_11248_amd.profiling import code_only, kernel_source_hash
+
+    a = {"k.hip": "__global__ void k(int* p) {  // store\n    p[0] = 1; /* one */\n}\n"}
+    b = {"k.hip": "// a kernel\n__global__ void k(int* p) {\n p[0] = 1;\n}"}
+    c = {"k.hip": "__global__ void k(int* p) { p[0] = 2; }"}
+    assert kernel_source_hash(a) == kernel_source_hash(b) != kernel_source_hash(c)
+    # literals keep what looks like a comment
+    assert code_only('x = "/* y */"; // z') == 'x = "/* y */";'
+    assert kernel_source_hash({"a.h": "int x;"}) != kernel_source_hash({"b.h": "int x;"})
