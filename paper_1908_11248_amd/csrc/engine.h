@@ -177,6 +177,7 @@ struct cc_graph {
     // endpoints of stored edge e, ascending
     uint64_t* cn_off = nullptr;
     int32_t* cn_col = nullptr;
+    uint64_t cn_total = 0;  // cn_off[2m]: the lists' total length
     // wedge index (built when an introduce first needs it and the graph has
     // at most 2^28 neighbour pairs): a hash of the vertex pairs x < y with a
     // common neighbour (keys x << wd_vb | y in wd_hk, their run in wd_hv) over

@@ -1114,6 +1114,7 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
             X.release(offs);
             gm->cn_off = off;
             gm->cn_col = lists;
+            gm->cn_total = total;
         }
         return gm->cn_off != nullptr;
     };
@@ -1244,6 +1245,24 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
             virt[size_t(a.in0)] = 1;
         }
     }
+    // An introduce in push form over such a pull (its only reader), whose new
+    // vertex is adjacent in F to both of the pull's vertices, at position 1
+    // or 2: its entries are triangles of G, emitted from the common-neighbour
+    // lists of the pull's edges (tri[j] = the pull; the pull's pairs are only
+    // counted, for its node size).
+    std::vector<int> tri(S, -1);
+    std::vector<char> tskip(S, 0);
+    if (!keep && rq.anchor_hi < 0 && g_all.n <= (1 << 27))
+        for (size_t j = 0; j < S; j++) {
+            const Step& st = plan.steps[j];
+            if (st.kind != S_INTRO_PUSH || st.in0 < 0 || !lpull[size_t(st.in0)] || uses[size_t(st.in0)] != 1 ||
+                st.b_in != 2 || (st.pos != 1 && st.pos != 2) || st.nchk != 1 || st.anchor < 0)
+                continue;
+            const int c0 = st.anchor, c1 = st.chk[0];
+            if (!((c0 == 0 && c1 == 1) || (c0 == 1 && c1 == 0)) || !cn_ready()) continue;
+            tri[j] = st.in0;
+            tskip[size_t(st.in0)] = 1;
+        }
     out->node_sizes.assign(dec.nodes.size(), 0);
 
     // dense one-column tables when the plan allows them and they fit a
@@ -1357,6 +1376,63 @@ void run_dp(cc_context* ctx, Lane& lane, const RunRequest& rq, RunResult* out) {
             for (int j = 0; j < 4; j++) ia.chk[j] = st.chk[j];
             ia.degF = rq.degree_mask ? st.degF : 0;
             DevTable& o = tab[i];
+            if (tskip[i] || tri[i] >= 0) {
+                const Step& pl = plan.steps[size_t(tskip[i] ? int(i) : tri[i])];  // the pull
+                const int m_pull = rq.degree_mask ? pl.degF : 0;
+                const int m_leaf = rq.degree_mask ? plan.steps[size_t(pl.in0)].degF : 0;
+                int64_t node_n = 0;
+                if (tskip[i]) {  // the pull's pairs: counted only
+                    const uint64_t tiles = leaf_pull_tiles(g, B);
+                    if (tiles) {
+                        uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                        X.timed("leaf_pull_count", 10.0 * double(B) * double(g.m2),
+                                [&] { launch_leaf_pull_count(g, B, m_pull, m_leaf, rq.colors, lo, tcount, s); });
+                        uint64_t* toff;
+                        node_n = int64_t(X.scan(tcount, tiles, &toff));
+                        X.release(toff);
+                        X.release(tcount);
+                    }
+                    // the per-table budget holds for this table too, as if it were stored
+                    if (X.max_entries && uint64_t(node_n) > X.max_entries)
+                        throw CcError{CC_ERANGE,
+                                      "a DP table of " + std::to_string(node_n) +
+                                          " entries exceeds the per-table budget of " + std::to_string(X.max_entries),
+                                      true};
+                } else {
+                    // output columns: the pull's u, then (pos 1) u and the
+                    // leaf vertex, or (pos 2) the leaf vertex and u
+                    const int m_u = ia.degF;
+                    const int m1 = st.pos == 1 ? m_u : m_leaf, m2 = st.pos == 1 ? m_leaf : m_u;
+                    const cc_graph* gm = rq.g;
+                    const uint64_t tiles = tri_tiles(gm->cn_total, B);
+                    uint64_t N = 0;
+                    uint64_t* toff = nullptr;
+                    if (tiles) {
+                        uint32_t* tcount = X.alloc<uint32_t>(tiles);
+                        X.timed("tri_count", double(B) * (13.0 * double(g.m2) + 4.0 * double(gm->cn_total)), [&] {
+                            launch_tri_count(g, gm->cn_off, gm->cn_col, gm->cn_total, B, m_pull, m1, m2, rq.colors, lo,
+                                             tcount, s);
+                        });
+                        N = X.scan(tcount, tiles, &toff);
+                        X.release(tcount);
+                    }
+                    o = X.table(lo, N);
+                    if (N)
+                        X.timed("tri_emit", double(B) * (13.0 * double(g.m2) + 4.0 * double(gm->cn_total)) +
+                                                double(N) * entry_bytes(lo.b), [&] {
+                            launch_tri_emit(g, gm->cn_off, gm->cn_col, gm->cn_total, B, m_pull, m1, m2, rq.colors, toff,
+                                            o, s);
+                        });
+                    if (toff) X.release(toff);
+                    node_n = int64_t(o.n);
+                }
+                if (st.node >= 0) out->node_sizes[st.node] = node_n;
+                if (!keep) {
+                    for (int in : {st.in0, st.in1})
+                        if (in >= 0 && --uses[in] == 0) X.drop(tab[in]);
+                }
+                continue;
+            }
             // Introduce by entries: candidates from the bag neighbour of u
             // whose image has the fewest neighbours, per child entry; used
             // when u has a further bag neighbour that the push or pull form

@@ -369,4 +369,87 @@ void launch_leaf_pull_emit(DevGraph g, int B, int degF_u, int degF_leaf, const u
     leaf_pull_launch<true>(g, B, degF_u, degF_leaf, colors, nullptr, toff, out.lay, out.keys, out.cnt, s);
 }
 
+// The introduce that follows such a pull, when its new vertex is adjacent in
+// F to both of the pull's vertices, whose images are adjacent in G: its
+// candidates are the common neighbours of that edge (Sec. 3.2), so its
+// entries are the triangles (v, a, c) of G, a edge (v, a) in CSR order and c
+// from the edge's common-neighbour list (ascending), with three distinct
+// colours and each vertex passing its column's degree mask (m0, m1, m2), each
+// of count 1.  Items are the positions of the lists, colouring-major, in key
+// order, so the output is sorted; neither the pull's table nor the
+// introduce's candidates are materialised.  A thread takes kTriItems
+// consecutive items (one search for its first edge, then it walks on).
+constexpr int kTriItems = 16;
+constexpr uint64_t kTriTile = uint64_t(kBlock) * kTriItems;
+
+uint64_t tri_tiles(uint64_t total, int B) { return uint64_t(B) * ((total + kTriTile - 1) / kTriTile); }
+
+template <class KO, bool EMIT>
+__global__ void __launch_bounds__(kBlock)
+k_tri(DevGraph g, const uint64_t* __restrict__ cn_off, const int32_t* __restrict__ cn_col, uint64_t total, int B,
+      int m0, int m1, int m2, const uint8_t* __restrict__ colors, uint64_t tpb, uint32_t* tcount,
+      const uint64_t* __restrict__ toff, Lay LO, KO* okeys, uint64_t* ocnt) {
+    const uint64_t tiles = tpb * uint64_t(B), E = uint64_t(g.m2);
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint32_t b = uint32_t(tile / tpb);
+        const uint64_t t0 = (tile - uint64_t(b) * tpb) * kTriTile + uint64_t(threadIdx.x) * kTriItems;
+        const uint64_t t1 = t0 + kTriItems < total ? t0 + kTriItems : total;
+        const uint8_t* cb = colors + uint64_t(b) * uint32_t(g.n);
+        // the edge of item t0: cn_off[e] <= t0 < cn_off[e + 1]
+        uint64_t e = t0 < t1 ? upper_bound_u64(cn_off, 0, E + 1, t0) - 1 : 0;
+        uint32_t pass = 0, n_pass = 0;
+        for (uint64_t t = t0; t < t1; t++) {
+            while (cn_off[e + 1] <= t) e++;
+            const uint32_t v = uint32_t(g.esrc[e]), a = uint32_t(g.col[e]), c = uint32_t(cn_col[t]);
+            const uint32_t cv = cb[v], ca = cb[a], cc = cb[c];
+            const bool ok = cv != ca && cv != cc && ca != cc && int(g.deg8[v]) >= m0 && int(g.deg8[a]) >= m1 &&
+                            int(g.deg8[c]) >= m2;
+            pass |= uint32_t(ok) << (t - t0);
+            n_pass += ok;
+        }
+        uint64_t sum;
+        const uint64_t my = block_excl_scan(n_pass, &sum);
+        if (!EMIT) {
+            if (threadIdx.x == 0) tcount[tile] = uint32_t(sum);
+            continue;
+        }
+        uint64_t o = toff[tile] + my;
+        e = t0 < t1 ? upper_bound_u64(cn_off, 0, E + 1, t0) - 1 : 0;
+        for (uint64_t t = t0; t < t1 && pass; t++) {
+            while (cn_off[e + 1] <= t) e++;
+            if (!((pass >> (t - t0)) & 1u)) continue;
+            const uint32_t cols[3] = {uint32_t(g.esrc[e]), uint32_t(g.col[e]), uint32_t(cn_col[t])};
+            okeys[o] = kpack<KO>(b, cols, 3, (1u << cb[cols[0]]) | (1u << cb[cols[1]]) | (1u << cb[cols[2]]), LO);
+            ocnt[o] = 1;
+            o++;
+        }
+    }
+}
+
+template <bool EMIT>
+static void tri_launch(DevGraph g, const uint64_t* cn_off, const int32_t* cn_col, uint64_t total, int B, int m0,
+                       int m1, int m2, const uint8_t* colors, uint32_t* tcount, const uint64_t* toff, Lay LO,
+                       void* okeys, uint64_t* ocnt, hipStream_t s) {
+    const uint64_t tiles = tri_tiles(total, B);
+    if (!tiles) return;
+    const uint64_t tpb = tiles / uint64_t(B);
+    const unsigned grid = unsigned(std::min<uint64_t>(tiles, 1u << 16));
+    if (LO.kw() == 1)
+        k_tri<uint64_t, EMIT><<<grid, kBlock, 0, s>>>(g, cn_off, cn_col, total, B, m0, m1, m2, colors, tpb, tcount,
+                                                      toff, LO, (uint64_t*)okeys, ocnt);
+    else
+        k_tri<u128, EMIT><<<grid, kBlock, 0, s>>>(g, cn_off, cn_col, total, B, m0, m1, m2, colors, tpb, tcount, toff,
+                                                  LO, (u128*)okeys, ocnt);
+}
+
+void launch_tri_count(DevGraph g, const uint64_t* cn_off, const int32_t* cn_col, uint64_t total, int B, int m0,
+                      int m1, int m2, const uint8_t* colors, Lay LO, uint32_t* tcount, hipStream_t s) {
+    tri_launch<false>(g, cn_off, cn_col, total, B, m0, m1, m2, colors, tcount, nullptr, LO, nullptr, nullptr, s);
+}
+
+void launch_tri_emit(DevGraph g, const uint64_t* cn_off, const int32_t* cn_col, uint64_t total, int B, int m0,
+                     int m1, int m2, const uint8_t* colors, const uint64_t* toff, DevTable& out, hipStream_t s) {
+    tri_launch<true>(g, cn_off, cn_col, total, B, m0, m1, m2, colors, nullptr, toff, out.lay, out.keys, out.cnt, s);
+}
+
 }  // namespace ccg

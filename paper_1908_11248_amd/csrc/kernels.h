@@ -275,6 +275,15 @@ void launch_leaf_pull_count(DevGraph g, int B, int degF_u, int degF_leaf, const 
                             uint32_t* tcount, hipStream_t s);
 void launch_leaf_pull_emit(DevGraph g, int B, int degF_u, int degF_leaf, const uint8_t* colors,
                            const uint64_t* toff, DevTable& out, hipStream_t s);
+// The introduce after such a pull whose new vertex is adjacent in F to both
+// of its vertices: the triangles (v, a, c), edge (v, a) in CSR order, c from
+// the edge's common-neighbour list (cn_off, cn_col; total list positions),
+// distinct colours, degree masks m0, m1, m2 per column; tri_tiles tiles.
+uint64_t tri_tiles(uint64_t total, int B);
+void launch_tri_count(DevGraph g, const uint64_t* cn_off, const int32_t* cn_col, uint64_t total, int B, int m0,
+                      int m1, int m2, const uint8_t* colors, Lay LO, uint32_t* tcount, hipStream_t s);
+void launch_tri_emit(DevGraph g, const uint64_t* cn_off, const int32_t* cn_col, uint64_t total, int B, int m0,
+                     int m1, int m2, const uint8_t* colors, const uint64_t* toff, DevTable& out, hipStream_t s);
 
 // enumeration support (enumerate.hip)
 // forget: dst[e] = output position of child entry e

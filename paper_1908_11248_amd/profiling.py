@@ -45,6 +45,7 @@ KERNEL_NAMES = [
     (r"k_expand<.*true, true>", "pull_emit"), (r"k_expand<.*false, true>", "pull_count"),
     (r"k_expand<.*true, false>", "push_emit"), (r"k_expand<.*false, false>", "push_count"),
     (r"k_leaf_pull<.*true>", "leaf_pull_emit"), (r"k_leaf_pull<.*false>", "leaf_pull_count"),
+    (r"k_tri<.*true>", "tri_emit"), (r"k_tri<.*false>", "tri_count"),
     (r"k_pull_index", "pull_index"), (r"k_root", "root"), (r"k_heads", "heads"),
     (r"k_group_starts", "group_starts"), (r"k_scan", "scan"), (r"k_radix", "radix_sort"),
     (r"k_permute", "permute"), (r"k_leaf_emit", "leaf_emit"), (r"k_leaf_count", "leaf_count"),
