@@ -136,8 +136,10 @@ def test_wrapping_push_matches_oracle(ctx):
 def test_pull_over_a_leaf_matches_oracle(ctx):
     # K4, C5 and a partial 3-tree start by introducing a vertex next to a leaf
     # in pull form with no edge test: those entries come straight from the
-    # edges (the leaf's table is never built).  Counts and every node's size
-    # against the oracle, on a graph with hubs and on one without.
+    # edges (the leaf's table is never built); in K4 the next vertex closes a
+    # triangle with them, whose entries come from the edges' common-neighbour
+    # lists.  Counts and every node's size against the oracle, on a graph
+    # with hubs and on one without.
     for g in (W.barabasi_albert(400, 3, 7), W.er_pairs(120, 0.08, 5)):
         for pat in (W.complete(4), W.cycle(5), W.partial_3tree(7, 2)):
             colors = np.random.default_rng(pat.n).integers(0, pat.n, size=(2, g.n)).astype(np.uint8)
@@ -147,6 +149,8 @@ def test_pull_over_a_leaf_matches_oracle(ctx):
             prof = ctx.profile_read()
             ctx.profile_enable(False)
             assert "leaf_pull_emit" in prof or "leaf_pull_count" in prof, (pat.name, sorted(prof))
+            if pat.name == "K4":  # the next vertex closes a triangle: common-neighbour lists
+                assert "tri_count" in prof, sorted(prof)
             ref_sizes = 0
             for b in range(2):
                 ref = O.dp_count(g, pat, pat.n, colors[b], td=D.export(), sizes=True)
