@@ -9,7 +9,8 @@
 // dense colour-set accumulator of (b, v).  The introduce table (the larger of
 // the two) is never written.  When the child is a leaf (Sec. 3.1 leaf rule)
 // its entries ({zeta(y)}, 1) are synthesised from the colouring instead of
-// read.  Units are (b, v) in key order, so the output is sorted.
+// read, and counted per neighbour colour (the outputs are {zeta(v), c}).
+// Units are (b, v) in key order, so the output is sorted.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,6 +62,45 @@ k_edge(const KI* __restrict__ keys, const uint64_t* __restrict__ cnt, Lay L, con
         if (!active) re = rb;
         const uint8_t* col_b = colors + uint64_t(bid) * g.n;
         if (active) cb = 1u << col_b[v];
+        if constexpr (LEAFCHILD) {
+            // The leaf's entries are ({zeta(y)}, 1), so the output sets are
+            // {zeta(v), c}: a count per neighbour colour c replaces the 2^k
+            // accumulator, and increasing c is increasing set order.
+            uint32_t* hc = reinterpret_cast<uint32_t*>(smem) + sub * 32;
+            for (int i = sl; i < 32; i += LN) hc[i] = 0;
+            __syncthreads();
+            uint32_t passed = 0;
+            for (int64_t e = rb + sl; e < re; e += LN) {
+                const uint32_t y = uint32_t(g.col[e]);
+                const uint32_t cy = col_b[y];
+                if (g.rp[y + 1] - g.rp[y] >= degF_child && !((1u << cy) & cb)) {
+                    atomicAdd(&hc[cy], 1u);
+                    passed++;
+                }
+            }
+            __syncthreads();
+            // lane sl takes colour sl (LN >= k); hc[zeta(v)] stays 0
+            const uint32_t h = active && sl < LO.kb ? hc[sl] : 0u;
+            const uint64_t m = (__ballot(h != 0) >> (sub * LN)) & subgroup_mask;
+            if (EMIT) {
+                if (h) {
+                    uint32_t colv[1] = {v};
+                    const KO prefix = kpack<KO>(bid, colv, 1, 0u, LO);
+                    const uint64_t o = goff[w] + uint64_t(__popcll(m & ((1ull << sl) - 1ull)));
+                    okeys[o] = prefix | KO(cb | (1u << sl));
+                    ocnt[o] = h;
+                }
+            } else {
+                uint64_t p = passed;
+                for (int d = LN / 2; d >= 1; d >>= 1) p += __shfl_xor(p, d, LN);
+                if (mine && sl == 0) {
+                    gcount[w] = active ? uint32_t(__popcll(m)) : 0u;
+                    icount[w] = active ? uint32_t(p) : 0u;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
         for (int i = sl; i < slots && EMIT; i += LN) val[i] = 0;
         for (int i = sl; i < words; i += LN) bits[i] = 0;
         bool over = false;
@@ -187,7 +227,8 @@ static void edge_launch_u(const DevTable* in, const uint64_t* rstart, const uint
     uint64_t blocks = (units + U - 1) / U;
     unsigned grid = unsigned(blocks < (1u << 20) ? blocks : (1u << 20));
     size_t words = LO.kb >= 5 ? (size_t(1) << (LO.kb - 5)) : 1;
-    size_t lds = (EMIT ? size_t(U) * (size_t(8) << LO.kb) : 0) + size_t(U) * 4 * words;
+    // a leaf child needs 32 colour counters per unit, else the 2^k accumulator
+    size_t lds = LEAFCHILD ? size_t(U) * 32 * 4 : (EMIT ? size_t(U) * (size_t(8) << LO.kb) : 0) + size_t(U) * 4 * words;
     const void* ik = in ? in->keys : nullptr;
     const uint64_t* ic = in ? in->cnt : nullptr;
     Lay LI = in ? in->lay : LO;
