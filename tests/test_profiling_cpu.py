@@ -88,3 +88,13 @@ def test_source_hash_ignores_comments_not_code():
     # literals keep what looks like a comment
     assert code_only('x = "/* y */"; // z') == 'x = "/* y */";'
     assert kernel_source_hash({"a.h": "int x;"}) != kernel_source_hash({"b.h": "int x;"})
+
+
+def test_kernel_names_of_the_fused_introduces():
+    # the profiler's short names of the pull over a leaf and the triangle step
+    assert P.short_name("void ccg::k_leaf_pull<unsigned long, true>(...)") == "leaf_pull_emit"
+    assert P.short_name("void ccg::k_leaf_pull<unsigned __int128, false>(...)") == "leaf_pull_count"
+    assert P.short_name("void ccg::k_tri<unsigned __int128, true>(...)") == "tri_emit"
+    assert P.short_name("void ccg::k_tri<unsigned long, false>(...)") == "tri_count"
+    assert P.short_name("void ccg::k_slot_edge_push<true, false, true, true>(...)") == "slot_edge_push"
+    assert P.short_name("void ccg::k_slot_leaf<1>(...)") == "slot_leaf"
